@@ -1,0 +1,224 @@
+"""Seeded workload generators: region layouts, right-hand sides and coefficient fields.
+
+Conventions shared by every consumer:
+
+* Coordinates are (x, y[, z]); composite arrays are C-ordered with x fastest,
+  i.e. numpy shape (nz, ny, nx) in 3D and (ny, nx) in 2D.
+* A region is an axis-aligned box of grid nodes, ``origin`` .. ``origin+extent-1``
+  per axis, in composite node coordinates.  Neighbouring boxes share their
+  interface nodes (the region decomposition of the paper's Section 3.1).
+* ``dirichlet_mask`` bit 2*d is the low face along axis d, bit 2*d+1 the high face.
+* Random numbers come from numpy's PCG64 seeded with the workload seed.
+
+Nothing here computes any part of the multigrid method.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Workload",
+    "tensor_layout",
+    "workload",
+    "WORKLOADS",
+    "rhs",
+    "uniform_composite",
+    "region_youngs_moduli",
+    "jump_coefficients",
+    "batched_extents",
+    "dirichlet_nodes",
+]
+
+
+@dataclass
+class Workload:
+    """A region layout plus the solver options a configuration is quoted with."""
+
+    name: str
+    dim: int
+    ndof: int
+    origins: np.ndarray  # (nreg, dim) int64, (x, y[, z])
+    extents: np.ndarray  # (nreg, dim) int64
+    dirichlet_mask: int
+    nlevels: int
+    cheb_degree: int
+    pde: str  # "fd5" (2D five-point), "laplace", "diffusion", "elasticity"
+    h: float = 1.0
+    nu: float = 0.3
+    seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def nreg(self) -> int:
+        return int(self.origins.shape[0])
+
+    @property
+    def composite_shape_xyz(self) -> tuple:
+        return tuple(int(v) for v in (self.origins + self.extents).max(axis=0))
+
+    @property
+    def composite_shape(self) -> tuple:
+        """numpy shape of a composite node array (x fastest)."""
+        return tuple(reversed(self.composite_shape_xyz))
+
+    @property
+    def n_composite_nodes(self) -> int:
+        return int(np.prod(self.composite_shape_xyz))
+
+    @property
+    def n_regional_nodes(self) -> int:
+        return int(np.prod(self.extents, axis=1).sum())
+
+
+def tensor_layout(slab_extents):
+    """Regions of a tensor-product layout.
+
+    ``slab_extents[d]`` lists the node extents of the slabs along axis d.
+    Neighbouring slabs share one node plane.  Regions are numbered with the
+    x slab index fastest.  Returns (origins, extents) as (nreg, dim) arrays.
+    """
+    dim = len(slab_extents)
+    starts = []
+    for ext in slab_extents:
+        s = [0]
+        for e in ext[:-1]:
+            s.append(s[-1] + int(e) - 1)
+        starts.append(s)
+    counts = [len(e) for e in slab_extents]
+    origins, extents = [], []
+    for idx in np.ndindex(*reversed(counts)):
+        idx = tuple(reversed(idx))  # (ix, iy[, iz]) with ix fastest
+        origins.append([starts[d][idx[d]] for d in range(dim)])
+        extents.append([int(slab_extents[d][idx[d]]) for d in range(dim)])
+    return np.asarray(origins, dtype=np.int64), np.asarray(extents, dtype=np.int64)
+
+
+def _uniform_layout(dim, nper, ext):
+    return tensor_layout([[ext] * nper] * dim)
+
+
+def batched_extents(seed: int = 0, counts=(8, 8, 4), choices=(28, 55, 82, 109)):
+    """Slab extents per axis drawn i.i.d. from ``choices`` (batched uneven-region mesh)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [list(rng.choice(np.asarray(choices), size=c)) for c in counts]
+
+
+def workload(name: str, seed: int = 0) -> Workload:
+    """Named configurations.
+
+    ``c1``  2D five-point Poisson, 2x2 regions of 82^2 nodes, 3 levels, Chebyshev degree 2.
+    ``c2``  3D Q1 Laplacian, 4x4x4 regions of 82^3, 4 levels, degree 3.
+    ``c3``  3D Q1 elasticity, 3x3x3 regions of 55^3, E per region lognormal, nu = 0.3.
+    ``c4``  3D Q1 Laplacian on 8x8x4 regions with slab extents from {28,55,82,109}.
+    ``c5``  3D Q1 diffusion with jump coefficients, 4x4x4 regions of 82^3.
+    Small variants (``*_small``) keep the structure at sizes a pure NumPy code
+    finishes in seconds.
+    """
+    full = lambda dim: (1 << (2 * dim)) - 1  # noqa: E731  all faces Dirichlet
+    if name == "c1":
+        o, e = _uniform_layout(2, 2, 82)
+        return Workload(name, 2, 1, o, e, full(2), 3, 2, "fd5", seed=seed)
+    if name == "c1_small":
+        o, e = _uniform_layout(2, 2, 10)
+        return Workload(name, 2, 1, o, e, full(2), 3, 2, "fd5", seed=seed)
+    if name == "c2":
+        o, e = _uniform_layout(3, 4, 82)
+        return Workload(name, 3, 1, o, e, full(3), 4, 3, "laplace", h=1.0 / 324, seed=seed)
+    if name == "c2_small":
+        o, e = _uniform_layout(3, 2, 10)
+        return Workload(name, 3, 1, o, e, full(3), 3, 3, "laplace", h=1.0 / 18, seed=seed)
+    if name == "c2_mid":
+        o, e = _uniform_layout(3, 2, 28)
+        return Workload(name, 3, 1, o, e, full(3), 3, 3, "laplace", h=1.0 / 54, seed=seed)
+    if name == "c3":
+        o, e = _uniform_layout(3, 3, 55)
+        return Workload(name, 3, 3, o, e, full(3), 4, 3, "elasticity", h=1.0 / 162, seed=seed)
+    if name == "c3_small":
+        o, e = _uniform_layout(3, 2, 10)
+        return Workload(name, 3, 3, o, e, full(3), 3, 3, "elasticity", h=1.0 / 18, seed=seed)
+    if name == "c4":
+        o, e = tensor_layout(batched_extents(seed))
+        return Workload(name, 3, 1, o, e, full(3), 4, 3, "laplace", seed=seed)
+    if name == "c4_small":
+        o, e = tensor_layout(batched_extents(seed, counts=(3, 2, 2), choices=(10, 19, 28)))
+        return Workload(name, 3, 1, o, e, full(3), 3, 3, "laplace", seed=seed)
+    if name == "c5":
+        o, e = _uniform_layout(3, 4, 82)
+        return Workload(name, 3, 1, o, e, full(3), 4, 3, "diffusion", h=1.0 / 324, seed=seed)
+    if name == "c5_small":
+        o, e = _uniform_layout(3, 2, 28)
+        return Workload(name, 3, 1, o, e, full(3), 3, 3, "diffusion", h=1.0 / 54, seed=seed)
+    raise KeyError(name)
+
+
+WORKLOADS = ("c1", "c1_small", "c2", "c2_small", "c2_mid", "c3", "c3_small",
+             "c4", "c4_small", "c5", "c5_small")
+
+
+def dirichlet_nodes(shape_xyz, mask: int) -> np.ndarray:
+    """Boolean composite array (x fastest) of nodes on the masked domain faces."""
+    dim = len(shape_xyz)
+    out = np.zeros(tuple(reversed(shape_xyz)), dtype=bool)
+    for d in range(dim):
+        ax = dim - 1 - d  # numpy axis of coordinate d
+        n = shape_xyz[d]
+        if mask & (1 << (2 * d)):
+            sl = [slice(None)] * dim
+            sl[ax] = 0
+            out[tuple(sl)] = True
+        if mask & (1 << (2 * d + 1)):
+            sl = [slice(None)] * dim
+            sl[ax] = n - 1
+            out[tuple(sl)] = True
+    return out
+
+
+def uniform_composite(shape_xyz, ndof: int, seed: int, stream: int = 0) -> np.ndarray:
+    """i.i.d. U[-1, 1] values on composite nodes, shape (..nodes.., ndof) if ndof > 1."""
+    rng = np.random.Generator(np.random.PCG64([seed, stream]))
+    shape = tuple(reversed(shape_xyz)) + ((ndof,) if ndof > 1 else ())
+    return rng.uniform(-1.0, 1.0, size=shape)
+
+
+def rhs(w: Workload, seed: int | None = None) -> np.ndarray:
+    """Right-hand side: U[-1, 1] per free dof, zero on Dirichlet nodes (composite layout)."""
+    seed = w.seed if seed is None else seed
+    b = uniform_composite(w.composite_shape_xyz, w.ndof, seed, stream=1)
+    dn = dirichlet_nodes(w.composite_shape_xyz, w.dirichlet_mask)
+    b[dn] = 0.0
+    return b
+
+
+def region_youngs_moduli(w: Workload, seed: int | None = None) -> np.ndarray:
+    """Young's modulus per region, E = exp(N(0, 1))."""
+    seed = w.seed if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64([seed, 2]))
+    return np.exp(rng.standard_normal(w.nreg))
+
+
+def jump_coefficients(w: Workload, seed: int | None = None) -> np.ndarray:
+    """Per-element diffusion coefficient on the composite element grid (x fastest).
+
+    c_e = 10**s_R * exp(xi_e) with xi_e ~ N(0, 1) per element; s_R ~ U(-4, 4)
+    for regions whose tensor index (I+J+K) is even and s_R = 0 otherwise.
+    The region of an element is the box that contains it.
+    """
+    seed = w.seed if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64([seed, 3]))
+    shape_e = tuple(n - 1 for n in reversed(w.composite_shape_xyz))
+    xi = rng.standard_normal(shape_e)
+    s = rng.uniform(-4.0, 4.0, size=w.nreg)
+    # tensor index of each region from its origin rank per axis
+    tidx = np.zeros((w.nreg, w.dim), dtype=np.int64)
+    for d in range(w.dim):
+        uniq = np.unique(w.origins[:, d])
+        tidx[:, d] = np.searchsorted(uniq, w.origins[:, d])
+    parity_even = (tidx.sum(axis=1) % 2) == 0
+    s = np.where(parity_even, s, 0.0)
+    c = np.exp(xi)
+    for k in range(w.nreg):
+        sl = tuple(slice(int(o), int(o + e - 1)) for o, e in zip(reversed(w.origins[k]), reversed(w.extents[k])))
+        c[sl] *= 10.0 ** s[k]
+    return c
