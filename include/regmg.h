@@ -1,0 +1,197 @@
+/*
+ * regmg — regional (semi-structured) multigrid preconditioned CG on one MI355X.
+ *
+ * Method: Mayr, Berger-Vergiat, Ohm, Tuminaro, "Non-invasive multigrid for
+ * semi-structured grids" (arXiv 2103.11962).  The domain is a set of boxes
+ * ("regions", Section 3.1) of grid nodes that overlap only on shared
+ * interface nodes.  Every region holds its own copy of its interface nodes and
+ * its own regional matrix A^(k); the composite matrix is A = sum_k
+ * Psi_k A^(k) Psi_k^T (eq. "extraction sum", Lemma on Psi [[A]] Psi^T = A).
+ * A regional V-cycle (Section 3.6 figure, applied recursively) with Chebyshev
+ * smoothing (Section 3.4, Algorithm 2), rate-3 linear transfers (Section 3.2),
+ * per-region Galerkin products (eq. "RegionalGalerkinProduct") and a dense
+ * direct solve of the coarsest composite operator (Section 3.5) preconditions
+ * FP64 conjugate gradients.
+ *
+ * Conventions for every call:
+ *  - All entry points return rmg_status; RMG_OK is 0.  On error the library
+ *    stores a message retrievable with rmg_last_error() (thread-local) and
+ *    leaves the handle usable unless the status is RMG_ERR_DEVICE.
+ *  - Every argument is validated on the host before any kernel is launched.
+ *  - Device pointers are HIP device addresses on the handle's device; "host"
+ *    pointers are ordinary host memory.  Caller buffers are borrowed for the
+ *    duration of the call only; the library never frees caller memory.
+ *  - All device work is ordered on the stream given to rmg_create; calls
+ *    that return results to the host synchronise that stream.
+ *  - Coordinates are (x, y[, z]); arrays over nodes are x-fastest.  A
+ *    COMPOSITE vector holds one value per composite dof (node-major, dof-minor);
+ *    a REGIONAL vector holds region 0's nodes, then region 1's, ... (each
+ *    region x-fastest, dof-minor), with interface nodes replicated (the
+ *    regional layout [[v]] of Section 3.1).
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef REGMG_H
+#define REGMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RMG_OK = 0,
+  RMG_ERR_ARG = 1,           /* bad argument value / null pointer / unsupported option */
+  RMG_ERR_SHAPE = 2,         /* region boxes do not tile the domain, or cannot be coarsened */
+  RMG_ERR_NUMERIC = 3,       /* NaN/Inf in input, non-positive diagonal, singular coarse matrix */
+  RMG_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+  RMG_ERR_OOM = 5,           /* device allocation failed */
+  RMG_ERR_NOT_SETUP = 6,     /* call made before the required earlier phase */
+  RMG_ERR_BREAKDOWN = 7,     /* CG breakdown: p^T A p <= 0 or (r, z) <= 0 or non-finite */
+  RMG_ERR_NOT_CONVERGED = 8  /* maxit reached; x holds the last iterate */
+} rmg_status;
+
+typedef enum { RMG_LAYOUT_COMPOSITE = 0, RMG_LAYOUT_REGIONAL = 1 } rmg_layout;
+
+typedef enum {
+  RMG_PDE_LAPLACE = 0,   /* Q1 Laplacian, element matrix scaled by h */
+  RMG_PDE_DIFFUSION = 1, /* Q1 Laplacian times a per-element coefficient */
+  RMG_PDE_ELASTICITY = 2 /* Q1 isotropic elasticity, Young's modulus per region */
+} rmg_pde;
+
+typedef enum {
+  RMG_PREC_FP64 = 0,        /* whole V-cycle in FP64 */
+  RMG_PREC_FP32 = 1,        /* V-cycle in FP32 inside FP64 CG */
+  RMG_PREC_FP32_BF16 = 2    /* FP32 V-cycle, finest-level stencil off-diagonals in BF16 */
+} rmg_precision;
+
+typedef struct rmg_handle rmg_handle;
+
+/* Hierarchy options (Section 3.2 setup, Section 3.4 Chebyshev parameters). */
+typedef struct {
+  int nlevels;        /* region levels, >= 2; the last one is solved directly */
+  int cheb_degree;    /* Chebyshev degree K >= 1, applied once before and once after */
+  double eig_ratio;   /* eta: lower end of the interval = lambda / eta (default 20) */
+  double boost;       /* kappa: upper end = kappa * lambda (default 1.1) */
+  int power_iters;    /* power iterations for lambda_max(D~^-1 A) (default 10) */
+  uint64_t seed;      /* seed of the counter-based power-method start vector */
+  int precision;      /* rmg_precision */
+} rmg_options;
+
+/* Filled by rmg_options_default with the values above. */
+void rmg_options_default(rmg_options* opt);
+
+typedef struct {
+  int iterations;        /* number of A p products */
+  int converged;         /* 1 if ||r||/||b|| <= rtol */
+  double relres;         /* recursive relative residual at exit */
+  double true_relres;    /* ||b - A x|| / ||b|| recomputed at exit */
+  double solve_ms;       /* wall time of the CG loop on the stream (HIP events) */
+  double* history;       /* caller-owned host array or NULL: relres per iteration, [0] = 1 */
+  int history_cap;       /* capacity of history */
+  int history_len;       /* entries written */
+} rmg_solve_info;
+
+/* Create a handle on HIP device `device`; all work goes to `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  *out owned by the library. */
+rmg_status rmg_create(rmg_handle** out, int device, void* hip_stream);
+
+/* Release all device memory of the handle.  NULL is accepted. */
+rmg_status rmg_destroy(rmg_handle* h);
+
+/* Last error message of the calling thread ("" if none). */
+const char* rmg_last_error(void);
+
+/* Region description supplied by the application (Section 4): for each
+ * region its node extent and the composite coordinates of its first node.
+ * extent, origin: host int32 arrays [nreg][dim].  dim 2 or 3, ndof 1 or 3
+ * (3 only with dim 3).  dirichlet_mask bit 2d / 2d+1 marks the low / high
+ * domain face along axis d as homogeneous Dirichlet.  The boxes must tile the
+ * bounding box of the domain, overlapping only on shared node planes
+ * (RMG_ERR_SHAPE otherwise).  Discards any previous regions and hierarchy. */
+rmg_status rmg_build_regions(rmg_handle* h, int dim, int ndof, int nreg, const int32_t* extent,
+                             const int32_t* origin, uint32_t dirichlet_mask);
+
+/* Finest-level regional matrix A^(k) of one region as a stencil
+ * (block diagonal region matrix, Section 3.1).  coef is FP64, structure of
+ * arrays: coef[s * nnodes + i] is the coupling of region node i to its
+ * neighbour at stencil offset s, i x-fastest over the region's nnodes.
+ * Offsets: npts 27 (3D): s = (dz+1)*9 + (dy+1)*3 + (dx+1); npts 9 (2D):
+ * s = (dy+1)*3 + (dx+1); npts 5 (2D): (0,-1), (-1,0), (0,0), (1,0), (0,1).
+ * Scalar problems only.  Couplings that point outside the region box are
+ * ignored (set to zero).  on_device: coef is a device (1) or host (0) pointer.
+ * RMG_ERR_NUMERIC on NaN/Inf. */
+rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const double* coef, int on_device);
+
+/* Non-invasive construction (Section 4): split an assembled composite operator,
+ * given as a composite stencil, into region matrices.  coef: FP64 structure of
+ * arrays [npts][n_composite nodes] (x fastest, offsets as in
+ * rmg_set_region_stencil); couplings that leave the domain must be zero.  An
+ * off-diagonal entry is divided by the number of regions containing both of
+ * its nodes; each region's diagonal is the row sum of A divided by the node's
+ * multiplicity minus that region's split off-diagonals (zero row sums are
+ * kept).  Needs a tensor-product region layout (RMG_ERR_SHAPE otherwise).
+ * on_device: coef is a device (1) or host (0) pointer. */
+rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef, int on_device);
+
+/* Assemble every region's matrix on the device from Q1 hexahedral elements of
+ * side h inside that region (one admissible split of A, Section 3.1), with
+ * symmetric elimination of Dirichlet nodes (identity rows split 1/mult).
+ * elem_coef: device FP64 array over the composite element grid
+ * ((nx-1)(ny-1)(nz-1), x fastest) for RMG_PDE_DIFFUSION, else NULL.
+ * youngs: host FP64 [nreg] for RMG_PDE_ELASTICITY (with Poisson ratio nu), else NULL. */
+rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* elem_coef,
+                           const double* youngs, double nu);
+
+/* Build the regional hierarchy (Section 3.2): composite diagonal
+ * D~ = Psi^T Psi diag([[A]]), lambda_max(D~^-1 A) by power iteration, rate-3
+ * linear interpolation with interface-replicated rows, per-region Galerkin
+ * products [[Abar]] = R^(r) [[A]] P^(r) on the device, and on the last level the
+ * composite operator Abar = Psi-bar [[Abar]] Psi-bar^T and its inverse.
+ * RMG_ERR_SHAPE if some region extent-1 or origin is not divisible by
+ * 3^(nlevels-1).  RMG_ERR_NUMERIC if a diagonal is not positive or the coarse
+ * matrix is singular. */
+rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt);
+
+/* z = V(r): one regional V-cycle with zero initial guess (device FP64
+ * vectors in `layout`).  r and z may not alias.  Asynchronous on the stream. */
+rmg_status rmg_apply_vcycle(rmg_handle* h, const double* r, double* z, int layout);
+
+/* Preconditioned CG for A x = b (device FP64 vectors in `layout`; x holds x0
+ * on entry, the solution on exit).  Stops when ||r_k|| / ||b|| <= rtol or after
+ * maxit iterations (RMG_ERR_NOT_CONVERGED).  info may be NULL.  Synchronises. */
+rmg_status rmg_solve(rmg_handle* h, const double* b, double* x, int layout, double rtol, int maxit,
+                     rmg_solve_info* info);
+
+/* ---- conversions and per-step entry points (used by parity tests) ---- */
+
+/* [[v]] = Psi^T v on level `level` (device FP64). */
+rmg_status rmg_to_regional(rmg_handle* h, int level, const double* comp, double* reg);
+/* v = owner copy of each composite dof (average = 0) or the average of the
+ * copies (average = 1, (Psi Psi^T)^-1 Psi [[v]]). */
+rmg_status rmg_to_composite(rmg_handle* h, int level, const double* reg, double* comp, int average);
+/* z = Psi^T Psi [[A]] v on level `level` (RegMatVec). */
+rmg_status rmg_regional_matvec(rmg_handle* h, int level, const double* v, double* z);
+/* w = Psi^T Psi v (interface summation). */
+rmg_status rmg_interface_sum(rmg_handle* h, int level, const double* v, double* w);
+/* Coarse w = Psi-bar^T Psi-bar R^(r) [[Psi Psi^T]]^-1 r from level to level+1 (Section 3.3). */
+rmg_status rmg_restrict(rmg_handle* h, int level, const double* r, double* w);
+/* Fine u += P^(r) ubar from level+1 to level (Section 3.3). */
+rmg_status rmg_prolongate_add(rmg_handle* h, int level, const double* ubar, double* u);
+/* u = S(b): one degree-K Chebyshev application with zero initial guess. */
+rmg_status rmg_smooth(rmg_handle* h, int level, const double* b, double* u);
+
+/* Level data.  n_regional / n_composite count dofs. */
+rmg_status rmg_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t* n_composite,
+                          int* npts, double* lambda_max);
+/* Copy region `region`'s stencil on `level` to host memory in the layout of
+ * rmg_set_region_stencil (npts 27 in 3D, 9 in 2D, all levels). */
+rmg_status rmg_get_level_stencil(rmg_handle* h, int level, int region, double* host_out);
+/* Dense composite operator of the coarsest level (host, n_composite^2, row-major). */
+rmg_status rmg_get_coarse_matrix(rmg_handle* h, double* host_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REGMG_H */

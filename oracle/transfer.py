@@ -32,7 +32,7 @@ def p1d(nf: int) -> sp.csr_matrix:
         c, t = divmod(x, 3)
         rows.append(x)
         cols.append(c)
-        vals.append(1.0 - t / 3.0)
+        vals.append((3 - t) / 3.0)
         if t:
             rows.append(x)
             cols.append(c + 1)

@@ -1,0 +1,467 @@
+// C ABI of the regional multigrid library: validation, error mapping, entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kernels.h"
+
+namespace rmg {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(rmg_status code, const std::string& msg) { throw Error{code, msg}; }
+
+// Reference Q1 Laplacian element matrix of a cube of side h: int grad phi_a . grad phi_b,
+// 2x2x2 Gauss-Legendre quadrature, corner a = (a&1, (a>>1)&1, (a>>2)&1).
+static void q1_laplace_element(double h, double K[64]) {
+  const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  for (int i = 0; i < 64; ++i) K[i] = 0.0;
+  for (int qz = 0; qz < 2; ++qz)
+    for (int qy = 0; qy < 2; ++qy)
+      for (int qx = 0; qx < 2; ++qx) {
+        const double xi[3] = {g[qx], g[qy], g[qz]};
+        double grad[8][3];
+        for (int a = 0; a < 8; ++a) {
+          const int c[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
+          double f[3], df[3];
+          for (int d = 0; d < 3; ++d) {
+            f[d] = c[d] ? xi[d] : 1.0 - xi[d];
+            df[d] = c[d] ? 1.0 : -1.0;
+          }
+          grad[a][0] = df[0] * f[1] * f[2];
+          grad[a][1] = f[0] * df[1] * f[2];
+          grad[a][2] = f[0] * f[1] * df[2];
+        }
+        for (int a = 0; a < 8; ++a)
+          for (int b = 0; b < 8; ++b)
+            K[a * 8 + b] += 0.125 * h * (grad[a][0] * grad[b][0] + grad[a][1] * grad[b][1] + grad[a][2] * grad[b][2]);
+      }
+}
+
+}  // namespace rmg
+
+using namespace rmg;
+
+rmg_handle::~rmg_handle() {
+  for (Level* L : levels) delete L;
+  levels.clear();
+  if (host_scalars) (void)hipHostFree(host_scalars);
+}
+
+#define API_BEGIN try {
+#define API_END                                   \
+  }                                               \
+  catch (const rmg::Error& e) {                   \
+    rmg::set_last_error(e.msg);                   \
+    return e.code;                                \
+  }                                               \
+  catch (const std::exception& e) {               \
+    rmg::set_last_error(e.what());                \
+    return RMG_ERR_ARG;                           \
+  }                                               \
+  return RMG_OK;
+
+static void use_device(rmg_handle* h) {
+  RMG_REQUIRE(h != nullptr, RMG_ERR_ARG, "null handle");
+  RMG_HIP(hipSetDevice(h->device));
+}
+
+static Level& level_of(rmg_handle* h, int level) {
+  RMG_REQUIRE(h->have_regions, RMG_ERR_NOT_SETUP, "regions not built");
+  RMG_REQUIRE(level >= 0 && level < (int)h->levels.size(), RMG_ERR_ARG,
+              "level " + std::to_string(level) + " does not exist");
+  return *h->levels[level];
+}
+
+extern "C" {
+
+void rmg_options_default(rmg_options* o) {
+  if (!o) return;
+  o->nlevels = 3;
+  o->cheb_degree = 2;
+  o->eig_ratio = 20.0;
+  o->boost = 1.1;
+  o->power_iters = 10;
+  o->seed = 0;
+  o->precision = RMG_PREC_FP64;
+}
+
+const char* rmg_last_error(void) { return g_last_error.c_str(); }
+
+rmg_status rmg_create(rmg_handle** out, int device, void* stream) {
+  API_BEGIN
+  RMG_REQUIRE(out != nullptr, RMG_ERR_ARG, "null output pointer");
+  int ndev = 0;
+  RMG_HIP(hipGetDeviceCount(&ndev));
+  RMG_REQUIRE(device >= 0 && device < ndev, RMG_ERR_ARG, "no HIP device " + std::to_string(device));
+  RMG_HIP(hipSetDevice(device));
+  rmg_handle* h = new rmg_handle();
+  h->device = device;
+  h->stream = static_cast<hipStream_t>(stream);
+  rmg_options_default(&h->opt);
+  try {
+    h->scalars.alloc(sizeof(double) * kNumSlots);
+    RMG_HIP(hipMemset(h->scalars.p, 0, sizeof(double) * kNumSlots));
+    RMG_HIP(hipHostMalloc((void**)&h->host_scalars, sizeof(double) * kNumSlots, hipHostMallocDefault));
+  } catch (...) {
+    delete h;
+    throw;
+  }
+  *out = h;
+  API_END
+}
+
+rmg_status rmg_destroy(rmg_handle* h) {
+  API_BEGIN
+  if (!h) return RMG_OK;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  delete h;
+  API_END
+}
+
+rmg_status rmg_build_regions(rmg_handle* h, int dim, int ndof, int nreg, const int32_t* extent,
+                             const int32_t* origin, uint32_t mask) {
+  API_BEGIN
+  use_device(h);
+  RMG_REQUIRE(dim == 2 || dim == 3, RMG_ERR_ARG, "dim must be 2 or 3");
+  RMG_REQUIRE(ndof == 1, RMG_ERR_ARG, "only scalar problems (ndof = 1) are supported by this build");
+  RMG_REQUIRE(nreg >= 1 && extent && origin, RMG_ERR_ARG, "need nreg >= 1 and extent/origin arrays");
+  RMG_REQUIRE(mask < (1u << (2 * dim)), RMG_ERR_ARG, "dirichlet mask has bits beyond 2*dim");
+  h->have_regions = h->have_operator = h->have_hierarchy = false;
+  h->dim = dim;
+  h->ndof = ndof;
+  h->nreg = nreg;
+  h->mask = mask;
+  h->extent.assign(3 * (size_t)nreg, 1);
+  h->origin.assign(3 * (size_t)nreg, 0);
+  for (int k = 0; k < nreg; ++k)
+    for (int d = 0; d < dim; ++d) {
+      const int32_t e = extent[(size_t)k * dim + d], o = origin[(size_t)k * dim + d];
+      RMG_REQUIRE(e >= 2 && o >= 0, RMG_ERR_SHAPE, "region extents must be >= 2 and origins >= 0");
+      h->extent[3 * (size_t)k + d] = e;
+      h->origin[3 * (size_t)k + d] = o;
+    }
+  build_level0(h);
+  h->region_set.assign(nreg, false);
+  Level& L = *h->levels[0];
+  const size_t nb = sizeof(double) * (size_t)L.n;
+  h->cg_x.alloc(nb);
+  h->cg_r.alloc(nb);
+  h->cg_p.alloc(nb);
+  h->cg_q.alloc(nb);
+  h->cg_z.alloc(nb);
+  h->cg_b.alloc(nb);
+  h->partials.alloc(sizeof(double) * ((int64_t)L.blocks.size() + (L.ngroups + kBlock - 1) / kBlock + 16));
+  h->have_regions = true;
+  API_END
+}
+
+rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const double* coef, int on_device) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, 0);
+  RMG_REQUIRE(region >= 0 && region < h->nreg, RMG_ERR_ARG, "region index out of range");
+  RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
+  const bool ok = (h->dim == 3 && npts == 27) || (h->dim == 2 && (npts == 5 || npts == 9));
+  RMG_REQUIRE(ok, RMG_ERR_ARG, "npts must be 27 in 3D and 5 or 9 in 2D");
+  bool any = false;
+  for (bool b : h->region_set) any = any || b;
+  if (!any || L.npts != npts || !L.coef.p) {
+    RMG_REQUIRE(!any || L.npts == npts, RMG_ERR_ARG, "all regions must use the same stencil size");
+    L.npts = npts;
+    L.coef.alloc(sizeof(double) * (size_t)npts * L.n);
+    RMG_HIP(hipMemsetAsync(L.coef.p, 0, sizeof(double) * (size_t)npts * L.n, h->stream));
+  }
+  const RegionGeo& R = L.regs[region];
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  for (int s = 0; s < npts; ++s)
+    RMG_HIP(hipMemcpyAsync(L.coef.as<double>() + (size_t)s * L.n + R.off, coef + (size_t)s * R.n,
+                           sizeof(double) * R.n, kind, h->stream));
+  DBuf flag;
+  flag.alloc(sizeof(int));
+  RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), h->stream));
+  launch_mask_stencil(L, flag.as<int>(), h->stream);
+  int hflag = 0;
+  RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "stencil has NaN or Inf entries");
+  h->region_set[region] = true;
+  h->have_hierarchy = false;
+  bool all = true;
+  for (bool b : h->region_set) all = all && b;
+  h->have_operator = all;
+  API_END
+}
+
+// True when the region boxes are the products of per-axis slabs (a tensor-product layout).
+static bool tensor_layout(const rmg_handle* h) {
+  size_t combos = 1;
+  std::vector<std::vector<std::pair<int, int>>> slabs(h->dim);
+  for (int d = 0; d < h->dim; ++d) {
+    for (int k = 0; k < h->nreg; ++k) {
+      std::pair<int, int> iv{h->origin[3 * k + d], h->extent[3 * k + d]};
+      bool found = false;
+      for (auto& q : slabs[d]) found = found || q == iv;
+      if (!found) slabs[d].push_back(iv);
+    }
+    // the slabs of one axis must form a chain sharing one node plane between neighbours
+    std::sort(slabs[d].begin(), slabs[d].end());
+    for (size_t i = 1; i < slabs[d].size(); ++i)
+      if (slabs[d][i - 1].first + slabs[d][i - 1].second - 1 != slabs[d][i].first) return false;
+    combos *= slabs[d].size();
+  }
+  // the tiling check already ran: boxes tile the domain without overlap, so a tensor layout
+  // is exactly one with as many regions as slab combinations
+  return combos == (size_t)h->nreg;
+}
+
+rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef, int on_device) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, 0);
+  RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
+  const bool ok = (h->dim == 3 && npts == 27) || (h->dim == 2 && (npts == 5 || npts == 9));
+  RMG_REQUIRE(ok, RMG_ERR_ARG, "npts must be 27 in 3D and 5 or 9 in 2D");
+  RMG_REQUIRE(tensor_layout(h), RMG_ERR_SHAPE, "the composite split needs a tensor-product region layout");
+  DBuf tmp;
+  const double* src = coef;
+  if (!on_device) {
+    tmp.alloc(sizeof(double) * (size_t)npts * L.ncomp);
+    RMG_HIP(hipMemcpyAsync(tmp.p, coef, sizeof(double) * (size_t)npts * L.ncomp, hipMemcpyHostToDevice, h->stream));
+    src = tmp.as<double>();
+  }
+  L.npts = npts;
+  L.coef.alloc(sizeof(double) * (size_t)npts * L.n);
+  DBuf flag;
+  flag.alloc(sizeof(int));
+  RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), h->stream));
+  launch_split_composite(L, src, flag.as<int>(), h->stream);
+  int hflag = 0;
+  RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "composite stencil has NaN or Inf entries");
+  h->region_set.assign(h->nreg, true);
+  h->have_operator = true;
+  h->have_hierarchy = false;
+  API_END
+}
+
+rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* elem_coef, const double* youngs,
+                           double nu) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, 0);
+  RMG_REQUIRE(h->dim == 3, RMG_ERR_ARG, "Q1 assembly needs a 3D layout");
+  RMG_REQUIRE(hsize > 0.0 && std::isfinite(hsize), RMG_ERR_ARG, "element size must be positive");
+  RMG_REQUIRE(pde == RMG_PDE_LAPLACE || pde == RMG_PDE_DIFFUSION, RMG_ERR_ARG,
+              "only Laplace and diffusion are supported by this build");
+  RMG_REQUIRE(pde != RMG_PDE_DIFFUSION || elem_coef != nullptr, RMG_ERR_ARG, "diffusion needs elem_coef");
+  (void)youngs;
+  (void)nu;
+  double K[64];
+  q1_laplace_element(hsize, K);
+  L.npts = 27;
+  L.coef.alloc(sizeof(double) * 27 * (size_t)L.n);
+  launch_assemble_q1_scalar(L, K, pde == RMG_PDE_DIFFUSION ? elem_coef : nullptr, h->stream);
+  launch_dirichlet_split(L, h->stream);
+  DBuf flag;
+  flag.alloc(sizeof(int));
+  RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), h->stream));
+  launch_mask_stencil(L, flag.as<int>(), h->stream);
+  int hflag = 0;
+  RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "assembled operator has NaN or Inf entries");
+  h->region_set.assign(h->nreg, true);
+  h->have_operator = true;
+  h->have_hierarchy = false;
+  API_END
+}
+
+rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
+  API_BEGIN
+  use_device(h);
+  RMG_REQUIRE(opt != nullptr, RMG_ERR_ARG, "null options");
+  RMG_REQUIRE(h->have_regions && h->have_operator, RMG_ERR_NOT_SETUP, "regions and operator must be set first");
+  RMG_REQUIRE(opt->nlevels >= 2 && opt->nlevels <= 12, RMG_ERR_ARG, "nlevels must be in [2, 12]");
+  RMG_REQUIRE(opt->cheb_degree >= 1 && opt->cheb_degree <= 16, RMG_ERR_ARG, "cheb_degree must be in [1, 16]");
+  RMG_REQUIRE(opt->eig_ratio > 1.0 && opt->boost > 0.0, RMG_ERR_ARG, "need eig_ratio > 1 and boost > 0");
+  RMG_REQUIRE(opt->power_iters >= 1, RMG_ERR_ARG, "power_iters must be >= 1");
+  RMG_REQUIRE(opt->precision == RMG_PREC_FP64, RMG_ERR_ARG, "only FP64 precision is supported by this build");
+  h->opt = *opt;
+  h->have_hierarchy = false;
+  setup_hierarchy(h);
+  h->have_hierarchy = true;
+  API_END
+}
+
+static void require_hierarchy(rmg_handle* h) {
+  RMG_REQUIRE(h->have_hierarchy, RMG_ERR_NOT_SETUP, "hierarchy not set up");
+}
+
+rmg_status rmg_apply_vcycle(rmg_handle* h, const double* r, double* z, int layout) {
+  API_BEGIN
+  use_device(h);
+  require_hierarchy(h);
+  RMG_REQUIRE(r && z && r != z, RMG_ERR_ARG, "r and z must be distinct non-null device pointers");
+  RMG_REQUIRE(layout == RMG_LAYOUT_COMPOSITE || layout == RMG_LAYOUT_REGIONAL, RMG_ERR_ARG, "bad layout");
+  Level& L = *h->levels[0];
+  if (layout == RMG_LAYOUT_REGIONAL) {
+    vcycle(h, 0, r, z);
+  } else {
+    launch_to_regional(L, r, h->cg_b.as<double>(), h->stream);
+    vcycle(h, 0, h->cg_b.as<double>(), h->cg_z.as<double>());
+    launch_to_composite(L, h->cg_z.as<double>(), z, 0, h->stream);
+  }
+  API_END
+}
+
+rmg_status rmg_solve(rmg_handle* h, const double* b, double* x, int layout, double rtol, int maxit,
+                     rmg_solve_info* info) {
+  API_BEGIN
+  use_device(h);
+  require_hierarchy(h);
+  RMG_REQUIRE(b && x && b != x, RMG_ERR_ARG, "b and x must be distinct non-null device pointers");
+  RMG_REQUIRE(layout == RMG_LAYOUT_COMPOSITE || layout == RMG_LAYOUT_REGIONAL, RMG_ERR_ARG, "bad layout");
+  RMG_REQUIRE(rtol > 0.0 && maxit >= 1, RMG_ERR_ARG, "need rtol > 0 and maxit >= 1");
+  Level& L = *h->levels[0];
+  rmg_status st = RMG_OK;
+  if (layout == RMG_LAYOUT_REGIONAL) {
+    pcg(h, b, x, rtol, maxit, info, &st);
+  } else {
+    launch_to_regional(L, b, h->cg_b.as<double>(), h->stream);
+    launch_to_regional(L, x, h->cg_x.as<double>(), h->stream);
+    pcg(h, h->cg_b.as<double>(), h->cg_x.as<double>(), rtol, maxit, info, &st);
+    launch_to_composite(L, h->cg_x.as<double>(), x, 0, h->stream);
+  }
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  if (st != RMG_OK) return st;
+  API_END
+}
+
+rmg_status rmg_to_regional(rmg_handle* h, int level, const double* comp, double* reg) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  RMG_REQUIRE(comp && reg, RMG_ERR_ARG, "null pointer");
+  launch_to_regional(L, comp, reg, h->stream);
+  API_END
+}
+
+rmg_status rmg_to_composite(rmg_handle* h, int level, const double* reg, double* comp, int average) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  RMG_REQUIRE(comp && reg, RMG_ERR_ARG, "null pointer");
+  launch_to_composite(L, reg, comp, average ? 1 : 0, h->stream);
+  API_END
+}
+
+rmg_status rmg_regional_matvec(rmg_handle* h, int level, const double* v, double* z) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  RMG_REQUIRE(v && z && v != z, RMG_ERR_ARG, "v and z must be distinct non-null device pointers");
+  RMG_REQUIRE(L.coef.p != nullptr && (level > 0 || h->have_operator), RMG_ERR_NOT_SETUP, "operator not set");
+  StencilArgs a;
+  a.op = StencilOp::Matvec;
+  a.x = v;
+  a.out = z;
+  launch_stencil_op(L, a, h->stream);
+  API_END
+}
+
+rmg_status rmg_interface_sum(rmg_handle* h, int level, const double* v, double* w) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  RMG_REQUIRE(v && w, RMG_ERR_ARG, "null pointer");
+  launch_interface_sum(L, v, w, h->stream);
+  API_END
+}
+
+rmg_status rmg_restrict(rmg_handle* h, int level, const double* r, double* w) {
+  API_BEGIN
+  use_device(h);
+  require_hierarchy(h);
+  RMG_REQUIRE(level >= 0 && level + 1 < (int)h->levels.size(), RMG_ERR_ARG, "no coarser level");
+  RMG_REQUIRE(r && w && r != w, RMG_ERR_ARG, "r and w must be distinct non-null device pointers");
+  Level& F = *h->levels[level];
+  Level& C = *h->levels[level + 1];
+  {
+    // r / mult on shared nodes: the ResidualScaled update with b = r and a zero product
+    launch_zero(F.n, F.u2.as<double>(), h->stream);
+    StencilArgs a;
+    a.op = StencilOp::ResidualScaled;
+    a.x = F.u2.as<double>();
+    a.out = F.r.as<double>();
+    a.b = r;
+    launch_stencil_op(F, a, h->stream);
+  }
+  launch_restrict(F, C, F.r.as<double>(), w, h->stream);
+  API_END
+}
+
+rmg_status rmg_prolongate_add(rmg_handle* h, int level, const double* ubar, double* u) {
+  API_BEGIN
+  use_device(h);
+  require_hierarchy(h);
+  RMG_REQUIRE(level >= 0 && level + 1 < (int)h->levels.size(), RMG_ERR_ARG, "no coarser level");
+  RMG_REQUIRE(ubar && u, RMG_ERR_ARG, "null pointer");
+  launch_prolong_add(*h->levels[level], *h->levels[level + 1], ubar, u, h->stream);
+  API_END
+}
+
+rmg_status rmg_smooth(rmg_handle* h, int level, const double* b, double* u) {
+  API_BEGIN
+  use_device(h);
+  require_hierarchy(h);
+  RMG_REQUIRE(level >= 0 && level + 1 < (int)h->levels.size(), RMG_ERR_ARG, "the coarsest level has no smoother");
+  RMG_REQUIRE(b && u && b != u, RMG_ERR_ARG, "b and u must be distinct non-null device pointers");
+  smooth_zero_guess(h, level, b, u);
+  API_END
+}
+
+rmg_status rmg_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t* n_composite, int* npts,
+                          double* lambda_max) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  if (n_regional) *n_regional = L.n * h->ndof;
+  if (n_composite) *n_composite = L.ncomp * h->ndof;
+  if (npts) *npts = L.npts;
+  if (lambda_max) *lambda_max = L.lambda;
+  API_END
+}
+
+rmg_status rmg_get_level_stencil(rmg_handle* h, int level, int region, double* host_out) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  RMG_REQUIRE(region >= 0 && region < L.nreg && host_out, RMG_ERR_ARG, "bad region or null output");
+  RMG_REQUIRE(L.coef.p != nullptr, RMG_ERR_NOT_SETUP, "no operator on this level");
+  const RegionGeo& R = L.regs[region];
+  for (int s = 0; s < L.npts; ++s)
+    RMG_HIP(hipMemcpyAsync(host_out + (size_t)s * R.n, L.coef.as<double>() + (size_t)s * L.n + R.off,
+                           sizeof(double) * R.n, hipMemcpyDeviceToHost, h->stream));
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  API_END
+}
+
+rmg_status rmg_get_coarse_matrix(rmg_handle* h, double* host_out) {
+  API_BEGIN
+  use_device(h);
+  require_hierarchy(h);
+  RMG_REQUIRE(host_out, RMG_ERR_ARG, "null output");
+  Level& L = *h->levels.back();
+  std::memcpy(host_out, L.abar_host.data(), sizeof(double) * L.abar_host.size());
+  API_END
+}
+
+}  // extern "C"

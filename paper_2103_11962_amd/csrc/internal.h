@@ -1,0 +1,147 @@
+// Internal data structures of the regional multigrid library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/regmg.h"
+
+namespace rmg {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  rmg_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(rmg_status code, const std::string& msg);
+void set_last_error(const std::string& msg);
+
+#define RMG_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      ::rmg::fail(e_ == hipErrorOutOfMemory ? RMG_ERR_OOM : RMG_ERR_DEVICE,                \
+                  std::string(#call " failed: ") + hipGetErrorString(e_));                 \
+  } while (0)
+
+#define RMG_REQUIRE(cond, code, msg) \
+  do {                               \
+    if (!(cond)) ::rmg::fail(code, msg); \
+  } while (0)
+
+// ------------------------------------------------------- device geometry
+// One region on one level.  2D problems use ez = oz = 0 extents of 1.
+struct RegionGeo {
+  int ex, ey, ez;     // node extents
+  int ox, oy, oz;     // composite coordinates of local node (0,0,0)
+  int64_t off;        // first node of the region in the level's regional vector
+  int n;              // ex*ey*ez
+  int pad;
+};
+
+// A block of consecutive nodes of one region: the unit of work of node-parallel kernels.
+struct BlockDesc {
+  int region;
+  int start;  // first local node index
+};
+
+constexpr int kBlock = 256;  // threads per block for node-parallel kernels
+
+// Everything a kernel needs to know about a level, passed by value.
+struct LevelView {
+  const RegionGeo* regs;
+  const BlockDesc* blocks;
+  int nblocks;
+  int nreg;
+  int64_t n;         // regional nodes on the level
+  int cx, cy, cz;    // composite node extents
+  unsigned mask;     // Dirichlet faces
+  int npts;          // stencil points stored (5, 9 or 27)
+};
+
+// Device buffer owned by the library.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void alloc(size_t nbytes);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+  ~DBuf() { release(); }
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+};
+
+struct Level {
+  int dim = 3;
+  int npts = 27;
+  int nreg = 0;
+  unsigned mask = 0;   // Dirichlet faces
+  int comp[3] = {1, 1, 1};
+  int64_t n = 0;       // regional nodes
+  int64_t ncomp = 0;   // composite nodes
+  std::vector<RegionGeo> regs;
+  std::vector<BlockDesc> blocks;
+  DBuf d_regs, d_blocks;
+  // interface groups: copies of each shared composite node, ascending region order
+  int64_t ngroups = 0;
+  DBuf d_gptr;    // int64 [ngroups+1]
+  DBuf d_gcopy;   // int32 regional node indices
+  DBuf d_gcomp;   // int32 composite node index of each group
+  // operator
+  DBuf coef;      // double [npts][n]
+  DBuf dinv;      // double [n]
+  double lambda = 0.0;
+  std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step: direction and residual factors
+  // work vectors (regional): b (rhs), u / u2 (ping-pong), d (Chebyshev direction), r (residual)
+  DBuf b, u, u2, d, r;
+  // coarsest level: composite inverse and owner map
+  int nc = 0;
+  DBuf ainv;       // double [nc][nc]
+  DBuf comp_owner; // int32 [nc] regional index of the owner copy
+  DBuf cvec, cvec2;  // double [nc]
+  std::vector<double> abar_host;  // dense composite coarse operator (for inspection)
+
+  LevelView view() const;
+};
+
+}  // namespace rmg
+
+struct rmg_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int dim = 0, ndof = 1, nreg = 0;
+  unsigned mask = 0;
+  std::vector<int32_t> extent, origin;  // finest level, [nreg][3] (2D padded)
+  bool have_regions = false, have_operator = false, have_hierarchy = false;
+  std::vector<bool> region_set;
+  rmg_options opt{};
+  std::vector<rmg::Level*> levels;
+  // CG work vectors (finest level, regional)
+  rmg::DBuf cg_x, cg_r, cg_p, cg_q, cg_z, cg_b, tmp_a, tmp_b;
+  rmg::DBuf partials;   // double partial sums
+  rmg::DBuf scalars;    // double device scalars
+  double* host_scalars = nullptr;  // pinned
+  ~rmg_handle();
+};
+
+namespace rmg {
+
+// planner.cpp
+void build_level0(rmg_handle* h);
+Level* make_coarse_level(const Level& fine);
+void build_tables(Level& L);
+void build_coarse_solver(rmg_handle* h, Level& L);
+
+// solver.cpp
+void setup_hierarchy(rmg_handle* h);
+// z = V_level(b) with zero initial guess; z must not be one of the level's work vectors.
+void vcycle(rmg_handle* h, int level, const double* b, double* z);
+void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
+         rmg_status* st);
+void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out);
+
+}  // namespace rmg

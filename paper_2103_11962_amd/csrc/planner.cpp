@@ -1,0 +1,269 @@
+// Host planner: region validation, level geometry, block tables, interface groups,
+// and the coarsest-level composite operator.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "kernels.h"
+
+namespace rmg {
+
+void DBuf::alloc(size_t nbytes) {
+  release();
+  if (nbytes == 0) return;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    fail(e == hipErrorOutOfMemory ? RMG_ERR_OOM : RMG_ERR_DEVICE,
+         "hipMalloc of " + std::to_string(nbytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  bytes = nbytes;
+}
+
+void DBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+LevelView Level::view() const {
+  LevelView v;
+  v.regs = d_regs.as<RegionGeo>();
+  v.blocks = d_blocks.as<BlockDesc>();
+  v.nblocks = (int)blocks.size();
+  v.nreg = nreg;
+  v.n = n;
+  v.cx = comp[0];
+  v.cy = comp[1];
+  v.cz = comp[2];
+  v.mask = mask;
+  v.npts = npts;
+  return v;
+}
+
+static bool shared_node(const Level& L, const RegionGeo& R, int x, int y, int z) {
+  const int gx = R.ox + x, gy = R.oy + y, gz = R.oz + z;
+  return (x == 0 && gx != 0) || (x == R.ex - 1 && gx != L.comp[0] - 1) || (y == 0 && gy != 0) ||
+         (y == R.ey - 1 && gy != L.comp[1] - 1) || (z == 0 && gz != 0) || (z == R.ez - 1 && gz != L.comp[2] - 1);
+}
+
+// Offsets, block table and interface groups of a level whose regs/comp are set.
+void build_tables(Level& L) {
+  int64_t off = 0;
+  L.blocks.clear();
+  for (int k = 0; k < L.nreg; ++k) {
+    RegionGeo& R = L.regs[k];
+    R.n = R.ex * R.ey * R.ez;
+    R.off = off;
+    off += R.n;
+    for (int s = 0; s < R.n; s += kBlock) L.blocks.push_back(BlockDesc{k, s});
+  }
+  L.n = off;
+  RMG_REQUIRE(L.n < (int64_t)1 << 31, RMG_ERR_ARG, "more than 2^31 regional nodes on one level");
+  L.ncomp = (int64_t)L.comp[0] * L.comp[1] * L.comp[2];
+  RMG_REQUIRE(L.ncomp < (int64_t)1 << 31, RMG_ERR_ARG, "more than 2^31 composite nodes");
+
+  // Interface groups: (composite index, regional index) pairs of every shared surface node,
+  // sorted by composite index; regional indices grow with the region id, so each group lists
+  // its copies in ascending region order.
+  std::vector<uint64_t> keys;
+  for (int k = 0; k < L.nreg; ++k) {
+    const RegionGeo& R = L.regs[k];
+    for (int z = 0; z < R.ez; ++z)
+      for (int y = 0; y < R.ey; ++y) {
+        const bool yz_face = (y == 0 || y == R.ey - 1 || z == 0 || z == R.ez - 1);
+        for (int x = 0; x < R.ex; x += (yz_face ? 1 : std::max(1, R.ex - 1))) {
+          if (!shared_node(L, R, x, y, z)) continue;
+          const int64_t c = ((int64_t)(R.oz + z) * L.comp[1] + (R.oy + y)) * L.comp[0] + (R.ox + x);
+          const int64_t ri = R.off + ((int64_t)z * R.ey + y) * R.ex + x;
+          keys.push_back(((uint64_t)c << 32) | (uint64_t)ri);
+        }
+      }
+  }
+  std::sort(keys.begin(), keys.end());
+  std::vector<int64_t> gptr;
+  std::vector<int32_t> gcopy, gcomp;
+  gptr.push_back(0);
+  for (size_t i = 0; i < keys.size();) {
+    size_t j = i;
+    const uint64_t c = keys[i] >> 32;
+    while (j < keys.size() && (keys[j] >> 32) == c) {
+      gcopy.push_back((int32_t)(keys[j] & 0xffffffffu));
+      ++j;
+    }
+    RMG_REQUIRE(j - i >= 2, RMG_ERR_SHAPE,
+                "a node on an inner region face belongs to one region only: boxes do not conform");
+    gcomp.push_back((int32_t)c);
+    gptr.push_back((int64_t)gcopy.size());
+    i = j;
+  }
+  // Order groups by multiplicity (faces, then edges, then corners) so a wavefront mostly sees
+  // groups of one size.
+  const int64_t ng = (int64_t)gcomp.size();
+  std::vector<int64_t> order(ng);
+  for (int64_t g = 0; g < ng; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return (gptr[a + 1] - gptr[a]) < (gptr[b + 1] - gptr[b]);
+  });
+  std::vector<int64_t> gptr2(1, 0);
+  std::vector<int32_t> gcopy2, gcomp2;
+  gcopy2.reserve(gcopy.size());
+  for (int64_t g : order) {
+    for (int64_t c = gptr[g]; c < gptr[g + 1]; ++c) gcopy2.push_back(gcopy[c]);
+    gptr2.push_back((int64_t)gcopy2.size());
+    gcomp2.push_back(gcomp[g]);
+  }
+  L.ngroups = ng;
+  L.d_regs.alloc(sizeof(RegionGeo) * L.regs.size());
+  RMG_HIP(hipMemcpy(L.d_regs.p, L.regs.data(), sizeof(RegionGeo) * L.regs.size(), hipMemcpyHostToDevice));
+  L.d_blocks.alloc(sizeof(BlockDesc) * L.blocks.size());
+  RMG_HIP(hipMemcpy(L.d_blocks.p, L.blocks.data(), sizeof(BlockDesc) * L.blocks.size(), hipMemcpyHostToDevice));
+  if (ng > 0) {
+    L.d_gptr.alloc(sizeof(int64_t) * gptr2.size());
+    RMG_HIP(hipMemcpy(L.d_gptr.p, gptr2.data(), sizeof(int64_t) * gptr2.size(), hipMemcpyHostToDevice));
+    L.d_gcopy.alloc(sizeof(int32_t) * gcopy2.size());
+    RMG_HIP(hipMemcpy(L.d_gcopy.p, gcopy2.data(), sizeof(int32_t) * gcopy2.size(), hipMemcpyHostToDevice));
+    L.d_gcomp.alloc(sizeof(int32_t) * gcomp2.size());
+    RMG_HIP(hipMemcpy(L.d_gcomp.p, gcomp2.data(), sizeof(int32_t) * gcomp2.size(), hipMemcpyHostToDevice));
+  }
+}
+
+// Region boxes must tile the bounding box of the domain: the element (cell) volumes add up
+// to the bounding box volume and no two cell boxes intersect.
+static void validate_tiling(int dim, int nreg, const std::vector<int32_t>& ext, const std::vector<int32_t>& org,
+                            const int comp[3]) {
+  int64_t vol = 0;
+  for (int k = 0; k < nreg; ++k) {
+    int64_t v = 1;
+    for (int d = 0; d < dim; ++d) v *= ext[3 * k + d] - 1;
+    vol += v;
+  }
+  int64_t total = 1;
+  for (int d = 0; d < dim; ++d) total *= comp[d] - 1;
+  RMG_REQUIRE(vol == total, RMG_ERR_SHAPE, "region boxes do not cover the domain exactly once");
+  for (int a = 0; a < nreg; ++a)
+    for (int b = a + 1; b < nreg; ++b) {
+      bool overlap = true;
+      for (int d = 0; d < dim; ++d) {
+        const int lo = std::max(org[3 * a + d], org[3 * b + d]);
+        const int hi = std::min(org[3 * a + d] + ext[3 * a + d] - 1, org[3 * b + d] + ext[3 * b + d] - 1);
+        if (hi - lo <= 0) overlap = false;  // cell ranges [o, o+e-1) do not intersect
+      }
+      RMG_REQUIRE(!overlap, RMG_ERR_SHAPE,
+                  "regions " + std::to_string(a) + " and " + std::to_string(b) + " overlap in more than an interface");
+    }
+}
+
+void build_level0(rmg_handle* h) {
+  Level* L = new Level();
+  L->dim = h->dim;
+  L->nreg = h->nreg;
+  L->npts = h->dim == 3 ? 27 : 9;
+  L->mask = h->mask;
+  L->comp[0] = L->comp[1] = L->comp[2] = 1;
+  L->regs.resize(h->nreg);
+  for (int k = 0; k < h->nreg; ++k) {
+    RegionGeo& R = L->regs[k];
+    R.ex = h->extent[3 * k + 0];
+    R.ey = h->extent[3 * k + 1];
+    R.ez = h->extent[3 * k + 2];
+    R.ox = h->origin[3 * k + 0];
+    R.oy = h->origin[3 * k + 1];
+    R.oz = h->origin[3 * k + 2];
+    R.pad = 0;
+    L->comp[0] = std::max(L->comp[0], R.ox + R.ex);
+    L->comp[1] = std::max(L->comp[1], R.oy + R.ey);
+    L->comp[2] = std::max(L->comp[2], R.oz + R.ez);
+  }
+  validate_tiling(h->dim, h->nreg, h->extent, h->origin, L->comp);
+  build_tables(*L);
+  for (Level* old : h->levels) delete old;
+  h->levels.clear();
+  h->levels.push_back(L);
+}
+
+Level* make_coarse_level(const Level& F) {
+  Level* C = new Level();
+  C->dim = F.dim;
+  C->nreg = F.nreg;
+  C->npts = F.dim == 3 ? 27 : 9;
+  C->mask = F.mask;
+  for (int d = 0; d < 3; ++d) {
+    const int n = F.comp[d];
+    C->comp[d] = (d < F.dim) ? (n - 1) / 3 + 1 : 1;
+  }
+  C->regs.resize(F.nreg);
+  for (int k = 0; k < F.nreg; ++k) {
+    const RegionGeo& R = F.regs[k];
+    RegionGeo& Q = C->regs[k];
+    Q.ex = (R.ex - 1) / 3 + 1;
+    Q.ey = (R.ey - 1) / 3 + 1;
+    Q.ez = F.dim == 3 ? (R.ez - 1) / 3 + 1 : 1;
+    Q.ox = R.ox / 3;
+    Q.oy = R.oy / 3;
+    Q.oz = R.oz / 3;
+    Q.pad = 0;
+  }
+  build_tables(*C);
+  return C;
+}
+
+// Coarsest level: Abar = Psi-bar [[Abar]] Psi-bar^T assembled densely on the host from the
+// regional stencils, then inverted on the device (Section 3.5, direct solver).
+void build_coarse_solver(rmg_handle* h, Level& L) {
+  hipStream_t st = h->stream;
+  const int64_t nc64 = L.ncomp;
+  RMG_REQUIRE(nc64 <= 20000, RMG_ERR_ARG, "coarsest composite problem too large for the dense solver");
+  const int nc = (int)nc64;
+  L.nc = nc;
+  std::vector<double> coef((size_t)L.npts * L.n);
+  RMG_HIP(hipMemcpyAsync(coef.data(), L.coef.p, sizeof(double) * coef.size(), hipMemcpyDeviceToHost, st));
+  RMG_HIP(hipStreamSynchronize(st));
+  L.abar_host.assign((size_t)nc * nc, 0.0);
+  std::vector<int32_t> owner(nc, -1);
+  for (int k = 0; k < L.nreg; ++k) {
+    const RegionGeo& R = L.regs[k];
+    for (int z = 0; z < R.ez; ++z)
+      for (int y = 0; y < R.ey; ++y)
+        for (int x = 0; x < R.ex; ++x) {
+          const int64_t li = ((int64_t)z * R.ey + y) * R.ex + x;
+          const int64_t i = ((int64_t)(R.oz + z) * L.comp[1] + (R.oy + y)) * L.comp[0] + (R.ox + x);
+          if (owner[i] < 0) owner[i] = (int32_t)(R.off + li);
+          for (int s = 0; s < L.npts; ++s) {
+            int dx, dy, dz;
+            if (L.npts == 27) {
+              dx = s % 3 - 1;
+              dy = (s / 3) % 3 - 1;
+              dz = s / 9 - 1;
+            } else {
+              dx = s % 3 - 1;
+              dy = s / 3 - 1;
+              dz = 0;
+            }
+            if (x + dx < 0 || x + dx >= R.ex || y + dy < 0 || y + dy >= R.ey || z + dz < 0 || z + dz >= R.ez) continue;
+            const double v = coef[(size_t)s * L.n + R.off + li];
+            if (v == 0.0) continue;
+            const int64_t j = ((int64_t)(R.oz + z + dz) * L.comp[1] + (R.oy + y + dy)) * L.comp[0] + (R.ox + x + dx);
+            L.abar_host[(size_t)i * nc + j] += v;
+          }
+        }
+  }
+  L.ainv.alloc(sizeof(double) * (size_t)nc * nc);
+  RMG_HIP(hipMemcpyAsync(L.ainv.p, L.abar_host.data(), sizeof(double) * (size_t)nc * nc, hipMemcpyHostToDevice, st));
+  L.comp_owner.alloc(sizeof(int32_t) * nc);
+  RMG_HIP(hipMemcpyAsync(L.comp_owner.p, owner.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st));
+  L.cvec.alloc(sizeof(double) * nc);
+  L.cvec2.alloc(sizeof(double) * nc);
+  DBuf flag;
+  flag.alloc(sizeof(int));
+  RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  launch_gauss_jordan(L.ainv.as<double>(), nc, L.cvec.as<double>(), L.cvec2.as<double>(), st);
+  launch_check_inverse(L.ainv.as<double>(), nc, flag.as<int>(), st);
+  int hflag = 0;
+  RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  RMG_HIP(hipStreamSynchronize(st));
+  RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "coarsest composite operator is not symmetric positive definite");
+}
+
+}  // namespace rmg

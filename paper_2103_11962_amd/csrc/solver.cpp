@@ -1,0 +1,299 @@
+// Hierarchy setup, regional V-cycle and preconditioned CG (host orchestration of the kernels).
+#include <cmath>
+#include <string>
+
+#include "kernels.h"
+
+namespace rmg {
+
+static int64_t partial_capacity(const Level& L) {
+  return (int64_t)L.blocks.size() + (L.ngroups + kBlock - 1) / kBlock + 16;
+}
+
+static double* scal(rmg_handle* h) { return h->scalars.as<double>(); }
+
+static void read_scalars(rmg_handle* h) {
+  RMG_HIP(hipMemcpyAsync(h->host_scalars, h->scalars.p, sizeof(double) * kNumSlots, hipMemcpyDeviceToHost,
+                         h->stream));
+  RMG_HIP(hipStreamSynchronize(h->stream));
+}
+
+static void dot(rmg_handle* h, const Level& L, const double* a, const double* b, int slot) {
+  const int64_t np = launch_dot(L, a, b, h->partials.as<double>(), h->stream);
+  launch_reduce(h->partials.as<double>(), np, scal(h), slot, h->stream);
+}
+
+// lambda_max(D~^-1 Psi^T Psi [[A]]) by power iteration: x <- x0/|x0|; y = D~^-1 A x,
+// lambda = (x, y), x = y/|y| (Section 3.4; start vector from the counter generator).
+static double power_method(rmg_handle* h, Level& L, int level) {
+  hipStream_t st = h->stream;
+  double* x = L.u.as<double>();
+  double* y = L.u2.as<double>();
+  double* t = L.r.as<double>();
+  launch_start_vector(L, level, h->opt.seed, x, st);
+  dot(h, L, x, x, kTmp);
+  launch_scale(L.n, scal(h), kTmp, 0, x, x, st);
+  for (int it = 0; it < h->opt.power_iters; ++it) {
+    StencilArgs a;
+    a.op = StencilOp::Matvec;
+    a.x = x;
+    a.out = t;
+    launch_stencil_op(L, a, st);
+    launch_mul(L.n, L.dinv.as<double>(), t, y, st);
+    dot(h, L, x, y, kTmp2);
+    dot(h, L, y, y, kTmp);
+    launch_scale(L.n, scal(h), kTmp, 0, y, x, st);
+  }
+  read_scalars(h);
+  return h->host_scalars[kTmp2];
+}
+
+static void chebyshev_coefficients(const rmg_options& o, Level& L) {
+  const double alpha = L.lambda / o.eig_ratio;
+  const double beta = o.boost * L.lambda;
+  const double theta = 0.5 * (alpha + beta);
+  const double delta = 2.0 / (beta - alpha);
+  L.cheb_c1.assign(o.cheb_degree, 0.0);
+  L.cheb_c2.assign(o.cheb_degree, 0.0);
+  double rho = 1.0 / (theta * delta);
+  L.cheb_c2[0] = 1.0 / theta;  // first correction d = D~^-1 r / theta
+  for (int k = 1; k < o.cheb_degree; ++k) {
+    const double rho_old = rho;
+    rho = 1.0 / (2.0 * theta * delta - rho_old);
+    L.cheb_c1[k] = rho * rho_old;
+    L.cheb_c2[k] = 2.0 * rho * delta;
+  }
+}
+
+static void alloc_vectors(Level& L, bool with_b) {
+  const size_t bytes = sizeof(double) * (size_t)L.n;
+  if (with_b) L.b.alloc(bytes);
+  L.u.alloc(bytes);
+  L.u2.alloc(bytes);
+  L.d.alloc(bytes);
+  L.r.alloc(bytes);
+}
+
+void setup_hierarchy(rmg_handle* h) {
+  const rmg_options& o = h->opt;
+  hipStream_t st = h->stream;
+  Level* L0 = h->levels[0];
+  for (size_t i = 1; i < h->levels.size(); ++i) delete h->levels[i];
+  h->levels.resize(1);
+  int64_t f = 1;
+  for (int l = 1; l < o.nlevels; ++l) f *= 3;
+  for (int k = 0; k < L0->nreg; ++k) {
+    const RegionGeo& R = L0->regs[k];
+    const int e[3] = {R.ex, R.ey, R.ez}, g[3] = {R.ox, R.oy, R.oz};
+    for (int d = 0; d < L0->dim; ++d)
+      RMG_REQUIRE((e[d] - 1) % f == 0 && g[d] % f == 0, RMG_ERR_SHAPE,
+                  "region " + std::to_string(k) + ": extent-1 and origin must be divisible by 3^(nlevels-1) = " +
+                      std::to_string(f));
+  }
+  h->partials.alloc(sizeof(double) * partial_capacity(*L0));
+  DBuf flag;
+  flag.alloc(sizeof(int));
+  for (int l = 0; l < o.nlevels; ++l) {
+    Level& L = *h->levels[l];
+    alloc_vectors(L, l > 0);
+    if (l == o.nlevels - 1) {
+      build_coarse_solver(h, L);
+      break;
+    }
+    // D~ = Psi^T Psi diag([[A]]), then its reciprocal (Section 3.2, smoother setup)
+    L.dinv.alloc(sizeof(double) * (size_t)L.n);
+    launch_diag(L, L.r.as<double>(), st);
+    launch_interface_sum(L, L.r.as<double>(), L.r.as<double>(), st);
+    RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+    launch_recip_check(L.n, L.r.as<double>(), L.dinv.as<double>(), flag.as<int>(), st);
+    int hflag = 0;
+    RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    RMG_HIP(hipStreamSynchronize(st));
+    RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "composite diagonal not positive on level " + std::to_string(l));
+    L.lambda = power_method(h, L, l);
+    RMG_REQUIRE(std::isfinite(L.lambda) && L.lambda > 0.0, RMG_ERR_NUMERIC,
+                "power method failed on level " + std::to_string(l));
+    chebyshev_coefficients(o, L);
+    // next level: geometry, then the per-region Galerkin product on the device
+    Level* C = make_coarse_level(L);
+    C->coef.alloc(sizeof(double) * (size_t)C->npts * C->n);
+    launch_rap(L, *C, st);
+    h->levels.push_back(C);
+  }
+  RMG_HIP(hipStreamSynchronize(st));
+}
+
+static void cheb_step(rmg_handle* h, Level& L, int k, bool first, const double* b, const double* uin, double* uout,
+                      const double* dotw = nullptr, double* partials = nullptr, int64_t* np = nullptr) {
+  StencilArgs a;
+  a.op = first ? StencilOp::ChebFirst : StencilOp::Cheb;
+  a.x = uin;
+  a.out = uout;
+  a.b = b;
+  a.dinv = L.dinv.as<double>();
+  a.d = L.d.as<double>();
+  a.c1 = L.cheb_c1[k];
+  a.c2 = L.cheb_c2[k];
+  a.dotw = dotw;
+  a.partials = partials;
+  const int64_t n = launch_stencil_op(L, a, h->stream);
+  if (np) *np = n;
+}
+
+void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out) {
+  Level& L = *h->levels[level];
+  hipStream_t st = h->stream;
+  const int K = h->opt.cheb_degree;
+  double* buf[2] = {L.u.as<double>(), u_out};
+  launch_cheb_zero(L, b, L.dinv.as<double>(), L.cheb_c2[0], L.d.as<double>(), buf[0], st);
+  int cur = 0;
+  for (int k = 1; k < K; ++k) {
+    cheb_step(h, L, k, false, b, buf[cur], buf[1 - cur]);
+    cur = 1 - cur;
+  }
+  if (buf[cur] != u_out) launch_copy(L.n, buf[cur], u_out, st);
+}
+
+void vcycle(rmg_handle* h, int level, const double* b, double* z) {
+  const int nl = (int)h->levels.size();
+  Level& L = *h->levels[level];
+  hipStream_t st = h->stream;
+  if (level == nl - 1) {
+    launch_coarse_solve(L, b, z, st);
+    return;
+  }
+  const int K = h->opt.cheb_degree;
+  // ping-pong buffers arranged so that the last post-smoothing step writes z
+  double* buf[2] = {L.u.as<double>(), z};
+  launch_cheb_zero(L, b, L.dinv.as<double>(), L.cheb_c2[0], L.d.as<double>(), buf[0], st);
+  int cur = 0;
+  for (int k = 1; k < K; ++k) {
+    cheb_step(h, L, k, false, b, buf[cur], buf[1 - cur]);
+    cur = 1 - cur;
+  }
+  // residual divided by multiplicity, restriction and coarse interface sum (Section 3.3)
+  StencilArgs a;
+  a.op = StencilOp::ResidualScaled;
+  a.x = buf[cur];
+  a.out = L.r.as<double>();
+  a.b = b;
+  launch_stencil_op(L, a, st);
+  Level& C = *h->levels[level + 1];
+  launch_restrict(L, C, L.r.as<double>(), C.b.as<double>(), st);
+  vcycle(h, level + 1, C.b.as<double>(), C.u2.as<double>());
+  launch_prolong_add(L, C, C.u2.as<double>(), buf[cur], st);
+  for (int k = 0; k < K; ++k) {
+    cheb_step(h, L, k, k == 0, b, buf[cur], buf[1 - cur]);
+    cur = 1 - cur;
+  }
+  RMG_REQUIRE(buf[cur] == z, RMG_ERR_ARG, "internal: V-cycle buffer parity");
+}
+
+void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
+         rmg_status* status) {
+  Level& L = *h->levels[0];
+  hipStream_t st = h->stream;
+  const int64_t n = L.n;
+  double* r = h->cg_r.as<double>();
+  double* p = h->cg_p.as<double>();
+  double* q = h->cg_q.as<double>();
+  double* z = h->cg_z.as<double>();
+  double* part = h->partials.as<double>();
+  hipEvent_t e0, e1;
+  RMG_HIP(hipEventCreate(&e0));
+  RMG_HIP(hipEventCreate(&e1));
+  RMG_HIP(hipEventRecord(e0, st));
+  *status = RMG_OK;
+  int hist_len = 0;
+  auto push_hist = [&](double v) {
+    if (info && info->history && hist_len < info->history_cap) info->history[hist_len] = v;
+    ++hist_len;
+  };
+  // r = b - A x0
+  {
+    StencilArgs a;
+    a.op = StencilOp::Residual;
+    a.x = x;
+    a.out = r;
+    a.b = b;
+    launch_stencil_op(L, a, st);
+  }
+  dot(h, L, b, b, kBB);
+  read_scalars(h);
+  const double bnorm = std::sqrt(h->host_scalars[kBB]);
+  int it = 0;
+  double rel = 1.0;
+  bool converged = false;
+  push_hist(1.0);
+  if (bnorm == 0.0) {
+    launch_zero(n, x, st);
+    rel = 0.0;
+    converged = true;
+  } else {
+    vcycle(h, 0, r, z);
+    launch_copy(n, z, p, st);
+    dot(h, L, r, z, kRZ);
+    while (it < maxit) {
+      StencilArgs a;
+      a.op = StencilOp::CgQ;
+      a.x = p;
+      a.out = q;
+      a.partials = part;
+      const int64_t np = launch_stencil_op(L, a, st);
+      launch_reduce(part, np, scal(h), kPQ, st);
+      launch_cg_scalars(scal(h), 0, st);
+      const int64_t nu = launch_cg_update(L, scal(h), x, r, p, q, part, st);
+      launch_reduce(part, nu, scal(h), kRR, st);
+      ++it;
+      read_scalars(h);
+      const double rz = h->host_scalars[kRZ], pq = h->host_scalars[kPQ], rr = h->host_scalars[kRR];
+      if (!(pq > 0.0) || !(rz > 0.0) || !std::isfinite(rr)) {
+        *status = RMG_ERR_BREAKDOWN;
+        set_last_error("CG breakdown: (r,z) = " + std::to_string(rz) + ", (p,Ap) = " + std::to_string(pq));
+        rel = std::sqrt(std::fabs(rr)) / bnorm;
+        break;
+      }
+      rel = std::sqrt(rr) / bnorm;
+      push_hist(rel);
+      if (rel <= rtol) {
+        converged = true;
+        break;
+      }
+      if (it >= maxit) break;
+      vcycle(h, 0, r, z);
+      dot(h, L, r, z, kRZnew);
+      launch_cg_scalars(scal(h), 1, st);
+      launch_cg_direction(n, scal(h), z, p, st);
+    }
+  }
+  RMG_HIP(hipEventRecord(e1, st));
+  // true residual
+  {
+    StencilArgs a;
+    a.op = StencilOp::Residual;
+    a.x = x;
+    a.out = q;
+    a.b = b;
+    launch_stencil_op(L, a, st);
+  }
+  dot(h, L, q, q, kTmp);
+  read_scalars(h);
+  float ms = 0.f;
+  RMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (*status == RMG_OK && !converged) {
+    *status = RMG_ERR_NOT_CONVERGED;
+    set_last_error("CG did not reach rtol within maxit iterations");
+  }
+  if (info) {
+    info->iterations = it;
+    info->converged = converged ? 1 : 0;
+    info->relres = rel;
+    info->true_relres = bnorm > 0.0 ? std::sqrt(h->host_scalars[kTmp]) / bnorm : 0.0;
+    info->solve_ms = ms;
+    info->history_len = hist_len;
+  }
+}
+
+}  // namespace rmg

@@ -1,0 +1,268 @@
+"""Python binding of the regmg C ABI (argument marshalling only).
+
+Every computation runs inside the HIP library ``_lib/libregmg.so``; this module
+only converts torch tensors / numpy arrays to pointers and status codes to
+exceptions.  Device vectors are torch tensors on the HIP device (float64,
+contiguous).  The library must be built first (``__graft_entry__.build()``);
+loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libregmg.so")
+
+LAYOUT_COMPOSITE = 0
+LAYOUT_REGIONAL = 1
+PDE_LAPLACE, PDE_DIFFUSION, PDE_ELASTICITY = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
+
+STATUS = {
+    0: "RMG_OK", 1: "RMG_ERR_ARG", 2: "RMG_ERR_SHAPE", 3: "RMG_ERR_NUMERIC", 4: "RMG_ERR_DEVICE",
+    5: "RMG_ERR_OOM", 6: "RMG_ERR_NOT_SETUP", 7: "RMG_ERR_BREAKDOWN", 8: "RMG_ERR_NOT_CONVERGED",
+}
+
+# every symbol the public header declares
+SYMBOLS = (
+    "rmg_options_default", "rmg_create", "rmg_destroy", "rmg_last_error", "rmg_build_regions",
+    "rmg_set_region_stencil", "rmg_set_composite_stencil", "rmg_assemble_q1", "rmg_setup_hierarchy",
+    "rmg_apply_vcycle", "rmg_solve", "rmg_to_regional", "rmg_to_composite", "rmg_regional_matvec",
+    "rmg_interface_sum", "rmg_restrict", "rmg_prolongate_add", "rmg_smooth", "rmg_level_info",
+    "rmg_get_level_stencil", "rmg_get_coarse_matrix",
+)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("nlevels", ctypes.c_int),
+        ("cheb_degree", ctypes.c_int),
+        ("eig_ratio", ctypes.c_double),
+        ("boost", ctypes.c_double),
+        ("power_iters", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("precision", ctypes.c_int),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("relres", ctypes.c_double),
+        ("true_relres", ctypes.c_double),
+        ("solve_ms", ctypes.c_double),
+        ("history", ctypes.POINTER(ctypes.c_double)),
+        ("history_cap", ctypes.c_int),
+        ("history_len", ctypes.c_int),
+    ]
+
+
+class RmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+_lib = None
+
+
+def load():
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"regmg library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.c_double
+    H = ctypes.c_void_p
+    sig = {
+        "rmg_options_default": (None, [ctypes.POINTER(Options)]),
+        "rmg_create": (I, [ctypes.POINTER(H), I, P]),
+        "rmg_destroy": (I, [H]),
+        "rmg_last_error": (ctypes.c_char_p, []),
+        "rmg_build_regions": (I, [H, I, I, I, P, P, ctypes.c_uint32]),
+        "rmg_set_region_stencil": (I, [H, I, I, P, I]),
+        "rmg_set_composite_stencil": (I, [H, I, P, I]),
+        "rmg_assemble_q1": (I, [H, I, D, P, P, D]),
+        "rmg_setup_hierarchy": (I, [H, ctypes.POINTER(Options)]),
+        "rmg_apply_vcycle": (I, [H, P, P, I]),
+        "rmg_solve": (I, [H, P, P, I, D, I, ctypes.POINTER(SolveInfo)]),
+        "rmg_to_regional": (I, [H, I, P, P]),
+        "rmg_to_composite": (I, [H, I, P, P, I]),
+        "rmg_regional_matvec": (I, [H, I, P, P]),
+        "rmg_interface_sum": (I, [H, I, P, P]),
+        "rmg_restrict": (I, [H, I, P, P]),
+        "rmg_prolongate_add": (I, [H, I, P, P]),
+        "rmg_smooth": (I, [H, I, P, P]),
+        "rmg_level_info": (I, [H, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "rmg_get_level_stencil": (I, [H, I, I, P]),
+        "rmg_get_coarse_matrix": (I, [H, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != 0:
+        raise RmgError(code, load().rmg_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64 torch tensor."""
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_contiguous() or t.dtype != torch.float64:
+        raise ValueError("device vectors must be contiguous float64 tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().rmg_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Handle:
+    """One solver instance on one HIP device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.rmg_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().rmg_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---------------------------------------------------------------- setup
+    def build_regions(self, dim, ndof, extents, origins, dirichlet_mask):
+        ext = np.ascontiguousarray(extents, dtype=np.int32).reshape(-1)
+        org = np.ascontiguousarray(origins, dtype=np.int32).reshape(-1)
+        nreg = ext.size // dim
+        _check(load().rmg_build_regions(self._h, dim, ndof, nreg, ext.ctypes.data_as(ctypes.c_void_p),
+                                        org.ctypes.data_as(ctypes.c_void_p), dirichlet_mask))
+
+    def set_region_stencil(self, region, npts, coef):
+        import torch
+
+        if isinstance(coef, torch.Tensor):
+            _check(load().rmg_set_region_stencil(self._h, region, npts, _ptr(coef), 1))
+        else:
+            c = np.ascontiguousarray(coef, dtype=np.float64)
+            _check(load().rmg_set_region_stencil(self._h, region, npts, c.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def set_composite_stencil(self, npts, coef):
+        import torch
+
+        if isinstance(coef, torch.Tensor):
+            _check(load().rmg_set_composite_stencil(self._h, npts, _ptr(coef), 1))
+        else:
+            c = np.ascontiguousarray(coef, dtype=np.float64)
+            _check(load().rmg_set_composite_stencil(self._h, npts, c.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def assemble_q1(self, pde, h, elem_coef=None, youngs=None, nu=0.3):
+        y = None if youngs is None else np.ascontiguousarray(youngs, dtype=np.float64)
+        _check(load().rmg_assemble_q1(self._h, pde, h, _ptr(elem_coef),
+                                      None if y is None else y.ctypes.data_as(ctypes.c_void_p), nu))
+
+    def setup_hierarchy(self, **kw):
+        o = default_options(**kw)
+        _check(load().rmg_setup_hierarchy(self._h, ctypes.byref(o)))
+
+    # ---------------------------------------------------------------- solve
+    def apply_vcycle(self, r, z, layout=LAYOUT_COMPOSITE):
+        _check(load().rmg_apply_vcycle(self._h, _ptr(r), _ptr(z), layout))
+
+    def solve(self, b, x, layout=LAYOUT_COMPOSITE, rtol=1e-8, maxit=200, history_cap=512, raise_on_fail=True):
+        info = SolveInfo()
+        hist = (ctypes.c_double * history_cap)()
+        info.history = hist
+        info.history_cap = history_cap
+        code = load().rmg_solve(self._h, _ptr(b), _ptr(x), layout, rtol, maxit, ctypes.byref(info))
+        if code != 0 and raise_on_fail:
+            _check(code)
+        out = {
+            "status": STATUS.get(code, code), "iterations": info.iterations, "converged": bool(info.converged),
+            "relres": info.relres, "true_relres": info.true_relres, "solve_ms": info.solve_ms,
+            "history": [hist[i] for i in range(min(info.history_len, history_cap))],
+        }
+        return out
+
+    # --------------------------------------------------------- step hooks
+    def to_regional(self, level, comp, reg):
+        _check(load().rmg_to_regional(self._h, level, _ptr(comp), _ptr(reg)))
+
+    def to_composite(self, level, reg, comp, average=False):
+        _check(load().rmg_to_composite(self._h, level, _ptr(reg), _ptr(comp), int(average)))
+
+    def regional_matvec(self, level, v, z):
+        _check(load().rmg_regional_matvec(self._h, level, _ptr(v), _ptr(z)))
+
+    def interface_sum(self, level, v, w):
+        _check(load().rmg_interface_sum(self._h, level, _ptr(v), _ptr(w)))
+
+    def restrict(self, level, r, w):
+        _check(load().rmg_restrict(self._h, level, _ptr(r), _ptr(w)))
+
+    def prolongate_add(self, level, ubar, u):
+        _check(load().rmg_prolongate_add(self._h, level, _ptr(ubar), _ptr(u)))
+
+    def smooth(self, level, b, u):
+        _check(load().rmg_smooth(self._h, level, _ptr(b), _ptr(u)))
+
+    def level_info(self, level):
+        nr, nc = ctypes.c_int64(), ctypes.c_int64()
+        npts, lam = ctypes.c_int(), ctypes.c_double()
+        _check(load().rmg_level_info(self._h, level, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(npts),
+                                     ctypes.byref(lam)))
+        return {"n_regional": nr.value, "n_composite": nc.value, "npts": npts.value, "lambda": lam.value}
+
+    def level_stencil(self, level, region, npts, nnodes):
+        out = np.zeros(npts * nnodes)
+        _check(load().rmg_get_level_stencil(self._h, level, region, out.ctypes.data_as(ctypes.c_void_p)))
+        return out.reshape(npts, nnodes)
+
+    def coarse_matrix(self, n):
+        out = np.zeros(n * n)
+        _check(load().rmg_get_coarse_matrix(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out.reshape(n, n)

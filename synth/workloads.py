@@ -29,6 +29,7 @@ __all__ = [
     "jump_coefficients",
     "batched_extents",
     "dirichlet_nodes",
+    "fd5_composite_stencil",
 ]
 
 
@@ -222,3 +223,32 @@ def jump_coefficients(w: Workload, seed: int | None = None) -> np.ndarray:
         sl = tuple(slice(int(o), int(o + e - 1)) for o, e in zip(reversed(w.origins[k]), reversed(w.extents[k])))
         c[sl] *= 10.0 ** s[k]
     return c
+
+
+def fd5_composite_stencil(w: Workload) -> np.ndarray:
+    """The 2D five-point problem as an assembled composite stencil, shape (5, ny*nx).
+
+    Stencil order (0,-1), (-1,0), (0,0), (1,0), (0,1); values [-1, -1, 4, -1, -1]
+    with homogeneous Dirichlet nodes kept as identity rows and every coupling to
+    or from them removed.  Couplings leaving the domain are zero.  This is the
+    problem statement A u = b handed to the solver, not part of the solver.
+    """
+    assert w.dim == 2
+    nx, ny = w.composite_shape_xyz
+    dn = dirichlet_nodes((nx, ny), w.dirichlet_mask)
+    offs = [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)]
+    vals = [-1.0, -1.0, 4.0, -1.0, -1.0]
+    out = np.zeros((5, ny, nx))
+    yy, xx = np.indices((ny, nx))
+    for s, ((dx, dy), v) in enumerate(zip(offs, vals)):
+        jx, jy = xx + dx, yy + dy
+        inside = (jx >= 0) & (jx < nx) & (jy >= 0) & (jy < ny)
+        nb_dir = np.zeros_like(inside)
+        nb_dir[inside] = dn[jy[inside], jx[inside]]
+        c = np.where(inside, v, 0.0)
+        if (dx, dy) != (0, 0):
+            c = np.where(dn | nb_dir, 0.0, c)
+        else:
+            c = np.where(dn, 1.0, c)
+        out[s] = c
+    return out.reshape(5, -1)

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP library against the CPU oracle on identical seeded inputs.
+
+Sizes span several 256-node blocks and ragged block tails (region sizes are
+not multiples of 256), uneven regions (c4_small) and both dimensions.
+Tolerances: FP64 operators and single kernels to 1e-12 relative, PCG solutions
+to 1e-10 relative (the FP64 target), interface sums bit-exact (same summation
+order on both sides).
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests import harness
+
+pytestmark = pytest.mark.gpu
+
+SMALL = ["c1_small", "c2_small", "c4_small", "c5_small", "c1", "c2_mid"]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def problems(hip_device):
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            w = synth.workload(name)
+            print(f"[gpu-parity] set up {name}", flush=True)
+            h = harness.gpu_problem(w)
+            o = harness.oracle_problem(w)
+            cache[name] = (w, h, o)
+        return cache[name]
+
+    yield get
+    for w, h, o in cache.values():
+        h.close()
+
+
+def five_to_nine(c5):
+    """Five-point SoA stencil (order (0,-1),(-1,0),(0,0),(1,0),(0,1)) as 9-point (dy+1)*3+(dx+1)."""
+    out = np.zeros((9,) + c5.shape[1:])
+    for s5, s9 in zip(range(5), (1, 3, 4, 5, 7)):
+        out[s9] = c5[s5]
+    return out
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_level_operators(problems, name):
+    """Finest operator (device split / assembly) and every Galerkin level, region by region."""
+    w, h, (lay, levels, opt) = problems(name)
+    for l, L in enumerate(levels):
+        info = h.level_info(l)
+        for k in range(L.lay.nreg):
+            ref = L.coefs[k].reshape(L.coefs[k].shape[0], -1)
+            got = h.level_stencil(l, k, info["npts"], ref.shape[1])
+            if info["npts"] == 5:
+                got = five_to_nine(got)
+            assert rel(got, ref) < 1e-12, (l, k, rel(got, ref))
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_eigenvalue_estimates(problems, name):
+    w, h, (lay, levels, opt) = problems(name)
+    for l, L in enumerate(levels[:-1]):
+        lam = h.level_info(l)["lambda"]
+        assert abs(lam - L.lam) <= 1e-12 * abs(L.lam), (l, lam, L.lam)
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_coarse_composite_matrix(problems, name):
+    w, h, (lay, levels, opt) = problems(name)
+    Ab = levels[-1].Abar
+    got = h.coarse_matrix(Ab.shape[0])
+    assert rel(got, Ab) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_regional_matvec_and_interface_sum(problems, name):
+    """Lemma: Psi [[A]] Psi^T x = A x; and Psi^T Psi bit-exact against the oracle."""
+    import torch
+
+    w, h, (lay, levels, opt) = problems(name)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1, 1, size=lay.shape)
+    L0 = levels[0]
+    xr = harness.to_dev(x)
+    reg = torch.empty(lay.n_regional, dtype=torch.float64, device="cuda:0")
+    h.to_regional(0, xr, reg)
+    z = torch.empty_like(reg)
+    h.regional_matvec(0, reg, z)
+    ref = lay.flatten(L0.matvec(lay.to_regional(x)))
+    assert rel(z.cpu().numpy(), ref) < 1e-13
+    # interface sum of an inconsistent regional vector
+    v = rng.uniform(-1, 1, size=lay.n_regional)
+    w_ = torch.empty_like(reg)
+    h.interface_sum(0, harness.to_dev(v), w_)
+    assert np.array_equal(w_.cpu().numpy(), lay.flatten(lay.interface_sum(lay.unflatten(v))))
+    # composite conversions: owner copy and average
+    comp = torch.empty(lay.n_composite, dtype=torch.float64, device="cuda:0")
+    h.to_composite(0, harness.to_dev(v), comp, average=True)
+    assert rel(comp.cpu().numpy(), lay.to_composite_avg(lay.unflatten(v)).reshape(-1)) < 1e-15
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_transfers(problems, name):
+    import torch
+
+    from oracle import transfer
+
+    w, h, (lay, levels, opt) = problems(name)
+    rng = np.random.default_rng(5)
+    for l in range(len(levels) - 1):
+        F, C = levels[l], levels[l + 1]
+        r = rng.uniform(-1, 1, size=F.lay.shape)
+        r[F.lay.dirichlet] = 0.0
+        rr = F.lay.to_regional(r)
+        wg = torch.empty(C.lay.n_regional, dtype=torch.float64, device="cuda:0")
+        h.restrict(l, harness.to_dev(F.lay.flatten(rr)), wg)
+        wref = C.lay.flatten(transfer.regional_restrict(F.lay, C.lay, F.P, rr))
+        assert rel(wg.cpu().numpy(), wref) < 1e-13, l
+        ub = rng.uniform(-1, 1, size=C.lay.shape)
+        ub[C.lay.dirichlet] = 0.0
+        u0 = rng.uniform(-1, 1, size=F.lay.shape)
+        ug = harness.to_dev(F.lay.flatten(F.lay.to_regional(u0)))
+        h.prolongate_add(l, harness.to_dev(C.lay.flatten(C.lay.to_regional(ub))), ug)
+        uref = F.lay.flatten([a + b for a, b in zip(F.lay.to_regional(u0), transfer.regional_prolongate(
+            F.lay, C.lay, F.P, C.lay.to_regional(ub)))])
+        assert rel(ug.cpu().numpy(), uref) < 1e-13, l
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_smoother(problems, name):
+    import torch
+
+    from oracle import regional
+
+    w, h, (lay, levels, opt) = problems(name)
+    b = synth.rhs(w)
+    L0 = levels[0]
+    br = lay.to_regional(b)
+    u = torch.empty(lay.n_regional, dtype=torch.float64, device="cuda:0")
+    h.smooth(0, harness.to_dev(lay.flatten(br)), u)
+    ref = regional.chebyshev(L0, lay.zeros_regional(), br, br, opt)
+    assert rel(u.cpu().numpy(), lay.flatten(ref)) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_vcycle(problems, name):
+    import torch
+
+    from oracle import regional
+
+    w, h, (lay, levels, opt) = problems(name)
+    b = synth.rhs(w)
+    z = torch.empty(lay.n_composite, dtype=torch.float64, device="cuda:0")
+    h.apply_vcycle(harness.to_dev(b), z)
+    ref = lay.to_composite_owner(regional.vcycle(levels, lay.to_regional(b), opt)).reshape(-1)
+    assert rel(z.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_pcg(problems, name):
+    import torch
+
+    from oracle import regional
+
+    w, h, (lay, levels, opt) = problems(name)
+    b = synth.rhs(w)
+    x = torch.zeros(lay.n_composite, dtype=torch.float64, device="cuda:0")
+    out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100)
+    ref = regional.pcg(levels, lay.to_regional(b), opt, rtol=1e-8, maxit=100)
+    xref = lay.to_composite_owner(ref.x).reshape(-1)
+    assert out["converged"] and ref.converged
+    assert out["iterations"] == ref.iterations
+    np.testing.assert_allclose(out["history"], ref.history, rtol=1e-8, atol=0)
+    assert rel(x.cpu().numpy(), xref) < 1e-10
+    assert out["true_relres"] <= 1.5e-8
+
+
+def test_errors_are_reported(hip_device):
+    from paper_2103_11962_amd import regmg
+
+    h = regmg.Handle(0)
+    with pytest.raises(regmg.RmgError) as e:
+        h.build_regions(2, 1, [[10, 10], [10, 10]], [[0, 0], [3, 0]], 0xF)  # overlapping boxes
+    assert e.value.status == "RMG_ERR_SHAPE"
+    w = synth.workload("c1_small")
+    h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
+    with pytest.raises(regmg.RmgError) as e:
+        h.setup_hierarchy(nlevels=3, cheb_degree=2)
+    assert e.value.status == "RMG_ERR_NOT_SETUP"
+    h.set_composite_stencil(5, synth.fd5_composite_stencil(w))
+    with pytest.raises(regmg.RmgError) as e:
+        h.setup_hierarchy(nlevels=4, cheb_degree=2)  # 10 nodes cannot be coarsened three times
+    assert e.value.status == "RMG_ERR_SHAPE"
+    bad = synth.fd5_composite_stencil(w)
+    bad[2, 50] = np.nan
+    with pytest.raises(regmg.RmgError) as e:
+        h.set_composite_stencil(5, bad)
+    assert e.value.status == "RMG_ERR_NUMERIC"
+    h.close()
