@@ -1,0 +1,189 @@
+"""Benchmark: regional multigrid preconditioned CG on one MI355X.
+
+Workload (default): 3D Q1 Laplacian (27-point stencil), 4x4x4 regions of 82^3
+nodes (composite 325^3, 35.3M regional rows), FP64, 4-level regional V-cycle
+with Chebyshev degree 3, CG to a 1e-8 relative residual, rhs U[-1, 1] from a
+fixed seed.  One step = device assembly of the region matrices, hierarchy
+setup (diagonal, power method, per-region Galerkin products, coarse inverse)
+and the PCG solve.  The region layout (planner tables) is built once.
+
+Prints one JSON line.  ``value`` is the PCG time-to-1e-8 (seconds, median over
+the timed steps); ``roofline`` is measured live on the finest-level fused
+Chebyshev kernel with HIP events; ``cpu_baseline`` times the CPU oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PCG time-to-1e-8 residual + stencil GB/s, FP64 vs mixed/learned forms"
+HBM_PEAK_GBS = 8000.0
+CHEB_BYTES_PER_ROW = 264  # 27 coefficients + u, b, D^-1, d read; d, u written (FP64)
+CG_MATVEC_BYTES_PER_ROW = 232  # 27 coefficients + p read; q written (FP64)
+
+CPU_SAMPLE = r"""
+import json, sys, time
+sys.path.insert(0, {root!r})
+import synth
+from oracle import regional
+from oracle.regions import Layout
+o, e = synth.tensor_layout([[82, 82], [82], [82]])
+w = synth.Workload("sample", 3, 1, o, e, 63, 4, 3, "laplace", h=1.0 / 324)
+lay = Layout(3, o, e, 63)
+coefs = regional.build_operator(lay, "laplace", h=w.h)
+opt = regional.Options(nlevels=4, degree=3)
+lv = regional.setup(lay, coefs, opt)
+b = lay.to_regional(synth.rhs(w))
+t = time.perf_counter()
+res = regional.pcg(lv, b, opt, rtol=1e-30, maxit={its})
+dt = time.perf_counter() - t
+print(json.dumps({{"seconds": dt, "iterations": res.iterations, "rows": lay.n_regional}}))
+"""
+
+
+def cpu_baseline(gpu_iterations: int, n_rows: int, its: int = 3):
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    res = subprocess.run([sys.executable, "-c", CPU_SAMPLE.format(root=ROOT, its=its)], capture_output=True,
+                         text=True, env=env, timeout=600)
+    if res.returncode != 0:
+        return {"value": None, "unit": "s", "cores": 1, "kind": "oracle", "sample": "failed: " + res.stderr[-300:]}
+    d = json.loads(res.stdout.strip().splitlines()[-1])
+    per_it = d["seconds"] / d["iterations"] * (n_rows / d["rows"])
+    return {
+        "value": per_it * gpu_iterations,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"NumPy FP64 oracle, {d['iterations']} PCG iterations (V-cycle + regional matvec each) on 2 "
+                   f"regions of 82^3 ({d['rows']} regional rows, {d['seconds']:.1f} s), scaled by "
+                   f"{n_rows / d['rows']:.0f}x rows and the GPU's {gpu_iterations} iterations"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the regional method here keeps all "
+              "regions on one device", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2103_11962_amd import regmg
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(args.workload)
+    b = torch.from_numpy(np.ascontiguousarray(synth.rhs(w)).reshape(-1)).to(dev)
+    x = torch.zeros_like(b)
+    ec = None
+    if w.pde == "diffusion":
+        ec = torch.from_numpy(np.ascontiguousarray(synth.jump_coefficients(w)).reshape(-1)).to(dev)
+    h = regmg.Handle(0)
+    h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
+
+    def step():
+        if w.pde == "fd5":
+            h.set_composite_stencil(5, synth.fd5_composite_stencil(w))
+        else:
+            h.assemble_q1(regmg.PDE_DIFFUSION if ec is not None else regmg.PDE_LAPLACE, w.h, elem_coef=ec)
+        t0 = time.perf_counter()
+        h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        x.zero_()
+        out = h.solve(b, x, rtol=1e-8, maxit=200)
+        return t_setup, out
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    setups, solves, outs = [], [], []
+    for i in range(args.steps):
+        ts, out = step()
+        setups.append(ts)
+        solves.append(out["solve_ms"] / 1e3)
+        outs.append(out)
+        print(f"[bench] step {i}: setup {ts*1e3:.1f} ms, solve {out['solve_ms']:.1f} ms, "
+              f"{out['iterations']} its, true relres {out['true_relres']:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    last = outs[-1]
+    assert last["converged"] and last["true_relres"] <= 1.5e-8, last
+    info0 = h.level_info(0)
+    rows = info0["n_regional"]
+    n_cheb, ms_cheb = h.profile_query(regmg.TIMED_CHEB)
+    n_cg, ms_cg = h.profile_query(regmg.TIMED_CG_MATVEC)
+    avg_cheb = ms_cheb / max(n_cheb, 1)
+    bytes_cheb = CHEB_BYTES_PER_ROW * rows
+    achieved = bytes_cheb / (avg_cheb * 1e-3) / 1e9
+    avg_cg = ms_cg / max(n_cg, 1)
+    achieved_cg = CG_MATVEC_BYTES_PER_ROW * rows / (avg_cg * 1e-3) / 1e9
+    h.close()
+
+    line = {
+        "metric": METRIC,
+        "value": float(np.median(solves)),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("3D Q1 Laplacian 27-point, 4x4x4 regions of 82^3 nodes (composite 325^3), FP64, "
+                         "4-level regional V-cycle, Chebyshev degree 3, PCG to 1e-8, rhs U[-1,1] seed 0"
+                         if args.workload == "c2" else args.workload),
+            "regional_rows": rows,
+            "iterations": last["iterations"],
+            "true_relres": last["true_relres"],
+            "setup_s_median": float(np.median(setups)),
+            "solve_s_per_step": solves,
+            "step": "device assembly + hierarchy setup + PCG solve",
+            "cg_matvec_gbs": achieved_cg,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stencil3d<Cheb> (finest-level fused Chebyshev step, 2.5D tiles)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_cheb,
+            "avg_launch_ms": avg_cheb,
+            "launches": n_cheb,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(last["iterations"], rows)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

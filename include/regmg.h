@@ -77,6 +77,8 @@ typedef struct {
   int power_iters;    /* power iterations for lambda_max(D~^-1 A) (default 10) */
   uint64_t seed;      /* seed of the counter-based power-method start vector */
   int precision;      /* rmg_precision */
+  int stencil_kernel; /* 3D stencil kernel: 0 auto (2.5D tiles on levels with >= 2048 tiles),
+                         1 node-parallel, 2 2.5D plane-marching tiles */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -190,6 +192,21 @@ rmg_status rmg_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t
 rmg_status rmg_get_level_stencil(rmg_handle* h, int level, int region, double* host_out);
 /* Dense composite operator of the coarsest level (host, n_composite^2, row-major). */
 rmg_status rmg_get_coarse_matrix(rmg_handle* h, double* host_out);
+
+/* ---- kernel timing (for roofline measurements) ---- */
+
+/* Timed kernels: 0 = finest-level fused Chebyshev step (stencil product,
+ * residual, direction and iterate update; excludes the first step of a
+ * smoothing pass), 1 = finest-level CG product q = A p with its (p, q) partial
+ * sums.  Only the stencil kernel is timed, not the interface-group kernel. */
+#define RMG_TIMED_CHEB 0
+#define RMG_TIMED_CG_MATVEC 1
+
+/* Enable (1) or disable (0) HIP-event timing of the kernels above and reset
+ * the counters.  Timing adds an event pair per timed launch. */
+rmg_status rmg_profile(rmg_handle* h, int enable);
+/* Launch count and summed duration (ms) of a timed kernel since the last reset. */
+rmg_status rmg_profile_query(rmg_handle* h, int kernel, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

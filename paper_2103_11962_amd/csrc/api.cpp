@@ -89,6 +89,7 @@ void rmg_options_default(rmg_options* o) {
   o->power_iters = 10;
   o->seed = 0;
   o->precision = RMG_PREC_FP64;
+  o->stencil_kernel = 0;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -175,14 +176,15 @@ rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const dou
   if (!any || L.npts != npts || !L.coef.p) {
     RMG_REQUIRE(!any || L.npts == npts, RMG_ERR_ARG, "all regions must use the same stencil size");
     L.npts = npts;
-    L.coef.alloc(sizeof(double) * (size_t)npts * L.n);
-    RMG_HIP(hipMemsetAsync(L.coef.p, 0, sizeof(double) * (size_t)npts * L.n, h->stream));
+    L.coef.alloc(sizeof(double) * coef_elems(L.n, npts));
+    RMG_HIP(hipMemsetAsync(L.coef.p, 0, sizeof(double) * coef_elems(L.n, npts), h->stream));
   }
   const RegionGeo& R = L.regs[region];
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  for (int s = 0; s < npts; ++s)
-    RMG_HIP(hipMemcpyAsync(L.coef.as<double>() + (size_t)s * L.n + R.off, coef + (size_t)s * R.n,
-                           sizeof(double) * R.n, kind, h->stream));
+  DBuf soa;
+  soa.alloc(sizeof(double) * (size_t)npts * R.n);
+  RMG_HIP(hipMemcpyAsync(soa.p, coef, sizeof(double) * (size_t)npts * R.n, kind, h->stream));
+  launch_region_stencil_io(L, region, soa.as<double>(), 1, h->stream);
   DBuf flag;
   flag.alloc(sizeof(int));
   RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), h->stream));
@@ -237,7 +239,7 @@ rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef
     src = tmp.as<double>();
   }
   L.npts = npts;
-  L.coef.alloc(sizeof(double) * (size_t)npts * L.n);
+  L.coef.alloc(sizeof(double) * coef_elems(L.n, npts));
   DBuf flag;
   flag.alloc(sizeof(int));
   RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), h->stream));
@@ -267,7 +269,7 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
   double K[64];
   q1_laplace_element(hsize, K);
   L.npts = 27;
-  L.coef.alloc(sizeof(double) * 27 * (size_t)L.n);
+  L.coef.alloc(sizeof(double) * coef_elems(L.n, 27));
   launch_assemble_q1_scalar(L, K, pde == RMG_PDE_DIFFUSION ? elem_coef : nullptr, h->stream);
   launch_dirichlet_split(L, h->stream);
   DBuf flag;
@@ -294,6 +296,7 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->eig_ratio > 1.0 && opt->boost > 0.0, RMG_ERR_ARG, "need eig_ratio > 1 and boost > 0");
   RMG_REQUIRE(opt->power_iters >= 1, RMG_ERR_ARG, "power_iters must be >= 1");
   RMG_REQUIRE(opt->precision == RMG_PREC_FP64, RMG_ERR_ARG, "only FP64 precision is supported by this build");
+  RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 2, RMG_ERR_ARG, "stencil_kernel must be 0, 1 or 2");
   h->opt = *opt;
   h->have_hierarchy = false;
   setup_hierarchy(h);
@@ -447,9 +450,10 @@ rmg_status rmg_get_level_stencil(rmg_handle* h, int level, int region, double* h
   RMG_REQUIRE(region >= 0 && region < L.nreg && host_out, RMG_ERR_ARG, "bad region or null output");
   RMG_REQUIRE(L.coef.p != nullptr, RMG_ERR_NOT_SETUP, "no operator on this level");
   const RegionGeo& R = L.regs[region];
-  for (int s = 0; s < L.npts; ++s)
-    RMG_HIP(hipMemcpyAsync(host_out + (size_t)s * R.n, L.coef.as<double>() + (size_t)s * L.n + R.off,
-                           sizeof(double) * R.n, hipMemcpyDeviceToHost, h->stream));
+  DBuf soa;
+  soa.alloc(sizeof(double) * (size_t)L.npts * R.n);
+  launch_region_stencil_io(L, region, soa.as<double>(), 0, h->stream);
+  RMG_HIP(hipMemcpyAsync(host_out, soa.p, sizeof(double) * (size_t)L.npts * R.n, hipMemcpyDeviceToHost, h->stream));
   RMG_HIP(hipStreamSynchronize(h->stream));
   API_END
 }
@@ -461,6 +465,26 @@ rmg_status rmg_get_coarse_matrix(rmg_handle* h, double* host_out) {
   RMG_REQUIRE(host_out, RMG_ERR_ARG, "null output");
   Level& L = *h->levels.back();
   std::memcpy(host_out, L.abar_host.data(), sizeof(double) * L.abar_host.size());
+  API_END
+}
+
+rmg_status rmg_profile(rmg_handle* h, int enable) {
+  API_BEGIN
+  use_device(h);
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  h->profiling = enable != 0;
+  for (auto& t : h->timers) t.reset();
+  API_END
+}
+
+rmg_status rmg_profile_query(rmg_handle* h, int kernel, int64_t* launches, double* total_ms) {
+  API_BEGIN
+  use_device(h);
+  RMG_REQUIRE(kernel >= 0 && kernel < kNumTimed, RMG_ERR_ARG, "unknown timed kernel id");
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  h->timers[kernel].harvest();
+  if (launches) *launches = h->timers[kernel].count;
+  if (total_ms) *total_ms = h->timers[kernel].total_ms;
   API_END
 }
 

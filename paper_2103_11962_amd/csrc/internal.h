@@ -50,6 +50,22 @@ struct BlockDesc {
 
 constexpr int kBlock = 256;  // threads per block for node-parallel kernels
 
+constexpr size_t kAutoTileMin = 2048;  // 2.5D tiles needed on a level before they are used by default
+
+// A 2.5D tile of a 3D region: ty x-rows of tx nodes starting at (x0, y0), planes z0 .. z0+nz-1.
+struct Tile3 {
+  int region, x0, y0, z0, tx, ty, nz, pad;
+};
+
+// Stencil coefficients are stored wave-tiled: the npts coefficients of 64 consecutive regional
+// nodes form one contiguous chunk laid out [s][lane], so a wavefront streams one contiguous
+// block of memory instead of npts separate streams.
+constexpr int kTile = 64;
+__host__ __device__ __forceinline__ int64_t coef_index(int64_t gi, int s, int npts) {
+  return ((gi >> 6) * npts + s) * kTile + (gi & (kTile - 1));
+}
+inline size_t coef_elems(int64_t n, int npts) { return (size_t)((n + kTile - 1) / kTile) * kTile * npts; }
+
 // Everything a kernel needs to know about a level, passed by value.
 struct LevelView {
   const RegionGeo* regs;
@@ -86,6 +102,9 @@ struct Level {
   std::vector<RegionGeo> regs;
   std::vector<BlockDesc> blocks;
   DBuf d_regs, d_blocks;
+  std::vector<Tile3> tiles;  // 2.5D tiles of a 3D level (empty in 2D)
+  DBuf d_tiles;
+  bool use_tiles = false;    // run 27-point stencil operations with the 2.5D kernel
   // interface groups: copies of each shared composite node, ascending region order
   int64_t ngroups = 0;
   DBuf d_gptr;    // int64 [ngroups+1]
@@ -110,6 +129,21 @@ struct Level {
 
 }  // namespace rmg
 
+namespace rmg {
+// Event-pair timing of selected finest-level kernels (enabled on request).
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  size_t used = 0;
+  int64_t count = 0;
+  double total_ms = 0.0;
+  void acquire(hipEvent_t* e0, hipEvent_t* e1);
+  void harvest();  // after a stream synchronisation: accumulate and recycle
+  void reset();
+  ~KernelTimer();
+};
+enum TimedKernel { kTimedCheb = 0, kTimedCgQ = 1, kNumTimed = 2 };
+}  // namespace rmg
+
 struct rmg_handle {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -125,6 +159,8 @@ struct rmg_handle {
   rmg::DBuf partials;   // double partial sums
   rmg::DBuf scalars;    // double device scalars
   double* host_scalars = nullptr;  // pinned
+  bool profiling = false;
+  rmg::KernelTimer timers[rmg::kNumTimed];
   ~rmg_handle();
 };
 

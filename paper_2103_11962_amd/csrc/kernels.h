@@ -24,6 +24,7 @@ struct StencilArgs {
   double c1 = 0.0, c2 = 0.0;
   double* partials = nullptr;  // CgQ / dot-fused variants: one double per block
   const double* dotw = nullptr;  // Cheb: when set, partial sums of (dotw, u_out) are produced
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // when set, recorded around the stencil kernel only
 };
 
 // Runs the stencil kernel over all nodes and then the interface-group kernel.
@@ -80,6 +81,10 @@ void launch_mask_stencil(const Level& L, int* flag, hipStream_t st);
 
 // Region matrices from a composite stencil [npts][ncomp] on a tensor-product layout (Section 4 split).
 void launch_split_composite(const Level& L, const double* comp, int* flag, hipStream_t st);
+
+// Copy one region's stencil between a structure-of-arrays buffer [npts][region nodes] and the
+// level's wave-tiled storage (to_level = 1: soa -> level).
+void launch_region_stencil_io(const Level& L, int region, double* soa, int to_level, hipStream_t st);
 
 // CG helpers.
 // alpha = s[rz]/s[pq]; x += alpha p; r -= alpha q; partial sums of owner-masked (r, r).

@@ -85,6 +85,7 @@ __device__ __forceinline__ double block_sum(double v) {
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+
 #define LAUNCH_CHECK() RMG_HIP(hipGetLastError())
 
 // ------------------------------------------------------- stencil operations
@@ -101,7 +102,19 @@ struct OpParams {
 // Final update of a node once z = (Psi^T Psi A x) at that node is known; m = multiplicity.
 // Returns this node's contribution to the fused reduction, if any.
 template <StencilOp OP, bool DOT>
+__device__ __forceinline__ double node_finish_x(const OpParams& p, int64_t gi, double z, int m, double xself);
+
+template <StencilOp OP, bool DOT>
 __device__ __forceinline__ double node_finish(const OpParams& p, int64_t gi, double z, int m) {
+  if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst || OP == StencilOp::CgQ)
+    return node_finish_x<OP, DOT>(p, gi, z, m, p.x[gi]);
+  else
+    return node_finish_x<OP, DOT>(p, gi, z, m, 0.0);
+}
+
+// xself = the stencil input at this node (used by the Chebyshev update and the CG dot product).
+template <StencilOp OP, bool DOT>
+__device__ __forceinline__ double node_finish_x(const OpParams& p, int64_t gi, double z, int m, double xself) {
   if constexpr (OP == StencilOp::Matvec) {
     p.out[gi] = z;
     return 0.0;
@@ -117,13 +130,13 @@ __device__ __forceinline__ double node_finish(const OpParams& p, int64_t gi, dou
     double dd = p.c2 * (p.dinv[gi] * r);
     if constexpr (OP == StencilOp::Cheb) dd = p.c1 * p.d[gi] + dd;
     p.d[gi] = dd;
-    const double u = p.x[gi] + dd;
+    const double u = xself + dd;
     p.out[gi] = u;
     if constexpr (DOT) return p.dotw[gi] * u;
     return 0.0;
   } else {  // CgQ
     p.out[gi] = z;
-    return p.x[gi] * z;
+    return xself * z;
   }
 }
 
@@ -139,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const double* _
     decompose(R, li, x, y, z);
     const int64_t gi = R.off + li;
     const double* __restrict__ xr = p.x + R.off;
-    const double* __restrict__ cf = coef + gi;
+    const double* __restrict__ cf = coef + coef_index(gi, 0, NPTS);
     const int sy = R.ex, sz = R.ex * R.ey;
     const bool inner = x > 0 && x < R.ex - 1 && y > 0 && y < R.ey - 1 && (NPTS != 27 || (z > 0 && z < R.ez - 1));
     double acc = 0.0;
@@ -148,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const double* _
       for (int s = 0; s < NPTS; ++s) {
         int dx, dy, dz;
         stencil_offset<NPTS>(s, dx, dy, dz);
-        acc += cf[(int64_t)s * L.n] * xr[li + dx + dy * sy + dz * sz];
+        acc += cf[s * kTile] * xr[li + dx + dy * sy + dz * sz];
       }
       contrib = node_finish<OP, DOT>(p, gi, acc, 1);
     } else {
@@ -158,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const double* _
         stencil_offset<NPTS>(s, dx, dy, dz);
         const bool ok = (unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
                         (unsigned)(z + dz) < (unsigned)R.ez;
-        if (ok) acc += cf[(int64_t)s * L.n] * xr[li + dx + dy * sy + dz * sz];
+        if (ok) acc += cf[s * kTile] * xr[li + dx + dy * sy + dz * sz];
       }
       if (is_shared(L, R, x, y, z)) {
         p.out[gi] = acc;  // partial product; summed over the copies by k_iface
@@ -170,6 +183,118 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const double* _
   if constexpr (DOT || OP == StencilOp::CgQ) {
     const double s = block_sum(contrib);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+
+// ------------------------------------------------ 3D stencil, 2.5D tiles
+// A block owns a tile of ty x-rows (tx nodes each) of one region and marches nz planes in z.
+// The input vector's planes pass through two LDS slots; each thread keeps its 3x3
+// neighbourhood of planes z-1, z, z+1 in registers (rotated per plane), so it reads only the
+// new plane from LDS, and the plane after next is prefetched from global memory into registers
+// while the current plane is computed.  Neighbours outside the region box read 0 from LDS and
+// have zero coefficients, so the 27-term sum needs no bounds branches.
+constexpr int kT3 = 512;           // threads per 3D tile block
+constexpr int kT3Plane = 1544;     // max (ty+2)(tx+2) over tx*ty <= 512
+constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
+
+template <StencilOp OP, bool DOT>
+__global__ __launch_bounds__(kT3) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles,
+                                                   const double* __restrict__ coef, OpParams p,
+                                                   double* __restrict__ partials) {
+  __shared__ double pl[2][kT3Plane];
+  const Tile3 T = tiles[blockIdx.x];
+  const RegionGeo R = L.regs[T.region];
+  const int W = T.tx + 2, PL = (T.ty + 2) * W;
+  const double* __restrict__ xr = p.x + R.off;
+  const int t = threadIdx.x;
+  const int ty = t / T.tx, tx = t - ty * T.tx;
+  const int x = T.x0 + tx, y = T.y0 + ty;
+  const bool active = ty < T.ty && x < R.ex && y < R.ey;
+  const int sy = R.ex, sz = R.ex * R.ey;
+  double pre[kT3Fetch];
+  auto fetch = [&](int zz) {
+#pragma unroll
+    for (int k = 0; k < kT3Fetch; ++k) {
+      const int idx = t + k * kT3;
+      double v = 0.0;
+      if (idx < PL) {
+        const int r = idx / W;
+        const int xx = T.x0 + idx - r * W - 1, yy = T.y0 - 1 + r;
+        if ((unsigned)zz < (unsigned)R.ez && (unsigned)yy < (unsigned)R.ey && (unsigned)xx < (unsigned)R.ex)
+          v = xr[zz * sz + yy * sy + xx];
+      }
+      pre[k] = v;
+    }
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int k = 0; k < kT3Fetch; ++k) {
+      const int idx = t + k * kT3;
+      if (idx < PL) pl[slot][idx] = pre[k];
+    }
+  };
+  double rm[9], rc[9], rp[9];
+  auto readn = [&](int slot, double* r) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const int dx = j % 3 - 1, dy = j / 3 - 1;
+      r[j] = pl[slot][(ty + 1 + dy) * W + tx + 1 + dx];
+    }
+  };
+  const int z0 = T.z0, z1 = T.z0 + T.nz;
+  fetch(z0 - 1);
+  store(0);
+  fetch(z0);
+  store(1);
+  __syncthreads();
+  if (active) {
+    readn(0, rm);
+    readn(1, rc);
+  }
+  __syncthreads();
+  fetch(z0 + 1);
+  store(0);
+  __syncthreads();
+  double contrib = 0.0;
+  for (int zz = z0; zz < z1; ++zz) {
+    const int sp = (zz - z0) & 1;  // slot holding plane zz+1
+    if (active) readn(sp, rp);
+    fetch(zz + 2);
+    if (active) {
+      const int li = zz * sz + y * sy + x;
+      const int64_t gi = R.off + li;
+      const double* __restrict__ cf = coef + coef_index(gi, 0, 27);
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < 27; ++s) {
+        const int j = s % 9, dz = s / 9 - 1;
+        const double v = dz < 0 ? rm[j] : (dz == 0 ? rc[j] : rp[j]);
+        acc += cf[s * kTile] * v;
+      }
+      const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
+      if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
+      else contrib += node_finish_x<OP, DOT>(p, gi, acc, 1, rc[4]);
+    }
+    store(sp ^ 1);  // plane zz+2 replaces plane zz
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      rm[j] = rc[j];
+      rc[j] = rp[j];
+    }
+    __syncthreads();
+  }
+  if constexpr (DOT || OP == StencilOp::CgQ) {
+    double v = contrib;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __shared__ double sm[kT3 / 64];
+    if ((t & 63) == 0) sm[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int i = 0; i < kT3 / 64; ++i) s += sm[i];
+      partials[blockIdx.x] = s;
+    }
   }
 }
 
@@ -195,12 +320,20 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
 }
 
 template <int NPTS, StencilOp OP, bool DOT>
-static int64_t run_stencil(const Level& L, const OpParams& p, double* partials, hipStream_t st) {
+static int64_t run_stencil(const Level& L, const OpParams& p, double* partials, hipStream_t st,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   const LevelView v = L.view();
-  hipLaunchKernelGGL((k_stencil<NPTS, OP, DOT>), dim3(L.blocks.size()), dim3(kBlock), 0, st, v,
-                     L.coef.as<double>(), p, partials);
+  const bool tiled = NPTS == 27 && L.use_tiles;
+  if (ev0) RMG_HIP(hipEventRecord(ev0, st));
+  if (tiled)
+    hipLaunchKernelGGL((k_stencil3d<OP, DOT>), dim3(L.tiles.size()), dim3(kT3), 0, st, v, L.d_tiles.as<Tile3>(),
+                       L.coef.as<double>(), p, partials);
+  else
+    hipLaunchKernelGGL((k_stencil<NPTS, OP, DOT>), dim3(L.blocks.size()), dim3(kBlock), 0, st, v,
+                       L.coef.as<double>(), p, partials);
   LAUNCH_CHECK();
-  const int64_t nb = (int64_t)L.blocks.size();
+  if (ev1) RMG_HIP(hipEventRecord(ev1, st));
+  const int64_t nb = tiled ? (int64_t)L.tiles.size() : (int64_t)L.blocks.size();
   int64_t ngb = 0;
   if (L.ngroups > 0) {
     ngb = cdiv(L.ngroups, kBlock);
@@ -220,12 +353,12 @@ static int64_t dispatch_op(const Level& L, const StencilArgs& a, const OpParams&
     case StencilOp::ResidualScaled:
       return run_stencil<NPTS, StencilOp::ResidualScaled, false>(L, p, nullptr, st);
     case StencilOp::Cheb:
-      return dot ? run_stencil<NPTS, StencilOp::Cheb, true>(L, p, a.partials, st)
-                 : run_stencil<NPTS, StencilOp::Cheb, false>(L, p, nullptr, st);
+      return dot ? run_stencil<NPTS, StencilOp::Cheb, true>(L, p, a.partials, st, a.ev0, a.ev1)
+                 : run_stencil<NPTS, StencilOp::Cheb, false>(L, p, nullptr, st, a.ev0, a.ev1);
     case StencilOp::ChebFirst:
       return dot ? run_stencil<NPTS, StencilOp::ChebFirst, true>(L, p, a.partials, st)
                  : run_stencil<NPTS, StencilOp::ChebFirst, false>(L, p, nullptr, st);
-    case StencilOp::CgQ: return run_stencil<NPTS, StencilOp::CgQ, false>(L, p, a.partials, st);
+    case StencilOp::CgQ: return run_stencil<NPTS, StencilOp::CgQ, false>(L, p, a.partials, st, a.ev0, a.ev1);
   }
   return 0;
 }
@@ -417,7 +550,7 @@ void launch_recip_check(int64_t n, const double* in, double* out, int* flag, hip
 template <int NPTS>
 __global__ void k_diag(int64_t n, const double* __restrict__ coef, double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = coef[(int64_t)center_index<NPTS>() * n + i];
+  if (i < n) out[i] = coef[coef_index(i, center_index<NPTS>(), NPTS)];
 }
 
 void launch_diag(const Level& L, double* out, hipStream_t st) {
@@ -591,7 +724,7 @@ __global__ __launch_bounds__(kRapBlock) void k_rap(LevelView F, LevelView C, con
         const int64_t fi = RF.off + (fz * RF.ey + fy) * RF.ex + fx;
 #pragma unroll
         for (int s = 0; s < NPTSF; ++s) {
-          const double a = coefF[(int64_t)s * F.n + fi];
+          const double a = coefF[coef_index(fi, s, NPTSF)];
           if (a == 0.0) continue;
           int dx, dy, dz;
           stencil_offset<NPTSF>(s, dx, dy, dz);
@@ -629,7 +762,7 @@ __global__ __launch_bounds__(kRapBlock) void k_rap(LevelView F, LevelView C, con
                        (unsigned)Zn < (unsigned)RC.ez;
     if (!inbox) v = 0.0;
     else if (!cdir && is_dirichlet(C, RC.ox + Xn, RC.oy + Yn, RC.oz + Zn)) v = 0.0;
-    coefC[(int64_t)o * C.n + gi] = v;
+    coefC[coef_index(gi, o, NC)] = v;
   }
 }
 
@@ -828,7 +961,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_q1(LevelView L, Kmat K, con
     if (!inbox) v = 0.0;
     if (dn) v = (s == 13) ? 1.0 : 0.0;
     else if (inbox && is_dirichlet(L, gx + dx, gy + dy, gz + dz)) v = 0.0;
-    coef[(int64_t)s * L.n + gi] = v;
+    coef[coef_index(gi, s, 27)] = v;
   }
 }
 
@@ -849,7 +982,7 @@ __global__ void k_dirichlet_split(const int64_t* __restrict__ gptr, const int* _
   const int gx = (int)(ci % L.cx), gy = (int)((ci / L.cx) % L.cy), gz = (int)(ci / ((int64_t)L.cx * L.cy));
   if (!is_dirichlet(L, gx, gy, gz)) return;
   const int64_t a = gptr[g], e = gptr[g + 1];
-  for (int64_t c = a; c < e; ++c) coef[(int64_t)center_index<NPTS>() * L.n + gcopy[c]] = 1.0 / (double)(e - a);
+  for (int64_t c = a; c < e; ++c) coef[coef_index(gcopy[c], center_index<NPTS>(), NPTS)] = 1.0 / (double)(e - a);
 }
 
 void launch_dirichlet_split(const Level& L, hipStream_t st) {
@@ -881,7 +1014,7 @@ __global__ __launch_bounds__(kBlock) void k_mask_stencil(LevelView L, double* __
   for (int s = 0; s < NPTS; ++s) {
     int dx, dy, dz;
     stencil_offset<NPTS>(s, dx, dy, dz);
-    double* c = coef + (int64_t)s * L.n + gi;
+    double* c = coef + coef_index(gi, s, NPTS);
     const bool ok = (unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
                     (unsigned)(z + dz) < (unsigned)R.ez;
     if (!isfinite(*c)) bad = true;
@@ -941,9 +1074,9 @@ __global__ __launch_bounds__(kBlock) void k_split_composite(LevelView L, const d
       v = a / (double)q;
       offsum += v;
     }
-    coef[(int64_t)s * L.n + gi] = v;
+    coef[coef_index(gi, s, NPTS)] = v;
   }
-  coef[(int64_t)c * L.n + gi] = rowsum / (double)(mx * my * mz) - offsum;
+  coef[coef_index(gi, c, NPTS)] = rowsum / (double)(mx * my * mz) - offsum;
   if (bad) atomicOr(flag, 1);
 }
 
@@ -955,6 +1088,26 @@ void launch_split_composite(const Level& L, const double* comp, int* flag, hipSt
     hipLaunchKernelGGL(k_split_composite<9>, g, dim3(kBlock), 0, st, L.view(), comp, L.ncomp, L.coef.as<double>(), flag);
   else
     hipLaunchKernelGGL(k_split_composite<5>, g, dim3(kBlock), 0, st, L.view(), comp, L.ncomp, L.coef.as<double>(), flag);
+  LAUNCH_CHECK();
+}
+
+// Caller layout (structure of arrays over one region) <-> wave-tiled level storage.
+__global__ void k_region_stencil_io(int64_t off, int nn, int npts, double* __restrict__ coef,
+                                    double* __restrict__ soa, int to_level) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nn * npts) return;
+  const int s = (int)(t / nn);
+  const int i = (int)(t - (int64_t)s * nn);
+  double* c = coef + coef_index(off + i, s, npts);
+  if (to_level) *c = soa[t];
+  else soa[t] = *c;
+}
+
+void launch_region_stencil_io(const Level& L, int region, double* soa, int to_level, hipStream_t st) {
+  const RegionGeo& R = L.regs[region];
+  const int64_t tot = (int64_t)R.n * L.npts;
+  hipLaunchKernelGGL(k_region_stencil_io, dim3(cdiv(tot, kBlock)), dim3(kBlock), 0, st, R.off, R.n, L.npts,
+                     L.coef.as<double>(), soa, to_level);
   LAUNCH_CHECK();
 }
 

@@ -115,6 +115,30 @@ void build_tables(Level& L) {
     gcomp2.push_back(gcomp[g]);
   }
   L.ngroups = ng;
+  // 2.5D tiles for the 3D stencil kernel: 512-thread tiles of whole (or 512-node) x-rows,
+  // 21 planes deep; by default used when the level has enough tiles to fill the GPU.
+  L.tiles.clear();
+  if (L.dim == 3) {
+    constexpr int kThreads = 512, kDepth = 21;
+    std::vector<Tile3> tiles;
+    for (int k = 0; k < L.nreg; ++k) {
+      const RegionGeo& R = L.regs[k];
+      const int tx = std::min(R.ex, kThreads);
+      const int ty = std::min(R.ey, kThreads / tx);
+      for (int z0 = 0; z0 < R.ez; z0 += kDepth)
+        for (int y0 = 0; y0 < R.ey; y0 += ty)
+          for (int x0 = 0; x0 < R.ex; x0 += tx)
+            tiles.push_back(Tile3{k, x0, y0, z0, tx, ty, std::min(kDepth, R.ez - z0), 0});
+    }
+    L.tiles = tiles;
+  }
+  L.use_tiles = L.tiles.size() >= kAutoTileMin;
+  for (const Tile3& T : L.tiles)
+    RMG_REQUIRE((T.tx + 2) * (T.ty + 2) <= 1544 && T.tx * T.ty <= 512, RMG_ERR_ARG, "internal: tile too large");
+  if (!L.tiles.empty()) {
+    L.d_tiles.alloc(sizeof(Tile3) * L.tiles.size());
+    RMG_HIP(hipMemcpy(L.d_tiles.p, L.tiles.data(), sizeof(Tile3) * L.tiles.size(), hipMemcpyHostToDevice));
+  }
   L.d_regs.alloc(sizeof(RegionGeo) * L.regs.size());
   RMG_HIP(hipMemcpy(L.d_regs.p, L.regs.data(), sizeof(RegionGeo) * L.regs.size(), hipMemcpyHostToDevice));
   L.d_blocks.alloc(sizeof(BlockDesc) * L.blocks.size());
@@ -217,7 +241,7 @@ void build_coarse_solver(rmg_handle* h, Level& L) {
   RMG_REQUIRE(nc64 <= 20000, RMG_ERR_ARG, "coarsest composite problem too large for the dense solver");
   const int nc = (int)nc64;
   L.nc = nc;
-  std::vector<double> coef((size_t)L.npts * L.n);
+  std::vector<double> coef(coef_elems(L.n, L.npts));
   RMG_HIP(hipMemcpyAsync(coef.data(), L.coef.p, sizeof(double) * coef.size(), hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));
   L.abar_host.assign((size_t)nc * nc, 0.0);
@@ -242,7 +266,7 @@ void build_coarse_solver(rmg_handle* h, Level& L) {
               dz = 0;
             }
             if (x + dx < 0 || x + dx >= R.ex || y + dy < 0 || y + dy >= R.ey || z + dz < 0 || z + dz >= R.ez) continue;
-            const double v = coef[(size_t)s * L.n + R.off + li];
+            const double v = coef[coef_index(R.off + li, s, L.npts)];
             if (v == 0.0) continue;
             const int64_t j = ((int64_t)(R.oz + z + dz) * L.comp[1] + (R.oy + y + dy)) * L.comp[0] + (R.ox + x + dx);
             L.abar_host[(size_t)i * nc + j] += v;

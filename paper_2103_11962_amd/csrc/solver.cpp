@@ -1,4 +1,5 @@
 // Hierarchy setup, regional V-cycle and preconditioned CG (host orchestration of the kernels).
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -6,8 +7,39 @@
 
 namespace rmg {
 
+void KernelTimer::acquire(hipEvent_t* e0, hipEvent_t* e1) {
+  while (ev.size() < used + 2) {
+    hipEvent_t e;
+    RMG_HIP(hipEventCreate(&e));
+    ev.push_back(e);
+  }
+  *e0 = ev[used];
+  *e1 = ev[used + 1];
+  used += 2;
+}
+
+void KernelTimer::harvest() {
+  for (size_t i = 0; i + 1 < used; i += 2) {
+    float ms = 0.f;
+    RMG_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    total_ms += ms;
+    ++count;
+  }
+  used = 0;
+}
+
+void KernelTimer::reset() {
+  used = 0;
+  count = 0;
+  total_ms = 0.0;
+}
+
+KernelTimer::~KernelTimer() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
 static int64_t partial_capacity(const Level& L) {
-  return (int64_t)L.blocks.size() + (L.ngroups + kBlock - 1) / kBlock + 16;
+  return (int64_t)std::max(L.blocks.size(), L.tiles.size()) + (L.ngroups + kBlock - 1) / kBlock + 16;
 }
 
 static double* scal(rmg_handle* h) { return h->scalars.as<double>(); }
@@ -95,6 +127,8 @@ void setup_hierarchy(rmg_handle* h) {
   flag.alloc(sizeof(int));
   for (int l = 0; l < o.nlevels; ++l) {
     Level& L = *h->levels[l];
+    L.use_tiles = !L.tiles.empty() &&
+                  (o.stencil_kernel == 2 || (o.stencil_kernel == 0 && L.tiles.size() >= kAutoTileMin));
     alloc_vectors(L, l > 0);
     if (l == o.nlevels - 1) {
       build_coarse_solver(h, L);
@@ -116,7 +150,7 @@ void setup_hierarchy(rmg_handle* h) {
     chebyshev_coefficients(o, L);
     // next level: geometry, then the per-region Galerkin product on the device
     Level* C = make_coarse_level(L);
-    C->coef.alloc(sizeof(double) * (size_t)C->npts * C->n);
+    C->coef.alloc(sizeof(double) * coef_elems(C->n, C->npts));
     launch_rap(L, *C, st);
     h->levels.push_back(C);
   }
@@ -136,6 +170,7 @@ static void cheb_step(rmg_handle* h, Level& L, int k, bool first, const double* 
   a.c2 = L.cheb_c2[k];
   a.dotw = dotw;
   a.partials = partials;
+  if (h->profiling && &L == h->levels[0] && !first) h->timers[kTimedCheb].acquire(&a.ev0, &a.ev1);
   const int64_t n = launch_stencil_op(L, a, h->stream);
   if (np) *np = n;
 }
@@ -239,6 +274,7 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
       a.x = p;
       a.out = q;
       a.partials = part;
+      if (h->profiling) h->timers[kTimedCgQ].acquire(&a.ev0, &a.ev1);
       const int64_t np = launch_stencil_op(L, a, st);
       launch_reduce(part, np, scal(h), kPQ, st);
       launch_cg_scalars(scal(h), 0, st);
@@ -246,6 +282,8 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
       launch_reduce(part, nu, scal(h), kRR, st);
       ++it;
       read_scalars(h);
+      if (h->profiling)
+        for (auto& t : h->timers) t.harvest();
       const double rz = h->host_scalars[kRZ], pq = h->host_scalars[kPQ], rr = h->host_scalars[kRR];
       if (!(pq > 0.0) || !(rz > 0.0) || !std::isfinite(rr)) {
         *status = RMG_ERR_BREAKDOWN;
@@ -278,6 +316,8 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
   }
   dot(h, L, q, q, kTmp);
   read_scalars(h);
+  if (h->profiling)
+    for (auto& t : h->timers) t.harvest();
   float ms = 0.f;
   RMG_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);

@@ -19,6 +19,7 @@ LAYOUT_COMPOSITE = 0
 LAYOUT_REGIONAL = 1
 PDE_LAPLACE, PDE_DIFFUSION, PDE_ELASTICITY = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
+KERNEL_AUTO, KERNEL_NODE, KERNEL_TILED = 0, 1, 2
 
 STATUS = {
     0: "RMG_OK", 1: "RMG_ERR_ARG", 2: "RMG_ERR_SHAPE", 3: "RMG_ERR_NUMERIC", 4: "RMG_ERR_DEVICE",
@@ -31,8 +32,9 @@ SYMBOLS = (
     "rmg_set_region_stencil", "rmg_set_composite_stencil", "rmg_assemble_q1", "rmg_setup_hierarchy",
     "rmg_apply_vcycle", "rmg_solve", "rmg_to_regional", "rmg_to_composite", "rmg_regional_matvec",
     "rmg_interface_sum", "rmg_restrict", "rmg_prolongate_add", "rmg_smooth", "rmg_level_info",
-    "rmg_get_level_stencil", "rmg_get_coarse_matrix",
+    "rmg_get_level_stencil", "rmg_get_coarse_matrix", "rmg_profile", "rmg_profile_query",
 )
+TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
 
 
 class Options(ctypes.Structure):
@@ -44,6 +46,7 @@ class Options(ctypes.Structure):
         ("power_iters", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("precision", ctypes.c_int),
+        ("stencil_kernel", ctypes.c_int),
     ]
 
 
@@ -105,6 +108,8 @@ def load():
                                ctypes.POINTER(I), ctypes.POINTER(D)]),
         "rmg_get_level_stencil": (I, [H, I, I, P]),
         "rmg_get_coarse_matrix": (I, [H, P]),
+        "rmg_profile": (I, [H, I]),
+        "rmg_profile_query": (I, [H, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -266,3 +271,12 @@ class Handle:
         out = np.zeros(n * n)
         _check(load().rmg_get_coarse_matrix(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return out.reshape(n, n)
+
+    # ---------------------------------------------------------- timing
+    def profile(self, enable=True):
+        _check(load().rmg_profile(self._h, int(enable)))
+
+    def profile_query(self, kernel):
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(load().rmg_profile_query(self._h, kernel, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value

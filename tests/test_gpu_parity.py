@@ -14,7 +14,10 @@ from tests import harness
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["c1_small", "c2_small", "c4_small", "c5_small", "c1", "c2_mid"]
+# (workload, 3D stencil kernel): 1 = node-parallel, 2 = 2.5D plane-marching tiles
+SMALL = [("c1_small", 0), ("c2_small", 1), ("c2_small", 2), ("c4_small", 1), ("c4_small", 2),
+         ("c5_small", 1), ("c5_small", 2), ("c1", 0), ("c2_mid", 1), ("c2_mid", 2)]
+IDS = [f"{n}-k{k}" for n, k in SMALL]
 
 
 def rel(a, b):
@@ -27,14 +30,15 @@ def rel(a, b):
 def problems(hip_device):
     cache = {}
 
-    def get(name):
-        if name not in cache:
+    def get(key):
+        name, kernel = key
+        if key not in cache:
             w = synth.workload(name)
-            print(f"[gpu-parity] set up {name}", flush=True)
-            h = harness.gpu_problem(w)
+            print(f"[gpu-parity] set up {name} kernel {kernel}", flush=True)
+            h = harness.gpu_problem(w, stencil_kernel=kernel)
             o = harness.oracle_problem(w)
-            cache[name] = (w, h, o)
-        return cache[name]
+            cache[key] = (w, h, o)
+        return cache[key]
 
     yield get
     for w, h, o in cache.values():
@@ -49,7 +53,7 @@ def five_to_nine(c5):
     return out
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL, ids=IDS)
 def test_level_operators(problems, name):
     """Finest operator (device split / assembly) and every Galerkin level, region by region."""
     w, h, (lay, levels, opt) = problems(name)
@@ -63,7 +67,7 @@ def test_level_operators(problems, name):
             assert rel(got, ref) < 1e-12, (l, k, rel(got, ref))
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL, ids=IDS)
 def test_eigenvalue_estimates(problems, name):
     w, h, (lay, levels, opt) = problems(name)
     for l, L in enumerate(levels[:-1]):
@@ -71,7 +75,7 @@ def test_eigenvalue_estimates(problems, name):
         assert abs(lam - L.lam) <= 1e-12 * abs(L.lam), (l, lam, L.lam)
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL, ids=IDS)
 def test_coarse_composite_matrix(problems, name):
     w, h, (lay, levels, opt) = problems(name)
     Ab = levels[-1].Abar
@@ -79,7 +83,7 @@ def test_coarse_composite_matrix(problems, name):
     assert rel(got, Ab) < 1e-12
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL, ids=IDS)
 def test_regional_matvec_and_interface_sum(problems, name):
     """Lemma: Psi [[A]] Psi^T x = A x; and Psi^T Psi bit-exact against the oracle."""
     import torch
@@ -106,7 +110,7 @@ def test_regional_matvec_and_interface_sum(problems, name):
     assert rel(comp.cpu().numpy(), lay.to_composite_avg(lay.unflatten(v)).reshape(-1)) < 1e-15
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL, ids=IDS)
 def test_transfers(problems, name):
     import torch
 
@@ -133,7 +137,7 @@ def test_transfers(problems, name):
         assert rel(ug.cpu().numpy(), uref) < 1e-13, l
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL, ids=IDS)
 def test_smoother(problems, name):
     import torch
 
@@ -149,7 +153,7 @@ def test_smoother(problems, name):
     assert rel(u.cpu().numpy(), lay.flatten(ref)) < 1e-12
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL, ids=IDS)
 def test_vcycle(problems, name):
     import torch
 
@@ -163,7 +167,7 @@ def test_vcycle(problems, name):
     assert rel(z.cpu().numpy(), ref) < 1e-12
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL, ids=IDS)
 def test_pcg(problems, name):
     import torch
 
