@@ -28,6 +28,11 @@ METRIC = "PCG time-to-1e-8 residual + stencil GB/s, FP64 vs mixed/learned forms"
 HBM_PEAK_GBS = 8000.0
 CHEB_BYTES_PER_ROW = 264  # 27 coefficients + u, b, D^-1, d read; d, u written (FP64)
 CG_MATVEC_BYTES_PER_ROW = 232  # 27 coefficients + p read; q written (FP64)
+# HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
+# plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
+# source they were taken with.
+TRAFFIC_BYTES = 9628084106
+TRAFFIC_KERNEL_SHA = "1f047817f411af9f"
 
 CPU_SAMPLE = r"""
 import json, sys, time
@@ -70,6 +75,24 @@ def cpu_baseline(gpu_iterations: int, n_rows: int, its: int = 3):
     }
 
 
+def kernel_source_sha():
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2103_11962_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def copy_probe():
+    import torch
+
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 8, "launches": 5}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,7 +100,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the regional method here keeps all "
               "regions on one device", file=sys.stderr)
@@ -174,7 +202,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (TRAFFIC_BYTES if args.workload == "c2" and kernel_source_sha() == TRAFFIC_KERNEL_SHA
+                        else None),
             "bytes_per_launch": bytes_cheb,
             "avg_launch_ms": avg_cheb,
             "launches": n_cheb,
