@@ -78,7 +78,7 @@ def cpu_baseline(gpu_iterations: int, n_rows: int, its: int = 3):
 def kernel_source_sha():
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2103_11962_amd", "csrc", "kernels.hip")
+    path = os.path.join(ROOT, "paper_2103_11962_amd", "csrc", "kernels_stencil.hip")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 

@@ -43,6 +43,57 @@ static void q1_laplace_element(double h, double K[64]) {
       }
 }
 
+// Reference Q1 isotropic elasticity element matrix (E = 1, Poisson ratio nu, cube of side h):
+// int B^T D B with Voigt strains (xx, yy, zz, yz, xz, xy), 2x2x2 Gauss-Legendre; dof 3a+i is
+// displacement component i of corner a.
+static void q1_elasticity_element(double nu, double h, double* K) {
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = 1.0 / (2.0 * (1.0 + nu));
+  double D[6][6] = {};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) D[i][j] = lam;
+  for (int i = 0; i < 3; ++i) D[i][i] += 2.0 * mu;
+  D[3][3] = D[4][4] = D[5][5] = mu;
+  const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  for (int i = 0; i < 576; ++i) K[i] = 0.0;
+  for (int qz = 0; qz < 2; ++qz)
+    for (int qy = 0; qy < 2; ++qy)
+      for (int qx = 0; qx < 2; ++qx) {
+        const double xi[3] = {g[qx], g[qy], g[qz]};
+        double B[6][24] = {};
+        for (int a = 0; a < 8; ++a) {
+          const int c[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
+          double f[3], df[3];
+          for (int d = 0; d < 3; ++d) {
+            f[d] = c[d] ? xi[d] : 1.0 - xi[d];
+            df[d] = c[d] ? 1.0 : -1.0;
+          }
+          const double gx = df[0] * f[1] * f[2] / h, gy = f[0] * df[1] * f[2] / h, gz = f[0] * f[1] * df[2] / h;
+          B[0][3 * a + 0] = gx;
+          B[1][3 * a + 1] = gy;
+          B[2][3 * a + 2] = gz;
+          B[3][3 * a + 1] = gz;
+          B[3][3 * a + 2] = gy;
+          B[4][3 * a + 0] = gz;
+          B[4][3 * a + 2] = gx;
+          B[5][3 * a + 0] = gy;
+          B[5][3 * a + 1] = gx;
+        }
+        double DB[6][24];
+        for (int i = 0; i < 6; ++i)
+          for (int j = 0; j < 24; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < 6; ++k) v += D[i][k] * B[k][j];
+            DB[i][j] = v;
+          }
+        for (int i = 0; i < 24; ++i)
+          for (int j = 0; j < 24; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < 6; ++k) v += B[k][i] * DB[k][j];
+            K[i * 24 + j] += 0.125 * h * h * h * v;
+          }
+      }
+}
+
 }  // namespace rmg
 
 using namespace rmg;
@@ -131,7 +182,7 @@ rmg_status rmg_build_regions(rmg_handle* h, int dim, int ndof, int nreg, const i
   API_BEGIN
   use_device(h);
   RMG_REQUIRE(dim == 2 || dim == 3, RMG_ERR_ARG, "dim must be 2 or 3");
-  RMG_REQUIRE(ndof == 1, RMG_ERR_ARG, "only scalar problems (ndof = 1) are supported by this build");
+  RMG_REQUIRE(ndof == 1 || (ndof == 3 && dim == 3), RMG_ERR_ARG, "ndof must be 1, or 3 with dim 3");
   RMG_REQUIRE(nreg >= 1 && extent && origin, RMG_ERR_ARG, "need nreg >= 1 and extent/origin arrays");
   RMG_REQUIRE(mask < (1u << (2 * dim)), RMG_ERR_ARG, "dirichlet mask has bits beyond 2*dim");
   h->have_regions = h->have_operator = h->have_hierarchy = false;
@@ -151,7 +202,7 @@ rmg_status rmg_build_regions(rmg_handle* h, int dim, int ndof, int nreg, const i
   build_level0(h);
   h->region_set.assign(nreg, false);
   Level& L = *h->levels[0];
-  const size_t nb = sizeof(double) * (size_t)L.n;
+  const size_t nb = sizeof(double) * (size_t)L.ndofs();
   h->cg_x.alloc(nb);
   h->cg_r.alloc(nb);
   h->cg_p.alloc(nb);
@@ -176,14 +227,14 @@ rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const dou
   if (!any || L.npts != npts || !L.coef.p) {
     RMG_REQUIRE(!any || L.npts == npts, RMG_ERR_ARG, "all regions must use the same stencil size");
     L.npts = npts;
-    L.coef.alloc(sizeof(double) * coef_elems(L.n, npts));
-    RMG_HIP(hipMemsetAsync(L.coef.p, 0, sizeof(double) * coef_elems(L.n, npts), h->stream));
+    L.coef.alloc(sizeof(double) * coef_elems(L.n, L.ncoef()));
+    RMG_HIP(hipMemsetAsync(L.coef.p, 0, sizeof(double) * coef_elems(L.n, L.ncoef()), h->stream));
   }
   const RegionGeo& R = L.regs[region];
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   DBuf soa;
-  soa.alloc(sizeof(double) * (size_t)npts * R.n);
-  RMG_HIP(hipMemcpyAsync(soa.p, coef, sizeof(double) * (size_t)npts * R.n, kind, h->stream));
+  soa.alloc(sizeof(double) * (size_t)L.ncoef() * R.n);
+  RMG_HIP(hipMemcpyAsync(soa.p, coef, sizeof(double) * (size_t)L.ncoef() * R.n, kind, h->stream));
   launch_region_stencil_io(L, region, soa.as<double>(), 1, h->stream);
   DBuf flag;
   flag.alloc(sizeof(int));
@@ -230,6 +281,7 @@ rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef
   RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
   const bool ok = (h->dim == 3 && npts == 27) || (h->dim == 2 && (npts == 5 || npts == 9));
   RMG_REQUIRE(ok, RMG_ERR_ARG, "npts must be 27 in 3D and 5 or 9 in 2D");
+  RMG_REQUIRE(h->ndof == 1, RMG_ERR_ARG, "the composite split handles scalar problems");
   RMG_REQUIRE(tensor_layout(h), RMG_ERR_SHAPE, "the composite split needs a tensor-product region layout");
   DBuf tmp;
   const double* src = coef;
@@ -261,16 +313,32 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
   Level& L = level_of(h, 0);
   RMG_REQUIRE(h->dim == 3, RMG_ERR_ARG, "Q1 assembly needs a 3D layout");
   RMG_REQUIRE(hsize > 0.0 && std::isfinite(hsize), RMG_ERR_ARG, "element size must be positive");
-  RMG_REQUIRE(pde == RMG_PDE_LAPLACE || pde == RMG_PDE_DIFFUSION, RMG_ERR_ARG,
-              "only Laplace and diffusion are supported by this build");
+  RMG_REQUIRE(pde == RMG_PDE_LAPLACE || pde == RMG_PDE_DIFFUSION || pde == RMG_PDE_ELASTICITY, RMG_ERR_ARG,
+              "unknown pde");
+  RMG_REQUIRE((pde == RMG_PDE_ELASTICITY) == (h->ndof == 3), RMG_ERR_ARG,
+              "elasticity needs ndof = 3, scalar problems ndof = 1");
   RMG_REQUIRE(pde != RMG_PDE_DIFFUSION || elem_coef != nullptr, RMG_ERR_ARG, "diffusion needs elem_coef");
-  (void)youngs;
-  (void)nu;
-  double K[64];
-  q1_laplace_element(hsize, K);
   L.npts = 27;
-  L.coef.alloc(sizeof(double) * coef_elems(L.n, 27));
-  launch_assemble_q1_scalar(L, K, pde == RMG_PDE_DIFFUSION ? elem_coef : nullptr, h->stream);
+  L.coef.alloc(sizeof(double) * coef_elems(L.n, L.ncoef()));
+  if (pde == RMG_PDE_ELASTICITY) {
+    RMG_REQUIRE(youngs != nullptr, RMG_ERR_ARG, "elasticity needs Young's modulus per region");
+    RMG_REQUIRE(nu > -1.0 && nu < 0.5, RMG_ERR_ARG, "Poisson ratio must lie in (-1, 0.5)");
+    for (int k = 0; k < h->nreg; ++k)
+      RMG_REQUIRE(youngs[k] > 0.0 && std::isfinite(youngs[k]), RMG_ERR_NUMERIC, "Young's moduli must be positive");
+    std::vector<double> K(576);
+    q1_elasticity_element(nu, hsize, K.data());
+    DBuf dK, dE;
+    dK.alloc(sizeof(double) * 576);
+    dE.alloc(sizeof(double) * h->nreg);
+    RMG_HIP(hipMemcpyAsync(dK.p, K.data(), sizeof(double) * 576, hipMemcpyHostToDevice, h->stream));
+    RMG_HIP(hipMemcpyAsync(dE.p, youngs, sizeof(double) * h->nreg, hipMemcpyHostToDevice, h->stream));
+    launch_assemble_q1_elasticity(L, dK.as<double>(), dE.as<double>(), h->stream);
+    RMG_HIP(hipStreamSynchronize(h->stream));
+  } else {
+    double K[64];
+    q1_laplace_element(hsize, K);
+    launch_assemble_q1_scalar(L, K, pde == RMG_PDE_DIFFUSION ? elem_coef : nullptr, h->stream);
+  }
   launch_dirichlet_split(L, h->stream);
   DBuf flag;
   flag.alloc(sizeof(int));
@@ -295,7 +363,10 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->cheb_degree >= 1 && opt->cheb_degree <= 16, RMG_ERR_ARG, "cheb_degree must be in [1, 16]");
   RMG_REQUIRE(opt->eig_ratio > 1.0 && opt->boost > 0.0, RMG_ERR_ARG, "need eig_ratio > 1 and boost > 0");
   RMG_REQUIRE(opt->power_iters >= 1, RMG_ERR_ARG, "power_iters must be >= 1");
-  RMG_REQUIRE(opt->precision == RMG_PREC_FP64, RMG_ERR_ARG, "only FP64 precision is supported by this build");
+  RMG_REQUIRE(opt->precision >= RMG_PREC_FP64 && opt->precision <= RMG_PREC_FP32_BF16, RMG_ERR_ARG,
+              "unknown precision");
+  RMG_REQUIRE(opt->precision == RMG_PREC_FP64 || h->dim == 3, RMG_ERR_ARG,
+              "the low-precision V-cycle needs 27-point (3D) levels");
   RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 2, RMG_ERR_ARG, "stencil_kernel must be 0, 1 or 2");
   h->opt = *opt;
   h->have_hierarchy = false;
@@ -316,10 +387,10 @@ rmg_status rmg_apply_vcycle(rmg_handle* h, const double* r, double* z, int layou
   RMG_REQUIRE(layout == RMG_LAYOUT_COMPOSITE || layout == RMG_LAYOUT_REGIONAL, RMG_ERR_ARG, "bad layout");
   Level& L = *h->levels[0];
   if (layout == RMG_LAYOUT_REGIONAL) {
-    vcycle(h, 0, r, z);
+    apply_preconditioner(h, r, z);
   } else {
     launch_to_regional(L, r, h->cg_b.as<double>(), h->stream);
-    vcycle(h, 0, h->cg_b.as<double>(), h->cg_z.as<double>());
+    apply_preconditioner(h, h->cg_b.as<double>(), h->cg_z.as<double>());
     launch_to_composite(L, h->cg_z.as<double>(), z, 0, h->stream);
   }
   API_END
@@ -399,7 +470,7 @@ rmg_status rmg_restrict(rmg_handle* h, int level, const double* r, double* w) {
   Level& C = *h->levels[level + 1];
   {
     // r / mult on shared nodes: the ResidualScaled update with b = r and a zero product
-    launch_zero(F.n, F.u2.as<double>(), h->stream);
+    launch_zero(F.ndofs(), F.u2.as<double>(), h->stream);
     StencilArgs a;
     a.op = StencilOp::ResidualScaled;
     a.x = F.u2.as<double>();
@@ -407,7 +478,7 @@ rmg_status rmg_restrict(rmg_handle* h, int level, const double* r, double* w) {
     a.b = r;
     launch_stencil_op(F, a, h->stream);
   }
-  launch_restrict(F, C, F.r.as<double>(), w, h->stream);
+  launch_restrict(F, C, false, F.r.as<double>(), w, h->stream);
   API_END
 }
 
@@ -417,7 +488,7 @@ rmg_status rmg_prolongate_add(rmg_handle* h, int level, const double* ubar, doub
   require_hierarchy(h);
   RMG_REQUIRE(level >= 0 && level + 1 < (int)h->levels.size(), RMG_ERR_ARG, "no coarser level");
   RMG_REQUIRE(ubar && u, RMG_ERR_ARG, "null pointer");
-  launch_prolong_add(*h->levels[level], *h->levels[level + 1], ubar, u, h->stream);
+  launch_prolong_add(*h->levels[level], *h->levels[level + 1], false, ubar, u, h->stream);
   API_END
 }
 
@@ -451,9 +522,10 @@ rmg_status rmg_get_level_stencil(rmg_handle* h, int level, int region, double* h
   RMG_REQUIRE(L.coef.p != nullptr, RMG_ERR_NOT_SETUP, "no operator on this level");
   const RegionGeo& R = L.regs[region];
   DBuf soa;
-  soa.alloc(sizeof(double) * (size_t)L.npts * R.n);
+  soa.alloc(sizeof(double) * (size_t)L.ncoef() * R.n);
   launch_region_stencil_io(L, region, soa.as<double>(), 0, h->stream);
-  RMG_HIP(hipMemcpyAsync(host_out, soa.p, sizeof(double) * (size_t)L.npts * R.n, hipMemcpyDeviceToHost, h->stream));
+  RMG_HIP(hipMemcpyAsync(host_out, soa.p, sizeof(double) * (size_t)L.ncoef() * R.n, hipMemcpyDeviceToHost,
+                         h->stream));
   RMG_HIP(hipStreamSynchronize(h->stream));
   API_END
 }

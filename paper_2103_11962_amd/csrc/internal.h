@@ -76,6 +76,7 @@ struct LevelView {
   int cx, cy, cz;    // composite node extents
   unsigned mask;     // Dirichlet faces
   int npts;          // stencil points stored (5, 9 or 27)
+  int ndof;          // unknowns per node (1, or 3 for elasticity)
 };
 
 // Device buffer owned by the library.
@@ -91,9 +92,13 @@ struct DBuf {
   DBuf& operator=(const DBuf&) = delete;
 };
 
+// Coefficient storage types of a level's low-precision copy.
+enum CoefType { kCoefF64 = 0, kCoefF32 = 1, kCoefBF16 = 2 };
+
 struct Level {
   int dim = 3;
   int npts = 27;
+  int ndof = 1;
   int nreg = 0;
   unsigned mask = 0;   // Dirichlet faces
   int comp[3] = {1, 1, 1};
@@ -110,20 +115,27 @@ struct Level {
   DBuf d_gptr;    // int64 [ngroups+1]
   DBuf d_gcopy;   // int32 regional node indices
   DBuf d_gcomp;   // int32 composite node index of each group
-  // operator
-  DBuf coef;      // double [npts][n]
-  DBuf dinv;      // double [n]
+  // operator (FP64, wave-tiled, ncoef() values per node: npts blocks of ndof x ndof)
+  DBuf coef;
+  DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
   double lambda = 0.0;
   std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step: direction and residual factors
   // work vectors (regional): b (rhs), u / u2 (ping-pong), d (Chebyshev direction), r (residual)
   DBuf b, u, u2, d, r;
-  // coarsest level: composite inverse and owner map
+  // low-precision V-cycle copy (FP32 vectors; FP32 or BF16 coefficients)
+  int ct_lo = kCoefF64;  // kCoefF64: no copy
+  DBuf coef_lo;          // float or uint16 (bf16), wave-tiled like coef
+  DBuf center_lo;        // bf16 storage only: FP32 centre blocks [n][ndof*ndof]
+  DBuf dinv_lo, b32, u32, u232, d32, r32;
+  // coarsest level: composite inverse and owner map (nc = composite dofs)
   int nc = 0;
   DBuf ainv;       // double [nc][nc]
-  DBuf comp_owner; // int32 [nc] regional index of the owner copy
+  DBuf comp_owner; // int32 [ncomp] regional node index of the owner copy
   DBuf cvec, cvec2;  // double [nc]
   std::vector<double> abar_host;  // dense composite coarse operator (for inspection)
 
+  int ncoef() const { return npts * ndof * ndof; }
+  int64_t ndofs() const { return n * ndof; }
   LevelView view() const;
 };
 
@@ -156,6 +168,7 @@ struct rmg_handle {
   std::vector<rmg::Level*> levels;
   // CG work vectors (finest level, regional)
   rmg::DBuf cg_x, cg_r, cg_p, cg_q, cg_z, cg_b, tmp_a, tmp_b;
+  rmg::DBuf cg_z32;     // FP32 output of the low-precision V-cycle
   rmg::DBuf partials;   // double partial sums
   rmg::DBuf scalars;    // double device scalars
   double* host_scalars = nullptr;  // pinned
@@ -175,7 +188,10 @@ void build_coarse_solver(rmg_handle* h, Level& L);
 // solver.cpp
 void setup_hierarchy(rmg_handle* h);
 // z = V_level(b) with zero initial guess; z must not be one of the level's work vectors.
-void vcycle(rmg_handle* h, int level, const double* b, double* z);
+// lowp: FP32 vectors and the levels' low-precision operators (b, z are float*), else FP64.
+void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z);
+// z = M^-1 r (one V-cycle in the configured precision); FP64 regional vectors.
+void apply_preconditioner(rmg_handle* h, const double* r, double* z);
 void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
          rmg_status* st);
 void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out);

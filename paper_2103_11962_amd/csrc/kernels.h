@@ -1,4 +1,8 @@
-// Launchers of the HIP kernels (FP64 scalar path).  All launches are asynchronous on `st`.
+// Launchers of the HIP kernels.  All launches are asynchronous on `st`.
+//
+// Vectors are regional (or composite) arrays with `ndof` values per node.  Launchers that take
+// `lowp` run on the level's FP32 vectors and its low-precision coefficient copy (FP32, or BF16
+// off-diagonals with FP32 centre blocks); otherwise vectors are FP64 with FP64 coefficients.
 #pragma once
 #include "internal.h"
 
@@ -6,24 +10,25 @@ namespace rmg {
 
 // Per-node operations applied after a regional stencil product z = A^(k) x.
 enum class StencilOp {
-  Matvec,       // y = Psi^T Psi A x
-  Residual,     // r = b - Psi^T Psi A x
+  Matvec,          // y = Psi^T Psi A x
+  Residual,        // r = b - Psi^T Psi A x
   ResidualScaled,  // r = (b - Psi^T Psi A x) / mult (input of the regional restriction)
-  Cheb,         // r = b - Psi^T Psi A u; d = c1 d + c2 D~^-1 r; u_out = u + d
-  ChebFirst,    // same with the old direction ignored (c1 treated as 0)
-  CgQ,          // q = Psi^T Psi A p and partial sums of (p, q)
+  Cheb,            // r = b - Psi^T Psi A u; d = c1 d + c2 D~^-1 r; u_out = u + d
+  ChebFirst,       // same with the old direction ignored (c1 treated as 0)
+  CgQ,             // q = Psi^T Psi A p and partial sums of (p, q)
 };
 
 struct StencilArgs {
   StencilOp op;
-  const double* x = nullptr;   // stencil input (u or p)
-  double* out = nullptr;       // y / r / u_out / q
-  const double* b = nullptr;   // right-hand side (Residual*, Cheb*)
-  const double* dinv = nullptr;
-  double* d = nullptr;
+  bool lowp = false;           // FP32 vectors, low-precision coefficients
+  const void* x = nullptr;     // stencil input (u or p)
+  void* out = nullptr;         // y / r / u_out / q
+  const void* b = nullptr;     // right-hand side (Residual*, Cheb*)
+  const void* dinv = nullptr;
+  void* d = nullptr;
   double c1 = 0.0, c2 = 0.0;
   double* partials = nullptr;  // CgQ / dot-fused variants: one double per block
-  const double* dotw = nullptr;  // Cheb: when set, partial sums of (dotw, u_out) are produced
+  const void* dotw = nullptr;  // Cheb: when set, partial sums of (dotw, u_out) are produced
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // when set, recorded around the stencil kernel only
 };
 
@@ -31,76 +36,80 @@ struct StencilArgs {
 // Returns the number of partial sums written (0 when no reduction was requested).
 int64_t launch_stencil_op(const Level& L, const StencilArgs& a, hipStream_t st);
 
-// Interface sum w = Psi^T Psi v on a level (in place allowed: v == w only if out-of-place not needed).
+// Interface sum w = Psi^T Psi v on a level (FP64; v == w allowed).
 void launch_interface_sum(const Level& L, const double* v, double* w, hipStream_t st);
 
-// Owner-masked composite dot product: partial sums written to `partials`; returns their count.
+// Owner-masked composite dot product (FP64): partial sums written to `partials`; returns their count.
 int64_t launch_dot(const Level& L, const double* a, const double* b, double* partials, hipStream_t st);
 
 // Deterministic sum of `n` partials into scalars[slot].
 void launch_reduce(const double* partials, int64_t n, double* scalars, int slot, hipStream_t st);
 
 // Pointwise: d = c * dinv * b; u = d (first Chebyshev step from a zero guess).
-void launch_cheb_zero(const Level& L, const double* b, const double* dinv, double c, double* d, double* u,
+void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* d, void* u,
                       hipStream_t st);
 
 // Restriction level -> level+1 (input already divided by multiplicity), including coarse interface sum.
-void launch_restrict(const Level& F, const Level& C, const double* r_scaled, double* w, hipStream_t st);
+void launch_restrict(const Level& F, const Level& C, bool lowp, const void* r_scaled, void* w, hipStream_t st);
 // Prolongation u += P ubar (level+1 -> level).
-void launch_prolong_add(const Level& F, const Level& C, const double* ubar, double* u, hipStream_t st);
-// Galerkin product per region: C.coef = R A P.
+void launch_prolong_add(const Level& F, const Level& C, bool lowp, const void* ubar, void* u, hipStream_t st);
+// Galerkin product per region (FP64): C.coef = R A P.
 void launch_rap(const Level& F, Level& C, hipStream_t st);
 
-// Diagonal (centre coefficient) into a regional vector.
+// Point diagonal (centre coefficient of every dof) into a regional FP64 vector.
 void launch_diag(const Level& L, double* out, hipStream_t st);
 // out = 1 / in; flags[0] set to 1 if some entry is not finite or not positive.
 void launch_recip_check(int64_t n, const double* in, double* out, int* flag, hipStream_t st);
 // Power-method start vector (SplitMix64 counter generator, zero on Dirichlet nodes).
 void launch_start_vector(const Level& L, int level, uint64_t seed, double* out, hipStream_t st);
-// Pointwise helpers.
+// Pointwise helpers (FP64).
 void launch_scale(int64_t n, const double* scalars, int slot, int mode, const double* x, double* y,
                   hipStream_t st);  // mode 0: y = x / sqrt(s); mode 1: y = x * s
 void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStream_t st);  // y = a*b
+void launch_f64_to_f32(int64_t n, const double* in, float* out, hipStream_t st);
+void launch_f32_to_f64(int64_t n, const float* in, double* out, hipStream_t st);
+// Low-precision copy of a level's operator: coef_lo (FP32, or BF16 off-diagonals with FP32
+// centre blocks whose diagonal keeps each row sum of the FP64 operator) and dinv_lo.
+void launch_make_lowp(Level& L, int coef_type, hipStream_t st);
 
-// Composite <-> regional.
+// Composite <-> regional (FP64).
 void launch_to_regional(const Level& L, const double* comp, double* reg, hipStream_t st);
 void launch_to_composite(const Level& L, const double* reg, double* comp, int average, hipStream_t st);
 
-// Coarsest level: gather owner copies, dense GEMV with the inverse, scatter to copies.
-void launch_coarse_solve(const Level& L, const double* b, double* u, hipStream_t st);
+// Coarsest level: gather owner copies, dense FP64 GEMV with the inverse, scatter to copies.
+void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipStream_t st);
 // In-place Gauss-Jordan inversion of an SPD n x n matrix (row-major), with work buffers row/col of n.
 void launch_gauss_jordan(double* A, int n, double* row, double* col, hipStream_t st);
 void launch_check_inverse(const double* A, int n, int* flag, hipStream_t st);
 
 // Q1 assembly (scalar): Kref = 8x8 element matrix of the unit cube scaled by h.
 void launch_assemble_q1_scalar(const Level& L, const double* Kref, const double* elem_coef, hipStream_t st);
+// Q1 elasticity: Kdev = device 24x24 element matrix for E = 1, youngs_dev = E per region.
+void launch_assemble_q1_elasticity(const Level& L, const double* Kdev, const double* youngs_dev, hipStream_t st);
 // Dirichlet identity split 1/mult on shared Dirichlet nodes (after assembly).
 void launch_dirichlet_split(const Level& L, hipStream_t st);
 // Zero couplings that point outside each region box; flag non-finite values.
 void launch_mask_stencil(const Level& L, int* flag, hipStream_t st);
-
 // Region matrices from a composite stencil [npts][ncomp] on a tensor-product layout (Section 4 split).
 void launch_split_composite(const Level& L, const double* comp, int* flag, hipStream_t st);
-
-// Copy one region's stencil between a structure-of-arrays buffer [npts][region nodes] and the
+// Copy one region's stencil between a structure-of-arrays buffer [ncoef][region nodes] and the
 // level's wave-tiled storage (to_level = 1: soa -> level).
 void launch_region_stencil_io(const Level& L, int region, double* soa, int to_level, hipStream_t st);
 
-// CG helpers.
-// alpha = s[rz]/s[pq]; x += alpha p; r -= alpha q; partial sums of owner-masked (r, r).
+// CG helpers (FP64).
+// x += alpha p; r -= alpha q; partial sums of owner-masked (r, r).
 int64_t launch_cg_update(const Level& L, double* scalars, double* x, double* r, const double* p,
                          const double* q, double* partials, hipStream_t st);
-// beta = s[rz_new]/s[rz]; s[rz] = s[rz_new]; p = z + beta p.
+// p = z + beta p.
 void launch_cg_direction(int64_t n, double* scalars, const double* z, double* p, hipStream_t st);
-// mode 0: alpha = rz / pq; mode 1: beta = rz_new / rz, rz = rz_new.
+// mode 0: alpha = rz / pq; mode 1: beta = rz_new / rz, rz = rz_new;
+// mode 2 (flexible CG): beta = -alpha (z_new, q) / rz, rz = rz_new.
 void launch_cg_scalars(double* scalars, int mode, hipStream_t st);
 void launch_copy(int64_t n, const double* src, double* dst, hipStream_t st);
 void launch_zero(int64_t n, double* dst, hipStream_t st);
-// y = b - y (pointwise)
-void launch_sub_from(int64_t n, const double* b, double* y, hipStream_t st);
 
 // scalar slots
-enum Slot { kRZ = 0, kPQ = 1, kRR = 2, kAlpha = 3, kBeta = 4, kRZnew = 5, kBB = 6, kTmp = 7, kTmp2 = 8,
+enum Slot { kRZ = 0, kPQ = 1, kRR = 2, kAlpha = 3, kBeta = 4, kRZnew = 5, kBB = 6, kTmp = 7, kTmp2 = 8, kZQ = 9,
             kNumSlots = 16 };
 
 }  // namespace rmg

@@ -1,0 +1,332 @@
+// Regional stencil operations: the stencil product z = A^(k) x of every region fused with the
+// node update it feeds (matvec, residual, Chebyshev step, CG product), followed by the
+// interface-group kernel that sums the partial products of shared nodes over their copies in
+// ascending region order (Psi^T Psi, Section 3.1 / the RegMatVec algorithm) and finishes them.
+//
+// Template parameters: NPTS stencil points, NDOF unknowns per node (3x3 coefficient blocks for
+// elasticity), V vector type (double or float), C coefficient storage type (double, float or
+// uint16_t = bfloat16; with bfloat16 the centre block comes from an FP32 array).
+#include "device_common.h"
+
+namespace rmg {
+
+template <class V>
+struct OpP {
+  const V* x;
+  V* out;
+  const V* b;
+  const V* dinv;
+  V* d;
+  V c1, c2;
+  const V* dotw;
+};
+
+// Final update of dof i once z = (Psi^T Psi A x)_i is known; m = multiplicity of its node,
+// xself = x_i.  Returns the dof's contribution to the fused reduction, if any.
+template <StencilOp OP, bool DOT, class V>
+__device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m, V xself) {
+  if constexpr (OP == StencilOp::Matvec) {
+    p.out[i] = z;
+    return 0.0;
+  } else if constexpr (OP == StencilOp::Residual) {
+    p.out[i] = p.b[i] - z;
+    return 0.0;
+  } else if constexpr (OP == StencilOp::ResidualScaled) {
+    const V r = p.b[i] - z;
+    p.out[i] = (m == 1) ? r : r / (V)m;
+    return 0.0;
+  } else if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) {
+    const V r = p.b[i] - z;
+    V dd = p.c2 * (p.dinv[i] * r);
+    if constexpr (OP == StencilOp::Cheb) dd = p.c1 * p.d[i] + dd;
+    p.d[i] = dd;
+    const V u = xself + dd;
+    p.out[i] = u;
+    if constexpr (DOT) return (double)p.dotw[i] * (double)u;
+    return 0.0;
+  } else {  // CgQ
+    p.out[i] = z;
+    return (double)xself * (double)z;
+  }
+}
+
+// Coefficient (s, a, b) of node gi; the bfloat16 storage keeps its centre block in FP32.
+template <int NPTS, int NDOF, class C>
+__device__ __forceinline__ auto coefv(const C* __restrict__ cf, const float* __restrict__ centre, int64_t gi, int s,
+                                      int a, int b) {
+  if constexpr (sizeof(C) == 2) {
+    if (s == center_index<NPTS>()) return centre[gi * NDOF * NDOF + a * NDOF + b];
+  }
+  return CoefLoad<C>::get(cf + (s * NDOF * NDOF + a * NDOF + b) * kTile);
+}
+
+// ---------------------------------------------------------------- node-parallel
+template <int NPTS, int NDOF, class V, class C, StencilOp OP, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __restrict__ coef,
+                                                    const float* __restrict__ centre, OpP<V> p,
+                                                    double* __restrict__ partials) {
+  constexpr int NCOEF = NPTS * NDOF * NDOF;
+  const BlockDesc bd = L.blocks[blockIdx.x];
+  const RegionGeo R = L.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  double contrib = 0.0;
+  if (li < R.n) {
+    int x, y, z;
+    decompose(R, li, x, y, z);
+    const int64_t gi = R.off + li;
+    const V* __restrict__ xr = p.x + R.off * NDOF;
+    const C* __restrict__ cf = coef + coef_index(gi, 0, NCOEF);
+    const int sy = R.ex, sz = R.ex * R.ey;
+    const bool inner = x > 0 && x < R.ex - 1 && y > 0 && y < R.ey - 1 && (NPTS != 27 || (z > 0 && z < R.ez - 1));
+    V acc[NDOF];
+#pragma unroll
+    for (int a = 0; a < NDOF; ++a) acc[a] = (V)0;
+#pragma unroll
+    for (int s = 0; s < NPTS; ++s) {
+      int dx, dy, dz;
+      stencil_offset<NPTS>(s, dx, dy, dz);
+      const bool ok = inner || ((unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
+                                (unsigned)(z + dz) < (unsigned)R.ez);
+      if (ok) {
+        const int nb = li + dx + dy * sy + dz * sz;
+#pragma unroll
+        for (int a = 0; a < NDOF; ++a)
+#pragma unroll
+          for (int b = 0; b < NDOF; ++b) acc[a] += (V)coefv<NPTS, NDOF, C>(cf, centre, gi, s, a, b) * xr[nb * NDOF + b];
+      }
+    }
+    if (!inner && is_shared(L, R, x, y, z)) {
+#pragma unroll
+      for (int a = 0; a < NDOF; ++a) p.out[gi * NDOF + a] = acc[a];  // summed over copies by k_iface
+    } else {
+#pragma unroll
+      for (int a = 0; a < NDOF; ++a) contrib += finish<OP, DOT, V>(p, gi * NDOF + a, acc[a], 1, xr[li * NDOF + a]);
+    }
+  }
+  if constexpr (DOT || OP == StencilOp::CgQ) {
+    const double s = block_sum(contrib);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------ 3D scalar stencil, 2.5D tiles
+// A block owns a tile of ty x-rows (tx nodes each) of one region and marches nz planes in z.
+// The input vector's planes pass through two LDS slots; each thread keeps its 3x3
+// neighbourhood of planes z-1, z, z+1 in registers (rotated per plane), so it reads only the
+// new plane from LDS, and the plane after next is prefetched from global memory into registers
+// while the current plane is computed.  Neighbours outside the region box read 0 from LDS and
+// have zero coefficients, so the 27-term sum needs no bounds branches.
+constexpr int kT3 = 512;           // threads per 3D tile block
+constexpr int kT3Plane = 1544;     // max (ty+2)(tx+2) over tx*ty <= 512
+constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
+
+template <class V, class C, StencilOp OP, bool DOT>
+__global__ __launch_bounds__(kT3) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles,
+                                                   const C* __restrict__ coef, const float* __restrict__ centre,
+                                                   OpP<V> p, double* __restrict__ partials) {
+  __shared__ V pl[2][kT3Plane];
+  const Tile3 T = tiles[blockIdx.x];
+  const RegionGeo R = L.regs[T.region];
+  const int W = T.tx + 2, PL = (T.ty + 2) * W;
+  const V* __restrict__ xr = p.x + R.off;
+  const int t = threadIdx.x;
+  const int ty = t / T.tx, tx = t - ty * T.tx;
+  const int x = T.x0 + tx, y = T.y0 + ty;
+  const bool active = ty < T.ty && x < R.ex && y < R.ey;
+  const int sy = R.ex, sz = R.ex * R.ey;
+  V pre[kT3Fetch];
+  auto fetch = [&](int zz) {
+#pragma unroll
+    for (int k = 0; k < kT3Fetch; ++k) {
+      const int idx = t + k * kT3;
+      V v = (V)0;
+      if (idx < PL) {
+        const int r = idx / W;
+        const int xx = T.x0 + idx - r * W - 1, yy = T.y0 - 1 + r;
+        if ((unsigned)zz < (unsigned)R.ez && (unsigned)yy < (unsigned)R.ey && (unsigned)xx < (unsigned)R.ex)
+          v = xr[zz * sz + yy * sy + xx];
+      }
+      pre[k] = v;
+    }
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int k = 0; k < kT3Fetch; ++k) {
+      const int idx = t + k * kT3;
+      if (idx < PL) pl[slot][idx] = pre[k];
+    }
+  };
+  V rm[9], rc[9], rp[9];
+  auto readn = [&](int slot, V* r) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const int dx = j % 3 - 1, dy = j / 3 - 1;
+      r[j] = pl[slot][(ty + 1 + dy) * W + tx + 1 + dx];
+    }
+  };
+  const int z0 = T.z0, z1 = T.z0 + T.nz;
+  fetch(z0 - 1);
+  store(0);
+  fetch(z0);
+  store(1);
+  __syncthreads();
+  if (active) {
+    readn(0, rm);
+    readn(1, rc);
+  }
+  __syncthreads();
+  fetch(z0 + 1);
+  store(0);
+  __syncthreads();
+  double contrib = 0.0;
+  for (int zz = z0; zz < z1; ++zz) {
+    const int sp = (zz - z0) & 1;  // slot holding plane zz+1
+    if (active) readn(sp, rp);
+    fetch(zz + 2);
+    if (active) {
+      const int li = zz * sz + y * sy + x;
+      const int64_t gi = R.off + li;
+      const C* __restrict__ cf = coef + coef_index(gi, 0, 27);
+      V acc = (V)0;
+#pragma unroll
+      for (int s = 0; s < 27; ++s) {
+        const int j = s % 9, dz = s / 9 - 1;
+        const V v = dz < 0 ? rm[j] : (dz == 0 ? rc[j] : rp[j]);
+        acc += (V)coefv<27, 1, C>(cf, centre, gi, s, 0, 0) * v;
+      }
+      const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
+      if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
+      else contrib += finish<OP, DOT, V>(p, gi, acc, 1, rc[4]);
+    }
+    store(sp ^ 1);  // plane zz+2 replaces plane zz
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      rm[j] = rc[j];
+      rc[j] = rp[j];
+    }
+    __syncthreads();
+  }
+  if constexpr (DOT || OP == StencilOp::CgQ) {
+    double v = contrib;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __shared__ double sm[kT3 / 64];
+    if ((t & 63) == 0) sm[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int i = 0; i < kT3 / 64; ++i) s += sm[i];
+      partials[blockIdx.x] = s;
+    }
+  }
+}
+
+// ----------------------------------------------------------- interface groups
+template <int NDOF, class V, StencilOp OP, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gptr, const int* __restrict__ gcopy,
+                                                  int64_t ng, OpP<V> p, double* __restrict__ partials) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double contrib = 0.0;
+  if (g < ng) {
+    const int64_t a0 = gptr[g], e = gptr[g + 1];
+    const int m = (int)(e - a0);
+#pragma unroll
+    for (int a = 0; a < NDOF; ++a) {
+      V s = (V)0;
+      for (int64_t c = a0; c < e; ++c) s += p.out[(int64_t)gcopy[c] * NDOF + a];
+      for (int64_t c = a0; c < e; ++c) {
+        const int64_t i = (int64_t)gcopy[c] * NDOF + a;
+        const double v = finish<OP, DOT, V>(p, i, s, m, p.x[i]);
+        if (c == a0) contrib += v;  // the first copy (lowest region) owns the composite dof
+      }
+    }
+  }
+  if constexpr (DOT || OP == StencilOp::CgQ) {
+    const double s = block_sum(contrib);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+template <int NPTS, int NDOF, class V, class C, StencilOp OP, bool DOT>
+static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
+  OpP<V> p{static_cast<const V*>(a.x), static_cast<V*>(a.out), static_cast<const V*>(a.b),
+           static_cast<const V*>(a.dinv), static_cast<V*>(a.d), (V)a.c1, (V)a.c2, static_cast<const V*>(a.dotw)};
+  const C* coef = a.lowp ? L.coef_lo.as<C>() : L.coef.as<C>();
+  const float* centre = L.center_lo.as<float>();
+  const LevelView v = L.view();
+  const bool tiled = NPTS == 27 && NDOF == 1 && L.use_tiles;
+  if (a.ev0) RMG_HIP(hipEventRecord(a.ev0, st));
+  if constexpr (NPTS == 27 && NDOF == 1) {
+    if (tiled) {
+      hipLaunchKernelGGL((k_stencil3d<V, C, OP, DOT>), dim3(L.tiles.size()), dim3(kT3), 0, st, v,
+                         L.d_tiles.as<Tile3>(), coef, centre, p, a.partials);
+    }
+  }
+  if (!tiled)
+    hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT>), dim3(L.blocks.size()), dim3(kBlock), 0, st, v, coef,
+                       centre, p, a.partials);
+  LAUNCH_CHECK();
+  if (a.ev1) RMG_HIP(hipEventRecord(a.ev1, st));
+  const int64_t nb = tiled ? (int64_t)L.tiles.size() : (int64_t)L.blocks.size();
+  int64_t ngb = 0;
+  if (L.ngroups > 0) {
+    ngb = cdiv(L.ngroups, kBlock);
+    hipLaunchKernelGGL((k_iface<NDOF, V, OP, DOT>), dim3(ngb), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
+                       L.d_gcopy.as<int>(), L.ngroups, p, a.partials ? a.partials + nb : nullptr);
+    LAUNCH_CHECK();
+  }
+  return (DOT || OP == StencilOp::CgQ) ? nb + ngb : 0;
+}
+
+// FP64: every operation.
+template <int NPTS, int NDOF>
+static int64_t ops_f64(const Level& L, const StencilArgs& a, hipStream_t st) {
+  const bool dot = a.dotw != nullptr;
+  switch (a.op) {
+    case StencilOp::Matvec: return run<NPTS, NDOF, double, double, StencilOp::Matvec, false>(L, a, st);
+    case StencilOp::Residual: return run<NPTS, NDOF, double, double, StencilOp::Residual, false>(L, a, st);
+    case StencilOp::ResidualScaled:
+      return run<NPTS, NDOF, double, double, StencilOp::ResidualScaled, false>(L, a, st);
+    case StencilOp::Cheb:
+      return dot ? run<NPTS, NDOF, double, double, StencilOp::Cheb, true>(L, a, st)
+                 : run<NPTS, NDOF, double, double, StencilOp::Cheb, false>(L, a, st);
+    case StencilOp::ChebFirst:
+      return dot ? run<NPTS, NDOF, double, double, StencilOp::ChebFirst, true>(L, a, st)
+                 : run<NPTS, NDOF, double, double, StencilOp::ChebFirst, false>(L, a, st);
+    case StencilOp::CgQ: return run<NPTS, NDOF, double, double, StencilOp::CgQ, false>(L, a, st);
+  }
+  return 0;
+}
+
+// FP32 vectors: the V-cycle operations only.
+template <int NDOF, class C>
+static int64_t ops_f32(const Level& L, const StencilArgs& a, hipStream_t st) {
+  RMG_REQUIRE(a.dotw == nullptr, RMG_ERR_ARG, "internal: fused dot products need FP64 vectors");
+  switch (a.op) {
+    case StencilOp::Matvec: return run<27, NDOF, float, C, StencilOp::Matvec, false>(L, a, st);
+    case StencilOp::ResidualScaled: return run<27, NDOF, float, C, StencilOp::ResidualScaled, false>(L, a, st);
+    case StencilOp::Cheb: return run<27, NDOF, float, C, StencilOp::Cheb, false>(L, a, st);
+    case StencilOp::ChebFirst: return run<27, NDOF, float, C, StencilOp::ChebFirst, false>(L, a, st);
+    default: fail(RMG_ERR_ARG, "internal: operation not available in FP32");
+  }
+}
+
+int64_t launch_stencil_op(const Level& L, const StencilArgs& a, hipStream_t st) {
+  if (a.lowp) {
+    RMG_REQUIRE(L.npts == 27 && L.ct_lo != kCoefF64, RMG_ERR_ARG, "internal: level has no low-precision copy");
+    if (L.ndof == 1) return L.ct_lo == kCoefBF16 ? ops_f32<1, uint16_t>(L, a, st) : ops_f32<1, float>(L, a, st);
+    return L.ct_lo == kCoefBF16 ? ops_f32<3, uint16_t>(L, a, st) : ops_f32<3, float>(L, a, st);
+  }
+  if (L.ndof == 3) {
+    RMG_REQUIRE(L.npts == 27, RMG_ERR_ARG, "internal: block stencils are 27-point");
+    return ops_f64<27, 3>(L, a, st);
+  }
+  switch (L.npts) {
+    case 27: return ops_f64<27, 1>(L, a, st);
+    case 9: return ops_f64<9, 1>(L, a, st);
+    case 5: return ops_f64<5, 1>(L, a, st);
+  }
+  fail(RMG_ERR_ARG, "unsupported stencil size");
+}
+
+}  // namespace rmg

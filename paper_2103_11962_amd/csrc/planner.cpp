@@ -39,6 +39,7 @@ LevelView Level::view() const {
   v.cz = comp[2];
   v.mask = mask;
   v.npts = npts;
+  v.ndof = ndof;
   return v;
 }
 
@@ -184,6 +185,7 @@ void build_level0(rmg_handle* h) {
   L->dim = h->dim;
   L->nreg = h->nreg;
   L->npts = h->dim == 3 ? 27 : 9;
+  L->ndof = h->ndof;
   L->mask = h->mask;
   L->comp[0] = L->comp[1] = L->comp[2] = 1;
   L->regs.resize(h->nreg);
@@ -212,6 +214,7 @@ Level* make_coarse_level(const Level& F) {
   C->dim = F.dim;
   C->nreg = F.nreg;
   C->npts = F.dim == 3 ? 27 : 9;
+  C->ndof = F.ndof;
   C->mask = F.mask;
   for (int d = 0; d < 3; ++d) {
     const int n = F.comp[d];
@@ -237,15 +240,16 @@ Level* make_coarse_level(const Level& F) {
 // regional stencils, then inverted on the device (Section 3.5, direct solver).
 void build_coarse_solver(rmg_handle* h, Level& L) {
   hipStream_t st = h->stream;
-  const int64_t nc64 = L.ncomp;
+  const int nd = L.ndof, nb = nd * nd, ncoef = L.ncoef();
+  const int64_t nc64 = L.ncomp * nd;
   RMG_REQUIRE(nc64 <= 20000, RMG_ERR_ARG, "coarsest composite problem too large for the dense solver");
   const int nc = (int)nc64;
   L.nc = nc;
-  std::vector<double> coef(coef_elems(L.n, L.npts));
+  std::vector<double> coef(coef_elems(L.n, ncoef));
   RMG_HIP(hipMemcpyAsync(coef.data(), L.coef.p, sizeof(double) * coef.size(), hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));
   L.abar_host.assign((size_t)nc * nc, 0.0);
-  std::vector<int32_t> owner(nc, -1);
+  std::vector<int32_t> owner(L.ncomp, -1);
   for (int k = 0; k < L.nreg; ++k) {
     const RegionGeo& R = L.regs[k];
     for (int z = 0; z < R.ez; ++z)
@@ -266,17 +270,19 @@ void build_coarse_solver(rmg_handle* h, Level& L) {
               dz = 0;
             }
             if (x + dx < 0 || x + dx >= R.ex || y + dy < 0 || y + dy >= R.ey || z + dz < 0 || z + dz >= R.ez) continue;
-            const double v = coef[coef_index(R.off + li, s, L.npts)];
-            if (v == 0.0) continue;
             const int64_t j = ((int64_t)(R.oz + z + dz) * L.comp[1] + (R.oy + y + dy)) * L.comp[0] + (R.ox + x + dx);
-            L.abar_host[(size_t)i * nc + j] += v;
+            for (int a = 0; a < nd; ++a)
+              for (int b = 0; b < nd; ++b) {
+                const double v = coef[coef_index(R.off + li, s * nb + a * nd + b, ncoef)];
+                if (v != 0.0) L.abar_host[(size_t)(i * nd + a) * nc + (j * nd + b)] += v;
+              }
           }
         }
   }
   L.ainv.alloc(sizeof(double) * (size_t)nc * nc);
   RMG_HIP(hipMemcpyAsync(L.ainv.p, L.abar_host.data(), sizeof(double) * (size_t)nc * nc, hipMemcpyHostToDevice, st));
-  L.comp_owner.alloc(sizeof(int32_t) * nc);
-  RMG_HIP(hipMemcpyAsync(L.comp_owner.p, owner.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st));
+  L.comp_owner.alloc(sizeof(int32_t) * owner.size());
+  RMG_HIP(hipMemcpyAsync(L.comp_owner.p, owner.data(), sizeof(int32_t) * owner.size(), hipMemcpyHostToDevice, st));
   L.cvec.alloc(sizeof(double) * nc);
   L.cvec2.alloc(sizeof(double) * nc);
   DBuf flag;

@@ -64,17 +64,17 @@ static double power_method(rmg_handle* h, Level& L, int level) {
   double* t = L.r.as<double>();
   launch_start_vector(L, level, h->opt.seed, x, st);
   dot(h, L, x, x, kTmp);
-  launch_scale(L.n, scal(h), kTmp, 0, x, x, st);
+  launch_scale(L.ndofs(), scal(h), kTmp, 0, x, x, st);
   for (int it = 0; it < h->opt.power_iters; ++it) {
     StencilArgs a;
     a.op = StencilOp::Matvec;
     a.x = x;
     a.out = t;
     launch_stencil_op(L, a, st);
-    launch_mul(L.n, L.dinv.as<double>(), t, y, st);
+    launch_mul(L.ndofs(), L.dinv.as<double>(), t, y, st);
     dot(h, L, x, y, kTmp2);
     dot(h, L, y, y, kTmp);
-    launch_scale(L.n, scal(h), kTmp, 0, y, x, st);
+    launch_scale(L.ndofs(), scal(h), kTmp, 0, y, x, st);
   }
   read_scalars(h);
   return h->host_scalars[kTmp2];
@@ -98,12 +98,21 @@ static void chebyshev_coefficients(const rmg_options& o, Level& L) {
 }
 
 static void alloc_vectors(Level& L, bool with_b) {
-  const size_t bytes = sizeof(double) * (size_t)L.n;
+  const size_t bytes = sizeof(double) * (size_t)L.ndofs();
   if (with_b) L.b.alloc(bytes);
   L.u.alloc(bytes);
   L.u2.alloc(bytes);
   L.d.alloc(bytes);
   L.r.alloc(bytes);
+}
+
+static void alloc_vectors_lowp(Level& L, bool with_b) {
+  const size_t bytes = sizeof(float) * (size_t)L.ndofs();
+  if (with_b) L.b32.alloc(bytes);
+  L.u32.alloc(bytes);
+  L.u232.alloc(bytes);
+  L.d32.alloc(bytes);
+  L.r32.alloc(bytes);
 }
 
 void setup_hierarchy(rmg_handle* h) {
@@ -122,24 +131,29 @@ void setup_hierarchy(rmg_handle* h) {
                   "region " + std::to_string(k) + ": extent-1 and origin must be divisible by 3^(nlevels-1) = " +
                       std::to_string(f));
   }
+  const bool lowp = o.precision != RMG_PREC_FP64;
   h->partials.alloc(sizeof(double) * partial_capacity(*L0));
   DBuf flag;
   flag.alloc(sizeof(int));
   for (int l = 0; l < o.nlevels; ++l) {
     Level& L = *h->levels[l];
-    L.use_tiles = !L.tiles.empty() &&
+    L.use_tiles = L.ndof == 1 && !L.tiles.empty() &&
                   (o.stencil_kernel == 2 || (o.stencil_kernel == 0 && L.tiles.size() >= kAutoTileMin));
     alloc_vectors(L, l > 0);
+    L.ct_lo = kCoefF64;
+    L.coef_lo.release();
+    L.center_lo.release();
+    if (lowp) alloc_vectors_lowp(L, true);  // level 0's b32 holds the FP32 copy of the CG residual
     if (l == o.nlevels - 1) {
       build_coarse_solver(h, L);
       break;
     }
-    // D~ = Psi^T Psi diag([[A]]), then its reciprocal (Section 3.2, smoother setup)
-    L.dinv.alloc(sizeof(double) * (size_t)L.n);
+    // D~ = Psi^T Psi diag([[A]]) (point diagonal), then its reciprocal (Section 3.2, smoother setup)
+    L.dinv.alloc(sizeof(double) * (size_t)L.ndofs());
     launch_diag(L, L.r.as<double>(), st);
     launch_interface_sum(L, L.r.as<double>(), L.r.as<double>(), st);
     RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
-    launch_recip_check(L.n, L.r.as<double>(), L.dinv.as<double>(), flag.as<int>(), st);
+    launch_recip_check(L.ndofs(), L.r.as<double>(), L.dinv.as<double>(), flag.as<int>(), st);
     int hflag = 0;
     RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
     RMG_HIP(hipStreamSynchronize(st));
@@ -148,87 +162,123 @@ void setup_hierarchy(rmg_handle* h) {
     RMG_REQUIRE(std::isfinite(L.lambda) && L.lambda > 0.0, RMG_ERR_NUMERIC,
                 "power method failed on level " + std::to_string(l));
     chebyshev_coefficients(o, L);
-    // next level: geometry, then the per-region Galerkin product on the device
+    // next level: geometry, then the per-region Galerkin product on the device (FP64)
     Level* C = make_coarse_level(L);
-    C->coef.alloc(sizeof(double) * coef_elems(C->n, C->npts));
+    C->coef.alloc(sizeof(double) * coef_elems(C->n, C->ncoef()));
     launch_rap(L, *C, st);
     h->levels.push_back(C);
+    // the V-cycle's copy of this level's operator, made after the Galerkin product used it
+    if (lowp) launch_make_lowp(L, (l == 0 && o.precision == RMG_PREC_FP32_BF16) ? kCoefBF16 : kCoefF32, st);
   }
+  if (lowp) h->cg_z32.alloc(sizeof(float) * (size_t)L0->ndofs());
   RMG_HIP(hipStreamSynchronize(st));
 }
 
-static void cheb_step(rmg_handle* h, Level& L, int k, bool first, const double* b, const double* uin, double* uout,
-                      const double* dotw = nullptr, double* partials = nullptr, int64_t* np = nullptr) {
+// Buffers of one level for the FP64 or the FP32 V-cycle.
+struct Bufs {
+  void *b, *u, *u2, *d, *r;
+  const void* dinv;
+};
+
+static Bufs bufs(Level& L, bool lowp) {
+  if (lowp) return {L.b32.p, L.u32.p, L.u232.p, L.d32.p, L.r32.p, L.dinv_lo.p};
+  return {L.b.p, L.u.p, L.u2.p, L.d.p, L.r.p, L.dinv.p};
+}
+
+static void cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, const void* b, const void* uin,
+                      void* uout) {
+  const Bufs B = bufs(L, lowp);
   StencilArgs a;
   a.op = first ? StencilOp::ChebFirst : StencilOp::Cheb;
+  a.lowp = lowp;
   a.x = uin;
   a.out = uout;
   a.b = b;
-  a.dinv = L.dinv.as<double>();
-  a.d = L.d.as<double>();
+  a.dinv = B.dinv;
+  a.d = B.d;
   a.c1 = L.cheb_c1[k];
   a.c2 = L.cheb_c2[k];
-  a.dotw = dotw;
-  a.partials = partials;
   if (h->profiling && &L == h->levels[0] && !first) h->timers[kTimedCheb].acquire(&a.ev0, &a.ev1);
-  const int64_t n = launch_stencil_op(L, a, h->stream);
-  if (np) *np = n;
+  launch_stencil_op(L, a, h->stream);
 }
 
 void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out) {
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
   const int K = h->opt.cheb_degree;
-  double* buf[2] = {L.u.as<double>(), u_out};
-  launch_cheb_zero(L, b, L.dinv.as<double>(), L.cheb_c2[0], L.d.as<double>(), buf[0], st);
+  void* buf[2] = {L.u.p, u_out};
+  launch_cheb_zero(L, false, b, L.dinv.p, L.cheb_c2[0], L.d.p, buf[0], st);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
-    cheb_step(h, L, k, false, b, buf[cur], buf[1 - cur]);
+    cheb_step(h, L, false, k, false, b, buf[cur], buf[1 - cur]);
     cur = 1 - cur;
   }
-  if (buf[cur] != u_out) launch_copy(L.n, buf[cur], u_out, st);
+  if (buf[cur] != u_out) launch_copy(L.ndofs(), (const double*)buf[cur], u_out, st);
 }
 
-void vcycle(rmg_handle* h, int level, const double* b, double* z) {
+void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
   const int nl = (int)h->levels.size();
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
   if (level == nl - 1) {
-    launch_coarse_solve(L, b, z, st);
+    launch_coarse_solve(L, lowp, b, z, st);
     return;
   }
   const int K = h->opt.cheb_degree;
+  const Bufs B = bufs(L, lowp);
   // ping-pong buffers arranged so that the last post-smoothing step writes z
-  double* buf[2] = {L.u.as<double>(), z};
-  launch_cheb_zero(L, b, L.dinv.as<double>(), L.cheb_c2[0], L.d.as<double>(), buf[0], st);
+  void* buf[2] = {B.u, z};
+  launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], B.d, buf[0], st);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
-    cheb_step(h, L, k, false, b, buf[cur], buf[1 - cur]);
+    cheb_step(h, L, lowp, k, false, b, buf[cur], buf[1 - cur]);
     cur = 1 - cur;
   }
   // residual divided by multiplicity, restriction and coarse interface sum (Section 3.3)
   StencilArgs a;
   a.op = StencilOp::ResidualScaled;
+  a.lowp = lowp;
   a.x = buf[cur];
-  a.out = L.r.as<double>();
+  a.out = B.r;
   a.b = b;
   launch_stencil_op(L, a, st);
   Level& C = *h->levels[level + 1];
-  launch_restrict(L, C, L.r.as<double>(), C.b.as<double>(), st);
-  vcycle(h, level + 1, C.b.as<double>(), C.u2.as<double>());
-  launch_prolong_add(L, C, C.u2.as<double>(), buf[cur], st);
+  const Bufs BC = bufs(C, lowp);
+  launch_restrict(L, C, lowp, B.r, BC.b, st);
+  vcycle(h, level + 1, lowp, BC.b, BC.u2);
+  launch_prolong_add(L, C, lowp, BC.u2, buf[cur], st);
   for (int k = 0; k < K; ++k) {
-    cheb_step(h, L, k, k == 0, b, buf[cur], buf[1 - cur]);
+    cheb_step(h, L, lowp, k, k == 0, b, buf[cur], buf[1 - cur]);
     cur = 1 - cur;
   }
   RMG_REQUIRE(buf[cur] == z, RMG_ERR_ARG, "internal: V-cycle buffer parity");
 }
 
+// z = M^-1 r with the configured precision (FP64 regional vectors in and out).
+static void precondition(rmg_handle* h, const double* r, double* z) {
+  Level& L = *h->levels[0];
+  if (h->opt.precision == RMG_PREC_FP64) {
+    vcycle(h, 0, false, r, z);
+    return;
+  }
+  launch_f64_to_f32(L.ndofs(), r, L.b32.as<float>(), h->stream);
+  vcycle(h, 0, true, L.b32.p, h->cg_z32.p);
+  launch_f32_to_f64(L.ndofs(), h->cg_z32.as<float>(), z, h->stream);
+}
+
+void apply_preconditioner(rmg_handle* h, const double* r, double* z) { precondition(h, r, z); }
+
+// Preconditioned CG (textbook Hestenes-Stiefel).  With a low-precision V-cycle the
+// preconditioner is only approximately a fixed symmetric operator, so the flexible
+// (Polak-Ribiere) coefficient beta = (z_new, r_new - r_old) / (z_old, r_old) =
+// -alpha (z_new, q) / (z_old, r_old) is used; the residual, the update and all inner products
+// stay in FP64.
 void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
          rmg_status* status) {
   Level& L = *h->levels[0];
   hipStream_t st = h->stream;
-  const int64_t n = L.n;
+  const int64_t n = L.ndofs();
+  const bool flexible = h->opt.precision != RMG_PREC_FP64;
   double* r = h->cg_r.as<double>();
   double* p = h->cg_p.as<double>();
   double* q = h->cg_q.as<double>();
@@ -265,7 +315,7 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
     rel = 0.0;
     converged = true;
   } else {
-    vcycle(h, 0, r, z);
+    precondition(h, r, z);
     launch_copy(n, z, p, st);
     dot(h, L, r, z, kRZ);
     while (it < maxit) {
@@ -298,9 +348,14 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
         break;
       }
       if (it >= maxit) break;
-      vcycle(h, 0, r, z);
+      precondition(h, r, z);
       dot(h, L, r, z, kRZnew);
-      launch_cg_scalars(scal(h), 1, st);
+      if (flexible) {
+        dot(h, L, z, q, kZQ);
+        launch_cg_scalars(scal(h), 2, st);
+      } else {
+        launch_cg_scalars(scal(h), 1, st);
+      }
       launch_cg_direction(n, scal(h), z, p, st);
     }
   }

@@ -24,6 +24,8 @@ def gpu_problem(w, device=0, setup=True, **opts):
         h.set_composite_stencil(5, synth.fd5_composite_stencil(w))
     elif w.pde == "laplace":
         h.assemble_q1(regmg.PDE_LAPLACE, w.h)
+    elif w.pde == "elasticity":
+        h.assemble_q1(regmg.PDE_ELASTICITY, w.h, youngs=synth.region_youngs_moduli(w), nu=w.nu)
     elif w.pde == "diffusion":
         ec = torch.from_numpy(np.ascontiguousarray(synth.jump_coefficients(w))).to(f"cuda:{device}")
         h.assemble_q1(regmg.PDE_DIFFUSION, w.h, elem_coef=ec.reshape(-1))
@@ -59,6 +61,15 @@ def to_dev(a, device=0):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to(f"cuda:{device}")
 
 
-def stencil_as_sparse_rows(coef, dim):
-    """Region stencil in the library's SoA layout [npts][nodes] from oracle arrays (S, ...)."""
-    return coef.reshape(coef.shape[0], -1)
+def stencil_soa(coef, dim, ndof=1):
+    """Oracle region stencil (S, nodes...[, ndof, ndof]) in the library's layout [S*ndof*ndof][nodes]."""
+    S = coef.shape[0]
+    if ndof == 1:
+        return coef.reshape(S, -1)
+    c = coef.reshape(S, -1, ndof, ndof)  # (S, nodes, a, b)
+    return np.transpose(c, (0, 2, 3, 1)).reshape(S * ndof * ndof, -1)
+
+
+def vshape(lay):
+    """numpy shape of a composite vector of the layout."""
+    return lay.shape + ((lay.ndof,) if lay.ndof > 1 else ())

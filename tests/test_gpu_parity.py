@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 # (workload, 3D stencil kernel): 1 = node-parallel, 2 = 2.5D plane-marching tiles
 SMALL = [("c1_small", 0), ("c2_small", 1), ("c2_small", 2), ("c4_small", 1), ("c4_small", 2),
-         ("c5_small", 1), ("c5_small", 2), ("c1", 0), ("c2_mid", 1), ("c2_mid", 2)]
+         ("c5_small", 1), ("c5_small", 2), ("c1", 0), ("c2_mid", 1), ("c2_mid", 2), ("c3_small", 0)]
 IDS = [f"{n}-k{k}" for n, k in SMALL]
 
 
@@ -60,8 +60,8 @@ def test_level_operators(problems, name):
     for l, L in enumerate(levels):
         info = h.level_info(l)
         for k in range(L.lay.nreg):
-            ref = L.coefs[k].reshape(L.coefs[k].shape[0], -1)
-            got = h.level_stencil(l, k, info["npts"], ref.shape[1])
+            ref = harness.stencil_soa(L.coefs[k], L.lay.dim, L.lay.ndof)
+            got = h.level_stencil(l, k, info["npts"] * L.lay.ndof ** 2, ref.shape[1])
             if info["npts"] == 5:
                 got = five_to_nine(got)
             assert rel(got, ref) < 1e-12, (l, k, rel(got, ref))
@@ -90,7 +90,7 @@ def test_regional_matvec_and_interface_sum(problems, name):
 
     w, h, (lay, levels, opt) = problems(name)
     rng = np.random.default_rng(11)
-    x = rng.uniform(-1, 1, size=lay.shape)
+    x = rng.uniform(-1, 1, size=harness.vshape(lay))
     L0 = levels[0]
     xr = harness.to_dev(x)
     reg = torch.empty(lay.n_regional, dtype=torch.float64, device="cuda:0")
@@ -120,16 +120,16 @@ def test_transfers(problems, name):
     rng = np.random.default_rng(5)
     for l in range(len(levels) - 1):
         F, C = levels[l], levels[l + 1]
-        r = rng.uniform(-1, 1, size=F.lay.shape)
+        r = rng.uniform(-1, 1, size=harness.vshape(F.lay))
         r[F.lay.dirichlet] = 0.0
         rr = F.lay.to_regional(r)
         wg = torch.empty(C.lay.n_regional, dtype=torch.float64, device="cuda:0")
         h.restrict(l, harness.to_dev(F.lay.flatten(rr)), wg)
         wref = C.lay.flatten(transfer.regional_restrict(F.lay, C.lay, F.P, rr))
         assert rel(wg.cpu().numpy(), wref) < 1e-13, l
-        ub = rng.uniform(-1, 1, size=C.lay.shape)
+        ub = rng.uniform(-1, 1, size=harness.vshape(C.lay))
         ub[C.lay.dirichlet] = 0.0
-        u0 = rng.uniform(-1, 1, size=F.lay.shape)
+        u0 = rng.uniform(-1, 1, size=harness.vshape(F.lay))
         ug = harness.to_dev(F.lay.flatten(F.lay.to_regional(u0)))
         h.prolongate_add(l, harness.to_dev(C.lay.flatten(C.lay.to_regional(ub))), ug)
         uref = F.lay.flatten([a + b for a, b in zip(F.lay.to_regional(u0), transfer.regional_prolongate(
@@ -208,3 +208,49 @@ def test_errors_are_reported(hip_device):
         h.set_composite_stencil(5, bad)
     assert e.value.status == "RMG_ERR_NUMERIC"
     h.close()
+
+
+# ---------------------------------------------------------------- low-precision V-cycle
+MIXED = [("c2_small", 1, 1), ("c2_small", 2, 2), ("c2_mid", 1, 2), ("c2_mid", 2, 1), ("c3_small", 1, 0),
+         ("c3_small", 2, 0), ("c4_small", 2, 2), ("c5_small", 1, 2)]
+
+
+@pytest.mark.parametrize("name,precision,kernel", MIXED, ids=[f"{n}-p{p}-k{k}" for n, p, k in MIXED])
+def test_mixed_precision_solve(hip_device, name, precision, kernel):
+    """FP32 (precision 1) or BF16-coefficient (2) V-cycle inside FP64 flexible CG: the true FP64
+    residual reaches 1e-8 and the solution matches the FP64 oracle within kappa-sized bounds."""
+    import torch
+
+    from oracle import regional
+
+    w = synth.workload(name)
+    lay, levels, opt = harness.oracle_problem(w)
+    h = harness.gpu_problem(w, precision=precision, stencil_kernel=kernel)
+    b = synth.rhs(w)
+    x = torch.zeros(lay.n_composite, dtype=torch.float64, device="cuda:0")
+    out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100)
+    ref = regional.pcg(levels, lay.to_regional(b), opt, rtol=1e-12, maxit=200)
+    xref = lay.to_composite_owner(ref.x).reshape(-1)
+    h.close()
+    assert out["converged"] and out["true_relres"] <= 1.5e-8, out
+    assert out["iterations"] <= ref.iterations + 6
+    assert rel(x.cpu().numpy(), xref) < 1e-6
+
+
+def test_mixed_vcycle_close_to_fp64(hip_device):
+    """The FP32 V-cycle differs from the FP64 oracle V-cycle only by FP32 rounding."""
+    import torch
+
+    from oracle import regional
+
+    w = synth.workload("c2_mid")
+    lay, levels, opt = harness.oracle_problem(w)
+    b = synth.rhs(w)
+    ref = lay.to_composite_owner(regional.vcycle(levels, lay.to_regional(b), opt)).reshape(-1)
+    for precision, tol in ((1, 1e-5), (2, 3e-2)):
+        h = harness.gpu_problem(w, precision=precision)
+        z = torch.empty(lay.n_composite, dtype=torch.float64, device="cuda:0")
+        h.apply_vcycle(harness.to_dev(b), z)
+        err = rel(z.cpu().numpy(), ref)
+        h.close()
+        assert err < tol, (precision, err)
