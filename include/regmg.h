@@ -78,7 +78,16 @@ typedef struct {
   uint64_t seed;      /* seed of the counter-based power-method start vector */
   int precision;      /* rmg_precision */
   int stencil_kernel; /* 3D stencil kernel: 0 auto (2.5D tiles on levels with >= 2048 tiles),
-                         1 node-parallel, 2 2.5D plane-marching tiles */
+                         1 node-parallel, 2 2.5D plane-marching tiles (one block per tile),
+                         3 the same tiles in a persistent grid (blocks stride over the tiles) */
+  int autotune;       /* 1: at setup, time the scalar 3D stencil variants (node-parallel; 2.5D tiles
+                         11/21/41 planes deep, one block per tile or a persistent grid striding
+                         over the tile list) on every level and keep the fastest; overrides
+                         stencil_kernel */
+  int use_graph;      /* 1: rmg_solve captures the two halves of a CG iteration (around the
+                         host convergence check) as HIP graphs once and replays them */
+  const char* autotune_cache; /* text file of autotuner choices keyed by level shape and
+                         precision; read before tuning, appended after (NULL: no file) */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -205,6 +214,9 @@ rmg_status rmg_get_coarse_matrix(rmg_handle* h, double* host_out);
 /* Enable (1) or disable (0) HIP-event timing of the kernels above and reset
  * the counters.  Timing adds an event pair per timed launch. */
 rmg_status rmg_profile(rmg_handle* h, int enable);
+/* Text of the autotuner's choices (one line per level: level, mode, depth, grid, time), copied
+ * into buf (NUL-terminated, truncated to cap bytes). */
+rmg_status rmg_tune_report(rmg_handle* h, char* buf, int cap);
 /* Launch count and summed duration (ms) of a timed kernel since the last reset. */
 rmg_status rmg_profile_query(rmg_handle* h, int kernel, int64_t* launches, double* total_ms);
 

@@ -98,7 +98,16 @@ static void q1_elasticity_element(double nu, double h, double* K) {
 
 using namespace rmg;
 
+void rmg_handle::drop_graphs() {
+  if (graph_a) (void)hipGraphExecDestroy(graph_a);
+  if (graph_b) (void)hipGraphExecDestroy(graph_b);
+  graph_a = graph_b = nullptr;
+  graph_b_ptr = graph_x_ptr = nullptr;
+}
+
 rmg_handle::~rmg_handle() {
+  drop_graphs();
+  if (gstream) (void)hipStreamDestroy(gstream);
   for (Level* L : levels) delete L;
   levels.clear();
   if (host_scalars) (void)hipHostFree(host_scalars);
@@ -141,6 +150,9 @@ void rmg_options_default(rmg_options* o) {
   o->seed = 0;
   o->precision = RMG_PREC_FP64;
   o->stencil_kernel = 0;
+  o->autotune = 0;
+  o->use_graph = 0;
+  o->autotune_cache = nullptr;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -367,9 +379,12 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
               "unknown precision");
   RMG_REQUIRE(opt->precision == RMG_PREC_FP64 || h->dim == 3, RMG_ERR_ARG,
               "the low-precision V-cycle needs 27-point (3D) levels");
-  RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 2, RMG_ERR_ARG, "stencil_kernel must be 0, 1 or 2");
+  RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 3, RMG_ERR_ARG, "stencil_kernel must be 0..3");
   h->opt = *opt;
+  h->autotune_cache = opt->autotune_cache ? std::string(opt->autotune_cache) : std::string();
+  h->opt.autotune_cache = nullptr;  // the caller's string is borrowed for this call only
   h->have_hierarchy = false;
+  h->drop_graphs();
   setup_hierarchy(h);
   h->have_hierarchy = true;
   API_END
@@ -546,6 +561,17 @@ rmg_status rmg_profile(rmg_handle* h, int enable) {
   RMG_HIP(hipStreamSynchronize(h->stream));
   h->profiling = enable != 0;
   for (auto& t : h->timers) t.reset();
+  API_END
+}
+
+rmg_status rmg_tune_report(rmg_handle* h, char* buf, int cap) {
+  API_BEGIN
+  RMG_REQUIRE(h && buf && cap > 0, RMG_ERR_ARG, "null handle or buffer");
+  std::string all;
+  for (const std::string& line : h->tune_report) all += line + "\n";
+  const size_t n = std::min(all.size(), (size_t)cap - 1);
+  std::memcpy(buf, all.data(), n);
+  buf[n] = 0;
   API_END
 }
 

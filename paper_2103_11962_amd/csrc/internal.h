@@ -110,6 +110,8 @@ struct Level {
   std::vector<Tile3> tiles;  // 2.5D tiles of a 3D level (empty in 2D)
   DBuf d_tiles;
   bool use_tiles = false;    // run 27-point stencil operations with the 2.5D kernel
+  int tile_depth = 21;       // planes per tile
+  int tile_grid = 0;         // > 0: persistent launch of this many blocks looping over the tiles
   // interface groups: copies of each shared composite node, ascending region order
   int64_t ngroups = 0;
   DBuf d_gptr;    // int64 [ngroups+1]
@@ -173,6 +175,14 @@ struct rmg_handle {
   rmg::DBuf scalars;    // double device scalars
   double* host_scalars = nullptr;  // pinned
   bool profiling = false;
+  std::string autotune_cache;
+  std::vector<std::string> tune_report;  // one line per tuned level
+  // CG iteration graphs (use_graph): valid for the recorded (b, x) pointers until the next setup
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t graph_a = nullptr, graph_b = nullptr;
+  const void* graph_b_ptr = nullptr;
+  const void* graph_x_ptr = nullptr;
+  void drop_graphs();
   rmg::KernelTimer timers[rmg::kNumTimed];
   ~rmg_handle();
 };
@@ -183,6 +193,7 @@ namespace rmg {
 void build_level0(rmg_handle* h);
 Level* make_coarse_level(const Level& fine);
 void build_tables(Level& L);
+void make_tiles(Level& L, int depth);
 void build_coarse_solver(rmg_handle* h, Level& L);
 
 // solver.cpp

@@ -120,91 +120,94 @@ constexpr int kT3 = 512;           // threads per 3D tile block
 constexpr int kT3Plane = 1544;     // max (ty+2)(tx+2) over tx*ty <= 512
 constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
 
+// Grid = one block per tile, or (persistent launch) fewer blocks that stride over the tile list.
 template <class V, class C, StencilOp OP, bool DOT>
-__global__ __launch_bounds__(kT3) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles,
+__global__ __launch_bounds__(kT3) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles, int ntiles,
                                                    const C* __restrict__ coef, const float* __restrict__ centre,
                                                    OpP<V> p, double* __restrict__ partials) {
   __shared__ V pl[2][kT3Plane];
-  const Tile3 T = tiles[blockIdx.x];
-  const RegionGeo R = L.regs[T.region];
-  const int W = T.tx + 2, PL = (T.ty + 2) * W;
-  const V* __restrict__ xr = p.x + R.off;
   const int t = threadIdx.x;
-  const int ty = t / T.tx, tx = t - ty * T.tx;
-  const int x = T.x0 + tx, y = T.y0 + ty;
-  const bool active = ty < T.ty && x < R.ex && y < R.ey;
-  const int sy = R.ex, sz = R.ex * R.ey;
-  V pre[kT3Fetch];
-  auto fetch = [&](int zz) {
-#pragma unroll
-    for (int k = 0; k < kT3Fetch; ++k) {
-      const int idx = t + k * kT3;
-      V v = (V)0;
-      if (idx < PL) {
-        const int r = idx / W;
-        const int xx = T.x0 + idx - r * W - 1, yy = T.y0 - 1 + r;
-        if ((unsigned)zz < (unsigned)R.ez && (unsigned)yy < (unsigned)R.ey && (unsigned)xx < (unsigned)R.ex)
-          v = xr[zz * sz + yy * sy + xx];
-      }
-      pre[k] = v;
-    }
-  };
-  auto store = [&](int slot) {
-#pragma unroll
-    for (int k = 0; k < kT3Fetch; ++k) {
-      const int idx = t + k * kT3;
-      if (idx < PL) pl[slot][idx] = pre[k];
-    }
-  };
-  V rm[9], rc[9], rp[9];
-  auto readn = [&](int slot, V* r) {
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      const int dx = j % 3 - 1, dy = j / 3 - 1;
-      r[j] = pl[slot][(ty + 1 + dy) * W + tx + 1 + dx];
-    }
-  };
-  const int z0 = T.z0, z1 = T.z0 + T.nz;
-  fetch(z0 - 1);
-  store(0);
-  fetch(z0);
-  store(1);
-  __syncthreads();
-  if (active) {
-    readn(0, rm);
-    readn(1, rc);
-  }
-  __syncthreads();
-  fetch(z0 + 1);
-  store(0);
-  __syncthreads();
   double contrib = 0.0;
-  for (int zz = z0; zz < z1; ++zz) {
-    const int sp = (zz - z0) & 1;  // slot holding plane zz+1
-    if (active) readn(sp, rp);
-    fetch(zz + 2);
-    if (active) {
-      const int li = zz * sz + y * sy + x;
-      const int64_t gi = R.off + li;
-      const C* __restrict__ cf = coef + coef_index(gi, 0, 27);
-      V acc = (V)0;
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const Tile3 T = tiles[ti];
+    const RegionGeo R = L.regs[T.region];
+    const int W = T.tx + 2, PL = (T.ty + 2) * W;
+    const V* __restrict__ xr = p.x + R.off;
+    const int ty = t / T.tx, tx = t - ty * T.tx;
+    const int x = T.x0 + tx, y = T.y0 + ty;
+    const bool active = ty < T.ty && x < R.ex && y < R.ey;
+    const int sy = R.ex, sz = R.ex * R.ey;
+    V pre[kT3Fetch];
+    auto fetch = [&](int zz) {
 #pragma unroll
-      for (int s = 0; s < 27; ++s) {
-        const int j = s % 9, dz = s / 9 - 1;
-        const V v = dz < 0 ? rm[j] : (dz == 0 ? rc[j] : rp[j]);
-        acc += (V)coefv<27, 1, C>(cf, centre, gi, s, 0, 0) * v;
+      for (int k = 0; k < kT3Fetch; ++k) {
+        const int idx = t + k * kT3;
+        V v = (V)0;
+        if (idx < PL) {
+          const int r = idx / W;
+          const int xx = T.x0 + idx - r * W - 1, yy = T.y0 - 1 + r;
+          if ((unsigned)zz < (unsigned)R.ez && (unsigned)yy < (unsigned)R.ey && (unsigned)xx < (unsigned)R.ex)
+            v = xr[zz * sz + yy * sy + xx];
+        }
+        pre[k] = v;
       }
-      const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
-      if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
-      else contrib += finish<OP, DOT, V>(p, gi, acc, 1, rc[4]);
-    }
-    store(sp ^ 1);  // plane zz+2 replaces plane zz
+    };
+    auto store = [&](int slot) {
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      rm[j] = rc[j];
-      rc[j] = rp[j];
+      for (int k = 0; k < kT3Fetch; ++k) {
+        const int idx = t + k * kT3;
+        if (idx < PL) pl[slot][idx] = pre[k];
+      }
+    };
+    V rm[9], rc[9], rp[9];
+    auto readn = [&](int slot, V* r) {
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        const int dx = j % 3 - 1, dy = j / 3 - 1;
+        r[j] = pl[slot][(ty + 1 + dy) * W + tx + 1 + dx];
+      }
+    };
+    const int z0 = T.z0, z1 = T.z0 + T.nz;
+    fetch(z0 - 1);
+    store(0);
+    fetch(z0);
+    store(1);
+    __syncthreads();
+    if (active) {
+      readn(0, rm);
+      readn(1, rc);
     }
     __syncthreads();
+    fetch(z0 + 1);
+    store(0);
+    __syncthreads();
+    for (int zz = z0; zz < z1; ++zz) {
+      const int sp = (zz - z0) & 1;  // slot holding plane zz+1
+      if (active) readn(sp, rp);
+      fetch(zz + 2);
+      if (active) {
+        const int li = zz * sz + y * sy + x;
+        const int64_t gi = R.off + li;
+        const C* __restrict__ cf = coef + coef_index(gi, 0, 27);
+        V acc = (V)0;
+#pragma unroll
+        for (int s = 0; s < 27; ++s) {
+          const int j = s % 9, dz = s / 9 - 1;
+          const V v = dz < 0 ? rm[j] : (dz == 0 ? rc[j] : rp[j]);
+          acc += (V)coefv<27, 1, C>(cf, centre, gi, s, 0, 0) * v;
+        }
+        const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
+        if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
+        else contrib += finish<OP, DOT, V>(p, gi, acc, 1, rc[4]);
+      }
+      store(sp ^ 1);  // plane zz+2 replaces plane zz
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        rm[j] = rc[j];
+        rc[j] = rp[j];
+      }
+      __syncthreads();
+    }
   }
   if constexpr (DOT || OP == StencilOp::CgQ) {
     double v = contrib;
@@ -255,11 +258,13 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   const float* centre = L.center_lo.as<float>();
   const LevelView v = L.view();
   const bool tiled = NPTS == 27 && NDOF == 1 && L.use_tiles;
+  const int ntiles = (int)L.tiles.size();
+  const int grid3 = (L.tile_grid > 0 && L.tile_grid < ntiles) ? L.tile_grid : ntiles;
   if (a.ev0) RMG_HIP(hipEventRecord(a.ev0, st));
   if constexpr (NPTS == 27 && NDOF == 1) {
     if (tiled) {
-      hipLaunchKernelGGL((k_stencil3d<V, C, OP, DOT>), dim3(L.tiles.size()), dim3(kT3), 0, st, v,
-                         L.d_tiles.as<Tile3>(), coef, centre, p, a.partials);
+      hipLaunchKernelGGL((k_stencil3d<V, C, OP, DOT>), dim3(grid3), dim3(kT3), 0, st, v, L.d_tiles.as<Tile3>(),
+                         ntiles, coef, centre, p, a.partials);
     }
   }
   if (!tiled)
@@ -267,7 +272,7 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
                        centre, p, a.partials);
   LAUNCH_CHECK();
   if (a.ev1) RMG_HIP(hipEventRecord(a.ev1, st));
-  const int64_t nb = tiled ? (int64_t)L.tiles.size() : (int64_t)L.blocks.size();
+  const int64_t nb = tiled ? (int64_t)grid3 : (int64_t)L.blocks.size();
   int64_t ngb = 0;
   if (L.ngroups > 0) {
     ngb = cdiv(L.ngroups, kBlock);

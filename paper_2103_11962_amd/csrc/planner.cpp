@@ -49,6 +49,33 @@ static bool shared_node(const Level& L, const RegionGeo& R, int x, int y, int z)
          (y == R.ey - 1 && gy != L.comp[1] - 1) || (z == 0 && gz != 0) || (z == R.ez - 1 && gz != L.comp[2] - 1);
 }
 
+// 2.5D tiles of a 3D level: 512-thread tiles of whole (or 512-node) x-rows, `depth` planes deep,
+// ordered largest first so a persistent launch hands out the costly tiles early.
+void make_tiles(Level& L, int depth) {
+  L.tiles.clear();
+  L.tile_depth = depth;
+  if (L.dim != 3) return;
+  constexpr int kThreads = 512;
+  for (int k = 0; k < L.nreg; ++k) {
+    const RegionGeo& R = L.regs[k];
+    const int tx = std::min(R.ex, kThreads);
+    const int ty = std::min(R.ey, kThreads / tx);
+    for (int z0 = 0; z0 < R.ez; z0 += depth)
+      for (int y0 = 0; y0 < R.ey; y0 += ty)
+        for (int x0 = 0; x0 < R.ex; x0 += tx)
+          L.tiles.push_back(Tile3{k, x0, y0, z0, tx, ty, std::min(depth, R.ez - z0), 0});
+  }
+  std::stable_sort(L.tiles.begin(), L.tiles.end(), [](const Tile3& a, const Tile3& b) {
+    return (int64_t)a.tx * a.ty * a.nz > (int64_t)b.tx * b.ty * b.nz;
+  });
+  for (const Tile3& T : L.tiles)
+    RMG_REQUIRE((T.tx + 2) * (T.ty + 2) <= 1544 && T.tx * T.ty <= 512, RMG_ERR_ARG, "internal: tile too large");
+  if (!L.tiles.empty()) {
+    L.d_tiles.alloc(sizeof(Tile3) * L.tiles.size());
+    RMG_HIP(hipMemcpy(L.d_tiles.p, L.tiles.data(), sizeof(Tile3) * L.tiles.size(), hipMemcpyHostToDevice));
+  }
+}
+
 // Offsets, block table and interface groups of a level whose regs/comp are set.
 void build_tables(Level& L) {
   int64_t off = 0;
@@ -116,30 +143,10 @@ void build_tables(Level& L) {
     gcomp2.push_back(gcomp[g]);
   }
   L.ngroups = ng;
-  // 2.5D tiles for the 3D stencil kernel: 512-thread tiles of whole (or 512-node) x-rows,
-  // 21 planes deep; by default used when the level has enough tiles to fill the GPU.
-  L.tiles.clear();
-  if (L.dim == 3) {
-    constexpr int kThreads = 512, kDepth = 21;
-    std::vector<Tile3> tiles;
-    for (int k = 0; k < L.nreg; ++k) {
-      const RegionGeo& R = L.regs[k];
-      const int tx = std::min(R.ex, kThreads);
-      const int ty = std::min(R.ey, kThreads / tx);
-      for (int z0 = 0; z0 < R.ez; z0 += kDepth)
-        for (int y0 = 0; y0 < R.ey; y0 += ty)
-          for (int x0 = 0; x0 < R.ex; x0 += tx)
-            tiles.push_back(Tile3{k, x0, y0, z0, tx, ty, std::min(kDepth, R.ez - z0), 0});
-    }
-    L.tiles = tiles;
-  }
+  // 2.5D tiles for the 3D stencil kernel, 21 planes deep by default; used when the level has
+  // enough tiles to fill the GPU unless the options or the autotuner say otherwise.
+  make_tiles(L, 21);
   L.use_tiles = L.tiles.size() >= kAutoTileMin;
-  for (const Tile3& T : L.tiles)
-    RMG_REQUIRE((T.tx + 2) * (T.ty + 2) <= 1544 && T.tx * T.ty <= 512, RMG_ERR_ARG, "internal: tile too large");
-  if (!L.tiles.empty()) {
-    L.d_tiles.alloc(sizeof(Tile3) * L.tiles.size());
-    RMG_HIP(hipMemcpy(L.d_tiles.p, L.tiles.data(), sizeof(Tile3) * L.tiles.size(), hipMemcpyHostToDevice));
-  }
   L.d_regs.alloc(sizeof(RegionGeo) * L.regs.size());
   RMG_HIP(hipMemcpy(L.d_regs.p, L.regs.data(), sizeof(RegionGeo) * L.regs.size(), hipMemcpyHostToDevice));
   L.d_blocks.alloc(sizeof(BlockDesc) * L.blocks.size());

@@ -1,5 +1,6 @@
 // Hierarchy setup, regional V-cycle and preconditioned CG (host orchestration of the kernels).
 #include <algorithm>
+#include <fstream>
 #include <cmath>
 #include <string>
 
@@ -115,6 +116,99 @@ static void alloc_vectors_lowp(Level& L, bool with_b) {
   L.r32.alloc(bytes);
 }
 
+// ------------------------------------------------------------------- autotuner
+// Candidate launch shapes of the scalar 3D stencil kernels on one level.
+struct TuneChoice {
+  int mode;   // 0 node-parallel, 1 one block per 2.5D tile, 2 persistent grid over the tiles
+  int depth;  // planes per tile
+  int grid;   // persistent grid size
+};
+
+static std::string tune_key(const Level& L, int level, int precision) {
+  std::string k = "n" + std::to_string(L.n) + "_r" + std::to_string(L.nreg) + "_l" + std::to_string(level) + "_p" +
+                  std::to_string(precision);
+  for (int i = 0; i < std::min(L.nreg, 4); ++i)
+    k += "_" + std::to_string(L.regs[i].ex) + "x" + std::to_string(L.regs[i].ey) + "x" + std::to_string(L.regs[i].ez);
+  return k;
+}
+
+static void apply_choice(Level& L, const TuneChoice& c) {
+  if (c.mode == 0) {
+    L.use_tiles = false;
+    L.tile_grid = 0;
+    return;
+  }
+  if (L.tile_depth != c.depth) make_tiles(L, c.depth);
+  L.use_tiles = true;
+  L.tile_grid = c.mode == 2 ? c.grid : 0;
+}
+
+// Times the Chebyshev step on the level's own operator and scratch vectors (zero-filled) for
+// every candidate and keeps the fastest.  Choices are cached in a text file when configured.
+static void autotune_level(rmg_handle* h, Level& L, int level, bool lowp) {
+  hipStream_t st = h->stream;
+  const std::string key = tune_key(L, level, h->opt.precision);
+  if (!h->autotune_cache.empty()) {
+    std::ifstream in(h->autotune_cache);
+    std::string k;
+    TuneChoice c;
+    while (in >> k >> c.mode >> c.depth >> c.grid) {
+      if (k == key) {
+        apply_choice(L, c);
+        h->tune_report.push_back("level " + std::to_string(level) + " cached mode " + std::to_string(c.mode) +
+                                 " depth " + std::to_string(c.depth) + " grid " + std::to_string(c.grid));
+        return;
+      }
+    }
+  }
+  std::vector<TuneChoice> cands = {{0, 21, 0}, {1, 11, 0}, {1, 21, 0}, {1, 41, 0}, {2, 21, 512}, {2, 21, 1024}};
+  const size_t vb = (lowp ? sizeof(float) : sizeof(double)) * (size_t)L.ndofs();
+  void* vec[5] = {lowp ? L.u32.p : L.u.p, lowp ? L.u232.p : L.u2.p, lowp ? L.d32.p : L.d.p,
+                  lowp ? L.r32.p : L.r.p, lowp ? L.b32.p : L.b.p};
+  for (void* v : vec)
+    if (v) RMG_HIP(hipMemsetAsync(v, 0, vb, st));
+  const void* dinv = lowp ? L.dinv_lo.p : L.dinv.p;
+  hipEvent_t e0, e1;
+  RMG_HIP(hipEventCreate(&e0));
+  RMG_HIP(hipEventCreate(&e1));
+  double best = 1e30;
+  TuneChoice bestc = cands[0];
+  for (const TuneChoice& c : cands) {
+    apply_choice(L, c);
+    StencilArgs a;
+    a.op = StencilOp::Cheb;
+    a.lowp = lowp;
+    a.x = vec[0];
+    a.out = vec[1];
+    a.b = vec[3];
+    a.dinv = dinv;
+    a.d = vec[2];
+    a.c1 = 0.5;
+    a.c2 = 0.5;
+    launch_stencil_op(L, a, st);  // warm-up
+    RMG_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) launch_stencil_op(L, a, st);
+    RMG_HIP(hipEventRecord(e1, st));
+    RMG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    RMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bestc = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  apply_choice(L, bestc);
+  h->tune_report.push_back("level " + std::to_string(level) + " mode " + std::to_string(bestc.mode) + " depth " +
+                           std::to_string(bestc.depth) + " grid " + std::to_string(bestc.grid) + " step_ms " +
+                           std::to_string(best / 3.0));
+  if (!h->autotune_cache.empty()) {
+    std::ofstream out(h->autotune_cache, std::ios::app);
+    out << key << " " << bestc.mode << " " << bestc.depth << " " << bestc.grid << "\n";
+  }
+}
+
 void setup_hierarchy(rmg_handle* h) {
   const rmg_options& o = h->opt;
   hipStream_t st = h->stream;
@@ -132,13 +226,19 @@ void setup_hierarchy(rmg_handle* h) {
                       std::to_string(f));
   }
   const bool lowp = o.precision != RMG_PREC_FP64;
+  h->tune_report.clear();
   h->partials.alloc(sizeof(double) * partial_capacity(*L0));
   DBuf flag;
   flag.alloc(sizeof(int));
   for (int l = 0; l < o.nlevels; ++l) {
     Level& L = *h->levels[l];
+    if (L.dim == 3 && L.tile_depth != 21) make_tiles(L, 21);
+    L.tile_grid = 0;
     L.use_tiles = L.ndof == 1 && !L.tiles.empty() &&
-                  (o.stencil_kernel == 2 || (o.stencil_kernel == 0 && L.tiles.size() >= kAutoTileMin));
+                  (o.stencil_kernel >= 2 || (o.stencil_kernel == 0 && L.tiles.size() >= kAutoTileMin));
+    // persistent tiles: 4 blocks per CU, and at least two tiles per block
+    if (L.use_tiles && o.stencil_kernel == 3)
+      L.tile_grid = std::max(1, std::min(1024, (int)(L.tiles.size() + 1) / 2));
     alloc_vectors(L, l > 0);
     L.ct_lo = kCoefF64;
     L.coef_lo.release();
@@ -169,6 +269,7 @@ void setup_hierarchy(rmg_handle* h) {
     h->levels.push_back(C);
     // the V-cycle's copy of this level's operator, made after the Galerkin product used it
     if (lowp) launch_make_lowp(L, (l == 0 && o.precision == RMG_PREC_FP32_BF16) ? kCoefBF16 : kCoefF32, st);
+    if (o.autotune && L.dim == 3 && L.ndof == 1 && L.npts == 27) autotune_level(h, L, l, lowp);
   }
   if (lowp) h->cg_z32.alloc(sizeof(float) * (size_t)L0->ndofs());
   RMG_HIP(hipStreamSynchronize(st));
@@ -273,12 +374,58 @@ void apply_preconditioner(rmg_handle* h, const double* r, double* z) { precondit
 // (Polak-Ribiere) coefficient beta = (z_new, r_new - r_old) / (z_old, r_old) =
 // -alpha (z_new, q) / (z_old, r_old) is used; the residual, the update and all inner products
 // stay in FP64.
-void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
-         rmg_status* status) {
+// Runs `body` under stream capture and instantiates the resulting graph.
+template <class F>
+static hipGraphExec_t capture_graph(hipStream_t st, F&& body) {
+  hipGraph_t g = nullptr;
+  RMG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(st, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  RMG_HIP(hipStreamEndCapture(st, &g));
+  hipGraphExec_t e = nullptr;
+  const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  RMG_HIP(err);
+  return e;
+}
+
+// While alive, the handle's work goes to its private capture stream, ordered after (and, on
+// exit, before) the caller's stream.
+struct GraphStream {
+  rmg_handle* h;
+  hipStream_t user;
+  GraphStream(rmg_handle* hh) : h(hh), user(hh->stream) {
+    if (!h->gstream) RMG_HIP(hipStreamCreate(&h->gstream));
+    hipEvent_t ev;
+    RMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    RMG_HIP(hipEventRecord(ev, user));
+    RMG_HIP(hipStreamWaitEvent(h->gstream, ev, 0));
+    (void)hipEventDestroy(ev);
+    h->stream = h->gstream;
+  }
+  ~GraphStream() {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+      (void)hipEventRecord(ev, h->gstream);
+      (void)hipStreamWaitEvent(user, ev, 0);
+      (void)hipEventDestroy(ev);
+    }
+    h->stream = user;
+  }
+};
+
+static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
+                     rmg_status* status) {
   Level& L = *h->levels[0];
   hipStream_t st = h->stream;
   const int64_t n = L.ndofs();
   const bool flexible = h->opt.precision != RMG_PREC_FP64;
+  const bool graphs = h->opt.use_graph != 0;
   double* r = h->cg_r.as<double>();
   double* p = h->cg_p.as<double>();
   double* q = h->cg_q.as<double>();
@@ -293,6 +440,32 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
   auto push_hist = [&](double v) {
     if (info && info->history && hist_len < info->history_cap) info->history[hist_len] = v;
     ++hist_len;
+  };
+  // first half of an iteration: q = A p, alpha, x and r updates, (r, r)
+  auto body_a = [&](bool timed) {
+    StencilArgs a;
+    a.op = StencilOp::CgQ;
+    a.x = p;
+    a.out = q;
+    a.partials = part;
+    if (timed) h->timers[kTimedCgQ].acquire(&a.ev0, &a.ev1);
+    const int64_t np = launch_stencil_op(L, a, st);
+    launch_reduce(part, np, scal(h), kPQ, st);
+    launch_cg_scalars(scal(h), 0, st);
+    const int64_t nu = launch_cg_update(L, scal(h), x, r, p, q, part, st);
+    launch_reduce(part, nu, scal(h), kRR, st);
+  };
+  // second half: z = M^-1 r, beta, p update
+  auto body_b = [&]() {
+    precondition(h, r, z);
+    dot(h, L, r, z, kRZnew);
+    if (flexible) {
+      dot(h, L, z, q, kZQ);
+      launch_cg_scalars(scal(h), 2, st);
+    } else {
+      launch_cg_scalars(scal(h), 1, st);
+    }
+    launch_cg_direction(n, scal(h), z, p, st);
   };
   // r = b - A x0
   {
@@ -318,18 +491,19 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
     precondition(h, r, z);
     launch_copy(n, z, p, st);
     dot(h, L, r, z, kRZ);
+    if (graphs && (!h->graph_a || h->graph_b_ptr != b || h->graph_x_ptr != x)) {
+      h->drop_graphs();
+      const bool prof = h->profiling;
+      h->profiling = false;  // no event records inside graphs
+      h->graph_a = capture_graph(st, [&] { body_a(false); });
+      h->graph_b = capture_graph(st, body_b);
+      h->profiling = prof;
+      h->graph_b_ptr = b;
+      h->graph_x_ptr = x;
+    }
     while (it < maxit) {
-      StencilArgs a;
-      a.op = StencilOp::CgQ;
-      a.x = p;
-      a.out = q;
-      a.partials = part;
-      if (h->profiling) h->timers[kTimedCgQ].acquire(&a.ev0, &a.ev1);
-      const int64_t np = launch_stencil_op(L, a, st);
-      launch_reduce(part, np, scal(h), kPQ, st);
-      launch_cg_scalars(scal(h), 0, st);
-      const int64_t nu = launch_cg_update(L, scal(h), x, r, p, q, part, st);
-      launch_reduce(part, nu, scal(h), kRR, st);
+      if (graphs) RMG_HIP(hipGraphLaunch(h->graph_a, st));
+      else body_a(h->profiling);
       ++it;
       read_scalars(h);
       if (h->profiling)
@@ -348,15 +522,8 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
         break;
       }
       if (it >= maxit) break;
-      precondition(h, r, z);
-      dot(h, L, r, z, kRZnew);
-      if (flexible) {
-        dot(h, L, z, q, kZQ);
-        launch_cg_scalars(scal(h), 2, st);
-      } else {
-        launch_cg_scalars(scal(h), 1, st);
-      }
-      launch_cg_direction(n, scal(h), z, p, st);
+      if (graphs) RMG_HIP(hipGraphLaunch(h->graph_b, st));
+      else body_b();
     }
   }
   RMG_HIP(hipEventRecord(e1, st));
@@ -388,6 +555,16 @@ void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_
     info->true_relres = bnorm > 0.0 ? std::sqrt(h->host_scalars[kTmp]) / bnorm : 0.0;
     info->solve_ms = ms;
     info->history_len = hist_len;
+  }
+}
+
+void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
+         rmg_status* status) {
+  if (h->opt.use_graph) {
+    GraphStream gs(h);
+    pcg_impl(h, b, x, rtol, maxit, info, status);
+  } else {
+    pcg_impl(h, b, x, rtol, maxit, info, status);
   }
 }
 

@@ -33,6 +33,7 @@ SYMBOLS = (
     "rmg_apply_vcycle", "rmg_solve", "rmg_to_regional", "rmg_to_composite", "rmg_regional_matvec",
     "rmg_interface_sum", "rmg_restrict", "rmg_prolongate_add", "rmg_smooth", "rmg_level_info",
     "rmg_get_level_stencil", "rmg_get_coarse_matrix", "rmg_profile", "rmg_profile_query",
+    "rmg_tune_report",
 )
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
 
@@ -47,6 +48,9 @@ class Options(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("precision", ctypes.c_int),
         ("stencil_kernel", ctypes.c_int),
+        ("autotune", ctypes.c_int),
+        ("use_graph", ctypes.c_int),
+        ("autotune_cache", ctypes.c_char_p),
     ]
 
 
@@ -109,6 +113,7 @@ def load():
         "rmg_get_level_stencil": (I, [H, I, I, P]),
         "rmg_get_coarse_matrix": (I, [H, P]),
         "rmg_profile": (I, [H, I]),
+        "rmg_tune_report": (I, [H, ctypes.c_char_p, I]),
         "rmg_profile_query": (I, [H, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
@@ -143,6 +148,8 @@ def default_options(**kw) -> Options:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k == "autotune_cache" and isinstance(v, str):
+            v = v.encode()
         setattr(o, k, v)
     return o
 
@@ -280,3 +287,8 @@ class Handle:
         n, ms = ctypes.c_int64(), ctypes.c_double()
         _check(load().rmg_profile_query(self._h, kernel, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    def tune_report(self):
+        buf = ctypes.create_string_buffer(8192)
+        _check(load().rmg_tune_report(self._h, buf, 8192))
+        return buf.value.decode()

@@ -14,9 +14,10 @@ from tests import harness
 
 pytestmark = pytest.mark.gpu
 
-# (workload, 3D stencil kernel): 1 = node-parallel, 2 = 2.5D plane-marching tiles
+# (workload, 3D stencil kernel): 1 = node-parallel, 2 = 2.5D plane-marching tiles, 3 = persistent tiles
 SMALL = [("c1_small", 0), ("c2_small", 1), ("c2_small", 2), ("c4_small", 1), ("c4_small", 2),
-         ("c5_small", 1), ("c5_small", 2), ("c1", 0), ("c2_mid", 1), ("c2_mid", 2), ("c3_small", 0)]
+         ("c5_small", 1), ("c5_small", 2), ("c1", 0), ("c2_mid", 1), ("c2_mid", 2), ("c3_small", 0),
+         ("c4_small", 3), ("c2_mid", 3)]
 IDS = [f"{n}-k{k}" for n, k in SMALL]
 
 
