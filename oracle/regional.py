@@ -109,7 +109,8 @@ def coarse_composite(lay: Layout, coefs):
     return assembly.assemble_from_regions(lay, coefs).toarray()
 
 
-def setup(lay0: Layout, coefs0, opt: Options):
+def setup(lay0: Layout, coefs0, opt: Options, P0=None):
+    """Regional hierarchy; ``P0`` optionally replaces the finest level's region prolongators."""
     levels = []
     lay, coefs = lay0, coefs0
     for l in range(opt.nlevels):
@@ -122,7 +123,10 @@ def setup(lay0: Layout, coefs0, opt: Options):
         if opt.smoother == "chebyshev":
             L.lam = power_method(L, start_vector(lay, l, opt.seed), opt.power_iters)
         coarse = lay.coarsen()
-        L.P = [transfer.region_prolongator(lay, coarse, k) for k in range(lay.nreg)]
+        if l == 0 and P0 is not None:
+            L.P = list(P0)
+        else:
+            L.P = [transfer.region_prolongator(lay, coarse, k) for k in range(lay.nreg)]
         ccoefs = []
         for k in range(lay.nreg):
             Ak = assembly.stencil_to_csr(coefs[k], lay.dim, lay.ndof)

@@ -1,0 +1,110 @@
+"""Pins of the learned-prolongator part of the oracle."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import assembly, learned, regional, transfer
+from oracle.regions import Layout
+
+
+def small_problem():
+    w = synth.workload("c5_small")
+    lay = Layout(w.dim, w.origins, w.extents, w.dirichlet_mask)
+    ec = synth.jump_coefficients(w)
+    return w, lay, ec
+
+
+def random_theta(seed=0, scale=0.3):
+    return np.random.default_rng(seed).standard_normal(learned.NPARAM) * scale
+
+
+def test_cell_node_table():
+    # 24 edge nodes x 2 corners + 24 face nodes x 4 + 8 interior x 8 = 208 logits
+    counts = [len(n[3]) for n in learned.NODES]
+    assert counts.count(2) == 24 and counts.count(4) == 24 and counts.count(8) == 8
+    assert learned.NPARAM == 19472
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((5, 27))
+    E = rng.standard_normal((5, 4, 4, 4))
+    theta = random_theta(1)
+    L, g = learned.loss_and_grad(theta, X, E)
+    h = 1e-6
+    idx = rng.choice(learned.NPARAM, size=40, replace=False)
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (learned.loss_and_grad(tp, X, E)[0] - learned.loss_and_grad(tm, X, E)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_softmax_weights_partition_of_unity():
+    X = np.random.default_rng(4).standard_normal((7, 27))
+    z, _ = learned.forward(random_theta(2), X)
+    for w in learned.weights_from_logits(z):
+        np.testing.assert_allclose(w.sum(axis=1), 1.0, atol=1e-15)
+        assert (w >= 0).all()
+
+
+def test_geometric_stored_weights_reproduce_linear_interpolation():
+    _, lay, _ = small_problem()
+    coarse = lay.coarsen()
+    W = learned.geometric_weights(lay, coarse)
+    for k in range(lay.nreg):
+        A = learned.stored_prolongator(lay, coarse, k, W[k])
+        B = transfer.region_prolongator(lay, coarse, k)
+        assert abs(A - B).max() < 1e-15
+
+
+def test_learned_weights_consistent_and_rap_theorem():
+    """Averaged learned weights: co-located rows match across regions (Lemma P holds), free rows
+    away from the boundary sum to 1, corners inject, and the Galerkin theorem holds with them."""
+    w, lay, ec = small_problem()
+    coarse = lay.coarsen()
+    W = learned.node_weights(lay, coarse, random_theta(5), ec)
+    Pk = [learned.stored_prolongator(lay, coarse, k, W[k]) for k in range(lay.nreg)]
+    Pr = sp.block_diag(Pk).tocsr()
+    Psi, Psib = lay.psi_matrix(), coarse.psi_matrix()
+    # Lemma P: P^(r) Psibar^T = Psi^T P for the composite P assembled from region 0.. rows
+    M = Pr @ Psib.T  # rows of every regional copy
+    P = sp.csr_matrix((Psi @ M).multiply(1.0 / lay.mult.reshape(-1)[:, None]))  # average of copies
+    assert abs(M - Psi.T @ P).max() < 1e-14  # copies agree
+    rows = np.asarray(P.sum(axis=1)).ravel().reshape(lay.shape)
+    inner = (slice(3, -3),) * 3
+    np.testing.assert_allclose(rows[inner], 1.0, atol=1e-13)
+    coefs = assembly.regional_q1(lay, "diffusion", h=w.h, elem_coef=ec)
+    A = assembly.composite_q1(lay, "diffusion", h=w.h, elem_coef=ec)
+    lv = regional.setup(lay, coefs, regional.Options(nlevels=2, degree=2), P0=Pk)
+    Ar = assembly.assemble_from_regions(lv[1].lay, lv[1].coefs)
+    RAP = P.T @ A @ P
+    assert abs(Ar - RAP).max() <= 1e-12 * abs(RAP).max()
+
+
+def test_adam_first_step():
+    theta = np.zeros(4)
+    g = np.array([1.0, -2.0, 0.5, 0.0])
+    t1, m, v = learned.adam_step(theta, g, np.zeros(4), np.zeros(4), 1, 0.1)
+    # bias-corrected first step moves every nonzero coordinate by lr against the gradient's sign
+    np.testing.assert_allclose(t1[:3], -0.1 * np.sign(g[:3]), rtol=1e-6)
+    assert t1[3] == 0.0
+
+
+def test_training_reduces_loss():
+    w, lay, ec = small_problem()
+    coefs = assembly.regional_q1(lay, "diffusion", h=w.h, elem_coef=ec)
+    opt = regional.Options(nlevels=2, degree=3)
+    lv = regional.setup(lay, coefs, opt)
+    X, E = learned.training_set(lay, lv, opt, ec, nsamples=2, seed=1)
+    theta = random_theta(6, 0.1)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    L0, _ = learned.loss_and_grad(theta, X, E)
+    for t in range(1, 61):
+        L, g = learned.loss_and_grad(theta, X, E)
+        theta, m, v = learned.adam_step(theta, g, m, v, t, 3e-3)
+    L1, _ = learned.loss_and_grad(theta, X, E)
+    assert L1 < 0.7 * L0, (L0, L1)
