@@ -88,6 +88,10 @@ typedef struct {
                          host convergence check) as HIP graphs once and replays them */
   const char* autotune_cache; /* text file of autotuner choices keyed by level shape and
                          precision; read before tuning, appended after (NULL: no file) */
+  int judge_cycles;   /* learned interpolation only: > 0 measures the convergence factor of
+                         this many stationary V-cycles (rmg_convergence_factor) with the learned
+                         and with the geometric interpolation at setup and keeps the better
+                         hierarchy (default 10); 0 keeps the learned one whenever it is valid */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -219,6 +223,120 @@ rmg_status rmg_profile(rmg_handle* h, int enable);
 rmg_status rmg_tune_report(rmg_handle* h, char* buf, int cap);
 /* Launch count and summed duration (ms) of a timed kernel since the last reset. */
 rmg_status rmg_profile_query(rmg_handle* h, int kernel, int64_t* launches, double* total_ms);
+
+/* ---- stored and learned interpolation (finest level -> level 1) ----
+ *
+ * Operator-dependent interpolation in the spirit of the black-box multigrid
+ * transfers that Section 3.2 names as needing interface averaging: the rows of
+ * P for shared interface nodes must be identical in every region holding a
+ * copy (the interpolation condition behind the Theorem on per-region Galerkin
+ * products).  Scalar 3D problems only.
+ *
+ * Stored weights: 8 FP64 values per regional node of the finest level
+ * ([n_regional][8]), for the corners (ix, iy, iz) of the node's canonical
+ * coarse cell c = min(x / 3, coarse extent - 2) per axis (region-local
+ * coordinates), slot ix + 2 iy + 4 iz.  Valid weights (checked at setup):
+ * finite; non-zero only towards corners on the node's own coarse face, edge or
+ * point; zero from a Dirichlet coarse node to a free fine node; summing to one
+ * unless such a Dirichlet weight was dropped; equal on all copies of a shared
+ * node (per composite coarse node). */
+
+/* Weight-validity flags (rmg_prolongator_info) and the judge's verdict. */
+#define RMG_PW_NONFINITE 1
+#define RMG_PW_SUPPORT 2
+#define RMG_PW_DIRICHLET 4
+#define RMG_PW_COPIES 8
+#define RMG_PW_SUM 16
+#define RMG_PW_JUDGED_WORSE 32
+
+/* Kinds of finest-level interpolation. */
+#define RMG_P_GEOMETRIC 0
+#define RMG_P_STORED 1
+#define RMG_P_LEARNED 2
+
+/* Caller weights for the next rmg_setup_hierarchy (copied; w: host or device
+ * FP64 [n_regional][8] as above, on_device selects).  NULL restores the
+ * geometric interpolation.  Invalid weights make the setup fail with
+ * RMG_ERR_ARG.  Needs regions of a scalar 3D problem; rmg_build_regions
+ * clears the weights. */
+rmg_status rmg_set_prolongator_weights(rmg_handle* h, const double* w, int on_device);
+
+/* MLP of the learned interpolation: 27 inputs (log of the coefficients of a
+ * coarse cell's 3 x 3 x 3 fine elements, x fastest, minus their mean), two
+ * hidden layers of 64 with ReLU, 208 outputs: one logit per (fine node,
+ * admissible coarse corner) for the cell's 56 non-corner nodes in x-fastest
+ * order over the 4 x 4 x 4 cell nodes (corners of a node in slot order), a
+ * softmax per node giving its weights.  FP32 parameters, flat in the order
+ * W1 [64][27], b1 [64], W2 [64][64], b2 [64], W3 [208][64], b3 [208]. */
+#define RMG_MLP_NIN 27
+#define RMG_MLP_NHIDDEN 64
+#define RMG_MLP_NOUT 208
+#define RMG_MLP_NPARAM 19472
+
+/* Use the MLP with parameters theta (host FP32 [RMG_MLP_NPARAM], copied) for
+ * the next rmg_setup_hierarchy: the setup evaluates it on every coarse cell of
+ * the finest level, averages the predictions of all cells containing a fine
+ * node, injects coarse points and drops Dirichlet weights as the geometric
+ * interpolation does.  Weights that fail the validity rules (e.g. NaN
+ * parameters) fall back to the geometric interpolation, as does a learned
+ * hierarchy that the judge (rmg_options.judge_cycles) finds slower to
+ * converge.  Features come from the element coefficients given to
+ * rmg_assemble_q1 (zero for RMG_PDE_LAPLACE).  NULL restores geometric. */
+rmg_status rmg_set_learned_prolongator(rmg_handle* h, const float* theta);
+
+/* Interpolation of the current hierarchy: kind (RMG_P_*), the validity flags
+ * and judge verdict that caused a fallback (0 if none), and the convergence
+ * factors measured by the judge (-1 when not measured).  Any output may be NULL. */
+rmg_status rmg_prolongator_info(rmg_handle* h, int* kind, int* flags, double* rho_learned, double* rho_geometric);
+
+/* Stored weights of the current hierarchy's finest level (host FP64
+ * [n_regional][8]); RMG_ERR_ARG when it interpolates geometrically. */
+rmg_status rmg_get_prolongator_weights(rmg_handle* h, double* host_out);
+
+/* Convergence factor of the preconditioner used as a stationary iteration on
+ * A x = 0: x0 from the counter-based generator (stream 63 of the hierarchy's
+ * seed, zero on Dirichlet dofs), x <- x + V(-A x) for `cycles` cycles,
+ * rho = (||r_cycles|| / ||r_0||)^(1/cycles) in the composite 2-norm.  Synchronises. */
+rmg_status rmg_convergence_factor(rmg_handle* h, int cycles, double* rho);
+
+/* ---- MLP training on the device ----
+ * Training data are pairs (X, E) per coarse cell: X the 27 features above and
+ * E the values of a smooth error on the cell's 4 x 4 x 4 fine nodes (x
+ * fastest).  Loss per pair: sum over the cell's nodes of (e_f - sum_c w_fc
+ * e_c)^2 / sum_f e_f^2, with e_c the corner values; the training loss is the
+ * mean over pairs.  Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+typedef struct rmg_mlp rmg_mlp;
+
+/* Create a trainer on HIP device `device`, work ordered on `hip_stream`.
+ * Parameters start at zero; set them with rmg_mlp_set_params. */
+rmg_status rmg_mlp_create(rmg_mlp** out, int device, void* hip_stream);
+rmg_status rmg_mlp_destroy(rmg_mlp* m);
+/* Parameters (host FP32 [RMG_MLP_NPARAM]); setting them resets Adam's state. */
+rmg_status rmg_mlp_set_params(rmg_mlp* m, const float* theta);
+rmg_status rmg_mlp_get_params(rmg_mlp* m, float* theta);
+/* Append n pairs: X [n][27], E [n][64] FP32 (host or device per on_device). */
+rmg_status rmg_mlp_add_data(rmg_mlp* m, int64_t n, const float* X, const float* E, int on_device);
+/* Append nsamples x (coarse cells of the finest level) pairs generated from a
+ * set-up scalar 3D hierarchy: for each sample s the error starts from the
+ * counter-based generator (stream 32 + s of `seed`, zero on Dirichlet nodes)
+ * and is smoothed by `sweeps` degree-K Chebyshev applications to A e = 0;
+ * cells are taken region by region, x fastest.  Synchronises h's stream. */
+rmg_status rmg_mlp_add_samples(rmg_mlp* m, rmg_handle* h, int nsamples, uint64_t seed, int sweeps);
+rmg_status rmg_mlp_clear_data(rmg_mlp* m);
+rmg_status rmg_mlp_num_data(rmg_mlp* m, int64_t* n);
+/* Copy pairs [first, first + count) to host arrays (either may be NULL). */
+rmg_status rmg_mlp_get_data(rmg_mlp* m, int64_t first, int64_t count, float* X, float* E);
+/* Logits Z [n][208] of inputs X [n][27] (host or device per on_device, both alike). */
+rmg_status rmg_mlp_forward(rmg_mlp* m, int64_t n, const float* X, float* Z, int on_device);
+/* Loss over all pairs and its gradient (grad: host FP32 [RMG_MLP_NPARAM] or
+ * NULL; the gradient also stays on the device for rmg_mlp_adam_step). */
+rmg_status rmg_mlp_loss_grad(rmg_mlp* m, double* loss, float* grad);
+/* One Adam step with learning rate lr, using `grad` (host FP32) or, if NULL,
+ * the gradient of the last rmg_mlp_loss_grad / training step. */
+rmg_status rmg_mlp_adam_step(rmg_mlp* m, const float* grad, double lr);
+/* `steps` full-batch steps (loss and gradient, then Adam) on the device;
+ * loss_history (host [steps] or NULL) receives the loss before each step. */
+rmg_status rmg_mlp_train(rmg_mlp* m, int steps, double lr, double* loss_history);
 
 #ifdef __cplusplus
 }

@@ -113,19 +113,6 @@ rmg_handle::~rmg_handle() {
   if (host_scalars) (void)hipHostFree(host_scalars);
 }
 
-#define API_BEGIN try {
-#define API_END                                   \
-  }                                               \
-  catch (const rmg::Error& e) {                   \
-    rmg::set_last_error(e.msg);                   \
-    return e.code;                                \
-  }                                               \
-  catch (const std::exception& e) {               \
-    rmg::set_last_error(e.what());                \
-    return RMG_ERR_ARG;                           \
-  }                                               \
-  return RMG_OK;
-
 static void use_device(rmg_handle* h) {
   RMG_REQUIRE(h != nullptr, RMG_ERR_ARG, "null handle");
   RMG_HIP(hipSetDevice(h->device));
@@ -153,6 +140,7 @@ void rmg_options_default(rmg_options* o) {
   o->autotune = 0;
   o->use_graph = 0;
   o->autotune_cache = nullptr;
+  o->judge_cycles = 10;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -198,6 +186,9 @@ rmg_status rmg_build_regions(rmg_handle* h, int dim, int ndof, int nreg, const i
   RMG_REQUIRE(nreg >= 1 && extent && origin, RMG_ERR_ARG, "need nreg >= 1 and extent/origin arrays");
   RMG_REQUIRE(mask < (1u << (2 * dim)), RMG_ERR_ARG, "dirichlet mask has bits beyond 2*dim");
   h->have_regions = h->have_operator = h->have_hierarchy = false;
+  h->user_pw.release();
+  h->logc.release();
+  if (h->pmode == RMG_P_STORED) h->pmode = RMG_P_GEOMETRIC;
   h->dim = dim;
   h->ndof = ndof;
   h->nreg = nreg;
@@ -258,6 +249,7 @@ rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const dou
   RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "stencil has NaN or Inf entries");
   h->region_set[region] = true;
   h->have_hierarchy = false;
+  h->logc.release();
   bool all = true;
   for (bool b : h->region_set) all = all && b;
   h->have_operator = all;
@@ -313,6 +305,7 @@ rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef
   RMG_HIP(hipStreamSynchronize(h->stream));
   RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "composite stencil has NaN or Inf entries");
   h->region_set.assign(h->nreg, true);
+  h->logc.release();
   h->have_operator = true;
   h->have_hierarchy = false;
   API_END
@@ -350,6 +343,14 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
     double K[64];
     q1_laplace_element(hsize, K);
     launch_assemble_q1_scalar(L, K, pde == RMG_PDE_DIFFUSION ? elem_coef : nullptr, h->stream);
+  }
+  // features of the learned interpolation: log of the element coefficients
+  if (pde == RMG_PDE_DIFFUSION) {
+    const int64_t nelem = (int64_t)(L.comp[0] - 1) * (L.comp[1] - 1) * (L.comp[2] - 1);
+    h->logc.alloc(sizeof(float) * (size_t)nelem);
+    launch_log(nelem, elem_coef, h->logc.as<float>(), h->stream);
+  } else {
+    h->logc.release();
   }
   launch_dirichlet_split(L, h->stream);
   DBuf flag;

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/regmg.h"
@@ -31,6 +33,20 @@ void set_last_error(const std::string& msg);
   do {                               \
     if (!(cond)) ::rmg::fail(code, msg); \
   } while (0)
+
+// Body of a C entry point: library errors become a status and the thread's last error.
+#define API_BEGIN try {
+#define API_END                                   \
+  }                                               \
+  catch (const rmg::Error& e) {                   \
+    rmg::set_last_error(e.msg);                   \
+    return e.code;                                \
+  }                                               \
+  catch (const std::exception& e) {               \
+    rmg::set_last_error(e.what());                \
+    return RMG_ERR_ARG;                           \
+  }                                               \
+  return RMG_OK;
 
 // ------------------------------------------------------- device geometry
 // One region on one level.  2D problems use ez = oz = 0 extents of 1.
@@ -86,6 +102,10 @@ struct DBuf {
   void alloc(size_t nbytes);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
+  void swap(DBuf& o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
   ~DBuf() { release(); }
   DBuf() = default;
   DBuf(const DBuf&) = delete;
@@ -120,6 +140,7 @@ struct Level {
   // operator (FP64, wave-tiled, ncoef() values per node: npts blocks of ndof x ndof)
   DBuf coef;
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
+  DBuf pw;        // stored interpolation weights to the next level, double [n][8] (null: geometric)
   double lambda = 0.0;
   std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step: direction and residual factors
   // work vectors (regional): b (rhs), u / u2 (ping-pong), d (Chebyshev direction), r (residual)
@@ -184,6 +205,14 @@ struct rmg_handle {
   const void* graph_x_ptr = nullptr;
   void drop_graphs();
   rmg::KernelTimer timers[rmg::kNumTimed];
+  // finest-level interpolation requested for the next setup (RMG_P_*) and its inputs
+  int pmode = 0;
+  rmg::DBuf user_pw;             // caller weights, double [n][8]
+  std::vector<float> mlp_theta;  // parameters of the learned interpolation
+  rmg::DBuf logc;                // float log of the per-element coefficients (diffusion), or empty
+  // interpolation of the current hierarchy
+  int p_used = 0, p_flags = 0;
+  double rho_learned = -1.0, rho_geometric = -1.0;
   ~rmg_handle();
 };
 
@@ -206,5 +235,15 @@ void apply_preconditioner(rmg_handle* h, const double* r, double* z);
 void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
          rmg_status* st);
 void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out);
+// u <- S(b, u): one degree-K Chebyshev application from the current iterate (tmp: work vector).
+void smooth_iterate(rmg_handle* h, int level, const double* b, double* u, double* tmp);
+// Convergence factor of `cycles` stationary V-cycles on A x = 0 (FP64 outer iteration).
+double convergence_factor(rmg_handle* h, int cycles);
+
+// learned.cpp
+// Stored weights of the finest level for the next coarse level C (caller or learned); returns the
+// validity flags (0: valid, weights in F.pw).  Releases F.pw when the interpolation is geometric.
+int prepare_stored_weights(rmg_handle* h, Level& F, const Level& C);
+int validate_weights(rmg_handle* h, const Level& F, const Level& C);
 
 }  // namespace rmg

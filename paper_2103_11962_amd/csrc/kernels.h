@@ -66,6 +66,8 @@ void launch_start_vector(const Level& L, int level, uint64_t seed, double* out, 
 void launch_scale(int64_t n, const double* scalars, int slot, int mode, const double* x, double* y,
                   hipStream_t st);  // mode 0: y = x / sqrt(s); mode 1: y = x * s
 void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStream_t st);  // y = a*b
+void launch_add(int64_t n, const double* x, double* y, hipStream_t st);  // y += x
+void launch_log(int64_t n, const double* in, float* out, hipStream_t st);  // out = log(in), FP32
 void launch_f64_to_f32(int64_t n, const double* in, float* out, hipStream_t st);
 void launch_f32_to_f64(int64_t n, const float* in, double* out, hipStream_t st);
 // Low-precision copy of a level's operator: coef_lo (FP32, or BF16 off-diagonals with FP32

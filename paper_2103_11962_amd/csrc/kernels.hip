@@ -183,6 +183,17 @@ void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStrea
   LAUNCH_CHECK();
 }
 
+__global__ void k_add(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
+void launch_add(int64_t n, const double* x, double* y, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_add, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, x, y);
+  LAUNCH_CHECK();
+}
+
 __global__ void k_zero(int64_t n, double* y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = 0.0;
@@ -280,12 +291,23 @@ void launch_start_vector(const Level& L, int level, uint64_t seed, double* out, 
 }
 
 // ------------------------------------------------------------ transfers
+// Stored interpolation weights (learned or caller-given): 8 per fine node for the corners
+// (ix, iy, iz) of its canonical coarse cell c = min(f / 3, coarse extent - 2), slot
+// ix + 2 iy + 4 iz.  Returns P(f, C) for fine node f and coarse node C of the same region.
+__device__ __forceinline__ double pweight(const double* __restrict__ pw, const RegionGeo& RF, const RegionGeo& RC,
+                                          int fx, int fy, int fz, int X, int Y, int Z) {
+  const int cx = min(fx / 3, RC.ex - 2), cy = min(fy / 3, RC.ey - 2), cz = RC.ez > 1 ? min(fz / 3, RC.ez - 2) : 0;
+  const int ix = X - cx, iy = Y - cy, iz = Z - cz;
+  if ((unsigned)ix > 1u || (unsigned)iy > 1u || (unsigned)iz > 1u) return 0.0;
+  return pw[(RF.off + ((int64_t)fz * RF.ey + fy) * RF.ex + fx) * 8 + ix + 2 * iy + 4 * iz];
+}
+
 // One thread per coarse node: w = sum_f P_fC r_f over the fine nodes of the same region within
 // two fine cells per axis (r already divided by multiplicity), per dof.  Coarse Dirichlet nodes
 // receive nothing (free fine nodes do not interpolate from them).
-template <int DIM, int NDOF, class V>
+template <int DIM, int NDOF, class V, bool STORED>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, const V* __restrict__ r,
-                                                     V* __restrict__ w) {
+                                                     V* __restrict__ w, const double* __restrict__ pw) {
   const BlockDesc bd = C.blocks[blockIdx.x];
   const RegionGeo RC = C.regs[bd.region];
   const RegionGeo RF = F.regs[bd.region];
@@ -313,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, c
         for (int tx = -2; tx <= 2; ++tx) {
           const int fx = 3 * X + tx;
           if ((unsigned)fx >= (unsigned)RF.ex) continue;
-          const V wt = (V)(wzy * w1(tx));
+          const V wt = STORED ? (V)pweight(pw, RF, RC, fx, fy, fz, X, Y, Z) : (V)(wzy * w1(tx));
 #pragma unroll
           for (int a = 0; a < NDOF; ++a) acc[a] += wt * rr[(int64_t)(base + fx) * NDOF + a];
         }
@@ -326,10 +348,21 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, c
 
 template <int NDOF, class V>
 static void restrict_t(const Level& F, const Level& C, const V* r, V* w, hipStream_t st) {
+  const double* pw = F.pw.as<double>();
+  const dim3 g(C.blocks.size()), b(kBlock);
+  if constexpr (NDOF == 1) {
+    if (pw) {
+      RMG_REQUIRE(F.dim == 3, RMG_ERR_ARG, "stored interpolation weights need a 3D level");
+      hipLaunchKernelGGL((k_restrict<3, 1, V, true>), g, b, 0, st, F.view(), C.view(), r, w, pw);
+      LAUNCH_CHECK();
+      iface_sum_inplace<V>(C, w, st);
+      return;
+    }
+  }
   if (F.dim == 3)
-    hipLaunchKernelGGL((k_restrict<3, NDOF, V>), dim3(C.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), r, w);
+    hipLaunchKernelGGL((k_restrict<3, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), r, w, pw);
   else
-    hipLaunchKernelGGL((k_restrict<2, NDOF, V>), dim3(C.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), r, w);
+    hipLaunchKernelGGL((k_restrict<2, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), r, w, pw);
   LAUNCH_CHECK();
   iface_sum_inplace<V>(C, w, st);
 }
@@ -346,9 +379,9 @@ void launch_restrict(const Level& F, const Level& C, bool lowp, const void* r_sc
 
 // One thread per fine node: u += sum_C P_fC ubar_C over the (up to 2 per axis) coarse nodes of
 // the coarse cell containing the node, per dof.
-template <int DIM, int NDOF, class V>
+template <int DIM, int NDOF, class V, bool STORED>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView F, LevelView C, const V* __restrict__ ubar,
-                                                        V* __restrict__ u) {
+                                                        V* __restrict__ u, const double* __restrict__ pw) {
   const BlockDesc bd = F.blocks[blockIdx.x];
   const RegionGeo RF = F.regs[bd.region];
   const RegionGeo RC = C.regs[bd.region];
@@ -362,6 +395,19 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView F, LevelView C
   V acc[NDOF];
 #pragma unroll
   for (int a = 0; a < NDOF; ++a) acc[a] = (V)0;
+  if constexpr (STORED) {
+    const double* __restrict__ wv = pw + (RF.off + li) * 8;
+    const int bx = min(cx, RC.ex - 2), by = min(cy, RC.ey - 2), bz = RC.ez > 1 ? min(cz, RC.ez - 2) : 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const double wt = wv[s];
+      if (wt == 0.0) continue;
+      const int X = bx + (s & 1), Y = by + ((s >> 1) & 1), Z = bz + ((s >> 2) & 1);
+      acc[0] += (V)wt * ub[(int64_t)((Z * RC.ey + Y) * RC.ex + X)];
+    }
+    u[RF.off + li] += acc[0];
+    return;
+  }
   const int nz = (DIM == 3 && tz) ? 2 : 1, ny = ty ? 2 : 1, nx = tx ? 2 : 1;
   for (int iz = 0; iz < nz; ++iz) {
     const double wz = DIM == 3 ? w1(tz - 3 * iz) : 1.0;
@@ -384,12 +430,20 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView F, LevelView C
 
 template <int NDOF, class V>
 static void prolong_t(const Level& F, const Level& C, const V* ubar, V* u, hipStream_t st) {
+  const double* pw = F.pw.as<double>();
+  const dim3 g(F.blocks.size()), b(kBlock);
+  if constexpr (NDOF == 1) {
+    if (pw) {
+      RMG_REQUIRE(F.dim == 3, RMG_ERR_ARG, "stored interpolation weights need a 3D level");
+      hipLaunchKernelGGL((k_prolong_add<3, 1, V, true>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
+      LAUNCH_CHECK();
+      return;
+    }
+  }
   if (F.dim == 3)
-    hipLaunchKernelGGL((k_prolong_add<3, NDOF, V>), dim3(F.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(),
-                       ubar, u);
+    hipLaunchKernelGGL((k_prolong_add<3, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
   else
-    hipLaunchKernelGGL((k_prolong_add<2, NDOF, V>), dim3(F.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(),
-                       ubar, u);
+    hipLaunchKernelGGL((k_prolong_add<2, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
   LAUNCH_CHECK();
 }
 
@@ -410,9 +464,9 @@ void launch_prolong_add(const Level& F, const Level& C, bool lowp, const void* u
 // the scalar weights.  Accumulators live in LDS (one column per thread).  Dirichlet reading: a
 // Dirichlet coarse row only collects Dirichlet fine nodes; entries of a free row towards
 // Dirichlet coarse nodes are zero.
-template <int NPTSF, int DIM, int NDOF, int BS>
+template <int NPTSF, int DIM, int NDOF, int BS, bool STORED>
 __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const double* __restrict__ coefF,
-                                            double* __restrict__ coefC) {
+                                            double* __restrict__ coefC, const double* __restrict__ pw) {
   constexpr int NC = DIM == 3 ? 27 : 9;
   constexpr int NB = NDOF * NDOF;
   constexpr int SUB = kBlock / BS;
@@ -439,7 +493,9 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
         const int fx = 3 * X + tx;
         if ((unsigned)fx >= (unsigned)RF.ex) continue;
         if (cdir && !is_dirichlet(F, RF.ox + fx, RF.oy + fy, RF.oz + fz)) continue;
-        const double wf = (DIM == 3 ? w1(tz) : 1.0) * w1(ty) * w1(tx);
+        const double wf = STORED ? pweight(pw, RF, RC, fx, fy, fz, X, Y, Z)
+                                 : (DIM == 3 ? w1(tz) : 1.0) * w1(ty) * w1(tx);
+        if (wf == 0.0) continue;
         const int64_t fi = RF.off + (fz * RF.ey + fy) * RF.ex + fx;
 #pragma unroll
         for (int s = 0; s < NPTSF; ++s) {
@@ -468,7 +524,15 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
                 const double wx = w1(ux - 3 * ox);
                 if (wx == 0.0) continue;
                 const int oi = DIM == 3 ? (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1) : (oy + 1) * 3 + (ox + 1);
-                const double wo = wz * wy * wx;
+                double wo = wz * wy * wx;
+                if constexpr (STORED) {
+                  const int gx = fx + dx, gy = fy + dy, gz = fz + dz;
+                  if ((unsigned)gx >= (unsigned)RF.ex || (unsigned)gy >= (unsigned)RF.ey ||
+                      (unsigned)gz >= (unsigned)RF.ez)
+                    continue;
+                  wo = pweight(pw, RF, RC, gx, gy, gz, X + ox, Y + oy, Z + oz);
+                  if (wo == 0.0) continue;
+                }
 #pragma unroll
                 for (int ab = 0; ab < NB; ++ab) acc[oi * NB + ab][tid] += (wf * a[ab]) * wo;
               }
@@ -496,17 +560,25 @@ void launch_rap(const Level& F, Level& C, hipStream_t st) {
   const LevelView fv = F.view(), cv = C.view();
   const double* cf = F.coef.as<double>();
   double* cc = C.coef.as<double>();
+  const double* pw = F.pw.as<double>();
+  RMG_REQUIRE(!pw || (F.dim == 3 && F.ndof == 1), RMG_ERR_ARG, "stored interpolation weights need a scalar 3D level");
   if (F.ndof == 3) {
     RMG_REQUIRE(F.npts == 27, RMG_ERR_ARG, "3D levels need 27-point stencils");
     constexpr int BS = 32;
-    hipLaunchKernelGGL((k_rap<27, 3, 3, BS>), dim3(C.blocks.size() * (kBlock / BS)), dim3(BS), 0, st, fv, cv, cf, cc);
+    hipLaunchKernelGGL((k_rap<27, 3, 3, BS, false>), dim3(C.blocks.size() * (kBlock / BS)), dim3(BS), 0, st, fv, cv,
+                       cf, cc, pw);
   } else if (F.dim == 3) {
     RMG_REQUIRE(F.npts == 27, RMG_ERR_ARG, "3D levels need 27-point stencils");
-    hipLaunchKernelGGL((k_rap<27, 3, 1, kBlock>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc);
+    if (pw)
+      hipLaunchKernelGGL((k_rap<27, 3, 1, kBlock, true>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc,
+                         pw);
+    else
+      hipLaunchKernelGGL((k_rap<27, 3, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc,
+                         pw);
   } else if (F.npts == 9) {
-    hipLaunchKernelGGL((k_rap<9, 2, 1, kBlock>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc);
+    hipLaunchKernelGGL((k_rap<9, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw);
   } else {
-    hipLaunchKernelGGL((k_rap<5, 2, 1, kBlock>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc);
+    hipLaunchKernelGGL((k_rap<5, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw);
   }
   LAUNCH_CHECK();
 }

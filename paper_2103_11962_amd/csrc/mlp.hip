@@ -1,0 +1,533 @@
+// Learned prolongation weights: a small MLP (27 -> 64 -> 64 -> 208, ReLU, FP32) maps the
+// centred log-coefficients of a coarse cell's 27 fine elements to one logit per (fine node,
+// coarse corner) pair of the cell; a softmax over each node's corners gives its weights.
+// Training, inference, data extraction and the assembly of per-node interpolation weights
+// (averaging the predictions of all cells that share a node) run in the kernels below.
+//
+// Training kernels follow the textbook layer-by-layer backward pass: per-sample kernels for
+// the forward pass, the loss and the activation gradients, and a split-N reduction of the
+// weight gradients (fixed summation order, so gradients are deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_common.h"
+#include "mlp.h"
+
+namespace rmg {
+
+// Non-corner fine nodes of a cell (x-fastest over the 4x4x4 cell nodes): position, number of
+// corners, first logit, corner slots (ix + 2 iy + 4 iz).  Filled on the host.
+__constant__ CellNode c_nodes[56];
+__constant__ signed char c_pos2node[64];  // -1 for the 8 corners
+
+// Once per device (constant memory is per device).
+static void upload_tables() {
+  static bool done[64] = {};
+  int dev = 0;
+  RMG_HIP(hipGetDevice(&dev));
+  RMG_REQUIRE(dev >= 0 && dev < 64, RMG_ERR_ARG, "device index beyond 63");
+  if (done[dev]) return;
+  CellNode nodes[56];
+  signed char pos2node[64];
+  int n = 0, off = 0;
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < 4; ++i) {
+        const int c[3] = {i, j, k};
+        const bool corner = (i == 0 || i == 3) && (j == 0 || j == 3) && (k == 0 || k == 3);
+        pos2node[(k * 4 + j) * 4 + i] = corner ? (signed char)-1 : (signed char)n;
+        if (corner) continue;
+        CellNode& nd = nodes[n];
+        nd.pos = (k * 4 + j) * 4 + i;
+        nd.first = off;
+        int opts[3][2], no[3];
+        for (int d = 0; d < 3; ++d) {
+          if (c[d] == 1 || c[d] == 2) {
+            opts[d][0] = 0;
+            opts[d][1] = 1;
+            no[d] = 2;
+          } else {
+            opts[d][0] = c[d] == 0 ? 0 : 1;
+            no[d] = 1;
+          }
+        }
+        int nc = 0;
+        for (int iz = 0; iz < no[2]; ++iz)
+          for (int iy = 0; iy < no[1]; ++iy)
+            for (int ix = 0; ix < no[0]; ++ix) nd.corner[nc++] = opts[0][ix] + 2 * opts[1][iy] + 4 * opts[2][iz];
+        nd.ncorner = nc;
+        off += nc;
+        ++n;
+      }
+  RMG_REQUIRE(n == 56 && off == kMlpOut, RMG_ERR_ARG, "internal: cell node table");
+  RMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_nodes), nodes, sizeof(nodes)));
+  RMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_pos2node), pos2node, sizeof(pos2node)));
+  done[dev] = true;
+}
+
+void mlp_tables() { upload_tables(); }
+
+// ------------------------------------------------------------------ forward
+// Parameter layout: W1 [64][27], b1 [64], W2 [64][64], b2 [64], W3 [208][64], b3 [208].
+__global__ __launch_bounds__(kBlock) void k_mlp_forward(int64_t n, const float* __restrict__ X,
+                                                        const float* __restrict__ th, float* __restrict__ Z,
+                                                        float* __restrict__ A1, float* __restrict__ A2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* W1 = th;
+  const float* b1 = W1 + kMlpH * kMlpIn;
+  const float* W2 = b1 + kMlpH;
+  const float* b2 = W2 + kMlpH * kMlpH;
+  const float* W3 = b2 + kMlpH;
+  const float* b3 = W3 + kMlpOut * kMlpH;
+  // hidden activations stay in registers: every loop that indexes them is fully unrolled
+  float x[kMlpIn], h1[kMlpH], h2[kMlpH];
+#pragma unroll
+  for (int j = 0; j < kMlpIn; ++j) x[j] = X[i * kMlpIn + j];
+#pragma unroll
+  for (int r = 0; r < kMlpH; ++r) {
+    float a = b1[r];
+#pragma unroll
+    for (int j = 0; j < kMlpIn; ++j) a += W1[r * kMlpIn + j] * x[j];
+    if (A1) A1[i * kMlpH + r] = a;
+    h1[r] = a > 0.f ? a : 0.f;
+  }
+#pragma unroll
+  for (int r = 0; r < kMlpH; ++r) {
+    float a = b2[r];
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) a += W2[r * kMlpH + j] * h1[j];
+    if (A2) A2[i * kMlpH + r] = a;
+    h2[r] = a > 0.f ? a : 0.f;
+  }
+  for (int r = 0; r < kMlpOut; ++r) {
+    float a = b3[r];
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) a += W3[r * kMlpH + j] * h2[j];
+    Z[i * kMlpOut + r] = a;
+  }
+}
+
+// Position (in the 4x4x4 cell nodes) of coarse corner slot s.
+__device__ __forceinline__ int corner_pos(int s) { return 48 * ((s >> 2) & 1) + 12 * ((s >> 1) & 1) + 3 * (s & 1); }
+
+// Softmax over the corners of node `nd` of a logit row (entries c >= nd.ncorner are left 0).
+__device__ __forceinline__ void node_softmax(const float* z, const CellNode& nd, float (&w)[8]) {
+  float m = z[nd.first];
+#pragma unroll
+  for (int c = 1; c < 8; ++c)
+    if (c < nd.ncorner) m = fmaxf(m, z[nd.first + c]);
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    w[c] = c < nd.ncorner ? expf(z[nd.first + c] - m) : 0.f;
+    s += w[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) w[c] /= s;
+}
+
+// Loss per sample sum_f (e_f - sum_c w_fc e_c)^2 / sum_f e_f^2 and its gradient with respect
+// to the logits, scaled by 1/n (the loss is a mean over samples).
+__global__ __launch_bounds__(kBlock) void k_mlp_loss(int64_t n, const float* __restrict__ Z,
+                                                     const float* __restrict__ E, float* __restrict__ dZ,
+                                                     double* __restrict__ partials) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double loss = 0.0;
+  if (i < n) {
+    const float* e = E + i * 64;
+    const float* z = Z + i * kMlpOut;
+    float* dz = dZ + i * kMlpOut;
+    float norm = 0.f;
+    for (int p = 0; p < 64; ++p) norm += e[p] * e[p];
+    if (!(norm > 0.f)) norm = 1.f;
+    const float inv_n = 1.0f / (float)n;
+    float l = 0.f;
+    for (int k = 0; k < 56; ++k) {
+      const CellNode nd = c_nodes[k];
+      float w[8], ev[8];
+      node_softmax(z, nd, w);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) ev[c] = c < nd.ncorner ? e[corner_pos(nd.corner[c])] : 0.f;
+      float pred = 0.f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) pred += w[c] * ev[c];
+      const float res = e[nd.pos] - pred;
+      l += res * res;
+      const float dpred = -2.f * res / norm;
+      float sdw = 0.f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) sdw += dpred * ev[c] * w[c];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < nd.ncorner) dz[nd.first + c] = w[c] * (dpred * ev[c] - sdw) * inv_n;
+    }
+    loss = (double)(l / norm);
+  }
+  const double s = block_sum(loss);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Activation gradients: D2 = (dZ W3) * [A2 > 0], D1 = (D2 W2) * [A1 > 0].
+__global__ __launch_bounds__(kBlock) void k_mlp_backact(int64_t n, const float* __restrict__ dZ,
+                                                        const float* __restrict__ A1, const float* __restrict__ A2,
+                                                        const float* __restrict__ th, float* __restrict__ D1,
+                                                        float* __restrict__ D2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* W2 = th + kMlpH * kMlpIn + kMlpH;
+  const float* W3 = W2 + kMlpH * kMlpH + kMlpH;
+  float d2[kMlpH];
+#pragma unroll
+  for (int k = 0; k < kMlpH; ++k) d2[k] = 0.f;
+  for (int j = 0; j < kMlpOut; ++j) {
+    const float g = dZ[i * kMlpOut + j];
+#pragma unroll
+    for (int k = 0; k < kMlpH; ++k) d2[k] += g * W3[j * kMlpH + k];
+  }
+#pragma unroll
+  for (int k = 0; k < kMlpH; ++k) {
+    d2[k] = A2[i * kMlpH + k] > 0.f ? d2[k] : 0.f;
+    D2[i * kMlpH + k] = d2[k];
+  }
+#pragma unroll 4
+  for (int r = 0; r < kMlpH; ++r) {
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMlpH; ++k) a += d2[k] * W2[k * kMlpH + r];
+    D1[i * kMlpH + r] = A1[i * kMlpH + r] > 0.f ? a : 0.f;
+  }
+}
+
+// Partial weight gradients over a chunk of samples: for output row r,
+// P[chunk][r][j] = sum_n D[n][r] H[n][j] (j < C, with H = ReLU(A) when relu), P[..][C] = sum_n D[n][r].
+__global__ __launch_bounds__(128) void k_mlp_outer(int64_t n, int R, int C, const float* __restrict__ D,
+                                                   const float* __restrict__ H, int relu, int64_t chunk,
+                                                   double* __restrict__ P) {
+  const int r = blockIdx.x, ch = blockIdx.y, j = threadIdx.x;
+  if (j > C) return;
+  const int64_t n0 = (int64_t)ch * chunk, n1 = min(n, n0 + chunk);
+  double acc = 0.0;
+  for (int64_t s = n0; s < n1; ++s) {
+    const float d = D[s * R + r];
+    if (j < C) {
+      float h = H[s * C + j];
+      if (relu) h = h > 0.f ? h : 0.f;
+      acc += (double)(d * h);
+    } else {
+      acc += (double)d;
+    }
+  }
+  P[((int64_t)ch * R + r) * (C + 1) + j] = acc;
+}
+
+// Sum the chunk partials into the flat gradient: W block at wofs (row-major R x C), bias at bofs.
+__global__ void k_mlp_outer_reduce(int R, int C, int nchunk, const double* __restrict__ P, float* __restrict__ grad,
+                                   int wofs, int bofs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= R * (C + 1)) return;
+  const int r = t / (C + 1), j = t - r * (C + 1);
+  double s = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) s += P[((int64_t)ch * R + r) * (C + 1) + j];
+  if (j < C) grad[wofs + r * C + j] = (float)s;
+  else grad[bofs + r] = (float)s;
+}
+
+__global__ void k_adam(int n, float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// --------------------------------------------------------------- launchers
+void mlp_forward(int64_t n, const float* X, const float* theta, float* Z, float* A1, float* A2, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, X, theta, Z, A1, A2);
+  LAUNCH_CHECK();
+}
+
+int64_t mlp_loss(int64_t n, const float* Z, const float* E, float* dZ, double* partials, hipStream_t st) {
+  upload_tables();
+  const int64_t nb = cdiv(n, kBlock);
+  hipLaunchKernelGGL(k_mlp_loss, dim3(nb), dim3(kBlock), 0, st, n, Z, E, dZ, partials);
+  LAUNCH_CHECK();
+  return nb;
+}
+
+void mlp_backact(int64_t n, const float* dZ, const float* A1, const float* A2, const float* theta, float* D1,
+                 float* D2, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_backact, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, dZ, A1, A2, theta, D1, D2);
+  LAUNCH_CHECK();
+}
+
+void mlp_weight_grads(int64_t n, const float* X, const float* A1, const float* A2, const float* dZ, const float* D1,
+                      const float* D2, float* grad, double* part, int nchunk, hipStream_t st) {
+  const int64_t chunk = cdiv(n, nchunk);
+  const int ofs_b1 = kMlpH * kMlpIn, ofs_W2 = ofs_b1 + kMlpH, ofs_b2 = ofs_W2 + kMlpH * kMlpH,
+            ofs_W3 = ofs_b2 + kMlpH, ofs_b3 = ofs_W3 + kMlpOut * kMlpH;
+  struct Job {
+    int R, C;
+    const float* D;
+    const float* H;
+    int relu, wofs, bofs;
+  } jobs[3] = {{kMlpOut, kMlpH, dZ, A2, 1, ofs_W3, ofs_b3},
+               {kMlpH, kMlpH, D2, A1, 1, ofs_W2, ofs_b2},
+               {kMlpH, kMlpIn, D1, X, 0, 0, ofs_b1}};
+  for (const Job& j : jobs) {
+    hipLaunchKernelGGL(k_mlp_outer, dim3(j.R, nchunk), dim3(128), 0, st, n, j.R, j.C, j.D, j.H, j.relu, chunk, part);
+    LAUNCH_CHECK();
+    const int tot = j.R * (j.C + 1);
+    hipLaunchKernelGGL(k_mlp_outer_reduce, dim3(cdiv(tot, kBlock)), dim3(kBlock), 0, st, j.R, j.C, nchunk, part, grad,
+                       j.wofs, j.bofs);
+    LAUNCH_CHECK();
+  }
+}
+
+void mlp_adam(float* theta, const float* grad, float* m, float* v, int t, double lr, hipStream_t st) {
+  const float c1 = (float)(1.0 - std::pow(0.9, t)), c2 = (float)(1.0 - std::pow(0.999, t));
+  hipLaunchKernelGGL(k_adam, dim3(cdiv(kMlpParams, kBlock)), dim3(kBlock), 0, st, kMlpParams, theta, grad, m, v,
+                     (float)lr, c1, c2);
+  LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------- data extraction
+// Cells of the finest level, region by region, x-fastest; cell_off[k] = first cell of region k.
+__device__ __forceinline__ int cell_region(const int64_t* __restrict__ cell_off, int nreg, int64_t c) {
+  int lo = 0, hi = nreg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cell_off[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_features(LevelView L, const int64_t* __restrict__ cell_off,
+                                                          int64_t ncell, const float* __restrict__ logc,
+                                                          float* __restrict__ X) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int k = cell_region(cell_off, L.nreg, c);
+  const RegionGeo R = L.regs[k];
+  const int ncx = (R.ex - 1) / 3, ncy = (R.ey - 1) / 3;
+  const int64_t lc = c - cell_off[k];
+  const int cx = (int)(lc % ncx), cy = (int)((lc / ncx) % ncy), cz = (int)(lc / ((int64_t)ncx * ncy));
+  const int ecx = L.cx - 1, ecy = L.cy - 1;
+  float v[27];
+  float mean = 0.f;
+#pragma unroll
+  for (int e = 0; e < 27; ++e) {
+    const int ex = R.ox + 3 * cx + e % 3, ey = R.oy + 3 * cy + (e / 3) % 3, ez = R.oz + 3 * cz + e / 9;
+    v[e] = logc ? logc[((int64_t)ez * ecy + ey) * ecx + ex] : 0.f;
+    mean += v[e];
+  }
+  mean *= (1.0f / 27.0f);
+#pragma unroll
+  for (int e = 0; e < 27; ++e) X[c * kMlpIn + e] = v[e] - mean;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_targets(LevelView L, const int64_t* __restrict__ cell_off,
+                                                         int64_t ncell, const double* __restrict__ e,
+                                                         float* __restrict__ E) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int k = cell_region(cell_off, L.nreg, c);
+  const RegionGeo R = L.regs[k];
+  const int ncx = (R.ex - 1) / 3, ncy = (R.ey - 1) / 3;
+  const int64_t lc = c - cell_off[k];
+  const int cx = (int)(lc % ncx), cy = (int)((lc / ncx) % ncy), cz = (int)(lc / ((int64_t)ncx * ncy));
+  for (int p = 0; p < 64; ++p) {
+    const int x = 3 * cx + p % 4, y = 3 * cy + (p / 4) % 4, z = 3 * cz + p / 16;
+    E[c * 64 + p] = (float)e[R.off + ((int64_t)z * R.ey + y) * R.ex + x];
+  }
+}
+
+void cell_features(const Level& L, const int64_t* cell_off, int64_t ncell, const float* logc, float* X,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_cell_features, dim3(cdiv(ncell, kBlock)), dim3(kBlock), 0, st, L.view(), cell_off, ncell, logc,
+                     X);
+  LAUNCH_CHECK();
+}
+
+void cell_targets(const Level& L, const int64_t* cell_off, int64_t ncell, const double* e, float* E, hipStream_t st) {
+  hipLaunchKernelGGL(k_cell_targets, dim3(cdiv(ncell, kBlock)), dim3(kBlock), 0, st, L.view(), cell_off, ncell, e, E);
+  LAUNCH_CHECK();
+}
+
+// ------------------------------------------------- learned weights per node
+// One thread per fine node of the finest level: average the predictions of every cell (of any
+// region) that contains the node, inject coarse corners, drop weights from Dirichlet coarse
+// nodes to free fine nodes, and store them against the corners of the node's canonical cell.
+// cellrow maps composite cells (x fastest) to logit rows.
+__global__ __launch_bounds__(kBlock) void k_learned_weights(LevelView F, LevelView C, const float* __restrict__ Z,
+                                                            const int* __restrict__ cellrow, double* __restrict__ pw) {
+  const BlockDesc bd = F.blocks[blockIdx.x];
+  const RegionGeo RF = F.regs[bd.region];
+  const RegionGeo RC = C.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= RF.n) return;
+  int x, y, z;
+  decompose(RF, li, x, y, z);
+  const int gx = RF.ox + x, gy = RF.oy + y, gz = RF.oz + z;
+  const int bx = min(x / 3, RC.ex - 2), by = min(y / 3, RC.ey - 2), bz = min(z / 3, RC.ez - 2);
+  const int BX = RC.ox + bx, BY = RC.oy + by, BZ = RC.oz + bz;  // composite coarse index of the cell's corner 0
+  double acc[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) acc[s] = 0.0;
+  const bool fdir = is_dirichlet(F, gx, gy, gz);
+  // slots are selected, never used as array indices, so the accumulators stay in registers
+  if (gx % 3 == 0 && gy % 3 == 0 && gz % 3 == 0) {
+    const int s = (gx / 3 - BX) + 2 * (gy / 3 - BY) + 4 * (gz / 3 - BZ);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = q == s ? 1.0 : 0.0;
+  } else {
+    const int ncx = (F.cx - 1) / 3, ncy = (F.cy - 1) / 3, ncz = (F.cz - 1) / 3;
+    int cnt = 0;
+    for (int dz = -1; dz <= 0; ++dz)
+      for (int dy = -1; dy <= 0; ++dy)
+        for (int dx = -1; dx <= 0; ++dx) {
+          // candidate cell (composite cell index) containing the node
+          const int cx = gx / 3 + dx, cy = gy / 3 + dy, cz = gz / 3 + dz;
+          if (cx < 0 || cy < 0 || cz < 0 || cx >= ncx || cy >= ncy || cz >= ncz) continue;
+          const int px = gx - 3 * cx, py = gy - 3 * cy, pz = gz - 3 * cz;
+          if (px > 3 || py > 3 || pz > 3) continue;
+          const int node = c_pos2node[(pz * 4 + py) * 4 + px];
+          if (node < 0) continue;
+          const CellNode nd = c_nodes[node];
+          const float* zr = Z + (int64_t)cellrow[((int64_t)cz * ncy + cy) * ncx + cx] * kMlpOut;
+          float w[8];
+          node_softmax(zr, nd, w);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            if (k >= nd.ncorner) continue;
+            const int cs = nd.corner[k];
+            const int s = (cx + (cs & 1) - BX) + 2 * (cy + ((cs >> 1) & 1) - BY) + 4 * (cz + ((cs >> 2) & 1) - BZ);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += q == s ? (double)w[k] : 0.0;
+          }
+          ++cnt;
+        }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc[s] /= (double)max(cnt, 1);
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int X = BX + (s & 1), Y = BY + ((s >> 1) & 1), Zc = BZ + ((s >> 2) & 1);
+    double v = acc[s];
+    if (!fdir && is_dirichlet(C, X, Y, Zc)) v = 0.0;
+    pw[(RF.off + li) * 8 + s] = v;
+  }
+}
+
+void learned_weights(const Level& F, const Level& C, const float* Z, const int* cellrow, double* pw, hipStream_t st) {
+  upload_tables();
+  hipLaunchKernelGGL(k_learned_weights, dim3(F.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), Z, cellrow,
+                     pw);
+  LAUNCH_CHECK();
+}
+
+// ------------------------------------------------ stored weight validation
+// Violation flags (WeightFlag): non-finite weights, support beyond the node's face, edge or
+// cell, a free fine node interpolating from a Dirichlet coarse node, and weights that do not sum
+// to one where no admissible corner is a dropped Dirichlet node.
+__global__ __launch_bounds__(kBlock) void k_check_weights(LevelView F, LevelView C, const double* __restrict__ pw,
+                                                          int* flag) {
+  const BlockDesc bd = F.blocks[blockIdx.x];
+  const RegionGeo RF = F.regs[bd.region];
+  const RegionGeo RC = C.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= RF.n) return;
+  int x, y, z;
+  decompose(RF, li, x, y, z);
+  const int bx = min(x / 3, RC.ex - 2), by = min(y / 3, RC.ey - 2), bz = min(z / 3, RC.ez - 2);
+  const int t[3] = {x - 3 * bx, y - 3 * by, z - 3 * bz};
+  const bool fdir = is_dirichlet(F, RF.ox + x, RF.oy + y, RF.oz + z);
+  int f = 0;
+  bool dropped = false;  // some admissible corner is a Dirichlet node (its weight is dropped)
+  double sum = 0.0;
+  for (int s = 0; s < 8; ++s) {
+    const int b[3] = {s & 1, (s >> 1) & 1, (s >> 2) & 1};
+    bool admissible = true;
+    for (int d = 0; d < 3; ++d)
+      if ((t[d] == 0 && b[d] == 1) || (t[d] == 3 && b[d] == 0)) admissible = false;
+    const bool cdir = is_dirichlet(C, RC.ox + bx + b[0], RC.oy + by + b[1], RC.oz + bz + b[2]);
+    if (admissible && cdir && !fdir) dropped = true;
+    const double v = pw[(RF.off + li) * 8 + s];
+    if (!isfinite(v)) f |= kWeightNonFinite;
+    if (v == 0.0) continue;
+    sum += v;
+    if (!admissible) f |= kWeightSupport;
+    if (cdir && !fdir) f |= kWeightDirichlet;
+  }
+  if (!dropped && !(fabs(sum - 1.0) <= 1e-6)) f |= kWeightSum;
+  if (f) atomicOr(flag, f);
+}
+
+// Copies of a shared node must carry the same weight for every composite coarse corner.
+__global__ __launch_bounds__(kBlock) void k_check_weight_copies(LevelView F, LevelView C,
+                                                                const int64_t* __restrict__ gptr,
+                                                                const int* __restrict__ gcopy,
+                                                                const int* __restrict__ gcomp, int64_t ng,
+                                                                const double* __restrict__ pw, int* flag) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= ng) return;
+  const int64_t ci = gcomp[g];
+  const int gx = (int)(ci % F.cx), gy = (int)((ci / F.cx) % F.cy), gz = (int)(ci / ((int64_t)F.cx * F.cy));
+  // composite weights of the first copy, keyed by composite corner offset from (gx/3, gy/3, gz/3) - 1
+  double ref[27];
+  for (int i = 0; i < 27; ++i) ref[i] = 0.0;
+  for (int64_t c = gptr[g]; c < gptr[g + 1]; ++c) {
+    const int gi = gcopy[c];
+    int k = 0;
+    while (k + 1 < F.nreg && F.regs[k + 1].off <= gi) ++k;
+    const RegionGeo RF = F.regs[k], RC = C.regs[k];
+    const int x = gx - RF.ox, y = gy - RF.oy, z = gz - RF.oz;
+    const int bx = min(x / 3, RC.ex - 2), by = min(y / 3, RC.ey - 2), bz = min(z / 3, RC.ez - 2);
+    double cur[27];
+    for (int i = 0; i < 27; ++i) cur[i] = 0.0;
+    for (int s = 0; s < 8; ++s) {
+      const int X = RC.ox + bx + (s & 1) - gx / 3 + 1, Y = RC.oy + by + ((s >> 1) & 1) - gy / 3 + 1,
+                Z = RC.oz + bz + ((s >> 2) & 1) - gz / 3 + 1;
+      if ((unsigned)X > 2u || (unsigned)Y > 2u || (unsigned)Z > 2u) {
+        if (pw[(int64_t)gi * 8 + s] != 0.0) atomicOr(flag, (int)kWeightSupport);
+        continue;
+      }
+      cur[(Z * 3 + Y) * 3 + X] = pw[(int64_t)gi * 8 + s];
+    }
+    for (int i = 0; i < 27; ++i) {
+      if (c == gptr[g]) ref[i] = cur[i];
+      else if (cur[i] != ref[i]) atomicOr(flag, (int)kWeightCopies);
+    }
+  }
+}
+
+void check_weights(const Level& F, const Level& C, const double* pw, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_weights, dim3(F.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), pw, flag);
+  LAUNCH_CHECK();
+  if (F.ngroups > 0) {
+    hipLaunchKernelGGL(k_check_weight_copies, dim3(cdiv(F.ngroups, kBlock)), dim3(kBlock), 0, st, F.view(), C.view(),
+                       F.d_gptr.as<int64_t>(), F.d_gcopy.as<int>(), F.d_gcomp.as<int>(), F.ngroups, pw, flag);
+    LAUNCH_CHECK();
+  }
+}
+
+// Log of per-element coefficients (composite element grid) for the MLP features.
+__global__ void k_log(int64_t n, const double* __restrict__ in, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)log(in[i]);
+}
+
+void launch_log(int64_t n, const double* in, float* out, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_log, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out);
+  LAUNCH_CHECK();
+}
+
+}  // namespace rmg

@@ -209,25 +209,19 @@ static void autotune_level(rmg_handle* h, Level& L, int level, bool lowp) {
   }
 }
 
-void setup_hierarchy(rmg_handle* h) {
+// Levels 0 .. nlevels-1: smoother data, next level by per-region Galerkin product, and the
+// coarsest level's direct solver.  `stored`: the finest level interpolates with stored (caller
+// or learned) weights when they are valid; returns their validity flags (0 when valid or unused).
+static int build_levels(rmg_handle* h, bool stored) {
   const rmg_options& o = h->opt;
   hipStream_t st = h->stream;
   Level* L0 = h->levels[0];
   for (size_t i = 1; i < h->levels.size(); ++i) delete h->levels[i];
   h->levels.resize(1);
-  int64_t f = 1;
-  for (int l = 1; l < o.nlevels; ++l) f *= 3;
-  for (int k = 0; k < L0->nreg; ++k) {
-    const RegionGeo& R = L0->regs[k];
-    const int e[3] = {R.ex, R.ey, R.ez}, g[3] = {R.ox, R.oy, R.oz};
-    for (int d = 0; d < L0->dim; ++d)
-      RMG_REQUIRE((e[d] - 1) % f == 0 && g[d] % f == 0, RMG_ERR_SHAPE,
-                  "region " + std::to_string(k) + ": extent-1 and origin must be divisible by 3^(nlevels-1) = " +
-                      std::to_string(f));
-  }
   const bool lowp = o.precision != RMG_PREC_FP64;
   h->tune_report.clear();
   h->partials.alloc(sizeof(double) * partial_capacity(*L0));
+  int pflags = 0;
   DBuf flag;
   flag.alloc(sizeof(int));
   for (int l = 0; l < o.nlevels; ++l) {
@@ -262,17 +256,70 @@ void setup_hierarchy(rmg_handle* h) {
     RMG_REQUIRE(std::isfinite(L.lambda) && L.lambda > 0.0, RMG_ERR_NUMERIC,
                 "power method failed on level " + std::to_string(l));
     chebyshev_coefficients(o, L);
-    // next level: geometry, then the per-region Galerkin product on the device (FP64)
+    // next level: geometry, interpolation weights, then the per-region Galerkin product (FP64)
     Level* C = make_coarse_level(L);
-    C->coef.alloc(sizeof(double) * coef_elems(C->n, C->ncoef()));
-    launch_rap(L, *C, st);
     h->levels.push_back(C);
+    C->coef.alloc(sizeof(double) * coef_elems(C->n, C->ncoef()));
+    if (l == 0) {
+      if (stored) pflags = prepare_stored_weights(h, L, *C);
+      else L.pw.release();
+    }
+    launch_rap(L, *C, st);
     // the V-cycle's copy of this level's operator, made after the Galerkin product used it
     if (lowp) launch_make_lowp(L, (l == 0 && o.precision == RMG_PREC_FP32_BF16) ? kCoefBF16 : kCoefF32, st);
     if (o.autotune && L.dim == 3 && L.ndof == 1 && L.npts == 27) autotune_level(h, L, l, lowp);
   }
   if (lowp) h->cg_z32.alloc(sizeof(float) * (size_t)L0->ndofs());
   RMG_HIP(hipStreamSynchronize(st));
+  return pflags;
+}
+
+void setup_hierarchy(rmg_handle* h) {
+  const rmg_options& o = h->opt;
+  Level* L0 = h->levels[0];
+  int64_t f = 1;
+  for (int l = 1; l < o.nlevels; ++l) f *= 3;
+  for (int k = 0; k < L0->nreg; ++k) {
+    const RegionGeo& R = L0->regs[k];
+    const int e[3] = {R.ex, R.ey, R.ez}, g[3] = {R.ox, R.oy, R.oz};
+    for (int d = 0; d < L0->dim; ++d)
+      RMG_REQUIRE((e[d] - 1) % f == 0 && g[d] % f == 0, RMG_ERR_SHAPE,
+                  "region " + std::to_string(k) + ": extent-1 and origin must be divisible by 3^(nlevels-1) = " +
+                      std::to_string(f));
+  }
+  const bool stored = h->pmode != RMG_P_GEOMETRIC;
+  RMG_REQUIRE(!stored || (L0->dim == 3 && L0->ndof == 1), RMG_ERR_ARG,
+              "stored or learned interpolation needs a scalar 3D problem");
+  h->p_used = RMG_P_GEOMETRIC;
+  h->rho_learned = h->rho_geometric = -1.0;
+  h->p_flags = build_levels(h, stored);
+  if (stored && h->p_flags == 0) h->p_used = h->pmode;
+  if (h->p_used != RMG_P_LEARNED || o.judge_cycles <= 0) return;
+  // the judge: keep the learned hierarchy only if it converges faster than the geometric one
+  const double rl = convergence_factor(h, o.judge_cycles);
+  std::vector<Level*> learned(h->levels.begin() + 1, h->levels.end());
+  h->levels.resize(1);
+  DBuf pw;
+  pw.swap(L0->pw);
+  try {
+    build_levels(h, false);
+  } catch (...) {
+    for (Level* l : learned) delete l;
+    throw;
+  }
+  const double rg = convergence_factor(h, o.judge_cycles);
+  h->rho_learned = rl;
+  h->rho_geometric = rg;
+  if (rl < rg) {
+    for (size_t i = 1; i < h->levels.size(); ++i) delete h->levels[i];
+    h->levels.resize(1);
+    h->levels.insert(h->levels.end(), learned.begin(), learned.end());
+    L0->pw.swap(pw);
+  } else {
+    for (Level* l : learned) delete l;
+    h->p_used = RMG_P_GEOMETRIC;
+    h->p_flags = RMG_PW_JUDGED_WORSE;
+  }
 }
 
 // Buffers of one level for the FP64 or the FP32 V-cycle.
@@ -315,6 +362,56 @@ void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out)
     cur = 1 - cur;
   }
   if (buf[cur] != u_out) launch_copy(L.ndofs(), (const double*)buf[cur], u_out, st);
+}
+
+void smooth_iterate(rmg_handle* h, int level, const double* b, double* u, double* tmp) {
+  Level& L = *h->levels[level];
+  void* buf[2] = {u, tmp};
+  int cur = 0;
+  for (int k = 0; k < h->opt.cheb_degree; ++k) {
+    cheb_step(h, L, false, k, k == 0, b, buf[cur], buf[1 - cur]);
+    cur = 1 - cur;
+  }
+  if (cur) launch_copy(L.ndofs(), tmp, u, h->stream);
+}
+
+// Counter stream of the start vector of rmg_convergence_factor (power-method streams are the level
+// numbers, training errors 32 + sample).
+constexpr int kRhoStream = 63;
+
+double convergence_factor(rmg_handle* h, int cycles) {
+  Level& L = *h->levels[0];
+  hipStream_t st = h->stream;
+  const int64_t n = L.ndofs();
+  DBuf zero, x, r, z;
+  zero.alloc(sizeof(double) * n);
+  x.alloc(sizeof(double) * n);
+  r.alloc(sizeof(double) * n);
+  z.alloc(sizeof(double) * n);
+  launch_zero(n, zero.as<double>(), st);
+  launch_start_vector(L, kRhoStream, h->opt.seed, x.as<double>(), st);
+  auto residual = [&] {
+    StencilArgs a;
+    a.op = StencilOp::Residual;
+    a.x = x.p;
+    a.out = r.p;
+    a.b = zero.p;
+    launch_stencil_op(L, a, st);
+  };
+  residual();
+  dot(h, L, r.as<double>(), r.as<double>(), kTmp);
+  read_scalars(h);
+  const double r0 = std::sqrt(h->host_scalars[kTmp]);
+  for (int c = 0; c < cycles; ++c) {
+    apply_preconditioner(h, r.as<double>(), z.as<double>());
+    launch_add(n, z.as<double>(), x.as<double>(), st);
+    residual();
+  }
+  dot(h, L, r.as<double>(), r.as<double>(), kTmp);
+  read_scalars(h);
+  const double rk = std::sqrt(h->host_scalars[kTmp]);
+  if (!(r0 > 0.0)) return 0.0;
+  return std::pow(rk / r0, 1.0 / cycles);
 }
 
 void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {

@@ -33,9 +33,16 @@ SYMBOLS = (
     "rmg_apply_vcycle", "rmg_solve", "rmg_to_regional", "rmg_to_composite", "rmg_regional_matvec",
     "rmg_interface_sum", "rmg_restrict", "rmg_prolongate_add", "rmg_smooth", "rmg_level_info",
     "rmg_get_level_stencil", "rmg_get_coarse_matrix", "rmg_profile", "rmg_profile_query",
-    "rmg_tune_report",
+    "rmg_tune_report", "rmg_set_prolongator_weights", "rmg_set_learned_prolongator", "rmg_prolongator_info",
+    "rmg_get_prolongator_weights", "rmg_convergence_factor", "rmg_mlp_create", "rmg_mlp_destroy",
+    "rmg_mlp_set_params", "rmg_mlp_get_params", "rmg_mlp_add_data", "rmg_mlp_add_samples", "rmg_mlp_clear_data",
+    "rmg_mlp_num_data", "rmg_mlp_get_data", "rmg_mlp_forward", "rmg_mlp_loss_grad", "rmg_mlp_adam_step",
+    "rmg_mlp_train",
 )
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
+P_GEOMETRIC, P_STORED, P_LEARNED = 0, 1, 2
+PW_NONFINITE, PW_SUPPORT, PW_DIRICHLET, PW_COPIES, PW_SUM, PW_JUDGED_WORSE = 1, 2, 4, 8, 16, 32
+MLP_NIN, MLP_NHIDDEN, MLP_NOUT, MLP_NPARAM = 27, 64, 208, 19472
 
 
 class Options(ctypes.Structure):
@@ -51,6 +58,7 @@ class Options(ctypes.Structure):
         ("autotune", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("autotune_cache", ctypes.c_char_p),
+        ("judge_cycles", ctypes.c_int),
     ]
 
 
@@ -115,6 +123,25 @@ def load():
         "rmg_profile": (I, [H, I]),
         "rmg_tune_report": (I, [H, ctypes.c_char_p, I]),
         "rmg_profile_query": (I, [H, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D)]),
+        "rmg_set_prolongator_weights": (I, [H, P, I]),
+        "rmg_set_learned_prolongator": (I, [H, P]),
+        "rmg_prolongator_info": (I, [H, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D),
+                                     ctypes.POINTER(D)]),
+        "rmg_get_prolongator_weights": (I, [H, P]),
+        "rmg_convergence_factor": (I, [H, I, ctypes.POINTER(D)]),
+        "rmg_mlp_create": (I, [ctypes.POINTER(H), I, P]),
+        "rmg_mlp_destroy": (I, [H]),
+        "rmg_mlp_set_params": (I, [H, P]),
+        "rmg_mlp_get_params": (I, [H, P]),
+        "rmg_mlp_add_data": (I, [H, ctypes.c_int64, P, P, I]),
+        "rmg_mlp_add_samples": (I, [H, H, I, ctypes.c_uint64, I]),
+        "rmg_mlp_clear_data": (I, [H]),
+        "rmg_mlp_num_data": (I, [H, ctypes.POINTER(ctypes.c_int64)]),
+        "rmg_mlp_get_data": (I, [H, ctypes.c_int64, ctypes.c_int64, P, P]),
+        "rmg_mlp_forward": (I, [H, ctypes.c_int64, P, P, I]),
+        "rmg_mlp_loss_grad": (I, [H, ctypes.POINTER(D), P]),
+        "rmg_mlp_adam_step": (I, [H, P, D]),
+        "rmg_mlp_train": (I, [H, I, D, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -292,3 +319,128 @@ class Handle:
         buf = ctypes.create_string_buffer(8192)
         _check(load().rmg_tune_report(self._h, buf, 8192))
         return buf.value.decode()
+
+    # ------------------------------------------------ stored / learned P
+    def set_prolongator_weights(self, w):
+        """Caller weights [n_regional][8] (numpy or device float64 tensor); None: geometric."""
+        import torch
+
+        if w is None:
+            _check(load().rmg_set_prolongator_weights(self._h, None, 0))
+        elif isinstance(w, torch.Tensor):
+            _check(load().rmg_set_prolongator_weights(self._h, _ptr(w), 1))
+        else:
+            a = np.ascontiguousarray(w, dtype=np.float64)
+            _check(load().rmg_set_prolongator_weights(self._h, a.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def set_learned_prolongator(self, theta):
+        """MLP parameters (RMG_MLP_NPARAM floats) of the learned interpolation; None: geometric."""
+        if theta is None:
+            _check(load().rmg_set_learned_prolongator(self._h, None))
+            return
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        if a.size != MLP_NPARAM:
+            raise ValueError(f"expected {MLP_NPARAM} parameters")
+        _check(load().rmg_set_learned_prolongator(self._h, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def prolongator_info(self):
+        kind, flags, rl, rg = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(load().rmg_prolongator_info(self._h, ctypes.byref(kind), ctypes.byref(flags), ctypes.byref(rl),
+                                           ctypes.byref(rg)))
+        return {"kind": kind.value, "flags": flags.value, "rho_learned": rl.value, "rho_geometric": rg.value}
+
+    def prolongator_weights(self, n_regional):
+        out = np.zeros((n_regional, 8))
+        _check(load().rmg_get_prolongator_weights(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def convergence_factor(self, cycles=10):
+        rho = ctypes.c_double()
+        _check(load().rmg_convergence_factor(self._h, cycles, ctypes.byref(rho)))
+        return rho.value
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Mlp:
+    """Trainer of the learned interpolation's MLP on one HIP device (rmg_mlp_*)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        m = ctypes.c_void_p()
+        _check(lib.rmg_mlp_create(ctypes.byref(m), device, ctypes.c_void_p(stream.cuda_stream)))
+        self._m = m
+
+    def close(self):
+        if getattr(self, "_m", None) is not None and self._m.value:
+            _check(load().rmg_mlp_destroy(self._m))
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        if a.size != MLP_NPARAM:
+            raise ValueError(f"expected {MLP_NPARAM} parameters")
+        _check(load().rmg_mlp_set_params(self._m, _fptr(a)))
+
+    def params(self):
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(load().rmg_mlp_get_params(self._m, _fptr(out)))
+        return out
+
+    def add_data(self, X, E):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, MLP_NIN)
+        E = np.ascontiguousarray(E, dtype=np.float32).reshape(-1, 64)
+        if X.shape[0] != E.shape[0]:
+            raise ValueError("X and E need the same number of rows")
+        _check(load().rmg_mlp_add_data(self._m, X.shape[0], _fptr(X), _fptr(E), 0))
+
+    def add_samples(self, handle: Handle, nsamples, seed, sweeps=20):
+        _check(load().rmg_mlp_add_samples(self._m, handle._h, nsamples, seed, sweeps))
+
+    def clear_data(self):
+        _check(load().rmg_mlp_clear_data(self._m))
+
+    def num_data(self):
+        n = ctypes.c_int64()
+        _check(load().rmg_mlp_num_data(self._m, ctypes.byref(n)))
+        return n.value
+
+    def data(self, first, count):
+        X = np.zeros((count, MLP_NIN), dtype=np.float32)
+        E = np.zeros((count, 64), dtype=np.float32)
+        _check(load().rmg_mlp_get_data(self._m, first, count, _fptr(X), _fptr(E)))
+        return X, E
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, MLP_NIN)
+        Z = np.zeros((X.shape[0], MLP_NOUT), dtype=np.float32)
+        _check(load().rmg_mlp_forward(self._m, X.shape[0], _fptr(X), _fptr(Z), 0))
+        return Z
+
+    def loss_grad(self):
+        loss = ctypes.c_double()
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(load().rmg_mlp_loss_grad(self._m, ctypes.byref(loss), _fptr(g)))
+        return loss.value, g
+
+    def adam_step(self, lr, grad=None):
+        g = None if grad is None else np.ascontiguousarray(grad, dtype=np.float32)
+        _check(load().rmg_mlp_adam_step(self._m, None if g is None else _fptr(g), lr))
+
+    def train(self, steps, lr):
+        hist = np.zeros(max(steps, 1))
+        _check(load().rmg_mlp_train(self._m, steps, lr, _fptr(hist)))
+        return hist[:steps]

@@ -27,6 +27,7 @@ __all__ = [
     "uniform_composite",
     "region_youngs_moduli",
     "jump_coefficients",
+    "mlp_params",
     "batched_extents",
     "dirichlet_nodes",
     "fd5_composite_stencil",
@@ -223,6 +224,19 @@ def jump_coefficients(w: Workload, seed: int | None = None) -> np.ndarray:
         sl = tuple(slice(int(o), int(o + e - 1)) for o, e in zip(reversed(w.origins[k]), reversed(w.extents[k])))
         c[sl] *= 10.0 ** s[k]
     return c
+
+
+def mlp_params(seed: int = 0, out_scale: float = 0.1) -> np.ndarray:
+    """Initial parameters (float32) of a 27 -> 64 -> 64 -> 208 perceptron, flat in the order
+    W1 (64x27), b1, W2 (64x64), b2, W3 (208x64), b3: weights U(-a, a) with a = sqrt(6 / fan_in)
+    (He-uniform; W3 scaled down by ``out_scale``), biases zero."""
+    rng = np.random.Generator(np.random.PCG64([seed, 4]))
+    parts = []
+    for rows, cols, scale in ((64, 27, 1.0), (64, 64, 1.0), (208, 64, out_scale)):
+        a = scale * np.sqrt(6.0 / cols)
+        parts.append(rng.uniform(-a, a, size=rows * cols))
+        parts.append(np.zeros(rows))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def fd5_composite_stencil(w: Workload) -> np.ndarray:
