@@ -311,6 +311,13 @@ typedef struct rmg_mlp rmg_mlp;
  * Parameters start at zero; set them with rmg_mlp_set_params. */
 rmg_status rmg_mlp_create(rmg_mlp** out, int device, void* hip_stream);
 rmg_status rmg_mlp_destroy(rmg_mlp* m);
+/* Initial parameters: hidden weights uniform in +-sqrt(6 / fan_in) and output
+ * weights in +-out_scale sqrt(6 / 64), drawn from the SplitMix64 counter
+ * generator (stream 96 of `seed`, seed < 2^16); zero hidden biases; output
+ * biases log(w) of the trilinear weights w, so that small output weights start
+ * every node at the geometric interpolation.  Resets Adam's state; theta_out
+ * (host [RMG_MLP_NPARAM] or NULL) receives the parameters. */
+rmg_status rmg_mlp_init_params(rmg_mlp* m, uint64_t seed, double out_scale, float* theta_out);
 /* Parameters (host FP32 [RMG_MLP_NPARAM]); setting them resets Adam's state. */
 rmg_status rmg_mlp_set_params(rmg_mlp* m, const float* theta);
 rmg_status rmg_mlp_get_params(rmg_mlp* m, float* theta);

@@ -1,6 +1,7 @@
 // Host side of the stored and learned interpolation: weights for the finest level at setup and
 // their validation, the MLP trainer (data, full-batch loss and gradient, Adam) and the entry
 // points of both.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -184,6 +185,45 @@ static void adam(rmg_mlp* m, double lr) {
   mlp_adam(m->theta.as<float>(), m->grad.as<float>(), m->m.as<float>(), m->v.as<float>(), m->t, lr, m->stream);
 }
 
+// SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014) on a counter; uniform in [-1, 1).
+static double counter_uniform(uint64_t ctr) {
+  uint64_t z = ctr + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return 2.0 * (double)(z >> 11) * 0x1p-53 - 1.0;
+}
+
+// Initial parameters: He-uniform hidden weights, output weights scaled by out_scale, zero hidden
+// biases, and output biases equal to the log of the geometric (trilinear) weights, so that with
+// small output weights every node starts at the geometric interpolation.
+static void init_params(uint64_t seed, double out_scale, float* th) {
+  constexpr uint64_t kStream = 96;  // counter stream of the initial parameters
+  const uint64_t base = (kStream << 40) + (seed << 48);
+  int o = 0;
+  const int rows[3] = {kMlpH, kMlpH, kMlpOut}, cols[3] = {kMlpIn, kMlpH, kMlpH};
+  for (int layer = 0; layer < 3; ++layer) {
+    const double a = (layer == 2 ? out_scale : 1.0) * std::sqrt(6.0 / cols[layer]);
+    for (int i = 0; i < rows[layer] * cols[layer]; ++i, ++o) th[o] = (float)(a * counter_uniform(base + o));
+    if (layer < 2)
+      for (int i = 0; i < rows[layer]; ++i) th[o++] = 0.0f;
+  }
+  CellNode nodes[56];
+  signed char pos2node[64];
+  cell_node_table(nodes, pos2node);
+  for (const CellNode& nd : nodes) {
+    const int p[3] = {nd.pos % 4, (nd.pos / 4) % 4, nd.pos / 16};
+    for (int c = 0; c < nd.ncorner; ++c) {
+      double w = 1.0;
+      for (int d = 0; d < 3; ++d) {
+        const int b = (nd.corner[c] >> d) & 1;
+        w *= b ? p[d] / 3.0 : (3 - p[d]) / 3.0;
+      }
+      th[o + nd.first + c] = (float)std::log(w);
+    }
+  }
+}
+
 extern "C" {
 
 rmg_status rmg_set_prolongator_weights(rmg_handle* h, const double* w, int on_device) {
@@ -296,6 +336,19 @@ rmg_status rmg_mlp_set_params(rmg_mlp* m, const float* theta) {
   RMG_HIP(hipStreamSynchronize(m->stream));
   m->t = 0;
   m->have_grad = false;
+  API_END
+}
+
+rmg_status rmg_mlp_init_params(rmg_mlp* m, uint64_t seed, double out_scale, float* theta_out) {
+  API_BEGIN
+  mlp_use(m);
+  RMG_REQUIRE(out_scale >= 0.0 && std::isfinite(out_scale), RMG_ERR_ARG, "out_scale must be finite and >= 0");
+  RMG_REQUIRE(seed < (1ull << 16), RMG_ERR_ARG, "seed must be below 2^16");
+  std::vector<float> th(kMlpParams);
+  init_params(seed, out_scale, th.data());
+  const rmg_status st = rmg_mlp_set_params(m, th.data());
+  if (st != RMG_OK) return st;
+  if (theta_out) std::copy(th.begin(), th.end(), theta_out);
   API_END
 }
 

@@ -18,7 +18,8 @@ struct CellNode {
   int corner[8];
 };
 
-void mlp_tables();
+// The 56 non-corner nodes of a cell and, per cell position (x fastest), its node or -1 at corners.
+void cell_node_table(CellNode* nodes, signed char* pos2node);
 
 // Z = MLP(X) for n samples; A1, A2 (pre-activations, [n][64]) are stored when non-null.
 void mlp_forward(int64_t n, const float* X, const float* theta, float* Z, float* A1, float* A2, hipStream_t st);

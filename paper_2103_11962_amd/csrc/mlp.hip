@@ -17,19 +17,11 @@
 namespace rmg {
 
 // Non-corner fine nodes of a cell (x-fastest over the 4x4x4 cell nodes): position, number of
-// corners, first logit, corner slots (ix + 2 iy + 4 iz).  Filled on the host.
+// corners, first logit, corner slots (ix + 2 iy + 4 iz).  Filled from cell_node_table.
 __constant__ CellNode c_nodes[56];
 __constant__ signed char c_pos2node[64];  // -1 for the 8 corners
 
-// Once per device (constant memory is per device).
-static void upload_tables() {
-  static bool done[64] = {};
-  int dev = 0;
-  RMG_HIP(hipGetDevice(&dev));
-  RMG_REQUIRE(dev >= 0 && dev < 64, RMG_ERR_ARG, "device index beyond 63");
-  if (done[dev]) return;
-  CellNode nodes[56];
-  signed char pos2node[64];
+void cell_node_table(CellNode* nodes, signed char* pos2node) {
   int n = 0, off = 0;
   for (int k = 0; k < 4; ++k)
     for (int j = 0; j < 4; ++j)
@@ -41,7 +33,8 @@ static void upload_tables() {
         CellNode& nd = nodes[n];
         nd.pos = (k * 4 + j) * 4 + i;
         nd.first = off;
-        int opts[3][2], no[3];
+        // per axis: an interior coordinate (1, 2) interpolates from both corners, 0 / 3 from one
+        int opts[3][2] = {}, no[3];
         for (int d = 0; d < 3; ++d) {
           if (c[d] == 1 || c[d] == 2) {
             opts[d][0] = 0;
@@ -56,17 +49,28 @@ static void upload_tables() {
         for (int iz = 0; iz < no[2]; ++iz)
           for (int iy = 0; iy < no[1]; ++iy)
             for (int ix = 0; ix < no[0]; ++ix) nd.corner[nc++] = opts[0][ix] + 2 * opts[1][iy] + 4 * opts[2][iz];
+        for (int q = nc; q < 8; ++q) nd.corner[q] = 0;
         nd.ncorner = nc;
         off += nc;
         ++n;
       }
   RMG_REQUIRE(n == 56 && off == kMlpOut, RMG_ERR_ARG, "internal: cell node table");
+}
+
+// Once per device (constant memory is per device).
+static void upload_tables() {
+  static bool done[64] = {};
+  int dev = 0;
+  RMG_HIP(hipGetDevice(&dev));
+  RMG_REQUIRE(dev >= 0 && dev < 64, RMG_ERR_ARG, "device index beyond 63");
+  if (done[dev]) return;
+  CellNode nodes[56];
+  signed char pos2node[64];
+  cell_node_table(nodes, pos2node);
   RMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_nodes), nodes, sizeof(nodes)));
   RMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_pos2node), pos2node, sizeof(pos2node)));
   done[dev] = true;
 }
-
-void mlp_tables() { upload_tables(); }
 
 // ------------------------------------------------------------------ forward
 // Parameter layout: W1 [64][27], b1 [64], W2 [64][64], b2 [64], W3 [208][64], b3 [208].

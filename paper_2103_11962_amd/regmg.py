@@ -37,7 +37,7 @@ SYMBOLS = (
     "rmg_get_prolongator_weights", "rmg_convergence_factor", "rmg_mlp_create", "rmg_mlp_destroy",
     "rmg_mlp_set_params", "rmg_mlp_get_params", "rmg_mlp_add_data", "rmg_mlp_add_samples", "rmg_mlp_clear_data",
     "rmg_mlp_num_data", "rmg_mlp_get_data", "rmg_mlp_forward", "rmg_mlp_loss_grad", "rmg_mlp_adam_step",
-    "rmg_mlp_train",
+    "rmg_mlp_train", "rmg_mlp_init_params",
 )
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
 P_GEOMETRIC, P_STORED, P_LEARNED = 0, 1, 2
@@ -142,6 +142,7 @@ def load():
         "rmg_mlp_loss_grad": (I, [H, ctypes.POINTER(D), P]),
         "rmg_mlp_adam_step": (I, [H, P, D]),
         "rmg_mlp_train": (I, [H, I, D, P]),
+        "rmg_mlp_init_params": (I, [H, ctypes.c_uint64, D, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -394,6 +395,11 @@ class Mlp:
         if a.size != MLP_NPARAM:
             raise ValueError(f"expected {MLP_NPARAM} parameters")
         _check(load().rmg_mlp_set_params(self._m, _fptr(a)))
+
+    def init_params(self, seed=0, out_scale=0.01):
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(load().rmg_mlp_init_params(self._m, seed, out_scale, _fptr(out)))
+        return out
 
     def params(self):
         out = np.zeros(MLP_NPARAM, dtype=np.float32)
