@@ -141,6 +141,7 @@ struct Level {
   DBuf coef;
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
   DBuf pw;        // stored interpolation weights to the next level, double [n][8] (null: geometric)
+  DBuf rw;        // with pw: the same weights per coarse node (125 taps, wave-tiled) for the restriction
   double lambda = 0.0;
   std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step: direction and residual factors
   // work vectors (regional): b (rhs), u / u2 (ping-pong), d (Chebyshev direction), r (residual)

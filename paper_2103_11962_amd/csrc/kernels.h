@@ -53,6 +53,8 @@ void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv
 void launch_restrict(const Level& F, const Level& C, bool lowp, const void* r_scaled, void* w, hipStream_t st);
 // Prolongation u += P ubar (level+1 -> level).
 void launch_prolong_add(const Level& F, const Level& C, bool lowp, const void* ubar, void* u, hipStream_t st);
+// Coarse-major restriction weights (F.rw, 125 per coarse node) from the stored weights F.pw.
+void launch_build_rw(const Level& F, const Level& C, double* rw, hipStream_t st);
 // Galerkin product per region (FP64): C.coef = R A P.
 void launch_rap(const Level& F, Level& C, hipStream_t st);
 

@@ -305,9 +305,9 @@ __device__ __forceinline__ double pweight(const double* __restrict__ pw, const R
 // One thread per coarse node: w = sum_f P_fC r_f over the fine nodes of the same region within
 // two fine cells per axis (r already divided by multiplicity), per dof.  Coarse Dirichlet nodes
 // receive nothing (free fine nodes do not interpolate from them).
-template <int DIM, int NDOF, class V, bool STORED>
+template <int DIM, int NDOF, class V>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, const V* __restrict__ r,
-                                                     V* __restrict__ w, const double* __restrict__ pw) {
+                                                     V* __restrict__ w) {
   const BlockDesc bd = C.blocks[blockIdx.x];
   const RegionGeo RC = C.regs[bd.region];
   const RegionGeo RF = F.regs[bd.region];
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, c
         for (int tx = -2; tx <= 2; ++tx) {
           const int fx = 3 * X + tx;
           if ((unsigned)fx >= (unsigned)RF.ex) continue;
-          const V wt = STORED ? (V)pweight(pw, RF, RC, fx, fy, fz, X, Y, Z) : (V)(wzy * w1(tx));
+          const V wt = (V)(wzy * w1(tx));
 #pragma unroll
           for (int a = 0; a < NDOF; ++a) acc[a] += wt * rr[(int64_t)(base + fx) * NDOF + a];
         }
@@ -346,23 +346,87 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, c
   for (int a = 0; a < NDOF; ++a) w[gi * NDOF + a] = acc[a];
 }
 
+// Stored interpolation, coarse-major copy of the restriction weights: for every coarse node C the
+// 125 weights P(3C + t, C), t in [-2, 2]^3 (slot (tz+2)*25 + (ty+2)*5 + tx+2), wave-tiled like the
+// stencil coefficients so that the restriction streams them instead of gathering single slots of
+// the fine nodes' weight records.  Zero outside the region box.
+constexpr int kRestrictTaps = 125;
+
+__global__ __launch_bounds__(kBlock) void k_build_rw(LevelView F, LevelView C, const double* __restrict__ pw,
+                                                     double* __restrict__ rw) {
+  const BlockDesc bd = C.blocks[blockIdx.x];
+  const RegionGeo RC = C.regs[bd.region];
+  const RegionGeo RF = F.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= RC.n) return;
+  int X, Y, Z;
+  decompose(RC, li, X, Y, Z);
+  const int64_t gi = RC.off + li;
+  for (int t = 0; t < kRestrictTaps; ++t) {
+    const int fx = 3 * X + t % 5 - 2, fy = 3 * Y + (t / 5) % 5 - 2, fz = 3 * Z + t / 25 - 2;
+    const bool in = (unsigned)fx < (unsigned)RF.ex && (unsigned)fy < (unsigned)RF.ey && (unsigned)fz < (unsigned)RF.ez;
+    rw[coef_index(gi, t, kRestrictTaps)] = in ? pweight(pw, RF, RC, fx, fy, fz, X, Y, Z) : 0.0;
+  }
+}
+
+void launch_build_rw(const Level& F, const Level& C, double* rw, hipStream_t st) {
+  hipLaunchKernelGGL(k_build_rw, dim3(C.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), F.pw.as<double>(),
+                     rw);
+  LAUNCH_CHECK();
+}
+
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_restrict_rw(LevelView F, LevelView C, const V* __restrict__ r,
+                                                        V* __restrict__ w, const double* __restrict__ rw) {
+  const BlockDesc bd = C.blocks[blockIdx.x];
+  const RegionGeo RC = C.regs[bd.region];
+  const RegionGeo RF = F.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= RC.n) return;
+  int X, Y, Z;
+  decompose(RC, li, X, Y, Z);
+  const int64_t gi = RC.off + li;
+  V acc = (V)0;
+  if (!is_dirichlet(C, RC.ox + X, RC.oy + Y, RC.oz + Z)) {
+    const V* __restrict__ rr = r + RF.off;
+    const double* __restrict__ wt = rw + coef_index(gi, 0, kRestrictTaps);  // slot t at wt[t * 64]
+    for (int tz = -2; tz <= 2; ++tz) {
+      const int fz = 3 * Z + tz;
+      if ((unsigned)fz >= (unsigned)RF.ez) continue;
+      for (int ty = -2; ty <= 2; ++ty) {
+        const int fy = 3 * Y + ty;
+        if ((unsigned)fy >= (unsigned)RF.ey) continue;
+        const int base = (fz * RF.ey + fy) * RF.ex;
+        const int t0 = (tz + 2) * 25 + (ty + 2) * 5;
+#pragma unroll
+        for (int tx = -2; tx <= 2; ++tx) {
+          const int fx = 3 * X + tx;
+          if ((unsigned)fx >= (unsigned)RF.ex) continue;
+          acc += (V)wt[(t0 + tx + 2) * kTile] * rr[base + fx];
+        }
+      }
+    }
+  }
+  w[gi] = acc;
+}
+
 template <int NDOF, class V>
 static void restrict_t(const Level& F, const Level& C, const V* r, V* w, hipStream_t st) {
   const double* pw = F.pw.as<double>();
   const dim3 g(C.blocks.size()), b(kBlock);
   if constexpr (NDOF == 1) {
     if (pw) {
-      RMG_REQUIRE(F.dim == 3, RMG_ERR_ARG, "stored interpolation weights need a 3D level");
-      hipLaunchKernelGGL((k_restrict<3, 1, V, true>), g, b, 0, st, F.view(), C.view(), r, w, pw);
+      RMG_REQUIRE(F.dim == 3 && F.rw.p, RMG_ERR_ARG, "stored interpolation weights need a 3D level");
+      hipLaunchKernelGGL((k_restrict_rw<V>), g, b, 0, st, F.view(), C.view(), r, w, F.rw.as<double>());
       LAUNCH_CHECK();
       iface_sum_inplace<V>(C, w, st);
       return;
     }
   }
   if (F.dim == 3)
-    hipLaunchKernelGGL((k_restrict<3, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), r, w, pw);
+    hipLaunchKernelGGL((k_restrict<3, NDOF, V>), g, b, 0, st, F.view(), C.view(), r, w);
   else
-    hipLaunchKernelGGL((k_restrict<2, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), r, w, pw);
+    hipLaunchKernelGGL((k_restrict<2, NDOF, V>), g, b, 0, st, F.view(), C.view(), r, w);
   LAUNCH_CHECK();
   iface_sum_inplace<V>(C, w, st);
 }
@@ -466,7 +530,8 @@ void launch_prolong_add(const Level& F, const Level& C, bool lowp, const void* u
 // Dirichlet coarse nodes are zero.
 template <int NPTSF, int DIM, int NDOF, int BS, bool STORED>
 __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const double* __restrict__ coefF,
-                                            double* __restrict__ coefC, const double* __restrict__ pw) {
+                                            double* __restrict__ coefC, const double* __restrict__ pw,
+                                            const double* __restrict__ rw) {
   constexpr int NC = DIM == 3 ? 27 : 9;
   constexpr int NB = NDOF * NDOF;
   constexpr int SUB = kBlock / BS;
@@ -493,7 +558,7 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
         const int fx = 3 * X + tx;
         if ((unsigned)fx >= (unsigned)RF.ex) continue;
         if (cdir && !is_dirichlet(F, RF.ox + fx, RF.oy + fy, RF.oz + fz)) continue;
-        const double wf = STORED ? pweight(pw, RF, RC, fx, fy, fz, X, Y, Z)
+        const double wf = STORED ? rw[coef_index(RC.off + li, (tz + 2) * 25 + (ty + 2) * 5 + tx + 2, 125)]
                                  : (DIM == 3 ? w1(tz) : 1.0) * w1(ty) * w1(tx);
         if (wf == 0.0) continue;
         const int64_t fi = RF.off + (fz * RF.ey + fy) * RF.ex + fx;
@@ -561,24 +626,28 @@ void launch_rap(const Level& F, Level& C, hipStream_t st) {
   const double* cf = F.coef.as<double>();
   double* cc = C.coef.as<double>();
   const double* pw = F.pw.as<double>();
-  RMG_REQUIRE(!pw || (F.dim == 3 && F.ndof == 1), RMG_ERR_ARG, "stored interpolation weights need a scalar 3D level");
+  const double* rw = F.rw.as<double>();
+  RMG_REQUIRE(!pw || (F.dim == 3 && F.ndof == 1 && rw), RMG_ERR_ARG,
+              "stored interpolation weights need a scalar 3D level");
   if (F.ndof == 3) {
     RMG_REQUIRE(F.npts == 27, RMG_ERR_ARG, "3D levels need 27-point stencils");
     constexpr int BS = 32;
     hipLaunchKernelGGL((k_rap<27, 3, 3, BS, false>), dim3(C.blocks.size() * (kBlock / BS)), dim3(BS), 0, st, fv, cv,
-                       cf, cc, pw);
+                       cf, cc, pw, rw);
   } else if (F.dim == 3) {
     RMG_REQUIRE(F.npts == 27, RMG_ERR_ARG, "3D levels need 27-point stencils");
     if (pw)
       hipLaunchKernelGGL((k_rap<27, 3, 1, kBlock, true>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc,
-                         pw);
+                         pw, rw);
     else
       hipLaunchKernelGGL((k_rap<27, 3, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc,
-                         pw);
+                         pw, rw);
   } else if (F.npts == 9) {
-    hipLaunchKernelGGL((k_rap<9, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw);
+    hipLaunchKernelGGL((k_rap<9, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw,
+                       rw);
   } else {
-    hipLaunchKernelGGL((k_rap<5, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw);
+    hipLaunchKernelGGL((k_rap<5, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw,
+                       rw);
   }
   LAUNCH_CHECK();
 }

@@ -98,9 +98,16 @@ static void learned_weights_of(rmg_handle* h, Level& F, const Level& C) {
   RMG_HIP(hipStreamSynchronize(st));  // before the temporaries are freed
 }
 
+// Coarse-major restriction copy of valid stored weights.
+static void build_restriction_weights(rmg_handle* h, Level& F, const Level& C) {
+  F.rw.alloc(sizeof(double) * coef_elems(C.n, 125));
+  launch_build_rw(F, C, F.rw.as<double>(), h->stream);
+}
+
 int prepare_stored_weights(rmg_handle* h, Level& F, const Level& C) {
   const size_t bytes = sizeof(double) * 8 * (size_t)F.n;
   F.pw.alloc(bytes);
+  F.rw.release();
   if (h->pmode == RMG_P_STORED) {
     RMG_REQUIRE(h->user_pw.bytes == bytes, RMG_ERR_ARG, "stored interpolation weights do not match the finest level");
     RMG_HIP(hipMemcpyAsync(F.pw.p, h->user_pw.p, bytes, hipMemcpyDeviceToDevice, h->stream));
@@ -109,11 +116,13 @@ int prepare_stored_weights(rmg_handle* h, Level& F, const Level& C) {
       F.pw.release();
       fail(RMG_ERR_ARG, "stored interpolation weights are invalid (flags " + std::to_string(flags) + ")");
     }
+    build_restriction_weights(h, F, C);
     return 0;
   }
   learned_weights_of(h, F, C);
   const int flags = validate_weights(h, F, C);
   if (flags) F.pw.release();  // fall back to the geometric interpolation
+  else build_restriction_weights(h, F, C);
   return flags;
 }
 
@@ -141,8 +150,6 @@ static void reserve_data(rmg_mlp* m, int64_t need) {
   m->cap = cap;
 }
 
-static int chunks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, (n + 2047) / 2048)); }
-
 static void reserve_work(rmg_mlp* m, int64_t n, int64_t nloss) {
   if (n > m->wcap) {
     m->Z.alloc(sizeof(float) * kMlpOut * (size_t)n);
@@ -152,7 +159,7 @@ static void reserve_work(rmg_mlp* m, int64_t n, int64_t nloss) {
     m->D1.alloc(sizeof(float) * kMlpH * (size_t)n);
     m->D2.alloc(sizeof(float) * kMlpH * (size_t)n);
     m->partials.alloc(sizeof(double) * (size_t)((n + kBlock - 1) / kBlock + 1));
-    m->part.alloc(sizeof(double) * (size_t)chunks_for(n) * kMlpOut * (kMlpH + 1));
+    if (!m->part.p) m->part.alloc(sizeof(float) * (size_t)mlp_grad_partials());
     m->wcap = n;
   }
   if (nloss > m->loss_cap) {
@@ -176,7 +183,7 @@ static void loss_grad(rmg_mlp* m, int slot) {
   const int64_t np = mlp_loss(n, Z, m->E.as<float>(), dZ, m->partials.as<double>(), st);
   launch_reduce(m->partials.as<double>(), np, m->losses.as<double>(), slot, st);
   mlp_backact(n, dZ, A1, A2, m->theta.as<float>(), D1, D2, st);
-  mlp_weight_grads(n, X, A1, A2, dZ, D1, D2, m->grad.as<float>(), m->part.as<double>(), chunks_for(n), st);
+  mlp_weight_grads(n, X, A1, A2, dZ, D1, D2, m->grad.as<float>(), m->part.as<float>(), st);
   m->have_grad = true;
 }
 

@@ -29,9 +29,10 @@ int64_t mlp_loss(int64_t n, const float* Z, const float* E, float* dZ, double* p
 void mlp_backact(int64_t n, const float* dZ, const float* A1, const float* A2, const float* theta, float* D1,
                  float* D2, hipStream_t st);
 // Weight gradients (flat, parameter order) from the activation gradients; part holds
-// nchunk * 208 * 65 doubles.
+// mlp_grad_partials() floats.
+int64_t mlp_grad_partials();
 void mlp_weight_grads(int64_t n, const float* X, const float* A1, const float* A2, const float* dZ, const float* D1,
-                      const float* D2, float* grad, double* part, int nchunk, hipStream_t st);
+                      const float* D2, float* grad, float* part, hipStream_t st);
 // Adam step t (from 1).
 void mlp_adam(float* theta, const float* grad, float* m, float* v, int t, double lr, hipStream_t st);
 

@@ -9,6 +9,7 @@
 // weight gradients (fixed summation order, so gradients are deterministic).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_common.h"
@@ -204,36 +205,83 @@ __global__ __launch_bounds__(kBlock) void k_mlp_backact(int64_t n, const float* 
   }
 }
 
-// Partial weight gradients over a chunk of samples: for output row r,
-// P[chunk][r][j] = sum_n D[n][r] H[n][j] (j < C, with H = ReLU(A) when relu), P[..][C] = sum_n D[n][r].
-__global__ __launch_bounds__(128) void k_mlp_outer(int64_t n, int R, int C, const float* __restrict__ D,
-                                                   const float* __restrict__ H, int relu, int64_t chunk,
-                                                   double* __restrict__ P) {
-  const int r = blockIdx.x, ch = blockIdx.y, j = threadIdx.x;
-  if (j > C) return;
-  const int64_t n0 = (int64_t)ch * chunk, n1 = min(n, n0 + chunk);
-  double acc = 0.0;
-  for (int64_t s = n0; s < n1; ++s) {
-    const float d = D[s * R + r];
-    if (j < C) {
-      float h = H[s * C + j];
-      if (relu) h = h > 0.f ? h : 0.f;
-      acc += (double)(d * h);
-    } else {
-      acc += (double)d;
-    }
+// Weight gradients of one layer over a slice of samples, a small GEMM with a long reduction
+// dimension: G[r][j] = sum_s D[s][r] H'[s][j] for j < C (H' = ReLU(H) when relu) and
+// G[r][C] = sum_s D[s][r] (bias).  Tiles of kWgS samples are staged through LDS; each thread
+// keeps an MR x MC register tile of G with rows r = tr + i TR and columns j = tc + k TC, so the
+// lanes of a wavefront read 16 consecutive rows and 4 columns (broadcasts, no bank conflicts).
+// One FP32 partial per block; the partials are summed in FP64 in block order.
+constexpr int kWgS = 32;     // samples per LDS tile
+constexpr int kWgBlocks = 512;
+
+template <int R, int C, int MR, int MC>
+__global__ __launch_bounds__(256) void k_mlp_wgrad(int64_t n, const float* __restrict__ D,
+                                                   const float* __restrict__ H, int relu, int64_t per_block,
+                                                   float* __restrict__ part) {
+  constexpr int TR = R / MR, TC = 256 / TR, CP = MC * TC;
+  static_assert(TR * MR == R && TR * TC == 256 && CP >= C, "tile shape");
+  __shared__ float sD[kWgS][R];
+  __shared__ float sH[kWgS][CP];
+  const int tr = threadIdx.x % TR, tc = threadIdx.x / TR;
+  float acc[MR][MC], accb[MR];
+#pragma unroll
+  for (int i = 0; i < MR; ++i) {
+    accb[i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) acc[i][k] = 0.f;
   }
-  P[((int64_t)ch * R + r) * (C + 1) + j] = acc;
+  const int64_t s0 = (int64_t)blockIdx.x * per_block, s1 = min(n, s0 + per_block);
+  for (int64_t t0 = s0; t0 < s1; t0 += kWgS) {
+    const int ns = (int)min((int64_t)kWgS, s1 - t0);
+    // rows of D and H are contiguous: the tile is one contiguous span of each
+    for (int idx = threadIdx.x; idx < kWgS * R; idx += 256) {
+      const int s = idx / R;
+      sD[s][idx - s * R] = s < ns ? D[t0 * R + idx] : 0.f;
+    }
+    for (int idx = threadIdx.x; idx < kWgS * CP; idx += 256) {
+      const int s = idx / CP, j = idx - s * CP;
+      float v = (s < ns && j < C) ? H[(t0 + s) * C + j] : 0.f;
+      if (relu) v = v > 0.f ? v : 0.f;
+      sH[s][j] = v;
+    }
+    __syncthreads();
+    for (int s = 0; s < kWgS; ++s) {
+      float d[MR], h[MC];
+#pragma unroll
+      for (int i = 0; i < MR; ++i) d[i] = sD[s][tr + i * TR];
+#pragma unroll
+      for (int k = 0; k < MC; ++k) h[k] = sH[s][tc + k * TC];
+#pragma unroll
+      for (int i = 0; i < MR; ++i) {
+        accb[i] += d[i];
+#pragma unroll
+        for (int k = 0; k < MC; ++k) acc[i][k] += d[i] * h[k];
+      }
+    }
+    __syncthreads();
+  }
+  float* out = part + (int64_t)blockIdx.x * R * (C + 1);
+#pragma unroll
+  for (int i = 0; i < MR; ++i) {
+    const int r = tr + i * TR;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+      const int j = tc + k * TC;
+      if (j < C) out[r * (C + 1) + j] = acc[i][k];
+    }
+    if (tc == 0) out[r * (C + 1) + C] = accb[i];
+  }
 }
 
-// Sum the chunk partials into the flat gradient: W block at wofs (row-major R x C), bias at bofs.
-__global__ void k_mlp_outer_reduce(int R, int C, int nchunk, const double* __restrict__ P, float* __restrict__ grad,
+// Sum the block partials into the flat gradient: W block at wofs (row-major R x C), bias at bofs.
+__global__ void k_mlp_wgrad_reduce(int R, int C, int nblk, const float* __restrict__ part, float* __restrict__ grad,
                                    int wofs, int bofs) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= R * (C + 1)) return;
+  const int per = R * (C + 1);
+  if (t >= per) return;
   const int r = t / (C + 1), j = t - r * (C + 1);
   double s = 0.0;
-  for (int ch = 0; ch < nchunk; ++ch) s += P[((int64_t)ch * R + r) * (C + 1) + j];
+  for (int b = 0; b < nblk; ++b) s += (double)part[(int64_t)b * per + t];
   if (j < C) grad[wofs + r * C + j] = (float)s;
   else grad[bofs + r] = (float)s;
 }
@@ -271,27 +319,30 @@ void mlp_backact(int64_t n, const float* dZ, const float* A1, const float* A2, c
   LAUNCH_CHECK();
 }
 
+int64_t mlp_grad_partials() { return (int64_t)kWgBlocks * kMlpOut * (kMlpH + 1); }
+
 void mlp_weight_grads(int64_t n, const float* X, const float* A1, const float* A2, const float* dZ, const float* D1,
-                      const float* D2, float* grad, double* part, int nchunk, hipStream_t st) {
-  const int64_t chunk = cdiv(n, nchunk);
+                      const float* D2, float* grad, float* part, hipStream_t st) {
+  // samples per block: a whole number of LDS tiles, at most kWgBlocks blocks
+  const int64_t per_block = cdiv(cdiv(n, std::min<int64_t>(kWgBlocks, cdiv(n, 256))), kWgS) * kWgS;
+  const int nblk = (int)cdiv(n, per_block);
   const int ofs_b1 = kMlpH * kMlpIn, ofs_W2 = ofs_b1 + kMlpH, ofs_b2 = ofs_W2 + kMlpH * kMlpH,
             ofs_W3 = ofs_b2 + kMlpH, ofs_b3 = ofs_W3 + kMlpOut * kMlpH;
-  struct Job {
-    int R, C;
-    const float* D;
-    const float* H;
-    int relu, wofs, bofs;
-  } jobs[3] = {{kMlpOut, kMlpH, dZ, A2, 1, ofs_W3, ofs_b3},
-               {kMlpH, kMlpH, D2, A1, 1, ofs_W2, ofs_b2},
-               {kMlpH, kMlpIn, D1, X, 0, 0, ofs_b1}};
-  for (const Job& j : jobs) {
-    hipLaunchKernelGGL(k_mlp_outer, dim3(j.R, nchunk), dim3(128), 0, st, n, j.R, j.C, j.D, j.H, j.relu, chunk, part);
+  auto reduce = [&](int R, int C, int wofs, int bofs) {
+    hipLaunchKernelGGL(k_mlp_wgrad_reduce, dim3(cdiv(R * (C + 1), kBlock)), dim3(kBlock), 0, st, R, C, nblk, part,
+                       grad, wofs, bofs);
     LAUNCH_CHECK();
-    const int tot = j.R * (j.C + 1);
-    hipLaunchKernelGGL(k_mlp_outer_reduce, dim3(cdiv(tot, kBlock)), dim3(kBlock), 0, st, j.R, j.C, nchunk, part, grad,
-                       j.wofs, j.bofs);
-    LAUNCH_CHECK();
-  }
+  };
+  hipLaunchKernelGGL((k_mlp_wgrad<kMlpOut, kMlpH, 13, 4>), dim3(nblk), dim3(256), 0, st, n, dZ, A2, 1, per_block,
+                     part);
+  LAUNCH_CHECK();
+  reduce(kMlpOut, kMlpH, ofs_W3, ofs_b3);
+  hipLaunchKernelGGL((k_mlp_wgrad<kMlpH, kMlpH, 4, 4>), dim3(nblk), dim3(256), 0, st, n, D2, A1, 1, per_block, part);
+  LAUNCH_CHECK();
+  reduce(kMlpH, kMlpH, ofs_W2, ofs_b2);
+  hipLaunchKernelGGL((k_mlp_wgrad<kMlpH, kMlpIn, 4, 2>), dim3(nblk), dim3(256), 0, st, n, D1, X, 0, per_block, part);
+  LAUNCH_CHECK();
+  reduce(kMlpH, kMlpIn, 0, ofs_b1);
 }
 
 void mlp_adam(float* theta, const float* grad, float* m, float* v, int t, double lr, hipStream_t st) {

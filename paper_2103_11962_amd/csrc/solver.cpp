@@ -261,8 +261,12 @@ static int build_levels(rmg_handle* h, bool stored) {
     h->levels.push_back(C);
     C->coef.alloc(sizeof(double) * coef_elems(C->n, C->ncoef()));
     if (l == 0) {
-      if (stored) pflags = prepare_stored_weights(h, L, *C);
-      else L.pw.release();
+      if (stored) {
+        pflags = prepare_stored_weights(h, L, *C);
+      } else {
+        L.pw.release();
+        L.rw.release();
+      }
     }
     launch_rap(L, *C, st);
     // the V-cycle's copy of this level's operator, made after the Galerkin product used it
@@ -299,8 +303,9 @@ void setup_hierarchy(rmg_handle* h) {
   const double rl = convergence_factor(h, o.judge_cycles);
   std::vector<Level*> learned(h->levels.begin() + 1, h->levels.end());
   h->levels.resize(1);
-  DBuf pw;
+  DBuf pw, rw;
   pw.swap(L0->pw);
+  rw.swap(L0->rw);
   try {
     build_levels(h, false);
   } catch (...) {
@@ -315,6 +320,7 @@ void setup_hierarchy(rmg_handle* h) {
     h->levels.resize(1);
     h->levels.insert(h->levels.end(), learned.begin(), learned.end());
     L0->pw.swap(pw);
+    L0->rw.swap(rw);
   } else {
     for (Level* l : learned) delete l;
     h->p_used = RMG_P_GEOMETRIC;
