@@ -75,6 +75,215 @@ def cpu_baseline(gpu_iterations: int, n_rows: int, its: int = 3):
     }
 
 
+# Algorithmic bytes per regional node of the finest-level fused Chebyshev step (stencil product,
+# residual, direction and iterate update): coefficients once, u, b, D~^-1, d read, d, u written.
+CHEB_BYTES = {
+    ("scalar", 0): 27 * 8 + 6 * 8,             # FP64: 264
+    ("scalar", 1): 27 * 4 + 6 * 4,             # FP32 coefficients and vectors: 132
+    ("block3", 0): 27 * 9 * 8 + 6 * 3 * 8,     # elasticity FP64: 2088
+    ("block3", 1): 27 * 9 * 4 + 6 * 3 * 4,     # FP32: 1044
+    ("block3", 2): 26 * 9 * 2 + 9 * 4 + 6 * 3 * 4,  # BF16 off-diagonal blocks, FP32 centre block: 576
+}
+PREC_NAME = {0: "fp64", 1: "fp32", 2: "fp32_bf16"}
+
+
+def _handle(w, dev):
+    """Regions and finest operator of workload w on the device (device assembly)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2103_11962_amd import regmg
+
+    h = regmg.Handle(0)
+    h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
+    if w.pde == "fd5":
+        h.set_composite_stencil(5, synth.fd5_composite_stencil(w))
+    elif w.pde == "elasticity":
+        h.assemble_q1(regmg.PDE_ELASTICITY, w.h, youngs=synth.region_youngs_moduli(w), nu=w.nu)
+    elif w.pde == "diffusion":
+        ec = torch.from_numpy(np.ascontiguousarray(synth.jump_coefficients(w)).reshape(-1)).to(dev)
+        h.assemble_q1(regmg.PDE_DIFFUSION, w.h, elem_coef=ec)
+        h._keep = ec
+    else:
+        h.assemble_q1(regmg.PDE_LAPLACE, w.h)
+    return h
+
+
+def _timed_solves(h, b, reps=2, **kw):
+    """Warm-up solve, then `reps` timed solves; median solve time and the last result."""
+    import numpy as np
+    import torch
+
+    x = torch.zeros_like(b)
+    h.solve(b, x, rtol=1e-8, maxit=400, **kw)
+    outs = []
+    for _ in range(reps):
+        x.zero_()
+        outs.append(h.solve(b, x, rtol=1e-8, maxit=400, **kw))
+    return float(np.median([o["solve_ms"] for o in outs])), outs[-1], x
+
+
+def _setup(h, w, **opts):
+    import torch
+
+    t0 = time.perf_counter()
+    h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree, **opts)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3
+
+
+def _cheb_gbs(h, kind, precision, rows):
+    from paper_2103_11962_amd import regmg
+
+    n, ms = h.profile_query(regmg.TIMED_CHEB)
+    if n == 0:
+        return None
+    return CHEB_BYTES[(kind, precision)] * rows / (ms / n * 1e-3) / 1e9
+
+
+def variant_mixed(dev):
+    """Elasticity 3x3x3 regions of 55^3: FP64 V-cycle vs FP32 vs FP32 with BF16 coefficients."""
+    import numpy as np
+
+    import synth
+
+    w = synth.workload("c3")
+    b = _to_dev(synth.rhs(w), dev)
+    out, x64 = {}, None
+    for prec in (0, 1, 2):
+        h = _handle(w, dev)
+        setup_ms = _setup(h, w, precision=prec)
+        rows = h.level_info(0)["n_regional"] // 3
+        h.profile(True)
+        ms, res, x = _timed_solves(h, b)
+        entry = {"setup_ms": setup_ms, "solve_ms": ms, "iterations": res["iterations"],
+                 "true_relres": res["true_relres"],
+                 "cheb_gbs": _cheb_gbs(h, "block3", prec, rows),
+                 "cheb_bytes_per_node": CHEB_BYTES[("block3", prec)]}
+        if prec == 0:
+            x64 = x.clone()
+        else:
+            entry["x_rel_diff_vs_fp64"] = float((x - x64).norm() / x64.norm())
+        out[PREC_NAME[prec]] = entry
+        h.close()
+        print(f"[bench] mixed {PREC_NAME[prec]}: {ms:.1f} ms, {res['iterations']} its", file=sys.stderr, flush=True)
+    out["speedup_fp32_bf16_vs_fp64"] = out["fp64"]["solve_ms"] / out["fp32_bf16"]["solve_ms"]
+    out["workload"] = ("3D Q1 elasticity, 3x3x3 regions of 55^3 nodes (3 dofs/node), E lognormal per region, "
+                       "nu 0.3, 4-level V-cycle, Chebyshev degree 3, PCG to 1e-8 (flexible in FP32/BF16)")
+    return out
+
+
+def variant_batched(dev):
+    """256 uneven regions: one persistent autotuned launch per step with graph-captured CG
+    iterations vs one launch per region, both with the FP32 V-cycle."""
+    import tempfile
+
+    import synth
+
+    w = synth.workload("c4")
+    b = _to_dev(synth.rhs(w), dev)
+    out = {}
+    cache = os.path.join(tempfile.gettempdir(), "regmg_bench_tune.txt")
+    for name, opts in (("region_by_region", dict(precision=1, batched=0)),
+                       ("batched", dict(precision=1, autotune=1, autotune_cache=cache, use_graph=1))):
+        h = _handle(w, dev)
+        setup_ms = _setup(h, w, **opts)
+        rows = h.level_info(0)["n_regional"]
+        h.profile(True)
+        ms, res, _ = _timed_solves(h, b)
+        out[name] = {"setup_ms": setup_ms, "solve_ms": ms, "iterations": res["iterations"],
+                     "true_relres": res["true_relres"], "cheb_gbs": _cheb_gbs(h, "scalar", 1, rows)}
+        if name == "batched":
+            out[name]["tuning"] = h.tune_report().strip().splitlines()
+        h.close()
+        print(f"[bench] batched {name}: {ms:.1f} ms, {res['iterations']} its", file=sys.stderr, flush=True)
+    out["regional_rows"] = rows
+    out["speedup_batched_vs_region_by_region"] = out["region_by_region"]["solve_ms"] / out["batched"]["solve_ms"]
+    out["workload"] = ("3D Q1 Laplacian, 8x8x4 regions with slab extents from {28,55,82,109} (seed 0), "
+                       "4-level FP32 V-cycle inside FP64 CG to 1e-8")
+    return out
+
+
+def variant_learned(dev, train_steps=400):
+    """Jump-coefficient diffusion 4x4x4 regions of 82^3: geometric vs learned interpolation (MLP
+    trained on the device on 8 other seeds of a 2x2x2-region 28^3 version)."""
+    import torch
+
+    import synth
+    from paper_2103_11962_amd import regmg
+
+    t0 = time.perf_counter()
+    m = regmg.Mlp(0)
+    for s in range(1, 9):
+        ws = synth.workload("c5_small", seed=s)
+        hs = _handle(ws, dev)
+        hs.setup_hierarchy(nlevels=ws.nlevels, cheb_degree=ws.cheb_degree)
+        m.add_samples(hs, nsamples=4, seed=s, sweeps=20)
+        hs.close()
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    m.init_params(seed=0, out_scale=0.0)
+    loss_geo, _ = m.loss_grad()
+    m.init_params(seed=0, out_scale=0.01)
+    t0 = time.perf_counter()
+    hist = m.train(train_steps, 1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    theta = m.params()
+    pairs = m.num_data()
+    m.close()
+    w = synth.workload("c5")
+    b = _to_dev(synth.rhs(w), dev)
+    out = {"training": {"pairs": pairs, "steps": train_steps, "data_s": t_data, "train_s": t_train,
+                        "loss_initial": float(hist[0]), "loss_final": float(hist[-1]),
+                        "loss_geometric_interpolation": loss_geo}}
+    for name in ("geometric", "learned"):
+        h = _handle(w, dev)
+        if name == "learned":
+            h.set_learned_prolongator(theta)
+        setup_ms = _setup(h, w)
+        info = h.prolongator_info()
+        ms, res, _ = _timed_solves(h, b)
+        out[name] = {"setup_ms": setup_ms, "solve_ms": ms, "iterations": res["iterations"],
+                     "true_relres": res["true_relres"], "rho_10_cycles": h.convergence_factor(10),
+                     "interpolation": {0: "geometric", 1: "stored", 2: "learned"}[info["kind"]]}
+        if name == "learned":
+            out[name]["judge"] = {"rho_learned": info["rho_learned"], "rho_geometric": info["rho_geometric"],
+                                  "flags": info["flags"]}
+        h.close()
+        print(f"[bench] learned {name}: {ms:.1f} ms, {res['iterations']} its", file=sys.stderr, flush=True)
+    out["speedup_learned_vs_geometric"] = out["geometric"]["solve_ms"] / out["learned"]["solve_ms"]
+    out["workload"] = ("3D Q1 diffusion, 4x4x4 regions of 82^3, coefficient 10^s_R exp(N(0,1)) per element "
+                       "(s_R ~ U(-4,4) on even regions), 4-level V-cycle, Chebyshev degree 3, PCG to 1e-8; "
+                       "learned interpolation on the finest level, judged by 10 stationary cycles")
+    return out
+
+
+def variant_graph_2d(dev):
+    """2D five-point 2x2 regions of 82^2 (cache-resident, launch-bound): eager vs graph replay."""
+    import synth
+
+    w = synth.workload("c1")
+    b = _to_dev(synth.rhs(w), dev)
+    out = {}
+    for name, g in (("eager", 0), ("graph", 1)):
+        h = _handle(w, dev)
+        _setup(h, w, use_graph=g)
+        ms, res, _ = _timed_solves(h, b, reps=5)
+        out[name] = {"solve_ms": ms, "iterations": res["iterations"], "true_relres": res["true_relres"]}
+        h.close()
+    out["workload"] = "2D five-point, 2x2 regions of 82^2, 3-level V-cycle, Chebyshev degree 2, PCG to 1e-8"
+    return out
+
+
+def _to_dev(a, dev):
+    import numpy as np
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to(dev)
+
+
 def kernel_source_sha():
     import hashlib
 
@@ -100,6 +309,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the mixed-precision, batched, learned and graph comparisons")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -209,6 +420,13 @@ def main():
             "launches": n_cheb,
         },
     }
+    if not args.no_variants and args.workload == "c2":
+        line["variants"] = {
+            "mixed_precision": variant_mixed(dev),
+            "batched": variant_batched(dev),
+            "learned_interpolation": variant_learned(dev),
+            "graph_2d": variant_graph_2d(dev),
+        }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(last["iterations"], rows)
     print(json.dumps(line), flush=True)

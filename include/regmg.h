@@ -88,6 +88,9 @@ typedef struct {
                          host convergence check) as HIP graphs once and replays them */
   const char* autotune_cache; /* text file of autotuner choices keyed by level shape and
                          precision; read before tuning, appended after (NULL: no file) */
+  int batched;        /* 1 (default): each stencil operation is one launch over the block or tile
+                         list of all regions; 0: one node-parallel launch per region (the
+                         region-by-region baseline of the batched form; no tiles, no autotuning) */
   int judge_cycles;   /* learned interpolation only: > 0 measures the convergence factor of
                          this many stationary V-cycles (rmg_convergence_factor) with the learned
                          and with the geometric interpolation at setup and keeps the better

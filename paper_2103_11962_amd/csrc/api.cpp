@@ -140,6 +140,7 @@ void rmg_options_default(rmg_options* o) {
   o->autotune = 0;
   o->use_graph = 0;
   o->autotune_cache = nullptr;
+  o->batched = 1;
   o->judge_cycles = 10;
 }
 
@@ -381,6 +382,8 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->precision == RMG_PREC_FP64 || h->dim == 3, RMG_ERR_ARG,
               "the low-precision V-cycle needs 27-point (3D) levels");
   RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 3, RMG_ERR_ARG, "stencil_kernel must be 0..3");
+  RMG_REQUIRE(opt->batched == 0 || opt->batched == 1, RMG_ERR_ARG, "batched must be 0 or 1");
+  RMG_REQUIRE(opt->judge_cycles >= 0 && opt->judge_cycles <= 1000, RMG_ERR_ARG, "judge_cycles must be in [0, 1000]");
   h->opt = *opt;
   h->autotune_cache = opt->autotune_cache ? std::string(opt->autotune_cache) : std::string();
   h->opt.autotune_cache = nullptr;  // the caller's string is borrowed for this call only

@@ -126,12 +126,14 @@ struct Level {
   int64_t ncomp = 0;   // composite nodes
   std::vector<RegionGeo> regs;
   std::vector<BlockDesc> blocks;
+  std::vector<int> region_block;  // [nreg + 1]: first block of each region (blocks are region-major)
   DBuf d_regs, d_blocks;
   std::vector<Tile3> tiles;  // 2.5D tiles of a 3D level (empty in 2D)
   DBuf d_tiles;
   bool use_tiles = false;    // run 27-point stencil operations with the 2.5D kernel
   int tile_depth = 21;       // planes per tile
   int tile_grid = 0;         // > 0: persistent launch of this many blocks looping over the tiles
+  bool per_region = false;   // stencil operations launch the node-parallel kernel once per region
   // interface groups: copies of each shared composite node, ascending region order
   int64_t ngroups = 0;
   DBuf d_gptr;    // int64 [ngroups+1]

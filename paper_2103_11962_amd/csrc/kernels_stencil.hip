@@ -267,9 +267,21 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
                          ntiles, coef, centre, p, a.partials);
     }
   }
-  if (!tiled)
+  if (!tiled && L.per_region) {
+    // unbatched: one launch per region over its slice of the block table (partials keep their slots)
+    for (int k = 0; k < L.nreg; ++k) {
+      const int b0 = L.region_block[k], b1 = L.region_block[k + 1];
+      if (b1 == b0) continue;
+      LevelView vk = v;
+      vk.blocks = v.blocks + b0;
+      vk.nblocks = b1 - b0;
+      hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT>), dim3(b1 - b0), dim3(kBlock), 0, st, vk, coef,
+                         centre, p, a.partials ? a.partials + b0 : nullptr);
+    }
+  } else if (!tiled) {
     hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT>), dim3(L.blocks.size()), dim3(kBlock), 0, st, v, coef,
                        centre, p, a.partials);
+  }
   LAUNCH_CHECK();
   if (a.ev1) RMG_HIP(hipEventRecord(a.ev1, st));
   const int64_t nb = tiled ? (int64_t)grid3 : (int64_t)L.blocks.size();

@@ -80,12 +80,14 @@ void make_tiles(Level& L, int depth) {
 void build_tables(Level& L) {
   int64_t off = 0;
   L.blocks.clear();
+  L.region_block.assign(1, 0);
   for (int k = 0; k < L.nreg; ++k) {
     RegionGeo& R = L.regs[k];
     R.n = R.ex * R.ey * R.ez;
     R.off = off;
     off += R.n;
     for (int s = 0; s < R.n; s += kBlock) L.blocks.push_back(BlockDesc{k, s});
+    L.region_block.push_back((int)L.blocks.size());
   }
   L.n = off;
   RMG_REQUIRE(L.n < (int64_t)1 << 31, RMG_ERR_ARG, "more than 2^31 regional nodes on one level");

@@ -228,7 +228,8 @@ static int build_levels(rmg_handle* h, bool stored) {
     Level& L = *h->levels[l];
     if (L.dim == 3 && L.tile_depth != 21) make_tiles(L, 21);
     L.tile_grid = 0;
-    L.use_tiles = L.ndof == 1 && !L.tiles.empty() &&
+    L.per_region = o.batched == 0;
+    L.use_tiles = !L.per_region && L.ndof == 1 && !L.tiles.empty() &&
                   (o.stencil_kernel >= 2 || (o.stencil_kernel == 0 && L.tiles.size() >= kAutoTileMin));
     // persistent tiles: 4 blocks per CU, and at least two tiles per block
     if (L.use_tiles && o.stencil_kernel == 3)
@@ -271,7 +272,7 @@ static int build_levels(rmg_handle* h, bool stored) {
     launch_rap(L, *C, st);
     // the V-cycle's copy of this level's operator, made after the Galerkin product used it
     if (lowp) launch_make_lowp(L, (l == 0 && o.precision == RMG_PREC_FP32_BF16) ? kCoefBF16 : kCoefF32, st);
-    if (o.autotune && L.dim == 3 && L.ndof == 1 && L.npts == 27) autotune_level(h, L, l, lowp);
+    if (o.autotune && !L.per_region && L.dim == 3 && L.ndof == 1 && L.npts == 27) autotune_level(h, L, l, lowp);
   }
   if (lowp) h->cg_z32.alloc(sizeof(float) * (size_t)L0->ndofs());
   RMG_HIP(hipStreamSynchronize(st));

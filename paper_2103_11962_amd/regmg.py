@@ -58,6 +58,7 @@ class Options(ctypes.Structure):
         ("autotune", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("autotune_cache", ctypes.c_char_p),
+        ("batched", ctypes.c_int),
         ("judge_cycles", ctypes.c_int),
     ]
 

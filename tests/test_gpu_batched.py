@@ -71,3 +71,28 @@ def test_autotuned_solve_and_cache(hip_device, tmp_path):
     assert np.array_equal(x2, x)
     assert os.path.getsize(cache) > 0
     h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_region_by_region_matches_batched(hip_device, precision):
+    """The unbatched baseline (one node-parallel launch per region) computes exactly what one
+    batched node-parallel launch computes, and stays at oracle parity in FP64."""
+    from oracle import regional
+
+    w = synth.workload("c4_small")
+    b = synth.rhs(w)
+    n = int(np.prod(b.shape))
+    hb = harness.gpu_problem(w, precision=precision, stencil_kernel=1)
+    hr = harness.gpu_problem(w, precision=precision, batched=0)
+    xb, ob = solve(hb, b, n)
+    xr, orr = solve(hr, b, n)
+    assert orr["iterations"] == ob["iterations"] and np.array_equal(xr, xb)
+    if precision == 0:
+        lay, levels, opt = harness.oracle_problem(w)
+        ref = regional.pcg(levels, lay.to_regional(b), opt, rtol=1e-8, maxit=100)
+        assert orr["iterations"] == ref.iterations
+        assert rel(xr, lay.to_composite_owner(ref.x).reshape(-1)) < 1e-10
+    else:
+        assert orr["converged"] and orr["true_relres"] <= 1.5e-8
+    hb.close()
+    hr.close()
