@@ -31,8 +31,8 @@ CG_MATVEC_BYTES_PER_ROW = 232  # 27 coefficients + p read; q written (FP64)
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
-TRAFFIC_BYTES = 9628084106
-TRAFFIC_KERNEL_SHA = "1f047817f411af9f"
+TRAFFIC_BYTES = 9628103346
+TRAFFIC_KERNEL_SHA = "d5d65f0d81f8f4a6"
 
 CPU_SAMPLE = r"""
 import json, sys, time
