@@ -82,8 +82,8 @@ void launch_to_composite(const Level& L, const double* reg, double* comp, int av
 
 // Coarsest level: gather owner copies, dense FP64 GEMV with the inverse, scatter to copies.
 void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipStream_t st);
-// In-place Gauss-Jordan inversion of an SPD n x n matrix (row-major), with work buffers row/col of n.
-void launch_gauss_jordan(double* A, int n, double* row, double* col, hipStream_t st);
+// In-place blocked Gauss-Jordan inversion of an SPD n x n matrix (row-major); synchronises st.
+void launch_gauss_jordan(double* A, int n, hipStream_t st);
 void launch_check_inverse(const double* A, int n, int* flag, hipStream_t st);
 
 // Q1 assembly (scalar): Kref = 8x8 element matrix of the unit cube scaled by h.

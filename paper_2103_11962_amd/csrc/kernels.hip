@@ -7,6 +7,7 @@
 // are unit-stride and a block never straddles two regions.  Vectors hold `ndof` values per node.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_common.h"
@@ -761,35 +762,162 @@ void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipS
   LAUNCH_CHECK();
 }
 
-__global__ void k_gj_save(int n, int k, const double* __restrict__ A, double* __restrict__ row,
-                          double* __restrict__ col) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    row[i] = A[(int64_t)k * n + i];
-    col[i] = A[(int64_t)i * n + k];
+// ------------------------------------------ coarse inverse: blocked Gauss-Jordan (SPD, in place)
+// For a pivot panel P = [k0, k0 + nb) and the other indices R, one block step maps
+//   A_PP -> X = A_PP^-1,  A_PR -> X A_PR,  A_RP -> -A_RP X,  A_RR -> A_RR - A_RP X A_PR,
+// the block form of the scalar Gauss-Jordan step (no pivoting: every pivot block of an SPD matrix
+// is SPD).  Four launches per panel: the panel inverse in LDS, T = A_RP X and W = X A_PR
+// (stored nb x n), the rank-nb update of A_RR as a tiled GEMM, and the panel rows and columns.
+constexpr int kGjB = 64;  // panel width
+
+__global__ __launch_bounds__(kBlock) void k_gj_panel(int n, int k0, int nb, const double* __restrict__ A,
+                                                     double* __restrict__ X) {
+  __shared__ double s[kGjB][kGjB + 1];
+  __shared__ double rowk[kGjB], colk[kGjB];
+  for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+    const int i = e / nb, j = e - i * nb;
+    s[i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if ((int)threadIdx.x < nb) {
+      rowk[threadIdx.x] = s[k][threadIdx.x];
+      colk[threadIdx.x] = s[threadIdx.x][k];
+    }
+    __syncthreads();
+    const double p = rowk[k];
+    for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+      const int i = e / nb, j = e - i * nb;
+      double v;
+      if (i == k && j == k) v = 1.0 / p;
+      else if (i == k) v = rowk[j] / p;
+      else if (j == k) v = -colk[i] / p;
+      else v = s[i][j] - colk[i] * (rowk[j] / p);
+      s[i][j] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+    const int i = e / nb, j = e - i * nb;
+    X[i * kGjB + j] = s[i][j];
   }
 }
 
-// In-place Gauss-Jordan step on pivot k (no pivoting; the matrix is SPD).
-__global__ void k_gj_update(int n, int k, double* __restrict__ A, const double* __restrict__ row,
-                            const double* __restrict__ col) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= n) return;
-  const double p = row[k];
-  double* a = A + (int64_t)i * n + j;
-  if (i == k && j == k) *a = 1.0 / p;
-  else if (i == k) *a = row[j] / p;
-  else if (j == k) *a = -col[i] / p;
-  else *a -= col[i] * (row[j] / p);
+// TT[q][i] = sum_p A[i][k0+p] X[p][q] (T transposed) and W[p][j] = sum_q X[p][q] A[k0+q][j], one
+// thread per index i (= j), X in LDS.  Rows and columns inside the panel are computed but unused.
+__global__ __launch_bounds__(kBlock) void k_gj_tw(int n, int k0, int nb, const double* __restrict__ A,
+                                                  const double* __restrict__ X, double* __restrict__ TT,
+                                                  double* __restrict__ W) {
+  __shared__ double sx[kGjB][kGjB];  // X, zero outside nb x nb
+  for (int e = threadIdx.x; e < kGjB * kGjB; e += kBlock) {
+    const int r = e / kGjB, c = e % kGjB;
+    sx[r][c] = (r < nb && c < nb) ? X[e] : 0.0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  // fixed trip counts keep a[] in registers; entries beyond nb are zero
+  double a[kGjB];
+#pragma unroll
+  for (int p = 0; p < kGjB; ++p) a[p] = p < nb ? A[(int64_t)i * n + k0 + p] : 0.0;  // row i, panel columns
+  for (int q = 0; q < nb; ++q) {
+    double t = 0.0;
+#pragma unroll
+    for (int p = 0; p < kGjB; ++p) t += a[p] * sx[p][q];
+    TT[(int64_t)q * n + i] = t;
+  }
+#pragma unroll
+  for (int q = 0; q < kGjB; ++q) a[q] = q < nb ? A[(int64_t)(k0 + q) * n + i] : 0.0;  // column i, panel rows
+  for (int p = 0; p < nb; ++p) {
+    double w = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGjB; ++q) w += sx[p][q] * a[q];
+    W[(int64_t)p * n + i] = w;
+  }
 }
 
-void launch_gauss_jordan(double* A, int n, double* row, double* col, hipStream_t st) {
-  for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_gj_save, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, k, A, row, col);
-    hipLaunchKernelGGL(k_gj_update, dim3(cdiv(n, kBlock), n), dim3(kBlock), 0, st, n, k, A, row, col);
+// A_RR -= T A_PR over 64 x 64 output tiles: T and the panel rows staged in LDS, 4 x 4 outputs per
+// thread (consecutive lanes own consecutive columns, so A is read and written coalesced).
+__global__ __launch_bounds__(kBlock) void k_gj_rank(int n, int k0, int nb, double* __restrict__ A,
+                                                    const double* __restrict__ TT) {
+  const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
+  const bool rows_in_panel = bi >= k0 && bi + 64 <= k0 + nb, cols_in_panel = bj >= k0 && bj + 64 <= k0 + nb;
+  if (rows_in_panel || cols_in_panel) return;  // uniform over the block
+  __shared__ double sT[kGjB][64];  // [q][row]
+  __shared__ double sB[kGjB][64];  // [q][col]
+  for (int e = threadIdx.x; e < nb * 64; e += kBlock) {
+    const int q = e / 64, c = e - q * 64;
+    sT[q][c] = bi + c < n ? TT[(int64_t)q * n + bi + c] : 0.0;
+    sB[q][c] = bj + c < n ? A[(int64_t)(k0 + q) * n + bj + c] : 0.0;
+  }
+  __syncthreads();
+  const int tj = threadIdx.x % 16, ti = threadIdx.x / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int q = 0; q < nb; ++q) {
+    double t[4], v[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) t[a] = sT[q][ti + 16 * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) v[b] = sB[q][tj + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += t[a] * v[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = bi + ti + 16 * a;
+    if (i >= n || (i >= k0 && i < k0 + nb)) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = bj + tj + 16 * b;
+      if (j >= n || (j >= k0 && j < k0 + nb)) continue;
+      A[(int64_t)i * n + j] -= acc[a][b];
+    }
+  }
+}
+
+// Panel rows A[k0+p][j] = W[p][j] (j outside the panel) and the pivot block = X; one thread per
+// (p, j), consecutive lanes on consecutive columns.
+__global__ __launch_bounds__(kBlock) void k_gj_rows(int n, int k0, int nb, double* __restrict__ A,
+                                                    const double* __restrict__ W, const double* __restrict__ X) {
+  const int j = blockIdx.x * kBlock + threadIdx.x, p = blockIdx.y;
+  if (j >= n) return;
+  A[(int64_t)(k0 + p) * n + j] = (j >= k0 && j < k0 + nb) ? X[p * kGjB + (j - k0)] : W[(int64_t)p * n + j];
+}
+
+// Panel columns A[i][k0+q] = -T[i][q] (i outside the panel); one wavefront per row, lane q.
+__global__ __launch_bounds__(kBlock) void k_gj_cols(int n, int k0, int nb, double* __restrict__ A,
+                                                    const double* __restrict__ TT) {
+  const int q = threadIdx.x & 63;
+  const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (i >= n || q >= nb || (i >= k0 && i < k0 + nb)) return;
+  A[(int64_t)i * n + k0 + q] = -TT[(int64_t)q * n + i];
+}
+
+void launch_gauss_jordan(double* A, int n, hipStream_t st) {
+  if (n == 0) return;
+  DBuf X, TT, W;
+  X.alloc(sizeof(double) * kGjB * kGjB);
+  TT.alloc(sizeof(double) * kGjB * (size_t)n);
+  W.alloc(sizeof(double) * kGjB * (size_t)n);
+  const int nt = (int)cdiv(n, 64);
+  for (int k0 = 0; k0 < n; k0 += kGjB) {
+    const int nb = std::min(kGjB, n - k0);
+    hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>());
+    hipLaunchKernelGGL(k_gj_tw, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>(),
+                       TT.as<double>(), W.as<double>());
+    hipLaunchKernelGGL(k_gj_rank, dim3(nt, nt), dim3(kBlock), 0, st, n, k0, nb, A, TT.as<double>());
+    hipLaunchKernelGGL(k_gj_rows, dim3(cdiv(n, kBlock), nb), dim3(kBlock), 0, st, n, k0, nb, A, W.as<double>(),
+                       X.as<double>());
+    hipLaunchKernelGGL(k_gj_cols, dim3(cdiv(n, kBlock / 64)), dim3(kBlock), 0, st, n, k0, nb, A, TT.as<double>());
   }
   LAUNCH_CHECK();
+  RMG_HIP(hipStreamSynchronize(st));  // before the work buffers are released
 }
 
 __global__ void k_check_inverse(int n, const double* __restrict__ A, int* flag) {

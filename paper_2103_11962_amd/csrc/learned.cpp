@@ -158,7 +158,7 @@ static void reserve_work(rmg_mlp* m, int64_t n, int64_t nloss) {
     m->A2.alloc(sizeof(float) * kMlpH * (size_t)n);
     m->D1.alloc(sizeof(float) * kMlpH * (size_t)n);
     m->D2.alloc(sizeof(float) * kMlpH * (size_t)n);
-    m->partials.alloc(sizeof(double) * (size_t)((n + kBlock - 1) / kBlock + 1));
+    m->partials.alloc(sizeof(double) * (size_t)mlp_loss_partials(n));
     if (!m->part.p) m->part.alloc(sizeof(float) * (size_t)mlp_grad_partials());
     m->wcap = n;
   }

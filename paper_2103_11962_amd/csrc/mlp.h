@@ -23,7 +23,9 @@ void cell_node_table(CellNode* nodes, signed char* pos2node);
 
 // Z = MLP(X) for n samples; A1, A2 (pre-activations, [n][64]) are stored when non-null.
 void mlp_forward(int64_t n, const float* X, const float* theta, float* Z, float* A1, float* A2, hipStream_t st);
-// Per-sample loss partial sums (one double per block, returned count) and dZ = dloss/dZ / n.
+// Loss partial sums (one double per block of samples; mlp_loss_partials(n) of them, also the
+// returned count) and dZ = dloss/dZ / n.
+int64_t mlp_loss_partials(int64_t n);
 int64_t mlp_loss(int64_t n, const float* Z, const float* E, float* dZ, double* partials, hipStream_t st);
 // Activation gradients of the two hidden layers.
 void mlp_backact(int64_t n, const float* dZ, const float* A1, const float* A2, const float* theta, float* D1,

@@ -133,45 +133,71 @@ __device__ __forceinline__ void node_softmax(const float* z, const CellNode& nd,
   for (int c = 0; c < 8; ++c) w[c] /= s;
 }
 
-// Loss per sample sum_f (e_f - sum_c w_fc e_c)^2 / sum_f e_f^2 and its gradient with respect
-// to the logits, scaled by 1/n (the loss is a mean over samples).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Loss per sample sum_f (e_f - sum_c w_fc e_c)^2 / sum_f e_f^2 and its gradient with respect to
+// the logits, scaled by 1/n (the loss is a mean over samples).  One wavefront per sample: lane p
+// holds the error at cell node p (x fastest over the 4x4x4 nodes), the corner values arrive by
+// lane shuffles, and each lane of a non-corner node evaluates that node's softmax, so the rows of
+// E, Z and dZ are read and written contiguously.  Partial sums: one per block of kMlpLossSamples.
+constexpr int kMlpLossSamples = kBlock / 64;
+
 __global__ __launch_bounds__(kBlock) void k_mlp_loss(int64_t n, const float* __restrict__ Z,
                                                      const float* __restrict__ E, float* __restrict__ dZ,
                                                      double* __restrict__ partials) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double loss = 0.0;
-  if (i < n) {
-    const float* e = E + i * 64;
-    const float* z = Z + i * kMlpOut;
-    float* dz = dZ + i * kMlpOut;
-    float norm = 0.f;
-    for (int p = 0; p < 64; ++p) norm += e[p] * e[p];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kMlpLossSamples + wid;
+  float loss = 0.f;
+  if (i < n) {  // uniform over the wavefront
+    const float ep = E[i * 64 + lane];
+    float norm = wave_sum(ep * ep);
     if (!(norm > 0.f)) norm = 1.f;
-    const float inv_n = 1.0f / (float)n;
+    float ec[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ec[q] = __shfl(ep, corner_pos(q), 64);
+    const int node = c_pos2node[lane];
     float l = 0.f;
-    for (int k = 0; k < 56; ++k) {
-      const CellNode nd = c_nodes[k];
+    if (node >= 0) {
+      const CellNode nd = c_nodes[node];
+      const float* z = Z + i * kMlpOut;
+      float* dz = dZ + i * kMlpOut;
       float w[8], ev[8];
       node_softmax(z, nd, w);
 #pragma unroll
-      for (int c = 0; c < 8; ++c) ev[c] = c < nd.ncorner ? e[corner_pos(nd.corner[c])] : 0.f;
+      for (int c = 0; c < 8; ++c) {
+        float v = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v = (c < nd.ncorner && nd.corner[c] == q) ? ec[q] : v;
+        ev[c] = v;
+      }
       float pred = 0.f;
 #pragma unroll
       for (int c = 0; c < 8; ++c) pred += w[c] * ev[c];
-      const float res = e[nd.pos] - pred;
-      l += res * res;
+      const float res = ep - pred;
+      l = res * res;
       const float dpred = -2.f * res / norm;
       float sdw = 0.f;
 #pragma unroll
       for (int c = 0; c < 8; ++c) sdw += dpred * ev[c] * w[c];
+      const float inv_n = 1.0f / (float)n;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         if (c < nd.ncorner) dz[nd.first + c] = w[c] * (dpred * ev[c] - sdw) * inv_n;
     }
-    loss = (double)(l / norm);
+    loss = wave_sum(l) / norm;
   }
-  const double s = block_sum(loss);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  __shared__ float sm[kMlpLossSamples];
+  if (lane == 0) sm[wid] = loss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < kMlpLossSamples; ++k) s += (double)sm[k];
+    partials[blockIdx.x] = s;
+  }
 }
 
 // Activation gradients: D2 = (dZ W3) * [A2 > 0], D1 = (D2 W2) * [A1 > 0].
@@ -274,16 +300,25 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(int64_t n, const float* __res
 }
 
 // Sum the block partials into the flat gradient: W block at wofs (row-major R x C), bias at bofs.
-__global__ void k_mlp_wgrad_reduce(int R, int C, int nblk, const float* __restrict__ part, float* __restrict__ grad,
-                                   int wofs, int bofs) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// A block owns 64 outputs; its four wavefronts sum every fourth partial and the four sums are
+// added in a fixed order (deterministic).
+__global__ __launch_bounds__(kBlock) void k_mlp_wgrad_reduce(int R, int C, int nblk, const float* __restrict__ part,
+                                                             float* __restrict__ grad, int wofs, int bofs) {
   const int per = R * (C + 1);
-  if (t >= per) return;
-  const int r = t / (C + 1), j = t - r * (C + 1);
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += (double)part[(int64_t)b * per + t];
-  if (j < C) grad[wofs + r * C + j] = (float)s;
-  else grad[bofs + r] = (float)s;
+  if (t < per)
+    for (int b = grp; b < nblk; b += kBlock / 64) s += (double)part[(int64_t)b * per + t];
+  __shared__ double sm[kBlock / 64][64];
+  sm[grp][lane] = s;
+  __syncthreads();
+  if (grp != 0 || t >= per) return;
+  double tot = 0.0;
+  for (int g = 0; g < kBlock / 64; ++g) tot += sm[g][lane];
+  const int r = t / (C + 1), j = t - r * (C + 1);
+  if (j < C) grad[wofs + r * C + j] = (float)tot;
+  else grad[bofs + r] = (float)tot;
 }
 
 __global__ void k_adam(int n, float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
@@ -305,9 +340,11 @@ void mlp_forward(int64_t n, const float* X, const float* theta, float* Z, float*
   LAUNCH_CHECK();
 }
 
+int64_t mlp_loss_partials(int64_t n) { return cdiv(n, kMlpLossSamples); }
+
 int64_t mlp_loss(int64_t n, const float* Z, const float* E, float* dZ, double* partials, hipStream_t st) {
   upload_tables();
-  const int64_t nb = cdiv(n, kBlock);
+  const int64_t nb = mlp_loss_partials(n);
   hipLaunchKernelGGL(k_mlp_loss, dim3(nb), dim3(kBlock), 0, st, n, Z, E, dZ, partials);
   LAUNCH_CHECK();
   return nb;
@@ -329,8 +366,8 @@ void mlp_weight_grads(int64_t n, const float* X, const float* A1, const float* A
   const int ofs_b1 = kMlpH * kMlpIn, ofs_W2 = ofs_b1 + kMlpH, ofs_b2 = ofs_W2 + kMlpH * kMlpH,
             ofs_W3 = ofs_b2 + kMlpH, ofs_b3 = ofs_W3 + kMlpOut * kMlpH;
   auto reduce = [&](int R, int C, int wofs, int bofs) {
-    hipLaunchKernelGGL(k_mlp_wgrad_reduce, dim3(cdiv(R * (C + 1), kBlock)), dim3(kBlock), 0, st, R, C, nblk, part,
-                       grad, wofs, bofs);
+    hipLaunchKernelGGL(k_mlp_wgrad_reduce, dim3(cdiv(R * (C + 1), 64)), dim3(kBlock), 0, st, R, C, nblk, part, grad,
+                       wofs, bofs);
     LAUNCH_CHECK();
   };
   hipLaunchKernelGGL((k_mlp_wgrad<kMlpOut, kMlpH, 13, 4>), dim3(nblk), dim3(256), 0, st, n, dZ, A2, 1, per_block,

@@ -297,7 +297,7 @@ void build_coarse_solver(rmg_handle* h, Level& L) {
   DBuf flag;
   flag.alloc(sizeof(int));
   RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
-  launch_gauss_jordan(L.ainv.as<double>(), nc, L.cvec.as<double>(), L.cvec2.as<double>(), st);
+  launch_gauss_jordan(L.ainv.as<double>(), nc, st);
   launch_check_inverse(L.ainv.as<double>(), nc, flag.as<int>(), st);
   int hflag = 0;
   RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));

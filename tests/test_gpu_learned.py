@@ -349,3 +349,37 @@ def test_learned_solve_converges(hip_device, oracle_c5, theta):
     out = h.solve(b, x, rtol=1e-8, maxit=200)
     assert out["converged"] and out["true_relres"] <= 1.5e-8
     h.close()
+
+
+def test_trained_network_gains_over_geometric(hip_device):
+    """Train on the device (seeds 1-8 of the small jump-coefficient problem), evaluate on the
+    held-out seed 0: the trained network lowers the interpolation loss below trilinear weights
+    and the learned hierarchy converges faster than the geometric one (smaller rho)."""
+    from paper_2103_11962_amd import regmg
+
+    m = trainer()
+    for s in range(1, 9):
+        ws = synth.workload(NAME, seed=s)
+        hs = harness.gpu_problem(ws)
+        m.add_samples(hs, nsamples=4, seed=s, sweeps=20)
+        hs.close()
+    m.init_params(seed=0, out_scale=0.0)
+    loss_geo, _ = m.loss_grad()
+    m.init_params(seed=0, out_scale=0.01)
+    hist = m.train(400, 1e-3)
+    assert hist[-1] < 0.85 * loss_geo, (loss_geo, hist[-1])
+    theta = m.params()
+    m.close()
+    w = synth.workload(NAME)
+    g = harness.gpu_problem(w)
+    rho_g = g.convergence_factor(10)
+    h = harness.gpu_problem(w, setup=False)
+    h.set_learned_prolongator(theta)
+    h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree)  # judged with 10 cycles
+    info = h.prolongator_info()
+    print(f"[learned] loss trilinear {loss_geo:.5f} -> trained {hist[-1]:.5f}; "
+          f"rho geometric {rho_g:.5f}, learned {info['rho_learned']:.5f}", flush=True)
+    assert info["kind"] == regmg.P_LEARNED, info
+    assert info["rho_learned"] < rho_g
+    g.close()
+    h.close()
