@@ -26,8 +26,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PCG time-to-1e-8 residual + stencil GB/s, FP64 vs mixed/learned forms"
 HBM_PEAK_GBS = 8000.0
-CHEB_BYTES_PER_ROW = 264  # 27 coefficients + u, b, D^-1, d read; d, u written (FP64)
-CG_MATVEC_BYTES_PER_ROW = 232  # 27 coefficients + p read; q written (FP64)
+# Algorithmic bytes per regional row of the finest-level FP64 kernels: the stencil coefficients
+# the kernel streams (27, or the 14 of the stored upper half of a symmetric stencil), then the
+# Chebyshev step reads u, b, D^-1, d and writes d, u; the CG product reads p and writes q.
+def cheb_bytes_per_row(coefs):
+    return 8 * coefs + 6 * 8
+
+
+def cg_matvec_bytes_per_row(coefs):
+    return 8 * coefs + 2 * 8
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
@@ -133,13 +140,23 @@ def _setup(h, w, **opts):
     return (time.perf_counter() - t0) * 1e3
 
 
+def _cheb_bytes(h, kind, precision):
+    """Algorithmic bytes per node of the level-0 Chebyshev step as the level runs it."""
+    lk = h.level_kernel(0)
+    if kind == "scalar":
+        coefs = lk["coefs"] if precision == 0 else lk["coefs_lo"]
+        width = 8 if precision == 0 else 4
+        return coefs * width + 6 * width
+    return CHEB_BYTES[(kind, precision)]
+
+
 def _cheb_gbs(h, kind, precision, rows):
     from paper_2103_11962_amd import regmg
 
     n, ms = h.profile_query(regmg.TIMED_CHEB)
     if n == 0:
         return None
-    return CHEB_BYTES[(kind, precision)] * rows / (ms / n * 1e-3) / 1e9
+    return _cheb_bytes(h, kind, precision) * rows / (ms / n * 1e-3) / 1e9
 
 
 def variant_mixed(dev):
@@ -193,7 +210,8 @@ def variant_batched(dev):
         h.profile(True)
         ms, res, _ = _timed_solves(h, b)
         out[name] = {"setup_ms": setup_ms, "solve_ms": ms, "iterations": res["iterations"],
-                     "true_relres": res["true_relres"], "cheb_gbs": _cheb_gbs(h, "scalar", 1, rows)}
+                     "true_relres": res["true_relres"], "cheb_gbs": _cheb_gbs(h, "scalar", 1, rows),
+                     "cheb_bytes_per_row": _cheb_bytes(h, "scalar", 1)}
         if name == "batched":
             out[name]["tuning"] = h.tune_report().strip().splitlines()
         h.close()
@@ -372,13 +390,14 @@ def main():
     assert last["converged"] and last["true_relres"] <= 1.5e-8, last
     info0 = h.level_info(0)
     rows = info0["n_regional"]
+    lk = h.level_kernel(0)
     n_cheb, ms_cheb = h.profile_query(regmg.TIMED_CHEB)
     n_cg, ms_cg = h.profile_query(regmg.TIMED_CG_MATVEC)
     avg_cheb = ms_cheb / max(n_cheb, 1)
-    bytes_cheb = CHEB_BYTES_PER_ROW * rows
+    bytes_cheb = cheb_bytes_per_row(lk["coefs"]) * rows
     achieved = bytes_cheb / (avg_cheb * 1e-3) / 1e9
     avg_cg = ms_cg / max(n_cg, 1)
-    achieved_cg = CG_MATVEC_BYTES_PER_ROW * rows / (avg_cg * 1e-3) / 1e9
+    achieved_cg = cg_matvec_bytes_per_row(lk["coefs"]) * rows / (avg_cg * 1e-3) / 1e9
     h.close()
 
     line = {
@@ -408,7 +427,10 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stencil3d<Cheb> (finest-level fused Chebyshev step, 2.5D tiles)",
+            "kernel": ("k_stencil3d<Cheb, half stencil> (finest-level fused Chebyshev step, 2.5D tiles, upper "
+                       "half of the symmetric stencil streamed, lower couplings shared through LDS)"
+                       if lk["coefs"] == 14 else "k_stencil3d<Cheb> (finest-level fused Chebyshev step, 2.5D tiles)"),
+            "bytes_per_row": cheb_bytes_per_row(lk["coefs"]),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -88,6 +88,10 @@ typedef struct {
                          host convergence check) as HIP graphs once and replays them */
   const char* autotune_cache; /* text file of autotuner choices keyed by level shape and
                          precision; read before tuning, appended after (NULL: no file) */
+  int symmetric;      /* 1 (default): on scalar 27-point 3D levels whose operator is symmetric to
+                         rounding, the 2.5D kernel keeps only the upper half of each stencil
+                         (14 coefficients per node) and reads a lower coupling from the
+                         neighbour's record; 0: always the full 27-point stencil */
   int batched;        /* 1 (default): each stencil operation is one launch over the block or tile
                          list of all regions; 0: one node-parallel launch per region (the
                          region-by-region baseline of the batched form; no tiles, no autotuning) */
@@ -203,6 +207,13 @@ rmg_status rmg_smooth(rmg_handle* h, int level, const double* b, double* u);
 /* Level data.  n_regional / n_composite count dofs. */
 rmg_status rmg_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t* n_composite,
                           int* npts, double* lambda_max);
+/* How level `level`'s stencil operations run: kernel 0 node-parallel, 1 2.5D
+ * tiles (one block per tile), 2 2.5D tiles in a persistent grid, 3 node-parallel
+ * with one launch per region; coefs = stencil coefficients streamed per node by
+ * the FP64 operations (npts x ndof^2, or 14 for the stored upper half of a
+ * symmetric 27-point stencil); coefs_lo = the same for the low-precision
+ * V-cycle copy (0 when there is none).  Any output may be NULL. */
+rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, int* coefs_lo);
 /* Copy region `region`'s stencil on `level` to host memory in the layout of
  * rmg_set_region_stencil (npts 27 in 3D, 9 in 2D, all levels). */
 rmg_status rmg_get_level_stencil(rmg_handle* h, int level, int region, double* host_out);

@@ -140,6 +140,7 @@ void rmg_options_default(rmg_options* o) {
   o->autotune = 0;
   o->use_graph = 0;
   o->autotune_cache = nullptr;
+  o->symmetric = 1;
   o->batched = 1;
   o->judge_cycles = 10;
 }
@@ -222,6 +223,8 @@ rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const dou
   API_BEGIN
   use_device(h);
   Level& L = level_of(h, 0);
+  L.coef_sym.release();  // the half stencils of the old operator
+  L.coef_lo_sym.release();
   RMG_REQUIRE(region >= 0 && region < h->nreg, RMG_ERR_ARG, "region index out of range");
   RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
   const bool ok = (h->dim == 3 && npts == 27) || (h->dim == 2 && (npts == 5 || npts == 9));
@@ -283,6 +286,8 @@ rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef
   API_BEGIN
   use_device(h);
   Level& L = level_of(h, 0);
+  L.coef_sym.release();  // the half stencils of the old operator
+  L.coef_lo_sym.release();
   RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
   const bool ok = (h->dim == 3 && npts == 27) || (h->dim == 2 && (npts == 5 || npts == 9));
   RMG_REQUIRE(ok, RMG_ERR_ARG, "npts must be 27 in 3D and 5 or 9 in 2D");
@@ -317,6 +322,8 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
   API_BEGIN
   use_device(h);
   Level& L = level_of(h, 0);
+  L.coef_sym.release();  // the half stencils of the old operator
+  L.coef_lo_sym.release();
   RMG_REQUIRE(h->dim == 3, RMG_ERR_ARG, "Q1 assembly needs a 3D layout");
   RMG_REQUIRE(hsize > 0.0 && std::isfinite(hsize), RMG_ERR_ARG, "element size must be positive");
   RMG_REQUIRE(pde == RMG_PDE_LAPLACE || pde == RMG_PDE_DIFFUSION || pde == RMG_PDE_ELASTICITY, RMG_ERR_ARG,
@@ -383,6 +390,7 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
               "the low-precision V-cycle needs 27-point (3D) levels");
   RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 3, RMG_ERR_ARG, "stencil_kernel must be 0..3");
   RMG_REQUIRE(opt->batched == 0 || opt->batched == 1, RMG_ERR_ARG, "batched must be 0 or 1");
+  RMG_REQUIRE(opt->symmetric == 0 || opt->symmetric == 1, RMG_ERR_ARG, "symmetric must be 0 or 1");
   RMG_REQUIRE(opt->judge_cycles >= 0 && opt->judge_cycles <= 1000, RMG_ERR_ARG, "judge_cycles must be in [0, 1000]");
   h->opt = *opt;
   h->autotune_cache = opt->autotune_cache ? std::string(opt->autotune_cache) : std::string();
@@ -530,6 +538,17 @@ rmg_status rmg_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t
   if (n_composite) *n_composite = L.ncomp * h->ndof;
   if (npts) *npts = L.npts;
   if (lambda_max) *lambda_max = L.lambda;
+  API_END
+}
+
+rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, int* coefs_lo) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  const bool tiled = L.use_tiles && L.ndof == 1 && L.npts == 27;
+  if (kernel) *kernel = L.per_region ? 3 : (!tiled ? 0 : (L.tile_grid > 0 && L.tile_grid < (int)L.tiles.size() ? 2 : 1));
+  if (coefs) *coefs = (tiled && L.coef_sym.p) ? kSymPts : L.ncoef();
+  if (coefs_lo) *coefs_lo = L.ct_lo == kCoefF64 ? 0 : ((tiled && L.coef_lo_sym.p) ? kSymPts : L.ncoef());
   API_END
 }
 

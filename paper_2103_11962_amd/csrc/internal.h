@@ -81,6 +81,7 @@ __host__ __device__ __forceinline__ int64_t coef_index(int64_t gi, int s, int np
   return ((gi >> 6) * npts + s) * kTile + (gi & (kTile - 1));
 }
 inline size_t coef_elems(int64_t n, int npts) { return (size_t)((n + kTile - 1) / kTile) * kTile * npts; }
+constexpr int kSymPts = 14;  // upper half of a symmetric 27-point stencil: offsets 13..26
 
 // Everything a kernel needs to know about a level, passed by value.
 struct LevelView {
@@ -141,6 +142,7 @@ struct Level {
   DBuf d_gcomp;   // int32 composite node index of each group
   // operator (FP64, wave-tiled, ncoef() values per node: npts blocks of ndof x ndof)
   DBuf coef;
+  DBuf coef_sym;     // symmetric scalar 27-point levels: the upper half (kSymPts per node), else empty
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
   DBuf pw;        // stored interpolation weights to the next level, double [n][8] (null: geometric)
   DBuf rw;        // with pw: the same weights per coarse node (125 taps, wave-tiled) for the restriction
@@ -152,6 +154,7 @@ struct Level {
   int ct_lo = kCoefF64;  // kCoefF64: no copy
   DBuf coef_lo;          // float or uint16 (bf16), wave-tiled like coef
   DBuf center_lo;        // bf16 storage only: FP32 centre blocks [n][ndof*ndof]
+  DBuf coef_lo_sym;      // FP32 storage of a symmetric level: the upper half, else empty
   DBuf dinv_lo, b32, u32, u232, d32, r32;
   // coarsest level: composite inverse and owner map (nc = composite dofs)
   int nc = 0;

@@ -76,6 +76,11 @@ void launch_f32_to_f64(int64_t n, const float* in, double* out, hipStream_t st);
 // centre blocks whose diagonal keeps each row sum of the FP64 operator) and dinv_lo.
 void launch_make_lowp(Level& L, int coef_type, hipStream_t st);
 
+// Upper-half stencil copy (L.coef_sym, or L.coef_lo_sym from the FP32 copy when lowp) of a scalar
+// 27-point 3D level whose operator is symmetric to rounding; returns false (and leaves the copy
+// empty) otherwise.  The 2.5D kernel then streams 14 instead of 27 coefficients per node.
+bool launch_make_sym(Level& L, bool lowp, hipStream_t st);
+
 // Composite <-> regional (FP64).
 void launch_to_regional(const Level& L, const double* comp, double* reg, hipStream_t st);
 void launch_to_composite(const Level& L, const double* reg, double* comp, int average, hipStream_t st);

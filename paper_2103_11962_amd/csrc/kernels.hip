@@ -1248,6 +1248,67 @@ void launch_make_lowp(Level& L, int coef_type, hipStream_t st) {
   launch_f64_to_f32(L.ndofs(), L.dinv.as<double>(), L.dinv_lo.as<float>(), st);
 }
 
+// ------------------------------------------------------ symmetric half stencil
+// Upper half (offsets 13..26) of a scalar 27-point level's stencils.  flag is set unless every
+// lower coupling equals the neighbour's mirrored upper coupling to rounding,
+// |A(i, i+s) - A(i+s, i)| <= tol (|A_ii| + |A_jj|), and couplings leaving the region box are zero.
+template <class C>
+__global__ __launch_bounds__(kBlock) void k_make_sym(LevelView L, const C* __restrict__ coef, C* __restrict__ sym,
+                                                     double tol, int* flag) {
+  const BlockDesc bd = L.blocks[blockIdx.x];
+  const RegionGeo R = L.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= R.n) return;
+  int x, y, z;
+  decompose(R, li, x, y, z);
+  const int64_t gi = R.off + li;
+  for (int s = 13; s < 27; ++s) sym[coef_index(gi, s - 13, kSymPts)] = coef[coef_index(gi, s, 27)];
+  const double dii = fabs((double)coef[coef_index(gi, 13, 27)]);
+  bool bad = false;
+  for (int s = 0; s < 13; ++s) {
+    int dx, dy, dz;
+    stencil_offset<27>(s, dx, dy, dz);
+    const double a = (double)coef[coef_index(gi, s, 27)];
+    if ((unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
+        (unsigned)(z + dz) < (unsigned)R.ez) {
+      const int64_t gn = gi + dx + (int64_t)dy * R.ex + (int64_t)dz * R.ex * R.ey;
+      const double b = (double)coef[coef_index(gn, 26 - s, 27)];
+      const double djj = fabs((double)coef[coef_index(gn, 13, 27)]);
+      if (!(fabs(a - b) <= tol * (dii + djj))) bad = true;
+    } else if (a != 0.0) {
+      bad = true;
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+bool launch_make_sym(Level& L, bool lowp, hipStream_t st) {
+  DBuf& out = lowp ? L.coef_lo_sym : L.coef_sym;
+  out.release();
+  if (L.dim != 3 || L.ndof != 1 || L.npts != 27) return false;
+  if (lowp && L.ct_lo != kCoefF32) return false;
+  DBuf flag;
+  flag.alloc(sizeof(int));
+  RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  const size_t ne = coef_elems(L.n, kSymPts);
+  const dim3 g(L.blocks.size()), b(kBlock);
+  if (lowp) {
+    out.alloc(sizeof(float) * ne);
+    hipLaunchKernelGGL(k_make_sym<float>, g, b, 0, st, L.view(), L.coef_lo.as<float>(), out.as<float>(), 1e-6,
+                       flag.as<int>());
+  } else {
+    out.alloc(sizeof(double) * ne);
+    hipLaunchKernelGGL(k_make_sym<double>, g, b, 0, st, L.view(), L.coef.as<double>(), out.as<double>(), 1e-11,
+                       flag.as<int>());
+  }
+  LAUNCH_CHECK();
+  int hflag = 0;
+  RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  RMG_HIP(hipStreamSynchronize(st));
+  if (hflag) out.release();
+  return hflag == 0;
+}
+
 // ------------------------------------------------------------------ CG
 template <int NDOF>
 __global__ __launch_bounds__(kBlock) void k_cg_update(LevelView L, const double* __restrict__ scalars,

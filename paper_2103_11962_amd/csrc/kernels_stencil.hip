@@ -6,6 +6,8 @@
 // Template parameters: NPTS stencil points, NDOF unknowns per node (3x3 coefficient blocks for
 // elasticity), V vector type (double or float), C coefficient storage type (double, float or
 // uint16_t = bfloat16; with bfloat16 the centre block comes from an FP32 array).
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace rmg {
@@ -121,11 +123,22 @@ constexpr int kT3Plane = 1544;     // max (ty+2)(tx+2) over tx*ty <= 512
 constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
 
 // Grid = one block per tile, or (persistent launch) fewer blocks that stride over the tile list.
-template <class V, class C, StencilOp OP, bool DOT>
+// SYM: the operator is symmetric and `coef` holds only the upper half of each stencil (offsets
+// s = 13..26 of the 27-point order, kSymPts per node, wave-tiled); a lower coupling A(i, i+s),
+// s < 13, is the upper coupling A(i+s, i) stored with node i+s at offset 26 - s.  Each thread
+// streams its node's 14 couplings once and leaves the ones its neighbours need in LDS: the
+// couplings towards z+1 for the next plane, the in-plane ones for this plane.  Only neighbours
+// outside the tile (its edge rows, and plane z-1 of the tile's first plane) are read from memory,
+// so HBM carries about 14 instead of 27 coefficients per node.
+template <class V, class C, StencilOp OP, bool DOT, bool SYM>
 __global__ __launch_bounds__(kT3) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles, int ntiles,
                                                    const C* __restrict__ coef, const float* __restrict__ centre,
                                                    OpP<V> p, double* __restrict__ partials) {
   __shared__ V pl[2][kT3Plane];
+  // SYM: the previous plane's couplings towards z+1 (9 per tile node) and this plane's in-plane upper
+  // couplings (4 per tile node), indexed by the tile-local node = thread index
+  __shared__ C sprev[SYM ? 9 : 1][SYM ? kT3 : 1];
+  __shared__ C srow[SYM ? 4 : 1][SYM ? kT3 : 1];
   const int t = threadIdx.x;
   double contrib = 0.0;
   for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
@@ -185,16 +198,75 @@ __global__ __launch_bounds__(kT3) void k_stencil3d(LevelView L, const Tile3* __r
       const int sp = (zz - z0) & 1;  // slot holding plane zz+1
       if (active) readn(sp, rp);
       fetch(zz + 2);
+      // SYM: own upper couplings u[k] = A(i, i + offset(13 + k)); lower couplings lo[s] = A(i, i +
+      // offset(s)) = A(i + offset(s), i), from LDS when the neighbour is a node of this tile (and,
+      // for z-1, when this tile computed that plane), else from the neighbour's record in memory.
+      V up[SYM ? kSymPts : 1], lo[SYM ? 13 : 1];
+      if constexpr (SYM) {
+        const int li = zz * sz + y * sy + x;
+        const int64_t gi = R.off + li;
+        const bool inner = x > 0 && x < R.ex - 1 && y > 0 && y < R.ey - 1 && zz > 0 && zz < R.ez - 1;
+        auto nb_ok = [&](int dx, int dy, int dz) {
+          return inner || ((unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
+                           (unsigned)(zz + dz) < (unsigned)R.ez);
+        };
+        auto in_tile = [&](int dx, int dy) {
+          return (unsigned)(tx + dx) < (unsigned)T.tx && (unsigned)(ty + dy) < (unsigned)T.ty;
+        };
+        auto mirror = [&](int s, int dx, int dy, int dz) {  // A(i + offset(s), i) from memory
+          return (V)CoefLoad<C>::get(coef + coef_index(gi + dx + dy * sy + dz * sz, 13 - s, kSymPts));
+        };
+        if (active) {
+          const C* __restrict__ cf = coef + coef_index(gi, 0, kSymPts);
+#pragma unroll
+          for (int k = 0; k < kSymPts; ++k) up[k] = (V)CoefLoad<C>::get(cf + k * kTile);
+#pragma unroll
+          for (int s = 0; s < 9; ++s) {  // z-1: the neighbour's coupling towards z+1
+            const int dx = s % 3 - 1, dy = s / 3 - 1;
+            V v = (V)0;
+            if (nb_ok(dx, dy, -1)) v = (zz > z0 && in_tile(dx, dy)) ? (V)sprev[8 - s][t + dx + dy * T.tx] : mirror(s, dx, dy, -1);
+            lo[s] = v;
+          }
+#pragma unroll
+          for (int k = 1; k < 5; ++k) srow[k - 1][t] = (C)up[k];
+        }
+        __syncthreads();  // srow visible; every read of sprev done
+        if (active) {
+#pragma unroll
+          for (int k = 5; k < kSymPts; ++k) sprev[k - 5][t] = (C)up[k];
+#pragma unroll
+          for (int s = 9; s < 13; ++s) {  // in-plane lower couplings
+            int dx, dy, dz;
+            stencil_offset<27>(s, dx, dy, dz);
+            V v = (V)0;
+            if (nb_ok(dx, dy, 0)) v = in_tile(dx, dy) ? (V)srow[12 - s][t + dx + dy * T.tx] : mirror(s, dx, dy, 0);
+            lo[s] = v;
+          }
+        }
+      }
       if (active) {
         const int li = zz * sz + y * sy + x;
         const int64_t gi = R.off + li;
-        const C* __restrict__ cf = coef + coef_index(gi, 0, 27);
         V acc = (V)0;
+        if constexpr (SYM) {
 #pragma unroll
-        for (int s = 0; s < 27; ++s) {
-          const int j = s % 9, dz = s / 9 - 1;
-          const V v = dz < 0 ? rm[j] : (dz == 0 ? rc[j] : rp[j]);
-          acc += (V)coefv<27, 1, C>(cf, centre, gi, s, 0, 0) * v;
+          for (int s = 13; s < 27; ++s) {
+            const int j = s % 9, dz = s / 9 - 1;
+            acc += up[s - 13] * (dz == 0 ? rc[j] : rp[j]);
+          }
+#pragma unroll
+          for (int s = 0; s < 13; ++s) {
+            const int j = s % 9;
+            acc += lo[s] * (s < 9 ? rm[j] : rc[j]);
+          }
+        } else {
+          const C* __restrict__ cf = coef + coef_index(gi, 0, 27);
+#pragma unroll
+          for (int s = 0; s < 27; ++s) {
+            const int j = s % 9, dz = s / 9 - 1;
+            const V v = dz < 0 ? rm[j] : (dz == 0 ? rc[j] : rp[j]);
+            acc += (V)coefv<27, 1, C>(cf, centre, gi, s, 0, 0) * v;
+          }
         }
         const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
         if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
@@ -263,8 +335,16 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   if (a.ev0) RMG_HIP(hipEventRecord(a.ev0, st));
   if constexpr (NPTS == 27 && NDOF == 1) {
     if (tiled) {
-      hipLaunchKernelGGL((k_stencil3d<V, C, OP, DOT>), dim3(grid3), dim3(kT3), 0, st, v, L.d_tiles.as<Tile3>(),
-                         ntiles, coef, centre, p, a.partials);
+      const C* sym = nullptr;
+      if constexpr (std::is_same<V, C>::value) sym = static_cast<const C*>(a.lowp ? L.coef_lo_sym.p : L.coef_sym.p);
+      if (sym) {
+        if constexpr (std::is_same<V, C>::value)
+          hipLaunchKernelGGL((k_stencil3d<V, C, OP, DOT, true>), dim3(grid3), dim3(kT3), 0, st, v,
+                             L.d_tiles.as<Tile3>(), ntiles, sym, centre, p, a.partials);
+      } else {
+        hipLaunchKernelGGL((k_stencil3d<V, C, OP, DOT, false>), dim3(grid3), dim3(kT3), 0, st, v,
+                           L.d_tiles.as<Tile3>(), ntiles, coef, centre, p, a.partials);
+      }
     }
   }
   if (!tiled && L.per_region) {

@@ -238,6 +238,9 @@ static int build_levels(rmg_handle* h, bool stored) {
     L.ct_lo = kCoefF64;
     L.coef_lo.release();
     L.center_lo.release();
+    L.coef_lo_sym.release();
+    if (o.symmetric && l < o.nlevels - 1) launch_make_sym(L, false, st);
+    else L.coef_sym.release();
     if (lowp) alloc_vectors_lowp(L, true);  // level 0's b32 holds the FP32 copy of the CG residual
     if (l == o.nlevels - 1) {
       build_coarse_solver(h, L);
@@ -271,7 +274,10 @@ static int build_levels(rmg_handle* h, bool stored) {
     }
     launch_rap(L, *C, st);
     // the V-cycle's copy of this level's operator, made after the Galerkin product used it
-    if (lowp) launch_make_lowp(L, (l == 0 && o.precision == RMG_PREC_FP32_BF16) ? kCoefBF16 : kCoefF32, st);
+    if (lowp) {
+      launch_make_lowp(L, (l == 0 && o.precision == RMG_PREC_FP32_BF16) ? kCoefBF16 : kCoefF32, st);
+      if (o.symmetric) launch_make_sym(L, true, st);
+    }
     if (o.autotune && !L.per_region && L.dim == 3 && L.ndof == 1 && L.npts == 27) autotune_level(h, L, l, lowp);
   }
   if (lowp) h->cg_z32.alloc(sizeof(float) * (size_t)L0->ndofs());

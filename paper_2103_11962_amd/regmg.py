@@ -37,7 +37,7 @@ SYMBOLS = (
     "rmg_get_prolongator_weights", "rmg_convergence_factor", "rmg_mlp_create", "rmg_mlp_destroy",
     "rmg_mlp_set_params", "rmg_mlp_get_params", "rmg_mlp_add_data", "rmg_mlp_add_samples", "rmg_mlp_clear_data",
     "rmg_mlp_num_data", "rmg_mlp_get_data", "rmg_mlp_forward", "rmg_mlp_loss_grad", "rmg_mlp_adam_step",
-    "rmg_mlp_train", "rmg_mlp_init_params",
+    "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel",
 )
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
 P_GEOMETRIC, P_STORED, P_LEARNED = 0, 1, 2
@@ -58,6 +58,7 @@ class Options(ctypes.Structure):
         ("autotune", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("autotune_cache", ctypes.c_char_p),
+        ("symmetric", ctypes.c_int),
         ("batched", ctypes.c_int),
         ("judge_cycles", ctypes.c_int),
     ]
@@ -144,6 +145,7 @@ def load():
         "rmg_mlp_adam_step": (I, [H, P, D]),
         "rmg_mlp_train": (I, [H, I, D, P]),
         "rmg_mlp_init_params": (I, [H, ctypes.c_uint64, D, P]),
+        "rmg_level_kernel": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -297,6 +299,11 @@ class Handle:
         _check(load().rmg_level_info(self._h, level, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(npts),
                                      ctypes.byref(lam)))
         return {"n_regional": nr.value, "n_composite": nc.value, "npts": npts.value, "lambda": lam.value}
+
+    def level_kernel(self, level):
+        k, c, cl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().rmg_level_kernel(self._h, level, ctypes.byref(k), ctypes.byref(c), ctypes.byref(cl)))
+        return {"kernel": k.value, "coefs": c.value, "coefs_lo": cl.value}
 
     def level_stencil(self, level, region, npts, nnodes):
         out = np.zeros(npts * nnodes)

@@ -255,3 +255,65 @@ def test_mixed_vcycle_close_to_fp64(hip_device):
         err = rel(z.cpu().numpy(), ref)
         h.close()
         assert err < tol, (precision, err)
+
+
+@pytest.mark.parametrize("kernel", [2, 3])
+def test_half_stencil_matches_full(hip_device, kernel):
+    """Symmetric levels: the 2.5D kernel on the stored upper half (lower couplings read from the
+    neighbours) gives the full-stencil solve to rounding, at oracle parity, also with FP32 copies."""
+    import torch
+
+    from oracle import regional
+
+    w = synth.workload("c2_mid")
+    lay, levels, opt = harness.oracle_problem(w)
+    b = synth.rhs(w)
+    ref = regional.pcg(levels, lay.to_regional(b), opt, rtol=1e-8, maxit=100)
+    xs = {}
+    for sym in (0, 1):
+        h = harness.gpu_problem(w, stencil_kernel=kernel, symmetric=sym)
+        x = torch.zeros(lay.n_composite, dtype=torch.float64, device="cuda:0")
+        out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100)
+        assert out["iterations"] == ref.iterations
+        xs[sym] = x.cpu().numpy()
+        assert rel(xs[sym], lay.to_composite_owner(ref.x).reshape(-1)) < 1e-10
+        h.close()
+        hl = harness.gpu_problem(w, stencil_kernel=kernel, symmetric=sym, precision=1)
+        x.zero_()
+        out = hl.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100)
+        assert out["converged"] and out["true_relres"] <= 1.5e-8
+        hl.close()
+    assert rel(xs[1], xs[0]) < 1e-12
+
+
+def test_asymmetric_stencils_use_the_full_kernel(hip_device):
+    """Caller stencils that are not symmetric keep all 27 couplings: the tiled matvec equals the
+    oracle's regional matvec of the same stencils."""
+    import torch
+
+    from oracle import assembly
+    from oracle.regions import Layout
+
+    w = synth.workload("c2_mid")
+    lay = Layout(w.dim, w.origins, w.extents, w.dirichlet_mask)
+    coefs = assembly.regional_q1(lay, "laplace", h=w.h)
+    rng = np.random.default_rng(4)
+    pert = []
+    for k, c in enumerate(coefs):
+        c = c.copy()
+        c[:13] *= 1.0 + 0.05 * rng.uniform(0.0, 1.0, size=c[:13].shape)  # lower couplings only
+        pert.append(c)
+    from paper_2103_11962_amd import regmg
+
+    h = regmg.Handle(0)
+    h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
+    for k, c in enumerate(pert):
+        h.set_region_stencil(k, 27, harness.stencil_soa(c, 3))
+    h.setup_hierarchy(nlevels=2, cheb_degree=w.cheb_degree, stencil_kernel=2)
+    x = rng.uniform(-1, 1, size=lay.shape)
+    reg = harness.to_dev(lay.flatten(lay.to_regional(x)))
+    z = torch.empty_like(reg)
+    h.regional_matvec(0, reg, z)
+    ref = lay.interface_sum([assembly.apply_stencil(pert[k], lay.to_regional(x)[k], 3, 1) for k in range(lay.nreg)])
+    assert rel(z.cpu().numpy(), lay.flatten(ref)) < 1e-13
+    h.close()
