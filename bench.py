@@ -38,8 +38,8 @@ def cg_matvec_bytes_per_row(coefs):
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
-TRAFFIC_BYTES = 9628103346
-TRAFFIC_KERNEL_SHA = "d5d65f0d81f8f4a6"
+TRAFFIC_BYTES = 6364174191
+TRAFFIC_KERNEL_SHA = "a99af12a8afd74e5"
 
 CPU_SAMPLE = r"""
 import json, sys, time
