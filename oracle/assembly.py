@@ -214,6 +214,41 @@ def composite_q1(lay: Layout, pde, h=1.0, elem_coef=None, youngs=None, nu=0.3):
     return eliminate_csr(A, dirichlet_dofs(lay))
 
 
+def q1_rows(shape_xyz, dirichlet, x, nodes, pde, h=1.0, elem_coef=None, nu=0.3):
+    """Rows of the composite Q1 product A x at selected nodes, evaluated one by one from the
+    element definition (for sizes where A itself is too large to assemble here).
+
+    A free node's row sums c_e K_e over the (up to 8) elements containing it, with the columns of
+    Dirichlet unknowns removed (symmetric elimination); a Dirichlet node's row is the identity.
+    ``elem_coef`` (composite element grid, [z][y][x]) is the diffusion coefficient, or the
+    Young's modulus per element for elasticity (K_e is linear in E); x is a composite array
+    [z][y][x] (and [dof] for elasticity).  Returns an array (len(nodes),) or (len(nodes), 3).
+    """
+    nx, ny, nz = shape_xyz
+    elastic = pde == "elasticity"
+    K = fem.q1_elasticity(1.0, nu, h) if elastic else fem.q1_laplace(h)
+    nd = 3 if elastic else 1
+    out = np.zeros((len(nodes), nd))
+    for r, (gx, gy, gz) in enumerate(nodes):
+        if dirichlet[gz, gy, gx]:
+            out[r] = x[gz, gy, gx]
+            continue
+        for ez in (gz - 1, gz):
+            for ey in (gy - 1, gy):
+                for ex in (gx - 1, gx):
+                    if not (0 <= ex < nx - 1 and 0 <= ey < ny - 1 and 0 <= ez < nz - 1):
+                        continue
+                    c = 1.0 if elem_coef is None else float(elem_coef[ez, ey, ex])
+                    a = (gx - ex) + 2 * (gy - ey) + 4 * (gz - ez)
+                    for b, cb in enumerate(fem.CORNERS3):
+                        bx, by, bz = ex + cb[0], ey + cb[1], ez + cb[2]
+                        if dirichlet[bz, by, bx]:
+                            continue
+                        xb = np.atleast_1d(x[bz, by, bx])
+                        out[r] += c * (K[nd * a:nd * a + nd, nd * b:nd * b + nd] @ xb)
+    return out[:, 0] if nd == 1 else out
+
+
 # --------------------------------------------------------- regional matrices
 def regional_q1(lay: Layout, pde, h=1.0, elem_coef=None, youngs=None, nu=0.3):
     """Per-region element assembly: A^(k) collects the elements inside region k.

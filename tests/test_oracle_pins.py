@@ -440,3 +440,33 @@ def test_iterations_roughly_mesh_independent():
         res = regional.pcg(lv, lay.to_regional(synth.rhs(wl)), opt)
         its.append(res.iterations)
     assert max(its) - min(its) <= 4, its
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c5_small", "c3_small"])
+def test_q1_rows_match_assembled_operator(name):
+    """Row-by-row evaluation of A x (used at sizes too large to assemble) equals the rows of the
+    assembled composite operator, at every kind of node (interior, interface, boundary)."""
+    from oracle import assembly
+    from oracle.regions import Layout
+
+    w = synth.workload(name)
+    lay = Layout(w.dim, w.origins, w.extents, w.dirichlet_mask, w.ndof)
+    ec = synth.jump_coefficients(w) if w.pde == "diffusion" else None
+    youngs = synth.region_youngs_moduli(w) if w.pde == "elasticity" else None
+    A = assembly.composite_q1(lay, w.pde, h=w.h, elem_coef=ec, youngs=youngs, nu=w.nu)
+    rng = np.random.default_rng(3)
+    shp = lay.shape + ((3,) if w.ndof == 3 else ())
+    x = rng.uniform(-1, 1, size=shp)
+    ref = (A @ x.reshape(-1)).reshape(shp)
+    nz, ny, nx = lay.shape
+    nodes = [tuple(int(v) for v in rng.integers(0, [nx, ny, nz])) for _ in range(60)]
+    nodes += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx // 2, ny // 2, nz // 2), (1, 1, 1)]
+    coef = ec
+    if w.pde == "elasticity":  # Young's modulus per element from the region containing it
+        coef = np.zeros((nz - 1, ny - 1, nx - 1))
+        for k in range(lay.nreg):
+            o, e = lay.origins[k], lay.extents[k]
+            coef[o[2]:o[2] + e[2] - 1, o[1]:o[1] + e[1] - 1, o[0]:o[0] + e[0] - 1] = youngs[k]
+    got = assembly.q1_rows((nx, ny, nz), lay.dirichlet, x, nodes, w.pde, h=w.h, elem_coef=coef, nu=w.nu)
+    want = np.array([ref[gz, gy, gx] for gx, gy, gz in nodes])
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
