@@ -85,15 +85,6 @@ def cpu_baseline(gpu_iterations: int, n_rows: int):
     }
 
 
-# Algorithmic bytes per regional node of the finest-level fused Chebyshev step (stencil product,
-# residual, direction and iterate update): coefficients once, u, b, D~^-1, d read, d, u written.
-CHEB_BYTES = {
-    ("scalar", 0): 27 * 8 + 6 * 8,             # FP64: 264
-    ("scalar", 1): 27 * 4 + 6 * 4,             # FP32 coefficients and vectors: 132
-    ("block3", 0): 27 * 9 * 8 + 6 * 3 * 8,     # elasticity FP64: 2088
-    ("block3", 1): 27 * 9 * 4 + 6 * 3 * 4,     # FP32: 1044
-    ("block3", 2): 26 * 9 * 2 + 9 * 4 + 6 * 3 * 4,  # BF16 off-diagonal blocks, FP32 centre block: 576
-}
 PREC_NAME = {0: "fp64", 1: "fp32", 2: "fp32_bf16"}
 
 
@@ -144,13 +135,16 @@ def _setup(h, w, **opts):
 
 
 def _cheb_bytes(h, kind, precision):
-    """Algorithmic bytes per node of the level-0 Chebyshev step as the level runs it."""
+    """Algorithmic bytes per node of the level-0 Chebyshev step as the level runs it: the
+    coefficients it streams (full or upper-half stencil, see rmg_level_kernel), u, b, D~^-1, d read
+    and d, u written; with BF16 storage the centre block comes from an FP32 array."""
     lk = h.level_kernel(0)
-    if kind == "scalar":
-        coefs = lk["coefs"] if precision == 0 else lk["coefs_lo"]
-        width = 8 if precision == 0 else 4
-        return coefs * width + 6 * width
-    return CHEB_BYTES[(kind, precision)]
+    nd = 1 if kind == "scalar" else 3
+    if precision == 0:
+        return lk["coefs"] * 8 + 6 * nd * 8
+    if precision == 1:
+        return lk["coefs_lo"] * 4 + 6 * nd * 4
+    return (lk["coefs_lo"] - nd * nd) * 2 + nd * nd * 4 + 6 * nd * 4
 
 
 def _cheb_gbs(h, kind, precision, rows):
@@ -180,7 +174,7 @@ def variant_mixed(dev):
         entry = {"setup_ms": setup_ms, "solve_ms": ms, "iterations": res["iterations"],
                  "true_relres": res["true_relres"],
                  "cheb_gbs": _cheb_gbs(h, "block3", prec, rows),
-                 "cheb_bytes_per_node": CHEB_BYTES[("block3", prec)]}
+                 "cheb_bytes_per_node": _cheb_bytes(h, "block3", prec)}
         if prec == 0:
             x64 = x.clone()
         else:

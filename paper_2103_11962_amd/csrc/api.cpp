@@ -547,8 +547,11 @@ rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, i
   Level& L = level_of(h, level);
   const bool tiled = L.use_tiles && L.ndof == 1 && L.npts == 27;
   if (kernel) *kernel = L.per_region ? 3 : (!tiled ? 0 : (L.tile_grid > 0 && L.tile_grid < (int)L.tiles.size() ? 2 : 1));
-  if (coefs) *coefs = (tiled && L.coef_sym.p) ? kSymPts : L.ncoef();
-  if (coefs_lo) *coefs_lo = L.ct_lo == kCoefF64 ? 0 : ((tiled && L.coef_lo_sym.p) ? kSymPts : L.ncoef());
+  const int nb = L.ndof * L.ndof;
+  if (coefs) *coefs = L.coef_sym.p ? kSymPts * nb : L.ncoef();
+  // the 2.5D kernel has no half-stencil path for BF16 storage
+  const bool sym_lo = L.coef_lo_sym.p && !(tiled && L.ct_lo == kCoefBF16);
+  if (coefs_lo) *coefs_lo = L.ct_lo == kCoefF64 ? 0 : (sym_lo ? kSymPts * nb : L.ncoef());
   API_END
 }
 

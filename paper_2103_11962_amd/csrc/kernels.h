@@ -76,9 +76,10 @@ void launch_f32_to_f64(int64_t n, const float* in, double* out, hipStream_t st);
 // centre blocks whose diagonal keeps each row sum of the FP64 operator) and dinv_lo.
 void launch_make_lowp(Level& L, int coef_type, hipStream_t st);
 
-// Upper-half stencil copy (L.coef_sym, or L.coef_lo_sym from the FP32 copy when lowp) of a scalar
-// 27-point 3D level whose operator is symmetric to rounding; returns false (and leaves the copy
-// empty) otherwise.  The 2.5D kernel then streams 14 instead of 27 coefficients per node.
+// Upper-half stencil copy of a 27-point 3D level (scalar or 3x3 blocks) whose FP64 operator is
+// symmetric to rounding: L.coef_sym, or with lowp L.coef_lo_sym from the low-precision copy of a
+// level that has L.coef_sym; returns false (and leaves the copy empty) otherwise.  The stencil
+// kernels then stream 14 instead of 27 blocks per node.
 bool launch_make_sym(Level& L, bool lowp, hipStream_t st);
 
 // Composite <-> regional (FP64).

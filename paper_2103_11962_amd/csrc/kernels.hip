@@ -1249,12 +1249,14 @@ void launch_make_lowp(Level& L, int coef_type, hipStream_t st) {
 }
 
 // ------------------------------------------------------ symmetric half stencil
-// Upper half (offsets 13..26) of a scalar 27-point level's stencils.  flag is set unless every
-// lower coupling equals the neighbour's mirrored upper coupling to rounding,
-// |A(i, i+s) - A(i+s, i)| <= tol (|A_ii| + |A_jj|), and couplings leaving the region box are zero.
-template <class C>
+// Upper half (offsets 13..26, NDOF x NDOF blocks) of a 27-point level's stencils.  With a flag the
+// FP64 operator is also checked: the flag is set unless every lower block equals the transposed
+// upper block of the neighbour to rounding, |A(i, i+s)_ab - A(i+s, i)_ba| <= tol (d_i + d_j) with d
+// the largest diagonal entry of a node's centre block, and couplings leaving the region are zero.
+template <int NDOF, class C>
 __global__ __launch_bounds__(kBlock) void k_make_sym(LevelView L, const C* __restrict__ coef, C* __restrict__ sym,
                                                      double tol, int* flag) {
+  constexpr int NB = NDOF * NDOF, NC = 27 * NB, NS = kSymPts * NB;
   const BlockDesc bd = L.blocks[blockIdx.x];
   const RegionGeo R = L.regs[bd.region];
   const int li = bd.start + (int)threadIdx.x;
@@ -1262,46 +1264,72 @@ __global__ __launch_bounds__(kBlock) void k_make_sym(LevelView L, const C* __res
   int x, y, z;
   decompose(R, li, x, y, z);
   const int64_t gi = R.off + li;
-  for (int s = 13; s < 27; ++s) sym[coef_index(gi, s - 13, kSymPts)] = coef[coef_index(gi, s, 27)];
-  const double dii = fabs((double)coef[coef_index(gi, 13, 27)]);
+  for (int k = 0; k < NS; ++k) sym[coef_index(gi, k, NS)] = coef[coef_index(gi, 13 * NB + k, NC)];
+  if (!flag) return;
+  auto dmax = [&](int64_t g) {
+    double d = 0.0;
+    for (int a = 0; a < NDOF; ++a) d = fmax(d, fabs((double)coef[coef_index(g, 13 * NB + a * NDOF + a, NC)]));
+    return d;
+  };
+  const double dii = dmax(gi);
   bool bad = false;
   for (int s = 0; s < 13; ++s) {
     int dx, dy, dz;
     stencil_offset<27>(s, dx, dy, dz);
-    const double a = (double)coef[coef_index(gi, s, 27)];
-    if ((unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
-        (unsigned)(z + dz) < (unsigned)R.ez) {
-      const int64_t gn = gi + dx + (int64_t)dy * R.ex + (int64_t)dz * R.ex * R.ey;
-      const double b = (double)coef[coef_index(gn, 26 - s, 27)];
-      const double djj = fabs((double)coef[coef_index(gn, 13, 27)]);
-      if (!(fabs(a - b) <= tol * (dii + djj))) bad = true;
-    } else if (a != 0.0) {
-      bad = true;
-    }
+    const bool in = (unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
+                    (unsigned)(z + dz) < (unsigned)R.ez;
+    const int64_t gn = gi + dx + (int64_t)dy * R.ex + (int64_t)dz * R.ex * R.ey;
+    const double djj = in ? dmax(gn) : 0.0;
+    for (int a = 0; a < NDOF; ++a)
+      for (int b = 0; b < NDOF; ++b) {
+        const double v = (double)coef[coef_index(gi, s * NB + a * NDOF + b, NC)];
+        if (!in) {
+          if (v != 0.0) bad = true;
+          continue;
+        }
+        const double m = (double)coef[coef_index(gn, (26 - s) * NB + b * NDOF + a, NC)];
+        if (!(fabs(v - m) <= tol * (dii + djj))) bad = true;
+      }
   }
   if (bad) atomicOr(flag, 1);
+}
+
+template <int NDOF>
+static void make_sym_t(Level& L, bool lowp, int* flag, hipStream_t st) {
+  const size_t ne = coef_elems(L.n, kSymPts * NDOF * NDOF);
+  const dim3 g(L.blocks.size()), b(kBlock);
+  if (!lowp) {
+    L.coef_sym.alloc(sizeof(double) * ne);
+    hipLaunchKernelGGL((k_make_sym<NDOF, double>), g, b, 0, st, L.view(), L.coef.as<double>(), L.coef_sym.as<double>(),
+                       1e-11, flag);
+  } else if (L.ct_lo == kCoefF32) {
+    L.coef_lo_sym.alloc(sizeof(float) * ne);
+    hipLaunchKernelGGL((k_make_sym<NDOF, float>), g, b, 0, st, L.view(), L.coef_lo.as<float>(),
+                       L.coef_lo_sym.as<float>(), 0.0, nullptr);
+  } else {
+    L.coef_lo_sym.alloc(sizeof(uint16_t) * ne);
+    hipLaunchKernelGGL((k_make_sym<NDOF, uint16_t>), g, b, 0, st, L.view(), L.coef_lo.as<uint16_t>(),
+                       L.coef_lo_sym.as<uint16_t>(), 0.0, nullptr);
+  }
+  LAUNCH_CHECK();
 }
 
 bool launch_make_sym(Level& L, bool lowp, hipStream_t st) {
   DBuf& out = lowp ? L.coef_lo_sym : L.coef_sym;
   out.release();
-  if (L.dim != 3 || L.ndof != 1 || L.npts != 27) return false;
-  if (lowp && L.ct_lo != kCoefF32) return false;
+  if (L.dim != 3 || L.npts != 27) return false;
+  if (lowp) {
+    // the low-precision copy rounds the same symmetric values: copy its upper half
+    if (!L.coef_sym.p || L.ct_lo == kCoefF64) return false;
+    if (L.ndof == 3) make_sym_t<3>(L, true, nullptr, st);
+    else make_sym_t<1>(L, true, nullptr, st);
+    return true;
+  }
   DBuf flag;
   flag.alloc(sizeof(int));
   RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
-  const size_t ne = coef_elems(L.n, kSymPts);
-  const dim3 g(L.blocks.size()), b(kBlock);
-  if (lowp) {
-    out.alloc(sizeof(float) * ne);
-    hipLaunchKernelGGL(k_make_sym<float>, g, b, 0, st, L.view(), L.coef_lo.as<float>(), out.as<float>(), 1e-6,
-                       flag.as<int>());
-  } else {
-    out.alloc(sizeof(double) * ne);
-    hipLaunchKernelGGL(k_make_sym<double>, g, b, 0, st, L.view(), L.coef.as<double>(), out.as<double>(), 1e-11,
-                       flag.as<int>());
-  }
-  LAUNCH_CHECK();
+  if (L.ndof == 3) make_sym_t<3>(L, false, flag.as<int>(), st);
+  else make_sym_t<1>(L, false, flag.as<int>(), st);
   int hflag = 0;
   RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));

@@ -63,11 +63,16 @@ __device__ __forceinline__ auto coefv(const C* __restrict__ cf, const float* __r
 }
 
 // ---------------------------------------------------------------- node-parallel
-template <int NPTS, int NDOF, class V, class C, StencilOp OP, bool DOT>
+// SYM (27-point levels whose operator is symmetric): `coef` holds the upper half of each stencil,
+// kSymPts blocks per node; the block of a lower offset s is the transpose of the neighbour's
+// upper block at offset 26 - s, read from the neighbour's record (consecutive lanes read
+// consecutive records, and the record was streamed moments before by a nearby block).
+template <int NPTS, int NDOF, class V, class C, StencilOp OP, bool DOT, bool SYM>
 __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __restrict__ coef,
                                                     const float* __restrict__ centre, OpP<V> p,
                                                     double* __restrict__ partials) {
-  constexpr int NCOEF = NPTS * NDOF * NDOF;
+  constexpr int NB = NDOF * NDOF;
+  constexpr int NCOEF = SYM ? kSymPts * NB : NPTS * NB;
   const BlockDesc bd = L.blocks[blockIdx.x];
   const RegionGeo R = L.regs[bd.region];
   const int li = bd.start + (int)threadIdx.x;
@@ -91,10 +96,32 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
                                 (unsigned)(z + dz) < (unsigned)R.ez);
       if (ok) {
         const int nb = li + dx + dy * sy + dz * sz;
+        if constexpr (SYM) {
+          if (s >= 13) {
 #pragma unroll
-        for (int a = 0; a < NDOF; ++a)
+            for (int a = 0; a < NDOF; ++a)
 #pragma unroll
-          for (int b = 0; b < NDOF; ++b) acc[a] += (V)coefv<NPTS, NDOF, C>(cf, centre, gi, s, a, b) * xr[nb * NDOF + b];
+              for (int b = 0; b < NDOF; ++b) {
+                V c;
+                if (sizeof(C) == 2 && s == 13) c = (V)centre[gi * NB + a * NDOF + b];
+                else c = (V)CoefLoad<C>::get(cf + ((s - 13) * NB + a * NDOF + b) * kTile);
+                acc[a] += c * xr[nb * NDOF + b];
+              }
+          } else {
+            const C* __restrict__ cn = coef + coef_index(R.off + nb, 0, NCOEF);
+#pragma unroll
+            for (int a = 0; a < NDOF; ++a)
+#pragma unroll
+              for (int b = 0; b < NDOF; ++b)
+                acc[a] += (V)CoefLoad<C>::get(cn + ((13 - s) * NB + b * NDOF + a) * kTile) * xr[nb * NDOF + b];
+          }
+        } else {
+#pragma unroll
+          for (int a = 0; a < NDOF; ++a)
+#pragma unroll
+            for (int b = 0; b < NDOF; ++b)
+              acc[a] += (V)coefv<NPTS, NDOF, C>(cf, centre, gi, s, a, b) * xr[nb * NDOF + b];
+        }
       }
     }
     if (!inner && is_shared(L, R, x, y, z)) {
@@ -347,20 +374,32 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
       }
     }
   }
-  if (!tiled && L.per_region) {
-    // unbatched: one launch per region over its slice of the block table (partials keep their slots)
-    for (int k = 0; k < L.nreg; ++k) {
-      const int b0 = L.region_block[k], b1 = L.region_block[k + 1];
-      if (b1 == b0) continue;
-      LevelView vk = v;
-      vk.blocks = v.blocks + b0;
-      vk.nblocks = b1 - b0;
-      hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT>), dim3(b1 - b0), dim3(kBlock), 0, st, vk, coef,
-                         centre, p, a.partials ? a.partials + b0 : nullptr);
+  if (!tiled) {
+    const C* symc = static_cast<const C*>(a.lowp ? L.coef_lo_sym.p : L.coef_sym.p);
+    auto node = [&](const LevelView& vk, int nblocks, double* part) {
+      if constexpr (NPTS == 27) {
+        if (symc) {
+          hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT, true>), dim3(nblocks), dim3(kBlock), 0, st, vk,
+                             symc, centre, p, part);
+          return;
+        }
+      }
+      hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT, false>), dim3(nblocks), dim3(kBlock), 0, st, vk, coef,
+                         centre, p, part);
+    };
+    if (L.per_region) {
+      // unbatched: one launch per region over its slice of the block table (partials keep their slots)
+      for (int k = 0; k < L.nreg; ++k) {
+        const int b0 = L.region_block[k], b1 = L.region_block[k + 1];
+        if (b1 == b0) continue;
+        LevelView vk = v;
+        vk.blocks = v.blocks + b0;
+        vk.nblocks = b1 - b0;
+        node(vk, b1 - b0, a.partials ? a.partials + b0 : nullptr);
+      }
+    } else {
+      node(v, (int)L.blocks.size(), a.partials);
     }
-  } else if (!tiled) {
-    hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT>), dim3(L.blocks.size()), dim3(kBlock), 0, st, v, coef,
-                       centre, p, a.partials);
   }
   LAUNCH_CHECK();
   if (a.ev1) RMG_HIP(hipEventRecord(a.ev1, st));

@@ -240,7 +240,7 @@ static int build_levels(rmg_handle* h, bool stored) {
     L.center_lo.release();
     L.coef_lo_sym.release();
     if (o.symmetric && l < o.nlevels - 1) launch_make_sym(L, false, st);
-    else L.coef_sym.release();
+    else L.coef_sym.release();  // (the coarsest level is solved directly)
     if (lowp) alloc_vectors_lowp(L, true);  // level 0's b32 holds the FP32 copy of the CG residual
     if (l == o.nlevels - 1) {
       build_coarse_solver(h, L);

@@ -317,3 +317,24 @@ def test_asymmetric_stencils_use_the_full_kernel(hip_device):
     ref = lay.interface_sum([assembly.apply_stencil(pert[k], lay.to_regional(x)[k], 3, 1) for k in range(lay.nreg)])
     assert rel(z.cpu().numpy(), lay.flatten(ref)) < 1e-13
     h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_block_half_stencil_matches_full(hip_device, precision):
+    """Elasticity (3x3 blocks, node-parallel kernel): the upper-half storage with transposed
+    neighbour blocks gives the full-storage result to rounding in FP64, FP32 and BF16."""
+    import torch
+
+    w = synth.workload("c3_small")
+    b = harness.to_dev(synth.rhs(w))
+    xs, its = {}, {}
+    for sym in (0, 1):
+        h = harness.gpu_problem(w, symmetric=sym, precision=precision)
+        assert h.level_kernel(0)["coefs" if precision == 0 else "coefs_lo"] == (126 if sym else 243)
+        x = torch.zeros_like(b)
+        out = h.solve(b, x, rtol=1e-8, maxit=100)
+        assert out["converged"] and out["true_relres"] <= 1.5e-8
+        xs[sym], its[sym] = x.cpu().numpy(), out["iterations"]
+        h.close()
+    assert its[0] == its[1]
+    assert rel(xs[1], xs[0]) < (1e-12 if precision == 0 else 1e-8)
