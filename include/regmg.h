@@ -157,6 +157,17 @@ rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const dou
  * on_device: coef is a device (1) or host (0) pointer. */
 rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef, int on_device);
 
+/* The same non-invasive split from an assembled composite matrix in CSR form
+ * (Section 4: the application hands over its assembled matrix and the region
+ * layout).  Rows and columns are composite nodes in x-fastest order
+ * (n_composite rows); rowptr int64 [n+1] (0 .. nnz, non-decreasing, checked on
+ * the host), colind int32 [nnz], values FP64 [nnz]; duplicate entries add up.
+ * Every entry must couple nodes within the npts neighbourhood (RMG_ERR_SHAPE
+ * otherwise; out-of-range columns RMG_ERR_ARG, NaN/Inf RMG_ERR_NUMERIC).
+ * on_device: the three arrays are device (1) or host (0) pointers. */
+rmg_status rmg_set_composite_csr(rmg_handle* h, int npts, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+                                 const double* values, int on_device);
+
 /* Assemble every region's matrix on the device from Q1 hexahedral elements of
  * side h inside that region (one admissible split of A, Section 3.1), with
  * symmetric elimination of Dirichlet nodes (identity rows split 1/mult).

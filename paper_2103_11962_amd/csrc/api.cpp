@@ -282,24 +282,16 @@ static bool tensor_layout(const rmg_handle* h) {
   return combos == (size_t)h->nreg;
 }
 
-rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef, int on_device) {
-  API_BEGIN
-  use_device(h);
-  Level& L = level_of(h, 0);
-  L.coef_sym.release();  // the half stencils of the old operator
-  L.coef_lo_sym.release();
-  RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
+// Shared checks of the composite split (Section 4) for a stencil or CSR input.
+static void check_composite_split(rmg_handle* h, int npts) {
   const bool ok = (h->dim == 3 && npts == 27) || (h->dim == 2 && (npts == 5 || npts == 9));
   RMG_REQUIRE(ok, RMG_ERR_ARG, "npts must be 27 in 3D and 5 or 9 in 2D");
   RMG_REQUIRE(h->ndof == 1, RMG_ERR_ARG, "the composite split handles scalar problems");
   RMG_REQUIRE(tensor_layout(h), RMG_ERR_SHAPE, "the composite split needs a tensor-product region layout");
-  DBuf tmp;
-  const double* src = coef;
-  if (!on_device) {
-    tmp.alloc(sizeof(double) * (size_t)npts * L.ncomp);
-    RMG_HIP(hipMemcpyAsync(tmp.p, coef, sizeof(double) * (size_t)npts * L.ncomp, hipMemcpyHostToDevice, h->stream));
-    src = tmp.as<double>();
-  }
+}
+
+// Region matrices from a device composite stencil [npts][ncomp].
+static void split_into_regions(rmg_handle* h, Level& L, int npts, const double* src) {
   L.npts = npts;
   L.coef.alloc(sizeof(double) * coef_elems(L.n, npts));
   DBuf flag;
@@ -314,6 +306,75 @@ rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef
   h->logc.release();
   h->have_operator = true;
   h->have_hierarchy = false;
+}
+
+rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef, int on_device) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, 0);
+  L.coef_sym.release();  // the half stencils of the old operator
+  L.coef_lo_sym.release();
+  RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
+  check_composite_split(h, npts);
+  DBuf tmp;
+  const double* src = coef;
+  if (!on_device) {
+    tmp.alloc(sizeof(double) * (size_t)npts * L.ncomp);
+    RMG_HIP(hipMemcpyAsync(tmp.p, coef, sizeof(double) * (size_t)npts * L.ncomp, hipMemcpyHostToDevice, h->stream));
+    src = tmp.as<double>();
+  }
+  split_into_regions(h, L, npts, src);
+  API_END
+}
+
+rmg_status rmg_set_composite_csr(rmg_handle* h, int npts, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+                                 const double* values, int on_device) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, 0);
+  L.coef_sym.release();  // the half stencils of the old operator
+  L.coef_lo_sym.release();
+  RMG_REQUIRE(rowptr && (nnz == 0 || (colind && values)) && nnz >= 0, RMG_ERR_ARG, "null CSR array or nnz < 0");
+  check_composite_split(h, npts);
+  const int64_t n = L.ncomp;
+  // row pointers are checked on the host before any kernel reads through them
+  std::vector<int64_t> rp(n + 1);
+  RMG_HIP(hipMemcpyAsync(rp.data(), rowptr, sizeof(int64_t) * (n + 1),
+                         on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, h->stream));
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  RMG_REQUIRE(rp[0] == 0 && rp[n] == nnz, RMG_ERR_ARG, "row pointers must start at 0 and end at nnz");
+  for (int64_t i = 0; i < n; ++i)
+    RMG_REQUIRE(rp[i + 1] >= rp[i], RMG_ERR_ARG, "row pointers must not decrease");
+  DBuf drp, dci, dv, comp, flag;
+  const int64_t* prp = rowptr;
+  const int* pci = colind;
+  const double* pv = values;
+  if (!on_device) {
+    drp.alloc(sizeof(int64_t) * (n + 1));
+    RMG_HIP(hipMemcpyAsync(drp.p, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, h->stream));
+    prp = drp.as<int64_t>();
+    if (nnz > 0) {
+      dci.alloc(sizeof(int32_t) * nnz);
+      dv.alloc(sizeof(double) * nnz);
+      RMG_HIP(hipMemcpyAsync(dci.p, colind, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, h->stream));
+      RMG_HIP(hipMemcpyAsync(dv.p, values, sizeof(double) * nnz, hipMemcpyHostToDevice, h->stream));
+      pci = dci.as<int>();
+      pv = dv.as<double>();
+    }
+  }
+  L.npts = npts;
+  comp.alloc(sizeof(double) * (size_t)npts * n);
+  RMG_HIP(hipMemsetAsync(comp.p, 0, sizeof(double) * (size_t)npts * n, h->stream));
+  flag.alloc(sizeof(int));
+  RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), h->stream));
+  launch_csr_to_stencil(L, prp, pci, pv, comp.as<double>(), flag.as<int>(), h->stream);
+  int hflag = 0;
+  RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  RMG_REQUIRE(!(hflag & 4), RMG_ERR_ARG, "CSR column index out of range");
+  RMG_REQUIRE(!(hflag & 2), RMG_ERR_SHAPE, "CSR entry outside the " + std::to_string(npts) + "-point neighbourhood");
+  RMG_REQUIRE(!(hflag & 1), RMG_ERR_NUMERIC, "CSR values have NaN or Inf entries");
+  split_into_regions(h, L, npts, comp.as<double>());
   API_END
 }
 

@@ -102,6 +102,10 @@ void launch_dirichlet_split(const Level& L, hipStream_t st);
 void launch_mask_stencil(const Level& L, int* flag, hipStream_t st);
 // Region matrices from a composite stencil [npts][ncomp] on a tensor-product layout (Section 4 split).
 void launch_split_composite(const Level& L, const double* comp, int* flag, hipStream_t st);
+// Assembled composite CSR matrix -> composite stencil [L.npts][L.ncomp] (comp zeroed by the caller);
+// flag bits: 1 non-finite value, 2 entry outside the stencil, 4 column out of range.
+void launch_csr_to_stencil(const Level& L, const int64_t* rowptr, const int* colind, const double* vals,
+                           double* comp, int* flag, hipStream_t st);
 // Copy one region's stencil between a structure-of-arrays buffer [ncoef][region nodes] and the
 // level's wave-tiled storage (to_level = 1: soa -> level).
 void launch_region_stencil_io(const Level& L, int region, double* soa, int to_level, hipStream_t st);

@@ -1162,6 +1162,57 @@ void launch_split_composite(const Level& L, const double* comp, int* flag, hipSt
   LAUNCH_CHECK();
 }
 
+// Assembled composite CSR matrix (rows and columns = composite nodes, x fastest) -> composite
+// stencil [npts][ncomp] (zero-initialised by the caller), one thread per row; duplicate entries add
+// up.  Flags: 1 a non-finite value, 2 an entry outside the stencil's neighbourhood, 4 a column
+// index out of range (such entries are skipped).
+template <int NPTS>
+__global__ __launch_bounds__(kBlock) void k_csr_to_stencil(int cx, int cy, int cz, const int64_t* __restrict__ rowptr,
+                                                           const int* __restrict__ colind,
+                                                           const double* __restrict__ vals, double* __restrict__ comp,
+                                                           int* flag) {
+  const int64_t n = (int64_t)cx * cy * cz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int gx = (int)(i % cx), gy = (int)((i / cx) % cy), gz = (int)(i / ((int64_t)cx * cy));
+  int f = 0;
+  for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const int j = colind[e];
+    if (j < 0 || (int64_t)j >= n) {
+      f |= 4;
+      continue;
+    }
+    const int dx = j % cx - gx, dy = (j / cx) % cy - gy, dz = (int)(j / ((int64_t)cx * cy)) - gz;
+    int s = -1;
+    if (NPTS == 27 && abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) s = (dz + 1) * 9 + (dy + 1) * 3 + dx + 1;
+    if (NPTS == 9 && abs(dx) <= 1 && abs(dy) <= 1 && dz == 0) s = (dy + 1) * 3 + dx + 1;
+    if (NPTS == 5 && dz == 0 && abs(dx) + abs(dy) <= 1) s = dy == -1 ? 0 : (dx == -1 ? 1 : (dx == 1 ? 3 : (dy == 1 ? 4 : 2)));
+    if (s < 0) {
+      f |= 2;
+      continue;
+    }
+    const double v = vals[e];
+    if (!isfinite(v)) f |= 1;
+    comp[(int64_t)s * n + i] += v;
+  }
+  if (f) atomicOr(flag, f);
+}
+
+void launch_csr_to_stencil(const Level& L, const int64_t* rowptr, const int* colind, const double* vals,
+                           double* comp, int* flag, hipStream_t st) {
+  const dim3 g(cdiv(L.ncomp, kBlock)), b(kBlock);
+  if (L.npts == 27)
+    hipLaunchKernelGGL(k_csr_to_stencil<27>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
+                       flag);
+  else if (L.npts == 9)
+    hipLaunchKernelGGL(k_csr_to_stencil<9>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
+                       flag);
+  else
+    hipLaunchKernelGGL(k_csr_to_stencil<5>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
+                       flag);
+  LAUNCH_CHECK();
+}
+
 // Caller layout (structure of arrays over one region, [ncoef][nodes]) <-> wave-tiled storage.
 __global__ void k_region_stencil_io(int64_t off, int nn, int ncoef, double* __restrict__ coef,
                                     double* __restrict__ soa, int to_level) {

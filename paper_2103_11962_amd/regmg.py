@@ -37,7 +37,7 @@ SYMBOLS = (
     "rmg_get_prolongator_weights", "rmg_convergence_factor", "rmg_mlp_create", "rmg_mlp_destroy",
     "rmg_mlp_set_params", "rmg_mlp_get_params", "rmg_mlp_add_data", "rmg_mlp_add_samples", "rmg_mlp_clear_data",
     "rmg_mlp_num_data", "rmg_mlp_get_data", "rmg_mlp_forward", "rmg_mlp_loss_grad", "rmg_mlp_adam_step",
-    "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel",
+    "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr",
 )
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
 P_GEOMETRIC, P_STORED, P_LEARNED = 0, 1, 2
@@ -146,6 +146,7 @@ def load():
         "rmg_mlp_train": (I, [H, I, D, P]),
         "rmg_mlp_init_params": (I, [H, ctypes.c_uint64, D, P]),
         "rmg_level_kernel": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "rmg_set_composite_csr": (I, [H, I, ctypes.c_int64, P, P, P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -242,6 +243,18 @@ class Handle:
         else:
             c = np.ascontiguousarray(coef, dtype=np.float64)
             _check(load().rmg_set_composite_stencil(self._h, npts, c.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def set_composite_csr(self, npts, A):
+        """Non-invasive split of an assembled composite matrix (scipy sparse, host)."""
+        import scipy.sparse as sp
+
+        A = sp.csr_matrix(A)
+        rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+        v = np.ascontiguousarray(A.data, dtype=np.float64)
+        _check(load().rmg_set_composite_csr(self._h, npts, int(v.size), rp.ctypes.data_as(ctypes.c_void_p),
+                                            ci.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p),
+                                            0))
 
     def assemble_q1(self, pde, h, elem_coef=None, youngs=None, nu=0.3):
         y = None if youngs is None else np.ascontiguousarray(youngs, dtype=np.float64)
