@@ -88,6 +88,10 @@ typedef struct {
                          host convergence check) as HIP graphs once and replays them */
   const char* autotune_cache; /* text file of autotuner choices keyed by level shape and
                          precision; read before tuning, appended after (NULL: no file) */
+  int smoother;       /* 0 (default): Chebyshev of degree cheb_degree (Section 3.4, Algorithm 2);
+                         1: damped Jacobi, cheb_degree sweeps of u += jacobi_omega D~^-1 r
+                         (Section 3.4, the smoother of Table 1) */
+  double jacobi_omega; /* damping of the Jacobi smoother (default 0.6) */
   int symmetric;      /* 1 (default): on scalar 27-point 3D levels whose operator is symmetric to
                          rounding, the 2.5D kernel keeps only the upper half of each stencil
                          (14 coefficients per node) and reads a lower coupling from the
@@ -196,6 +200,13 @@ rmg_status rmg_apply_vcycle(rmg_handle* h, const double* r, double* z, int layou
  * maxit iterations (RMG_ERR_NOT_CONVERGED).  info may be NULL.  Synchronises. */
 rmg_status rmg_solve(rmg_handle* h, const double* b, double* x, int layout, double rtol, int maxit,
                      rmg_solve_info* info);
+
+/* Multigrid as a solver (the paper's experiments, Section 6): x <- x + V(b - A x)
+ * until ||b - A x|| / ||b|| <= rtol or maxit cycles (RMG_ERR_NOT_CONVERGED, x =
+ * last iterate).  Vectors and info as in rmg_solve (iterations = cycles, history
+ * = relative residual after each cycle, [0] = ||b - A x0|| / ||b||).  Synchronises. */
+rmg_status rmg_mg_solve(rmg_handle* h, const double* b, double* x, int layout, double rtol, int maxit,
+                        rmg_solve_info* info);
 
 /* ---- conversions and per-step entry points (used by parity tests) ---- */
 

@@ -140,6 +140,8 @@ void rmg_options_default(rmg_options* o) {
   o->autotune = 0;
   o->use_graph = 0;
   o->autotune_cache = nullptr;
+  o->smoother = 0;
+  o->jacobi_omega = 0.6;
   o->symmetric = 1;
   o->batched = 1;
   o->judge_cycles = 10;
@@ -452,6 +454,9 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 3, RMG_ERR_ARG, "stencil_kernel must be 0..3");
   RMG_REQUIRE(opt->batched == 0 || opt->batched == 1, RMG_ERR_ARG, "batched must be 0 or 1");
   RMG_REQUIRE(opt->symmetric == 0 || opt->symmetric == 1, RMG_ERR_ARG, "symmetric must be 0 or 1");
+  RMG_REQUIRE(opt->smoother == 0 || opt->smoother == 1, RMG_ERR_ARG, "smoother must be 0 (Chebyshev) or 1 (Jacobi)");
+  RMG_REQUIRE(opt->smoother == 0 || (opt->jacobi_omega > 0.0 && opt->jacobi_omega < 2.0), RMG_ERR_ARG,
+              "jacobi_omega must lie in (0, 2)");
   RMG_REQUIRE(opt->judge_cycles >= 0 && opt->judge_cycles <= 1000, RMG_ERR_ARG, "judge_cycles must be in [0, 1000]");
   h->opt = *opt;
   h->autotune_cache = opt->autotune_cache ? std::string(opt->autotune_cache) : std::string();
@@ -500,6 +505,29 @@ rmg_status rmg_solve(rmg_handle* h, const double* b, double* x, int layout, doub
     launch_to_regional(L, b, h->cg_b.as<double>(), h->stream);
     launch_to_regional(L, x, h->cg_x.as<double>(), h->stream);
     pcg(h, h->cg_b.as<double>(), h->cg_x.as<double>(), rtol, maxit, info, &st);
+    launch_to_composite(L, h->cg_x.as<double>(), x, 0, h->stream);
+  }
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  if (st != RMG_OK) return st;
+  API_END
+}
+
+rmg_status rmg_mg_solve(rmg_handle* h, const double* b, double* x, int layout, double rtol, int maxit,
+                        rmg_solve_info* info) {
+  API_BEGIN
+  use_device(h);
+  require_hierarchy(h);
+  RMG_REQUIRE(b && x && b != x, RMG_ERR_ARG, "b and x must be distinct non-null device pointers");
+  RMG_REQUIRE(layout == RMG_LAYOUT_COMPOSITE || layout == RMG_LAYOUT_REGIONAL, RMG_ERR_ARG, "bad layout");
+  RMG_REQUIRE(rtol > 0.0 && maxit >= 1, RMG_ERR_ARG, "need rtol > 0 and maxit >= 1");
+  Level& L = *h->levels[0];
+  rmg_status st = RMG_OK;
+  if (layout == RMG_LAYOUT_REGIONAL) {
+    mg_solve(h, b, x, rtol, maxit, info, &st);
+  } else {
+    launch_to_regional(L, b, h->cg_b.as<double>(), h->stream);
+    launch_to_regional(L, x, h->cg_x.as<double>(), h->stream);
+    mg_solve(h, h->cg_b.as<double>(), h->cg_x.as<double>(), rtol, maxit, info, &st);
     launch_to_composite(L, h->cg_x.as<double>(), x, 0, h->stream);
   }
   RMG_HIP(hipStreamSynchronize(h->stream));

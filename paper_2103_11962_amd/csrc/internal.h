@@ -240,6 +240,9 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z);
 void apply_preconditioner(rmg_handle* h, const double* r, double* z);
 void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
          rmg_status* st);
+// Multigrid as a solver: x <- x + V(b - A x) (regional FP64 vectors).
+void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
+              rmg_status* st);
 void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out);
 // u <- S(b, u): one degree-K Chebyshev application from the current iterate (tmp: work vector).
 void smooth_iterate(rmg_handle* h, int level, const double* b, double* u, double* tmp);

@@ -82,6 +82,11 @@ static double power_method(rmg_handle* h, Level& L, int level) {
 }
 
 static void chebyshev_coefficients(const rmg_options& o, Level& L) {
+  if (o.smoother == 1) {  // damped Jacobi: every step is d = omega D~^-1 r, u += d
+    L.cheb_c1.assign(o.cheb_degree, 0.0);
+    L.cheb_c2.assign(o.cheb_degree, o.jacobi_omega);
+    return;
+  }
   const double alpha = L.lambda / o.eig_ratio;
   const double beta = o.boost * L.lambda;
   const double theta = 0.5 * (alpha + beta);
@@ -425,6 +430,78 @@ double convergence_factor(rmg_handle* h, int cycles) {
   const double rk = std::sqrt(h->host_scalars[kTmp]);
   if (!(r0 > 0.0)) return 0.0;
   return std::pow(rk / r0, 1.0 / cycles);
+}
+
+void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
+              rmg_status* status) {
+  Level& L = *h->levels[0];
+  hipStream_t st = h->stream;
+  const int64_t n = L.ndofs();
+  double* r = h->cg_r.as<double>();
+  double* z = h->cg_z.as<double>();
+  hipEvent_t e0, e1;
+  RMG_HIP(hipEventCreate(&e0));
+  RMG_HIP(hipEventCreate(&e1));
+  RMG_HIP(hipEventRecord(e0, st));
+  auto residual = [&] {
+    StencilArgs a;
+    a.op = StencilOp::Residual;
+    a.x = x;
+    a.out = r;
+    a.b = b;
+    launch_stencil_op(L, a, st);
+  };
+  int hist_len = 0;
+  auto push_hist = [&](double v) {
+    if (info && info->history && hist_len < info->history_cap) info->history[hist_len] = v;
+    ++hist_len;
+  };
+  *status = RMG_OK;
+  dot(h, L, b, b, kBB);
+  residual();
+  dot(h, L, r, r, kRR);
+  read_scalars(h);
+  const double bnorm = std::sqrt(h->host_scalars[kBB]);
+  double rel = bnorm > 0.0 ? std::sqrt(h->host_scalars[kRR]) / bnorm : 0.0;
+  push_hist(rel);
+  int it = 0;
+  bool converged = bnorm == 0.0 || rel <= rtol;
+  if (bnorm == 0.0) launch_zero(n, x, st);
+  while (!converged && it < maxit) {
+    apply_preconditioner(h, r, z);
+    launch_add(n, z, x, st);
+    residual();
+    dot(h, L, r, r, kRR);
+    read_scalars(h);
+    ++it;
+    const double rr = h->host_scalars[kRR];
+    if (!std::isfinite(rr)) {
+      *status = RMG_ERR_BREAKDOWN;
+      set_last_error("multigrid iteration diverged (non-finite residual)");
+      break;
+    }
+    rel = std::sqrt(rr) / bnorm;
+    push_hist(rel);
+    converged = rel <= rtol;
+  }
+  RMG_HIP(hipEventRecord(e1, st));
+  RMG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  RMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (*status == RMG_OK && !converged) {
+    *status = RMG_ERR_NOT_CONVERGED;
+    set_last_error("multigrid did not reach rtol within maxit cycles");
+  }
+  if (info) {
+    info->iterations = it;
+    info->converged = converged ? 1 : 0;
+    info->relres = rel;
+    info->true_relres = rel;  // the residual is recomputed from x every cycle
+    info->solve_ms = ms;
+    info->history_len = hist_len;
+  }
 }
 
 void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {

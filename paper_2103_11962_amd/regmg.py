@@ -37,7 +37,7 @@ SYMBOLS = (
     "rmg_get_prolongator_weights", "rmg_convergence_factor", "rmg_mlp_create", "rmg_mlp_destroy",
     "rmg_mlp_set_params", "rmg_mlp_get_params", "rmg_mlp_add_data", "rmg_mlp_add_samples", "rmg_mlp_clear_data",
     "rmg_mlp_num_data", "rmg_mlp_get_data", "rmg_mlp_forward", "rmg_mlp_loss_grad", "rmg_mlp_adam_step",
-    "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr",
+    "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr", "rmg_mg_solve",
 )
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
 P_GEOMETRIC, P_STORED, P_LEARNED = 0, 1, 2
@@ -58,6 +58,8 @@ class Options(ctypes.Structure):
         ("autotune", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("autotune_cache", ctypes.c_char_p),
+        ("smoother", ctypes.c_int),
+        ("jacobi_omega", ctypes.c_double),
         ("symmetric", ctypes.c_int),
         ("batched", ctypes.c_int),
         ("judge_cycles", ctypes.c_int),
@@ -147,6 +149,7 @@ def load():
         "rmg_mlp_init_params": (I, [H, ctypes.c_uint64, D, P]),
         "rmg_level_kernel": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "rmg_set_composite_csr": (I, [H, I, ctypes.c_int64, P, P, P, I]),
+        "rmg_mg_solve": (I, [H, P, P, I, D, I, ctypes.POINTER(SolveInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -269,12 +272,15 @@ class Handle:
     def apply_vcycle(self, r, z, layout=LAYOUT_COMPOSITE):
         _check(load().rmg_apply_vcycle(self._h, _ptr(r), _ptr(z), layout))
 
-    def solve(self, b, x, layout=LAYOUT_COMPOSITE, rtol=1e-8, maxit=200, history_cap=512, raise_on_fail=True):
+    def solve(self, b, x, layout=LAYOUT_COMPOSITE, rtol=1e-8, maxit=200, history_cap=512, raise_on_fail=True,
+              method="pcg"):
+        """PCG (method "pcg") or multigrid as a solver (method "mg")."""
         info = SolveInfo()
         hist = (ctypes.c_double * history_cap)()
         info.history = hist
         info.history_cap = history_cap
-        code = load().rmg_solve(self._h, _ptr(b), _ptr(x), layout, rtol, maxit, ctypes.byref(info))
+        fn = load().rmg_solve if method == "pcg" else load().rmg_mg_solve
+        code = fn(self._h, _ptr(b), _ptr(x), layout, rtol, maxit, ctypes.byref(info))
         if code != 0 and raise_on_fail:
             _check(code)
         out = {

@@ -1,0 +1,97 @@
+"""Multigrid as a solver and the damped Jacobi smoother on the GPU.
+
+The structure of the paper's Table 1: with damped Jacobi (omega 0.6, one sweep) and MG as a
+solver on a 2D mesh of 730^2 nodes in 3x3 regions, the regional method's residual history is the
+composite method's (the oracle's plain composite multigrid), cycle by cycle.  The table's own
+numbers are not reproducible (its right-hand side and initial guess are not given).
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests import harness
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def test_table1_structure_jacobi_histories(hip_device):
+    import torch
+
+    from oracle import assembly, composite, regional
+    from oracle.regions import Layout
+
+    o, e = synth.tensor_layout([[244] * 3, [244] * 3])
+    w = synth.Workload("table1", 2, 1, o, e, 15, 4, 1, "fd5", seed=0)
+    lay = Layout(2, o, e, 15)
+    opt = regional.Options(nlevels=4, degree=1, smoother="jacobi", jacobi_omega=0.6)
+    clv = composite.setup(lay, assembly.composite_fd5(lay), opt)
+    b = synth.rhs(w)
+    h = harness.gpu_problem(w, nlevels=4, cheb_degree=1, smoother=1, jacobi_omega=0.6)
+    x = torch.zeros(lay.n_composite, dtype=torch.float64, device="cuda:0")
+    out = h.solve(harness.to_dev(b), x, rtol=1e-12, maxit=300, method="mg")
+    assert out["converged"]
+    n = out["iterations"]
+    xc, hc = composite.stationary(clv, b.reshape(-1), np.zeros(b.size), opt, n)
+    hc = np.asarray(hc)
+    hg = np.asarray(out["history"][: n + 1])
+    np.testing.assert_allclose(hg[:30], hc[:30], rtol=1e-9)  # cycle by cycle
+    big = hc > 1e-9
+    np.testing.assert_allclose(hg[big], hc[big], rtol=1e-6)
+    assert hc[-1] <= 1e-12 and (n == 1 or hc[-2] > 1e-12)  # same stopping cycle
+    assert rel(x.cpu().numpy(), xc) < 1e-10
+    print(f"[table1] {n} cycles to 1e-12, asymptotic factor {(hc[-1] / hc[-11]) ** 0.1:.3f}", flush=True)
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c5_small", "c1_small"])
+def test_chebyshev_mg_as_solver(hip_device, name):
+    import torch
+
+    from oracle import regional
+
+    w = synth.workload(name)
+    lay, levels, opt = harness.oracle_problem(w)
+    b = synth.rhs(w)
+    h = harness.gpu_problem(w)
+    x = torch.zeros(lay.n_composite, dtype=torch.float64, device="cuda:0")
+    out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100, method="mg")
+    n = out["iterations"]
+    xr, hr = regional.stationary(levels, lay.to_regional(b), lay.zeros_regional(), opt, n)
+    np.testing.assert_allclose(out["history"][: n + 1], hr, rtol=1e-8)
+    assert out["converged"] and hr[-1] <= 1e-8 < hr[-2]
+    assert rel(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1)) < 1e-10
+    h.close()
+
+
+def test_jacobi_smoothed_pcg(hip_device):
+    import torch
+
+    from oracle import regional
+
+    w = synth.workload("c2_small")
+    lay, levels, opt = harness.oracle_problem(w, smoother="jacobi", jacobi_omega=0.6)
+    b = synth.rhs(w)
+    ref = regional.pcg(levels, lay.to_regional(b), opt, rtol=1e-8, maxit=200)
+    h = harness.gpu_problem(w, smoother=1, jacobi_omega=0.6)
+    x = torch.zeros(lay.n_composite, dtype=torch.float64, device="cuda:0")
+    out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=200)
+    assert out["iterations"] == ref.iterations
+    np.testing.assert_allclose(out["history"], ref.history, rtol=1e-8)
+    assert rel(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1)) < 1e-10
+    h.close()
+
+
+def test_mg_solver_reports_maxit(hip_device):
+    import torch
+
+    w = synth.workload("c2_small")
+    h = harness.gpu_problem(w)
+    b = harness.to_dev(synth.rhs(w))
+    x = torch.zeros_like(b)
+    out = h.solve(b, x, rtol=1e-14, maxit=2, method="mg", raise_on_fail=False)
+    assert out["status"] == "RMG_ERR_NOT_CONVERGED" and out["iterations"] == 2 and len(out["history"]) == 3
+    h.close()
