@@ -111,17 +111,18 @@ def _handle(w, dev):
     return h
 
 
-def _timed_solves(h, b, reps=2, **kw):
+def _timed_solves(h, b, reps=2, rtol_override=None, **kw):
     """Warm-up solve, then `reps` timed solves; median solve time and the last result."""
     import numpy as np
     import torch
 
+    rtol = rtol_override or 1e-8
     x = torch.zeros_like(b)
-    h.solve(b, x, rtol=1e-8, maxit=400, **kw)
+    h.solve(b, x, rtol=rtol, maxit=400, **kw)
     outs = []
     for _ in range(reps):
         x.zero_()
-        outs.append(h.solve(b, x, rtol=1e-8, maxit=400, **kw))
+        outs.append(h.solve(b, x, rtol=rtol, maxit=400, **kw))
     return float(np.median([o["solve_ms"] for o in outs])), outs[-1], x
 
 
@@ -292,6 +293,94 @@ def variant_graph_2d(dev):
     return out
 
 
+def _stencil_to_csr(w, stencil):
+    """The assembled composite five-point matrix of a workload as CSR arrays (input preparation:
+    the same numbers as its composite stencil, rows x fastest)."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    nx, ny = w.composite_shape_xyz
+    n = nx * ny
+    idx = np.arange(n).reshape(ny, nx)
+    rows, cols, vals = [], [], []
+    for s, (dx, dy) in enumerate(((0, -1), (-1, 0), (0, 0), (1, 0), (0, 1))):
+        ys, xs = np.nonzero(stencil[s].reshape(ny, nx))
+        ok = (xs + dx >= 0) & (xs + dx < nx) & (ys + dy >= 0) & (ys + dy < ny)
+        ys, xs = ys[ok], xs[ok]
+        rows.append(idx[ys, xs])
+        cols.append(idx[ys + dy, xs + dx])
+        vals.append(stencil[s].reshape(ny, nx)[ys, xs])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+def variant_noninvasive(dev):
+    """2D five-point, 2x2 regions of 82^2 (Section 4 input): region matrices split on the device
+    from the assembled composite matrix given as CSR, versus from its composite stencil."""
+    import synth
+
+    w = synth.workload("c1")
+    st = synth.fd5_composite_stencil(w)
+    A = _stencil_to_csr(w, st)
+    b = _to_dev(synth.rhs(w), dev)
+    out = {}
+    for name in ("composite_stencil", "composite_csr"):
+        h = _handle(w, dev) if name == "composite_stencil" else None
+        if h is None:
+            from paper_2103_11962_amd import regmg
+
+            h = regmg.Handle(0)
+            h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
+        import torch
+
+        ms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "composite_csr":
+                h.set_composite_csr(5, A)
+            else:
+                h.set_composite_stencil(5, st)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        _setup(h, w)
+        solve_ms, res, _ = _timed_solves(h, b)
+        out[name] = {"split_ms_host_input": min(ms), "solve_ms": solve_ms, "iterations": res["iterations"],
+                     "true_relres": res["true_relres"]}
+        h.close()
+    out["csr_nnz"] = int(A.nnz)
+    out["workload"] = "2D five-point, 2x2 regions of 82^2 (composite 163^2), operator handed over assembled"
+    return out
+
+
+def variant_mg_solver(dev):
+    """Multigrid as a solver (the paper's experiments): damped Jacobi (omega 0.6, one sweep) on the
+    2D five-point 730^2 mesh in 3x3 regions to 1e-12 (the setting of the paper's Table 1), and the
+    Chebyshev V-cycle on the 3D Laplacian to 1e-8 beside its PCG solve."""
+    import synth
+
+    out = {}
+    o, e = synth.tensor_layout([[244] * 3, [244] * 3])
+    w = synth.Workload("table1", 2, 1, o, e, 15, 4, 1, "fd5", seed=0)
+    h = _handle(w, dev)
+    _setup(h, w, smoother=1, jacobi_omega=0.6)
+    b = _to_dev(synth.rhs(w), dev)
+    ms, res, _ = _timed_solves(h, b, reps=3, method="mg", rtol_override=1e-12)
+    hist = res["history"]
+    out["jacobi_2d_730"] = {"solve_ms": ms, "cycles": res["iterations"], "relres": res["relres"],
+                            "asymptotic_factor": (hist[-1] / hist[-11]) ** 0.1 if len(hist) > 11 else None}
+    h.close()
+    w = synth.workload("c2")
+    h = _handle(w, dev)
+    _setup(h, w)
+    b = _to_dev(synth.rhs(w), dev)
+    ms, res, _ = _timed_solves(h, b, reps=2, method="mg")
+    out["chebyshev_3d_c2"] = {"solve_ms": ms, "cycles": res["iterations"], "relres": res["relres"]}
+    h.close()
+    out["workload"] = ("2D five-point 3x3 regions of 244^2 (730^2), 4 levels, Jacobi, to 1e-12; 3D Q1 Laplacian "
+                       "4x4x4 regions of 82^3, 4 levels, Chebyshev degree 3, to 1e-8")
+    return out
+
+
 def _to_dev(a, dev):
     import numpy as np
     import torch
@@ -447,6 +536,8 @@ def main():
             "batched": variant_batched(dev),
             "learned_interpolation": variant_learned(dev),
             "graph_2d": variant_graph_2d(dev),
+            "noninvasive_csr": variant_noninvasive(dev),
+            "mg_as_solver": variant_mg_solver(dev),
         }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(last["iterations"], rows)
