@@ -25,6 +25,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
+from . import fem
 from .regions import Layout
 
 NIN, NH, NOUT = 27, 64, 208
@@ -89,10 +90,28 @@ def corner_values(E):
     return np.stack([E[:, 3 * ((s >> 2) & 1), 3 * ((s >> 1) & 1), 3 * (s & 1)] for s in range(8)], axis=1)
 
 
-def loss_and_grad(theta, X, E):
+def cell_matrix(X):
+    """Local operator of a cell for the energy loss: sum over its 27 elements of c_e K_e, with
+    c_e = exp(X_e) (the centred log-coefficients; the loss is a ratio, so the common scale drops
+    out) and K_e the Q1 Laplace element matrix of a unit cube, on the 64 cell nodes [k, j, i]
+    flattened x fastest.  Returns (N, 64, 64)."""
+    K = fem.q1_laplace(1.0)
+    N = X.shape[0]
+    A = np.zeros((N, 64, 64))
+    for e in range(27):
+        ex, ey, ez = e % 3, (e // 3) % 3, e // 9
+        nodes = [(ez + c[2]) * 16 + (ey + c[1]) * 4 + (ex + c[0]) for c in fem.CORNERS3]
+        A[:, np.ix_(nodes, nodes)[0], np.ix_(nodes, nodes)[1]] += np.exp(X[:, e])[:, None, None] * K[None]
+    return A
+
+
+def loss_and_grad(theta, X, E, kind="l2"):
     """Mean loss over samples and its gradient (flat, same order as theta).
 
     X: (N, 27) features, E: (N, 4, 4, 4) smooth-error values on the cell's nodes [k, j, i].
+    kind "l2": per sample sum_f (e_f - sum_c w_fc e_c)^2 / sum_f e_f^2.
+    kind "energy": the interpolation error delta (zero at the corners) in the cell operator's
+    energy norm, delta^T A_cell delta / (cbar sum_f e_f^2), cbar the mean element coefficient.
     """
     z, (X, a1, h1, a2, h2) = forward(theta, X)
     N = X.shape[0]
@@ -101,19 +120,31 @@ def loss_and_grad(theta, X, E):
     norm = np.sum(E.reshape(N, -1) ** 2, axis=1)
     norm = np.where(norm > 0, norm, 1.0)
     ws = weights_from_logits(z)
-    loss = np.zeros(N)
     dz = np.zeros_like(z)
+    # interpolation error on the 64 cell nodes (zero at the corners)
+    delta = np.zeros((N, 64))
+    for n, (i, j, k, corners) in enumerate(NODES):
+        pred = np.sum(ws[n] * ec[:, corners], axis=1)
+        delta[:, (k * 4 + j) * 4 + i] = E[:, k, j, i] - pred
+    if kind == "l2":
+        loss = np.sum(delta ** 2, axis=1) / norm
+        g = 2.0 * delta / norm[:, None]  # d loss / d delta
+    elif kind == "energy":
+        A = cell_matrix(X)
+        Ad = np.einsum("nij,nj->ni", A, delta)
+        enorm = np.mean(np.exp(X), axis=1) * norm
+        loss = np.sum(delta * Ad, axis=1) / enorm
+        g = 2.0 * Ad / enorm[:, None]
+    else:
+        raise ValueError(kind)
     for n, (i, j, k, corners) in enumerate(NODES):
         w = ws[n]
-        pred = np.sum(w * ec[:, corners], axis=1)
-        res = E[:, k, j, i] - pred
-        loss += res ** 2
-        # d loss / d pred = -2 res / norm ; d pred / d w_c = e_c ; softmax backward
-        dpred = -2.0 * res / norm
+        # d loss / d pred_f = -g_f ; d pred / d w_c = e_c ; softmax backward
+        dpred = -g[:, (k * 4 + j) * 4 + i]
         dw = dpred[:, None] * ec[:, corners]
         s = np.sum(dw * w, axis=1, keepdims=True)
         dz[:, LOGIT_OFFSET[n]:LOGIT_OFFSET[n] + len(corners)] = w * (dw - s)
-    L = float(np.mean(loss / norm))
+    L = float(np.mean(loss))
     dz /= N
     dW3 = dz.T @ h2
     db3 = dz.sum(axis=0)

@@ -108,3 +108,51 @@ def test_training_reduces_loss():
         theta, m, v = learned.adam_step(theta, g, m, v, t, 3e-3)
     L1, _ = learned.loss_and_grad(theta, X, E)
     assert L1 < 0.7 * L0, (L0, L1)
+
+
+def test_energy_gradient_matches_central_differences():
+    rng = np.random.default_rng(13)
+    X = rng.standard_normal((4, 27))
+    E = rng.standard_normal((4, 4, 4, 4))
+    theta = random_theta(7)
+    L, g = learned.loss_and_grad(theta, X, E, kind="energy")
+    h = 1e-6
+    for i in rng.choice(learned.NPARAM, size=40, replace=False):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (learned.loss_and_grad(tp, X, E, kind="energy")[0] - learned.loss_and_grad(tm, X, E, kind="energy")[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_cell_matrix_is_the_assembled_cube_operator():
+    """With unit coefficients the cell operator is the Q1 Laplacian assembled on one 4^3-node
+    box without boundary conditions; it is symmetric and annihilates constants for any c."""
+    lay = Layout(3, np.array([[0, 0, 0]]), np.array([[4, 4, 4]]), 0)
+    A1 = assembly.composite_q1(lay, "laplace", h=1.0).toarray()
+    np.testing.assert_allclose(learned.cell_matrix(np.zeros((1, 27)))[0], A1, atol=1e-14)
+    X = np.random.default_rng(2).standard_normal((3, 27))
+    A = learned.cell_matrix(X)
+    np.testing.assert_allclose(A, np.transpose(A, (0, 2, 1)), atol=1e-14)
+    np.testing.assert_allclose(A @ np.ones(64), 0.0, atol=1e-12)
+
+
+def test_energy_loss_vanishes_for_trilinear_errors():
+    """Trilinear weights (zero hidden-to-output weights, output biases log w) reproduce any
+    affine error exactly, so both losses vanish."""
+    theta = np.zeros(learned.NPARAM)
+    b3 = theta[-learned.NOUT:]
+    for n, (i, j, k, corners) in enumerate(learned.NODES):
+        for c, slot in enumerate(corners):
+            w = 1.0
+            for d, p in enumerate((i, j, k)):
+                w *= p / 3.0 if (slot >> d) & 1 else (3 - p) / 3.0
+            b3[learned.LOGIT_OFFSET[n] + c] = np.log(w)
+    g = np.arange(4.0)
+    a = np.random.default_rng(1).standard_normal((3, 4))
+    E = np.stack([a[s, 0] + a[s, 1] * g[None, None, :] + a[s, 2] * g[None, :, None] + a[s, 3] * g[:, None, None]
+                  for s in range(3)])
+    X = np.random.default_rng(5).standard_normal((3, 27))
+    for kind in ("l2", "energy"):
+        L, _ = learned.loss_and_grad(theta, X, E, kind=kind)
+        assert L < 1e-28, (kind, L)
