@@ -354,6 +354,14 @@ rmg_status rmg_mlp_destroy(rmg_mlp* m);
  * every node at the geometric interpolation.  Resets Adam's state; theta_out
  * (host [RMG_MLP_NPARAM] or NULL) receives the parameters. */
 rmg_status rmg_mlp_init_params(rmg_mlp* m, uint64_t seed, double out_scale, float* theta_out);
+/* Training loss (default RMG_MLP_LOSS_L2, as above).  RMG_MLP_LOSS_ENERGY
+ * measures the interpolation error delta (zero at the cell corners) in the
+ * energy norm of the cell's local operator: delta^T A_cell delta / (cbar
+ * sum_f e_f^2) with A_cell = sum over the 27 elements of exp(X_e) K_Q1 (unit
+ * cube Laplacian) and cbar the mean of exp(X_e). */
+#define RMG_MLP_LOSS_L2 0
+#define RMG_MLP_LOSS_ENERGY 1
+rmg_status rmg_mlp_set_loss(rmg_mlp* m, int kind);
 /* Parameters (host FP32 [RMG_MLP_NPARAM]); setting them resets Adam's state. */
 rmg_status rmg_mlp_set_params(rmg_mlp* m, const float* theta);
 rmg_status rmg_mlp_get_params(rmg_mlp* m, float* theta);

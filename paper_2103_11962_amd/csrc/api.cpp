@@ -18,7 +18,7 @@ void fail(rmg_status code, const std::string& msg) { throw Error{code, msg}; }
 
 // Reference Q1 Laplacian element matrix of a cube of side h: int grad phi_a . grad phi_b,
 // 2x2x2 Gauss-Legendre quadrature, corner a = (a&1, (a>>1)&1, (a>>2)&1).
-static void q1_laplace_element(double h, double K[64]) {
+void q1_laplace_element(double h, double K[64]) {
   const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
   for (int i = 0; i < 64; ++i) K[i] = 0.0;
   for (int qz = 0; qz < 2; ++qz)
@@ -341,9 +341,12 @@ rmg_status rmg_set_composite_csr(rmg_handle* h, int npts, int64_t nnz, const int
   const int64_t n = L.ncomp;
   // row pointers are checked on the host before any kernel reads through them
   std::vector<int64_t> rp(n + 1);
-  RMG_HIP(hipMemcpyAsync(rp.data(), rowptr, sizeof(int64_t) * (n + 1),
-                         on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, h->stream));
-  RMG_HIP(hipStreamSynchronize(h->stream));
+  if (on_device) {
+    RMG_HIP(hipMemcpyAsync(rp.data(), rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, h->stream));
+    RMG_HIP(hipStreamSynchronize(h->stream));
+  } else {
+    std::copy(rowptr, rowptr + n + 1, rp.begin());
+  }
   RMG_REQUIRE(rp[0] == 0 && rp[n] == nnz, RMG_ERR_ARG, "row pointers must start at 0 and end at nnz");
   for (int64_t i = 0; i < n; ++i)
     RMG_REQUIRE(rp[i + 1] >= rp[i], RMG_ERR_ARG, "row pointers must not decrease");

@@ -224,6 +224,9 @@ struct rmg_handle {
 
 namespace rmg {
 
+// api.cpp: Q1 Laplace element matrix of a cube of side h (2x2x2 Gauss-Legendre), corners ax + 2 ay + 4 az.
+void q1_laplace_element(double h, double K[64]);
+
 // planner.cpp
 void build_level0(rmg_handle* h);
 Level* make_coarse_level(const Level& fine);

@@ -16,6 +16,7 @@ struct rmg_mlp {
   hipStream_t stream = nullptr;
   DBuf theta, grad, m, v;  // float [kMlpParams]
   int t = 0;               // Adam steps taken since the parameters were set
+  int loss_kind = 0;       // RMG_MLP_LOSS_*
   bool have_grad = false;
   int64_t n = 0, cap = 0;  // pairs held and capacity
   DBuf X, E;               // float [cap][27], [cap][64]
@@ -180,7 +181,7 @@ static void loss_grad(rmg_mlp* m, int slot) {
   float* D1 = m->D1.as<float>();
   float* D2 = m->D2.as<float>();
   mlp_forward(n, X, m->theta.as<float>(), Z, A1, A2, st);
-  const int64_t np = mlp_loss(n, Z, m->E.as<float>(), dZ, m->partials.as<double>(), st);
+  const int64_t np = mlp_loss(n, Z, m->E.as<float>(), X, m->loss_kind, dZ, m->partials.as<double>(), st);
   launch_reduce(m->partials.as<double>(), np, m->losses.as<double>(), slot, st);
   mlp_backact(n, dZ, A1, A2, m->theta.as<float>(), D1, D2, st);
   mlp_weight_grads(n, X, A1, A2, dZ, D1, D2, m->grad.as<float>(), m->part.as<float>(), st);
@@ -356,6 +357,15 @@ rmg_status rmg_mlp_init_params(rmg_mlp* m, uint64_t seed, double out_scale, floa
   const rmg_status st = rmg_mlp_set_params(m, th.data());
   if (st != RMG_OK) return st;
   if (theta_out) std::copy(th.begin(), th.end(), theta_out);
+  API_END
+}
+
+rmg_status rmg_mlp_set_loss(rmg_mlp* m, int kind) {
+  API_BEGIN
+  mlp_use(m);
+  RMG_REQUIRE(kind == RMG_MLP_LOSS_L2 || kind == RMG_MLP_LOSS_ENERGY, RMG_ERR_ARG, "unknown loss");
+  m->loss_kind = kind;
+  m->have_grad = false;
   API_END
 }
 

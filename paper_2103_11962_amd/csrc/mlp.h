@@ -26,7 +26,9 @@ void mlp_forward(int64_t n, const float* X, const float* theta, float* Z, float*
 // Loss partial sums (one double per block of samples; mlp_loss_partials(n) of them, also the
 // returned count) and dZ = dloss/dZ / n.
 int64_t mlp_loss_partials(int64_t n);
-int64_t mlp_loss(int64_t n, const float* Z, const float* E, float* dZ, double* partials, hipStream_t st);
+// kind 0: interpolation error in L2; 1: in the energy norm of the cell's local operator (needs X).
+int64_t mlp_loss(int64_t n, const float* Z, const float* E, const float* X, int kind, float* dZ, double* partials,
+                 hipStream_t st);
 // Activation gradients of the two hidden layers.
 void mlp_backact(int64_t n, const float* dZ, const float* A1, const float* A2, const float* theta, float* D1,
                  float* D2, hipStream_t st);

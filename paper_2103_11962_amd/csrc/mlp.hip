@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "device_common.h"
 #include "mlp.h"
@@ -21,6 +22,7 @@ namespace rmg {
 // corners, first logit, corner slots (ix + 2 iy + 4 iz).  Filled from cell_node_table.
 __constant__ CellNode c_nodes[56];
 __constant__ signed char c_pos2node[64];  // -1 for the 8 corners
+__constant__ float c_kq1[64];              // Q1 Laplace element matrix of the unit cube (energy loss)
 
 void cell_node_table(CellNode* nodes, signed char* pos2node) {
   int n = 0, off = 0;
@@ -58,18 +60,25 @@ void cell_node_table(CellNode* nodes, signed char* pos2node) {
   RMG_REQUIRE(n == 56 && off == kMlpOut, RMG_ERR_ARG, "internal: cell node table");
 }
 
-// Once per device (constant memory is per device).
+// Once per device (constant memory is per device); handles on other threads may call it too.
 static void upload_tables() {
+  static std::mutex mu;
   static bool done[64] = {};
   int dev = 0;
   RMG_HIP(hipGetDevice(&dev));
   RMG_REQUIRE(dev >= 0 && dev < 64, RMG_ERR_ARG, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(mu);
   if (done[dev]) return;
   CellNode nodes[56];
   signed char pos2node[64];
   cell_node_table(nodes, pos2node);
   RMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_nodes), nodes, sizeof(nodes)));
   RMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_pos2node), pos2node, sizeof(pos2node)));
+  double K[64];
+  q1_laplace_element(1.0, K);
+  float Kf[64];
+  for (int i = 0; i < 64; ++i) Kf[i] = (float)K[i];
+  RMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_kq1), Kf, sizeof(Kf)));
   done[dev] = true;
 }
 
@@ -139,16 +148,21 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Loss per sample sum_f (e_f - sum_c w_fc e_c)^2 / sum_f e_f^2 and its gradient with respect to
-// the logits, scaled by 1/n (the loss is a mean over samples).  One wavefront per sample: lane p
-// holds the error at cell node p (x fastest over the 4x4x4 nodes), the corner values arrive by
-// lane shuffles, and each lane of a non-corner node evaluates that node's softmax, so the rows of
-// E, Z and dZ are read and written contiguously.  Partial sums: one per block of kMlpLossSamples.
+// Loss per sample and its gradient with respect to the logits, scaled by 1/n (the loss is a mean
+// over samples), on the interpolation error delta_f = e_f - sum_c w_fc e_c (zero at the corners):
+//   L2:      sum_f delta_f^2 / sum_f e_f^2;
+//   ENERGY:  delta^T A_cell delta / (cbar sum_f e_f^2), A_cell = sum over the cell's 27 elements of
+//            c_e K (Q1 Laplace, unit cube), c_e = exp(X_e), cbar the mean of the c_e.
+// One wavefront per sample: lane p holds the error at cell node p (x fastest over the 4x4x4 nodes),
+// the corner values and neighbouring errors arrive by lane shuffles, and each lane of a non-corner
+// node evaluates that node's softmax, so rows of E, X, Z and dZ are read and written contiguously.
+// Partial sums: one per block of kMlpLossSamples.
 constexpr int kMlpLossSamples = kBlock / 64;
 
+template <bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_mlp_loss(int64_t n, const float* __restrict__ Z,
-                                                     const float* __restrict__ E, float* __restrict__ dZ,
-                                                     double* __restrict__ partials) {
+                                                     const float* __restrict__ E, const float* __restrict__ X,
+                                                     float* __restrict__ dZ, double* __restrict__ partials) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * kMlpLossSamples + wid;
   float loss = 0.f;
@@ -160,13 +174,11 @@ __global__ __launch_bounds__(kBlock) void k_mlp_loss(int64_t n, const float* __r
 #pragma unroll
     for (int q = 0; q < 8; ++q) ec[q] = __shfl(ep, corner_pos(q), 64);
     const int node = c_pos2node[lane];
-    float l = 0.f;
+    float w[8], ev[8], delta = 0.f;
+    CellNode nd{};
     if (node >= 0) {
-      const CellNode nd = c_nodes[node];
-      const float* z = Z + i * kMlpOut;
-      float* dz = dZ + i * kMlpOut;
-      float w[8], ev[8];
-      node_softmax(z, nd, w);
+      nd = c_nodes[node];
+      node_softmax(Z + i * kMlpOut, nd, w);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         float v = 0.f;
@@ -177,18 +189,46 @@ __global__ __launch_bounds__(kBlock) void k_mlp_loss(int64_t n, const float* __r
       float pred = 0.f;
 #pragma unroll
       for (int c = 0; c < 8; ++c) pred += w[c] * ev[c];
-      const float res = ep - pred;
-      l = res * res;
-      const float dpred = -2.f * res / norm;
+      delta = ep - pred;
+    }
+    float g;  // d loss / d delta at this lane's node
+    if constexpr (ENERGY) {
+      const float ce = lane < 27 ? expf(X[i * kMlpIn + lane]) : 0.f;
+      const float cbar = wave_sum(ce) * (1.0f / 27.0f);
+      const int px = lane & 3, py = (lane >> 2) & 3, pz = lane >> 4;
+      float ad = 0.f;  // (A_cell delta) at this node: its elements, corner roles a, neighbours b
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int ex = px - (a & 1), ey = py - ((a >> 1) & 1), ez = pz - ((a >> 2) & 1);
+        const bool valid = (unsigned)ex < 3u && (unsigned)ey < 3u && (unsigned)ez < 3u;
+        const int e0x = valid ? ex : 0, e0y = valid ? ey : 0, e0z = valid ? ez : 0;
+        const float c = __shfl(ce, e0x + 3 * e0y + 9 * e0z, 64);  // every lane takes part
+        float sum = 0.f;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int nb = ((e0z + ((b >> 2) & 1)) * 4 + e0y + ((b >> 1) & 1)) * 4 + e0x + (b & 1);
+          sum += c_kq1[a * 8 + b] * __shfl(delta, nb, 64);
+        }
+        if (valid) ad += c * sum;
+      }
+      const float enorm = cbar * norm;
+      loss = wave_sum(delta * ad) / enorm;
+      g = 2.f * ad / enorm;
+    } else {
+      loss = wave_sum(delta * delta) / norm;
+      g = 2.f * delta / norm;
+    }
+    if (node >= 0) {
+      const float dpred = -g;
       float sdw = 0.f;
 #pragma unroll
       for (int c = 0; c < 8; ++c) sdw += dpred * ev[c] * w[c];
       const float inv_n = 1.0f / (float)n;
+      float* dz = dZ + i * kMlpOut;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         if (c < nd.ncorner) dz[nd.first + c] = w[c] * (dpred * ev[c] - sdw) * inv_n;
     }
-    loss = wave_sum(l) / norm;
   }
   __shared__ float sm[kMlpLossSamples];
   if (lane == 0) sm[wid] = loss;
@@ -342,10 +382,14 @@ void mlp_forward(int64_t n, const float* X, const float* theta, float* Z, float*
 
 int64_t mlp_loss_partials(int64_t n) { return cdiv(n, kMlpLossSamples); }
 
-int64_t mlp_loss(int64_t n, const float* Z, const float* E, float* dZ, double* partials, hipStream_t st) {
+int64_t mlp_loss(int64_t n, const float* Z, const float* E, const float* X, int kind, float* dZ, double* partials,
+                 hipStream_t st) {
   upload_tables();
   const int64_t nb = mlp_loss_partials(n);
-  hipLaunchKernelGGL(k_mlp_loss, dim3(nb), dim3(kBlock), 0, st, n, Z, E, dZ, partials);
+  if (kind == 1)
+    hipLaunchKernelGGL(k_mlp_loss<true>, dim3(nb), dim3(kBlock), 0, st, n, Z, E, X, dZ, partials);
+  else
+    hipLaunchKernelGGL(k_mlp_loss<false>, dim3(nb), dim3(kBlock), 0, st, n, Z, E, X, dZ, partials);
   LAUNCH_CHECK();
   return nb;
 }

@@ -38,11 +38,13 @@ SYMBOLS = (
     "rmg_mlp_set_params", "rmg_mlp_get_params", "rmg_mlp_add_data", "rmg_mlp_add_samples", "rmg_mlp_clear_data",
     "rmg_mlp_num_data", "rmg_mlp_get_data", "rmg_mlp_forward", "rmg_mlp_loss_grad", "rmg_mlp_adam_step",
     "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr", "rmg_mg_solve",
+    "rmg_mlp_set_loss",
 )
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
 P_GEOMETRIC, P_STORED, P_LEARNED = 0, 1, 2
 PW_NONFINITE, PW_SUPPORT, PW_DIRICHLET, PW_COPIES, PW_SUM, PW_JUDGED_WORSE = 1, 2, 4, 8, 16, 32
 MLP_NIN, MLP_NHIDDEN, MLP_NOUT, MLP_NPARAM = 27, 64, 208, 19472
+MLP_LOSS_L2, MLP_LOSS_ENERGY = 0, 1
 
 
 class Options(ctypes.Structure):
@@ -150,6 +152,7 @@ def load():
         "rmg_level_kernel": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "rmg_set_composite_csr": (I, [H, I, ctypes.c_int64, P, P, P, I]),
         "rmg_mg_solve": (I, [H, P, P, I, D, I, ctypes.POINTER(SolveInfo)]),
+        "rmg_mlp_set_loss": (I, [H, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -416,6 +419,10 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+    def set_loss(self, kind):
+        """MLP_LOSS_L2 or MLP_LOSS_ENERGY."""
+        _check(load().rmg_mlp_set_loss(self._m, kind))
 
     def set_params(self, theta):
         a = np.ascontiguousarray(theta, dtype=np.float32)

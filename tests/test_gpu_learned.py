@@ -84,6 +84,26 @@ def test_mlp_loss_and_gradient(hip_device, theta, n):
     m.close()
 
 
+@pytest.mark.parametrize("n", [3, 2000])
+def test_mlp_energy_loss_and_gradient(hip_device, theta, n):
+    from oracle import learned
+    from paper_2103_11962_amd import regmg
+
+    rng = np.random.default_rng(20 + n)
+    X = rng.standard_normal((n, 27)).astype(np.float32)
+    E = rng.standard_normal((n, 64)).astype(np.float32)
+    m = trainer()
+    m.set_params(theta)
+    m.set_loss(regmg.MLP_LOSS_ENERGY)
+    m.add_data(X, E)
+    loss, g = m.loss_grad()
+    Lr, gr = learned.loss_and_grad(theta.astype(np.float64), X.astype(np.float64),
+                                   E.astype(np.float64).reshape(n, 4, 4, 4), kind="energy")
+    assert abs(loss - Lr) <= 1e-5 * abs(Lr)
+    assert rel(g, gr) <= 1e-4, rel(g, gr)
+    m.close()
+
+
 def test_adam_steps(hip_device, theta):
     from oracle import learned
 
