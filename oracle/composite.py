@@ -1,7 +1,7 @@
 """Plain composite multigrid (the standard two-level method of the paper's
 Section 3 figure, applied recursively): sparse A, linear P, R = P^T,
 Abar = R A P, Chebyshev or damped Jacobi smoothing with the composite
-diagonal, dense coarse solve, and preconditioned CG.
+diagonal, or true lexicographic Gauss-Seidel, dense coarse solve, and preconditioned CG.
 
 This is the textbook method the regional form must reproduce up to rounding
 (Lemmas and Theorem of Section 3.1, Table 1 equivalence).  It uses the same
@@ -14,6 +14,7 @@ from dataclasses import dataclass
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import assembly, rng, transfer
 from .regional import Options
@@ -89,17 +90,39 @@ def jacobi(L: CLevel, u, b, r, opt: Options):
     return u
 
 
+def gauss_seidel(L: CLevel, u, b, r, opt: Options, backward=False):
+    """True Gauss-Seidel on the composite matrix, ``degree`` sweeps in lexicographic order
+    (reverse order when ``backward``): u += (D / omega + L)^-1 (b - A u), L the strictly lower
+    triangle of A (upper, ``backward``)."""
+    T = (sp.triu(L.A, 1) if backward else sp.tril(L.A, -1)) + sp.diags(L.A.diagonal() / opt.jacobi_omega)
+    T = sp.csr_matrix(T)
+    for i in range(opt.degree):
+        if i:
+            r = b - L.A @ u
+        u = u + spla.spsolve_triangular(T, r, lower=not backward)
+    return u
+
+
+def smooth(L: CLevel, u, b, r, opt: Options, post=False):
+    if opt.smoother == "chebyshev":
+        return chebyshev(L, u, b, r, opt)
+    if opt.smoother == "jacobi":
+        return jacobi(L, u, b, r, opt)
+    if opt.smoother in ("gs", "sgs"):
+        return gauss_seidel(L, u, b, r, opt, backward=post and opt.smoother == "sgs")
+    raise ValueError(f"unknown smoother {opt.smoother!r}")
+
+
 def vcycle(levels, b, opt: Options, l=0):
     L = levels[l]
     if l == len(levels) - 1:
         return np.linalg.solve(L.A.toarray(), b)
-    sm = chebyshev if opt.smoother == "chebyshev" else jacobi
-    u = sm(L, np.zeros_like(b), b, b, opt)
+    u = smooth(L, np.zeros_like(b), b, b, opt)
     r = b - L.A @ u
     ubar = vcycle(levels, L.P.T @ r, opt, l + 1)
     u = u + L.P @ ubar
     r = b - L.A @ u
-    return sm(L, u, b, r, opt)
+    return smooth(L, u, b, r, opt, post=True)
 
 
 def pcg(levels, b, opt: Options, rtol=1e-8, maxit=200):

@@ -15,6 +15,12 @@ Readings of points the paper leaves open:
 * Coarse composite operator Abar = Psi-bar [[Abar]] Psi-bar^T (the printed
   formula omits the right factor), solved densely.
 * Pre- and post-smoothing each apply one degree-K Chebyshev polynomial.
+* Region-local Gauss-Seidel (Algorithm 1): after a sweep the copies of an
+  interface node carry different corrections (each region saw only its own
+  updates); they are replaced by their average, so that u stays the regional
+  form of a composite vector.  The "gs" smoother sweeps forward before and after
+  the coarse correction; "sgs" sweeps backward (reverse lexicographic order)
+  after it.  The damping omega of Algorithm 1 is ``jacobi_omega``.
 * CG: textbook Hestenes-Stiefel with x0 = 0, preconditioner z = V(r, 0),
   stopping on the recursive residual ||r||/||b|| <= rtol.  Inner products are
   composite ones: every composite dof counted once.
@@ -25,6 +31,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import assembly, rng, transfer
 from .regions import Layout
@@ -70,7 +77,7 @@ class Options:
     boost: float = 1.1
     power_iters: int = 10
     seed: int = 0
-    smoother: str = "chebyshev"  # or "jacobi" (equivalence tests)
+    smoother: str = "chebyshev"  # or "jacobi", "gs", "sgs" (equivalence tests)
     jacobi_omega: float = 0.6
 
 
@@ -163,8 +170,47 @@ def jacobi(L: Level, u, b, r, opt: Options):
     return u
 
 
-def smooth(L, u, b, r, opt):
-    return chebyshev(L, u, b, r, opt) if opt.smoother == "chebyshev" else jacobi(L, u, b, r, opt)
+def region_matrix(L: Level, k: int):
+    """Region k's matrix [[A]]_k in region-local lexicographic order (x fastest, dof fastest)."""
+    cache = L.extra.setdefault("csr", {})
+    if k not in cache:
+        cache[k] = sp.csr_matrix(assembly.stencil_to_csr(L.coefs[k], L.lay.dim, L.lay.ndof))
+    return cache[k]
+
+
+def gauss_seidel(L: Level, u, b, r, opt: Options, backward=False):
+    """Region-local Gauss-Seidel (Algorithm 1), ``degree`` sweeps; r = b - A u on entry.
+
+    Per sweep: the composite residual r (its interface sum is the sweep's only communication);
+    then in every region k, visiting its dofs in lexicographic order, r_i -= sum_j A^(k)_ij delta_j
+    over the dofs already visited and delta_i = omega r_i / d~_i.  Unrolled, that is the triangular
+    solve (D~_k / omega + L_k) delta_k = r_k with L_k the strictly lower triangle of [[A]]_k (upper
+    triangle, ``backward``).  The copies' corrections are averaged (reading in the module header).
+    """
+    lay = L.lay
+    w = opt.jacobi_omega
+    for i in range(opt.degree):
+        if i:
+            r = L.residual(b, u)
+        delta = []
+        for k in range(lay.nreg):
+            A = region_matrix(L, k)
+            dg = 1.0 / L.dinv[k].reshape(-1)
+            T = (sp.triu(A, 1) if backward else sp.tril(A, -1)) + sp.diags(dg / w)
+            dk = spla.spsolve_triangular(sp.csr_matrix(T), r[k].reshape(-1), lower=not backward)
+            delta.append(dk.reshape(r[k].shape))
+        u = lin(1.0, u, 1.0, lay.to_regional(lay.to_composite_avg(delta)))
+    return u
+
+
+def smooth(L, u, b, r, opt, post=False):
+    if opt.smoother == "chebyshev":
+        return chebyshev(L, u, b, r, opt)
+    if opt.smoother == "jacobi":
+        return jacobi(L, u, b, r, opt)
+    if opt.smoother in ("gs", "sgs"):
+        return gauss_seidel(L, u, b, r, opt, backward=post and opt.smoother == "sgs")
+    raise ValueError(f"unknown smoother {opt.smoother!r}")
 
 
 def coarse_solve(L: Level, w):
@@ -188,7 +234,7 @@ def vcycle(levels, b, opt: Options, l: int = 0):
     ubar = vcycle(levels, w, opt, l + 1)
     u = lin(1.0, u, 1.0, transfer.regional_prolongate(L.lay, C.lay, L.P, ubar))
     r = L.residual(b, u)
-    return smooth(L, u, b, r, opt)
+    return smooth(L, u, b, r, opt, post=True)
 
 
 @dataclass

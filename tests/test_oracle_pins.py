@@ -470,3 +470,134 @@ def test_q1_rows_match_assembled_operator(name):
     got = assembly.q1_rows((nx, ny, nz), lay.dirichlet, x, nodes, w.pde, h=w.h, elem_coef=coef, nu=w.nu)
     want = np.array([ref[gz, gy, gx] for gx, gy, gz in nodes])
     np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+# ------------------------------------------------- region-local Gauss-Seidel
+def brute_force_region_gs(lay, coefs, dg, u, b, omega, sweeps, backward=False):
+    """Algorithm 1 node by node on dense region matrices: per sweep the composite residual, then
+    each region's dofs in (reverse) lexicographic order, r_i -= sum_j A_ij delta_j,
+    delta_i = omega r_i / d~_i, u_i += delta_i; finally the copies of u are averaged."""
+    Ad = [assembly.stencil_to_csr(c, lay.dim, lay.ndof).toarray() for c in coefs]
+    for _ in range(sweeps):
+        z = lay.interface_sum([(Ad[k] @ u[k].reshape(-1)).reshape(u[k].shape) for k in range(lay.nreg)])
+        r = [b[k] - z[k] for k in range(lay.nreg)]
+        new = []
+        for k in range(lay.nreg):
+            rk, uk, dk = r[k].reshape(-1).copy(), u[k].reshape(-1).copy(), dg[k].reshape(-1)
+            delta = np.zeros_like(rk)
+            order = range(rk.size - 1, -1, -1) if backward else range(rk.size)
+            for i in order:
+                rk[i] = rk[i] - sum(Ad[k][i, j] * delta[j] for j in np.nonzero(Ad[k][i])[0])
+                delta[i] = omega * rk[i] / dk[i]
+                uk[i] += delta[i]
+            new.append(uk.reshape(u[k].shape))
+        u = lay.to_regional(lay.to_composite_avg(new))
+    return u
+
+
+@pytest.mark.parametrize("case", ["2d", "3d", "elasticity", "uneven"])
+@pytest.mark.parametrize("backward", [False, True])
+def test_region_gs_against_brute_force(case, backward):
+    rg = np.random.default_rng(7)
+    if case == "elasticity":
+        o, e = synth.tensor_layout([[4, 4], [4], [4]])
+        lay = Layout(3, o, e, 1, 3)
+        coefs = assembly.regional_q1(lay, "elasticity", youngs=np.array([1.0, 3.0]), nu=0.3)
+    else:
+        dim, slabs = {"2d": (2, [[4, 5], [4, 4]]), "3d": (3, [[4, 4], [4, 4], [4]]),
+                      "uneven": (2, [[4, 7, 4], [7, 4]])}[case]
+        o, e = synth.tensor_layout(slabs)
+        lay = Layout(dim, o, e, 1)
+        if dim == 2:
+            coefs = assembly.regional_fd5(lay)
+        else:
+            coefs = assembly.regional_q1(lay, "diffusion",
+                                         elem_coef=np.exp(rg.normal(size=tuple(s - 1 for s in lay.shape))))
+    shp = lay.shape + ((lay.ndof,) if lay.ndof > 1 else ())
+    x0 = rg.uniform(-1, 1, size=shp)
+    x0[lay.dirichlet] = 0.0
+    b = rg.uniform(-1, 1, size=shp)
+    b[lay.dirichlet] = 0.0
+    u0, br = lay.to_regional(x0), lay.to_regional(b)
+    opt = regional.Options(nlevels=2, degree=2, smoother="gs", jacobi_omega=0.8)
+    L = regional.Level(lay, coefs)
+    dg = regional.composite_diagonal(lay, coefs)
+    L.dinv = [1.0 / d for d in dg]
+    got = regional.gauss_seidel(L, u0, br, L.residual(br, u0), opt, backward=backward)
+    ref = brute_force_region_gs(lay, coefs, dg, u0, br, 0.8, 2, backward=backward)
+    np.testing.assert_allclose(lay.flatten(got), lay.flatten(ref), rtol=0, atol=1e-13)
+
+
+def test_one_region_gs_is_textbook_gs():
+    """Without interfaces the region sweep is classical Gauss-Seidel on A: one sweep is
+    u + (D/omega + L)^-1 (b - A u) with dense matrices; many sweeps reach A^-1 b."""
+    o, e = synth.tensor_layout([[6], [5]])
+    lay = Layout(2, o, e, 15)
+    coefs = assembly.regional_fd5(lay)
+    A = assembly.composite_fd5(lay).toarray()
+    rg = np.random.default_rng(3)
+    b = rg.uniform(-1, 1, size=lay.shape)
+    b[lay.dirichlet] = 0.0
+    u = rg.uniform(-1, 1, size=lay.shape)
+    u[lay.dirichlet] = 0.0
+    for backward in (False, True):
+        opt = regional.Options(nlevels=1, degree=1, smoother="gs", jacobi_omega=0.7)
+        L = regional.Level(lay, coefs)
+        L.dinv = [1.0 / d for d in regional.composite_diagonal(lay, coefs)]
+        got = regional.gauss_seidel(L, [u.copy()], [b], L.residual([b], [u.copy()]), opt, backward=backward)[0]
+        T = (np.triu(A, 1) if backward else np.tril(A, -1)) + np.diag(np.diag(A)) / 0.7
+        ref = u.reshape(-1) + np.linalg.solve(T, b.reshape(-1) - A @ u.reshape(-1))
+        np.testing.assert_allclose(got.reshape(-1), ref, rtol=0, atol=1e-14)
+    opt = regional.Options(nlevels=1, degree=400, smoother="gs", jacobi_omega=1.0)
+    got = regional.gauss_seidel(L, [np.zeros_like(b)], [b], [b], opt)[0]
+    np.testing.assert_allclose(got.reshape(-1), np.linalg.solve(A, b.reshape(-1)), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("smoother", ["gs", "sgs"])
+def test_one_region_gs_vcycle_equals_composite(smoother):
+    o, e = synth.tensor_layout([[19], [19]])
+    lay = Layout(2, o, e, 15)
+    opt = regional.Options(nlevels=3, degree=1, smoother=smoother, jacobi_omega=1.0)
+    lv = regional.setup(lay, assembly.regional_fd5(lay), opt)
+    clv = composite.setup(lay, assembly.composite_fd5(lay), opt)
+    b = np.random.default_rng(5).uniform(-1, 1, size=lay.shape)
+    b[lay.dirichlet] = 0.0
+    z = regional.vcycle(lv, [b], opt)[0]
+    zc = composite.vcycle(clv, b.reshape(-1), opt)
+    np.testing.assert_allclose(z.reshape(-1), zc, rtol=0, atol=1e-13 * np.abs(zc).max())
+
+
+def test_symmetric_gs_vcycle_is_symmetric():
+    """Forward pre-sweeps and backward post-sweeps make the composite V-cycle a symmetric operator
+    (a transposed sweep direction breaks it); forward sweeps on both sides do not."""
+    w, lay = layout_of("c1_small")
+    A = assembly.composite_fd5(lay)
+    free = np.flatnonzero(~lay.dirichlet.reshape(-1))
+    rg = np.random.default_rng(11)
+    a, c = np.zeros(A.shape[0]), np.zeros(A.shape[0])
+    a[free], c[free] = rg.uniform(-1, 1, free.size), rg.uniform(-1, 1, free.size)
+    asym = {}
+    for sm in ("sgs", "gs"):
+        opt = regional.Options(nlevels=3, degree=1, smoother=sm, jacobi_omega=1.0)
+        clv = composite.setup(lay, A, opt)
+        va, vc = composite.vcycle(clv, a, opt), composite.vcycle(clv, c, opt)
+        asym[sm] = abs(c @ va - a @ vc) / (np.linalg.norm(a) * np.linalg.norm(vc))
+    assert asym["sgs"] < 1e-13 and asym["gs"] > 1e-4
+
+
+def test_region_gs_histories_close_to_composite():
+    """MG as a solver with Gauss-Seidel (Table 1 setting): the region-local smoother differs from
+    true Gauss-Seidel only through the interface updates, so the histories stay close."""
+    w, lay = layout_of("c1_small")
+    opt = regional.Options(nlevels=3, degree=1, smoother="gs", jacobi_omega=1.0)
+    lv = regional.setup(lay, assembly.regional_fd5(lay), opt)
+    clv = composite.setup(lay, assembly.composite_fd5(lay), opt)
+    b = synth.rhs(w)
+    _, h = regional.stationary(lv, lay.to_regional(b), lay.zeros_regional(), opt, 12)
+    _, hc = composite.stationary(clv, b.reshape(-1), np.zeros(b.size), opt, 12)
+    h, hc = np.asarray(h), np.asarray(hc)
+    ratio = h[1:] / hc[1:]
+    print("regional/composite GS residual ratios", np.round(ratio, 3))
+    assert np.all(ratio > 0.5) and np.all(ratio < 2.0)
+    assert not np.allclose(h, hc, rtol=1e-6)  # not the same smoother
+    assert h[-1] < 1e-6 and hc[-1] < 1e-6
