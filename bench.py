@@ -38,8 +38,8 @@ def cg_matvec_bytes_per_row(coefs):
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
-TRAFFIC_BYTES = 6364174191
-TRAFFIC_KERNEL_SHA = "a99af12a8afd74e5"
+TRAFFIC_BYTES = 6364099543
+TRAFFIC_KERNEL_SHA = "68845258008b14fe"
 
 CPU_SAMPLE = r"""
 import json, sys, time
@@ -353,9 +353,10 @@ def variant_noninvasive(dev):
 
 
 def variant_mg_solver(dev):
-    """Multigrid as a solver (the paper's experiments): damped Jacobi (omega 0.6, one sweep) on the
-    2D five-point 730^2 mesh in 3x3 regions to 1e-12 (the setting of the paper's Table 1), and the
-    Chebyshev V-cycle on the 3D Laplacian to 1e-8 beside its PCG solve."""
+    """Multigrid as a solver (the paper's experiments): damped Jacobi (omega 0.6, one sweep) and
+    region-local Gauss-Seidel on the 2D five-point 730^2 mesh in 3x3 regions to 1e-12 (the setting
+    of the paper's Table 1), and the Chebyshev V-cycle on the 3D Laplacian to 1e-8 beside its PCG
+    solve."""
     import synth
 
     out = {}
@@ -368,6 +369,14 @@ def variant_mg_solver(dev):
     hist = res["history"]
     out["jacobi_2d_730"] = {"solve_ms": ms, "cycles": res["iterations"], "relres": res["relres"],
                             "asymptotic_factor": (hist[-1] / hist[-11]) ** 0.1 if len(hist) > 11 else None}
+    # the same mesh with region-local Gauss-Seidel (one forward sweep, omega 1) and the
+    # symmetric variant (backward post-sweep)
+    for key, sm in (("gauss_seidel_2d_730", 2), ("symmetric_gauss_seidel_2d_730", 3)):
+        _setup(h, w, smoother=sm, jacobi_omega=1.0)
+        ms, res, _ = _timed_solves(h, b, reps=3, method="mg", rtol_override=1e-12)
+        hist = res["history"]
+        out[key] = {"solve_ms": ms, "cycles": res["iterations"], "relres": res["relres"],
+                    "asymptotic_factor": (hist[-1] / hist[-11]) ** 0.1 if len(hist) > 11 else None}
     h.close()
     w = synth.workload("c2")
     h = _handle(w, dev)
@@ -376,7 +385,8 @@ def variant_mg_solver(dev):
     ms, res, _ = _timed_solves(h, b, reps=2, method="mg")
     out["chebyshev_3d_c2"] = {"solve_ms": ms, "cycles": res["iterations"], "relres": res["relres"]}
     h.close()
-    out["workload"] = ("2D five-point 3x3 regions of 244^2 (730^2), 4 levels, Jacobi, to 1e-12; 3D Q1 Laplacian "
+    out["workload"] = ("2D five-point 3x3 regions of 244^2 (730^2), 4 levels, Jacobi or Gauss-Seidel, to 1e-12; "
+                       "3D Q1 Laplacian "
                        "4x4x4 regions of 82^3, 4 levels, Chebyshev degree 3, to 1e-8")
     return out
 

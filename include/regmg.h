@@ -90,8 +90,17 @@ typedef struct {
                          precision; read before tuning, appended after (NULL: no file) */
   int smoother;       /* 0 (default): Chebyshev of degree cheb_degree (Section 3.4, Algorithm 2);
                          1: damped Jacobi, cheb_degree sweeps of u += jacobi_omega D~^-1 r
-                         (Section 3.4, the smoother of Table 1) */
-  double jacobi_omega; /* damping of the Jacobi smoother (default 0.6) */
+                         (Section 3.4, the smoother of Table 1);
+                         2: region-local Gauss-Seidel (Section 3.4, Algorithm 1), cheb_degree
+                         sweeps before and after the coarse correction: per sweep the composite
+                         residual, then each region solves (D~/omega + L_k) delta = r with the
+                         lower triangle L_k of its own matrix in lexicographic order (x fastest,
+                         dofs of a node in order); the copies of an interface dof then take the
+                         average of their corrections;
+                         3: as 2, with the post-smoothing sweeps backward (upper triangle,
+                         reverse order).  2 and 3 need precision RMG_PREC_FP64 and cannot produce
+                         training errors for the interpolation network (rmg_mlp_add_samples) */
+  double jacobi_omega; /* damping omega of the Jacobi and Gauss-Seidel smoothers (default 0.6) */
   int symmetric;      /* 1 (default): on scalar 27-point 3D levels whose operator is symmetric to
                          rounding, the 2.5D kernel keeps only the upper half of each stencil
                          (14 coefficients per node) and reads a lower coupling from the

@@ -457,7 +457,10 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 3, RMG_ERR_ARG, "stencil_kernel must be 0..3");
   RMG_REQUIRE(opt->batched == 0 || opt->batched == 1, RMG_ERR_ARG, "batched must be 0 or 1");
   RMG_REQUIRE(opt->symmetric == 0 || opt->symmetric == 1, RMG_ERR_ARG, "symmetric must be 0 or 1");
-  RMG_REQUIRE(opt->smoother == 0 || opt->smoother == 1, RMG_ERR_ARG, "smoother must be 0 (Chebyshev) or 1 (Jacobi)");
+  RMG_REQUIRE(opt->smoother >= 0 && opt->smoother <= 3, RMG_ERR_ARG,
+              "smoother must be 0 (Chebyshev), 1 (Jacobi), 2 (Gauss-Seidel) or 3 (symmetric Gauss-Seidel)");
+  RMG_REQUIRE(opt->smoother < 2 || opt->precision == RMG_PREC_FP64, RMG_ERR_ARG,
+              "the Gauss-Seidel smoothers run in FP64 only");
   RMG_REQUIRE(opt->smoother == 0 || (opt->jacobi_omega > 0.0 && opt->jacobi_omega < 2.0), RMG_ERR_ARG,
               "jacobi_omega must lie in (0, 2)");
   RMG_REQUIRE(opt->judge_cycles >= 0 && opt->judge_cycles <= 1000, RMG_ERR_ARG, "judge_cycles must be in [0, 1000]");

@@ -38,6 +38,10 @@ int64_t launch_stencil_op(const Level& L, const StencilArgs& a, hipStream_t st);
 
 // Interface sum w = Psi^T Psi v on a level (FP64; v == w allowed).
 void launch_interface_sum(const Level& L, const double* v, double* w, hipStream_t st);
+// Region-local Gauss-Seidel sweep (kernels_gs.hip): delta = (D~/omega + L_k)^-1 r per region k
+// (upper triangle, reverse order, when backward); every copy of an interface dof := their average.
+void launch_gs_sweep(const Level& L, const double* r, double* delta, double omega, bool backward, hipStream_t st);
+void launch_interface_avg(const Level& L, double* w, hipStream_t st);
 
 // Owner-masked composite dot product (FP64): partial sums written to `partials`; returns their count.
 int64_t launch_dot(const Level& L, const double* a, const double* b, double* partials, hipStream_t st);

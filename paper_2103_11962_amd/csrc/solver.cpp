@@ -82,7 +82,7 @@ static double power_method(rmg_handle* h, Level& L, int level) {
 }
 
 static void chebyshev_coefficients(const rmg_options& o, Level& L) {
-  if (o.smoother == 1) {  // damped Jacobi: every step is d = omega D~^-1 r, u += d
+  if (o.smoother >= 1) {  // damped Jacobi: every step is d = omega D~^-1 r, u += d (unused by Gauss-Seidel)
     L.cheb_c1.assign(o.cheb_degree, 0.0);
     L.cheb_c2.assign(o.cheb_degree, o.jacobi_omega);
     return;
@@ -368,9 +368,38 @@ static void cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, con
   launch_stencil_op(L, a, h->stream);
 }
 
+// Region-local Gauss-Seidel (Section 3.4, Algorithm 1), cheb_degree sweeps on u in place (FP64).
+// Each sweep: the composite residual r = b - A u with its interface sum, the region sweeps into d,
+// the average of the copies of every interface dof, u += d.  zero: u is 0 on entry, so the first
+// residual is b and the first sweep writes its corrections straight into u.
+static void gs_smooth(rmg_handle* h, Level& L, const double* b, double* u, bool zero, bool backward) {
+  hipStream_t st = h->stream;
+  const double omega = h->opt.jacobi_omega;
+  for (int k = 0; k < h->opt.cheb_degree; ++k) {
+    if (zero && k == 0) {
+      launch_gs_sweep(L, b, u, omega, backward, st);
+      launch_interface_avg(L, u, st);
+      continue;
+    }
+    StencilArgs a;
+    a.op = StencilOp::Residual;
+    a.x = u;
+    a.out = L.r.p;
+    a.b = b;
+    launch_stencil_op(L, a, st);
+    launch_gs_sweep(L, L.r.as<double>(), L.d.as<double>(), omega, backward, st);
+    launch_interface_avg(L, L.d.as<double>(), st);
+    launch_add(L.ndofs(), L.d.as<double>(), u, st);
+  }
+}
+
 void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out) {
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
+  if (h->opt.smoother >= 2) {
+    gs_smooth(h, L, b, u_out, true, false);
+    return;
+  }
   const int K = h->opt.cheb_degree;
   void* buf[2] = {L.u.p, u_out};
   launch_cheb_zero(L, false, b, L.dinv.p, L.cheb_c2[0], L.d.p, buf[0], st);
@@ -384,6 +413,7 @@ void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out)
 
 void smooth_iterate(rmg_handle* h, int level, const double* b, double* u, double* tmp) {
   Level& L = *h->levels[level];
+  RMG_REQUIRE(h->opt.smoother < 2, RMG_ERR_ARG, "smooth_iterate: Chebyshev or Jacobi smoother only");
   void* buf[2] = {u, tmp};
   int cur = 0;
   for (int k = 0; k < h->opt.cheb_degree; ++k) {
@@ -510,6 +540,22 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
   hipStream_t st = h->stream;
   if (level == nl - 1) {
     launch_coarse_solve(L, lowp, b, z, st);
+    return;
+  }
+  if (h->opt.smoother >= 2) {  // region-local Gauss-Seidel (FP64 only), in place on z
+    double* u = static_cast<double*>(z);
+    gs_smooth(h, L, static_cast<const double*>(b), u, true, false);
+    StencilArgs a;
+    a.op = StencilOp::ResidualScaled;
+    a.x = u;
+    a.out = L.r.p;
+    a.b = b;
+    launch_stencil_op(L, a, st);
+    Level& C = *h->levels[level + 1];
+    launch_restrict(L, C, false, L.r.p, C.b.p, st);
+    vcycle(h, level + 1, false, C.b.p, C.u2.p);
+    launch_prolong_add(L, C, false, C.u2.p, u, st);
+    gs_smooth(h, L, static_cast<const double*>(b), u, false, h->opt.smoother == 3);
     return;
   }
   const int K = h->opt.cheb_degree;
