@@ -173,6 +173,27 @@ def composite_fd5(lay: Layout):
     return eliminate_csr(A, dirichlet_dofs(lay))
 
 
+def composite_fd7(lay: Layout):
+    """Composite seven-point Laplacian (6 on the diagonal, -1 to each face neighbour) with
+    eliminated Dirichlet nodes."""
+    assert lay.dim == 3 and lay.ndof == 1
+    nz, ny, nx = lay.shape
+    n = nx * ny * nz
+    idx = np.arange(n).reshape(nz, ny, nx)
+    rows, cols, vals = [idx.reshape(-1)], [idx.reshape(-1)], [np.full(n, 6.0)]
+    for ax in range(3):
+        a = [slice(None)] * 3
+        b = [slice(None)] * 3
+        a[ax] = slice(0, -1)
+        b[ax] = slice(1, None)
+        lo, hi = idx[tuple(a)].reshape(-1), idx[tuple(b)].reshape(-1)
+        rows += [lo, hi]
+        cols += [hi, lo]
+        vals += [np.full(lo.size, -1.0), np.full(lo.size, -1.0)]
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    return eliminate_csr(A, dirichlet_dofs(lay))
+
+
 def composite_q1(lay: Layout, pde, h=1.0, elem_coef=None, youngs=None, nu=0.3):
     """Composite Q1 operator assembled element by element over the whole mesh."""
     assert lay.dim == 3

@@ -110,6 +110,13 @@ def smooth(L: CLevel, u, b, r, opt: Options, post=False):
         return jacobi(L, u, b, r, opt)
     if opt.smoother in ("gs", "sgs"):
         return gauss_seidel(L, u, b, r, opt, backward=post and opt.smoother == "sgs")
+    if opt.smoother == "symgs":
+        for i in range(opt.degree):
+            if i:
+                r = b - L.A @ u
+            u = gauss_seidel(L, u, b, r, Options(degree=1, jacobi_omega=opt.jacobi_omega))
+            u = gauss_seidel(L, u, b, b - L.A @ u, Options(degree=1, jacobi_omega=opt.jacobi_omega), backward=True)
+        return u
     raise ValueError(f"unknown smoother {opt.smoother!r}")
 
 
@@ -119,7 +126,10 @@ def vcycle(levels, b, opt: Options, l=0):
         return np.linalg.solve(L.A.toarray(), b)
     u = smooth(L, np.zeros_like(b), b, b, opt)
     r = b - L.A @ u
-    ubar = vcycle(levels, L.P.T @ r, opt, l + 1)
+    bc = L.P.T @ r
+    ubar = vcycle(levels, bc, opt, l + 1)
+    if opt.gamma == 2 and l + 1 < len(levels) - 1:
+        ubar = ubar + vcycle(levels, bc - levels[l + 1].A @ ubar, opt, l + 1)
     u = u + L.P @ ubar
     r = b - L.A @ u
     return smooth(L, u, b, r, opt, post=True)

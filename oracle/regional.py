@@ -20,7 +20,9 @@ Readings of points the paper leaves open:
   updates); they are replaced by their average, so that u stays the regional
   form of a composite vector.  The "gs" smoother sweeps forward before and after
   the coarse correction; "sgs" sweeps backward (reverse lexicographic order)
-  after it.  The damping omega of Algorithm 1 is ``jacobi_omega``.
+  after it; "symgs" (symmetric Gauss-Seidel) does a forward then a backward
+  sweep per iteration, before and after.  The damping omega of Algorithm 1 is
+  ``jacobi_omega``.
 * CG: textbook Hestenes-Stiefel with x0 = 0, preconditioner z = V(r, 0),
   stopping on the recursive residual ||r||/||b|| <= rtol.  Inner products are
   composite ones: every composite dof counted once.
@@ -77,7 +79,8 @@ class Options:
     boost: float = 1.1
     power_iters: int = 10
     seed: int = 0
-    smoother: str = "chebyshev"  # or "jacobi", "gs", "sgs" (equivalence tests)
+    smoother: str = "chebyshev"  # or "jacobi", "gs", "sgs", "symgs"
+    gamma: int = 1  # coarse-level cycles per visit: 1 V-cycle, 2 W-cycle
     jacobi_omega: float = 0.6
 
 
@@ -178,28 +181,44 @@ def region_matrix(L: Level, k: int):
     return cache[k]
 
 
-def gauss_seidel(L: Level, u, b, r, opt: Options, backward=False):
-    """Region-local Gauss-Seidel (Algorithm 1), ``degree`` sweeps; r = b - A u on entry.
+def gs_sweep(L: Level, u, r, omega, backward=False):
+    """One region-local Gauss-Seidel sweep (Algorithm 1) from the composite residual r = b - A u.
 
-    Per sweep: the composite residual r (its interface sum is the sweep's only communication);
-    then in every region k, visiting its dofs in lexicographic order, r_i -= sum_j A^(k)_ij delta_j
-    over the dofs already visited and delta_i = omega r_i / d~_i.  Unrolled, that is the triangular
-    solve (D~_k / omega + L_k) delta_k = r_k with L_k the strictly lower triangle of [[A]]_k (upper
+    In every region k, visiting its dofs in lexicographic order, r_i -= sum_j A^(k)_ij delta_j over
+    the dofs already visited and delta_i = omega r_i / d~_i.  Unrolled, that is the triangular solve
+    (D~_k / omega + L_k) delta_k = r_k with L_k the strictly lower triangle of [[A]]_k (upper
     triangle, ``backward``).  The copies' corrections are averaged (reading in the module header).
     """
     lay = L.lay
-    w = opt.jacobi_omega
+    delta = []
+    for k in range(lay.nreg):
+        A = region_matrix(L, k)
+        dg = 1.0 / L.dinv[k].reshape(-1)
+        T = (sp.triu(A, 1) if backward else sp.tril(A, -1)) + sp.diags(dg / omega)
+        dk = spla.spsolve_triangular(sp.csr_matrix(T), r[k].reshape(-1), lower=not backward)
+        delta.append(dk.reshape(r[k].shape))
+    return lin(1.0, u, 1.0, lay.to_regional(lay.to_composite_avg(delta)))
+
+
+def gauss_seidel(L: Level, u, b, r, opt: Options, backward=False):
+    """``degree`` region-local Gauss-Seidel sweeps; r = b - A u on entry; the composite residual
+    is recomputed before every further sweep (its interface sum is the sweep's only
+    communication)."""
     for i in range(opt.degree):
         if i:
             r = L.residual(b, u)
-        delta = []
-        for k in range(lay.nreg):
-            A = region_matrix(L, k)
-            dg = 1.0 / L.dinv[k].reshape(-1)
-            T = (sp.triu(A, 1) if backward else sp.tril(A, -1)) + sp.diags(dg / w)
-            dk = spla.spsolve_triangular(sp.csr_matrix(T), r[k].reshape(-1), lower=not backward)
-            delta.append(dk.reshape(r[k].shape))
-        u = lin(1.0, u, 1.0, lay.to_regional(lay.to_composite_avg(delta)))
+        u = gs_sweep(L, u, r, opt.jacobi_omega, backward)
+    return u
+
+
+def symmetric_gauss_seidel(L: Level, u, b, r, opt: Options):
+    """``degree`` symmetric Gauss-Seidel iterations: each a forward sweep then a backward sweep,
+    each sweep from a fresh composite residual."""
+    for i in range(opt.degree):
+        if i:
+            r = L.residual(b, u)
+        u = gs_sweep(L, u, r, opt.jacobi_omega, backward=False)
+        u = gs_sweep(L, u, L.residual(b, u), opt.jacobi_omega, backward=True)
     return u
 
 
@@ -210,6 +229,8 @@ def smooth(L, u, b, r, opt, post=False):
         return jacobi(L, u, b, r, opt)
     if opt.smoother in ("gs", "sgs"):
         return gauss_seidel(L, u, b, r, opt, backward=post and opt.smoother == "sgs")
+    if opt.smoother == "symgs":
+        return symmetric_gauss_seidel(L, u, b, r, opt)
     raise ValueError(f"unknown smoother {opt.smoother!r}")
 
 
@@ -222,7 +243,8 @@ def coarse_solve(L: Level, w):
 
 
 def vcycle(levels, b, opt: Options, l: int = 0):
-    """z = V_l(b) with zero initial guess (Section 3.6 figure, recursive)."""
+    """z = V_l(b) with zero initial guess (Section 3.6 figure, recursive); with gamma = 2 every
+    level above the coarsest is visited twice per visit of the level above (W-cycle)."""
     L = levels[l]
     if l == len(levels) - 1:
         return coarse_solve(L, b)
@@ -232,6 +254,8 @@ def vcycle(levels, b, opt: Options, l: int = 0):
     C = levels[l + 1]
     w = transfer.regional_restrict(L.lay, C.lay, L.P, r)
     ubar = vcycle(levels, w, opt, l + 1)
+    if opt.gamma == 2 and l + 1 < len(levels) - 1:  # W-cycle: a second coarse cycle on its residual
+        ubar = lin(1.0, ubar, 1.0, vcycle(levels, C.residual(w, ubar), opt, l + 1))
     u = lin(1.0, u, 1.0, transfer.regional_prolongate(L.lay, C.lay, L.P, ubar))
     r = L.residual(b, u)
     return smooth(L, u, b, r, opt, post=True)

@@ -31,6 +31,7 @@ __all__ = [
     "batched_extents",
     "dirichlet_nodes",
     "fd5_composite_stencil",
+    "fd7_composite_stencil",
 ]
 
 
@@ -266,3 +267,28 @@ def fd5_composite_stencil(w: Workload) -> np.ndarray:
             c = np.where(dn, 1.0, c)
         out[s] = c
     return out.reshape(5, -1)
+
+
+def fd7_composite_stencil(w: Workload) -> np.ndarray:
+    """The 3D seven-point problem as an assembled composite stencil in the 27-point order
+    (dx fastest, then dy, dz), shape (27, nz*ny*nx): 6 on the diagonal, -1 to the six face
+    neighbours, every other offset zero; homogeneous Dirichlet nodes are identity rows with every
+    coupling to or from them removed.  This is the problem statement handed to the solver."""
+    assert w.dim == 3
+    nx, ny, nz = w.composite_shape_xyz
+    dn = dirichlet_nodes((nx, ny, nz), w.dirichlet_mask)
+    out = np.zeros((27, nz, ny, nx))
+    zz, yy, xx = np.indices((nz, ny, nx))
+    for s in range(27):
+        dx, dy, dz = s % 3 - 1, (s // 3) % 3 - 1, s // 9 - 1
+        if abs(dx) + abs(dy) + abs(dz) > 1:
+            continue
+        if (dx, dy, dz) == (0, 0, 0):
+            out[s] = np.where(dn, 1.0, 6.0)
+            continue
+        jx, jy, jz = xx + dx, yy + dy, zz + dz
+        inside = (jx >= 0) & (jx < nx) & (jy >= 0) & (jy < ny) & (jz >= 0) & (jz < nz)
+        nb_dir = np.zeros_like(inside)
+        nb_dir[inside] = dn[jz[inside], jy[inside], jx[inside]]
+        out[s] = np.where(inside & ~dn & ~nb_dir, -1.0, 0.0)
+    return out.reshape(27, -1)
