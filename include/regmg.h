@@ -98,8 +98,11 @@ typedef struct {
                          dofs of a node in order); the copies of an interface dof then take the
                          average of their corrections;
                          3: as 2, with the post-smoothing sweeps backward (upper triangle,
-                         reverse order).  2 and 3 need precision RMG_PREC_FP64 and cannot produce
-                         training errors for the interpolation network (rmg_mlp_add_samples) */
+                         reverse order);
+                         4: symmetric Gauss-Seidel: each of the cheb_degree iterations, before
+                         and after the coarse correction, is a forward sweep then a backward sweep.
+                         2, 3 and 4 need precision RMG_PREC_FP64 and cannot produce training
+                         errors for the interpolation network (rmg_mlp_add_samples) */
   double jacobi_omega; /* damping omega of the Jacobi and Gauss-Seidel smoothers (default 0.6) */
   int symmetric;      /* 1 (default): on scalar 27-point 3D levels whose operator is symmetric to
                          rounding, the 2.5D kernel keeps only the upper half of each stencil
@@ -112,6 +115,16 @@ typedef struct {
                          this many stationary V-cycles (rmg_convergence_factor) with the learned
                          and with the geometric interpolation at setup and keeps the better
                          hierarchy (default 10); 0 keeps the learned one whenever it is valid */
+  int hybrid;         /* 1: the hierarchy of the structured/unstructured mesh hybrid (Table 5):
+                         piecewise-constant transfers over aggregates, structured regions
+                         aggregating every node to its nearest rate-3 coarse point, unstructured
+                         regions (rmg_set_region_kinds) by staged plain aggregation whose first
+                         stage aggregates their interface nodes by the structured rule; every
+                         level's region matrices are sparse (Galerkin product per region); scalar
+                         FP64 problems, smoother 1, 2 or 4.  0 (default): geometric linear
+                         transfers on stencil levels */
+  int cycle_gamma;    /* coarse cycles per visit of a level: 1 (default) V-cycle, 2 W-cycle
+                         (hybrid hierarchy only) */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -250,6 +263,24 @@ rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, i
 rmg_status rmg_get_level_stencil(rmg_handle* h, int level, int region, double* host_out);
 /* Dense composite operator of the coarsest level (host, n_composite^2, row-major). */
 rmg_status rmg_get_coarse_matrix(rmg_handle* h, double* host_out);
+
+/* ---- structured/unstructured mesh hybrid (the paper's hybrid section, Table 5) ---- */
+/* Kind of every finest-level region for rmg_options.hybrid = 1: kinds[k] = 0 structured (default),
+   1 unstructured.  Host array of nreg entries; takes effect at the next rmg_setup_hierarchy. */
+rmg_status rmg_set_region_kinds(rmg_handle* h, const int32_t* kinds);
+/* Sizes of level `level` of the hybrid hierarchy: regional rows, composite nodes, stored nonzeros
+   of the region matrices.  RMG_ERR_NOT_SETUP without a hybrid hierarchy. */
+rmg_status rmg_hybrid_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t* n_composite,
+                                 int64_t* nnz);
+/* Aggregate of every regional row of level `level` (< nlevels - 1): the regional row of its coarse
+   node on level + 1, or -1 for a Dirichlet row.  Host array of n_regional entries. */
+rmg_status rmg_hybrid_aggregates(rmg_handle* h, int level, int32_t* agg);
+/* Composite node of every regional row of level `level` (finest level: the composite lattice
+   index; coarser levels: numbered by first sight, regions in order).  Host array of n_regional. */
+rmg_status rmg_hybrid_composite_ids(rmg_handle* h, int level, int64_t* comp);
+/* The region matrices of level `level` as one block-diagonal CSR matrix over the regional rows
+   (host arrays: rowptr n_regional + 1, colind and values nnz; columns ascending per row). */
+rmg_status rmg_hybrid_matrix(rmg_handle* h, int level, int64_t* rowptr, int32_t* colind, double* values);
 
 /* ---- kernel timing (for roofline measurements) ---- */
 

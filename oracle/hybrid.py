@@ -371,6 +371,39 @@ def stationary(levels, b, x0, opt: HOptions, rtol=1e-6, maxit=100):
     return x, hist
 
 
+def pcg(levels, b, opt: HOptions, rtol=1e-6, maxit=100):
+    """CG preconditioned by one cycle, x0 = 0, with the flexible coefficient
+    beta = (z_new, r_new - r_old) / (z_old, r_old) (the region-local sweeps average the interface
+    copies, so the cycle is not exactly a symmetric operator); composite inner products.
+    Returns (x, history of ||r|| / ||b||)."""
+    L = levels[0]
+
+    def dot(a, c):
+        return float(L.to_composite_owner(a) @ L.to_composite_owner(c))
+
+    x = [np.zeros_like(bk) for bk in b]
+    r = [bk.copy() for bk in b]
+    bnorm = L.norm(b)
+    hist = [1.0]
+    z = cycle(levels, r, opt)
+    p = [zk.copy() for zk in z]
+    rz = dot(r, z)
+    while len(hist) <= maxit:
+        q = L.matvec(p)
+        alpha = rz / dot(p, q)
+        x = [xk + alpha * pk for xk, pk in zip(x, p)]
+        r_old = r
+        r = [rk - alpha * qk for rk, qk in zip(r, q)]
+        hist.append(L.norm(r) / bnorm)
+        if hist[-1] <= rtol:
+            break
+        z = cycle(levels, r, opt)
+        beta = dot(z, [a - c for a, c in zip(r, r_old)]) / rz
+        rz = dot(r, z)
+        p = [zk + beta * pk for zk, pk in zip(z, p)]
+    return x, hist
+
+
 # ------------------------------------------------------------ composite form
 def composite_prolongator(L: HLevel, C: HLevel):
     """Composite P assembled from the region prolongators (each composite row from any copy;

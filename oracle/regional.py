@@ -324,10 +324,14 @@ def build_operator(lay: Layout, pde, h=1.0, elem_coef=None, youngs=None, nu=0.3)
     """Finest-level region matrices for the model problems."""
     if pde == "fd5":
         return assembly.regional_fd5(lay)
+    if pde == "fd7":
+        return assembly.split_composite(lay, assembly.composite_fd7(lay))
     return assembly.regional_q1(lay, pde, h=h, elem_coef=elem_coef, youngs=youngs, nu=nu)
 
 
 def composite_operator(lay: Layout, pde, h=1.0, elem_coef=None, youngs=None, nu=0.3):
     if pde == "fd5":
         return assembly.composite_fd5(lay)
+    if pde == "fd7":
+        return assembly.composite_fd7(lay)
     return assembly.composite_q1(lay, pde, h=h, elem_coef=elem_coef, youngs=youngs, nu=nu)

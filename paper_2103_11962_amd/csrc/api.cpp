@@ -107,6 +107,7 @@ void rmg_handle::drop_graphs() {
 
 rmg_handle::~rmg_handle() {
   drop_graphs();
+  rmg::hybrid_destroy(this);
   if (gstream) (void)hipStreamDestroy(gstream);
   for (Level* L : levels) delete L;
   levels.clear();
@@ -145,6 +146,8 @@ void rmg_options_default(rmg_options* o) {
   o->symmetric = 1;
   o->batched = 1;
   o->judge_cycles = 10;
+  o->hybrid = 0;
+  o->cycle_gamma = 1;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -457,8 +460,17 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 3, RMG_ERR_ARG, "stencil_kernel must be 0..3");
   RMG_REQUIRE(opt->batched == 0 || opt->batched == 1, RMG_ERR_ARG, "batched must be 0 or 1");
   RMG_REQUIRE(opt->symmetric == 0 || opt->symmetric == 1, RMG_ERR_ARG, "symmetric must be 0 or 1");
-  RMG_REQUIRE(opt->smoother >= 0 && opt->smoother <= 3, RMG_ERR_ARG,
-              "smoother must be 0 (Chebyshev), 1 (Jacobi), 2 (Gauss-Seidel) or 3 (symmetric Gauss-Seidel)");
+  RMG_REQUIRE(opt->smoother >= 0 && opt->smoother <= 4, RMG_ERR_ARG,
+              "smoother must be 0 (Chebyshev), 1 (Jacobi), 2 (Gauss-Seidel), 3 (forward/backward "
+              "Gauss-Seidel) or 4 (symmetric Gauss-Seidel)");
+  RMG_REQUIRE(opt->hybrid == 0 || opt->hybrid == 1, RMG_ERR_ARG, "hybrid must be 0 or 1");
+  RMG_REQUIRE(opt->cycle_gamma == 1 || (opt->cycle_gamma == 2 && opt->hybrid == 1), RMG_ERR_ARG,
+              "cycle_gamma must be 1, or 2 with the hybrid hierarchy");
+  RMG_REQUIRE(!opt->hybrid || opt->smoother == 1 || opt->smoother == 2 || opt->smoother == 4, RMG_ERR_ARG,
+              "the hybrid hierarchy smooths with Jacobi (1), Gauss-Seidel (2) or symmetric Gauss-Seidel (4)");
+  RMG_REQUIRE(!opt->hybrid || opt->precision == RMG_PREC_FP64, RMG_ERR_ARG, "the hybrid hierarchy runs in FP64");
+  RMG_REQUIRE(!opt->hybrid || h->pmode == RMG_P_GEOMETRIC, RMG_ERR_ARG,
+              "the hybrid hierarchy builds its own transfers (no stored or learned interpolation)");
   RMG_REQUIRE(opt->smoother < 2 || opt->precision == RMG_PREC_FP64, RMG_ERR_ARG,
               "the Gauss-Seidel smoothers run in FP64 only");
   RMG_REQUIRE(opt->smoother == 0 || (opt->jacobi_omega > 0.0 && opt->jacobi_omega < 2.0), RMG_ERR_ARG,

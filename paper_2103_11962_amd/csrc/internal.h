@@ -185,6 +185,10 @@ struct KernelTimer {
 enum TimedKernel { kTimedCheb = 0, kTimedCgQ = 1, kNumTimed = 2 };
 }  // namespace rmg
 
+namespace rmg {
+struct Hybrid;  // hybrid.cpp
+}
+
 struct rmg_handle {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -219,6 +223,9 @@ struct rmg_handle {
   // interpolation of the current hierarchy
   int p_used = 0, p_flags = 0;
   double rho_learned = -1.0, rho_geometric = -1.0;
+  // structured/unstructured hybrid: region kinds (0 structured, 1 unstructured) and the hierarchy
+  std::vector<int32_t> region_kind;
+  rmg::Hybrid* hy = nullptr;
   ~rmg_handle();
 };
 
@@ -251,6 +258,15 @@ void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out)
 void smooth_iterate(rmg_handle* h, int level, const double* b, double* u, double* tmp);
 // Convergence factor of `cycles` stationary V-cycles on A x = 0 (FP64 outer iteration).
 double convergence_factor(rmg_handle* h, int cycles);
+
+// solver.cpp: finest-level work vectors and launch configuration for the outer CG / MG loop.
+void prepare_finest(rmg_handle* h);
+
+// hybrid.cpp: the structured/unstructured hybrid hierarchy (rmg_options.hybrid = 1).
+void hybrid_setup(rmg_handle* h);
+void hybrid_destroy(rmg_handle* h);
+// z = cycle_0(b) with zero initial guess (regional FP64 vectors of the finest level).
+void hybrid_cycle(rmg_handle* h, const double* b, double* z);
 
 // learned.cpp
 // Stored weights of the finest level for the next coarse level C (caller or learned); returns the

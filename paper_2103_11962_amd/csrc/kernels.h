@@ -42,6 +42,8 @@ void launch_interface_sum(const Level& L, const double* v, double* w, hipStream_
 // (upper triangle, reverse order, when backward); every copy of an interface dof := their average.
 void launch_gs_sweep(const Level& L, const double* r, double* delta, double omega, bool backward, hipStream_t st);
 void launch_interface_avg(const Level& L, double* w, hipStream_t st);
+// The same on explicit interface groups: every copy := sum (avg = false) or average of the copies.
+void launch_group_reduce(const int64_t* gptr, const int* gcopy, int64_t ngroups, double* w, bool avg, hipStream_t st);
 
 // Owner-masked composite dot product (FP64): partial sums written to `partials`; returns their count.
 int64_t launch_dot(const Level& L, const double* a, const double* b, double* partials, hipStream_t st);
@@ -92,6 +94,8 @@ void launch_to_composite(const Level& L, const double* reg, double* comp, int av
 
 // Coarsest level: gather owner copies, dense FP64 GEMV with the inverse, scatter to copies.
 void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipStream_t st);
+// y = A x, A row-major n x n (one wavefront per row).
+void launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t st);
 // In-place blocked Gauss-Jordan inversion of an SPD n x n matrix (row-major); synchronises st.
 void launch_gauss_jordan(double* A, int n, hipStream_t st);
 void launch_check_inverse(const double* A, int n, int* flag, hipStream_t st);

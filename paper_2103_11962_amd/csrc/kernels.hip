@@ -740,6 +740,12 @@ __global__ __launch_bounds__(256) void k_gemv(int n, const double* __restrict__ 
   if (lane == 0) y[row] = s;
 }
 
+void launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, 4)), dim3(256), 0, st, n, A, x, y);
+  LAUNCH_CHECK();
+}
+
 void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipStream_t st) {
   const int n = L.nc;
   const int ncnode = (int)L.ncomp;

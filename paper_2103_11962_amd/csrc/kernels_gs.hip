@@ -16,8 +16,8 @@
 // the barrier (all waves of a block share the CU's vector L1, and the barrier orders the accesses).
 //
 // After the sweep the copies of an interface node hold different corrections (each region saw only
-// its own updates); k_iface_avg replaces them by their average, so the regional vector stays the
-// regional form of a composite one.
+// its own updates); k_group_reduce<AVG> replaces them by their average, so the regional vector
+// stays the regional form of a composite one.
 #include "device_common.h"
 
 namespace rmg {
@@ -106,20 +106,19 @@ void launch_gs_sweep(const Level& L, const double* r, double* delta, double omeg
   else gs_launch<5, 1>(L, r, delta, omega, backward, st);
 }
 
-// Every copy of an interface dof receives the average of the copies (summed in ascending region
-// order, then divided by the number of copies).
-template <int NDOF>
-__global__ __launch_bounds__(kBlock) void k_iface_avg(const int64_t* __restrict__ gptr, const int* __restrict__ gcopy,
-                                                      int64_t ng, double* w) {
+// Every copy of an interface dof receives the sum (AVG: the average) of the copies, summed in
+// ascending region order.
+template <int NDOF, bool AVG>
+__global__ __launch_bounds__(kBlock) void k_group_reduce(const int64_t* __restrict__ gptr,
+                                                         const int* __restrict__ gcopy, int64_t ng, double* w) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= ng) return;
   const int64_t a0 = gptr[g], e = gptr[g + 1];
-  const double inv = 1.0 / (double)(e - a0);
 #pragma unroll
   for (int a = 0; a < NDOF; ++a) {
     double s = 0.0;
     for (int64_t c = a0; c < e; ++c) s += w[(int64_t)gcopy[c] * NDOF + a];
-    s *= inv;
+    if (AVG) s *= 1.0 / (double)(e - a0);
     for (int64_t c = a0; c < e; ++c) w[(int64_t)gcopy[c] * NDOF + a] = s;
   }
 }
@@ -128,11 +127,21 @@ void launch_interface_avg(const Level& L, double* w, hipStream_t st) {
   if (L.ngroups == 0) return;
   const dim3 g(cdiv(L.ngroups, kBlock));
   if (L.ndof == 3)
-    hipLaunchKernelGGL((k_iface_avg<3>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
-                       L.ngroups, w);
+    hipLaunchKernelGGL((k_group_reduce<3, true>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
+                       L.d_gcopy.as<int>(), L.ngroups, w);
   else
-    hipLaunchKernelGGL((k_iface_avg<1>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
-                       L.ngroups, w);
+    hipLaunchKernelGGL((k_group_reduce<1, true>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
+                       L.d_gcopy.as<int>(), L.ngroups, w);
+  LAUNCH_CHECK();
+}
+
+void launch_group_reduce(const int64_t* gptr, const int* gcopy, int64_t ngroups, double* w, bool avg, hipStream_t st) {
+  if (ngroups == 0) return;
+  const dim3 g(cdiv(ngroups, kBlock));
+  if (avg)
+    hipLaunchKernelGGL((k_group_reduce<1, true>), g, dim3(kBlock), 0, st, gptr, gcopy, ngroups, w);
+  else
+    hipLaunchKernelGGL((k_group_reduce<1, false>), g, dim3(kBlock), 0, st, gptr, gcopy, ngroups, w);
   LAUNCH_CHECK();
 }
 

@@ -214,6 +214,37 @@ static void autotune_level(rmg_handle* h, Level& L, int level, bool lowp) {
   }
 }
 
+// Launch configuration, work vectors and symmetric half-stencil copy of one stencil level.
+static void configure_level(rmg_handle* h, Level& L, bool with_b, bool sym) {
+  const rmg_options& o = h->opt;
+  if (L.dim == 3 && L.tile_depth != 21) make_tiles(L, 21);
+  L.tile_grid = 0;
+  L.per_region = o.batched == 0;
+  L.use_tiles = !L.per_region && L.ndof == 1 && !L.tiles.empty() &&
+                (o.stencil_kernel >= 2 || (o.stencil_kernel == 0 && L.tiles.size() >= kAutoTileMin));
+  // persistent tiles: 4 blocks per CU, and at least two tiles per block
+  if (L.use_tiles && o.stencil_kernel == 3) L.tile_grid = std::max(1, std::min(1024, (int)(L.tiles.size() + 1) / 2));
+  alloc_vectors(L, with_b);
+  L.ct_lo = kCoefF64;
+  L.coef_lo.release();
+  L.center_lo.release();
+  L.coef_lo_sym.release();
+  if (sym) launch_make_sym(L, false, h->stream);
+  else L.coef_sym.release();
+}
+
+void prepare_finest(rmg_handle* h) {
+  Level* L0 = h->levels[0];
+  for (size_t i = 1; i < h->levels.size(); ++i) delete h->levels[i];
+  h->levels.resize(1);
+  h->tune_report.clear();
+  h->partials.alloc(sizeof(double) * partial_capacity(*L0));
+  configure_level(h, *L0, false, h->opt.symmetric != 0);
+  L0->pw.release();
+  L0->rw.release();
+  RMG_HIP(hipStreamSynchronize(h->stream));
+}
+
 // Levels 0 .. nlevels-1: smoother data, next level by per-region Galerkin product, and the
 // coarsest level's direct solver.  `stored`: the finest level interpolates with stored (caller
 // or learned) weights when they are valid; returns their validity flags (0 when valid or unused).
@@ -231,21 +262,7 @@ static int build_levels(rmg_handle* h, bool stored) {
   flag.alloc(sizeof(int));
   for (int l = 0; l < o.nlevels; ++l) {
     Level& L = *h->levels[l];
-    if (L.dim == 3 && L.tile_depth != 21) make_tiles(L, 21);
-    L.tile_grid = 0;
-    L.per_region = o.batched == 0;
-    L.use_tiles = !L.per_region && L.ndof == 1 && !L.tiles.empty() &&
-                  (o.stencil_kernel >= 2 || (o.stencil_kernel == 0 && L.tiles.size() >= kAutoTileMin));
-    // persistent tiles: 4 blocks per CU, and at least two tiles per block
-    if (L.use_tiles && o.stencil_kernel == 3)
-      L.tile_grid = std::max(1, std::min(1024, (int)(L.tiles.size() + 1) / 2));
-    alloc_vectors(L, l > 0);
-    L.ct_lo = kCoefF64;
-    L.coef_lo.release();
-    L.center_lo.release();
-    L.coef_lo_sym.release();
-    if (o.symmetric && l < o.nlevels - 1) launch_make_sym(L, false, st);
-    else L.coef_sym.release();  // (the coarsest level is solved directly)
+    configure_level(h, L, l > 0, o.symmetric && l < o.nlevels - 1);  // (the coarsest is solved directly)
     if (lowp) alloc_vectors_lowp(L, true);  // level 0's b32 holds the FP32 copy of the CG residual
     if (l == o.nlevels - 1) {
       build_coarse_solver(h, L);
@@ -303,11 +320,18 @@ void setup_hierarchy(rmg_handle* h) {
                   "region " + std::to_string(k) + ": extent-1 and origin must be divisible by 3^(nlevels-1) = " +
                       std::to_string(f));
   }
+  h->p_used = RMG_P_GEOMETRIC;
+  h->rho_learned = h->rho_geometric = -1.0;
+  h->p_flags = 0;
+  hybrid_destroy(h);
+  if (o.hybrid) {  // aggregation hierarchy of the structured/unstructured hybrid
+    prepare_finest(h);
+    hybrid_setup(h);
+    return;
+  }
   const bool stored = h->pmode != RMG_P_GEOMETRIC;
   RMG_REQUIRE(!stored || (L0->dim == 3 && L0->ndof == 1), RMG_ERR_ARG,
               "stored or learned interpolation needs a scalar 3D problem");
-  h->p_used = RMG_P_GEOMETRIC;
-  h->rho_learned = h->rho_geometric = -1.0;
   h->p_flags = build_levels(h, stored);
   if (stored && h->p_flags == 0) h->p_used = h->pmode;
   if (h->p_used != RMG_P_LEARNED || o.judge_cycles <= 0) return;
@@ -372,28 +396,35 @@ static void cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, con
 // Each sweep: the composite residual r = b - A u with its interface sum, the region sweeps into d,
 // the average of the copies of every interface dof, u += d.  zero: u is 0 on entry, so the first
 // residual is b and the first sweep writes its corrections straight into u.
-static void gs_smooth(rmg_handle* h, Level& L, const double* b, double* u, bool zero, bool backward) {
+static void gs_sweep(rmg_handle* h, Level& L, const double* b, double* u, bool zero, bool backward) {
   hipStream_t st = h->stream;
   const double omega = h->opt.jacobi_omega;
+  if (zero) {
+    launch_gs_sweep(L, b, u, omega, backward, st);
+    launch_interface_avg(L, u, st);
+    return;
+  }
+  StencilArgs a;
+  a.op = StencilOp::Residual;
+  a.x = u;
+  a.out = L.r.p;
+  a.b = b;
+  launch_stencil_op(L, a, st);
+  launch_gs_sweep(L, L.r.as<double>(), L.d.as<double>(), omega, backward, st);
+  launch_interface_avg(L, L.d.as<double>(), st);
+  launch_add(L.ndofs(), L.d.as<double>(), u, st);
+}
+
+// smoother 4 (symmetric Gauss-Seidel): every iteration a forward then a backward sweep.
+static void gs_smooth(rmg_handle* h, Level& L, const double* b, double* u, bool zero, bool backward) {
   for (int k = 0; k < h->opt.cheb_degree; ++k) {
-    if (zero && k == 0) {
-      launch_gs_sweep(L, b, u, omega, backward, st);
-      launch_interface_avg(L, u, st);
-      continue;
-    }
-    StencilArgs a;
-    a.op = StencilOp::Residual;
-    a.x = u;
-    a.out = L.r.p;
-    a.b = b;
-    launch_stencil_op(L, a, st);
-    launch_gs_sweep(L, L.r.as<double>(), L.d.as<double>(), omega, backward, st);
-    launch_interface_avg(L, L.d.as<double>(), st);
-    launch_add(L.ndofs(), L.d.as<double>(), u, st);
+    gs_sweep(h, L, b, u, zero && k == 0, backward && h->opt.smoother != 4);
+    if (h->opt.smoother == 4) gs_sweep(h, L, b, u, false, true);
   }
 }
 
 void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out) {
+  RMG_REQUIRE(h->hy == nullptr, RMG_ERR_ARG, "per-level smoothing is not available on the hybrid hierarchy");
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
   if (h->opt.smoother >= 2) {
@@ -591,6 +622,10 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
 // z = M^-1 r with the configured precision (FP64 regional vectors in and out).
 static void precondition(rmg_handle* h, const double* r, double* z) {
   Level& L = *h->levels[0];
+  if (h->hy) {
+    hybrid_cycle(h, r, z);
+    return;
+  }
   if (h->opt.precision == RMG_PREC_FP64) {
     vcycle(h, 0, false, r, z);
     return;
@@ -602,8 +637,8 @@ static void precondition(rmg_handle* h, const double* r, double* z) {
 
 void apply_preconditioner(rmg_handle* h, const double* r, double* z) { precondition(h, r, z); }
 
-// Preconditioned CG (textbook Hestenes-Stiefel).  With a low-precision V-cycle the
-// preconditioner is only approximately a fixed symmetric operator, so the flexible
+// Preconditioned CG (textbook Hestenes-Stiefel).  With a low-precision V-cycle, or the hybrid
+// cycle, the preconditioner is only approximately a fixed symmetric operator, so the flexible
 // (Polak-Ribiere) coefficient beta = (z_new, r_new - r_old) / (z_old, r_old) =
 // -alpha (z_new, q) / (z_old, r_old) is used; the residual, the update and all inner products
 // stay in FP64.
@@ -657,7 +692,8 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
   Level& L = *h->levels[0];
   hipStream_t st = h->stream;
   const int64_t n = L.ndofs();
-  const bool flexible = h->opt.precision != RMG_PREC_FP64;
+  // the hybrid cycle's region-local sweeps average the interface copies: not exactly symmetric
+  const bool flexible = h->opt.precision != RMG_PREC_FP64 || h->hy != nullptr;
   const bool graphs = h->opt.use_graph != 0;
   double* r = h->cg_r.as<double>();
   double* p = h->cg_p.as<double>();

@@ -38,8 +38,10 @@ SYMBOLS = (
     "rmg_mlp_set_params", "rmg_mlp_get_params", "rmg_mlp_add_data", "rmg_mlp_add_samples", "rmg_mlp_clear_data",
     "rmg_mlp_num_data", "rmg_mlp_get_data", "rmg_mlp_forward", "rmg_mlp_loss_grad", "rmg_mlp_adam_step",
     "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr", "rmg_mg_solve",
-    "rmg_mlp_set_loss",
+    "rmg_mlp_set_loss", "rmg_set_region_kinds", "rmg_hybrid_level_info", "rmg_hybrid_aggregates",
+    "rmg_hybrid_composite_ids", "rmg_hybrid_matrix",
 )
+SMOOTHER_CHEBYSHEV, SMOOTHER_JACOBI, SMOOTHER_GS, SMOOTHER_GS_FB, SMOOTHER_SYMGS = 0, 1, 2, 3, 4
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
 P_GEOMETRIC, P_STORED, P_LEARNED = 0, 1, 2
 PW_NONFINITE, PW_SUPPORT, PW_DIRICHLET, PW_COPIES, PW_SUM, PW_JUDGED_WORSE = 1, 2, 4, 8, 16, 32
@@ -65,6 +67,8 @@ class Options(ctypes.Structure):
         ("symmetric", ctypes.c_int),
         ("batched", ctypes.c_int),
         ("judge_cycles", ctypes.c_int),
+        ("hybrid", ctypes.c_int),
+        ("cycle_gamma", ctypes.c_int),
     ]
 
 
@@ -153,6 +157,12 @@ def load():
         "rmg_set_composite_csr": (I, [H, I, ctypes.c_int64, P, P, P, I]),
         "rmg_mg_solve": (I, [H, P, P, I, D, I, ctypes.POINTER(SolveInfo)]),
         "rmg_mlp_set_loss": (I, [H, I]),
+        "rmg_set_region_kinds": (I, [H, P]),
+        "rmg_hybrid_level_info": (I, [H, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]),
+        "rmg_hybrid_aggregates": (I, [H, I, P]),
+        "rmg_hybrid_composite_ids": (I, [H, I, P]),
+        "rmg_hybrid_matrix": (I, [H, I, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -321,6 +331,40 @@ class Handle:
         _check(load().rmg_level_info(self._h, level, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(npts),
                                      ctypes.byref(lam)))
         return {"n_regional": nr.value, "n_composite": nc.value, "npts": npts.value, "lambda": lam.value}
+
+    # ---- structured/unstructured hybrid hierarchy
+    def set_region_kinds(self, kinds):
+        """kinds[k] = 0 structured, 1 unstructured (used with setup_hierarchy(hybrid=1))."""
+        k = np.ascontiguousarray(kinds, dtype=np.int32)
+        _check(load().rmg_set_region_kinds(self._h, k.ctypes.data_as(ctypes.c_void_p)))
+
+    def hybrid_level_info(self, level):
+        n, c, z = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().rmg_hybrid_level_info(self._h, level, ctypes.byref(n), ctypes.byref(c), ctypes.byref(z)))
+        return {"n_regional": n.value, "n_composite": c.value, "nnz": z.value}
+
+    def hybrid_aggregates(self, level):
+        out = np.zeros(self.hybrid_level_info(level)["n_regional"], dtype=np.int32)
+        _check(load().rmg_hybrid_aggregates(self._h, level, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def hybrid_composite_ids(self, level):
+        out = np.zeros(self.hybrid_level_info(level)["n_regional"], dtype=np.int64)
+        _check(load().rmg_hybrid_composite_ids(self._h, level, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def hybrid_matrix(self, level):
+        """The level's region matrices as one block-diagonal scipy CSR matrix over regional rows."""
+        import scipy.sparse as sp
+
+        info = self.hybrid_level_info(level)
+        n, nnz = info["n_regional"], info["nnz"]
+        rp = np.zeros(n + 1, dtype=np.int64)
+        ci = np.zeros(max(nnz, 1), dtype=np.int32)
+        v = np.zeros(max(nnz, 1))
+        _check(load().rmg_hybrid_matrix(self._h, level, rp.ctypes.data_as(ctypes.c_void_p),
+                                        ci.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p)))
+        return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(n, n))
 
     def level_kernel(self, level):
         k, c, cl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -47,7 +47,7 @@ class Workload:
     dirichlet_mask: int
     nlevels: int
     cheb_degree: int
-    pde: str  # "fd5" (2D five-point), "laplace", "diffusion", "elasticity"
+    pde: str  # "fd5" (2D five-point), "fd7" (3D seven-point), "laplace", "diffusion", "elasticity"
     h: float = 1.0
     nu: float = 0.3
     seed: int = 0

@@ -22,6 +22,8 @@ def gpu_problem(w, device=0, setup=True, **opts):
     h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
     if w.pde == "fd5":
         h.set_composite_stencil(5, synth.fd5_composite_stencil(w))
+    elif w.pde == "fd7":
+        h.set_composite_stencil(27, synth.fd7_composite_stencil(w))
     elif w.pde == "laplace":
         h.assemble_q1(regmg.PDE_LAPLACE, w.h)
     elif w.pde == "elasticity":

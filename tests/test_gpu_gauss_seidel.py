@@ -17,7 +17,7 @@ from tests import harness
 pytestmark = pytest.mark.gpu
 
 CASES = ["c1_small", "c2_small", "c3_small", "c4_small", "c5_small"]
-NAMES = {2: "gs", 3: "sgs"}
+NAMES = {2: "gs", 3: "sgs", 4: "symgs"}
 
 
 def rel(a, b):
@@ -47,7 +47,7 @@ def test_gs_smoother_regional_output(hip_device, name):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("smoother", [2, 3])
+@pytest.mark.parametrize("smoother", [2, 3, 4])
 def test_gs_vcycle(hip_device, name, smoother):
     import torch
 
@@ -125,7 +125,7 @@ def test_gs_option_errors(hip_device):
 
     w = synth.workload("c2_small")
     h = harness.gpu_problem(w, setup=False)
-    for bad in (dict(smoother=4), dict(smoother=2, precision=1), dict(smoother=2, jacobi_omega=2.0)):
+    for bad in (dict(smoother=5), dict(smoother=2, precision=1), dict(smoother=4, jacobi_omega=2.0)):
         with pytest.raises(regmg.RmgError) as e:
             h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree, **bad)
         assert e.value.status == "RMG_ERR_ARG"
