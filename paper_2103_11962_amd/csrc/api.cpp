@@ -193,6 +193,8 @@ rmg_status rmg_build_regions(rmg_handle* h, int dim, int ndof, int nreg, const i
   RMG_REQUIRE(nreg >= 1 && extent && origin, RMG_ERR_ARG, "need nreg >= 1 and extent/origin arrays");
   RMG_REQUIRE(mask < (1u << (2 * dim)), RMG_ERR_ARG, "dirichlet mask has bits beyond 2*dim");
   h->have_regions = h->have_operator = h->have_hierarchy = false;
+  hybrid_destroy(h);
+  h->region_kind.clear();
   h->user_pw.release();
   h->logc.release();
   if (h->pmode == RMG_P_STORED) h->pmode = RMG_P_GEOMETRIC;

@@ -428,15 +428,48 @@ void upload_level(rmg_handle* h, HLevel& H, bool coarsest, int64_t nc_next) {
     RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "hybrid: coarsest composite matrix is singular");
     return;
   }
-  std::vector<int32_t> reg, lv, rows;
-  gs_schedule(H, false, reg, lv, rows);
-  upload(D.f_reg, reg, st);
-  upload(D.f_lv, lv, st);
-  upload(D.f_rows, rows, st);
-  gs_schedule(H, true, reg, lv, rows);
-  upload(D.b_reg, reg, st);
-  upload(D.b_lv, lv, st);
-  upload(D.b_rows, rows, st);
+  for (int dir = 0; dir < 2; ++dir) {  // Gauss-Seidel schedules with their couplings by position
+    const bool backward = dir == 1;
+    HLevelDev::Sweep& S = backward ? D.bwd : D.fwd;
+    std::vector<int32_t> reg, lv, rows;
+    gs_schedule(H, backward, reg, lv, rows);
+    std::vector<int32_t> tcnt(n);
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t i = rows[t];
+      const HRegionHost& G = H.regs[rreg[i]];
+      const int64_t li = i - H.off[rreg[i]];
+      int32_t c = 0;
+      for (int64_t e = G.ptr[li]; e < G.ptr[li + 1]; ++e) c += backward ? G.col[e] > li : G.col[e] < li;
+      tcnt[t] = c;
+    }
+    std::vector<int64_t> tsptr(ns + 1, 0);
+    for (int64_t s = 0; s < ns; ++s) {
+      int32_t w = 0;
+      for (int64_t t = s * 64; t < std::min(n, (s + 1) * 64); ++t) w = std::max(w, tcnt[t]);
+      tsptr[s + 1] = tsptr[s] + 64 * (int64_t)w;
+    }
+    std::vector<int32_t> tcol(tsptr[ns], 0);
+    std::vector<double> tval(tsptr[ns], 0.0);
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t i = rows[t];
+      const HRegionHost& G = H.regs[rreg[i]];
+      const int64_t li = i - H.off[rreg[i]];
+      int64_t at = tsptr[t / 64] + (t & 63);
+      for (int64_t e = G.ptr[li]; e < G.ptr[li + 1]; ++e)
+        if (backward ? G.col[e] > li : G.col[e] < li) {
+          tcol[at] = (int32_t)(H.off[rreg[i]] + G.col[e]);
+          tval[at] = G.val[e];
+          at += 64;
+        }
+    }
+    upload(S.reg, reg, st);
+    upload(S.lv, lv, st);
+    upload(S.rows, rows, st);
+    upload(S.tsptr, tsptr, st);
+    upload(S.tcnt, tcnt, st);
+    upload(S.tcol, tcol, st);
+    upload(S.tval, tval, st);
+  }
   // transfers: aggregate of every row; rows of every coarse row
   const int64_t nc = nc_next;
   std::vector<int64_t> cptr(nc + 1, 0);

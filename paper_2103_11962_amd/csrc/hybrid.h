@@ -35,9 +35,15 @@ struct HLevelDev {
   int64_t ngroups = 0;
   DBuf gptr;   // int64 [ngroups + 1]: copies of each shared composite node, ascending region order
   DBuf gcopy;  // int32
-  // Gauss-Seidel schedules: region k owns levels reg[k] .. reg[k+1]-1, level v owns rows[lv[v] ..
-  // lv[v+1]-1]; a row's lower (forward) or upper (backward) neighbours lie on earlier levels
-  DBuf f_reg, f_lv, f_rows, b_reg, b_lv, b_rows;
+  // Gauss-Seidel schedules, forward and backward: region k owns levels reg[k] .. reg[k+1]-1,
+  // level v owns the schedule positions lv[v] .. lv[v+1]-1, position t updates row rows[t]; a
+  // row's lower (forward) or upper (backward) neighbours lie on earlier levels.  The couplings a
+  // position needs are stored by position in ELL slices of 64 positions: the e-th of position t
+  // at tsptr[t / 64] + 64 e + t % 64, e < tcnt[t], so a wavefront loads them contiguously and
+  // independently of its rows
+  struct Sweep {
+    DBuf reg, lv, rows, tsptr, tcnt, tcol, tval;
+  } fwd, bwd;
   // transfers to the next level: coarse regional row of each row (-1: Dirichlet); the rows of
   // each coarse row (ascending)
   DBuf agg, cptr, crows;

@@ -59,29 +59,24 @@ void launch_hyb_finish(int64_t n, const double* b, const double* y, const double
   LAUNCH_CHECK();
 }
 
-// One block per region; the region's schedule levels in order, a barrier after each.  Row i's
-// lower (upper) couplings are its stored entries with column < i (> i); the diagonal entry and
-// padding (column i) are skipped, the composite diagonal enters through dinv.
-template <bool BACKWARD>
+// One block per region; the region's schedule levels in order, a barrier after each.  Position t
+// of a level updates row rows[t] from its lower (upper) couplings stored at t; their neighbours'
+// corrections were written on earlier levels.  The composite diagonal enters through dinv.
 __global__ __launch_bounds__(kHybGsThreads) void k_hyb_gs(const int* __restrict__ reg, const int* __restrict__ lv,
                                                           const int* __restrict__ rows,
-                                                          const int64_t* __restrict__ sptr,
-                                                          const int* __restrict__ col,
-                                                          const double* __restrict__ val,
+                                                          const int64_t* __restrict__ tsptr,
+                                                          const int* __restrict__ tcnt, const int* __restrict__ tcol,
+                                                          const double* __restrict__ tval,
                                                           const double* __restrict__ dinv,
                                                           const double* __restrict__ r, double* d, double omega) {
   const int k = blockIdx.x;
   for (int v = reg[k]; v < reg[k + 1]; ++v) {
     for (int t = lv[v] + (int)threadIdx.x; t < lv[v + 1]; t += kHybGsThreads) {
       const int i = rows[t];
-      int64_t base;
-      int w;
-      ell_row(sptr, i, base, w);
+      const int c = tcnt[t];
+      const int64_t base = tsptr[t >> 6] + (t & 63);
       double acc = r[i];
-      for (int e = 0; e < w; ++e) {
-        const int j = col[base + 64 * e];
-        if (BACKWARD ? j > i : j < i) acc -= val[base + 64 * e] * d[j];
-      }
+      for (int e = 0; e < c; ++e) acc -= tval[base + 64 * e] * d[tcol[base + 64 * e]];
       d[i] = omega * acc * dinv[i];
     }
     __syncthreads();
@@ -90,14 +85,10 @@ __global__ __launch_bounds__(kHybGsThreads) void k_hyb_gs(const int* __restrict_
 
 void launch_hyb_gs(const HLevelDev& L, const double* r, double* d, double omega, bool backward, hipStream_t st) {
   if (L.n == 0) return;
-  if (backward)
-    hipLaunchKernelGGL(k_hyb_gs<true>, dim3(L.nreg), dim3(kHybGsThreads), 0, st, L.b_reg.as<int>(),
-                       L.b_lv.as<int>(), L.b_rows.as<int>(), L.sptr.as<int64_t>(), L.col.as<int>(),
-                       L.val.as<double>(), L.dinv.as<double>(), r, d, omega);
-  else
-    hipLaunchKernelGGL(k_hyb_gs<false>, dim3(L.nreg), dim3(kHybGsThreads), 0, st, L.f_reg.as<int>(),
-                       L.f_lv.as<int>(), L.f_rows.as<int>(), L.sptr.as<int64_t>(), L.col.as<int>(),
-                       L.val.as<double>(), L.dinv.as<double>(), r, d, omega);
+  const HLevelDev::Sweep& S = backward ? L.bwd : L.fwd;
+  hipLaunchKernelGGL(k_hyb_gs, dim3(L.nreg), dim3(kHybGsThreads), 0, st, S.reg.as<int>(), S.lv.as<int>(),
+                     S.rows.as<int>(), S.tsptr.as<int64_t>(), S.tcnt.as<int>(), S.tcol.as<int>(),
+                     S.tval.as<double>(), L.dinv.as<double>(), r, d, omega);
   LAUNCH_CHECK();
 }
 

@@ -175,3 +175,43 @@ def test_hybrid_option_errors(hip_device):
         h.hybrid_level_info(0)
     assert e.value.status == "RMG_ERR_NOT_SETUP"
     h.close()
+
+
+@pytest.mark.parametrize("case", ["2d_centre", "2d_unstructured", "uneven_3d"])
+def test_hybrid_other_layouts(hip_device, case):
+    """2D five-point problems in 3x3 regions (one or all unstructured) and uneven 3D regions with
+    unstructured ones: aggregates bit for bit, and one symmetric-GS W-cycle against the oracle."""
+    import torch
+
+    from oracle import assembly, hybrid
+    from oracle.regions import Layout
+
+    print(f"[hybrid] layout {case}", flush=True)
+    if case.startswith("2d"):
+        o, e = synth.tensor_layout([[10] * 3, [10] * 3])
+        w = synth.Workload(case, 2, 1, o, e, 15, 3, 2, "fd5", seed=0)
+        kinds = np.zeros(9, dtype=np.int32)
+        kinds[[4] if case == "2d_centre" else list(range(9))] = 1
+        lay = Layout(2, o, e, 15)
+        A = assembly.composite_fd5(lay)
+    else:
+        o, e = synth.tensor_layout([[10, 19], [19], [19, 10]])
+        w = synth.Workload(case, 3, 1, o, e, 63, 3, 2, "fd7", seed=0)
+        kinds = np.array([1, 0, 0, 1], dtype=np.int32)
+        lay = Layout(3, o, e, 63)
+        A = assembly.composite_fd7(lay)
+    opt = hybrid.HOptions(nlevels=3, degree=2, smoother="symgs", omega=1.0, gamma=2)
+    lv = hybrid.setup(hybrid.finest_level(lay, assembly.split_composite(lay, A)), kinds, opt)
+    b = synth.rhs(w).reshape(-1)
+    ref = lv[0].to_composite_owner(hybrid.cycle(lv, lv[0].to_regional(b), opt))
+    h = harness.gpu_problem(w, setup=False)
+    h.set_region_kinds(kinds)
+    h.setup_hierarchy(nlevels=3, cheb_degree=2, smoother=4, jacobi_omega=1.0, hybrid=1, cycle_gamma=2)
+    for l in range(2):
+        coffs = np.cumsum([0] + [R.comp.size for R in lv[l + 1].regions])
+        agg = np.concatenate([np.where(a >= 0, a + coffs[k], -1) for k, a in enumerate(lv[l].agg)])
+        np.testing.assert_array_equal(h.hybrid_aggregates(l), agg)
+    z = torch.empty(b.size, dtype=torch.float64, device="cuda:0")
+    h.apply_vcycle(harness.to_dev(b), z)
+    assert rel(z.cpu().numpy(), ref) < 1e-12
+    h.close()
