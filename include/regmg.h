@@ -139,11 +139,25 @@ typedef struct {
   double* history;       /* caller-owned host array or NULL: relres per iteration, [0] = 1 */
   int history_cap;       /* capacity of history */
   int history_len;       /* entries written */
+  double setup_ms;       /* host wall time of the last rmg_setup_hierarchy (stream synchronised) */
 } rmg_solve_info;
 
+/* Device memory provider for a handle (optional).  alloc(bytes, ctx) returns at least `bytes` of
+   device memory on the handle's device usable on its stream, or NULL; free(ptr, ctx) takes back a
+   pointer alloc returned.  Both are called only from inside this library's entry points for that
+   handle (never from a kernel or a stream callback); every buffer is returned to the provider that
+   gave it.  The caller keeps the functions and ctx valid until rmg_destroy of the handle returns. */
+typedef struct rmg_allocator {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} rmg_allocator;
+
 /* Create a handle on HIP device `device`; all work goes to `hip_stream`
- * (a hipStream_t, or NULL for the default stream).  *out owned by the library. */
-rmg_status rmg_create(rmg_handle** out, int device, void* hip_stream);
+ * (a hipStream_t, or NULL for the default stream).  *out owned by the library.  `alloc` (may be
+ * NULL: hipMalloc/hipFree) provides every device buffer the handle's entry points allocate; the
+ * struct is copied. */
+rmg_status rmg_create(rmg_handle** out, int device, void* hip_stream, const rmg_allocator* alloc);
 
 /* Release all device memory of the handle.  NULL is accepted. */
 rmg_status rmg_destroy(rmg_handle* h);

@@ -1,5 +1,6 @@
 // C ABI of the regional multigrid library: validation, error mapping, entry points.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -114,9 +115,14 @@ rmg_handle::~rmg_handle() {
   if (host_scalars) (void)hipHostFree(host_scalars);
 }
 
+void rmg::bind_handle(rmg_handle* h) {
+  RMG_HIP(hipSetDevice(h->device));
+  current_allocator() = h->alloc;
+}
+
 static void use_device(rmg_handle* h) {
   RMG_REQUIRE(h != nullptr, RMG_ERR_ARG, "null handle");
-  RMG_HIP(hipSetDevice(h->device));
+  bind_handle(h);
 }
 
 static Level& level_of(rmg_handle* h, int level) {
@@ -152,18 +158,20 @@ void rmg_options_default(rmg_options* o) {
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
 
-rmg_status rmg_create(rmg_handle** out, int device, void* stream) {
+rmg_status rmg_create(rmg_handle** out, int device, void* stream, const rmg_allocator* alloc) {
   API_BEGIN
   RMG_REQUIRE(out != nullptr, RMG_ERR_ARG, "null output pointer");
+  RMG_REQUIRE(!alloc || (alloc->alloc && alloc->free), RMG_ERR_ARG, "allocator needs both alloc and free");
   int ndev = 0;
   RMG_HIP(hipGetDeviceCount(&ndev));
   RMG_REQUIRE(device >= 0 && device < ndev, RMG_ERR_ARG, "no HIP device " + std::to_string(device));
-  RMG_HIP(hipSetDevice(device));
   rmg_handle* h = new rmg_handle();
   h->device = device;
   h->stream = static_cast<hipStream_t>(stream);
+  if (alloc) h->alloc = DevAlloc{alloc->alloc, alloc->free, alloc->ctx};
   rmg_options_default(&h->opt);
   try {
+    bind_handle(h);
     h->scalars.alloc(sizeof(double) * kNumSlots);
     RMG_HIP(hipMemset(h->scalars.p, 0, sizeof(double) * kNumSlots));
     RMG_HIP(hipHostMalloc((void**)&h->host_scalars, sizeof(double) * kNumSlots, hipHostMallocDefault));
@@ -483,7 +491,10 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   h->opt.autotune_cache = nullptr;  // the caller's string is borrowed for this call only
   h->have_hierarchy = false;
   h->drop_graphs();
+  const auto t0 = std::chrono::steady_clock::now();
   setup_hierarchy(h);
+  RMG_HIP(hipStreamSynchronize(h->stream));
+  h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   h->have_hierarchy = true;
   API_END
 }

@@ -34,8 +34,25 @@ void set_last_error(const std::string& msg);
     if (!(cond)) ::rmg::fail(code, msg); \
   } while (0)
 
+// Device memory provider of the entry point running on this thread (empty: hipMalloc/hipFree).
+struct DevAlloc {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+DevAlloc& current_allocator();
+// Restores the thread's provider when an entry point returns; bind_handle(h) selects h's device
+// and provider for the rest of the entry point.
+struct AllocatorScope {
+  DevAlloc saved;
+  AllocatorScope() : saved(current_allocator()) { current_allocator() = DevAlloc(); }
+  ~AllocatorScope() { current_allocator() = saved; }
+};
+
 // Body of a C entry point: library errors become a status and the thread's last error.
-#define API_BEGIN try {
+#define API_BEGIN             \
+  try {                       \
+    rmg::AllocatorScope alloc_scope_;
 #define API_END                                   \
   }                                               \
   catch (const rmg::Error& e) {                   \
@@ -100,12 +117,14 @@ struct LevelView {
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  DevAlloc from;  // the provider p came from
   void alloc(size_t nbytes);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
   void swap(DBuf& o) {
     std::swap(p, o.p);
     std::swap(bytes, o.bytes);
+    std::swap(from, o.from);
   }
   ~DBuf() { release(); }
   DBuf() = default;
@@ -226,11 +245,15 @@ struct rmg_handle {
   // structured/unstructured hybrid: region kinds (0 structured, 1 unstructured) and the hierarchy
   std::vector<int32_t> region_kind;
   rmg::Hybrid* hy = nullptr;
+  rmg::DevAlloc alloc;     // device memory provider (empty: hipMalloc)
+  double setup_ms = 0.0;   // wall time of the last rmg_setup_hierarchy
   ~rmg_handle();
 };
 
 namespace rmg {
 
+// api.cpp: select h's device and memory provider for the rest of the current entry point.
+void bind_handle(rmg_handle* h);
 // api.cpp: Q1 Laplace element matrix of a cube of side h (2x2x2 Gauss-Legendre), corners ax + 2 ay + 4 az.
 void q1_laplace_element(double h, double K[64]);
 

@@ -237,7 +237,7 @@ extern "C" {
 rmg_status rmg_set_prolongator_weights(rmg_handle* h, const double* w, int on_device) {
   API_BEGIN
   RMG_REQUIRE(h != nullptr, RMG_ERR_ARG, "null handle");
-  RMG_HIP(hipSetDevice(h->device));
+  bind_handle(h);
   if (!w) {
     h->user_pw.release();
     h->pmode = RMG_P_GEOMETRIC;
@@ -282,7 +282,7 @@ rmg_status rmg_prolongator_info(rmg_handle* h, int* kind, int* flags, double* rh
 rmg_status rmg_get_prolongator_weights(rmg_handle* h, double* host_out) {
   API_BEGIN
   RMG_REQUIRE(h != nullptr && host_out != nullptr, RMG_ERR_ARG, "null handle or output");
-  RMG_HIP(hipSetDevice(h->device));
+  bind_handle(h);
   RMG_REQUIRE(h->have_hierarchy, RMG_ERR_NOT_SETUP, "hierarchy not set up");
   const Level& L = *h->levels[0];
   RMG_REQUIRE(L.pw.p != nullptr, RMG_ERR_ARG, "the hierarchy interpolates geometrically");
@@ -294,7 +294,7 @@ rmg_status rmg_get_prolongator_weights(rmg_handle* h, double* host_out) {
 rmg_status rmg_convergence_factor(rmg_handle* h, int cycles, double* rho) {
   API_BEGIN
   RMG_REQUIRE(h != nullptr && rho != nullptr, RMG_ERR_ARG, "null handle or output");
-  RMG_HIP(hipSetDevice(h->device));
+  bind_handle(h);
   RMG_REQUIRE(h->have_hierarchy, RMG_ERR_NOT_SETUP, "hierarchy not set up");
   RMG_REQUIRE(cycles >= 1 && cycles <= 10000, RMG_ERR_ARG, "cycles must be in [1, 10000]");
   *rho = convergence_factor(h, cycles);

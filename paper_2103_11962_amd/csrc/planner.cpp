@@ -9,22 +9,39 @@
 
 namespace rmg {
 
+DevAlloc& current_allocator() {
+  thread_local DevAlloc a;
+  return a;
+}
+
 void DBuf::alloc(size_t nbytes) {
   release();
   if (nbytes == 0) return;
-  hipError_t e = hipMalloc(&p, nbytes);
-  if (e != hipSuccess) {
-    p = nullptr;
-    fail(e == hipErrorOutOfMemory ? RMG_ERR_OOM : RMG_ERR_DEVICE,
-         "hipMalloc of " + std::to_string(nbytes) + " bytes failed: " + hipGetErrorString(e));
+  const DevAlloc& a = current_allocator();
+  if (a.alloc) {
+    p = a.alloc(nbytes, a.ctx);
+    if (!p) fail(RMG_ERR_OOM, "device memory provider returned no memory for " + std::to_string(nbytes) + " bytes");
+    from = a;
+  } else {
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+      p = nullptr;
+      fail(e == hipErrorOutOfMemory ? RMG_ERR_OOM : RMG_ERR_DEVICE,
+           "hipMalloc of " + std::to_string(nbytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    from = DevAlloc();
   }
   bytes = nbytes;
 }
 
 void DBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (from.free) from.free(p, from.ctx);
+    else (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
+  from = DevAlloc();
 }
 
 LevelView Level::view() const {

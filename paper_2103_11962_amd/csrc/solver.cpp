@@ -562,6 +562,7 @@ void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit,
     info->true_relres = rel;  // the residual is recomputed from x every cycle
     info->solve_ms = ms;
     info->history_len = hist_len;
+    info->setup_ms = h->setup_ms;
   }
 }
 
@@ -824,6 +825,7 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
     info->true_relres = bnorm > 0.0 ? std::sqrt(h->host_scalars[kTmp]) / bnorm : 0.0;
     info->solve_ms = ms;
     info->history_len = hist_len;
+    info->setup_ms = h->setup_ms;
   }
 }
 

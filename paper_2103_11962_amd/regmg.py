@@ -82,7 +82,32 @@ class SolveInfo(ctypes.Structure):
         ("history", ctypes.POINTER(ctypes.c_double)),
         ("history_cap", ctypes.c_int),
         ("history_len", ctypes.c_int),
+        ("setup_ms", ctypes.c_double),
     ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+def _torch_allocator(device, stream):
+    """rmg_allocator backed by PyTorch's caching allocator on `stream` of `device`."""
+    import torch
+
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device, stream=stream)
+        except RuntimeError:
+            return None
+
+    def free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return Allocator(ALLOC_FN(alloc), FREE_FN(free), None)
 
 
 class RmgError(RuntimeError):
@@ -109,7 +134,7 @@ def load():
     H = ctypes.c_void_p
     sig = {
         "rmg_options_default": (None, [ctypes.POINTER(Options)]),
-        "rmg_create": (I, [ctypes.POINTER(H), I, P]),
+        "rmg_create": (I, [ctypes.POINTER(H), I, P, ctypes.POINTER(Allocator)]),
         "rmg_destroy": (I, [H]),
         "rmg_last_error": (ctypes.c_char_p, []),
         "rmg_build_regions": (I, [H, I, I, I, P, P, ctypes.c_uint32]),
@@ -205,15 +230,20 @@ def default_options(**kw) -> Options:
 class Handle:
     """One solver instance on one HIP device and stream."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = False):
+        """torch_allocator: take every device buffer of the handle from PyTorch's caching
+        allocator (on the handle's stream) instead of hipMalloc."""
         import torch
 
         lib = load()
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self._stream = stream
+        # the callbacks must outlive every buffer they provided: kept on the handle until close()
+        self._alloc = _torch_allocator(device, stream) if torch_allocator else None
         h = ctypes.c_void_p()
-        _check(lib.rmg_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)))
+        _check(lib.rmg_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream),
+                              ctypes.byref(self._alloc) if self._alloc is not None else None))
         self._h = h
         self.device = device
 
@@ -299,6 +329,7 @@ class Handle:
         out = {
             "status": STATUS.get(code, code), "iterations": info.iterations, "converged": bool(info.converged),
             "relres": info.relres, "true_relres": info.true_relres, "solve_ms": info.solve_ms,
+            "setup_ms": info.setup_ms,
             "history": [hist[i] for i in range(min(info.history_len, history_cap))],
         }
         return out

@@ -12,13 +12,13 @@ import numpy as np
 import synth
 
 
-def gpu_problem(w, device=0, setup=True, **opts):
+def gpu_problem(w, device=0, setup=True, torch_allocator=False, **opts):
     """Handle with regions, finest operator and (optionally) the hierarchy of workload ``w``."""
     import torch
 
     from paper_2103_11962_amd import regmg
 
-    h = regmg.Handle(device)
+    h = regmg.Handle(device, torch_allocator=torch_allocator)
     h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
     if w.pde == "fd5":
         h.set_composite_stencil(5, synth.fd5_composite_stencil(w))

@@ -41,7 +41,7 @@ def test_create_without_device_fails_cleanly():
 
     lib = regmg.load()
     h = ctypes.c_void_p()
-    code = lib.rmg_create(ctypes.byref(h), 0, None)
+    code = lib.rmg_create(ctypes.byref(h), 0, None, None)
     assert code in (1, 4)  # no device: argument or device error, never a crash
     assert lib.rmg_last_error()
 
