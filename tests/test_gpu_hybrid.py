@@ -177,7 +177,7 @@ def test_hybrid_option_errors(hip_device):
     h.close()
 
 
-@pytest.mark.parametrize("case", ["2d_centre", "2d_unstructured", "uneven_3d"])
+@pytest.mark.parametrize("case", ["2d_centre", "2d_unstructured", "uneven_3d", "one_region"])
 def test_hybrid_other_layouts(hip_device, case):
     """2D five-point problems in 3x3 regions (one or all unstructured) and uneven 3D regions with
     unstructured ones: aggregates bit for bit, and one symmetric-GS W-cycle against the oracle."""
@@ -194,6 +194,12 @@ def test_hybrid_other_layouts(hip_device, case):
         kinds[[4] if case == "2d_centre" else list(range(9))] = 1
         lay = Layout(2, o, e, 15)
         A = assembly.composite_fd5(lay)
+    elif case == "one_region":  # no interfaces: stage I is empty, every node aggregated by stages II-IV
+        o, e = synth.tensor_layout([[28]] * 3)
+        w = synth.Workload(case, 3, 1, o, e, 63, 3, 2, "fd7", seed=0)
+        kinds = np.array([1], dtype=np.int32)
+        lay = Layout(3, o, e, 63)
+        A = assembly.composite_fd7(lay)
     else:
         o, e = synth.tensor_layout([[10, 19], [19], [19, 10]])
         w = synth.Workload(case, 3, 1, o, e, 63, 3, 2, "fd7", seed=0)
