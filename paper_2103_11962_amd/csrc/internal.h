@@ -165,6 +165,13 @@ struct Level {
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
   DBuf pw;        // stored interpolation weights to the next level, double [n][8] (null: geometric)
   DBuf rw;        // with pw: the same weights per coarse node (125 taps, wave-tiled) for the restriction
+  // region-local Gauss-Seidel (smoothers 2-4): the level's stencils and D~^-1 copied into the
+  // sweep's hyperplane order ("slots"), so that a wavefront's loads are contiguous
+  DBuf gs_rplane;  // int32 [nreg + 1]: first plane of each region in gs_pbase
+  DBuf gs_pbase;   // int64: first slot of every plane of every region, then one past the last
+  DBuf gs_coef;    // double, wave-tiled by slot: ncoef() values per slot
+  DBuf gs_dinv;    // double [slots * ndof]
+  DBuf gs_d;       // double [slots * ndof]: the sweep's corrections by slot
   double lambda = 0.0;
   std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step: direction and residual factors
   // work vectors (regional): b (rhs), u / u2 (ping-pong), d (Chebyshev direction), r (residual)

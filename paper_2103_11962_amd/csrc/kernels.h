@@ -40,6 +40,8 @@ int64_t launch_stencil_op(const Level& L, const StencilArgs& a, hipStream_t st);
 void launch_interface_sum(const Level& L, const double* v, double* w, hipStream_t st);
 // Region-local Gauss-Seidel sweep (kernels_gs.hip): delta = (D~/omega + L_k)^-1 r per region k
 // (upper triangle, reverse order, when backward); every copy of an interface dof := their average.
+// launch_gs_prepare copies the level's stencils and D~^-1 into the sweep's slot order (setup).
+void launch_gs_prepare(Level& L, hipStream_t st);
 void launch_gs_sweep(const Level& L, const double* r, double* delta, double omega, bool backward, hipStream_t st);
 void launch_interface_avg(const Level& L, double* w, hipStream_t st);
 // The same on explicit interface groups: every copy := sum (avg = false) or average of the copies.

@@ -12,49 +12,115 @@
 // 9- and 27-point stencils, WY = 1 for the five-point one).  The nodes of one hyperplane are
 // independent, so one block per region walks the hyperplanes in order with a barrier between
 // them and updates each plane's nodes in parallel: the same arithmetic as the sequential sweep.
-// The neighbours' corrections are read back from global memory written by the same block before
-// the barrier (all waves of a block share the CU's vector L1, and the barrier orders the accesses).
+//
+// Within a plane no two nodes are neighbours in x, so reading the regional arrays would give every
+// lane its own cache line.  The sweep therefore works in "slot" order: plane t of a region owns
+// slots pbase[t] + q, q = (z - z0(t)) * ycand + (y - ylo(t, z)) enumerating its (z, y) candidates
+// (x follows from t).  At setup the level's stencils and D~^-1 are copied into slot order
+// (k_gs_fill); a sweep reads them and the neighbours' corrections by slot, which for consecutive
+// lanes are consecutive.  Only r and the regional output are touched once per node in regional
+// order.  The corrections are read back from the slot array written by the same block before the
+// barrier (all waves of a block share the CU's vector L1, and the barrier orders the accesses).
 //
 // After the sweep the copies of an interface node hold different corrections (each region saw only
 // its own updates); k_group_reduce<AVG> replaces them by their average, so the regional vector
 // stays the regional form of a composite one.
+#include <vector>
+
 #include "device_common.h"
 
 namespace rmg {
 
 constexpr int kGsThreads = 1024;
 
+// Hyperplanes x + wy y + 4 z = t of a region box and the slots of their nodes.
+struct GsPlanes {
+  static constexpr int WZ = 4;
+  int ex, ey, ez, wy, ycand, tmax;
+  __host__ __device__ GsPlanes(int ex_, int ey_, int ez_, int wy_) : ex(ex_), ey(ey_), ez(ez_), wy(wy_) {
+    const int c = (ex - 1) / wy + 1;  // y candidates of one (t, z): y in [ylo, ylo + c)
+    ycand = ey < c ? ey : c;
+    tmax = (ex - 1) + wy * (ey - 1) + WZ * (ez - 1);
+  }
+  __host__ __device__ int z0(int t) const {
+    const int n = t - (ex - 1) - wy * (ey - 1);
+    return n <= 0 ? 0 : (n + WZ - 1) / WZ;
+  }
+  __host__ __device__ int z1(int t) const {
+    const int m = t / WZ;
+    return m < ez - 1 ? m : ez - 1;
+  }
+  __host__ __device__ int count(int t) const {
+    const int a = z0(t), b = z1(t);
+    return b >= a ? (b - a + 1) * ycand : 0;
+  }
+  __host__ __device__ int ylo(int t, int z) const {
+    const int n = t - WZ * z - (ex - 1);
+    return n <= 0 ? 0 : (n + wy - 1) / wy;
+  }
+  // node of candidate q of plane t; false if the candidate lies outside the box
+  __host__ __device__ bool node(int t, int q, int& x, int& y, int& z) const {
+    z = z0(t) + q / ycand;
+    y = ylo(t, z) + q % ycand;
+    x = t - WZ * z - wy * y;
+    return y < ey && x >= 0 && x < ex;
+  }
+  __host__ __device__ int slot(int t, int y, int z) const { return (z - z0(t)) * ycand + (y - ylo(t, z)); }
+};
+
+template <int NPTS>
+constexpr int gs_wy() {
+  return NPTS == 5 ? 1 : 2;
+}
+
+// Setup: the level's stencil blocks and D~^-1 in slot order (one block per region).
+template <int NPTS, int NDOF>
+__global__ __launch_bounds__(kGsThreads) void k_gs_fill(LevelView L, const int* __restrict__ rplane,
+                                                        const int64_t* __restrict__ pbase,
+                                                        const double* __restrict__ coef,
+                                                        const double* __restrict__ dinv, double* __restrict__ cs,
+                                                        double* __restrict__ ds_inv) {
+  constexpr int NC = NPTS * NDOF * NDOF;
+  const RegionGeo R = L.regs[blockIdx.x];
+  const GsPlanes P(R.ex, R.ey, R.ez, gs_wy<NPTS>());
+  const int64_t* __restrict__ pb = pbase + rplane[blockIdx.x];
+  for (int t = 0; t <= P.tmax; ++t) {
+    const int cnt = P.count(t);
+    for (int q = threadIdx.x; q < cnt; q += kGsThreads) {
+      int x, y, z;
+      if (!P.node(t, q, x, y, z)) continue;
+      const int64_t gi = R.off + x + (int64_t)R.ex * (y + (int64_t)R.ey * z);
+      const int64_t p = pb[t] + q;
+      for (int c = 0; c < NC; ++c) cs[coef_index(p, c, NC)] = coef[coef_index(gi, c, NC)];
+#pragma unroll
+      for (int a = 0; a < NDOF; ++a) ds_inv[p * NDOF + a] = dinv[gi * NDOF + a];
+    }
+  }
+}
+
 template <int NPTS, int NDOF, bool BACKWARD>
-__global__ __launch_bounds__(kGsThreads) void k_gs_sweep(LevelView L, const double* __restrict__ coef,
-                                                         const double* __restrict__ dinv,
-                                                         const double* __restrict__ r, double* delta,
-                                                         double omega) {
+__global__ __launch_bounds__(kGsThreads) void k_gs_sweep(LevelView L, const int* __restrict__ rplane,
+                                                         const int64_t* __restrict__ pbase,
+                                                         const double* __restrict__ cs,
+                                                         const double* __restrict__ ds_inv,
+                                                         const double* __restrict__ r, double* __restrict__ delta,
+                                                         double* ds, double omega) {
   constexpr int NB = NDOF * NDOF;
   constexpr int NC = NPTS * NB;
   constexpr int CEN = center_index<NPTS>();
-  constexpr int WY = NPTS == 5 ? 1 : 2;
-  constexpr int WZ = 4;
+  constexpr int WY = gs_wy<NPTS>();
   const RegionGeo R = L.regs[blockIdx.x];
-  const int tmax = (R.ex - 1) + WY * (R.ey - 1) + WZ * (R.ez - 1);
-  // for a fixed z, the nodes of plane t have y in [ceil((t - WZ z - ex + 1) / WY), (t - WZ z) / WY]
-  const int ycand = min(R.ey, (R.ex - 1) / WY + 1);
-  const int sy = R.ex, sz = R.ex * R.ey;
-  for (int step = 0; step <= tmax; ++step) {
-    const int t = BACKWARD ? tmax - step : step;
-    const int zlo_num = t - (R.ex - 1) - WY * (R.ey - 1);
-    const int z0 = zlo_num <= 0 ? 0 : (zlo_num + WZ - 1) / WZ;
-    const int z1 = min(R.ez - 1, t / WZ);
-    const int cnt = z1 >= z0 ? (z1 - z0 + 1) * ycand : 0;
+  const GsPlanes P(R.ex, R.ey, R.ez, WY);
+  const int64_t* __restrict__ pb = pbase + rplane[blockIdx.x];
+  for (int step = 0; step <= P.tmax; ++step) {
+    const int t = BACKWARD ? P.tmax - step : step;
+    const int cnt = P.count(t);
     for (int q = threadIdx.x; q < cnt; q += kGsThreads) {
-      const int z = z0 + q / ycand;
-      const int rem = t - WZ * z;  // x + WY y, >= 0
-      const int ylo_num = rem - (R.ex - 1);
-      const int y = (ylo_num <= 0 ? 0 : (ylo_num + WY - 1) / WY) + q % ycand;
-      const int x = rem - WY * y;
-      if (y >= R.ey || x < 0 || x >= R.ex) continue;
-      const int li = x + sy * y + sz * z;
-      const int64_t gi = R.off + li;
-      const double* __restrict__ cf = coef + coef_index(gi, 0, NC);
+      int x, y, z;
+      if (!P.node(t, q, x, y, z)) continue;
+      const int64_t gi = R.off + x + (int64_t)R.ex * (y + (int64_t)R.ey * z);
+      const int64_t p = pb[t] + q;
+      const double* __restrict__ c = cs + coef_index(p, 0, NC);
       double dl[NDOF];
 #pragma unroll
       for (int aa = 0; aa < NDOF; ++aa) {
@@ -66,40 +132,87 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_sweep(LevelView L, const doub
           stencil_offset<NPTS>(s, dx, dy, dz);
           if ((unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
               (unsigned)(z + dz) < (unsigned)R.ez) {
-            const int64_t nb = R.off + li + dx + dy * sy + dz * sz;
+            const int tn = t + dx + WY * dy + GsPlanes::WZ * dz;
+            const int64_t pn = pb[tn] + P.slot(tn, y + dy, z + dz);
 #pragma unroll
-            for (int b = 0; b < NDOF; ++b) acc -= cf[(s * NB + a * NDOF + b) * kTile] * delta[nb * NDOF + b];
+            for (int b = 0; b < NDOF; ++b) acc -= c[(s * NB + a * NDOF + b) * kTile] * ds[pn * NDOF + b];
           }
         }
         // dofs of the same node visited before this one
 #pragma unroll
         for (int b = 0; b < NDOF; ++b)
-          if (BACKWARD ? b > a : b < a) acc -= cf[(CEN * NB + a * NDOF + b) * kTile] * dl[b];
-        dl[a] = omega * acc * dinv[gi * NDOF + a];
+          if (BACKWARD ? b > a : b < a) acc -= c[(CEN * NB + a * NDOF + b) * kTile] * dl[b];
+        dl[a] = omega * acc * ds_inv[p * NDOF + a];
       }
 #pragma unroll
-      for (int a = 0; a < NDOF; ++a) delta[gi * NDOF + a] = dl[a];
+      for (int a = 0; a < NDOF; ++a) {
+        ds[p * NDOF + a] = dl[a];
+        delta[gi * NDOF + a] = dl[a];
+      }
     }
     __syncthreads();
   }
 }
 
 template <int NPTS, int NDOF>
+static void gs_fill_launch(const Level& L, hipStream_t st) {
+  hipLaunchKernelGGL((k_gs_fill<NPTS, NDOF>), dim3(L.nreg), dim3(kGsThreads), 0, st, L.view(), L.gs_rplane.as<int>(),
+                     L.gs_pbase.as<int64_t>(), L.coef.as<double>(), L.dinv.as<double>(), L.gs_coef.as<double>(),
+                     L.gs_dinv.as<double>());
+  LAUNCH_CHECK();
+}
+
+void launch_gs_prepare(Level& L, hipStream_t st) {
+  RMG_REQUIRE(L.ndof == 1 || L.npts == 27, RMG_ERR_ARG, "internal: Gauss-Seidel blocks need 27-point levels");
+  const int wy = L.npts == 5 ? 1 : 2;
+  std::vector<int32_t> rplane(L.nreg + 1, 0);
+  std::vector<int64_t> pbase;
+  int64_t slots = 0;
+  for (int k = 0; k < L.nreg; ++k) {
+    const RegionGeo& R = L.regs[k];
+    const GsPlanes P(R.ex, R.ey, R.ez, wy);
+    rplane[k] = (int32_t)pbase.size();
+    for (int t = 0; t <= P.tmax; ++t) {
+      pbase.push_back(slots);
+      slots += P.count(t);
+    }
+  }
+  rplane[L.nreg] = (int32_t)pbase.size();
+  pbase.push_back(slots);
+  L.gs_rplane.alloc(sizeof(int32_t) * rplane.size());
+  L.gs_pbase.alloc(sizeof(int64_t) * pbase.size());
+  RMG_HIP(hipMemcpyAsync(L.gs_rplane.p, rplane.data(), sizeof(int32_t) * rplane.size(), hipMemcpyHostToDevice, st));
+  RMG_HIP(hipMemcpyAsync(L.gs_pbase.p, pbase.data(), sizeof(int64_t) * pbase.size(), hipMemcpyHostToDevice, st));
+  L.gs_coef.alloc(sizeof(double) * coef_elems(slots, L.ncoef()));
+  L.gs_dinv.alloc(sizeof(double) * (size_t)slots * L.ndof);
+  L.gs_d.alloc(sizeof(double) * (size_t)slots * L.ndof);
+  if (L.npts == 27 && L.ndof == 3) gs_fill_launch<27, 3>(L, st);
+  else if (L.npts == 27) gs_fill_launch<27, 1>(L, st);
+  else if (L.npts == 9) gs_fill_launch<9, 1>(L, st);
+  else gs_fill_launch<5, 1>(L, st);
+  RMG_HIP(hipStreamSynchronize(st));  // the host tables above are released on return
+}
+
+template <int NPTS, int NDOF>
 static void gs_launch(const Level& L, const double* r, double* delta, double omega, bool backward, hipStream_t st) {
   const LevelView V = L.view();
-  const double* cf = L.coef.as<double>();
-  const double* di = L.dinv.as<double>();
+  const int* rp = L.gs_rplane.as<int>();
+  const int64_t* pb = L.gs_pbase.as<int64_t>();
+  const double* cs = L.gs_coef.as<double>();
+  const double* di = L.gs_dinv.as<double>();
+  double* ds = L.gs_d.as<double>();
   if (backward)
-    hipLaunchKernelGGL((k_gs_sweep<NPTS, NDOF, true>), dim3(L.nreg), dim3(kGsThreads), 0, st, V, cf, di, r, delta,
-                       omega);
+    hipLaunchKernelGGL((k_gs_sweep<NPTS, NDOF, true>), dim3(L.nreg), dim3(kGsThreads), 0, st, V, rp, pb, cs, di, r,
+                       delta, ds, omega);
   else
-    hipLaunchKernelGGL((k_gs_sweep<NPTS, NDOF, false>), dim3(L.nreg), dim3(kGsThreads), 0, st, V, cf, di, r, delta,
-                       omega);
+    hipLaunchKernelGGL((k_gs_sweep<NPTS, NDOF, false>), dim3(L.nreg), dim3(kGsThreads), 0, st, V, rp, pb, cs, di, r,
+                       delta, ds, omega);
   LAUNCH_CHECK();
 }
 
 void launch_gs_sweep(const Level& L, const double* r, double* delta, double omega, bool backward, hipStream_t st) {
   if (L.n == 0) return;
+  RMG_REQUIRE(L.gs_pbase.p != nullptr, RMG_ERR_NOT_SETUP, "internal: Gauss-Seidel slot tables missing");
   if (L.npts == 27 && L.ndof == 3) gs_launch<27, 3>(L, r, delta, omega, backward, st);
   else if (L.npts == 27) gs_launch<27, 1>(L, r, delta, omega, backward, st);
   else if (L.npts == 9) gs_launch<9, 1>(L, r, delta, omega, backward, st);

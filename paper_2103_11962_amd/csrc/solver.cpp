@@ -282,6 +282,14 @@ static int build_levels(rmg_handle* h, bool stored) {
     RMG_REQUIRE(std::isfinite(L.lambda) && L.lambda > 0.0, RMG_ERR_NUMERIC,
                 "power method failed on level " + std::to_string(l));
     chebyshev_coefficients(o, L);
+    if (o.smoother >= 2) launch_gs_prepare(L, st);
+    else {
+      L.gs_rplane.release();
+      L.gs_pbase.release();
+      L.gs_coef.release();
+      L.gs_dinv.release();
+      L.gs_d.release();
+    }
     // next level: geometry, interpolation weights, then the per-region Galerkin product (FP64)
     Level* C = make_coarse_level(L);
     h->levels.push_back(C);
