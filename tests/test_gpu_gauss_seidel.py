@@ -130,3 +130,27 @@ def test_gs_option_errors(hip_device):
             h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree, **bad)
         assert e.value.status == "RMG_ERR_ARG"
     h.close()
+
+
+def test_gs_graph_replay_matches_eager(hip_device):
+    """CG half-iterations captured as HIP graphs with the symmetric Gauss-Seidel V-cycle inside:
+    every replay gives the eager result bit for bit, with eager work between replays."""
+    import torch
+
+    w = synth.workload("c2_small")
+    b = harness.to_dev(synth.rhs(w))
+    he = harness.gpu_problem(w, smoother=4, jacobi_omega=1.0)
+    xe = torch.zeros_like(b)
+    oe = he.solve(b, xe, rtol=1e-8, maxit=100)
+    hg = harness.gpu_problem(w, smoother=4, jacobi_omega=1.0, use_graph=1)
+    for rep in range(3):
+        xg = torch.zeros_like(b)
+        og = hg.solve(b, xg, rtol=1e-8, maxit=100)
+        assert og["iterations"] == oe["iterations"] and og["history"] == oe["history"], rep
+        assert torch.equal(xg, xe), rep
+        z = torch.empty_like(b)
+        hg.apply_vcycle(b, z)
+        torch.cuda.synchronize()
+        assert torch.isfinite(z).all()
+    he.close()
+    hg.close()
