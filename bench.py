@@ -438,6 +438,27 @@ def kernel_source_sha():
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
+def copy_rate_gbs():
+    """Read + write GB/s of a plain 1 GiB device-to-device copy (torch), median of 5 timed copies:
+    the streaming rate this GPU reaches outside the method, for reading the roofline fraction."""
+    import numpy as np
+    import torch
+
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    return 2 * (1 << 30) / (float(np.median(ms)) * 1e-3) / 1e9
+
+
 def copy_probe():
     import torch
 
@@ -571,6 +592,7 @@ def main():
             "bytes_per_launch": bytes_cheb,
             "avg_launch_ms": avg_cheb,
             "launches": n_cheb,
+            "copy_gbs": copy_rate_gbs(),
         },
     }
     if not args.no_variants and args.workload == "c2":
