@@ -142,26 +142,29 @@ def _setup(h, w, **opts):
     return (time.perf_counter() - t0) * 1e3
 
 
-def _cheb_bytes(h, kind, precision):
-    """Algorithmic bytes per node of the level-0 Chebyshev step as the level runs it: the
-    coefficients it streams (full or upper-half stencil, see rmg_level_kernel), u, b, D~^-1, d read
-    and d, u written; with BF16 storage the centre block comes from an FP32 array."""
+def _cheb_bytes(h, kind, precision, stored=True):
+    """Bytes per node of the level-0 Chebyshev step: the stencil blocks (stored: the ones the level
+    streams, full or upper half, see rmg_level_kernel; else the method's full 27 blocks), u, b,
+    D~^-1, d read and d, u written; with BF16 storage the centre block comes from an FP32 array."""
     lk = h.level_kernel(0)
     nd = 1 if kind == "scalar" else 3
+    nb = nd * nd
+    coefs = lk["coefs"] if stored else 27 * nb
+    coefs_lo = lk["coefs_lo"] if stored else 27 * nb
     if precision == 0:
-        return lk["coefs"] * 8 + 6 * nd * 8
+        return coefs * 8 + 6 * nd * 8
     if precision == 1:
-        return lk["coefs_lo"] * 4 + 6 * nd * 4
-    return (lk["coefs_lo"] - nd * nd) * 2 + nd * nd * 4 + 6 * nd * 4
+        return coefs_lo * 4 + 6 * nd * 4
+    return (coefs_lo - nb) * 2 + nb * 4 + 6 * nd * 4
 
 
-def _cheb_gbs(h, kind, precision, rows):
+def _cheb_gbs(h, kind, precision, rows, stored=True):
     from paper_2103_11962_amd import regmg
 
     n, ms = h.profile_query(regmg.TIMED_CHEB)
     if n == 0:
         return None
-    return _cheb_bytes(h, kind, precision) * rows / (ms / n * 1e-3) / 1e9
+    return _cheb_bytes(h, kind, precision, stored) * rows / (ms / n * 1e-3) / 1e9
 
 
 def variant_mixed(dev):
@@ -181,8 +184,10 @@ def variant_mixed(dev):
         ms, res, x = _timed_solves(h, b)
         entry = {"setup_ms": setup_ms, "solve_ms": ms, "iterations": res["iterations"],
                  "true_relres": res["true_relres"],
-                 "cheb_gbs": _cheb_gbs(h, "block3", prec, rows),
-                 "cheb_bytes_per_node": _cheb_bytes(h, "block3", prec)}
+                 "cheb_gbs": _cheb_gbs(h, "block3", prec, rows, stored=False),
+                 "cheb_bytes_per_node": _cheb_bytes(h, "block3", prec, stored=False),
+                 "cheb_gbs_at_stored_bytes": _cheb_gbs(h, "block3", prec, rows),
+                 "cheb_stored_bytes_per_node": _cheb_bytes(h, "block3", prec)}
         if prec == 0:
             x64 = x.clone()
         else:
@@ -215,8 +220,10 @@ def variant_batched(dev):
         h.profile(True)
         ms, res, _ = _timed_solves(h, b)
         out[name] = {"setup_ms": setup_ms, "solve_ms": ms, "iterations": res["iterations"],
-                     "true_relres": res["true_relres"], "cheb_gbs": _cheb_gbs(h, "scalar", 1, rows),
-                     "cheb_bytes_per_row": _cheb_bytes(h, "scalar", 1)}
+                     "true_relres": res["true_relres"], "cheb_gbs": _cheb_gbs(h, "scalar", 1, rows, stored=False),
+                     "cheb_bytes_per_row": _cheb_bytes(h, "scalar", 1, stored=False),
+                     "cheb_gbs_at_stored_bytes": _cheb_gbs(h, "scalar", 1, rows),
+                     "cheb_stored_bytes_per_row": _cheb_bytes(h, "scalar", 1)}
         if name == "batched":
             out[name]["tuning"] = h.tune_report().strip().splitlines()
         h.close()
