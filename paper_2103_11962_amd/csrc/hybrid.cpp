@@ -55,10 +55,13 @@ void host_offsets(int npts, int s, int& dx, int& dy, int& dz) {
   }
 }
 
+// Setup upload of a host table; waits for the copy, so the table may die on return.
 template <class T>
 void upload(DBuf& d, const std::vector<T>& v, hipStream_t st) {
   d.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
-  if (!v.empty()) RMG_HIP(hipMemcpyAsync(d.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  if (v.empty()) return;
+  RMG_HIP(hipMemcpyAsync(d.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  RMG_HIP(hipStreamSynchronize(st));
 }
 
 // The finest level's region matrices from the stencil level (nonzeros only, ascending columns).
@@ -415,6 +418,7 @@ void upload_level(rmg_handle* h, HLevel& H, bool coarsest, int64_t nc_next) {
     upload(D.rowcomp, rowcomp, st);
     D.ainv.alloc(sizeof(double) * (size_t)nc * nc);
     RMG_HIP(hipMemcpyAsync(D.ainv.p, abar.data(), sizeof(double) * abar.size(), hipMemcpyHostToDevice, st));
+    RMG_HIP(hipStreamSynchronize(st));  // abar is a local table
     D.cvec.alloc(sizeof(double) * nc);
     D.cvec2.alloc(sizeof(double) * nc);
     launch_gauss_jordan(D.ainv.as<double>(), nc, st);

@@ -46,9 +46,11 @@ static Cells cells_of(const Level& L) {
   return c;
 }
 
+// Setup upload of a host table; waits for the copy, so the table may die on return.
 static void upload(DBuf& d, const void* host, size_t bytes, hipStream_t st) {
   d.alloc(bytes);
   RMG_HIP(hipMemcpyAsync(d.p, host, bytes, hipMemcpyHostToDevice, st));
+  RMG_HIP(hipStreamSynchronize(st));
 }
 
 int validate_weights(rmg_handle* h, const Level& F, const Level& C) {
