@@ -1,6 +1,7 @@
 // Host planner: region validation, level geometry, block tables, interface groups,
 // and the coarsest-level composite operator.
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -207,7 +208,7 @@ static void validate_tiling(int dim, int nreg, const std::vector<int32_t>& ext, 
 }
 
 void build_level0(rmg_handle* h) {
-  Level* L = new Level();
+  std::unique_ptr<Level> L(new Level());  // owned here until the handle takes it
   L->dim = h->dim;
   L->nreg = h->nreg;
   L->npts = h->dim == 3 ? 27 : 9;
@@ -232,11 +233,11 @@ void build_level0(rmg_handle* h) {
   build_tables(*L);
   for (Level* old : h->levels) delete old;
   h->levels.clear();
-  h->levels.push_back(L);
+  h->levels.push_back(L.release());
 }
 
 Level* make_coarse_level(const Level& F) {
-  Level* C = new Level();
+  std::unique_ptr<Level> C(new Level());  // released to the caller once complete
   C->dim = F.dim;
   C->nreg = F.nreg;
   C->npts = F.dim == 3 ? 27 : 9;
@@ -259,7 +260,7 @@ Level* make_coarse_level(const Level& F) {
     Q.pad = 0;
   }
   build_tables(*C);
-  return C;
+  return C.release();
 }
 
 // Coarsest level: Abar = Psi-bar [[Abar]] Psi-bar^T assembled densely on the host from the

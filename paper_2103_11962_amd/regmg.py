@@ -230,17 +230,19 @@ def default_options(**kw) -> Options:
 class Handle:
     """One solver instance on one HIP device and stream."""
 
-    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = False):
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = False, allocator=None):
         """torch_allocator: take every device buffer of the handle from PyTorch's caching
-        allocator (on the handle's stream) instead of hipMalloc."""
+        allocator (on the handle's stream) instead of hipMalloc; allocator: any other
+        ``Allocator`` (its callbacks must stay valid until close())."""
         import torch
 
         lib = load()
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self._stream = stream
-        # the callbacks must outlive every buffer they provided: kept on the handle until close()
-        self._alloc = _torch_allocator(device, stream) if torch_allocator else None
+        # the callbacks must outlive every buffer they provided: kept on the handle
+        self._alloc = allocator if allocator is not None else (_torch_allocator(device, stream) if torch_allocator
+                                                               else None)
         h = ctypes.c_void_p()
         _check(lib.rmg_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream),
                               ctypes.byref(self._alloc) if self._alloc is not None else None))

@@ -47,3 +47,44 @@ def test_torch_allocator(hip_device, case):
     h1.__dict__.pop("_keep", None)  # the harness's input tensor (element coefficients), not a library buffer
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == before
+
+
+def test_provider_failure_mid_setup(hip_device):
+    """A provider that runs dry partway through setup: the setup fails with RMG_ERR_OOM, the
+    handle can still be closed, and every buffer it did get is returned."""
+    import torch
+
+    from paper_2103_11962_amd import regmg
+
+    w = synth.workload("c2_small")
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    state = {"left": None}
+
+    def alloc(nbytes, ctx):
+        if state["left"] is not None:
+            if state["left"] == 0:
+                return None
+            state["left"] -= 1
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=0, stream=torch.cuda.current_stream(0))
+
+    def free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    prov = regmg.Allocator(regmg.ALLOC_FN(alloc), regmg.FREE_FN(free), None)
+    h = regmg.Handle(0, allocator=prov)
+    h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
+    h.assemble_q1(regmg.PDE_LAPLACE, w.h)
+    state["left"] = 25  # a few buffers more, then nothing
+    with pytest.raises(regmg.RmgError) as e:
+        h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree)
+    assert e.value.status == "RMG_ERR_OOM"
+    state["left"] = None  # the provider recovers: a new setup succeeds and solves
+    h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree)
+    b = harness.to_dev(synth.rhs(w))
+    x = torch.zeros_like(b)
+    assert h.solve(b, x)["converged"]
+    h.close()
+    del b, x
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
