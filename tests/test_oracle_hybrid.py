@@ -178,3 +178,23 @@ def test_table5_structure():
         its[name] = len(h) - 1
     print("Table 5 structure, cycles to 1e-6:", its)
     assert max(its.values()) <= 30 and max(its.values()) - min(its.values()) <= 4
+
+
+def test_staged_aggregation_hand_example():
+    """One unstructured 4x3 region of the five-point operator, no interfaces and no Dirichlet
+    nodes, rows i = x + 4y.  Worked by hand: stage II makes roots 0 -> {0, 1, 4}, 3 -> {3, 2, 7}
+    and 9 -> {9, 8, 10, 5} (2, 5, 6, 8 and 11 each have an aggregated neighbour when visited);
+    stage III: node 6 couples twice to {2, 3, 7} and twice to {5, 8, 9, 10}, node 11 once to each,
+    and both ties go to the aggregate whose smallest member comes first ({2, 3, 7}); stage IV has
+    nothing left.  Coarse nodes in order of smallest member: {0,1,4}, {2,3,6,7,11}, {5,8,9,10}."""
+    o, e = synth.tensor_layout([[4], [3]])
+    lay = Layout(2, o, e, 0)
+    L = hybrid.finest_level(lay, assembly.split_composite(lay, assembly.composite_fd5(lay)))
+    R = L.regions[0]
+    agg, points = hybrid.aggregate_region(R, True, np.zeros(R.comp.size, dtype=bool), L.shape, L.mask)
+    first = {}
+    for i, a in enumerate(agg):
+        first.setdefault(a, i)
+    order = {a: c for c, a in enumerate(sorted(first, key=first.get))}
+    np.testing.assert_array_equal([order[a] for a in agg], [0, 0, 1, 1, 0, 2, 1, 1, 2, 2, 2, 1])
+    assert points == {}  # no aggregate came from the structured rule
