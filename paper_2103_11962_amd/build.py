@@ -12,7 +12,7 @@ SOURCES = ["kernels.hip", "kernels_stencil.hip", "kernels_gs.hip", "kernels_hybr
            "solver.cpp", "learned.cpp", "hybrid.cpp", "api.cpp"]
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

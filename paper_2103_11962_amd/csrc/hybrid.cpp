@@ -19,6 +19,10 @@
 // The aggregation is sequential and runs here once per setup; the cycle runs on the device.
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "hybrid.h"
@@ -27,6 +31,36 @@
 namespace rmg {
 
 namespace {
+
+// fn(k) for k in [0, n) on up to 16 host threads; each k writes only its own outputs and makes
+// no HIP calls.  The first exception is rethrown on the calling thread.
+template <class F>
+void parallel_for(int64_t n, F&& fn) {
+  const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+  const int nt = (int)std::min<int64_t>(std::min<int64_t>(n, 16), hw);
+  if (nt <= 1) {
+    for (int64_t k = 0; k < n; ++k) fn(k);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::exception_ptr err;
+  std::mutex m;
+  auto work = [&] {
+    for (int64_t k; (k = next.fetch_add(1)) < n;) {
+      try {
+        fn(k);
+      } catch (...) {
+        std::lock_guard<std::mutex> g(m);
+        if (!err) err = std::current_exception();
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (std::thread& t : pool) t.join();
+  if (err) std::rethrow_exception(err);
+}
 
 int coarse_coord(int g, int axis, const int shape[3], unsigned mask) {
   int c = 3 * ((g + 1) / 3);
@@ -76,7 +110,7 @@ void finest_level(rmg_handle* h, HLevel& H) {
   H.regs.assign(L.nreg, HRegionHost());
   H.off.assign(L.nreg + 1, 0);
   const int cx = L.comp[0], cy = L.comp[1], cz = L.comp[2];
-  for (int k = 0; k < L.nreg; ++k) {
+  parallel_for(L.nreg, [&](int64_t k) {
     const RegionGeo& R = L.regs[k];
     HRegionHost& G = H.regs[k];
     G.ptr.assign(1, 0);
@@ -102,8 +136,8 @@ void finest_level(rmg_handle* h, HLevel& H) {
                            ((m & 8u) && gy == cy - 1) || ((m & 16u) && gz == 0) || ((m & 32u) && gz == cz - 1);
           G.free.push_back(dir ? 0 : 1);
         }
-    H.off[k + 1] = H.off[k] + G.n();
-  }
+  });
+  for (int k = 0; k < L.nreg; ++k) H.off[k + 1] = H.off[k] + H.regs[k].n();
 }
 
 std::vector<int32_t> multiplicity(const HLevel& H) {
@@ -214,8 +248,9 @@ void coarsen(const Hybrid& hy, HLevel& F, HLevel& C, const std::vector<int32_t>&
   const int nreg = (int)F.regs.size();
   std::vector<std::vector<int32_t>> local(nreg);
   std::vector<std::vector<std::array<int32_t, 3>>> cxyz(nreg);
-  for (int k = 0; k < nreg; ++k)
+  parallel_for(nreg, [&](int64_t k) {
     aggregate(F.regs[k], kinds[k] != 0, mult, F.shape, hy.mask, dim, local[k], cxyz[k]);
+  });
   for (int a = 0; a < 3; ++a) C.shape[a] = a < dim ? (F.shape[a] - 1) / 3 + 1 : 1;
   C.regs.assign(nreg, HRegionHost());
   C.off.assign(nreg + 1, 0);
@@ -244,7 +279,7 @@ void coarsen(const Hybrid& hy, HLevel& F, HLevel& C, const std::vector<int32_t>&
     for (size_t i = 0; i < local[k].size(); ++i)
       if (local[k][i] >= 0) F.agg[F.off[k] + i] = (int32_t)(C.off[k] + local[k][i]);
   // Galerkin product per region: coarse row a sums the rows of its aggregate, columns mapped by P
-  for (int k = 0; k < nreg; ++k) {
+  parallel_for(nreg, [&](int64_t k) {
     const HRegionHost& A = F.regs[k];
     HRegionHost& G = C.regs[k];
     const int64_t nc = G.n();
@@ -284,17 +319,16 @@ void coarsen(const Hybrid& hy, HLevel& F, HLevel& C, const std::vector<int32_t>&
       }
       G.ptr.push_back((int64_t)G.col.size());
     }
-  }
+  });
 }
 
 // Dependency levels of the forward (lower triangle) or backward (upper triangle) sweep of every
 // region, flattened: region k owns levels reg[k] .. reg[k+1]-1, level v owns rows lv[v] .. lv[v+1]-1.
 void gs_schedule(const HLevel& H, bool backward, std::vector<int32_t>& reg, std::vector<int32_t>& lv,
                  std::vector<int32_t>& rows) {
-  reg.assign(1, 0);
-  lv.assign(1, 0);
-  rows.clear();
-  for (size_t k = 0; k < H.regs.size(); ++k) {
+  const int nreg = (int)H.regs.size();
+  std::vector<std::vector<int32_t>> order(nreg), bounds(nreg);  // per region: rows by level, level ends
+  parallel_for(nreg, [&](int64_t k) {
     const HRegionHost& G = H.regs[k];
     const int64_t n = G.n();
     std::vector<int32_t> level(n, 0);
@@ -312,11 +346,18 @@ void gs_schedule(const HLevel& H, bool backward, std::vector<int32_t>& reg, std:
     std::vector<int32_t> cnt(nlev + 1, 0);
     for (int32_t l : level) ++cnt[l + 1];
     for (int32_t l = 0; l < nlev; ++l) cnt[l + 1] += cnt[l];
-    const int32_t base = (int32_t)rows.size();
-    rows.resize(rows.size() + n);
+    order[k].resize(n);
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int64_t i = 0; i < n; ++i) rows[base + fill[level[i]]++] = (int32_t)(H.off[k] + i);
-    for (int32_t l = 0; l < nlev; ++l) lv.push_back(base + cnt[l + 1]);
+    for (int64_t i = 0; i < n; ++i) order[k][fill[level[i]]++] = (int32_t)(H.off[k] + i);
+    bounds[k].assign(cnt.begin() + 1, cnt.end());
+  });
+  reg.assign(1, 0);
+  lv.assign(1, 0);
+  rows.clear();
+  for (int k = 0; k < nreg; ++k) {
+    const int32_t base = (int32_t)rows.size();
+    rows.insert(rows.end(), order[k].begin(), order[k].end());
+    for (int32_t b : bounds[k]) lv.push_back(base + b);
     reg.push_back((int32_t)lv.size() - 1);
   }
 }
@@ -349,19 +390,21 @@ void upload_level(rmg_handle* h, HLevel& H, bool coarsest, int64_t nc_next) {
   }
   std::vector<int32_t> col(sptr[ns], 0);
   std::vector<double> val(sptr[ns], 0.0);
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t s = i / 64, w = (sptr[s + 1] - sptr[s]) / 64;
-    const HRegionHost& G = H.regs[rreg[i]];
-    for (int64_t e = 0; e < w; ++e) {
-      const int64_t at = sptr[s] + 64 * e + (i & 63);
-      if (e < rlen[i]) {
-        col[at] = (int32_t)(H.off[rreg[i]] + G.col[rbeg[i] + e]);
-        val[at] = G.val[rbeg[i] + e];
-      } else {
-        col[at] = (int32_t)i;
+  parallel_for(ns, [&](int64_t s) {
+    const int64_t w = (sptr[s + 1] - sptr[s]) / 64;
+    for (int64_t i = s * 64; i < std::min(n, (s + 1) * 64); ++i) {
+      const HRegionHost& G = H.regs[rreg[i]];
+      for (int64_t e = 0; e < w; ++e) {
+        const int64_t at = sptr[s] + 64 * e + (i & 63);
+        if (e < rlen[i]) {
+          col[at] = (int32_t)(H.off[rreg[i]] + G.col[rbeg[i] + e]);
+          val[at] = G.val[rbeg[i] + e];
+        } else {
+          col[at] = (int32_t)i;
+        }
       }
     }
-  }
+  });
   upload(D.sptr, sptr, st);
   upload(D.col, col, st);
   upload(D.val, val, st);
@@ -454,18 +497,20 @@ void upload_level(rmg_handle* h, HLevel& H, bool coarsest, int64_t nc_next) {
     }
     std::vector<int32_t> tcol(tsptr[ns], 0);
     std::vector<double> tval(tsptr[ns], 0.0);
-    for (int64_t t = 0; t < n; ++t) {
-      const int64_t i = rows[t];
-      const HRegionHost& G = H.regs[rreg[i]];
-      const int64_t li = i - H.off[rreg[i]];
-      int64_t at = tsptr[t / 64] + (t & 63);
-      for (int64_t e = G.ptr[li]; e < G.ptr[li + 1]; ++e)
-        if (backward ? G.col[e] > li : G.col[e] < li) {
-          tcol[at] = (int32_t)(H.off[rreg[i]] + G.col[e]);
-          tval[at] = G.val[e];
-          at += 64;
-        }
-    }
+    parallel_for(ns, [&](int64_t s) {
+      for (int64_t t = s * 64; t < std::min(n, (s + 1) * 64); ++t) {
+        const int64_t i = rows[t];
+        const HRegionHost& G = H.regs[rreg[i]];
+        const int64_t li = i - H.off[rreg[i]];
+        int64_t at = tsptr[s] + (t & 63);
+        for (int64_t e = G.ptr[li]; e < G.ptr[li + 1]; ++e)
+          if (backward ? G.col[e] > li : G.col[e] < li) {
+            tcol[at] = (int32_t)(H.off[rreg[i]] + G.col[e]);
+            tval[at] = G.val[e];
+            at += 64;
+          }
+      }
+    });
     upload(S.reg, reg, st);
     upload(S.lv, lv, st);
     upload(S.rows, rows, st);
