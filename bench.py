@@ -43,8 +43,8 @@ ALGO_COEFS = 27
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
-TRAFFIC_BYTES = 6364099543
-TRAFFIC_KERNEL_SHA = "68845258008b14fe"
+TRAFFIC_BYTES = 6179689364
+TRAFFIC_KERNEL_SHA = "c192c4a37ff748ec"
 
 CPU_SAMPLE = r"""
 import json, sys, time

@@ -85,6 +85,15 @@ constexpr int kBlock = 256;  // threads per block for node-parallel kernels
 
 constexpr size_t kAutoTileMin = 2048;  // 2.5D tiles needed on a level before they are used by default
 
+// Threads per 2.5D tile block.  The FP64 kernel needs about 142 VGPRs (3 waves per SIMD), so a
+// 768-thread block (12 waves) is the widest that fits and one block runs per CU; the FP32 kernel
+// needs about 91 (5 waves per SIMD), where two 512-thread blocks (16 waves) run per CU.  A level
+// whose V-cycle runs in FP32 uses the narrow tiles for every operation.
+constexpr int kTileThreadsF64 = 768;
+constexpr int kTileThreadsF32 = 512;
+// Largest (tx + 2)(ty + 2) over tiles of at most nt nodes (tx * ty <= nt): the single row, ty = 1.
+constexpr int tile_plane_cap(int nt) { return 3 * (nt + 2); }
+
 // A 2.5D tile of a 3D region: ty x-rows of tx nodes starting at (x0, y0), planes z0 .. z0+nz-1.
 struct Tile3 {
   int region, x0, y0, z0, tx, ty, nz, pad;
@@ -152,6 +161,7 @@ struct Level {
   DBuf d_tiles;
   bool use_tiles = false;    // run 27-point stencil operations with the 2.5D kernel
   int tile_depth = 21;       // planes per tile
+  int tile_threads = kTileThreadsF64;  // threads per 2.5D tile block (tiles hold at most this many nodes)
   int tile_grid = 0;         // > 0: persistent launch of this many blocks looping over the tiles
   bool per_region = false;   // stencil operations launch the node-parallel kernel once per region
   // interface groups: copies of each shared composite node, ascending region order

@@ -145,9 +145,6 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
 // new plane from LDS, and the plane after next is prefetched from global memory into registers
 // while the current plane is computed.  Neighbours outside the region box read 0 from LDS and
 // have zero coefficients, so the 27-term sum needs no bounds branches.
-constexpr int kT3 = 512;           // threads per 3D tile block
-constexpr int kT3Plane = 1544;     // max (ty+2)(tx+2) over tx*ty <= 512
-constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
 
 // Grid = one block per tile, or (persistent launch) fewer blocks that stride over the tile list.
 // SYM: the operator is symmetric and `coef` holds only the upper half of each stencil (offsets
@@ -157,10 +154,14 @@ constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
 // couplings towards z+1 for the next plane, the in-plane ones for this plane.  Only neighbours
 // outside the tile (its edge rows, and plane z-1 of the tile's first plane) are read from memory,
 // so HBM carries about 14 instead of 27 coefficients per node.
-template <class V, class C, StencilOp OP, bool DOT, bool SYM>
-__global__ __launch_bounds__(kT3) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles, int ntiles,
-                                                   const C* __restrict__ coef, const float* __restrict__ centre,
-                                                   OpP<V> p, double* __restrict__ partials) {
+// NT threads per block (the level's tile_threads); tiles hold at most NT nodes.
+template <int NT, class V, class C, StencilOp OP, bool DOT, bool SYM>
+__global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles, int ntiles,
+                                                  const C* __restrict__ coef, const float* __restrict__ centre,
+                                                  OpP<V> p, double* __restrict__ partials) {
+  constexpr int kT3 = NT;
+  constexpr int kT3Plane = tile_plane_cap(NT);
+  constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
   __shared__ V pl[2][kT3Plane];
   // SYM: the previous plane's couplings towards z+1 (9 per tile node) and this plane's in-plane upper
   // couplings (4 per tile node), indexed by the tile-local node = thread index
@@ -364,13 +365,23 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
     if (tiled) {
       const C* sym = nullptr;
       if constexpr (std::is_same<V, C>::value) sym = static_cast<const C*>(a.lowp ? L.coef_lo_sym.p : L.coef_sym.p);
-      if (sym) {
-        if constexpr (std::is_same<V, C>::value)
-          hipLaunchKernelGGL((k_stencil3d<V, C, OP, DOT, true>), dim3(grid3), dim3(kT3), 0, st, v,
-                             L.d_tiles.as<Tile3>(), ntiles, sym, centre, p, a.partials);
+      auto launch3d = [&](auto nt) {
+        constexpr int NT = decltype(nt)::value;
+        if (sym) {
+          if constexpr (std::is_same<V, C>::value)
+            hipLaunchKernelGGL((k_stencil3d<NT, V, C, OP, DOT, true>), dim3(grid3), dim3(NT), 0, st, v,
+                               L.d_tiles.as<Tile3>(), ntiles, sym, centre, p, a.partials);
+        } else {
+          hipLaunchKernelGGL((k_stencil3d<NT, V, C, OP, DOT, false>), dim3(grid3), dim3(NT), 0, st, v,
+                             L.d_tiles.as<Tile3>(), ntiles, coef, centre, p, a.partials);
+        }
+      };
+      if constexpr (sizeof(V) == 8) {
+        if (L.tile_threads == kTileThreadsF64) launch3d(std::integral_constant<int, kTileThreadsF64>());
+        else launch3d(std::integral_constant<int, kTileThreadsF32>());
       } else {
-        hipLaunchKernelGGL((k_stencil3d<V, C, OP, DOT, false>), dim3(grid3), dim3(kT3), 0, st, v,
-                           L.d_tiles.as<Tile3>(), ntiles, coef, centre, p, a.partials);
+        RMG_REQUIRE(L.tile_threads == kTileThreadsF32, RMG_ERR_ARG, "internal: FP32 tiles must be narrow");
+        launch3d(std::integral_constant<int, kTileThreadsF32>());
       }
     }
   }

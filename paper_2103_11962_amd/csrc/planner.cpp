@@ -67,27 +67,32 @@ static bool shared_node(const Level& L, const RegionGeo& R, int x, int y, int z)
          (y == R.ey - 1 && gy != L.comp[1] - 1) || (z == 0 && gz != 0) || (z == R.ez - 1 && gz != L.comp[2] - 1);
 }
 
-// 2.5D tiles of a 3D level: 512-thread tiles of whole (or 512-node) x-rows, `depth` planes deep,
+// 2.5D tiles of a 3D level: L.tile_threads-node tiles of whole (or that many nodes of) x-rows, `depth` planes deep,
 // ordered largest first so a persistent launch hands out the costly tiles early.
 void make_tiles(Level& L, int depth) {
   L.tiles.clear();
   L.tile_depth = depth;
   if (L.dim != 3) return;
-  constexpr int kThreads = 512;
+  const int kThreads = L.tile_threads;
   for (int k = 0; k < L.nreg; ++k) {
     const RegionGeo& R = L.regs[k];
     const int tx = std::min(R.ex, kThreads);
-    const int ty = std::min(R.ey, kThreads / tx);
+    const int tymax = std::min(R.ey, kThreads / tx);
+    const int nty = (R.ey + tymax - 1) / tymax;  // tiles per column, rows shared out evenly
     for (int z0 = 0; z0 < R.ez; z0 += depth)
-      for (int y0 = 0; y0 < R.ey; y0 += ty)
+      for (int j = 0, y0 = 0; j < nty; ++j) {
+        const int ty = R.ey / nty + (j < R.ey % nty ? 1 : 0);
         for (int x0 = 0; x0 < R.ex; x0 += tx)
           L.tiles.push_back(Tile3{k, x0, y0, z0, tx, ty, std::min(depth, R.ez - z0), 0});
+        y0 += ty;
+      }
   }
   std::stable_sort(L.tiles.begin(), L.tiles.end(), [](const Tile3& a, const Tile3& b) {
     return (int64_t)a.tx * a.ty * a.nz > (int64_t)b.tx * b.ty * b.nz;
   });
   for (const Tile3& T : L.tiles)
-    RMG_REQUIRE((T.tx + 2) * (T.ty + 2) <= 1544 && T.tx * T.ty <= 512, RMG_ERR_ARG, "internal: tile too large");
+    RMG_REQUIRE((T.tx + 2) * (T.ty + 2) <= tile_plane_cap(kThreads) && T.tx * T.ty <= kThreads, RMG_ERR_ARG,
+                "internal: tile too large");
   if (!L.tiles.empty()) {
     L.d_tiles.alloc(sizeof(Tile3) * L.tiles.size());
     RMG_HIP(hipMemcpy(L.d_tiles.p, L.tiles.data(), sizeof(Tile3) * L.tiles.size(), hipMemcpyHostToDevice));

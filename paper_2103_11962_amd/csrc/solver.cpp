@@ -166,7 +166,7 @@ static void autotune_level(rmg_handle* h, Level& L, int level, bool lowp) {
       }
     }
   }
-  std::vector<TuneChoice> cands = {{0, 21, 0}, {1, 11, 0}, {1, 21, 0}, {1, 41, 0}, {2, 21, 512}, {2, 21, 1024}};
+  std::vector<TuneChoice> cands = {{0, 21, 0}, {1, 11, 0}, {1, 21, 0}, {1, 41, 0}, {2, 21, 256}, {2, 21, 512}, {2, 21, 1024}};
   const size_t vb = (lowp ? sizeof(float) : sizeof(double)) * (size_t)L.ndofs();
   void* vec[5] = {lowp ? L.u32.p : L.u.p, lowp ? L.u232.p : L.u2.p, lowp ? L.d32.p : L.d.p,
                   lowp ? L.r32.p : L.r.p, lowp ? L.b32.p : L.b.p};
@@ -217,7 +217,11 @@ static void autotune_level(rmg_handle* h, Level& L, int level, bool lowp) {
 // Launch configuration, work vectors and symmetric half-stencil copy of one stencil level.
 static void configure_level(rmg_handle* h, Level& L, bool with_b, bool sym) {
   const rmg_options& o = h->opt;
-  if (L.dim == 3 && L.tile_depth != 21) make_tiles(L, 21);
+  const int threads = o.precision == RMG_PREC_FP64 ? kTileThreadsF64 : kTileThreadsF32;
+  if (L.dim == 3 && (L.tile_depth != 21 || L.tile_threads != threads)) {
+    L.tile_threads = threads;
+    make_tiles(L, 21);
+  }
   L.tile_grid = 0;
   L.per_region = o.batched == 0;
   L.use_tiles = !L.per_region && L.ndof == 1 && !L.tiles.empty() &&
