@@ -22,6 +22,12 @@ import numpy as np
 import scipy.sparse as sp
 
 
+def coarse_positions(e: int):
+    """Local positions of a region's coarse nodes along an axis of e nodes: 0, 3, 6, ... below
+    e - 1, then e - 1 (Section 3.2: the region's end nodes must be coarse)."""
+    return list(range(0, e - 1, 3)) + [e - 1]
+
+
 class Layout:
     """Region boxes on a composite node lattice."""
 
@@ -79,11 +85,35 @@ class Layout:
         return out
 
     def coarsen(self):
-        """Layout of the next level: every third node of each region (rate 3)."""
-        if ((self.extents - 1) % 3).any() or (self.origins % 3).any():
-            raise ValueError("region extents-1 and origins must be divisible by 3 to coarsen")
-        return Layout(self.dim, self.origins // 3, (self.extents - 1) // 3 + 1,
-                      self.dirichlet_mask, self.ndof)
+        """Layout of the next level (coarsening rate 3, Section 3.2 construction rules).
+
+        Along each axis a region keeps every third node counted from its first one, and its last
+        node (``coarse_positions``), so its end nodes -- the interface -- are coarse and its last
+        coarse interval spans 1, 2 or 3 cells.  The composite coarse lattice along an axis is the
+        union of the regions' coarse positions; it must agree with each region's own choice on
+        that region's range, so that co-located fine interface nodes see the same coarse nodes from
+        every region.  ``fine_positions`` of the result keeps, per axis, the composite fine
+        coordinate of each coarse lattice line.  With region extents - 1 and origins divisible by 3
+        this is every third node of the composite lattice.
+        """
+        origins = np.zeros_like(self.origins)
+        extents = np.zeros_like(self.extents)
+        lines = []
+        for d in range(self.dim):
+            local = [[int(o) + p for p in coarse_positions(int(e))]
+                     for o, e in zip(self.origins[:, d], self.extents[:, d])]
+            lattice = sorted({g for pts in local for g in pts})
+            index = {g: i for i, g in enumerate(lattice)}
+            for k, pts in enumerate(local):
+                inside = [g for g in lattice if pts[0] <= g <= pts[-1]]
+                if inside != pts:
+                    raise ValueError(f"coarse points of region {k} disagree with its neighbours' along axis {d}")
+                origins[k, d] = index[pts[0]]
+                extents[k, d] = len(pts)
+            lines.append(np.asarray(lattice, dtype=np.int64))
+        coarse = Layout(self.dim, origins, extents, self.dirichlet_mask, self.ndof)
+        coarse.fine_positions = lines
+        return coarse
 
     # ------------------------------------------------------------- vectors
     def _vshape(self, shape):
