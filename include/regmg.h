@@ -222,7 +222,13 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
  * linear interpolation with interface-replicated rows, per-region Galerkin
  * products [[Abar]] = R^(r) [[A]] P^(r) on the device, and on the last level the
  * composite operator Abar = Psi-bar [[Abar]] Psi-bar^T and its inverse.
- * RMG_ERR_SHAPE if some region extent-1 or origin is not divisible by
+ * Coarsening: along each axis a region keeps every third node from its first
+ * one and its last node ((e + 1) / 3 + 1 of e nodes), interpolating linearly
+ * over the actual spacing, so any extent >= 2 coarsens; the composite coarse
+ * lattice is the union of the regions' coarse points.  RMG_ERR_SHAPE if two
+ * regions' coarse points disagree on a shared interface (possible only when the
+ * boxes do not form a tensor-product layout), or, with stored interpolation
+ * weights or opt->hybrid, if some region extent-1 or origin is not divisible by
  * 3^(nlevels-1).  RMG_ERR_NUMERIC if a diagonal is not positive or the coarse
  * matrix is singular. */
 rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt);

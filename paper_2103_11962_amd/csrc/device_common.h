@@ -59,10 +59,59 @@ __device__ __forceinline__ void decompose(const RegionGeo& R, int li, int& x, in
   z = t / R.ey;
 }
 
-// Linear interpolation weight of a fine node at distance t (in fine cells) from a coarse node.
-__device__ __forceinline__ double w1(int t) {
-  t = t < 0 ? -t : t;
-  return t == 0 ? 1.0 : (t == 1 ? 2.0 / 3.0 : (t == 2 ? 1.0 / 3.0 : 0.0));
+// 1/m for a coarse interval of m = 1, 2 or 3 cells.  num * (1/m) equals num / m exactly for
+// 0 <= num <= m (2 * (1/3) rounds like 2/3, 3 * (1/3) rounds to 1), with no division.
+__device__ __forceinline__ double inv_span(int m) { return m == 3 ? 1.0 / 3.0 : (m == 2 ? 0.5 : 1.0); }
+
+// Rate-3 coarsening of one region axis of e fine nodes into E coarse nodes: coarse node C sits at
+// fine position min(3C, e - 1) (every third node from the region's first, and its last node).
+// Fine node g (0 <= g < e) takes its interpolation from the coarse nodes lo (weight wlo) and, when
+// whi != 0, lo + 1: lo = min(g / 3, E - 2) is the start of its coarse interval [p0, p1], p0 = 3 lo,
+// p1 = min(3 lo + 3, e - 1), with linear weights (p1 - g) / (p1 - p0) and (g - p0) / (p1 - p0); a
+// node at a coarse position takes that node alone (weight 1).  A degenerate axis (E = 1, the z
+// axis of a 2D level) has one coarse node.
+__device__ __forceinline__ void bracket(int g, int e, int E, int& lo, double& wlo, double& whi) {
+  if (E < 2) {
+    lo = 0;
+    wlo = 1.0;
+    whi = 0.0;
+    return;
+  }
+  lo = min(g / 3, E - 2);
+  const int p0 = 3 * lo, m = min(p0 + 3, e - 1) - p0, a = g - p0;
+  const double inv = inv_span(m);
+  const bool at_end = a == m;  // g is the interval's end node, the next coarse node
+  lo += at_end ? 1 : 0;
+  wlo = at_end ? 1.0 : (double)(m - a) * inv;
+  whi = at_end ? 0.0 : (double)a * inv;
+}
+
+// Fine position of coarse node C on an axis of e fine nodes.
+__device__ __forceinline__ int coarse_pos(int C, int e) { return min(3 * C, e - 1); }
+
+// The coarse intervals on either side of coarse node C: mL cells to the left (0 for the first
+// node), mR to the right (0 for the last); a degenerate axis (E = 1) has neither.
+__device__ __forceinline__ void coarse_spans(int C, int e, int E, int& mL, int& mR) {
+  const int p = coarse_pos(C, e);
+  mL = C > 0 ? p - coarse_pos(C - 1, e) : 0;
+  mR = C < E - 1 ? coarse_pos(C + 1, e) - p : 0;
+}
+
+// The two coarse nodes whose interval holds the fine node u cells from coarse node C (C's spans
+// mL, mR; -mL <= u <= mR): C + o0 with weight w0 and C + o0 + 1 with weight w1.
+__device__ __forceinline__ void interval_weights(int u, int mL, int mR, int& o0, double& w0, double& w1) {
+  const bool neg = u < 0;
+  o0 = neg ? -1 : 0;
+  const int m = max(neg ? mL : mR, 1), a = neg ? mL + u : u;  // a: cells from the interval's start
+  const double inv = inv_span(m);
+  w0 = (double)(m - a) * inv;
+  w1 = (double)a * inv;
+}
+
+// Weight of coarse node C for the fine node t cells from it (|t| <= 2), given its spans.
+__device__ __forceinline__ double tap(int t, int mL, int mR) {
+  const int m = t < 0 ? mL : mR, d = t < 0 ? -t : t;
+  return t == 0 ? 1.0 : (d < m ? (double)(m - d) * inv_span(m) : 0.0);
 }
 
 // Sum over a block of kBlock threads; the result is valid in thread 0.

@@ -276,6 +276,9 @@ void q1_laplace_element(double h, double K[64]);
 
 // planner.cpp
 void build_level0(rmg_handle* h);
+// Coarse region boxes and composite lattice extents of the next level; RMG_ERR_SHAPE when the
+// regions' coarse points disagree on an interface.
+void coarse_geometry(int dim, const std::vector<RegionGeo>& fine, std::vector<RegionGeo>& coarse, int comp[3]);
 Level* make_coarse_level(const Level& fine);
 void build_tables(Level& L);
 void make_tiles(Level& L, int depth);

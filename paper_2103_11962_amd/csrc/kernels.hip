@@ -303,9 +303,10 @@ __device__ __forceinline__ double pweight(const double* __restrict__ pw, const R
   return pw[(RF.off + ((int64_t)fz * RF.ey + fy) * RF.ex + fx) * 8 + ix + 2 * iy + 4 * iz];
 }
 
-// One thread per coarse node: w = sum_f P_fC r_f over the fine nodes of the same region within
-// two fine cells per axis (r already divided by multiplicity), per dof.  Coarse Dirichlet nodes
-// receive nothing (free fine nodes do not interpolate from them).
+// One thread per coarse node: w = sum_f P_fC r_f over the fine nodes of the same region in the
+// coarse intervals on either side of the node (at most two fine cells per side; r already divided
+// by multiplicity), per dof.  Coarse Dirichlet nodes receive nothing (free fine nodes do not
+// interpolate from them).
 template <int DIM, int NDOF, class V>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, const V* __restrict__ r,
                                                      V* __restrict__ w) {
@@ -322,21 +323,35 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, c
   for (int a = 0; a < NDOF; ++a) acc[a] = (V)0;
   if (!is_dirichlet(C, RC.ox + X, RC.oy + Y, RC.oz + Z)) {
     const V* __restrict__ rr = r + RF.off * NDOF;
+    const int px = coarse_pos(X, RF.ex), py = coarse_pos(Y, RF.ey), pz = DIM == 3 ? coarse_pos(Z, RF.ez) : 0;
+    int mxl, mxr, myl, myr, mzl = 0, mzr = 0;
+    coarse_spans(X, RF.ex, RC.ex, mxl, mxr);
+    coarse_spans(Y, RF.ey, RC.ey, myl, myr);
+    if (DIM == 3) coarse_spans(Z, RF.ez, RC.ez, mzl, mzr);
+    double wxs[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) wxs[t] = tap(t - 2, mxl, mxr);
     const int tzlo = DIM == 3 ? -2 : 0, tzhi = DIM == 3 ? 2 : 0;
+#pragma unroll 1
     for (int tz = tzlo; tz <= tzhi; ++tz) {
-      const int fz = 3 * Z + tz;
+      const int fz = pz + tz;
       if ((unsigned)fz >= (unsigned)RF.ez) continue;
-      const double wz = w1(tz);
+      const double wz = DIM == 3 ? tap(tz, mzl, mzr) : 1.0;
+      if (wz == 0.0) continue;
       for (int ty = -2; ty <= 2; ++ty) {
-        const int fy = 3 * Y + ty;
+        const int fy = py + ty;
         if ((unsigned)fy >= (unsigned)RF.ey) continue;
-        const double wzy = wz * w1(ty);
+        const double wy = tap(ty, myl, myr);
+        if (wy == 0.0) continue;
+        const double wzy = wz * wy;
         const int base = (fz * RF.ey + fy) * RF.ex;
 #pragma unroll
         for (int tx = -2; tx <= 2; ++tx) {
-          const int fx = 3 * X + tx;
+          const int fx = px + tx;
           if ((unsigned)fx >= (unsigned)RF.ex) continue;
-          const V wt = (V)(wzy * w1(tx));
+          const double wx = wxs[tx + 2];
+          if (wx == 0.0) continue;
+          const V wt = (V)(wzy * wx);
 #pragma unroll
           for (int a = 0; a < NDOF; ++a) acc[a] += wt * rr[(int64_t)(base + fx) * NDOF + a];
         }
@@ -443,7 +458,8 @@ void launch_restrict(const Level& F, const Level& C, bool lowp, const void* r_sc
 }
 
 // One thread per fine node: u += sum_C P_fC ubar_C over the (up to 2 per axis) coarse nodes of
-// the coarse cell containing the node, per dof.
+// the coarse interval containing the node, per dof.  Stored weights are kept per canonical cell
+// of the rate-3 lattice (extents 3^k + 1).
 template <int DIM, int NDOF, class V, bool STORED>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView F, LevelView C, const V* __restrict__ ubar,
                                                         V* __restrict__ u, const double* __restrict__ pw) {
@@ -454,15 +470,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView F, LevelView C
   if (li >= RF.n) return;
   int x, y, z;
   decompose(RF, li, x, y, z);
-  const bool fdir = is_dirichlet(F, RF.ox + x, RF.oy + y, RF.oz + z);
-  const int cx = x / 3, tx = x - 3 * cx, cy = y / 3, ty = y - 3 * cy, cz = z / 3, tz = z - 3 * cz;
   const V* __restrict__ ub = ubar + RC.off * NDOF;
   V acc[NDOF];
 #pragma unroll
   for (int a = 0; a < NDOF; ++a) acc[a] = (V)0;
   if constexpr (STORED) {
     const double* __restrict__ wv = pw + (RF.off + li) * 8;
-    const int bx = min(cx, RC.ex - 2), by = min(cy, RC.ey - 2), bz = RC.ez > 1 ? min(cz, RC.ez - 2) : 0;
+    const int bx = min(x / 3, RC.ex - 2), by = min(y / 3, RC.ey - 2), bz = RC.ez > 1 ? min(z / 3, RC.ez - 2) : 0;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const double wt = wv[s];
@@ -473,15 +487,21 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView F, LevelView C
     u[RF.off + li] += acc[0];
     return;
   }
-  const int nz = (DIM == 3 && tz) ? 2 : 1, ny = ty ? 2 : 1, nx = tx ? 2 : 1;
+  const bool fdir = is_dirichlet(F, RF.ox + x, RF.oy + y, RF.oz + z);
+  int lx, ly, lz = 0;
+  double ax0, ax1, ay0, ay1, az0 = 1.0, az1 = 0.0;
+  bracket(x, RF.ex, RC.ex, lx, ax0, ax1);
+  bracket(y, RF.ey, RC.ey, ly, ay0, ay1);
+  if (DIM == 3) bracket(z, RF.ez, RC.ez, lz, az0, az1);
+  const int nx = ax1 != 0.0 ? 2 : 1, ny = ay1 != 0.0 ? 2 : 1, nz = az1 != 0.0 ? 2 : 1;
   for (int iz = 0; iz < nz; ++iz) {
-    const double wz = DIM == 3 ? w1(tz - 3 * iz) : 1.0;
+    const double wz = iz ? az1 : az0;
     for (int iy = 0; iy < ny; ++iy) {
-      const double wzy = wz * w1(ty - 3 * iy);
+      const double wzy = wz * (iy ? ay1 : ay0);
       for (int ix = 0; ix < nx; ++ix) {
-        const int X = cx + ix, Y = cy + iy, Z = cz + iz;
+        const int X = lx + ix, Y = ly + iy, Z = lz + iz;
         if (!fdir && is_dirichlet(C, RC.ox + X, RC.oy + Y, RC.oz + Z)) continue;
-        const V wt = (V)(wzy * w1(tx - 3 * ix));
+        const V wt = (V)(wzy * (ix ? ax1 : ax0));
         const int64_t ci = (int64_t)((Z * RC.ey + Y) * RC.ex + X) * NDOF;
 #pragma unroll
         for (int a = 0; a < NDOF; ++a) acc[a] += wt * ub[ci + a];
@@ -524,11 +544,13 @@ void launch_prolong_add(const Level& F, const Level& C, bool lowp, const void* u
 
 // ------------------------------------------------------------------ RAP
 // Per-region Galerkin product [[Abar]] = P^T A^(k) P, one thread per coarse node C:
-// Abar(C, C+o) = sum_{t, s} P(3C+t, C) A(3C+t, s) P(3C+t+s, C+o), with the fine node 3C+t within
-// two cells of C and t+s-3o within two cells per axis; blocks of NDOF x NDOF coefficients share
-// the scalar weights.  Accumulators live in LDS (one column per thread).  Dirichlet reading: a
-// Dirichlet coarse row only collects Dirichlet fine nodes; entries of a free row towards
-// Dirichlet coarse nodes are zero.
+// Abar(C, C') = sum_{f, s} P(f, C) A(f, f+s) P(f+s, C') over the fine nodes f in the coarse
+// intervals on either side of C (at most two fine cells per side) and their stencil neighbours
+// f+s, whose coarse intervals give C' within one coarse node of C per axis (the coarse stencil
+// keeps 27 points); blocks of NDOF x NDOF coefficients share the scalar weights.  Accumulators
+// live in LDS (one column per thread).  Dirichlet reading: a Dirichlet coarse row only collects
+// Dirichlet fine nodes; entries of a free row towards Dirichlet coarse nodes are zero.  STORED
+// weights come from the fine nodes' records (rate-3 lattice, extents 3^k + 1).
 template <int NPTSF, int DIM, int NDOF, int BS, bool STORED>
 __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const double* __restrict__ coefF,
                                             double* __restrict__ coefC, const double* __restrict__ pw,
@@ -548,19 +570,24 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
   int X, Y, Z;
   decompose(RC, li, X, Y, Z);
   const bool cdir = is_dirichlet(C, RC.ox + X, RC.oy + Y, RC.oz + Z);
+  const int px = coarse_pos(X, RF.ex), py = coarse_pos(Y, RF.ey), pz = DIM == 3 ? coarse_pos(Z, RF.ez) : 0;
+  int mxl, mxr, myl, myr, mzl = 0, mzr = 0;
+  coarse_spans(X, RF.ex, RC.ex, mxl, mxr);
+  coarse_spans(Y, RF.ey, RC.ey, myl, myr);
+  if (DIM == 3) coarse_spans(Z, RF.ez, RC.ez, mzl, mzr);
   const int tzlo = DIM == 3 ? -2 : 0, tzhi = DIM == 3 ? 2 : 0;
   for (int tz = tzlo; tz <= tzhi; ++tz) {
-    const int fz = 3 * Z + tz;
+    const int fz = pz + tz;
     if ((unsigned)fz >= (unsigned)RF.ez) continue;
     for (int ty = -2; ty <= 2; ++ty) {
-      const int fy = 3 * Y + ty;
+      const int fy = py + ty;
       if ((unsigned)fy >= (unsigned)RF.ey) continue;
       for (int tx = -2; tx <= 2; ++tx) {
-        const int fx = 3 * X + tx;
+        const int fx = px + tx;
         if ((unsigned)fx >= (unsigned)RF.ex) continue;
         if (cdir && !is_dirichlet(F, RF.ox + fx, RF.oy + fy, RF.oz + fz)) continue;
         const double wf = STORED ? rw[coef_index(RC.off + li, (tz + 2) * 25 + (ty + 2) * 5 + tx + 2, 125)]
-                                 : (DIM == 3 ? w1(tz) : 1.0) * w1(ty) * w1(tx);
+                                 : (DIM == 3 ? tap(tz, mzl, mzr) : 1.0) * tap(ty, myl, myr) * tap(tx, mxl, mxr);
         if (wf == 0.0) continue;
         const int64_t fi = RF.off + (fz * RF.ey + fy) * RF.ex + fx;
 #pragma unroll
@@ -575,27 +602,34 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
           if (!any) continue;
           int dx, dy, dz;
           stencil_offset<NPTSF>(s, dx, dy, dz);
-          const int ux = tx + dx, uy = ty + dy, uz = tz + dz;
-          const int oxl = ux <= -1 ? -1 : 0, oyl = uy <= -1 ? -1 : 0, ozl = uz <= -1 ? -1 : 0;
+          const int gx = fx + dx, gy = fy + dy, gz = fz + dz;
+          if ((unsigned)gx >= (unsigned)RF.ex || (unsigned)gy >= (unsigned)RF.ey || (unsigned)gz >= (unsigned)RF.ez)
+            continue;
+          // the coarse interval holding the neighbour, per axis: nodes C + o0, C + o0 + 1 (the
+          // neighbour lies within C's two intervals because f does and A couples adjacent nodes)
+          int oxl, oyl, ozl = 0;
+          double bx[2], by[2], bz[2] = {1.0, 0.0};
+          interval_weights(tx + dx, mxl, mxr, oxl, bx[0], bx[1]);
+          interval_weights(ty + dy, myl, myr, oyl, by[0], by[1]);
+          if (DIM == 3) interval_weights(tz + dz, mzl, mzr, ozl, bz[0], bz[1]);
+#pragma unroll
           for (int kz = 0; kz < (DIM == 3 ? 2 : 1); ++kz) {
-            const int oz = DIM == 3 ? ozl + kz : 0;
-            const double wz = DIM == 3 ? w1(uz - 3 * oz) : 1.0;
+            const int oz = ozl + kz;
+            const double wz = bz[kz];
             if (wz == 0.0) continue;
+#pragma unroll
             for (int ky = 0; ky < 2; ++ky) {
               const int oy = oyl + ky;
-              const double wy = w1(uy - 3 * oy);
+              const double wy = by[ky];
               if (wy == 0.0) continue;
+#pragma unroll
               for (int kx = 0; kx < 2; ++kx) {
                 const int ox = oxl + kx;
-                const double wx = w1(ux - 3 * ox);
+                const double wx = bx[kx];
                 if (wx == 0.0) continue;
                 const int oi = DIM == 3 ? (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1) : (oy + 1) * 3 + (ox + 1);
                 double wo = wz * wy * wx;
                 if constexpr (STORED) {
-                  const int gx = fx + dx, gy = fy + dy, gz = fz + dz;
-                  if ((unsigned)gx >= (unsigned)RF.ex || (unsigned)gy >= (unsigned)RF.ey ||
-                      (unsigned)gz >= (unsigned)RF.ez)
-                    continue;
                   wo = pweight(pw, RF, RC, gx, gy, gz, X + ox, Y + oy, Z + oz);
                   if (wo == 0.0) continue;
                 }

@@ -241,6 +241,53 @@ void build_level0(rmg_handle* h) {
   h->levels.push_back(L.release());
 }
 
+// Rate-3 coarsening of the region boxes (Section 3.2: each region's structured coarsening keeps
+// coarse points on its interface).  Along each axis a region keeps every third node from its
+// first one and its last node, (e + 1) / 3 + 1 nodes in all, so its last coarse interval spans 1,
+// 2 or 3 cells.  The composite coarse lattice along an axis is the union of these positions; it
+// must agree with each region's own positions on that region's range, so that co-located fine
+// interface nodes interpolate from the same coarse nodes in every region (RMG_ERR_SHAPE
+// otherwise).  Coarse origins index that lattice.  Extents 3^k + 1 at origins divisible by 3 give
+// every third composite node.
+void coarse_geometry(int dim, const std::vector<RegionGeo>& fine, std::vector<RegionGeo>& coarse, int comp[3]) {
+  const size_t nreg = fine.size();
+  coarse.assign(nreg, RegionGeo{});
+  auto ext = [](RegionGeo& R, int d) -> int& { return d == 0 ? R.ex : (d == 1 ? R.ey : R.ez); };
+  auto org = [](RegionGeo& R, int d) -> int& { return d == 0 ? R.ox : (d == 1 ? R.oy : R.oz); };
+  for (int d = 0; d < 3; ++d) {
+    if (d >= dim) {
+      for (RegionGeo& Q : coarse) {
+        ext(Q, d) = 1;
+        org(Q, d) = 0;
+      }
+      comp[d] = 1;
+      continue;
+    }
+    std::vector<int> lattice;
+    for (size_t k = 0; k < nreg; ++k) {
+      RegionGeo R = fine[k];
+      const int o = org(R, d), e = ext(R, d);
+      for (int p = 0; p < e - 1; p += 3) lattice.push_back(o + p);
+      lattice.push_back(o + e - 1);
+    }
+    std::sort(lattice.begin(), lattice.end());
+    lattice.erase(std::unique(lattice.begin(), lattice.end()), lattice.end());
+    for (size_t k = 0; k < nreg; ++k) {
+      RegionGeo R = fine[k];
+      const int o = org(R, d), e = ext(R, d), E = (e + 1) / 3 + 1;
+      const size_t i0 = (size_t)(std::lower_bound(lattice.begin(), lattice.end(), o) - lattice.begin());
+      bool same = i0 + E <= lattice.size();
+      for (int j = 0; same && j < E; ++j) same = lattice[i0 + j] == o + std::min(3 * j, e - 1);
+      RMG_REQUIRE(same, RMG_ERR_SHAPE,
+                  "coarse points of region " + std::to_string(k) + " disagree with its neighbours' along axis " +
+                      std::to_string(d));
+      org(coarse[k], d) = (int)i0;
+      ext(coarse[k], d) = E;
+    }
+    comp[d] = (int)lattice.size();
+  }
+}
+
 Level* make_coarse_level(const Level& F) {
   std::unique_ptr<Level> C(new Level());  // released to the caller once complete
   C->dim = F.dim;
@@ -248,22 +295,7 @@ Level* make_coarse_level(const Level& F) {
   C->npts = F.dim == 3 ? 27 : 9;
   C->ndof = F.ndof;
   C->mask = F.mask;
-  for (int d = 0; d < 3; ++d) {
-    const int n = F.comp[d];
-    C->comp[d] = (d < F.dim) ? (n - 1) / 3 + 1 : 1;
-  }
-  C->regs.resize(F.nreg);
-  for (int k = 0; k < F.nreg; ++k) {
-    const RegionGeo& R = F.regs[k];
-    RegionGeo& Q = C->regs[k];
-    Q.ex = (R.ex - 1) / 3 + 1;
-    Q.ey = (R.ey - 1) / 3 + 1;
-    Q.ez = F.dim == 3 ? (R.ez - 1) / 3 + 1 : 1;
-    Q.ox = R.ox / 3;
-    Q.oy = R.oy / 3;
-    Q.oz = R.oz / 3;
-    Q.pad = 0;
-  }
+  coarse_geometry(F.dim, F.regs, C->regs, C->comp);
   build_tables(*C);
   return C.release();
 }

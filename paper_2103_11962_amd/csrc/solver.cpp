@@ -322,15 +322,25 @@ static int build_levels(rmg_handle* h, bool stored) {
 void setup_hierarchy(rmg_handle* h) {
   const rmg_options& o = h->opt;
   Level* L0 = h->levels[0];
-  int64_t f = 1;
-  for (int l = 1; l < o.nlevels; ++l) f *= 3;
-  for (int k = 0; k < L0->nreg; ++k) {
-    const RegionGeo& R = L0->regs[k];
-    const int e[3] = {R.ex, R.ey, R.ez}, g[3] = {R.ox, R.oy, R.oz};
-    for (int d = 0; d < L0->dim; ++d)
-      RMG_REQUIRE((e[d] - 1) % f == 0 && g[d] % f == 0, RMG_ERR_SHAPE,
-                  "region " + std::to_string(k) + ": extent-1 and origin must be divisible by 3^(nlevels-1) = " +
-                      std::to_string(f));
+  if (o.hybrid || h->pmode != RMG_P_GEOMETRIC) {
+    // stored interpolation weights and the hybrid aggregation work on the uniform rate-3 lattice
+    int64_t f = 1;
+    for (int l = 1; l < o.nlevels; ++l) f *= 3;
+    for (int k = 0; k < L0->nreg; ++k) {
+      const RegionGeo& R = L0->regs[k];
+      const int e[3] = {R.ex, R.ey, R.ez}, g[3] = {R.ox, R.oy, R.oz};
+      for (int d = 0; d < L0->dim; ++d)
+        RMG_REQUIRE((e[d] - 1) % f == 0 && g[d] % f == 0, RMG_ERR_SHAPE,
+                    "region " + std::to_string(k) + ": extent-1 and origin must be divisible by 3^(nlevels-1) = " +
+                        std::to_string(f));
+    }
+  } else {  // every level's coarse lattice must agree across interfaces: check before building
+    std::vector<RegionGeo> fine = L0->regs, coarse;
+    int comp[3];
+    for (int l = 1; l < o.nlevels; ++l) {
+      coarse_geometry(L0->dim, fine, coarse, comp);
+      fine.swap(coarse);
+    }
   }
   h->p_used = RMG_P_GEOMETRIC;
   h->rho_learned = h->rho_geometric = -1.0;

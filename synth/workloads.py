@@ -29,6 +29,7 @@ __all__ = [
     "jump_coefficients",
     "mlp_params",
     "batched_extents",
+    "even_slabs",
     "dirichlet_nodes",
     "fd5_composite_stencil",
     "fd7_composite_stencil",
@@ -108,6 +109,17 @@ def batched_extents(seed: int = 0, counts=(8, 8, 4), choices=(28, 55, 82, 109)):
     return [list(rng.choice(np.asarray(choices), size=c)) for c in counts]
 
 
+def even_slabs(n: int, parts: int):
+    """Extents of ``parts`` slabs sharing end nodes that cover n nodes as evenly as possible
+    (the first slabs take the extra cells)."""
+    cells = n - 1
+    base = cells // parts
+    ext = [base + 1] * parts
+    for i in range(cells - base * parts):
+        ext[i] += 1
+    return ext
+
+
 def workload(name: str, seed: int = 0) -> Workload:
     """Named configurations.
 
@@ -118,6 +130,10 @@ def workload(name: str, seed: int = 0) -> Workload:
     ``c5``  3D Q1 diffusion with jump coefficients, 4x4x4 regions of 82^3.
     Small variants (``*_small``) keep the structure at sizes a pure NumPy code
     finishes in seconds.
+    ``table1_rect``  2D five-point, 700 x 720 nodes in 3x3 regions (extents 234 and 241/240, not
+    3^k + 1), 4 levels, one smoothing step.
+    ``uneven*``  region extents that are not 3^k + 1 (2D five-point, 3D Q1 Laplace, elasticity,
+    and an 8-region mesh with slab extents drawn from 11..31).
     """
     full = lambda dim: (1 << (2 * dim)) - 1  # noqa: E731  all faces Dirichlet
     if name == "c1":
@@ -153,11 +169,27 @@ def workload(name: str, seed: int = 0) -> Workload:
     if name == "c5_small":
         o, e = _uniform_layout(3, 2, 28)
         return Workload(name, 3, 1, o, e, full(3), 3, 3, "diffusion", h=1.0 / 54, seed=seed)
+    if name == "table1_rect":
+        o, e = tensor_layout([even_slabs(700, 3), even_slabs(720, 3)])
+        return Workload(name, 2, 1, o, e, full(2), 4, 1, "fd5", seed=seed)
+    if name == "uneven2d_small":
+        o, e = tensor_layout([[12, 17, 10], [16, 11]])
+        return Workload(name, 2, 1, o, e, full(2), 3, 2, "fd5", seed=seed)
+    if name == "uneven3d_small":
+        o, e = tensor_layout([[12, 8], [11, 7], [9, 13]])
+        return Workload(name, 3, 1, o, e, full(3), 3, 3, "laplace", h=1.0 / 18, seed=seed)
+    if name == "uneven3e_small":
+        o, e = tensor_layout([[8, 6], [7, 6], [6, 8]])
+        return Workload(name, 3, 3, o, e, full(3), 3, 3, "elasticity", h=1.0 / 12, seed=seed)
+    if name == "uneven_c4_small":
+        o, e = tensor_layout(batched_extents(seed, counts=(2, 2, 2), choices=tuple(range(11, 32))))
+        return Workload(name, 3, 1, o, e, full(3), 4, 3, "laplace", seed=seed)
     raise KeyError(name)
 
 
 WORKLOADS = ("c1", "c1_small", "c2", "c2_small", "c2_mid", "c3", "c3_small",
-             "c4", "c4_small", "c5", "c5_small")
+             "c4", "c4_small", "c5", "c5_small", "table1_rect", "uneven2d_small", "uneven3d_small",
+             "uneven3e_small", "uneven_c4_small")
 
 
 def dirichlet_nodes(shape_xyz, mask: int) -> np.ndarray:

@@ -403,3 +403,21 @@ def test_trained_network_gains_over_geometric(hip_device):
     assert info["rho_learned"] < rho_g
     g.close()
     h.close()
+
+
+def test_stored_weights_need_the_uniform_lattice(hip_device):
+    """Stored interpolation weights are kept per canonical rate-3 cell, so they need region extents
+    - 1 and origins divisible by 3^(nlevels-1); other extents are RMG_ERR_SHAPE (the geometric
+    interpolation coarsens them)."""
+    from paper_2103_11962_amd import regmg
+
+    w = synth.workload("uneven3d_small")
+    h = harness.gpu_problem(w, setup=False)
+    n = int(np.prod(w.extents, axis=1).sum())
+    h.set_prolongator_weights(np.zeros((n, 8)))
+    with pytest.raises(regmg.RmgError) as e:
+        h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree)
+    assert e.value.status == "RMG_ERR_SHAPE"
+    h.set_prolongator_weights(None)
+    h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree)
+    h.close()

@@ -95,3 +95,45 @@ def test_mg_solver_reports_maxit(hip_device):
     out = h.solve(b, x, rtol=1e-14, maxit=2, method="mg", raise_on_fail=False)
     assert out["status"] == "RMG_ERR_NOT_CONVERGED" and out["iterations"] == 2 and len(out["history"]) == 3
     h.close()
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "chebyshev"])
+def test_table1_rectangular_histories(hip_device, smoother):
+    """Table 1(b): 700 x 720 nodes in 3x3 regions (extents 234 and 241/240, not 3^k + 1), 4 levels,
+    one smoothing step before and after the coarse correction, MG as a solver to 1e-12.  The GPU's
+    regional history is the oracle's regional history cycle by cycle.  Serial structured MG on the
+    whole mesh coarsens by the same rule on a different lattice (every third node of 700/720
+    instead of the union of the regions' points), so its history is close, not identical, and it
+    stops at the same cycle."""
+    import torch
+
+    from oracle import assembly, composite, regional
+    from oracle.regions import Layout
+
+    w = synth.workload("table1_rect")
+    jac = smoother == "jacobi"
+    lay, levels, opt = harness.oracle_problem(w, **(dict(smoother="jacobi", jacobi_omega=0.6) if jac else {}))
+    b = synth.rhs(w)
+    print(f"[table1-rect] {smoother}: GPU solve", flush=True)
+    h = harness.gpu_problem(w, **(dict(smoother=1, jacobi_omega=0.6) if jac else {}))
+    x = torch.zeros(lay.n_composite, dtype=torch.float64, device="cuda:0")
+    out = h.solve(harness.to_dev(b), x, rtol=1e-12, maxit=300, method="mg")
+    assert out["converged"]
+    n = out["iterations"]
+    xr, hr = regional.stationary(levels, lay.to_regional(b), lay.zeros_regional(), opt, n)
+    hr = np.asarray(hr)
+    hg = np.asarray(out["history"][: n + 1])
+    np.testing.assert_allclose(hg[:30], hr[:30], rtol=1e-9)
+    big = hr > 1e-9
+    np.testing.assert_allclose(hg[big], hr[big], rtol=1e-6)
+    assert hr[-1] <= 1e-12 and hr[-2] > 1e-12  # same stopping cycle
+    assert rel(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1)) < 1e-10
+    h.close()
+    one = Layout(2, [[0, 0]], [list(w.composite_shape_xyz)], w.dirichlet_mask)
+    sl = composite.setup(one, assembly.composite_fd5(one), opt)
+    hs = np.asarray(composite.stationary(sl, b.reshape(-1), np.zeros(b.size), opt, n + 2)[1])
+    ns = int(np.argmax(hs <= 1e-12))
+    d = np.abs(hr[1:] - hs[1:n + 1]) / hs[1:n + 1]
+    print(f"[table1-rect] {smoother}: {n} cycles regional, {ns} structured, histories within {d.max():.3%}",
+          flush=True)
+    assert abs(ns - n) <= 1 and 1e-6 < d.max() < 0.25

@@ -17,7 +17,10 @@ pytestmark = pytest.mark.gpu
 # (workload, 3D stencil kernel): 1 = node-parallel, 2 = 2.5D plane-marching tiles, 3 = persistent tiles
 SMALL = [("c1_small", 0), ("c2_small", 1), ("c2_small", 2), ("c4_small", 1), ("c4_small", 2),
          ("c5_small", 1), ("c5_small", 2), ("c1", 0), ("c2_mid", 1), ("c2_mid", 2), ("c3_small", 0),
-         ("c4_small", 3), ("c2_mid", 3)]
+         ("c4_small", 3), ("c2_mid", 3),
+         # region extents that are not 3^k + 1: shortened last coarse intervals on every level
+         ("uneven2d_small", 0), ("uneven3d_small", 1), ("uneven3d_small", 2), ("uneven3d_small", 3),
+         ("uneven3e_small", 0), ("uneven_c4_small", 2)]
 IDS = [f"{n}-k{k}" for n, k in SMALL]
 
 
@@ -200,20 +203,28 @@ def test_errors_are_reported(hip_device):
         h.setup_hierarchy(nlevels=3, cheb_degree=2)
     assert e.value.status == "RMG_ERR_NOT_SETUP"
     h.set_composite_stencil(5, synth.fd5_composite_stencil(w))
-    with pytest.raises(regmg.RmgError) as e:
-        h.setup_hierarchy(nlevels=4, cheb_degree=2)  # 10 nodes cannot be coarsened three times
-    assert e.value.status == "RMG_ERR_SHAPE"
+    h.setup_hierarchy(nlevels=4, cheb_degree=2)  # 10 -> 4 -> 2 -> 2 nodes per region and axis
     bad = synth.fd5_composite_stencil(w)
     bad[2, 50] = np.nan
     with pytest.raises(regmg.RmgError) as e:
         h.set_composite_stencil(5, bad)
     assert e.value.status == "RMG_ERR_NUMERIC"
     h.close()
+    # bricks: region 0 spans x 0..9 (coarse x 0 3 6 9) above regions spanning x 0..4 (0 3 4) and
+    # 4..9 (4 7 9); their shared interface would interpolate from different coarse nodes
+    h = regmg.Handle(0)
+    h.build_regions(3, 1, [[10, 5, 4], [5, 6, 4], [6, 6, 4]], [[0, 0, 0], [0, 4, 0], [4, 4, 0]], 63)
+    h.assemble_q1(regmg.PDE_LAPLACE, 0.1)
+    with pytest.raises(regmg.RmgError) as e:
+        h.setup_hierarchy(nlevels=2, cheb_degree=2)
+    assert e.value.status == "RMG_ERR_SHAPE" and "disagree" in str(e.value)
+    h.close()
 
 
 # ---------------------------------------------------------------- low-precision V-cycle
 MIXED = [("c2_small", 1, 1), ("c2_small", 2, 2), ("c2_mid", 1, 2), ("c2_mid", 2, 1), ("c3_small", 1, 0),
-         ("c3_small", 2, 0), ("c4_small", 2, 2), ("c5_small", 1, 2)]
+         ("c3_small", 2, 0), ("c4_small", 2, 2), ("c5_small", 1, 2), ("uneven3d_small", 1, 2),
+         ("uneven3e_small", 1, 0), ("uneven_c4_small", 2, 3)]
 
 
 @pytest.mark.parametrize("name,precision,kernel", MIXED, ids=[f"{n}-p{p}-k{k}" for n, p, k in MIXED])

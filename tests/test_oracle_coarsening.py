@@ -20,16 +20,6 @@ from oracle import assembly, composite, regional, transfer
 from oracle.regions import Layout, coarse_positions
 
 
-def split(n, parts):
-    """Extents of `parts` slabs sharing end nodes that cover n nodes as evenly as possible."""
-    iv = n - 1
-    base = iv // parts
-    ext = [base + 1] * parts
-    for i in range(iv - base * parts):
-        ext[i] += 1
-    return ext
-
-
 def test_coarse_positions_rule():
     expect = {2: [0, 1], 3: [0, 2], 4: [0, 3], 5: [0, 3, 4], 6: [0, 3, 5], 7: [0, 3, 6], 11: [0, 3, 6, 9, 10],
               234: list(range(0, 232, 3)) + [233]}
@@ -150,7 +140,7 @@ def test_table1_rectangular_structure(smoother, kw):
     implicit coarse lattice (Theorem), and close to serial structured MG, which coarsens the whole
     mesh by the same rule but on a different lattice (same number of cycles, histories within 25%)."""
     nx, ny = 100, 106
-    o, e = synth.tensor_layout([split(nx, 3), split(ny, 3)])
+    o, e = synth.tensor_layout([synth.even_slabs(nx, 3), synth.even_slabs(ny, 3)])
     lay = Layout(2, o, e, 15)
     one = Layout(2, [[0, 0]], [[nx, ny]], 15)
     w = synth.Workload("rect", 2, 1, o, e, 15, 4, 1, "fd5", seed=0)
