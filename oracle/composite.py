@@ -16,7 +16,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import assembly, rng, transfer
+from . import amg, assembly, rng, transfer
 from .regional import Options
 from .regions import Layout
 
@@ -28,6 +28,7 @@ class CLevel:
     dinv: np.ndarray = None
     lam: float = None
     P: sp.csr_matrix = None
+    amg: list = None  # coarsest level with the AMG coarse solver
 
 
 def start_vector(lay: Layout, level: int, seed: int):
@@ -54,6 +55,8 @@ def setup(lay0: Layout, A0, opt: Options, lams=None):
         L = CLevel(lay, A)
         levels.append(L)
         if l == opt.nlevels - 1:
+            if opt.coarse_amg:
+                L.amg = amg.setup(A, ~lay.dirichlet.reshape(-1), opt.amg_coarse_size)
             break
         L.dinv = 1.0 / A.diagonal()
         if opt.smoother == "chebyshev":
@@ -123,6 +126,8 @@ def smooth(L: CLevel, u, b, r, opt: Options, post=False):
 def vcycle(levels, b, opt: Options, l=0):
     L = levels[l]
     if l == len(levels) - 1:
+        if L.amg is not None:
+            return amg.vcycle(L.amg, b)
         return np.linalg.solve(L.A.toarray(), b)
     u = smooth(L, np.zeros_like(b), b, b, opt)
     r = b - L.A @ u

@@ -35,7 +35,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import assembly, rng, transfer
+from . import amg, assembly, rng, transfer
 from .regions import Layout
 
 
@@ -59,6 +59,7 @@ class Level:
     lam: float = None
     P: list = None  # region prolongators to the next level
     Abar: np.ndarray = None  # coarsest composite operator (dense)
+    amg: list = None  # coarsest level with the AMG coarse solver: its levels (amg.setup)
     extra: dict = field(default_factory=dict)
 
     def matvec(self, x):
@@ -82,6 +83,8 @@ class Options:
     smoother: str = "chebyshev"  # or "jacobi", "gs", "sgs", "symgs"
     gamma: int = 1  # coarse-level cycles per visit: 1 V-cycle, 2 W-cycle
     jacobi_omega: float = 0.6
+    coarse_amg: bool = False  # coarse solve: one AMG V-cycle on Abar instead of a direct solve
+    amg_coarse_size: int = 2000  # the AMG's directly solved level has at most this many rows
 
 
 def composite_diagonal(lay: Layout, coefs):
@@ -127,7 +130,13 @@ def setup(lay0: Layout, coefs0, opt: Options, P0=None):
         L = Level(lay, coefs)
         levels.append(L)
         if l == opt.nlevels - 1:
-            L.Abar = coarse_composite(lay, coefs)
+            if opt.coarse_amg:  # Section 3.5: an AMG V-cycle on Abar replaces the direct solver
+                if lay.ndof != 1:
+                    raise ValueError("the AMG coarse solver handles scalar problems")
+                L.amg = amg.setup(assembly.assemble_from_regions(lay, coefs), ~lay.dirichlet.reshape(-1),
+                                  opt.amg_coarse_size)
+            else:
+                L.Abar = coarse_composite(lay, coefs)
             break
         L.dinv = [1.0 / d for d in composite_diagonal(lay, coefs)]
         if opt.smoother == "chebyshev":
@@ -237,7 +246,7 @@ def smooth(L, u, b, r, opt, post=False):
 def coarse_solve(L: Level, w):
     lay = L.lay
     wbar = lay.to_composite_owner(w).reshape(-1)
-    ubar = np.linalg.solve(L.Abar, wbar)
+    ubar = amg.vcycle(L.amg, wbar) if L.amg is not None else np.linalg.solve(L.Abar, wbar)
     shp = lay.shape + ((lay.ndof,) if lay.ndof > 1 else ())
     return lay.to_regional(ubar.reshape(shp))
 
