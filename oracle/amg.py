@@ -15,8 +15,11 @@ Hierarchy (smoothed aggregation, after the SA-AMG the section cites):
   (Gershgorin's bound on lambda_max(D^-1 A), so no random start vector is needed);
 * coarse operator P^T A P; coarsening stops at the first level with at most ``coarse_size`` rows,
   or when a level no longer shrinks, and that level is solved directly;
-* cycle: a V-cycle with zero initial guess, one forward Gauss-Seidel sweep before the coarse
-  correction and one backward sweep after it, so the cycle is a symmetric operator.
+* smoother: the region levels' degree-K Chebyshev recurrence (Algorithm 2 as read for the region
+  levels) on the interval [rho / eta, rho] of D^-1 A, the Gershgorin bound rho standing in for the
+  power method's estimate (it bounds lambda_max from above, so no boost factor);
+* cycle: a V-cycle with zero initial guess, the same polynomial before and after the coarse
+  correction, so the cycle is a symmetric operator.
 """
 from __future__ import annotations
 
@@ -24,7 +27,6 @@ from dataclasses import dataclass
 
 import numpy as np
 import scipy.sparse as sp
-import scipy.sparse.linalg as spla
 
 from .hybrid import HRegion, aggregate_region
 
@@ -36,6 +38,9 @@ class AmgLevel:
     agg: np.ndarray = None      # coarse row of every row, -1 if not aggregated
     P: sp.csr_matrix = None     # smoothed prolongator to the next level
     omega: float = 0.0
+    rho: float = 0.0            # Gershgorin bound on lambda_max(D^-1 A)
+    degree: int = 2             # Chebyshev degree
+    eta: float = 20.0           # lambda_max / lambda_min of the smoothing interval
     Adense: np.ndarray = None   # coarsest level
 
 
@@ -60,20 +65,21 @@ def tentative(agg: np.ndarray) -> sp.csr_matrix:
     return sp.csr_matrix((np.ones(rows.size), (rows, agg[rows])), shape=(agg.size, nc))
 
 
-def smoothing_weight(A: sp.csr_matrix) -> float:
-    """omega = 4 / (3 rho), rho = max_i sum_j |a_ij| / a_ii."""
+def gershgorin(A: sp.csr_matrix) -> float:
+    """rho = max_i sum_j |a_ij| / a_ii >= lambda_max(D^-1 A)."""
     d = A.diagonal()
     rowabs = np.asarray(abs(A).sum(axis=1)).ravel()
-    return 4.0 / (3.0 * float(np.max(rowabs / d)))
+    return float(np.max(rowabs / d))
 
 
-def setup(A: sp.csr_matrix, free: np.ndarray, coarse_size: int = 2000, max_levels: int = 20):
+def setup(A: sp.csr_matrix, free: np.ndarray, coarse_size: int = 2000, degree: int = 2, eta: float = 20.0,
+          max_levels: int = 20):
     """AMG levels of A; the last one is solved directly."""
     levels = []
     A = sp.csr_matrix(A)
     free = np.asarray(free, dtype=bool)
     for _ in range(max_levels - 1):
-        L = AmgLevel(A, free)
+        L = AmgLevel(A, free, degree=degree, eta=eta)
         levels.append(L)
         if A.shape[0] <= coarse_size:
             break
@@ -82,23 +88,37 @@ def setup(A: sp.csr_matrix, free: np.ndarray, coarse_size: int = 2000, max_level
         if T.shape[1] == 0 or T.shape[1] >= A.shape[0]:
             break
         L.agg = agg
-        L.omega = smoothing_weight(A)
+        L.rho = gershgorin(A)
+        L.omega = 4.0 / (3.0 * L.rho)
         Dinv = sp.diags(1.0 / A.diagonal())
         L.P = sp.csr_matrix(T - L.omega * (Dinv @ (A @ T)))
         A = sp.csr_matrix(L.P.T @ A @ L.P)
         free = np.ones(A.shape[0], dtype=bool)
     else:
-        levels.append(AmgLevel(A, free))
+        levels.append(AmgLevel(A, free, degree=degree, eta=eta))
     last = levels[-1]
     last.agg, last.P = None, None
     last.Adense = last.A.toarray()
     return levels
 
 
-def gs(A: sp.csr_matrix, r: np.ndarray, backward: bool) -> np.ndarray:
-    """(D + L)^-1 r (forward) or (D + U)^-1 r (backward)."""
-    M = sp.csr_matrix(sp.triu(A) if backward else sp.tril(A))
-    return spla.spsolve_triangular(M, r, lower=not backward)
+def chebyshev(L: AmgLevel, u, b, r):
+    """Degree-K Chebyshev smoothing on [rho / eta, rho]; r = b - A u on entry."""
+    alpha = L.rho / L.eta
+    beta = L.rho
+    theta = 0.5 * (alpha + beta)
+    delta = 2.0 / (beta - alpha)
+    rho = 1.0 / (theta * delta)
+    dinv = 1.0 / L.A.diagonal()
+    d = (1.0 / theta) * (dinv * r)
+    u = u + d
+    for _ in range(L.degree - 1):
+        r = b - L.A @ u
+        rho_old = rho
+        rho = 1.0 / (2.0 * theta * delta - rho_old)
+        d = (rho * rho_old) * d + (2.0 * rho * delta) * (dinv * r)
+        u = u + d
+    return u
 
 
 def vcycle(levels, b: np.ndarray, l: int = 0) -> np.ndarray:
@@ -106,7 +126,7 @@ def vcycle(levels, b: np.ndarray, l: int = 0) -> np.ndarray:
     L = levels[l]
     if L.P is None:
         return np.linalg.solve(L.Adense, b)
-    u = gs(L.A, b, backward=False)
+    u = chebyshev(L, np.zeros_like(b), b, b)
     r = b - L.A @ u
     u = u + L.P @ vcycle(levels, L.P.T @ r, l + 1)
-    return u + gs(L.A, b - L.A @ u, backward=True)
+    return chebyshev(L, u, b, b - L.A @ u)

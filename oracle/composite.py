@@ -56,7 +56,7 @@ def setup(lay0: Layout, A0, opt: Options, lams=None):
         levels.append(L)
         if l == opt.nlevels - 1:
             if opt.coarse_amg:
-                L.amg = amg.setup(A, ~lay.dirichlet.reshape(-1), opt.amg_coarse_size)
+                L.amg = amg.setup(A, ~lay.dirichlet.reshape(-1), opt.amg_coarse_size, opt.degree, opt.eig_ratio)
             break
         L.dinv = 1.0 / A.diagonal()
         if opt.smoother == "chebyshev":

@@ -134,7 +134,7 @@ def setup(lay0: Layout, coefs0, opt: Options, P0=None):
                 if lay.ndof != 1:
                     raise ValueError("the AMG coarse solver handles scalar problems")
                 L.amg = amg.setup(assembly.assemble_from_regions(lay, coefs), ~lay.dirichlet.reshape(-1),
-                                  opt.amg_coarse_size)
+                                  opt.amg_coarse_size, opt.degree, opt.eig_ratio)
             else:
                 L.Abar = coarse_composite(lay, coefs)
             break

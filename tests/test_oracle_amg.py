@@ -5,8 +5,8 @@ cites).
 Pinned by a hand-worked 1D example (aggregates, smoothing weight, smoothed prolongator and coarse
 operator written out as fractions), the constant preserved by P on rows where A 1 = 0 (closed
 form of the smoothing step), aggregates partitioning the free rows, the two-level cycle against
-its error propagator composed from dense matrices, symmetry of the multilevel cycle, the direct
-solve it reduces to, and the Theorem: the region cycle with the AMG coarse solver equals the
+its error propagator composed from dense matrices and the closed-form Chebyshev polynomial,
+symmetry of the multilevel cycle, the direct solve it reduces to, and the Theorem: the region cycle with the AMG coarse solver equals the
 composite cycle with the same coarse solver.
 """
 from fractions import Fraction as F
@@ -83,19 +83,36 @@ def test_smoothed_prolongator_keeps_constants():
     np.testing.assert_allclose((P @ ones)[rows], 1.0, atol=1e-14)
 
 
-def test_two_level_cycle_is_its_error_propagator():
-    """With an exact coarse solve, V(b) = (I - E) A^-1 b with E = (I - (D+U)^-1 A)(I - P Ac^-1 P^T A)
-    (I - (D+L)^-1 A), composed here from dense matrices."""
+def chebyshev_matrix(Ad, K, rho, eta):
+    """p_K(D^-1 A) = T_K((theta I - D^-1 A) / h) / T_K(theta / h), theta, h the centre and half
+    width of [rho / eta, rho], T_K by its three-term recurrence (the polynomial the smoother's
+    error follows)."""
+    n = Ad.shape[0]
+    alpha, beta = rho / eta, rho
+    theta, h = 0.5 * (alpha + beta), 0.5 * (beta - alpha)
+    X = (theta * np.eye(n) - Ad / np.diag(Ad)[:, None]) / h
+    Tm, T = np.eye(n), X
+    tm, t = 1.0, theta / h
+    for _ in range(K - 1):
+        Tm, T = T, 2.0 * X @ T - Tm
+        tm, t = t, 2.0 * (theta / h) * t - tm
+    return (np.eye(n) if K == 0 else T) / (1.0 if K == 0 else t)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_two_level_cycle_is_its_error_propagator(K):
+    """With an exact coarse solve, V(b) = (I - E) A^-1 b with E = S (I - P Ac^-1 P^T A) S and
+    S = p_K(D^-1 A) the Chebyshev polynomial, composed here from dense matrices."""
     lay, A, free = lattice_laplace(13)
-    lv = amg.setup(A, free, coarse_size=60)
+    lv = amg.setup(A, free, coarse_size=60, degree=K)
     assert len(lv) == 2
     Ad = A.toarray()
     n = Ad.shape[0]
     I = np.eye(n)
     P = lv[0].P.toarray()
     Ac = P.T @ Ad @ P
-    Mf, Mb = np.tril(Ad), np.triu(Ad)
-    E = (I - np.linalg.solve(Mb, Ad)) @ (I - P @ np.linalg.solve(Ac, P.T @ Ad)) @ (I - np.linalg.solve(Mf, Ad))
+    S = chebyshev_matrix(Ad, K, amg.gershgorin(A), 20.0)
+    E = S @ (I - P @ np.linalg.solve(Ac, P.T @ Ad)) @ S
     B = np.random.default_rng(1).standard_normal((n, 3))
     for j in range(3):
         expect = (I - E) @ np.linalg.solve(Ad, B[:, j])
