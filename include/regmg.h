@@ -125,6 +125,16 @@ typedef struct {
                          transfers on stencil levels */
   int cycle_gamma;    /* coarse cycles per visit of a level: 1 (default) V-cycle, 2 W-cycle
                          (hybrid hierarchy only) */
+  int coarse_amg;     /* coarse solver of the region hierarchy (Section 3.5): 0 (default) the
+                         dense inverse of Abar (at most 20,000 composite dofs); 1: one V-cycle of
+                         smoothed-aggregation AMG on Abar (scalar problems, geometric region
+                         hierarchy): staged plain aggregation of the free rows (roots, joins,
+                         leftovers), P = (I - omega D^-1 A) T with omega = 4 / (3 rho) and rho the
+                         Gershgorin bound max_i sum_j |a_ij| / a_ii, coarse operators P^T A P, the
+                         degree-cheb_degree Chebyshev smoother on [rho / eig_ratio, rho] before and
+                         after each coarse correction, and a dense inverse on the first AMG level
+                         with at most amg_coarse_size rows */
+  int amg_coarse_size; /* rows of the directly solved AMG level, in [1, 20000] (default 2000) */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -301,6 +311,19 @@ rmg_status rmg_hybrid_composite_ids(rmg_handle* h, int level, int64_t* comp);
 /* The region matrices of level `level` as one block-diagonal CSR matrix over the regional rows
    (host arrays: rowptr n_regional + 1, colind and values nnz; columns ascending per row). */
 rmg_status rmg_hybrid_matrix(rmg_handle* h, int level, int64_t* rowptr, int32_t* colind, double* values);
+
+/* Levels of the AMG coarse solver of the current hierarchy (coarse_amg = 1), 0 without one.  Level
+ * 0 is the coarsest region level's composite operator Abar (rows in composite node order). */
+rmg_status rmg_amg_levels(rmg_handle* h, int* nlevels);
+
+/* Rows of AMG level `level`, nonzeros of its matrix, nonzeros of its prolongator to the next level
+ * (0 on the directly solved last level).  RMG_ERR_ARG for a level out of range. */
+rmg_status rmg_amg_level_info(rmg_handle* h, int level, int64_t* n, int64_t* nnz_a, int64_t* nnz_p);
+
+/* The level's matrix (which = 0, n x n) or prolongator to the next level (which = 1, n x n_next)
+ * in CSR with ascending columns, copied into caller host arrays sized by rmg_amg_level_info
+ * (rowptr: n + 1 entries). */
+rmg_status rmg_amg_matrix(rmg_handle* h, int level, int which, int64_t* rowptr, int32_t* colind, double* values);
 
 /* ---- kernel timing (for roofline measurements) ---- */
 

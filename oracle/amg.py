@@ -7,8 +7,9 @@ Hierarchy (smoothed aggregation, after the SA-AMG the section cites):
 
 * aggregates: the staged plain aggregation of the hybrid section (hybrid.aggregate_region) without
   its interface stage, since one composite matrix has no interfaces: roots, joins, leftovers on the
-  graph of nonzero off-diagonal couplings between free rows.  Dirichlet rows are not aggregated.
-  Coarse rows are numbered by the smallest row of their aggregate;
+  graph of couplings |a_ij| > 1e-12 sqrt(a_ii a_jj) between free rows (the rounding residue of a
+  Galerkin product, which depends on the order of its sums, is no coupling).  Dirichlet rows are
+  not aggregated.  Coarse rows are numbered by the smallest row of their aggregate;
 * tentative prolongator T: a 1 in the column of its aggregate for every aggregated row (the
   constant near-null space of a scalar problem);
 * smoothed prolongator P = (I - omega D^-1 A) T, omega = 4 / (3 rho), rho = max_i sum_j |a_ij| / a_ii
@@ -44,10 +45,17 @@ class AmgLevel:
     Adense: np.ndarray = None   # coarsest level
 
 
+STRENGTH = 1e-12
+
+
 def aggregates(A: sp.csr_matrix, free: np.ndarray) -> np.ndarray:
     """Coarse row of every row (-1: not aggregated), numbered by each aggregate's smallest row."""
     n = A.shape[0]
-    R = HRegion(sp.csr_matrix(A), np.arange(n), np.full((n, 1), -1), np.asarray(free, dtype=bool))
+    C = sp.coo_matrix(A)
+    d = np.abs(A.diagonal())
+    keep = (C.row == C.col) | (np.abs(C.data) > STRENGTH * np.sqrt(d[C.row] * d[C.col]))
+    G = sp.csr_matrix((C.data[keep], (C.row[keep], C.col[keep])), shape=A.shape)
+    R = HRegion(G, np.arange(n), np.full((n, 1), -1), np.asarray(free, dtype=bool))
     lab, _ = aggregate_region(R, True, np.zeros(n, dtype=bool), (n, 1, 1), 0)
     out = np.full(n, -1, dtype=np.int64)
     number = {}

@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_lib", "libregmg.so")
 
-SOURCES = ["kernels.hip", "kernels_stencil.hip", "kernels_gs.hip", "kernels_hybrid.hip", "mlp.hip", "planner.cpp",
-           "solver.cpp", "learned.cpp", "hybrid.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "kernels_stencil.hip", "kernels_gs.hip", "kernels_hybrid.hip", "kernels_amg.hip", "mlp.hip",
+           "planner.cpp", "solver.cpp", "learned.cpp", "hybrid.cpp", "amg.cpp", "api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",

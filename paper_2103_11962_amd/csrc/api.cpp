@@ -109,6 +109,7 @@ void rmg_handle::drop_graphs() {
 rmg_handle::~rmg_handle() {
   drop_graphs();
   rmg::hybrid_destroy(this);
+  rmg::amg_destroy(this);
   if (gstream) (void)hipStreamDestroy(gstream);
   for (Level* L : levels) delete L;
   levels.clear();
@@ -154,6 +155,8 @@ void rmg_options_default(rmg_options* o) {
   o->judge_cycles = 10;
   o->hybrid = 0;
   o->cycle_gamma = 1;
+  o->coarse_amg = 0;
+  o->amg_coarse_size = 2000;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -202,6 +205,7 @@ rmg_status rmg_build_regions(rmg_handle* h, int dim, int ndof, int nreg, const i
   RMG_REQUIRE(mask < (1u << (2 * dim)), RMG_ERR_ARG, "dirichlet mask has bits beyond 2*dim");
   h->have_regions = h->have_operator = h->have_hierarchy = false;
   hybrid_destroy(h);
+  amg_destroy(h);
   h->region_kind.clear();
   h->user_pw.release();
   h->logc.release();
@@ -486,6 +490,12 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->smoother == 0 || (opt->jacobi_omega > 0.0 && opt->jacobi_omega < 2.0), RMG_ERR_ARG,
               "jacobi_omega must lie in (0, 2)");
   RMG_REQUIRE(opt->judge_cycles >= 0 && opt->judge_cycles <= 1000, RMG_ERR_ARG, "judge_cycles must be in [0, 1000]");
+  RMG_REQUIRE(opt->coarse_amg == 0 || opt->coarse_amg == 1, RMG_ERR_ARG, "coarse_amg must be 0 or 1");
+  RMG_REQUIRE(!opt->coarse_amg || (opt->amg_coarse_size >= 1 && opt->amg_coarse_size <= 20000), RMG_ERR_ARG,
+              "amg_coarse_size must be in [1, 20000]");
+  RMG_REQUIRE(!opt->coarse_amg || !opt->hybrid, RMG_ERR_ARG,
+              "the AMG coarse solver belongs to the geometric region hierarchy (not the hybrid one)");
+  RMG_REQUIRE(!opt->coarse_amg || h->ndof == 1, RMG_ERR_ARG, "the AMG coarse solver handles scalar problems");
   h->opt = *opt;
   h->autotune_cache = opt->autotune_cache ? std::string(opt->autotune_cache) : std::string();
   h->opt.autotune_cache = nullptr;  // the caller's string is borrowed for this call only
@@ -697,6 +707,7 @@ rmg_status rmg_get_coarse_matrix(rmg_handle* h, double* host_out) {
   require_hierarchy(h);
   RMG_REQUIRE(host_out, RMG_ERR_ARG, "null output");
   Level& L = *h->levels.back();
+  RMG_REQUIRE(!L.abar_host.empty(), RMG_ERR_NOT_SETUP, "no dense coarse matrix (the AMG coarse solver is in use)");
   std::memcpy(host_out, L.abar_host.data(), sizeof(double) * L.abar_host.size());
   API_END
 }

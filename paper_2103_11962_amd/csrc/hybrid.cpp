@@ -632,6 +632,24 @@ void hybrid_setup(rmg_handle* h) {
 
 void hybrid_cycle(rmg_handle* h, const double* b, double* z) { cycle(h, 0, b, z); }
 
+int64_t aggregate_plain(const std::vector<int64_t>& ptr, const std::vector<int32_t>& col,
+                        const std::vector<double>& val, const std::vector<uint8_t>& free, std::vector<int32_t>& agg) {
+  HRegionHost G;
+  const int64_t n = (int64_t)free.size();
+  G.ptr = ptr;
+  G.col = col;
+  G.val = val;
+  G.free = free;
+  G.comp.resize(n);
+  for (int64_t i = 0; i < n; ++i) G.comp[i] = i;
+  G.xyz.assign(n, {-1, -1, -1});
+  const std::vector<int32_t> mult(n, 1);  // no interface: the structured stage never applies
+  const int shape[3] = {1, 1, 1};
+  std::vector<std::array<int32_t, 3>> cxyz;
+  aggregate(G, true, mult, shape, 0u, 1, agg, cxyz);
+  return (int64_t)cxyz.size();
+}
+
 }  // namespace rmg
 
 // ------------------------------------------------------------------ C entry points

@@ -70,6 +70,12 @@ struct Hybrid {
   std::vector<std::unique_ptr<HLevel>> lv;
 };
 
+// Staged plain aggregation of one matrix's free rows (roots, joins, leftovers; no interface
+// stage), CSR with ascending columns: coarse index of every row (-1: not aggregated), numbered by
+// each aggregate's smallest row.  Returns the number of aggregates.  (hybrid.cpp)
+int64_t aggregate_plain(const std::vector<int64_t>& ptr, const std::vector<int32_t>& col,
+                        const std::vector<double>& val, const std::vector<uint8_t>& free, std::vector<int32_t>& agg);
+
 // ---- kernels_hybrid.hip
 // y = [[A]] x, region by region (no interface sum).
 void launch_hyb_spmv(const HLevelDev& L, const double* x, double* y, hipStream_t st);

@@ -223,6 +223,7 @@ enum TimedKernel { kTimedCheb = 0, kTimedCgQ = 1, kNumTimed = 2 };
 
 namespace rmg {
 struct Hybrid;  // hybrid.cpp
+struct Amg;     // amg.cpp
 }
 
 struct rmg_handle {
@@ -262,6 +263,7 @@ struct rmg_handle {
   // structured/unstructured hybrid: region kinds (0 structured, 1 unstructured) and the hierarchy
   std::vector<int32_t> region_kind;
   rmg::Hybrid* hy = nullptr;
+  rmg::Amg* amg = nullptr;  // AMG coarse solver below the region hierarchy (coarse_amg = 1)
   rmg::DevAlloc alloc;     // device memory provider (empty: hipMalloc)
   double setup_ms = 0.0;   // wall time of the last rmg_setup_hierarchy
   ~rmg_handle();
@@ -283,6 +285,13 @@ Level* make_coarse_level(const Level& fine);
 void build_tables(Level& L);
 void make_tiles(Level& L, int depth);
 void build_coarse_solver(rmg_handle* h, Level& L);
+
+// amg.cpp: AMG coarse solver on the coarsest region level's composite operator (Section 3.5).
+// amg_setup builds it from L's stencils (L.nc, comp_owner, cvec, cvec2 set as for the direct
+// solver); amg_cycle runs one V-cycle z = M^-1 b on composite vectors of L.nc entries.
+void amg_setup(rmg_handle* h, Level& L);
+void amg_cycle(rmg_handle* h, const double* b, double* z);
+void amg_destroy(rmg_handle* h);
 
 // solver.cpp
 void setup_hierarchy(rmg_handle* h);

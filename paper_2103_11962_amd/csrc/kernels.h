@@ -96,6 +96,9 @@ void launch_to_composite(const Level& L, const double* reg, double* comp, int av
 
 // Coarsest level: gather owner copies, dense FP64 GEMV with the inverse, scatter to copies.
 void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipStream_t st);
+// The coarse solve's halves: owner copies of b into L.cvec (FP64); L.cvec2 to every regional copy.
+void launch_coarse_gather(const Level& L, bool lowp, const void* b, hipStream_t st);
+void launch_coarse_scatter(const Level& L, bool lowp, void* u, hipStream_t st);
 // y = A x, A row-major n x n (one wavefront per row).
 void launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t st);
 // In-place blocked Gauss-Jordan inversion of an SPD n x n matrix (row-major); synchronises st.

@@ -780,7 +780,7 @@ void launch_dense_gemv(int n, const double* A, const double* x, double* y, hipSt
   LAUNCH_CHECK();
 }
 
-void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipStream_t st) {
+void launch_coarse_gather(const Level& L, bool lowp, const void* b, hipStream_t st) {
   const int n = L.nc;
   const int ncnode = (int)L.ncomp;
   if (lowp)
@@ -790,9 +790,9 @@ void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipS
     hipLaunchKernelGGL(k_gather<double>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, ncnode, L.ndof,
                        L.comp_owner.as<int>(), (const double*)b, L.cvec.as<double>());
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, 4)), dim3(256), 0, st, n, L.ainv.as<double>(), L.cvec.as<double>(),
-                     L.cvec2.as<double>());
-  LAUNCH_CHECK();
+}
+
+void launch_coarse_scatter(const Level& L, bool lowp, void* u, hipStream_t st) {
   if (lowp)
     hipLaunchKernelGGL(k_to_regional<float>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(),
                        L.cvec2.as<double>(), (float*)u);
@@ -800,6 +800,15 @@ void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipS
     hipLaunchKernelGGL(k_to_regional<double>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(),
                        L.cvec2.as<double>(), (double*)u);
   LAUNCH_CHECK();
+}
+
+void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipStream_t st) {
+  launch_coarse_gather(L, lowp, b, st);
+  const int n = L.nc;
+  hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, 4)), dim3(256), 0, st, n, L.ainv.as<double>(), L.cvec.as<double>(),
+                     L.cvec2.as<double>());
+  LAUNCH_CHECK();
+  launch_coarse_scatter(L, lowp, u, st);
 }
 
 // ------------------------------------------ coarse inverse: blocked Gauss-Jordan (SPD, in place)

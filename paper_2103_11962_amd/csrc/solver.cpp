@@ -269,7 +269,8 @@ static int build_levels(rmg_handle* h, bool stored) {
     configure_level(h, L, l > 0, o.symmetric && l < o.nlevels - 1);  // (the coarsest is solved directly)
     if (lowp) alloc_vectors_lowp(L, true);  // level 0's b32 holds the FP32 copy of the CG residual
     if (l == o.nlevels - 1) {
-      build_coarse_solver(h, L);
+      if (o.coarse_amg) amg_setup(h, L);  // Section 3.5: an AMG V-cycle instead of the direct solver
+      else build_coarse_solver(h, L);
       break;
     }
     // D~ = Psi^T Psi diag([[A]]) (point diagonal), then its reciprocal (Section 3.2, smoother setup)
@@ -346,6 +347,7 @@ void setup_hierarchy(rmg_handle* h) {
   h->rho_learned = h->rho_geometric = -1.0;
   h->p_flags = 0;
   hybrid_destroy(h);
+  amg_destroy(h);
   if (o.hybrid) {  // aggregation hierarchy of the structured/unstructured hybrid
     prepare_finest(h);
     hybrid_setup(h);
@@ -593,7 +595,13 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
   if (level == nl - 1) {
-    launch_coarse_solve(L, lowp, b, z, st);
+    if (h->amg) {
+      launch_coarse_gather(L, lowp, b, st);
+      amg_cycle(h, L.cvec.as<double>(), L.cvec2.as<double>());
+      launch_coarse_scatter(L, lowp, z, st);
+    } else {
+      launch_coarse_solve(L, lowp, b, z, st);
+    }
     return;
   }
   if (h->opt.smoother >= 2) {  // region-local Gauss-Seidel (FP64 only), in place on z

@@ -39,7 +39,7 @@ SYMBOLS = (
     "rmg_mlp_num_data", "rmg_mlp_get_data", "rmg_mlp_forward", "rmg_mlp_loss_grad", "rmg_mlp_adam_step",
     "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr", "rmg_mg_solve",
     "rmg_mlp_set_loss", "rmg_set_region_kinds", "rmg_hybrid_level_info", "rmg_hybrid_aggregates",
-    "rmg_hybrid_composite_ids", "rmg_hybrid_matrix",
+    "rmg_hybrid_composite_ids", "rmg_hybrid_matrix", "rmg_amg_levels", "rmg_amg_level_info", "rmg_amg_matrix",
 )
 SMOOTHER_CHEBYSHEV, SMOOTHER_JACOBI, SMOOTHER_GS, SMOOTHER_GS_FB, SMOOTHER_SYMGS = 0, 1, 2, 3, 4
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
@@ -69,6 +69,8 @@ class Options(ctypes.Structure):
         ("judge_cycles", ctypes.c_int),
         ("hybrid", ctypes.c_int),
         ("cycle_gamma", ctypes.c_int),
+        ("coarse_amg", ctypes.c_int),
+        ("amg_coarse_size", ctypes.c_int),
     ]
 
 
@@ -188,6 +190,10 @@ def load():
         "rmg_hybrid_aggregates": (I, [H, I, P]),
         "rmg_hybrid_composite_ids": (I, [H, I, P]),
         "rmg_hybrid_matrix": (I, [H, I, P, P, P]),
+        "rmg_amg_levels": (I, [H, ctypes.POINTER(ctypes.c_int)]),
+        "rmg_amg_level_info": (I, [H, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int64)]),
+        "rmg_amg_matrix": (I, [H, I, I, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -398,6 +404,32 @@ class Handle:
         _check(load().rmg_hybrid_matrix(self._h, level, rp.ctypes.data_as(ctypes.c_void_p),
                                         ci.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p)))
         return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(n, n))
+
+    def amg_levels(self):
+        """Levels of the AMG coarse solver (0 without one)."""
+        n = ctypes.c_int()
+        _check(load().rmg_amg_levels(self._h, ctypes.byref(n)))
+        return n.value
+
+    def amg_level_info(self, level):
+        n, a, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().rmg_amg_level_info(self._h, level, ctypes.byref(n), ctypes.byref(a), ctypes.byref(p)))
+        return {"n": n.value, "nnz_a": a.value, "nnz_p": p.value}
+
+    def amg_matrix(self, level, which=0):
+        """AMG level `level`'s matrix (which 0) or prolongator to the next level (which 1), scipy CSR."""
+        import scipy.sparse as sp
+
+        info = self.amg_level_info(level)
+        n = info["n"]
+        nnz = info["nnz_a"] if which == 0 else info["nnz_p"]
+        ncols = n if which == 0 else self.amg_level_info(level + 1)["n"]
+        rp = np.zeros(n + 1, dtype=np.int64)
+        ci = np.zeros(max(nnz, 1), dtype=np.int32)
+        v = np.zeros(max(nnz, 1))
+        _check(load().rmg_amg_matrix(self._h, level, which, rp.ctypes.data_as(ctypes.c_void_p),
+                                     ci.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p)))
+        return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(n, ncols))
 
     def level_kernel(self, level):
         k, c, cl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
