@@ -30,9 +30,11 @@ HBM_PEAK_GBS = 8000.0
 # the Chebyshev step reads the coefficients, u, b, D^-1, d and writes d, u; the CG product reads
 # the coefficients and p and writes q.  The algorithmic figures are the method's 27-point
 # operator: 264 B/row for the fused Chebyshev step, 232 B/row for the product.  On a symmetric
-# level the kernels store and stream only the upper half (14 coefficients: 160 and 128 B/row).
-def cheb_bytes_per_row(coefs):
-    return 8 * coefs + 6 * 8
+# level the kernels store and stream only the upper half (14 coefficients), and the tiled FP64
+# Chebyshev kernel takes D^-1 of a one-region row from its centre coefficient instead of reading
+# it (only shared rows, about 5%, read it when their interface sum is finished): 152 and 128 B/row.
+def cheb_bytes_per_row(coefs, reads_dinv=True):
+    return 8 * coefs + (6 if reads_dinv else 5) * 8
 
 
 def cg_matvec_bytes_per_row(coefs):
@@ -43,8 +45,8 @@ ALGO_COEFS = 27
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
-TRAFFIC_BYTES = 6179689364
-TRAFFIC_KERNEL_SHA = "c192c4a37ff748ec"
+TRAFFIC_BYTES = 5900246932
+TRAFFIC_KERNEL_SHA = "eda9ad904ad6d81e"
 
 CPU_SAMPLE = r"""
 import json, sys, time
@@ -597,7 +599,8 @@ def main():
     avg_cheb = ms_cheb / max(n_cheb, 1)
     bytes_cheb = cheb_bytes_per_row(ALGO_COEFS) * rows
     achieved = bytes_cheb / (avg_cheb * 1e-3) / 1e9
-    achieved_stored = cheb_bytes_per_row(lk["coefs"]) * rows / (avg_cheb * 1e-3) / 1e9
+    tiled = lk["kernel"] in (1, 2)  # the 2.5D kernel computes D^-1 of one-region rows
+    achieved_stored = cheb_bytes_per_row(lk["coefs"], not tiled) * rows / (avg_cheb * 1e-3) / 1e9
     avg_cg = ms_cg / max(n_cg, 1)
     achieved_cg = cg_matvec_bytes_per_row(ALGO_COEFS) * rows / (avg_cg * 1e-3) / 1e9
     traffic = TRAFFIC_BYTES if args.workload == "c2" and kernel_source_sha() == TRAFFIC_KERNEL_SHA else None
@@ -642,7 +645,7 @@ def main():
             "traffic": traffic,
             # the bytes the kernel stores and streams (upper half of the symmetric stencil), and the
             # HBM rate the counters measured: the same launches seen from the memory side
-            "stored_bytes_per_row": cheb_bytes_per_row(lk["coefs"]),
+            "stored_bytes_per_row": cheb_bytes_per_row(lk["coefs"], not tiled),
             "achieved_at_stored_bytes": achieved_stored,
             "frac_at_stored_bytes": achieved_stored / HBM_PEAK_GBS,
             "counted_hbm_gbs": traffic / (avg_cheb * 1e-3) / 1e9 if traffic else None,

@@ -25,8 +25,11 @@ struct OpP {
 
 // Final update of dof i once z = (Psi^T Psi A x)_i is known; m = multiplicity of its node,
 // xself = x_i.  Returns the dof's contribution to the fused reduction, if any.
-template <StencilOp OP, bool DOT, class V>
-__device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m, V xself) {
+// OWN: the dof belongs to one region, whose centre coefficient `centre` is then the composite
+// diagonal: the Chebyshev steps take 1 / centre (the same correctly rounded quotient as the stored
+// D~^-1) instead of reading it.
+template <StencilOp OP, bool DOT, class V, bool OWN = false>
+__device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre = (V)0) {
   if constexpr (OP == StencilOp::Matvec) {
     p.out[i] = z;
     return 0.0;
@@ -39,7 +42,8 @@ __device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m,
     return 0.0;
   } else if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) {
     const V r = p.b[i] - z;
-    V dd = p.c2 * (p.dinv[i] * r);
+    const V di = OWN ? (V)1 / centre : p.dinv[i];
+    V dd = p.c2 * (di * r);
     if constexpr (OP == StencilOp::Cheb) dd = p.c1 * p.d[i] + dd;
     p.d[i] = dd;
     const V u = xself + dd;
@@ -162,6 +166,10 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
   constexpr int kT3 = NT;
   constexpr int kT3Plane = tile_plane_cap(NT);
   constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
+  // FP64 Chebyshev steps compute D~^-1 of one-region nodes from the centre coefficient; the FP32
+  // copies keep the stored (rounded FP64) reciprocal
+  constexpr bool kOwnDiag = std::is_same<V, double>::value && std::is_same<C, double>::value &&
+                            (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst);
   __shared__ V pl[2][kT3Plane];
   // SYM: the previous plane's couplings towards z+1 (9 per tile node) and this plane's in-plane upper
   // couplings (4 per tile node), indexed by the tile-local node = thread index
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
       if (active) {
         const int li = zz * sz + y * sy + x;
         const int64_t gi = R.off + li;
-        V acc = (V)0;
+        V acc = (V)0, ctr = (V)0;  // ctr: centre coefficient (the diagonal of a one-region node)
         if constexpr (SYM) {
 #pragma unroll
           for (int s = 13; s < 27; ++s) {
@@ -287,18 +295,21 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
             const int j = s % 9;
             acc += lo[s] * (s < 9 ? rm[j] : rc[j]);
           }
+          ctr = up[0];
         } else {
           const C* __restrict__ cf = coef + coef_index(gi, 0, 27);
 #pragma unroll
           for (int s = 0; s < 27; ++s) {
             const int j = s % 9, dz = s / 9 - 1;
             const V v = dz < 0 ? rm[j] : (dz == 0 ? rc[j] : rp[j]);
-            acc += (V)coefv<27, 1, C>(cf, centre, gi, s, 0, 0) * v;
+            const V cv = (V)coefv<27, 1, C>(cf, centre, gi, s, 0, 0);
+            if (s == 13) ctr = cv;
+            acc += cv * v;
           }
         }
         const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
         if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
-        else contrib += finish<OP, DOT, V>(p, gi, acc, 1, rc[4]);
+        else contrib += finish<OP, DOT, V, kOwnDiag>(p, gi, acc, 1, rc[4], ctr);
       }
       store(sp ^ 1);  // plane zz+2 replaces plane zz
 #pragma unroll
