@@ -133,7 +133,7 @@ def workload(name: str, seed: int = 0) -> Workload:
     ``table1_rect``  2D five-point, 700 x 720 nodes in 3x3 regions (extents 234 and 241/240, not
     3^k + 1), 4 levels, one smoothing step.
     ``uneven*``  region extents that are not 3^k + 1 (2D five-point, 3D Q1 Laplace, elasticity,
-    and an 8-region mesh with slab extents drawn from 11..31).
+    an 8-region mesh with slab extents drawn from 11..31, and 2D/3D meshes of extents 2 to 5).
     """
     full = lambda dim: (1 << (2 * dim)) - 1  # noqa: E731  all faces Dirichlet
     if name == "c1":
@@ -181,6 +181,12 @@ def workload(name: str, seed: int = 0) -> Workload:
     if name == "uneven3e_small":
         o, e = tensor_layout([[8, 6], [7, 6], [6, 8]])
         return Workload(name, 3, 3, o, e, full(3), 3, 3, "elasticity", h=1.0 / 12, seed=seed)
+    if name == "uneven_tiny3d":  # extents 2 to 5: single-cell and two-cell coarse intervals, levels
+        o, e = tensor_layout([[2, 5, 3], [3, 4], [4, 2]])  # that stop shrinking at 2 nodes per axis
+        return Workload(name, 3, 1, o, e, full(3), 3, 2, "laplace", h=0.25, seed=seed)
+    if name == "uneven_tiny2d":
+        o, e = tensor_layout([[2, 3, 4], [5, 2]])
+        return Workload(name, 2, 1, o, e, full(2), 4, 2, "fd5", seed=seed)
     if name == "uneven_c4_small":
         o, e = tensor_layout(batched_extents(seed, counts=(2, 2, 2), choices=tuple(range(11, 32))))
         return Workload(name, 3, 1, o, e, full(3), 4, 3, "laplace", seed=seed)
@@ -189,7 +195,7 @@ def workload(name: str, seed: int = 0) -> Workload:
 
 WORKLOADS = ("c1", "c1_small", "c2", "c2_small", "c2_mid", "c3", "c3_small",
              "c4", "c4_small", "c5", "c5_small", "table1_rect", "uneven2d_small", "uneven3d_small",
-             "uneven3e_small", "uneven_c4_small")
+             "uneven3e_small", "uneven_c4_small", "uneven_tiny3d", "uneven_tiny2d")
 
 
 def dirichlet_nodes(shape_xyz, mask: int) -> np.ndarray:

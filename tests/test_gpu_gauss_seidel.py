@@ -16,7 +16,8 @@ from tests import harness
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["c1_small", "c2_small", "c3_small", "c4_small", "c5_small", "uneven2d_small", "uneven3d_small"]
+CASES = ["c1_small", "c2_small", "c3_small", "c4_small", "c5_small", "uneven2d_small", "uneven3d_small",
+         "uneven_tiny3d", "uneven_tiny2d"]
 NAMES = {2: "gs", 3: "sgs", 4: "symgs"}
 
 

@@ -20,7 +20,9 @@ SMALL = [("c1_small", 0), ("c2_small", 1), ("c2_small", 2), ("c4_small", 1), ("c
          ("c4_small", 3), ("c2_mid", 3),
          # region extents that are not 3^k + 1: shortened last coarse intervals on every level
          ("uneven2d_small", 0), ("uneven3d_small", 1), ("uneven3d_small", 2), ("uneven3d_small", 3),
-         ("uneven3e_small", 0), ("uneven_c4_small", 2)]
+         ("uneven3e_small", 0), ("uneven_c4_small", 2),
+         # extents 2 to 5: one- and two-cell coarse intervals, levels that stop shrinking
+         ("uneven_tiny3d", 1), ("uneven_tiny3d", 2), ("uneven_tiny3d", 3), ("uneven_tiny2d", 0)]
 IDS = [f"{n}-k{k}" for n, k in SMALL]
 
 
@@ -224,7 +226,7 @@ def test_errors_are_reported(hip_device):
 # ---------------------------------------------------------------- low-precision V-cycle
 MIXED = [("c2_small", 1, 1), ("c2_small", 2, 2), ("c2_mid", 1, 2), ("c2_mid", 2, 1), ("c3_small", 1, 0),
          ("c3_small", 2, 0), ("c4_small", 2, 2), ("c5_small", 1, 2), ("uneven3d_small", 1, 2),
-         ("uneven3e_small", 1, 0), ("uneven_c4_small", 2, 3)]
+         ("uneven3e_small", 1, 0), ("uneven_c4_small", 2, 3), ("uneven_tiny3d", 1, 2)]
 
 
 @pytest.mark.parametrize("name,precision,kernel", MIXED, ids=[f"{n}-p{p}-k{k}" for n, p, k in MIXED])
