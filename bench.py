@@ -630,6 +630,8 @@ def main():
             "solve_s_per_step": solves,
             "step": "device assembly + hierarchy setup + PCG solve",
             "cg_matvec_gbs": achieved_cg,
+            # device ms of each region level's share of the preconditioner in the last timed solve
+            "level_ms": last["level_ms"][:w.nlevels],
         },
         "roofline": {
             "bound": "hbm",

@@ -150,6 +150,11 @@ typedef struct {
   int history_cap;       /* capacity of history */
   int history_len;       /* entries written */
   double setup_ms;       /* host wall time of the last rmg_setup_hierarchy (stream synchronised) */
+  double level_ms[12];   /* with rmg_profile on and no graph replay: device time of each region
+                            level's share of the preconditioner over this solve (HIP events around
+                            its smoothing, residual and transfers; on the last level the coarse
+                            solve, the AMG V-cycle included); 0 otherwise and beyond nlevels (and
+                            for the hybrid hierarchy) */
 } rmg_solve_info;
 
 /* Device memory provider for a handle (optional).  alloc(bytes, ctx) returns at least `bytes` of

@@ -252,6 +252,8 @@ struct rmg_handle {
   const void* graph_x_ptr = nullptr;
   void drop_graphs();
   rmg::KernelTimer timers[rmg::kNumTimed];
+  rmg::KernelTimer level_timers[12];  // per region level, reset at the start of every solve
+  bool timing_levels = false;         // a solve with profiling on is running
   // finest-level interpolation requested for the next setup (RMG_P_*) and its inputs
   int pmode = 0;
   rmg::DBuf user_pw;             // caller weights, double [n][8]

@@ -517,6 +517,34 @@ double convergence_factor(rmg_handle* h, int cycles) {
   return std::pow(rk / r0, 1.0 / cycles);
 }
 
+// Per-level preconditioner time (rmg_profile on; never inside a captured graph, where profiling is
+// switched off): an event pair around a level's own launches.  begin returns the closing event.
+static hipEvent_t level_span_begin(rmg_handle* h, int level) {
+  if (!h->profiling || !h->timing_levels) return nullptr;
+  hipEvent_t e0, e1;
+  h->level_timers[level].acquire(&e0, &e1);
+  RMG_HIP(hipEventRecord(e0, h->stream));
+  return e1;
+}
+
+static void level_span_end(rmg_handle* h, hipEvent_t e1) {
+  if (e1) RMG_HIP(hipEventRecord(e1, h->stream));
+}
+
+static void level_times_reset(rmg_handle* h) {
+  for (auto& t : h->level_timers) t.reset();
+  h->timing_levels = true;
+}
+
+// After a stream synchronisation: the solve's per-level totals into info.
+static void level_times_report(rmg_handle* h, rmg_solve_info* info) {
+  h->timing_levels = false;
+  for (int l = 0; l < 12; ++l) {
+    h->level_timers[l].harvest();
+    if (info) info->level_ms[l] = h->level_timers[l].total_ms;
+  }
+}
+
 void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
               rmg_status* status) {
   Level& L = *h->levels[0];
@@ -527,6 +555,7 @@ void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit,
   hipEvent_t e0, e1;
   RMG_HIP(hipEventCreate(&e0));
   RMG_HIP(hipEventCreate(&e1));
+  level_times_reset(h);
   RMG_HIP(hipEventRecord(e0, st));
   auto residual = [&] {
     StencilArgs a;
@@ -575,6 +604,7 @@ void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit,
   RMG_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  level_times_report(h, info);
   if (*status == RMG_OK && !converged) {
     *status = RMG_ERR_NOT_CONVERGED;
     set_last_error("multigrid did not reach rtol within maxit cycles");
@@ -595,6 +625,7 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
   if (level == nl - 1) {
+    hipEvent_t span = level_span_begin(h, level);
     if (h->amg) {
       launch_coarse_gather(L, lowp, b, st);
       amg_cycle(h, L.cvec.as<double>(), L.cvec2.as<double>());
@@ -602,8 +633,10 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
     } else {
       launch_coarse_solve(L, lowp, b, z, st);
     }
+    level_span_end(h, span);
     return;
   }
+  hipEvent_t span = level_span_begin(h, level);
   if (h->opt.smoother >= 2) {  // region-local Gauss-Seidel (FP64 only), in place on z
     double* u = static_cast<double*>(z);
     gs_smooth(h, L, static_cast<const double*>(b), u, true, false);
@@ -615,9 +648,12 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
     launch_stencil_op(L, a, st);
     Level& C = *h->levels[level + 1];
     launch_restrict(L, C, false, L.r.p, C.b.p, st);
+    level_span_end(h, span);
     vcycle(h, level + 1, false, C.b.p, C.u2.p);
+    span = level_span_begin(h, level);
     launch_prolong_add(L, C, false, C.u2.p, u, st);
     gs_smooth(h, L, static_cast<const double*>(b), u, false, h->opt.smoother == 3);
+    level_span_end(h, span);
     return;
   }
   const int K = h->opt.cheb_degree;
@@ -641,12 +677,15 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
   Level& C = *h->levels[level + 1];
   const Bufs BC = bufs(C, lowp);
   launch_restrict(L, C, lowp, B.r, BC.b, st);
+  level_span_end(h, span);
   vcycle(h, level + 1, lowp, BC.b, BC.u2);
+  span = level_span_begin(h, level);
   launch_prolong_add(L, C, lowp, BC.u2, buf[cur], st);
   for (int k = 0; k < K; ++k) {
     cheb_step(h, L, lowp, k, k == 0, b, buf[cur], buf[1 - cur]);
     cur = 1 - cur;
   }
+  level_span_end(h, span);
   RMG_REQUIRE(buf[cur] == z, RMG_ERR_ARG, "internal: V-cycle buffer parity");
 }
 
@@ -734,6 +773,7 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
   hipEvent_t e0, e1;
   RMG_HIP(hipEventCreate(&e0));
   RMG_HIP(hipEventCreate(&e1));
+  level_times_reset(h);
   RMG_HIP(hipEventRecord(e0, st));
   *status = RMG_OK;
   int hist_len = 0;
@@ -806,8 +846,10 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
       else body_a(h->profiling);
       ++it;
       read_scalars(h);
-      if (h->profiling)
+      if (h->profiling) {
         for (auto& t : h->timers) t.harvest();
+        for (auto& t : h->level_timers) t.harvest();
+      }
       const double rz = h->host_scalars[kRZ], pq = h->host_scalars[kPQ], rr = h->host_scalars[kRR];
       if (!(pq > 0.0) || !(rz > 0.0) || !std::isfinite(rr)) {
         *status = RMG_ERR_BREAKDOWN;
@@ -840,6 +882,7 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
   read_scalars(h);
   if (h->profiling)
     for (auto& t : h->timers) t.harvest();
+  level_times_report(h, info);
   float ms = 0.f;
   RMG_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);

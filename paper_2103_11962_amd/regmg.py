@@ -85,6 +85,7 @@ class SolveInfo(ctypes.Structure):
         ("history_cap", ctypes.c_int),
         ("history_len", ctypes.c_int),
         ("setup_ms", ctypes.c_double),
+        ("level_ms", ctypes.c_double * 12),
     ]
 
 
@@ -338,6 +339,7 @@ class Handle:
             "status": STATUS.get(code, code), "iterations": info.iterations, "converged": bool(info.converged),
             "relres": info.relres, "true_relres": info.true_relres, "solve_ms": info.solve_ms,
             "setup_ms": info.setup_ms,
+            "level_ms": list(info.level_ms),
             "history": [hist[i] for i in range(min(info.history_len, history_cap))],
         }
         return out

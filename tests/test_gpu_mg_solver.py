@@ -137,3 +137,29 @@ def test_table1_rectangular_histories(hip_device, smoother):
     print(f"[table1-rect] {smoother}: {n} cycles regional, {ns} structured, histories within {d.max():.3%}",
           flush=True)
     assert abs(ns - n) <= 1 and 1e-6 < d.max() < 0.25
+
+
+def test_per_level_solve_times(hip_device):
+    """rmg_solve_info.level_ms: with profiling on, each region level's share of the preconditioner
+    (smoothing, residual, transfers; the coarse solve on the last level) is positive and the shares
+    add up to less than the solve; zero with profiling off and beyond the hierarchy."""
+    import torch
+
+    w = synth.workload("c2_mid")
+    h = harness.gpu_problem(w)
+    b = harness.to_dev(synth.rhs(w))
+    x = torch.zeros_like(b)
+    out = h.solve(b, x)
+    assert len(out["level_ms"]) == 12 and all(v == 0.0 for v in out["level_ms"])
+    h.profile(True)
+    for method in ("pcg", "mg"):
+        x.zero_()
+        out = h.solve(b, x, method=method)
+        lm = out["level_ms"]
+        print(f"[level-ms] {method}: {[round(v, 3) for v in lm[:w.nlevels]]} of {out['solve_ms']:.2f} ms", flush=True)
+        assert all(v > 0.0 for v in lm[:w.nlevels]) and all(v == 0.0 for v in lm[w.nlevels:])
+        assert sum(lm) < out["solve_ms"]
+    h.profile(False)
+    x.zero_()
+    assert all(v == 0.0 for v in h.solve(b, x)["level_ms"])
+    h.close()
