@@ -45,8 +45,8 @@ ALGO_COEFS = 27
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
-TRAFFIC_BYTES = 5900246932
-TRAFFIC_KERNEL_SHA = "eda9ad904ad6d81e"
+TRAFFIC_BYTES = 5900177265
+TRAFFIC_KERNEL_SHA = "b127e020ce9b1ddc"
 
 CPU_SAMPLE = r"""
 import json, sys, time
@@ -147,16 +147,19 @@ def _setup(h, w, **opts):
 def _cheb_bytes(h, kind, precision, stored=True):
     """Bytes per node of the level-0 Chebyshev step: the stencil blocks (stored: the ones the level
     streams, full or upper half, see rmg_level_kernel; else the method's full 27 blocks), u, b,
-    D~^-1, d read and d, u written; with BF16 storage the centre block comes from an FP32 array."""
+    D~^-1, d read and d, u written; with BF16 storage the centre block comes from an FP32 array.
+    Stored: the scalar tiled kernel in FP64 or FP32 computes D~^-1 of one-region rows instead of
+    reading it."""
     lk = h.level_kernel(0)
     nd = 1 if kind == "scalar" else 3
     nb = nd * nd
     coefs = lk["coefs"] if stored else 27 * nb
     coefs_lo = lk["coefs_lo"] if stored else 27 * nb
+    vecs = 5 if stored and kind == "scalar" and lk["kernel"] in (1, 2) and precision in (0, 1) else 6
     if precision == 0:
-        return coefs * 8 + 6 * nd * 8
+        return coefs * 8 + vecs * nd * 8
     if precision == 1:
-        return coefs_lo * 4 + 6 * nd * 4
+        return coefs_lo * 4 + vecs * nd * 4
     return (coefs_lo - nb) * 2 + nb * 4 + 6 * nd * 4
 
 

@@ -166,10 +166,10 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
   constexpr int kT3 = NT;
   constexpr int kT3Plane = tile_plane_cap(NT);
   constexpr int kT3Fetch = (kT3Plane + kT3 - 1) / kT3;
-  // FP64 Chebyshev steps compute D~^-1 of one-region nodes from the centre coefficient; the FP32
-  // copies keep the stored (rounded FP64) reciprocal
-  constexpr bool kOwnDiag = std::is_same<V, double>::value && std::is_same<C, double>::value &&
-                            (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst);
+  // Chebyshev steps compute D~^-1 of one-region nodes from the centre coefficient when it is stored
+  // in the arithmetic's own type (FP64, or the FP32 copy); the BF16 storage's centre carries the
+  // row-sum correction, so it keeps reading the stored reciprocal
+  constexpr bool kOwnDiag = std::is_same<V, C>::value && (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst);
   __shared__ V pl[2][kT3Plane];
   // SYM: the previous plane's couplings towards z+1 (9 per tile node) and this plane's in-plane upper
   // couplings (4 per tile node), indexed by the tile-local node = thread index
