@@ -229,8 +229,16 @@ void upload(DBuf& d, const std::vector<T>& v, hipStream_t st) {
   RMG_HIP(hipStreamSynchronize(st));  // v may be a local table
 }
 
-void upload_ell(const Csr& M, EllDev& D, hipStream_t st) {
+void upload_sp(const Csr& M, SpDev& D, hipStream_t st) {
   const int64_t n = M.rows, ns = (n + 63) / 64;
+  D.n = n;
+  D.wave = M.nnz() > 32 * std::max<int64_t>(n, 1);
+  if (D.wave) {  // long rows: plain CSR, a wavefront per row
+    upload(D.sptr, M.ptr, st);
+    upload(D.col, M.col, st);
+    upload(D.val, M.val, st);
+    return;
+  }
   std::vector<int64_t> sptr((size_t)ns + 1, 0);
   for (int64_t s = 0; s < ns; ++s) {
     int64_t w = 0;
@@ -249,7 +257,6 @@ void upload_ell(const Csr& M, EllDev& D, hipStream_t st) {
         val[at] = q < M.ptr[i + 1] ? M.val[q] : 0.0;
       }
   }
-  D.n = n;
   upload(D.sptr, sptr, st);
   upload(D.col, col, st);
   upload(D.val, val, st);
@@ -272,18 +279,18 @@ void cycle(rmg_handle* h, int l, const double* b, double* z) {
   auto chebyshev = [&](const double* r0, bool zero) {  // r0 = b - A z on entry
     launch_amg_cheb_first(n, L.inv_theta, dinv, r0, d, z, zero, st);
     for (int k = 1; k < K; ++k) {
-      launch_ell_apply(L.dA, z, y, false, st);
+      launch_sp_apply(L.dA, z, y, false, st);
       launch_amg_cheb_step(n, L.c1[k], L.c2[k], dinv, b, y, d, z, st);
     }
   };
   chebyshev(b, true);
-  launch_ell_apply(L.dA, z, y, false, st);
+  launch_sp_apply(L.dA, z, y, false, st);
   launch_amg_sub(n, b, y, r, st);
   AmgLevel& C = *amg.lv[l + 1];
-  launch_ell_apply(L.dPt, r, C.b.as<double>(), false, st);
+  launch_sp_apply(L.dPt, r, C.b.as<double>(), false, st);
   cycle(h, l + 1, C.b.as<double>(), C.u.as<double>());
-  launch_ell_apply(L.dP, C.u.as<double>(), z, true, st);
-  launch_ell_apply(L.dA, z, y, false, st);
+  launch_sp_apply(L.dP, C.u.as<double>(), z, true, st);
+  launch_sp_apply(L.dA, z, y, false, st);
   launch_amg_sub(n, b, y, r, st);
   chebyshev(r, false);
 }
@@ -374,11 +381,11 @@ void amg_setup(rmg_handle* h, Level& L) {
       RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "AMG: the last level's matrix is singular");
       continue;
     }
-    upload_ell(V.A, V.dA, st);
-    upload_ell(V.P, V.dP, st);
+    upload_sp(V.A, V.dA, st);
+    upload_sp(V.P, V.dP, st);
     Csr Pt;
     transpose(V.P, Pt);
-    upload_ell(Pt, V.dPt, st);
+    upload_sp(Pt, V.dPt, st);
     const std::vector<double> diag = diagonal(V.A);
     std::vector<double> dinv((size_t)n);
     for (int64_t i = 0; i < n; ++i) dinv[i] = 1.0 / diag[i];

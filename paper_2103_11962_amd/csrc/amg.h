@@ -18,11 +18,13 @@ struct Csr {
   int64_t nnz() const { return (int64_t)col.size(); }
 };
 
-// Device matrix in ELL slices of 64 rows: the e-th stored entry of row i at
-// sptr[i / 64] + 64 e + i % 64, e < (sptr[i / 64 + 1] - sptr[i / 64]) / 64; padding entries have
-// column i and value 0.
-struct EllDev {
+// Device matrix.  Short rows (at most 32 entries on average): ELL slices of 64 rows, the e-th
+// stored entry of row i at sptr[i / 64] + 64 e + i % 64, e < (sptr[i / 64 + 1] - sptr[i / 64]) / 64,
+// padding entries with a valid column and value 0; one thread per row.  Long rows (wave): CSR
+// (sptr = row pointers), one wavefront per row, its lanes reading the row contiguously.
+struct SpDev {
   int64_t n = 0;
+  bool wave = false;
   DBuf sptr, col, val;
 };
 
@@ -33,7 +35,7 @@ struct AmgLevel {
   double rho = 0.0;          // Gershgorin bound on lambda_max(D^-1 A)
   double omega = 0.0;        // prolongator smoothing weight 4 / (3 rho)
   // device
-  EllDev dA, dP, dPt;
+  SpDev dA, dP, dPt;
   DBuf dinv, b, u, r, d, y;
   double inv_theta = 0.0;      // Chebyshev: first correction (1/theta) D^-1 r
   std::vector<double> c1, c2;  // Chebyshev step k >= 1: d = c1[k] d + c2[k] D^-1 r
@@ -47,7 +49,7 @@ struct Amg {
 
 // ---- kernels_amg.hip
 // y = M x, or y += M x when accumulate.
-void launch_ell_apply(const EllDev& M, const double* x, double* y, bool accumulate, hipStream_t st);
+void launch_sp_apply(const SpDev& M, const double* x, double* y, bool accumulate, hipStream_t st);
 // d = inv_theta D^-1 r; u = d (zero) or u += d.
 void launch_amg_cheb_first(int64_t n, double inv_theta, const double* dinv, const double* r, double* d, double* u,
                            bool zero, hipStream_t st);

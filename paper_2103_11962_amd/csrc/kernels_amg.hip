@@ -1,7 +1,7 @@
-// Kernels of the AMG coarse solver below the region hierarchy (Section 3.5): one composite matrix
-// per level in ELL slices of 64 rows (the e-th stored entry of row i at sptr[i / 64] + 64 e + i % 64,
-// so a wavefront reads each entry slot of its 64 rows as one contiguous chunk), the smoothed
-// prolongator and its transpose in the same format, and the Chebyshev smoother's element-wise
+// Kernels of the AMG coarse solver below the region hierarchy (Section 3.5): products with each
+// level's composite matrix, smoothed prolongator and its transpose (ELL slices of 64 rows read one
+// contiguous chunk per entry slot and wavefront; matrices with long rows, such as the transpose of
+// the prolongator, in CSR with a wavefront per row), and the Chebyshev smoother's element-wise
 // steps.  The levels are small (the coarse problem of the region hierarchy): L2-resident, latency
 // bound; one thread per row.
 #include "amg.h"
@@ -9,7 +9,7 @@
 
 namespace rmg {
 
-// y = M x (accumulate 0) or y += M x (accumulate 1).
+// y = M x (accumulate 0) or y += M x (accumulate 1); ELL, one thread per row.
 __global__ __launch_bounds__(kBlock) void k_ell_apply(int64_t n, const int64_t* __restrict__ sptr,
                                                       const int* __restrict__ col, const double* __restrict__ val,
                                                       const double* __restrict__ x, double* __restrict__ y,
@@ -24,10 +24,32 @@ __global__ __launch_bounds__(kBlock) void k_ell_apply(int64_t n, const int64_t* 
   y[i] = accumulate ? y[i] + acc : acc;
 }
 
-void launch_ell_apply(const EllDev& M, const double* x, double* y, bool accumulate, hipStream_t st) {
+// The same for CSR with long rows: one wavefront per row; lane l sums entries l, l + 64, ... of
+// the row, then the lanes combine in a fixed tree, so the result does not depend on timing.
+constexpr int kWaveRows = kBlock / 64;
+
+__global__ __launch_bounds__(kBlock) void k_csr_wave_apply(int64_t n, const int64_t* __restrict__ ptr,
+                                                           const int* __restrict__ col,
+                                                           const double* __restrict__ val,
+                                                           const double* __restrict__ x, double* __restrict__ y,
+                                                           int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * kWaveRows + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;  // whole wavefronts leave together
+  double acc = 0.0;
+  for (int64_t e = ptr[i] + lane; e < ptr[i + 1]; e += 64) acc += val[e] * x[col[e]];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) y[i] = accumulate ? y[i] + acc : acc;
+}
+
+void launch_sp_apply(const SpDev& M, const double* x, double* y, bool accumulate, hipStream_t st) {
   if (M.n == 0) return;
-  hipLaunchKernelGGL(k_ell_apply, dim3(cdiv(M.n, kBlock)), dim3(kBlock), 0, st, M.n, M.sptr.as<int64_t>(),
-                     M.col.as<int>(), M.val.as<double>(), x, y, accumulate ? 1 : 0);
+  if (M.wave)
+    hipLaunchKernelGGL(k_csr_wave_apply, dim3(cdiv(M.n, kWaveRows)), dim3(kBlock), 0, st, M.n, M.sptr.as<int64_t>(),
+                       M.col.as<int>(), M.val.as<double>(), x, y, accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_ell_apply, dim3(cdiv(M.n, kBlock)), dim3(kBlock), 0, st, M.n, M.sptr.as<int64_t>(),
+                       M.col.as<int>(), M.val.as<double>(), x, y, accumulate ? 1 : 0);
   LAUNCH_CHECK();
 }
 
