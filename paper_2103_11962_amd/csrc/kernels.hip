@@ -493,15 +493,21 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView F, LevelView C
   bracket(x, RF.ex, RC.ex, lx, ax0, ax1);
   bracket(y, RF.ey, RC.ey, ly, ay0, ay1);
   if (DIM == 3) bracket(z, RF.ez, RC.ez, lz, az0, az1);
-  const int nx = ax1 != 0.0 ? 2 : 1, ny = ay1 != 0.0 ? 2 : 1, nz = az1 != 0.0 ? 2 : 1;
-  for (int iz = 0; iz < nz; ++iz) {
-    const double wz = iz ? az1 : az0;
-    for (int iy = 0; iy < ny; ++iy) {
-      const double wzy = wz * (iy ? ay1 : ay0);
-      for (int ix = 0; ix < nx; ++ix) {
-        const int X = lx + ix, Y = ly + iy, Z = lz + iz;
-        if (!fdir && is_dirichlet(C, RC.ox + X, RC.oy + Y, RC.oz + Z)) continue;
-        const V wt = (V)(wzy * (ix ? ax1 : ax0));
+  // all 2 x 2 (x 2) candidates, unrolled: an absent one (zero weight, or a Dirichlet coarse node
+  // seen from a free fine node) adds 0 to the sum, its index clamped into the box
+  const double ax[2] = {ax0, ax1}, ay[2] = {ay0, ay1}, az[2] = {az0, az1};
+#pragma unroll
+  for (int iz = 0; iz < (DIM == 3 ? 2 : 1); ++iz) {
+    const int Z = min(lz + iz, RC.ez - 1);
+#pragma unroll
+    for (int iy = 0; iy < 2; ++iy) {
+      const int Y = min(ly + iy, RC.ey - 1);
+      const double wzy = az[iz] * ay[iy];
+#pragma unroll
+      for (int ix = 0; ix < 2; ++ix) {
+        const int X = min(lx + ix, RC.ex - 1);
+        const bool off = !fdir && is_dirichlet(C, RC.ox + X, RC.oy + Y, RC.oz + Z);
+        const V wt = off ? (V)0 : (V)(wzy * ax[ix]);
         const int64_t ci = (int64_t)((Z * RC.ey + Y) * RC.ex + X) * NDOF;
 #pragma unroll
         for (int a = 0; a < NDOF; ++a) acc[a] += wt * ub[ci + a];
