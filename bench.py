@@ -421,16 +421,16 @@ def variant_mg_solver(dev):
 
 
 def variant_hybrid(dev):
-    """The structured/unstructured hybrid of Table 5: 3D seven-point Laplacian on 109^3 nodes in
-    3x3x3 regions (37^3 each), 3-level W-cycle, two symmetric Gauss-Seidel iterations before and
+    """The structured/unstructured hybrid of Table 5: 3D seven-point Laplacian on 100^3 nodes (the
+    paper's mesh) in 3x3x3 regions (34^3 each), 3-level W-cycle, two symmetric Gauss-Seidel iterations before and
     after, piecewise-constant transfers, flexible PCG and MG as a solver to 1e-6; all regions
     structured, the centre region unstructured, and all regions unstructured."""
     import numpy as np
 
     import synth
 
-    o, e = synth.tensor_layout([[37] * 3] * 3)
-    w = synth.Workload("fd7_109", 3, 1, o, e, 63, 3, 2, "fd7", seed=0)
+    o, e = synth.tensor_layout([[34] * 3] * 3)
+    w = synth.Workload("fd7_100", 3, 1, o, e, 63, 3, 2, "fd7", seed=0)
     b = _to_dev(synth.rhs(w), dev)
     out = {}
     for name, unstructured in (("structured", []), ("centre_unstructured", [13]), ("unstructured", list(range(27)))):
@@ -446,7 +446,7 @@ def variant_hybrid(dev):
         row["levels"] = [h.hybrid_level_info(l) for l in range(3)]
         out[name] = row
         h.close()
-    out["workload"] = ("3D seven-point Laplacian 109^3 in 3x3x3 regions of 37^3, 3-level W-cycle, 2 symmetric "
+    out["workload"] = ("3D seven-point Laplacian 100^3 (the paper's mesh) in 3x3x3 regions of 34^3, 3-level W-cycle, 2 symmetric "
                        "Gauss-Seidel iterations, piecewise-constant aggregation transfers, to 1e-6")
     return out
 

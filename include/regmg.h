@@ -243,8 +243,9 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
  * lattice is the union of the regions' coarse points.  RMG_ERR_SHAPE if two
  * regions' coarse points disagree on a shared interface (possible only when the
  * boxes do not form a tensor-product layout), or, with stored interpolation
- * weights or opt->hybrid, if some region extent-1 or origin is not divisible by
- * 3^(nlevels-1).  RMG_ERR_NUMERIC if a diagonal is not positive or the coarse
+ * weights, if some region extent-1 or origin is not divisible by 3^(nlevels-1);
+ * the hybrid hierarchy (opt->hybrid) needs every aggregated level's composite
+ * extent - 1 divisible by 3 and at least 6.  RMG_ERR_NUMERIC if a diagonal is not positive or the coarse
  * matrix is singular. */
 rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt);
 

@@ -323,8 +323,10 @@ static int build_levels(rmg_handle* h, bool stored) {
 void setup_hierarchy(rmg_handle* h) {
   const rmg_options& o = h->opt;
   Level* L0 = h->levels[0];
-  if (o.hybrid || h->pmode != RMG_P_GEOMETRIC) {
-    // stored interpolation weights and the hybrid aggregation work on the uniform rate-3 lattice
+  if (o.hybrid) {
+    // the aggregation hierarchy checks its own composite lattice level by level (hybrid.cpp)
+  } else if (h->pmode != RMG_P_GEOMETRIC) {
+    // stored interpolation weights are kept per canonical cell of the uniform rate-3 lattice
     int64_t f = 1;
     for (int l = 1; l < o.nlevels; ++l) f *= 3;
     for (int k = 0; k < L0->nreg; ++k) {

@@ -6,8 +6,8 @@ region matrices of every level (Galerkin products), one cycle (Jacobi, Gauss-Sei
 Gauss-Seidel; V and W) for several region-kind layouts, and the Table 5 setting: a 3D seven-point
 Laplacian in 3x3x3 regions, 3-level W-cycle, two symmetric Gauss-Seidel iterations, piecewise-
 constant transfers, to 1e-6, by flexible PCG and by MG as a solver; parity on 55^3 nodes, every
-layout on 109^3 (regions of 37^3 so that every region boundary is a coarse point on both
-aggregated levels; the paper uses 100^3).
+layout on 109^3 (regions of 37^3, every region boundary a coarse point on both aggregated
+levels), and the paper's own 100^3 mesh (regions of 34^3, whose level-1 boundaries are not).
 """
 import numpy as np
 import pytest
@@ -159,6 +159,32 @@ def test_table5_layouts_gpu(hip_device):
     assert max(pcg) - min(pcg) <= 3
 
 
+def test_table5_paper_mesh(hip_device):
+    """The paper's Table 5 mesh, 100^3 nodes in 3x3x3 regions of 34^3 (whose boundaries are no
+    coarse points on level 1): all regions structured, the centre region unstructured, and all
+    unstructured converge to 1e-6 by PCG and MG, the unstructured layouts needing at most a few
+    more iterations (the paper reports 15 to 18)."""
+    import torch
+
+    w = workload(34)
+    b = harness.to_dev(synth.rhs(w))
+    its = {}
+    for name in ("structured", "centre", "unstructured"):
+        print(f"[table5-100] {name}", flush=True)
+        h = gpu_handle(w, kinds_of(name))
+        assert h.hybrid_level_info(0)["n_composite"] == 100 ** 3
+        row = {}
+        for method in ("pcg", "mg"):
+            x = torch.zeros_like(b)
+            out = h.solve(b, x, rtol=1e-6, maxit=100, method=method)
+            assert out["converged"] and out["true_relres"] <= 1.5e-6, (name, method)
+            row[method] = out["iterations"]
+        its[name] = row
+        h.close()
+    print(f"[table5-100] iterations to 1e-6 (pcg, mg): {its}", flush=True)
+    assert its["structured"]["pcg"] <= its["unstructured"]["pcg"] <= its["structured"]["pcg"] + 4
+
+
 def test_hybrid_option_errors(hip_device):
     from paper_2103_11962_amd import regmg
 
@@ -177,7 +203,7 @@ def test_hybrid_option_errors(hip_device):
     h.close()
 
 
-@pytest.mark.parametrize("case", ["2d_centre", "2d_unstructured", "uneven_3d", "one_region"])
+@pytest.mark.parametrize("case", ["2d_centre", "2d_unstructured", "uneven_3d", "one_region", "offset_level1"])
 def test_hybrid_other_layouts(hip_device, case):
     """2D five-point problems in 3x3 regions (one or all unstructured) and uneven 3D regions with
     unstructured ones: aggregates bit for bit, and one symmetric-GS W-cycle against the oracle."""
@@ -194,6 +220,14 @@ def test_hybrid_other_layouts(hip_device, case):
         kinds[[4] if case == "2d_centre" else list(range(9))] = 1
         lay = Layout(2, o, e, 15)
         A = assembly.composite_fd5(lay)
+    elif case == "offset_level1":  # regions of 13^3: on level 1 their boundaries (4, 8) are no coarse
+        # points, so interface aggregates take coarse points outside their own region's box
+        o, e = synth.tensor_layout([[13] * 3] * 3)
+        w = synth.Workload(case, 3, 1, o, e, 63, 3, 2, "fd7", seed=0)
+        kinds = np.zeros(27, dtype=np.int32)
+        kinds[[4, 13, 22]] = 1
+        lay = Layout(3, o, e, 63)
+        A = assembly.composite_fd7(lay)
     elif case == "one_region":  # no interfaces: stage I is empty, every node aggregated by stages II-IV
         o, e = synth.tensor_layout([[28]] * 3)
         w = synth.Workload(case, 3, 1, o, e, 63, 3, 2, "fd7", seed=0)
