@@ -45,8 +45,8 @@ ALGO_COEFS = 27
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
-TRAFFIC_BYTES = 5900177265
-TRAFFIC_KERNEL_SHA = "b127e020ce9b1ddc"
+TRAFFIC_BYTES = 5900226311
+TRAFFIC_KERNEL_SHA = "b4d4bfbd98de7726"
 
 CPU_SAMPLE = r"""
 import json, sys, time

@@ -24,36 +24,46 @@ struct OpP {
 };
 
 // Final update of dof i once z = (Psi^T Psi A x)_i is known; m = multiplicity of its node,
-// xself = x_i.  Returns the dof's contribution to the fused reduction, if any.
+// xself = x_i: the value `out` the operation writes to p.out[i] and, for the Chebyshev steps, the
+// new direction `dd` for p.d[i].  Returns the dof's contribution to the fused reduction, if any.
 // OWN: the dof belongs to one region, whose centre coefficient `centre` is then the composite
 // diagonal: the Chebyshev steps take 1 / centre (the same correctly rounded quotient as the stored
 // D~^-1) instead of reading it.
 template <StencilOp OP, bool DOT, class V, bool OWN = false>
-__device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre = (V)0) {
+__device__ __forceinline__ double finish_value(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre, V& out,
+                                               V& dd) {
   if constexpr (OP == StencilOp::Matvec) {
-    p.out[i] = z;
+    out = z;
     return 0.0;
   } else if constexpr (OP == StencilOp::Residual) {
-    p.out[i] = p.b[i] - z;
+    out = p.b[i] - z;
     return 0.0;
   } else if constexpr (OP == StencilOp::ResidualScaled) {
     const V r = p.b[i] - z;
-    p.out[i] = (m == 1) ? r : r / (V)m;
+    out = (m == 1) ? r : r / (V)m;
     return 0.0;
   } else if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) {
     const V r = p.b[i] - z;
     const V di = OWN ? (V)1 / centre : p.dinv[i];
-    V dd = p.c2 * (di * r);
+    dd = p.c2 * (di * r);
     if constexpr (OP == StencilOp::Cheb) dd = p.c1 * p.d[i] + dd;
-    p.d[i] = dd;
-    const V u = xself + dd;
-    p.out[i] = u;
-    if constexpr (DOT) return (double)p.dotw[i] * (double)u;
+    out = xself + dd;
+    if constexpr (DOT) return (double)p.dotw[i] * (double)out;
     return 0.0;
   } else {  // CgQ
-    p.out[i] = z;
+    out = z;
     return (double)xself * (double)z;
   }
+}
+
+// The same, written to dof i.
+template <StencilOp OP, bool DOT, class V, bool OWN = false>
+__device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre = (V)0) {
+  V out, dd = (V)0;
+  const double c = finish_value<OP, DOT, V, OWN>(p, i, z, m, xself, centre, out, dd);
+  if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) p.d[i] = dd;
+  p.out[i] = out;
+  return c;
 }
 
 // Coefficient (s, a, b) of node gi; the bfloat16 storage keeps its centre block in FP32.
@@ -347,10 +357,16 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
     for (int a = 0; a < NDOF; ++a) {
       V s = (V)0;
       for (int64_t c = a0; c < e; ++c) s += p.out[(int64_t)gcopy[c] * NDOF + a];
+      // the copies of a composite dof hold equal b, x, d and D~^-1 (consistent regional vectors),
+      // so the update is computed from the first copy (the lowest region, which owns the dof) and
+      // written to every copy
+      const int64_t i0 = (int64_t)gcopy[a0] * NDOF + a;
+      V out, dd = (V)0;
+      contrib += finish_value<OP, DOT, V>(p, i0, s, m, p.x[i0], (V)0, out, dd);
       for (int64_t c = a0; c < e; ++c) {
         const int64_t i = (int64_t)gcopy[c] * NDOF + a;
-        const double v = finish<OP, DOT, V>(p, i, s, m, p.x[i]);
-        if (c == a0) contrib += v;  // the first copy (lowest region) owns the composite dof
+        if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) p.d[i] = dd;
+        p.out[i] = out;
       }
     }
   }
