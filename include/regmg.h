@@ -281,7 +281,10 @@ rmg_status rmg_interface_sum(rmg_handle* h, int level, const double* v, double* 
 rmg_status rmg_restrict(rmg_handle* h, int level, const double* r, double* w);
 /* Fine u += P^(r) ubar from level+1 to level (Section 3.3). */
 rmg_status rmg_prolongate_add(rmg_handle* h, int level, const double* ubar, double* u);
-/* u = S(b): one degree-K Chebyshev application with zero initial guess. */
+/* u = S(b): one degree-K Chebyshev application with zero initial guess.  b must be
+ * consistent (every copy of a composite dof holds the same value), as the cycle's
+ * right-hand sides are: the update of a shared dof is computed once, from the
+ * copy in the lowest region, and written to every copy. */
 rmg_status rmg_smooth(rmg_handle* h, int level, const double* b, double* u);
 
 /* Level data.  n_regional / n_composite count dofs. */
