@@ -45,8 +45,8 @@ ALGO_COEFS = 27
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
 # source they were taken with.
-TRAFFIC_BYTES = 5900226311
-TRAFFIC_KERNEL_SHA = "b4d4bfbd98de7726"
+TRAFFIC_BYTES = 5818470379
+TRAFFIC_KERNEL_SHA = "08cca5b89259bd3e"
 
 CPU_SAMPLE = r"""
 import json, sys, time
@@ -490,8 +490,11 @@ def _to_dev(a, dev):
 def kernel_source_sha():
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2103_11962_amd", "csrc", "kernels_stencil.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    # the stencil kernels, and the planner and solver sources that fix their tiles and launch shapes
+    sha = hashlib.sha256()
+    for name in ("kernels_stencil.hip", "planner.cpp", "solver.cpp"):
+        sha.update(open(os.path.join(ROOT, "paper_2103_11962_amd", "csrc", name), "rb").read())
+    return sha.hexdigest()[:16]
 
 
 def copy_rate_gbs():

@@ -77,7 +77,8 @@ typedef struct {
   int power_iters;    /* power iterations for lambda_max(D~^-1 A) (default 10) */
   uint64_t seed;      /* seed of the counter-based power-method start vector */
   int precision;      /* rmg_precision */
-  int stencil_kernel; /* 3D stencil kernel: 0 auto (2.5D tiles on levels with >= 2048 tiles),
+  int stencil_kernel; /* 3D stencil kernel: 0 auto (2.5D tiles on levels with >= 2048 tiles of
+                         21 planes; FP64 tiles are 41 planes deep where that still leaves >= 1024),
                          1 node-parallel, 2 2.5D plane-marching tiles (one block per tile),
                          3 the same tiles in a persistent grid (blocks stride over the tiles) */
   int autotune;       /* 1: at setup, time the scalar 3D stencil variants (node-parallel; 2.5D tiles

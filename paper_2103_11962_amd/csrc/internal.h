@@ -84,6 +84,7 @@ struct BlockDesc {
 constexpr int kBlock = 256;  // threads per block for node-parallel kernels
 
 constexpr size_t kAutoTileMin = 2048;  // 2.5D tiles needed on a level before they are used by default
+constexpr size_t kDeepTileMin = 1024;  // 41-plane FP64 tiles needed before they replace 21-plane ones
 
 // Threads per 2.5D tile block.  The FP64 kernel needs about 142 VGPRs (3 waves per SIMD), so a
 // 768-thread block (12 waves) is the widest that fits and one block runs per CU; the FP32 kernel

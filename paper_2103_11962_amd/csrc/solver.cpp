@@ -217,15 +217,23 @@ static void autotune_level(rmg_handle* h, Level& L, int level, bool lowp) {
 // Launch configuration, work vectors and symmetric half-stencil copy of one stencil level.
 static void configure_level(rmg_handle* h, Level& L, bool with_b, bool sym) {
   const rmg_options& o = h->opt;
-  const int threads = o.precision == RMG_PREC_FP64 ? kTileThreadsF64 : kTileThreadsF32;
+  const bool fp64 = o.precision == RMG_PREC_FP64;
+  const int threads = fp64 ? kTileThreadsF64 : kTileThreadsF32;
   if (L.dim == 3 && (L.tile_depth != 21 || L.tile_threads != threads)) {
     L.tile_threads = threads;
     make_tiles(L, 21);
   }
+  const size_t tiles21 = L.tiles.size();
+  // FP64 tiles run one block per CU: on a level large enough for tiles, 41-plane tiles read two
+  // halo planes per 41 instead of per 21, kept while they still give every CU four or more.
+  if (L.dim == 3 && fp64 && tiles21 >= kAutoTileMin) {
+    make_tiles(L, 41);
+    if (L.tiles.size() < kDeepTileMin) make_tiles(L, 21);
+  }
   L.tile_grid = 0;
   L.per_region = o.batched == 0;
   L.use_tiles = !L.per_region && L.ndof == 1 && !L.tiles.empty() &&
-                (o.stencil_kernel >= 2 || (o.stencil_kernel == 0 && L.tiles.size() >= kAutoTileMin));
+                (o.stencil_kernel >= 2 || (o.stencil_kernel == 0 && tiles21 >= kAutoTileMin));
   // persistent tiles: 4 blocks per CU, and at least two tiles per block
   if (L.use_tiles && o.stencil_kernel == 3) L.tile_grid = std::max(1, std::min(1024, (int)(L.tiles.size() + 1) / 2));
   alloc_vectors(L, with_b);
