@@ -43,8 +43,8 @@ def cg_matvec_bytes_per_row(coefs):
 
 ALGO_COEFS = 27
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
-# plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only for the kernel
-# source they were taken with.
+# plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only while the kernel
+# source and the planner and solver sources that fix its tiles are the ones they were taken with.
 TRAFFIC_BYTES = 5818470379
 TRAFFIC_KERNEL_SHA = "08cca5b89259bd3e"
 
