@@ -136,6 +136,16 @@ typedef struct {
                          after each coarse correction, and a dense inverse on the first AMG level
                          with at most amg_coarse_size rows */
   int amg_coarse_size; /* rows of the directly solved AMG level, in [1, 20000] (default 2000) */
+  int region_table;   /* 1 (default): on FP64 levels run by the symmetric 2.5D kernel on 768-thread
+                         tiles (the FP64 V-cycle; the FP32 V-cycle's narrower tiles gained nothing
+                         from it and always stream), setup compares the
+                         stored upper couplings of every node two or more nodes inside its region
+                         (all 27 neighbours then lie inside the region) with those of the node
+                         (2, 2, 2); where all are equal bit for bit (a constant-coefficient
+                         region, as the structured regions of the Q1 Laplacian, the per-region
+                         diffusion and elasticity problems give), the kernel takes them from a
+                         14-value table of the region instead of streaming them from memory.
+                         Results are bit for bit those of 0, which always streams them */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -298,6 +308,9 @@ rmg_status rmg_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t
  * symmetric 27-point stencil); coefs_lo = the same for the low-precision
  * V-cycle copy (0 when there is none).  Any output may be NULL. */
 rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, int* coefs_lo);
+/* Regions of `level` whose interior couplings the symmetric 2.5D kernel takes from the region table
+ * (rmg_options.region_table); 0 where no table was built.  Output may be NULL. */
+rmg_status rmg_level_table_regions(rmg_handle* h, int level, int* nregions);
 /* Copy region `region`'s stencil on `level` to host memory in the layout of
  * rmg_set_region_stencil (npts 27 in 3D, 9 in 2D, all levels). */
 rmg_status rmg_get_level_stencil(rmg_handle* h, int level, int region, double* host_out);

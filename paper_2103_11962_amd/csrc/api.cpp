@@ -157,6 +157,7 @@ void rmg_options_default(rmg_options* o) {
   o->cycle_gamma = 1;
   o->coarse_amg = 0;
   o->amg_coarse_size = 2000;
+  o->region_table = 1;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -244,6 +245,8 @@ rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const dou
   Level& L = level_of(h, 0);
   L.coef_sym.release();  // the half stencils of the old operator
   L.coef_lo_sym.release();
+  L.sym_table.release();
+  L.sym_table_ok.release();
   RMG_REQUIRE(region >= 0 && region < h->nreg, RMG_ERR_ARG, "region index out of range");
   RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
   const bool ok = (h->dim == 3 && npts == 27) || (h->dim == 2 && (npts == 5 || npts == 9));
@@ -333,6 +336,8 @@ rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef
   Level& L = level_of(h, 0);
   L.coef_sym.release();  // the half stencils of the old operator
   L.coef_lo_sym.release();
+  L.sym_table.release();
+  L.sym_table_ok.release();
   RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
   check_composite_split(h, npts);
   DBuf tmp;
@@ -353,6 +358,8 @@ rmg_status rmg_set_composite_csr(rmg_handle* h, int npts, int64_t nnz, const int
   Level& L = level_of(h, 0);
   L.coef_sym.release();  // the half stencils of the old operator
   L.coef_lo_sym.release();
+  L.sym_table.release();
+  L.sym_table_ok.release();
   RMG_REQUIRE(rowptr && (nnz == 0 || (colind && values)) && nnz >= 0, RMG_ERR_ARG, "null CSR array or nnz < 0");
   check_composite_split(h, npts);
   const int64_t n = L.ncomp;
@@ -407,6 +414,8 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
   Level& L = level_of(h, 0);
   L.coef_sym.release();  // the half stencils of the old operator
   L.coef_lo_sym.release();
+  L.sym_table.release();
+  L.sym_table_ok.release();
   RMG_REQUIRE(h->dim == 3, RMG_ERR_ARG, "Q1 assembly needs a 3D layout");
   RMG_REQUIRE(hsize > 0.0 && std::isfinite(hsize), RMG_ERR_ARG, "element size must be positive");
   RMG_REQUIRE(pde == RMG_PDE_LAPLACE || pde == RMG_PDE_DIFFUSION || pde == RMG_PDE_ELASTICITY, RMG_ERR_ARG,
@@ -474,6 +483,7 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 3, RMG_ERR_ARG, "stencil_kernel must be 0..3");
   RMG_REQUIRE(opt->batched == 0 || opt->batched == 1, RMG_ERR_ARG, "batched must be 0 or 1");
   RMG_REQUIRE(opt->symmetric == 0 || opt->symmetric == 1, RMG_ERR_ARG, "symmetric must be 0 or 1");
+  RMG_REQUIRE(opt->region_table == 0 || opt->region_table == 1, RMG_ERR_ARG, "region_table must be 0 or 1");
   RMG_REQUIRE(opt->smoother >= 0 && opt->smoother <= 4, RMG_ERR_ARG,
               "smoother must be 0 (Chebyshev), 1 (Jacobi), 2 (Gauss-Seidel), 3 (forward/backward "
               "Gauss-Seidel) or 4 (symmetric Gauss-Seidel)");
@@ -682,6 +692,22 @@ rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, i
   // the 2.5D kernel has no half-stencil path for BF16 storage
   const bool sym_lo = L.coef_lo_sym.p && !(tiled && L.ct_lo == kCoefBF16);
   if (coefs_lo) *coefs_lo = L.ct_lo == kCoefF64 ? 0 : (sym_lo ? kSymPts * nb : L.ncoef());
+  API_END
+}
+
+rmg_status rmg_level_table_regions(rmg_handle* h, int level, int* nregions) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  const DBuf& ok = L.sym_table_ok;
+  int count = 0;
+  if (ok.p) {
+    std::vector<int> flags(L.nreg);
+    RMG_HIP(hipStreamSynchronize(h->stream));
+    RMG_HIP(hipMemcpy(flags.data(), ok.p, sizeof(int) * L.nreg, hipMemcpyDeviceToHost));
+    for (int f : flags) count += f != 0;
+  }
+  if (nregions) *nregions = count;
   API_END
 }
 

@@ -173,6 +173,10 @@ struct Level {
   // operator (FP64, wave-tiled, ncoef() values per node: npts blocks of ndof x ndof)
   DBuf coef;
   DBuf coef_sym;     // symmetric scalar 27-point levels: the upper half (kSymPts per node), else empty
+  // per region: the upper couplings shared by every node two or more nodes inside the region
+  // (kSymPts values from coef_sym) and a flag that they all agree; built for FP64 levels run by
+  // 768-thread 2.5D tiles, else empty
+  DBuf sym_table, sym_table_ok;
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
   DBuf pw;        // stored interpolation weights to the next level, double [n][8] (null: geometric)
   DBuf rw;        // with pw: the same weights per coarse node (125 taps, wave-tiled) for the restriction

@@ -88,7 +88,7 @@ void launch_make_lowp(Level& L, int coef_type, hipStream_t st);
 // symmetric to rounding: L.coef_sym, or with lowp L.coef_lo_sym from the low-precision copy of a
 // level that has L.coef_sym; returns false (and leaves the copy empty) otherwise.  The stencil
 // kernels then stream 14 instead of 27 blocks per node.
-bool launch_make_sym(Level& L, bool lowp, hipStream_t st);
+bool launch_make_sym(Level& L, bool lowp, hipStream_t st, bool table);
 
 // Composite <-> regional (FP64).
 void launch_to_regional(const Level& L, const double* comp, double* reg, hipStream_t st);

@@ -1400,6 +1400,62 @@ __global__ __launch_bounds__(kBlock) void k_make_sym(LevelView L, const C* __res
   if (bad) atomicOr(flag, 1);
 }
 
+// Region table of the symmetric 2.5D kernel: the upper couplings of node (2, 2, 2) of every region
+// with at least 5 nodes a side (one block per region), then every node two or more nodes inside its
+// region (x, y, z in [2, extent - 3]) compares its own with them bit for bit and clears the
+// region's flag on a difference.
+__device__ __forceinline__ bool same_bits(double a, double b) { return __double_as_longlong(a) == __double_as_longlong(b); }
+__device__ __forceinline__ bool same_bits(float a, float b) { return __float_as_int(a) == __float_as_int(b); }
+
+template <class C>
+__global__ void k_sym_table_ref(LevelView L, const C* __restrict__ sym, C* __restrict__ table, int* __restrict__ ok) {
+  const int k = blockIdx.x, s = threadIdx.x;
+  const RegionGeo R = L.regs[k];
+  const bool deep = R.ex >= 5 && R.ey >= 5 && R.ez >= 5;
+  if (s < kSymPts)
+    table[k * kSymPts + s] = deep ? sym[coef_index(R.off + 2 + 2 * R.ex + 2 * (int64_t)R.ex * R.ey, s, kSymPts)] : (C)0;
+  if (s == 0) ok[k] = deep ? 1 : 0;
+}
+
+template <class C>
+__global__ __launch_bounds__(kBlock) void k_sym_table_check(LevelView L, const C* __restrict__ sym,
+                                                            const C* __restrict__ table, int* __restrict__ ok) {
+  const BlockDesc bd = L.blocks[blockIdx.x];
+  const RegionGeo R = L.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= R.n) return;
+  int x, y, z;
+  decompose(R, li, x, y, z);
+  if (x < 2 || x >= R.ex - 2 || y < 2 || y >= R.ey - 2 || z < 2 || z >= R.ez - 2) return;
+  const int64_t gi = R.off + li;
+  bool same = true;
+  for (int s = 0; s < kSymPts; ++s) same = same && same_bits(sym[coef_index(gi, s, kSymPts)], table[bd.region * kSymPts + s]);
+  if (!same) ok[bd.region] = 0;
+}
+
+template <class C>
+static void make_sym_table(Level& L, hipStream_t st) {
+  DBuf& tab = L.sym_table;
+  DBuf& ok = L.sym_table_ok;
+  const C* sym = static_cast<const C*>(L.coef_sym.p);
+  tab.alloc(sizeof(C) * kSymPts * L.nreg);
+  ok.alloc(sizeof(int) * L.nreg);
+  hipLaunchKernelGGL((k_sym_table_ref<C>), dim3(L.nreg), dim3(64), 0, st, L.view(), sym, tab.as<C>(), ok.as<int>());
+  hipLaunchKernelGGL((k_sym_table_check<C>), dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
+                     static_cast<const C*>(tab.p), ok.as<int>());
+  LAUNCH_CHECK();
+  // no region served: drop the table, so the kernel without it runs
+  std::vector<int> flags(L.nreg);
+  RMG_HIP(hipMemcpyAsync(flags.data(), ok.p, sizeof(int) * L.nreg, hipMemcpyDeviceToHost, st));
+  RMG_HIP(hipStreamSynchronize(st));
+  int served = 0;
+  for (int f : flags) served += f != 0;
+  if (served == 0) {
+    tab.release();
+    ok.release();
+  }
+}
+
 template <int NDOF>
 static void make_sym_t(Level& L, bool lowp, int* flag, hipStream_t st) {
   const size_t ne = coef_elems(L.n, kSymPts * NDOF * NDOF);
@@ -1420,9 +1476,13 @@ static void make_sym_t(Level& L, bool lowp, int* flag, hipStream_t st) {
   LAUNCH_CHECK();
 }
 
-bool launch_make_sym(Level& L, bool lowp, hipStream_t st) {
+bool launch_make_sym(Level& L, bool lowp, hipStream_t st, bool table) {
   DBuf& out = lowp ? L.coef_lo_sym : L.coef_sym;
   out.release();
+  if (!lowp) {
+    L.sym_table.release();
+    L.sym_table_ok.release();
+  }
   if (L.dim != 3 || L.npts != 27) return false;
   if (lowp) {
     // the low-precision copy rounds the same symmetric values: copy its upper half
@@ -1440,6 +1500,7 @@ bool launch_make_sym(Level& L, bool lowp, hipStream_t st) {
   RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));
   if (hflag) out.release();
+  else if (table && L.ndof == 1) make_sym_table<double>(L, st);
   return hflag == 0;
 }
 

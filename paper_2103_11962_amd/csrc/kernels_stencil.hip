@@ -167,11 +167,15 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
 // streams its node's 14 couplings once and leaves the ones its neighbours need in LDS: the
 // couplings towards z+1 for the next plane, the in-plane ones for this plane.  Only neighbours
 // outside the tile (its edge rows, and plane z-1 of the tile's first plane) are read from memory,
-// so HBM carries about 14 instead of 27 coefficients per node.
+// so HBM carries about 14 instead of 27 coefficients per node.  TAB: with the region table (the
+// region's flag set), a node two or more nodes inside its region takes its 14 couplings
+// from the table, which equals every such node's stored ones bit for bit, and the memory read is
+// skipped; neighbours read from memory are served the same way.
 // NT threads per block (the level's tile_threads); tiles hold at most NT nodes.
-template <int NT, class V, class C, StencilOp OP, bool DOT, bool SYM>
+template <int NT, class V, class C, StencilOp OP, bool DOT, bool SYM, bool TAB = false>
 __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles, int ntiles,
                                                   const C* __restrict__ coef, const float* __restrict__ centre,
+                                                  const C* __restrict__ table, const int* __restrict__ table_ok,
                                                   OpP<V> p, double* __restrict__ partials) {
   constexpr int kT3 = NT;
   constexpr int kT3Plane = tile_plane_cap(NT);
@@ -259,13 +263,29 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
         auto in_tile = [&](int dx, int dy) {
           return (unsigned)(tx + dx) < (unsigned)T.tx && (unsigned)(ty + dy) < (unsigned)T.ty;
         };
-        auto mirror = [&](int s, int dx, int dy, int dz) {  // A(i + offset(s), i) from memory
+        bool rtab = false;
+        const C* __restrict__ tab = nullptr;
+        if constexpr (TAB) {
+          rtab = table_ok[T.region] != 0;
+          tab = table + T.region * kSymPts;
+        }
+        auto deep = [&](int xx, int yy, int z2) {
+          if constexpr (!TAB) return false;
+          return rtab && xx >= 2 && xx < R.ex - 2 && yy >= 2 && yy < R.ey - 2 && z2 >= 2 && z2 < R.ez - 2;
+        };
+        auto mirror = [&](int s, int dx, int dy, int dz) {  // A(i + offset(s), i) from the table or memory
+          if (deep(x + dx, y + dy, zz + dz)) return (V)CoefLoad<C>::get(tab + 13 - s);
           return (V)CoefLoad<C>::get(coef + coef_index(gi + dx + dy * sy + dz * sz, 13 - s, kSymPts));
         };
         if (active) {
-          const C* __restrict__ cf = coef + coef_index(gi, 0, kSymPts);
+          if (deep(x, y, zz)) {
 #pragma unroll
-          for (int k = 0; k < kSymPts; ++k) up[k] = (V)CoefLoad<C>::get(cf + k * kTile);
+            for (int k = 0; k < kSymPts; ++k) up[k] = (V)CoefLoad<C>::get(tab + k);
+          } else {
+            const C* __restrict__ cf = coef + coef_index(gi, 0, kSymPts);
+#pragma unroll
+            for (int k = 0; k < kSymPts; ++k) up[k] = (V)CoefLoad<C>::get(cf + k * kTile);
+          }
 #pragma unroll
           for (int s = 0; s < 9; ++s) {  // z-1: the neighbour's coupling towards z+1
             const int dx = s % 3 - 1, dy = s / 3 - 1;
@@ -391,16 +411,33 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   if constexpr (NPTS == 27 && NDOF == 1) {
     if (tiled) {
       const C* sym = nullptr;
-      if constexpr (std::is_same<V, C>::value) sym = static_cast<const C*>(a.lowp ? L.coef_lo_sym.p : L.coef_sym.p);
+      const C* table = nullptr;
+      const int* table_ok = nullptr;
+      if constexpr (std::is_same<V, C>::value) {
+        sym = static_cast<const C*>(a.lowp ? L.coef_lo_sym.p : L.coef_sym.p);
+        // the region table serves the FP64 operator on 768-thread tiles
+        if (!a.lowp && L.tile_threads == kTileThreadsF64 && L.sym_table.p && L.sym_table_ok.p) {
+          table = static_cast<const C*>(L.sym_table.p);
+          table_ok = static_cast<const int*>(L.sym_table_ok.p);
+        }
+      }
       auto launch3d = [&](auto nt) {
         constexpr int NT = decltype(nt)::value;
         if (sym) {
-          if constexpr (std::is_same<V, C>::value)
+          if constexpr (std::is_same<V, C>::value) {
+            if constexpr (NT == kTileThreadsF64 && std::is_same<V, double>::value) {
+              if (table) {
+                hipLaunchKernelGGL((k_stencil3d<NT, V, C, OP, DOT, true, true>), dim3(grid3), dim3(NT), 0, st, v,
+                                   L.d_tiles.as<Tile3>(), ntiles, sym, centre, table, table_ok, p, a.partials);
+                return;
+              }
+            }
             hipLaunchKernelGGL((k_stencil3d<NT, V, C, OP, DOT, true>), dim3(grid3), dim3(NT), 0, st, v,
-                               L.d_tiles.as<Tile3>(), ntiles, sym, centre, p, a.partials);
+                               L.d_tiles.as<Tile3>(), ntiles, sym, centre, nullptr, nullptr, p, a.partials);
+          }
         } else {
           hipLaunchKernelGGL((k_stencil3d<NT, V, C, OP, DOT, false>), dim3(grid3), dim3(NT), 0, st, v,
-                             L.d_tiles.as<Tile3>(), ntiles, coef, centre, p, a.partials);
+                             L.d_tiles.as<Tile3>(), ntiles, coef, centre, nullptr, nullptr, p, a.partials);
         }
       };
       if constexpr (sizeof(V) == 8) {

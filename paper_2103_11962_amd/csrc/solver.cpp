@@ -241,8 +241,13 @@ static void configure_level(rmg_handle* h, Level& L, bool with_b, bool sym) {
   L.coef_lo.release();
   L.center_lo.release();
   L.coef_lo_sym.release();
-  if (sym) launch_make_sym(L, false, h->stream);
-  else L.coef_sym.release();
+  if (sym) {
+    launch_make_sym(L, false, h->stream, o.region_table != 0 && L.use_tiles && L.tile_threads == kTileThreadsF64);
+  } else {
+    L.coef_sym.release();
+    L.sym_table.release();
+    L.sym_table_ok.release();
+  }
 }
 
 void prepare_finest(rmg_handle* h) {
@@ -319,7 +324,7 @@ static int build_levels(rmg_handle* h, bool stored) {
     // the V-cycle's copy of this level's operator, made after the Galerkin product used it
     if (lowp) {
       launch_make_lowp(L, (l == 0 && o.precision == RMG_PREC_FP32_BF16) ? kCoefBF16 : kCoefF32, st);
-      if (o.symmetric) launch_make_sym(L, true, st);
+      if (o.symmetric) launch_make_sym(L, true, st, false);
     }
     if (o.autotune && !L.per_region && L.dim == 3 && L.ndof == 1 && L.npts == 27) autotune_level(h, L, l, lowp);
   }

@@ -40,6 +40,7 @@ SYMBOLS = (
     "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr", "rmg_mg_solve",
     "rmg_mlp_set_loss", "rmg_set_region_kinds", "rmg_hybrid_level_info", "rmg_hybrid_aggregates",
     "rmg_hybrid_composite_ids", "rmg_hybrid_matrix", "rmg_amg_levels", "rmg_amg_level_info", "rmg_amg_matrix",
+    "rmg_level_table_regions",
 )
 SMOOTHER_CHEBYSHEV, SMOOTHER_JACOBI, SMOOTHER_GS, SMOOTHER_GS_FB, SMOOTHER_SYMGS = 0, 1, 2, 3, 4
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
@@ -71,6 +72,7 @@ class Options(ctypes.Structure):
         ("cycle_gamma", ctypes.c_int),
         ("coarse_amg", ctypes.c_int),
         ("amg_coarse_size", ctypes.c_int),
+        ("region_table", ctypes.c_int),
     ]
 
 
@@ -183,6 +185,7 @@ def load():
         "rmg_mlp_init_params": (I, [H, ctypes.c_uint64, D, P]),
         "rmg_level_kernel": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "rmg_set_composite_csr": (I, [H, I, ctypes.c_int64, P, P, P, I]),
+        "rmg_level_table_regions": (I, [H, I, ctypes.POINTER(I)]),
         "rmg_mg_solve": (I, [H, P, P, I, D, I, ctypes.POINTER(SolveInfo)]),
         "rmg_mlp_set_loss": (I, [H, I]),
         "rmg_set_region_kinds": (I, [H, P]),
@@ -437,6 +440,11 @@ class Handle:
         k, c, cl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(load().rmg_level_kernel(self._h, level, ctypes.byref(k), ctypes.byref(c), ctypes.byref(cl)))
         return {"kernel": k.value, "coefs": c.value, "coefs_lo": cl.value}
+
+    def level_table_regions(self, level):
+        n = ctypes.c_int()
+        _check(load().rmg_level_table_regions(self._h, level, ctypes.byref(n)))
+        return n.value
 
     def level_stencil(self, level, region, npts, nnodes):
         out = np.zeros(npts * nnodes)
