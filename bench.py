@@ -45,8 +45,8 @@ ALGO_COEFS = 27
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
 # plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only while the kernel
 # source and the planner and solver sources that fix its tiles are the ones they were taken with.
-TRAFFIC_BYTES = 2790401508
-TRAFFIC_KERNEL_SHA = "8ec562497ec9a93f"
+TRAFFIC_BYTES = 2811027189
+TRAFFIC_KERNEL_SHA = "957da7231ead3eb9"
 
 CPU_SAMPLE = r"""
 import json, sys, time
@@ -662,6 +662,9 @@ def main():
             # the bytes the kernel stores and streams (upper half of the symmetric stencil), and the
             # HBM rate the counters measured: the same launches seen from the memory side
             "stored_bytes_per_row": round(stored_bpr, 2),
+            "note": ("frac prices the method's 264 B/row (the whole operator streamed); with the region "
+                     "table the kernel streams stored_bytes_per_row, so frac can exceed 1: counted_hbm_gbs "
+                     "and frac_at_stored_bytes give how hard it drives HBM") if table_regions else None,
             "achieved_at_stored_bytes": achieved_stored,
             "frac_at_stored_bytes": achieved_stored / HBM_PEAK_GBS,
             "counted_hbm_gbs": traffic / (avg_cheb * 1e-3) / 1e9 if traffic else None,

@@ -66,6 +66,32 @@ __device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m,
   return c;
 }
 
+// The same with b_i and the old direction d_i already in registers (read a plane ahead); the
+// arithmetic is finish_value's.
+template <StencilOp OP, bool DOT, class V, bool OWN = false>
+__device__ __forceinline__ double finish_pre(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre, V bi, V dold) {
+  if constexpr (OP == StencilOp::Residual) {
+    p.out[i] = bi - z;
+    return 0.0;
+  } else if constexpr (OP == StencilOp::ResidualScaled) {
+    const V r = bi - z;
+    p.out[i] = (m == 1) ? r : r / (V)m;
+    return 0.0;
+  } else if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) {
+    const V r = bi - z;
+    const V di = OWN ? (V)1 / centre : p.dinv[i];
+    V dd = p.c2 * (di * r);
+    if constexpr (OP == StencilOp::Cheb) dd = p.c1 * dold + dd;
+    const V out = xself + dd;
+    p.d[i] = dd;
+    p.out[i] = out;
+    if constexpr (DOT) return (double)p.dotw[i] * (double)out;
+    return 0.0;
+  } else {
+    return finish<OP, DOT, V, OWN>(p, i, z, m, xself, centre);
+  }
+}
+
 // Coefficient (s, a, b) of node gi; the bfloat16 storage keeps its centre block in FP32.
 template <int NPTS, int NDOF, class C>
 __device__ __forceinline__ auto coefv(const C* __restrict__ cf, const float* __restrict__ centre, int64_t gi, int s,
@@ -231,6 +257,19 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
       }
     };
     const int z0 = T.z0, z1 = T.z0 + T.nz;
+    // SYM: b and the old direction of this thread's node on the next plane, read a plane ahead
+    constexpr bool kPreB = SYM && (OP == StencilOp::Residual || OP == StencilOp::ResidualScaled ||
+                                   OP == StencilOp::Cheb || OP == StencilOp::ChebFirst);
+    constexpr bool kPreD = SYM && OP == StencilOp::Cheb;
+    V nb = (V)0, nd = (V)0;
+    auto load_bd = [&](int z2) {
+      if (active && z2 < z1) {
+        const int64_t g = R.off + (int64_t)z2 * sz + (int64_t)y * sy + x;
+        if constexpr (kPreB) nb = p.b[g];
+        if constexpr (kPreD) nd = p.d[g];
+      }
+    };
+    if constexpr (kPreB) load_bd(z0);
     fetch(z0 - 1);
     store(0);
     fetch(z0);
@@ -246,6 +285,8 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
     __syncthreads();
     for (int zz = z0; zz < z1; ++zz) {
       const int sp = (zz - z0) & 1;  // slot holding plane zz+1
+      const V cb = nb, cd = nd;
+      if constexpr (kPreB) load_bd(zz + 1);
       if (active) readn(sp, rp);
       fetch(zz + 2);
       // SYM: own upper couplings u[k] = A(i, i + offset(13 + k)); lower couplings lo[s] = A(i, i +
@@ -339,6 +380,7 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
         }
         const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
         if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
+        else if constexpr (kPreB) contrib += finish_pre<OP, DOT, V, kOwnDiag>(p, gi, acc, 1, rc[4], ctr, cb, cd);
         else contrib += finish<OP, DOT, V, kOwnDiag>(p, gi, acc, 1, rc[4], ctr);
       }
       store(sp ^ 1);  // plane zz+2 replaces plane zz
