@@ -158,7 +158,10 @@ def pcg(levels, b, opt: Options, rtol=1e-8, maxit=200):
         it += 1
         hist.append(np.linalg.norm(r) / bnorm)
         if hist[-1] <= rtol:
-            break
+            rt = b - A @ x  # accepted only if the true residual agrees (residual replacement)
+            if np.linalg.norm(rt) / bnorm <= rtol:
+                break
+            r = rt
         z = vcycle(levels, r, opt)
         rz_new = r @ z
         p = z + (rz_new / rz) * p

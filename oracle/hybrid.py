@@ -396,7 +396,11 @@ def pcg(levels, b, opt: HOptions, rtol=1e-6, maxit=100):
         r = [rk - alpha * qk for rk, qk in zip(r, q)]
         hist.append(L.norm(r) / bnorm)
         if hist[-1] <= rtol:
-            break
+            # accepted only if the true residual b - A x agrees; else CG continues from it
+            rt = [bk - ak for bk, ak in zip(b, L.matvec(x))]
+            if L.norm(rt) / bnorm <= rtol:
+                break
+            r = rt
         z = cycle(levels, r, opt)
         beta = dot(z, [a - c for a, c in zip(r, r_old)]) / rz
         rz = dot(r, z)

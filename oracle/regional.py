@@ -24,8 +24,9 @@ Readings of points the paper leaves open:
   sweep per iteration, before and after.  The damping omega of Algorithm 1 is
   ``jacobi_omega``.
 * CG: textbook Hestenes-Stiefel with x0 = 0, preconditioner z = V(r, 0),
-  stopping on the recursive residual ||r||/||b|| <= rtol.  Inner products are
-  composite ones: every composite dof counted once.
+  stopping when the recursive residual ||r||/||b|| <= rtol and the true residual
+  ||b - A x||/||b|| agrees (else r is replaced by the true residual and CG goes
+  on).  Inner products are composite ones: every composite dof counted once.
 """
 from __future__ import annotations
 
@@ -303,8 +304,14 @@ def pcg(levels, b, opt: Options, rtol=1e-8, maxit=200, precondition=True):
         rel = lay.norm(r) / bnorm
         hist.append(rel)
         if rel <= rtol:
-            converged = True
-            break
+            # the tolerance is on the relative residual of the system, so the recursively
+            # updated residual is checked against b - A x before the solve ends; where rounding
+            # has separated them, CG goes on from the true residual (residual replacement)
+            rt = L.residual(b, x)
+            if lay.norm(rt) / bnorm <= rtol:
+                converged = True
+                break
+            r = rt
         z = vcycle(levels, r, opt) if precondition else [ri.copy() for ri in r]
         rz_new = lay.dot(r, z)
         beta = rz_new / rz
