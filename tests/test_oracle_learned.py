@@ -42,6 +42,54 @@ def test_gradient_matches_central_differences():
         assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])), (i, fd, g[i])
 
 
+def test_forward_hand_computed_network():
+    """A network worked by hand: sparse weights, non-zero biases on every layer and negative
+    pre-activations in both hidden layers, so each ReLU, each bias, the layer order and the
+    orientation of every weight matrix change the logits if done wrong.  The flat parameter
+    vector is laid out here from the documented order (W1 64x27 row-major, b1, W2 64x64, b2,
+    W3 208x64, b3), not through the oracle's own unpacking."""
+    nin, nh, nout = 27, 64, 208
+    theta = np.zeros(nh * nin + nh + nh * nh + nh + nout * nh + nout)
+    oW1, ob1 = 0, nh * nin
+    oW2, ob2 = ob1 + nh, ob1 + nh + nh * nh
+    oW3, ob3 = ob2 + nh, ob2 + nh + nout * nh
+    # layer 1: a1_0 = x0 + x1 + 0.5 = -0.5 (ReLU -> 0); a1_1 = 2 x0 + 0.25 = 2.25;
+    #          a1_2 = -x1 - 3 = -1 (ReLU -> 0)
+    theta[oW1 + 0 * nin + 0] = 1.0
+    theta[oW1 + 0 * nin + 1] = 1.0
+    theta[ob1 + 0] = 0.5
+    theta[oW1 + 1 * nin + 0] = 2.0
+    theta[ob1 + 1] = 0.25
+    theta[oW1 + 2 * nin + 1] = -1.0
+    theta[ob1 + 2] = -3.0
+    # layer 2: a2_0 = 100 h1_0 + 2 h1_1 - 7 h1_2 - 1 = 3.5; a2_1 = -h1_1 + 0.5 = -1.75 (ReLU -> 0);
+    #          W2[1, 0] = 5 would move h1_0 into a2_1 if W2 were applied transposed: it is 0 there
+    theta[oW2 + 0 * nh + 0] = 100.0
+    theta[oW2 + 0 * nh + 1] = 2.0
+    theta[oW2 + 0 * nh + 2] = -7.0
+    theta[ob2 + 0] = -1.0
+    theta[oW2 + 1 * nh + 1] = -1.0
+    theta[ob2 + 1] = 0.5
+    theta[oW2 + 1 * nh + 0] = 5.0
+    # layer 3: z_0 = h2_0 + 10 h2_1 + 0.125 = 3.625; z_5 = -2 h2_0 + b3_5 = -7 + 0.05;
+    #          every other z_k = b3_k = 0.01 k
+    theta[oW3 + 0 * nh + 0] = 1.0
+    theta[oW3 + 0 * nh + 1] = 10.0
+    theta[oW3 + 5 * nh + 0] = -2.0
+    theta[ob3:ob3 + nout] = 0.01 * np.arange(nout)
+    theta[ob3 + 0] = 0.125
+    X = np.zeros((2, nin))
+    X[0, 0], X[0, 1] = 1.0, -2.0  # sample 0 as above
+    # sample 1: x0 = -1: a1_0 = -0.5 -> 0, a1_1 = -1.75 -> 0, a1_2 = -3 -> 0; a2_0 = -1 -> 0,
+    # a2_1 = 0.5; z_0 = 10 * 0.5 + 0.125 = 5.125, z_5 = 0.05
+    X[1, 0] = -1.0
+    z, _ = learned.forward(theta, X)
+    expect = np.tile(0.01 * np.arange(nout), (2, 1))
+    expect[0, 0], expect[0, 5] = 3.625, -7.0 + 0.05
+    expect[1, 0], expect[1, 5] = 5.125, 0.05
+    np.testing.assert_allclose(z, expect, rtol=0, atol=1e-14)
+
+
 def test_softmax_weights_partition_of_unity():
     X = np.random.default_rng(4).standard_normal((7, 27))
     z, _ = learned.forward(random_theta(2), X)

@@ -324,7 +324,34 @@ def test_power_method_bounds():
     d = np.diag(Af)
     lmax = np.linalg.eigvalsh(Af / np.sqrt(np.outer(d, d))).max()
     assert lv[0].lam <= lmax * (1 + 1e-12)
-    assert lv[0].lam >= 0.9 * lmax  # sanity: 10 iterations land within 10%; the boost 1.1 covers the rest
+    # sanity: 10 iterations land within 6% here (0.948 of lambda_max at this size and at C1's
+    # 163^2); the boost 1.1 covers the rest
+    assert lv[0].lam >= 0.94 * lmax
+
+
+@pytest.mark.parametrize("name", ["c1_small", "c2_small"])
+def test_power_method_equals_spectral_rayleigh_quotient(name):
+    """The estimate is exactly the Rayleigh quotient (x, D^-1 A x) of the unit 10th iterate
+    x ~ (D^-1 A)^9 x0, evaluated here from an eigendecomposition of the composite operator
+    (D^-1 A = D^-1/2 V diag(mu) V^T D^1/2 with S = D^-1/2 A D^-1/2 = V diag(mu) V^T): a wrong
+    iteration count, quotient, diagonal or interface sum in the regional iteration changes it."""
+    w, lay = layout_of(name)
+    coefs = regional.build_operator(lay, w.pde, h=w.h)
+    opt = regional.Options(nlevels=2, power_iters=10)
+    lv = regional.setup(lay, coefs, opt)
+    A = regional.composite_operator(lay, w.pde, h=w.h)
+    A = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+    free = ~lay.dirichlet.reshape(-1)
+    Af = A[np.ix_(free, free)]
+    d = np.diag(Af)
+    mu, V = np.linalg.eigh(Af / np.sqrt(np.outer(d, d)))
+    x0 = rng.uniform_pm1(lay.n_composite, 0, opt.seed)[free]
+    c = V.T @ (np.sqrt(d) * x0)
+    x9 = (V @ (mu ** 9 * c)) / np.sqrt(d)  # D^-1/2 V mu^9 V^T D^1/2 x0
+    x9 /= np.linalg.norm(x9)
+    Mx = (V @ (mu * (V.T @ (np.sqrt(d) * x9)))) / np.sqrt(d)
+    lam = float(x9 @ Mx)
+    assert abs(lv[0].lam - lam) <= 1e-12 * lam, (lv[0].lam, lam)
 
 
 def test_counter_rng_reference_values():
@@ -386,7 +413,7 @@ def test_pcg_against_dense_solve():
     kappa = np.linalg.cond(A)
     assert res.converged
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 1e-8
-    assert res.true_relres <= 1.5e-8
+    assert res.true_relres <= 1e-8
 
 
 def test_pcg_manufactured_solution_3d():
