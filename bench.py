@@ -8,9 +8,11 @@ setup (diagonal, power method, per-region Galerkin products, coarse inverse)
 and the PCG solve.  The region layout (planner tables) is built once.
 
 Prints one JSON line.  ``value`` is the PCG time-to-1e-8 (seconds, median over
-the timed steps); ``roofline`` is measured live on the finest-level fused
-Chebyshev kernel with HIP events; ``cpu_baseline`` times the CPU oracle on a
-bounded sample of the same workload.
+the timed steps, which run without kernel timing); ``roofline`` is measured live
+on the finest-level fused Chebyshev kernel with HIP events in a profiled pass of
+the same step right after them, on the bytes that kernel must move, with the
+same launch timed with every coupling streamed beside it (``general_path``);
+``cpu_baseline`` times the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -42,11 +44,25 @@ def cg_matvec_bytes_per_row(coefs):
 
 
 ALGO_COEFS = 27
-# HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters, scaled by a
-# plain-copy calibration (profiles/k_stencil3d_cheb_c2_counters.md); valid only while the kernel
-# source and the planner and solver sources that fix its tiles are the ones they were taken with.
-TRAFFIC_BYTES = 2811027189
-TRAFFIC_KERNEL_SHA = "957da7231ead3eb9"
+# HBM bytes per launch of the dominant kernel from FETCH_SIZE/WRITE_SIZE counters scaled by a
+# plain-copy calibration, read from the committed counter summary; used only while the sources
+# that define the kernel, its tiles, launch shapes and region table hash as they did when the
+# counters were taken.
+COUNTERS = os.path.join(ROOT, "profiles", "k_stencil3d_cheb_c2_counters.md")
+KERNEL_SOURCES = ("kernels_stencil.hip", "kernels.hip", "planner.cpp", "solver.cpp", "api.cpp")
+
+
+def counted_traffic():
+    """(bytes per launch, sources hash) recorded in the counter summary, or (None, None)."""
+    import re
+
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None, None
+    m = re.search(r"traffic_bytes_per_launch\s+(\d+)\s+sources_sha\s+([0-9a-f]{16})", text)
+    return (int(m.group(1)), m.group(2)) if m else (None, None)
+
 
 CPU_SAMPLE = r"""
 import json, sys, time
@@ -86,9 +102,12 @@ def cpu_baseline(gpu_iterations: int, n_rows: int):
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
+        # not a measurement of the whole workload: a 1/8 sample extrapolated by its row count
+        "extrapolated": f"x{n_rows / d['rows']:.0f} from a 1/{n_rows / d['rows']:.0f} sample (rows)",
+        "sample_seconds": d["seconds"],
         "sample": (f"NumPy FP64 oracle, {d['iterations']} PCG iterations (V-cycle + regional matvec each) on "
-                   f"2x2x2 regions of 82^3 ({d['rows']} regional rows, {d['seconds']:.1f} s timed, setup "
-                   f"excluded), scaled by {n_rows / d['rows']:.0f}x rows"),
+                   f"2x2x2 of the 64 regions of 82^3 ({d['rows']} regional rows, {d['seconds']:.1f} s timed, "
+                   f"setup excluded); value = that time x {n_rows / d['rows']:.0f} (rows of the full workload)"),
     }
 
 
@@ -302,11 +321,23 @@ def variant_graph_2d(dev):
     w = synth.workload("c1")
     b = _to_dev(synth.rhs(w), dev)
     out = {}
+    import torch
+
+    from paper_2103_11962_amd import regmg
+
     for name, g in (("eager", 0), ("graph", 1)):
         h = _handle(w, dev)
         _setup(h, w, use_graph=g)
         ms, res, _ = _timed_solves(h, b, reps=5)
         out[name] = {"solve_ms": ms, "iterations": res["iterations"], "true_relres": res["true_relres"]}
+        if not g:
+            # launch-bound: count the kernels one solve issues
+            n0 = regmg.kernel_launches()
+            x = torch.zeros_like(b)
+            r = h.solve(b, x, rtol=1e-8, maxit=400)
+            n1 = regmg.kernel_launches()
+            out[name]["kernel_launches_per_solve"] = n1 - n0
+            out[name]["kernel_launches_per_iteration"] = (n1 - n0) / max(r["iterations"], 1)
         h.close()
     out["workload"] = "2D five-point, 2x2 regions of 82^2, 3-level V-cycle, Chebyshev degree 2, PCG to 1e-8"
     return out
@@ -490,9 +521,10 @@ def _to_dev(a, dev):
 def kernel_source_sha():
     import hashlib
 
-    # the stencil kernels, and the planner and solver sources that fix their tiles and launch shapes
+    # the stencil kernels, the setup kernels that build the region table, the planner and solver
+    # sources that fix tiles and launch shapes, and the entry points that set option defaults
     sha = hashlib.sha256()
-    for name in ("kernels_stencil.hip", "planner.cpp", "solver.cpp"):
+    for name in KERNEL_SOURCES:
         sha.update(open(os.path.join(ROOT, "paper_2103_11962_amd", "csrc", name), "rb").read())
     return sha.hexdigest()[:16]
 
@@ -536,6 +568,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=1,
+                    help="steps of the profiled pass that times the dominant kernel after the timed steps")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision, batched, learned and graph comparisons")
     ap.add_argument("--copy-probe", action="store_true",
@@ -565,13 +599,13 @@ def main():
     h = regmg.Handle(0)
     h.build_regions(w.dim, w.ndof, w.extents, w.origins, w.dirichlet_mask)
 
-    def step():
+    def step(**opts):
         if w.pde == "fd5":
             h.set_composite_stencil(5, synth.fd5_composite_stencil(w))
         else:
             h.assemble_q1(regmg.PDE_DIFFUSION if ec is not None else regmg.PDE_LAPLACE, w.h, elem_coef=ec)
         t0 = time.perf_counter()
-        h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree)
+        h.setup_hierarchy(nlevels=w.nlevels, cheb_degree=w.cheb_degree, **opts)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         x.zero_()
@@ -581,7 +615,7 @@ def main():
     for i in range(args.warmup):
         step()
         print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
-    h.profile(True)
+    # timed steps: no kernel timing inside them (rmg_profile off)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     setups, solves, outs = [], [], []
@@ -596,27 +630,63 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) / args.steps * 1e3
     last = outs[-1]
-    assert last["converged"] and last["true_relres"] <= 1.5e-8, last
+    assert last["converged"] and last["true_relres"] <= 1e-8, last
+    launches = regmg.kernel_launches()
+    x.zero_()
+    h.solve(b, x, rtol=1e-8, maxit=200)
+    launches = regmg.kernel_launches() - launches
+
+    # profiled pass, after the timed steps: the same step with an event pair around every
+    # finest-level Chebyshev step and CG product (same hierarchy, inputs and launch shapes)
+    def profiled(n_steps, **opts):
+        h.profile(True)
+        outs_p = [step(**opts)[1] for _ in range(n_steps)]
+        n_cheb, ms_cheb = h.profile_query(regmg.TIMED_CHEB)
+        n_cg, ms_cg = h.profile_query(regmg.TIMED_CG_MATVEC)
+        h.profile(False)
+        return n_cheb, ms_cheb / max(n_cheb, 1), n_cg, ms_cg / max(n_cg, 1), outs_p[-1]
+
+    n_cheb, avg_cheb, n_cg, avg_cg, prof_out = profiled(args.profile_steps)
+    print(f"[bench] profiled pass: Chebyshev step {avg_cheb * 1e3:.1f} us over {n_cheb} launches",
+          file=sys.stderr, flush=True)
     info0 = h.level_info(0)
     rows = info0["n_regional"]
     lk = h.level_kernel(0)
+    tiles = h.level_tiles(0)
     table_regions = h.level_table_regions(0)
-    n_cheb, ms_cheb = h.profile_query(regmg.TIMED_CHEB)
-    n_cg, ms_cg = h.profile_query(regmg.TIMED_CG_MATVEC)
-    avg_cheb = ms_cheb / max(n_cheb, 1)
-    bytes_cheb = cheb_bytes_per_row(ALGO_COEFS) * rows
-    achieved = bytes_cheb / (avg_cheb * 1e-3) / 1e9
     tiled = lk["kernel"] in (1, 2)  # the 2.5D kernel computes D^-1 of one-region rows
-    stored_bpr = float(cheb_bytes_per_row(lk["coefs"], not tiled))
-    if tiled and table_regions == w.nreg:
-        # couplings of nodes two or more nodes inside a region come from the region table
-        ext = np.asarray(w.extents, dtype=np.int64)
-        deep = float(np.prod(np.maximum(ext - 4, 0), axis=1).sum()) / rows
-        stored_bpr -= 8 * lk["coefs"] * deep
-    achieved_stored = stored_bpr * rows / (avg_cheb * 1e-3) / 1e9
-    avg_cg = ms_cg / max(n_cg, 1)
+
+    def stored_bytes_per_row(table):
+        bpr = float(cheb_bytes_per_row(lk["coefs"], not tiled))
+        if table:
+            # couplings of nodes two or more nodes inside a region come from the region table
+            ext = np.asarray(w.extents, dtype=np.int64)
+            deep = float(np.prod(np.maximum(ext - 4, 0), axis=1).sum()) / rows
+            bpr -= 8 * lk["coefs"] * deep
+        return bpr
+
+    stored_bpr = stored_bytes_per_row(table_regions == w.nreg)
+    achieved = stored_bpr * rows / (avg_cheb * 1e-3) / 1e9
+    method_bpr = cheb_bytes_per_row(ALGO_COEFS)
     achieved_cg = cg_matvec_bytes_per_row(ALGO_COEFS) * rows / (avg_cg * 1e-3) / 1e9
-    traffic = TRAFFIC_BYTES if args.workload == "c2" and kernel_source_sha() == TRAFFIC_KERNEL_SHA else None
+    traffic, traffic_sha = counted_traffic()
+    if args.workload != "c2" or traffic_sha != kernel_source_sha():
+        traffic = None
+    general = None
+    if table_regions:
+        # the general path: the same operator and tiles with every coupling streamed
+        n0, avg0, _, _, out0 = profiled(1, region_table=0)
+        bpr0 = stored_bytes_per_row(False)
+        general = {
+            "kernel": "k_stencil3d<Cheb, half stencil> (region_table = 0: all 14 upper couplings streamed)",
+            "bytes_per_row": bpr0,
+            "avg_launch_ms": avg0,
+            "launches": n0,
+            "achieved": bpr0 * rows / (avg0 * 1e-3) / 1e9,
+            "frac": bpr0 * rows / (avg0 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "solve_ms": out0["solve_ms"],
+            "iterations": out0["iterations"],
+        }
     h.close()
 
     line = {
@@ -638,39 +708,43 @@ def main():
                          if args.workload == "c2" else args.workload),
             "regional_rows": rows,
             "table_regions": table_regions,
+            "tiles": tiles,
             "iterations": last["iterations"],
             "true_relres": last["true_relres"],
             "setup_s_median": float(np.median(setups)),
             "solve_s_per_step": solves,
             "step": "device assembly + hierarchy setup + PCG solve",
-            "cg_matvec_gbs": achieved_cg,
-            # device ms of each region level's share of the preconditioner in the last timed solve
-            "level_ms": last["level_ms"][:w.nlevels],
+            "kernel_launches_per_solve": launches,
+            "cg_matvec_gbs_method_bytes": achieved_cg,
+            # device ms of each region level's share of the preconditioner (profiled pass)
+            "level_ms": prof_out["level_ms"][:w.nlevels],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_stencil3d<Cheb, half stencil> (finest-level fused Chebyshev step, 2.5D tiles, upper "
-                       "half of the symmetric stencil streamed, lower couplings shared through LDS)"
-                       if lk["coefs"] == 14 else "k_stencil3d<Cheb> (finest-level fused Chebyshev step, 2.5D tiles)"),
-            # algorithmic bytes: the method's 27-point operator, 264 B/row
-            "bytes_per_row": cheb_bytes_per_row(ALGO_COEFS),
+            "kernel": ("k_stencil3d<Cheb, half stencil, region table> (finest-level fused Chebyshev step, 2.5D "
+                       "tiles, upper half of the symmetric stencil, interior couplings from the region table)"
+                       if table_regions else
+                       "k_stencil3d<Cheb, half stencil> (finest-level fused Chebyshev step, 2.5D tiles, upper "
+                       "half of the symmetric stencil streamed)" if lk["coefs"] == 14 else
+                       "k_stencil3d<Cheb> (finest-level fused Chebyshev step, 2.5D tiles)"),
+            # the bytes this kernel must move per row: u, b, d read, d, u written, the upper couplings
+            # of the rows the region table does not serve, D^-1 of shared rows
+            "bytes_per_row": round(stored_bpr, 2),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            # the bytes the kernel stores and streams (upper half of the symmetric stencil), and the
-            # HBM rate the counters measured: the same launches seen from the memory side
-            "stored_bytes_per_row": round(stored_bpr, 2),
-            "note": ("frac prices the method's 264 B/row (the whole operator streamed); with the region "
-                     "table the kernel streams stored_bytes_per_row, so frac can exceed 1: counted_hbm_gbs "
-                     "and frac_at_stored_bytes give how hard it drives HBM") if table_regions else None,
-            "achieved_at_stored_bytes": achieved_stored,
-            "frac_at_stored_bytes": achieved_stored / HBM_PEAK_GBS,
             "counted_hbm_gbs": traffic / (avg_cheb * 1e-3) / 1e9 if traffic else None,
-            "bytes_per_launch": bytes_cheb,
+            "bytes_per_launch": stored_bpr * rows,
             "avg_launch_ms": avg_cheb,
             "launches": n_cheb,
+            "timing": "HIP events around each launch, in a profiled pass after the timed steps",
+            # the method's own step streams the whole 27-point operator (264 B/row): the rate this
+            # step runs at in those terms (above the HBM peak where the table spares the stream)
+            "method_bytes_per_row": method_bpr,
+            "method_equivalent_gbs": method_bpr * rows / (avg_cheb * 1e-3) / 1e9,
+            "general_path": general,
             "copy_gbs": copy_rate_gbs(),
         },
     }

@@ -146,6 +146,15 @@ typedef struct {
                          diffusion and elasticity problems give), the kernel takes them from a
                          14-value table of the region instead of streaming them from memory.
                          Results are bit for bit those of 0, which always streams them */
+  int tile_planes;    /* planes per 2.5D tile: 0 (default) chooses (41 on FP64 levels that keep at
+                         least 1024 such tiles, else 21); 21 or 41 forces that depth on every
+                         tiled level, so that a problem small enough for the oracle runs the launch
+                         shape of the large ones (used by the parity tests) */
+  int galerkin_generic; /* 0 (default): on scalar 3D levels with the geometric interpolation the
+                         per-region Galerkin product P^T A P runs as three one-axis products (P is
+                         the tensor product of one rate-3 interpolation per axis); 1: the generic
+                         product of every coarse node over its 5 x 5 x 5 fine window (also used for
+                         2D, elasticity and stored weights) */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -260,13 +269,24 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
  * matrix is singular. */
 rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt);
 
-/* z = V(r): one regional V-cycle with zero initial guess (device FP64
- * vectors in `layout`).  r and z may not alias.  Asynchronous on the stream. */
+/* z = V(r): one regional V-cycle with zero initial guess (device FP64 vectors in `layout`), the
+ * cycle of Section 3.3 (the regional V-cycle figure and the regional residual and restriction
+ * formulas): degree-K Chebyshev pre-smoothing (Algorithm 2), residual b - Psi^T Psi [[A]] u,
+ * restriction of the residual divided by multiplicity with the coarse interface sum, the coarse
+ * level's cycle (the direct solve of Section 3.5 at the bottom), interpolation added without an
+ * interface sum, post-smoothing.  r and z may not alias.  Asynchronous on the stream. */
 rmg_status rmg_apply_vcycle(rmg_handle* h, const double* r, double* z, int layout);
 
 /* Preconditioned CG for A x = b (device FP64 vectors in `layout`; x holds x0
- * on entry, the solution on exit).  Stops when ||r_k|| / ||b|| <= rtol or after
- * maxit iterations (RMG_ERR_NOT_CONVERGED).  info may be NULL.  Synchronises. */
+ * on entry, the solution on exit) with one rmg_apply_vcycle per iteration as the
+ * preconditioner: the paper's experiments run the V-cycle as a solver and note that
+ * applications use it inside a Krylov method (Section 6.2); every product is the
+ * regional matrix-vector product of the Lemma on Psi [[A]] Psi^T (Section 3.1) and every inner
+ * product counts each composite dof once.  Stops when the recursive residual satisfies
+ * ||r_k|| / ||b|| <= rtol and the true residual ||b - A x_k|| / ||b|| does too (otherwise
+ * CG continues from the true residual), or after maxit iterations (RMG_ERR_NOT_CONVERGED,
+ * x = last iterate); RMG_ERR_BREAKDOWN if (p, A p) or (r, z) is not positive.  info may be
+ * NULL.  Synchronises. */
 rmg_status rmg_solve(rmg_handle* h, const double* b, double* x, int layout, double rtol, int maxit,
                      rmg_solve_info* info);
 
@@ -308,6 +328,13 @@ rmg_status rmg_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t
  * symmetric 27-point stencil); coefs_lo = the same for the low-precision
  * V-cycle copy (0 when there is none).  Any output may be NULL. */
 rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, int* coefs_lo);
+/* Kernel launches this library has issued in the process so far (every handle and trainer, every
+ * thread; a replayed HIP graph counts once per captured launch when it was recorded, not when
+ * replayed).  The difference around a call is that call's launch count. */
+rmg_status rmg_kernel_launches(int64_t* count);
+/* 2.5D tile shape of `level`: the number of tiles, threads per tile block and planes per tile
+ * (all 0 where the level runs node-parallel kernels).  Any output may be NULL. */
+rmg_status rmg_level_tiles(rmg_handle* h, int level, int* ntiles, int* threads, int* planes);
 /* Regions of `level` whose interior couplings the symmetric 2.5D kernel takes from the region table
  * (rmg_options.region_table); 0 where no table was built.  Output may be NULL. */
 rmg_status rmg_level_table_regions(rmg_handle* h, int level, int* nregions);

@@ -158,6 +158,8 @@ void rmg_options_default(rmg_options* o) {
   o->coarse_amg = 0;
   o->amg_coarse_size = 2000;
   o->region_table = 1;
+  o->tile_planes = 0;
+  o->galerkin_generic = 0;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -239,22 +241,35 @@ rmg_status rmg_build_regions(rmg_handle* h, int dim, int ndof, int nreg, const i
   API_END
 }
 
+// Called once every argument of an operator-setting call has been checked, before level 0's
+// operator buffers change: the hierarchy and the CG graphs recorded against the old operator stop
+// being valid, so a call rejected later (non-finite values found on the device) leaves no
+// hierarchy that reads half-replaced or freed buffers.
+static void begin_operator_change(rmg_handle* h, Level& L) {
+  h->have_hierarchy = false;
+  h->have_operator = false;
+  h->drop_graphs();
+  L.coef_sym.release();  // the half stencils and region table of the old operator
+  L.coef_lo_sym.release();
+  L.sym_table.release();
+  L.sym_table_ok.release();
+  clear_split(L);
+}
+
 rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const double* coef, int on_device) {
   API_BEGIN
   use_device(h);
   Level& L = level_of(h, 0);
-  L.coef_sym.release();  // the half stencils of the old operator
-  L.coef_lo_sym.release();
-  L.sym_table.release();
-  L.sym_table_ok.release();
   RMG_REQUIRE(region >= 0 && region < h->nreg, RMG_ERR_ARG, "region index out of range");
   RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
   const bool ok = (h->dim == 3 && npts == 27) || (h->dim == 2 && (npts == 5 || npts == 9));
   RMG_REQUIRE(ok, RMG_ERR_ARG, "npts must be 27 in 3D and 5 or 9 in 2D");
   bool any = false;
   for (bool b : h->region_set) any = any || b;
+  RMG_REQUIRE(!any || L.npts == npts, RMG_ERR_ARG, "all regions must use the same stencil size");
+  begin_operator_change(h, L);
+  h->region_set[region] = false;
   if (!any || L.npts != npts || !L.coef.p) {
-    RMG_REQUIRE(!any || L.npts == npts, RMG_ERR_ARG, "all regions must use the same stencil size");
     L.npts = npts;
     L.coef.alloc(sizeof(double) * coef_elems(L.n, L.ncoef()));
     RMG_HIP(hipMemsetAsync(L.coef.p, 0, sizeof(double) * coef_elems(L.n, L.ncoef()), h->stream));
@@ -274,7 +289,6 @@ rmg_status rmg_set_region_stencil(rmg_handle* h, int region, int npts, const dou
   RMG_HIP(hipStreamSynchronize(h->stream));
   RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "stencil has NaN or Inf entries");
   h->region_set[region] = true;
-  h->have_hierarchy = false;
   h->logc.release();
   bool all = true;
   for (bool b : h->region_set) all = all && b;
@@ -314,6 +328,8 @@ static void check_composite_split(rmg_handle* h, int npts) {
 
 // Region matrices from a device composite stencil [npts][ncomp].
 static void split_into_regions(rmg_handle* h, Level& L, int npts, const double* src) {
+  begin_operator_change(h, L);
+  h->region_set.assign(h->nreg, false);
   L.npts = npts;
   L.coef.alloc(sizeof(double) * coef_elems(L.n, npts));
   DBuf flag;
@@ -327,17 +343,12 @@ static void split_into_regions(rmg_handle* h, Level& L, int npts, const double* 
   h->region_set.assign(h->nreg, true);
   h->logc.release();
   h->have_operator = true;
-  h->have_hierarchy = false;
 }
 
 rmg_status rmg_set_composite_stencil(rmg_handle* h, int npts, const double* coef, int on_device) {
   API_BEGIN
   use_device(h);
   Level& L = level_of(h, 0);
-  L.coef_sym.release();  // the half stencils of the old operator
-  L.coef_lo_sym.release();
-  L.sym_table.release();
-  L.sym_table_ok.release();
   RMG_REQUIRE(coef != nullptr, RMG_ERR_ARG, "null coefficient pointer");
   check_composite_split(h, npts);
   DBuf tmp;
@@ -356,10 +367,6 @@ rmg_status rmg_set_composite_csr(rmg_handle* h, int npts, int64_t nnz, const int
   API_BEGIN
   use_device(h);
   Level& L = level_of(h, 0);
-  L.coef_sym.release();  // the half stencils of the old operator
-  L.coef_lo_sym.release();
-  L.sym_table.release();
-  L.sym_table_ok.release();
   RMG_REQUIRE(rowptr && (nnz == 0 || (colind && values)) && nnz >= 0, RMG_ERR_ARG, "null CSR array or nnz < 0");
   check_composite_split(h, npts);
   const int64_t n = L.ncomp;
@@ -391,6 +398,9 @@ rmg_status rmg_set_composite_csr(rmg_handle* h, int npts, int64_t nnz, const int
       pv = dv.as<double>();
     }
   }
+  // the conversion reads the level's stencil size: from here on level 0 changes
+  begin_operator_change(h, L);
+  h->region_set.assign(h->nreg, false);
   L.npts = npts;
   comp.alloc(sizeof(double) * (size_t)npts * n);
   RMG_HIP(hipMemsetAsync(comp.p, 0, sizeof(double) * (size_t)npts * n, h->stream));
@@ -412,10 +422,6 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
   API_BEGIN
   use_device(h);
   Level& L = level_of(h, 0);
-  L.coef_sym.release();  // the half stencils of the old operator
-  L.coef_lo_sym.release();
-  L.sym_table.release();
-  L.sym_table_ok.release();
   RMG_REQUIRE(h->dim == 3, RMG_ERR_ARG, "Q1 assembly needs a 3D layout");
   RMG_REQUIRE(hsize > 0.0 && std::isfinite(hsize), RMG_ERR_ARG, "element size must be positive");
   RMG_REQUIRE(pde == RMG_PDE_LAPLACE || pde == RMG_PDE_DIFFUSION || pde == RMG_PDE_ELASTICITY, RMG_ERR_ARG,
@@ -423,13 +429,17 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
   RMG_REQUIRE((pde == RMG_PDE_ELASTICITY) == (h->ndof == 3), RMG_ERR_ARG,
               "elasticity needs ndof = 3, scalar problems ndof = 1");
   RMG_REQUIRE(pde != RMG_PDE_DIFFUSION || elem_coef != nullptr, RMG_ERR_ARG, "diffusion needs elem_coef");
-  L.npts = 27;
-  L.coef.alloc(sizeof(double) * coef_elems(L.n, L.ncoef()));
   if (pde == RMG_PDE_ELASTICITY) {
     RMG_REQUIRE(youngs != nullptr, RMG_ERR_ARG, "elasticity needs Young's modulus per region");
     RMG_REQUIRE(nu > -1.0 && nu < 0.5, RMG_ERR_ARG, "Poisson ratio must lie in (-1, 0.5)");
     for (int k = 0; k < h->nreg; ++k)
       RMG_REQUIRE(youngs[k] > 0.0 && std::isfinite(youngs[k]), RMG_ERR_NUMERIC, "Young's moduli must be positive");
+  }
+  begin_operator_change(h, L);
+  h->region_set.assign(h->nreg, false);
+  L.npts = 27;
+  L.coef.alloc(sizeof(double) * coef_elems(L.n, L.ncoef()));
+  if (pde == RMG_PDE_ELASTICITY) {
     std::vector<double> K(576);
     q1_elasticity_element(nu, hsize, K.data());
     DBuf dK, dE;
@@ -463,7 +473,6 @@ rmg_status rmg_assemble_q1(rmg_handle* h, int pde, double hsize, const double* e
   RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "assembled operator has NaN or Inf entries");
   h->region_set.assign(h->nreg, true);
   h->have_operator = true;
-  h->have_hierarchy = false;
   API_END
 }
 
@@ -484,6 +493,10 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->batched == 0 || opt->batched == 1, RMG_ERR_ARG, "batched must be 0 or 1");
   RMG_REQUIRE(opt->symmetric == 0 || opt->symmetric == 1, RMG_ERR_ARG, "symmetric must be 0 or 1");
   RMG_REQUIRE(opt->region_table == 0 || opt->region_table == 1, RMG_ERR_ARG, "region_table must be 0 or 1");
+  RMG_REQUIRE(opt->tile_planes == 0 || opt->tile_planes == 21 || opt->tile_planes == 41, RMG_ERR_ARG,
+              "tile_planes must be 0, 21 or 41");
+  RMG_REQUIRE(opt->galerkin_generic == 0 || opt->galerkin_generic == 1, RMG_ERR_ARG,
+              "galerkin_generic must be 0 or 1");
   RMG_REQUIRE(opt->smoother >= 0 && opt->smoother <= 4, RMG_ERR_ARG,
               "smoother must be 0 (Chebyshev), 1 (Jacobi), 2 (Gauss-Seidel), 3 (forward/backward "
               "Gauss-Seidel) or 4 (symmetric Gauss-Seidel)");
@@ -692,6 +705,24 @@ rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, i
   // the 2.5D kernel has no half-stencil path for BF16 storage
   const bool sym_lo = L.coef_lo_sym.p && !(tiled && L.ct_lo == kCoefBF16);
   if (coefs_lo) *coefs_lo = L.ct_lo == kCoefF64 ? 0 : (sym_lo ? kSymPts * nb : L.ncoef());
+  API_END
+}
+
+rmg_status rmg_kernel_launches(int64_t* count) {
+  API_BEGIN
+  RMG_REQUIRE(count != nullptr, RMG_ERR_ARG, "null output");
+  *count = g_kernel_launches.load(std::memory_order_relaxed);
+  API_END
+}
+
+rmg_status rmg_level_tiles(rmg_handle* h, int level, int* ntiles, int* threads, int* planes) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  const bool tiled = L.use_tiles && L.ndof == 1 && L.npts == 27 && !L.per_region;
+  if (ntiles) *ntiles = tiled ? (int)L.tiles.size() : 0;
+  if (threads) *threads = tiled ? L.tile_threads : 0;
+  if (planes) *planes = tiled ? L.tile_depth : 0;
   API_END
 }
 

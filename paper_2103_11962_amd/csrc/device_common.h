@@ -12,6 +12,14 @@ static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 #define LAUNCH_CHECK() RMG_HIP(hipGetLastError())
 
+// Every kernel launch of the library goes through RMG_LAUNCH, which counts it in
+// g_kernel_launches (all handles and threads of the process).
+#define RMG_LAUNCH(...)                                                  \
+  do {                                                                   \
+    ::rmg::g_kernel_launches.fetch_add(1, std::memory_order_relaxed);    \
+    hipLaunchKernelGGL(__VA_ARGS__);                                     \
+  } while (0)
+
 template <int NPTS>
 __device__ __forceinline__ void stencil_offset(int s, int& dx, int& dy, int& dz) {
   if constexpr (NPTS == 27) {

@@ -92,8 +92,18 @@ constexpr size_t kDeepTileMin = 1024;  // 41-plane FP64 tiles needed before they
 // whose V-cycle runs in FP32 uses the narrow tiles for every operation.
 constexpr int kTileThreadsF64 = 768;
 constexpr int kTileThreadsF32 = 512;
+// Threads per deep-box tile of the region-table split (k_stencil_deep: no coupling stream, about 90
+// VGPRs, so several 4-wave blocks share a CU) and planes per tile (two per 78-plane deep box).
+constexpr int kDeepThreads = 256;
+constexpr int kDeepPlanes = 40;
 // Largest (tx + 2)(ty + 2) over tiles of at most nt nodes (tx * ty <= nt): the single row, ty = 1.
 constexpr int tile_plane_cap(int nt) { return 3 * (nt + 2); }
+
+// Nodes of a region-table region whose couplings, upper and lower, are the table's: [lo, hi) per
+// axis, two nodes inside the region, or one on a face whose layer-one nodes carry the table too.
+struct DeepBox {
+  int lo[3], hi[3];
+};
 
 // A 2.5D tile of a 3D region: ty x-rows of tx nodes starting at (x0, y0), planes z0 .. z0+nz-1.
 struct Tile3 {
@@ -164,6 +174,7 @@ struct Level {
   int tile_depth = 21;       // planes per tile
   int tile_threads = kTileThreadsF64;  // threads per 2.5D tile block (tiles hold at most this many nodes)
   int tile_grid = 0;         // > 0: persistent launch of this many blocks looping over the tiles
+  bool rap_separable = true; // scalar 3D geometric Galerkin product as three one-axis products
   bool per_region = false;   // stencil operations launch the node-parallel kernel once per region
   // interface groups: copies of each shared composite node, ascending region order
   int64_t ngroups = 0;
@@ -177,6 +188,23 @@ struct Level {
   // (kSymPts values from coef_sym) and a flag that they all agree; built for FP64 levels run by
   // 768-thread 2.5D tiles, else empty
   DBuf sym_table, sym_table_ok;
+  // With the table: each served region runs as deep-box tiles (every node two or more nodes
+  // inside, couplings from the table) and its outer two layers as node blocks; the tiles of the
+  // other regions run the streaming 2.5D kernel.  Built with the table (make_split), refreshed
+  // when the tiles change.
+  std::vector<int> table_served;     // per region: 1 when the table serves it
+  std::vector<DeepBox> deep_box;     // per region: the box of nodes whose couplings are the table's
+  DBuf d_deep_box, sym_table_face;   // device copy; per region and face (x-, x+, y-, y+, z-, z+) a flag
+                                     // that the box may reach one node from that face
+  std::vector<Tile3> deep_tiles;     // kDeepThreads-thread tiles of the served regions' deep boxes
+  std::vector<BlockDesc> shell_blocks;  // kBlock shell nodes of one served region (start = shell index)
+  std::vector<Tile3> other_tiles;    // the level's 2.5D tiles of the regions not served
+  DBuf d_deep_tiles, d_shell_blocks, d_other_tiles;
+  // The shell's x-face nodes (x < 2 or x >= ex - 2, y and z two or more inside) sit four to a row,
+  // so their couplings would be read a few lanes per cache line: their upper couplings are also
+  // kept packed in shell order (wave-tiled, kSymPts per node), from d_xface_off[region] on.
+  std::vector<int64_t> xface_off;    // per region: first packed x-face node (served regions)
+  DBuf d_xface_off, xface_coef;
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
   DBuf pw;        // stored interpolation weights to the next level, double [n][8] (null: geometric)
   DBuf rw;        // with pw: the same weights per coarse node (125 taps, wave-tiled) for the restriction
@@ -291,6 +319,10 @@ void coarse_geometry(int dim, const std::vector<RegionGeo>& fine, std::vector<Re
 Level* make_coarse_level(const Level& fine);
 void build_tables(Level& L);
 void make_tiles(Level& L, int depth);
+// Region-table split of a level whose table flags are `served` (per region): deep tiles, shell
+// blocks and the remaining regions' tiles (also rebuilt by make_tiles while a split exists).
+void make_split(Level& L, const std::vector<int>& served, const std::vector<DeepBox>& boxes);
+void clear_split(Level& L);
 void build_coarse_solver(rmg_handle* h, Level& L);
 
 // amg.cpp: AMG coarse solver on the coarsest region level's composite operator (Section 3.5).
@@ -316,7 +348,8 @@ void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out)
 // u <- S(b, u): one degree-K Chebyshev application from the current iterate (tmp: work vector).
 void smooth_iterate(rmg_handle* h, int level, const double* b, double* u, double* tmp);
 // Convergence factor of `cycles` stationary V-cycles on A x = 0 (FP64 outer iteration).
-double convergence_factor(rmg_handle* h, int cycles);
+// work: device memory for 4 n_regional doubles, or nullptr (then allocated for the call).
+double convergence_factor(rmg_handle* h, int cycles, double* work = nullptr);
 
 // solver.cpp: finest-level work vectors and launch configuration for the outer CG / MG loop.
 void prepare_finest(rmg_handle* h);

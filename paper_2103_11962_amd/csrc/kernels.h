@@ -4,9 +4,15 @@
 // `lowp` run on the level's FP32 vectors and its low-precision coefficient copy (FP32, or BF16
 // off-diagonals with FP32 centre blocks); otherwise vectors are FP64 with FP64 coefficients.
 #pragma once
+#include <atomic>
+
 #include "internal.h"
 
 namespace rmg {
+
+// Kernel launches issued by the library in this process (counted by RMG_LAUNCH; read by
+// rmg_kernel_launches).
+extern std::atomic<int64_t> g_kernel_launches;
 
 // Per-node operations applied after a regional stencil product z = A^(k) x.
 enum class StencilOp {

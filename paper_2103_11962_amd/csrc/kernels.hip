@@ -14,6 +14,8 @@
 
 namespace rmg {
 
+std::atomic<int64_t> g_kernel_launches{0};
+
 // ------------------------------------------------------- interface sum
 template <int NDOF, class V>
 __global__ __launch_bounds__(kBlock) void k_iface_sum(const int64_t* __restrict__ gptr, const int* __restrict__ gcopy,
@@ -34,10 +36,10 @@ static void iface_sum_inplace(const Level& L, V* w, hipStream_t st) {
   if (L.ngroups == 0) return;
   const dim3 g(cdiv(L.ngroups, kBlock));
   if (L.ndof == 3)
-    hipLaunchKernelGGL((k_iface_sum<3, V>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
+    RMG_LAUNCH((k_iface_sum<3, V>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
                        L.ngroups, w);
   else
-    hipLaunchKernelGGL((k_iface_sum<1, V>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
+    RMG_LAUNCH((k_iface_sum<1, V>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
                        L.ngroups, w);
   LAUNCH_CHECK();
 }
@@ -49,7 +51,7 @@ __global__ void k_copy(int64_t n, const double* __restrict__ src, double* __rest
 
 void launch_copy(int64_t n, const double* src, double* dst, hipStream_t st) {
   if (n == 0 || src == dst) return;
-  hipLaunchKernelGGL(k_copy, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, src, dst);
+  RMG_LAUNCH(k_copy, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, src, dst);
   LAUNCH_CHECK();
 }
 
@@ -98,10 +100,10 @@ static int64_t dot_groups(const Level& L, const double* a, const double* b, doub
   if (L.ngroups == 0) return 0;
   const int64_t ngb = cdiv(L.ngroups, kBlock);
   if (L.ndof == 3)
-    hipLaunchKernelGGL(k_dot_groups<3>, dim3(ngb), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
+    RMG_LAUNCH(k_dot_groups<3>, dim3(ngb), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
                        L.ngroups, a, b, partials);
   else
-    hipLaunchKernelGGL(k_dot_groups<1>, dim3(ngb), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
+    RMG_LAUNCH(k_dot_groups<1>, dim3(ngb), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(),
                        L.ngroups, a, b, partials);
   LAUNCH_CHECK();
   return ngb;
@@ -109,8 +111,8 @@ static int64_t dot_groups(const Level& L, const double* a, const double* b, doub
 
 int64_t launch_dot(const Level& L, const double* a, const double* b, double* partials, hipStream_t st) {
   const int64_t nb = (int64_t)L.blocks.size();
-  if (L.ndof == 3) hipLaunchKernelGGL(k_dot_nodes<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), a, b, partials);
-  else hipLaunchKernelGGL(k_dot_nodes<1>, dim3(nb), dim3(kBlock), 0, st, L.view(), a, b, partials);
+  if (L.ndof == 3) RMG_LAUNCH(k_dot_nodes<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), a, b, partials);
+  else RMG_LAUNCH(k_dot_nodes<1>, dim3(nb), dim3(kBlock), 0, st, L.view(), a, b, partials);
   LAUNCH_CHECK();
   return nb + dot_groups(L, a, b, partials + nb, st);
 }
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double* __restr
 }
 
 void launch_reduce(const double* partials, int64_t n, double* scalars, int slot, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceThreads), 0, st, partials, n, scalars, slot);
+  RMG_LAUNCH(k_reduce, dim3(1), dim3(kReduceThreads), 0, st, partials, n, scalars, slot);
   LAUNCH_CHECK();
 }
 
@@ -151,10 +153,10 @@ void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv
                       hipStream_t st) {
   const int64_t n = L.ndofs();
   if (lowp)
-    hipLaunchKernelGGL(k_cheb_zero<float>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, (const float*)b,
+    RMG_LAUNCH(k_cheb_zero<float>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, (const float*)b,
                        (const float*)dinv, (float)c, (float*)d, (float*)u);
   else
-    hipLaunchKernelGGL(k_cheb_zero<double>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, (const double*)b,
+    RMG_LAUNCH(k_cheb_zero<double>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, (const double*)b,
                        (const double*)dinv, c, (double*)d, (double*)u);
   LAUNCH_CHECK();
 }
@@ -170,7 +172,7 @@ __global__ void k_scale(int64_t n, const double* scalars, int slot, int mode, co
 
 void launch_scale(int64_t n, const double* scalars, int slot, int mode, const double* x, double* y,
                   hipStream_t st) {
-  hipLaunchKernelGGL(k_scale, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, scalars, slot, mode, x, y);
+  RMG_LAUNCH(k_scale, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, scalars, slot, mode, x, y);
   LAUNCH_CHECK();
 }
 
@@ -180,7 +182,7 @@ __global__ void k_mul(int64_t n, const double* __restrict__ a, const double* __r
 }
 
 void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_mul, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, a, b, y);
+  RMG_LAUNCH(k_mul, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, a, b, y);
   LAUNCH_CHECK();
 }
 
@@ -191,7 +193,7 @@ __global__ void k_add(int64_t n, const double* __restrict__ x, double* __restric
 
 void launch_add(int64_t n, const double* x, double* y, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_add, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, x, y);
+  RMG_LAUNCH(k_add, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, x, y);
   LAUNCH_CHECK();
 }
 
@@ -202,7 +204,7 @@ __global__ void k_zero(int64_t n, double* y) {
 
 void launch_zero(int64_t n, double* y, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_zero, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, y);
+  RMG_LAUNCH(k_zero, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, y);
   LAUNCH_CHECK();
 }
 
@@ -216,11 +218,11 @@ __global__ void k_f32_to_f64(int64_t n, const float* __restrict__ in, double* __
 }
 
 void launch_f64_to_f32(int64_t n, const double* in, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out);
+  RMG_LAUNCH(k_f64_to_f32, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out);
   LAUNCH_CHECK();
 }
 void launch_f32_to_f64(int64_t n, const float* in, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out);
+  RMG_LAUNCH(k_f32_to_f64, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out);
   LAUNCH_CHECK();
 }
 
@@ -233,7 +235,7 @@ __global__ void k_recip_check(int64_t n, const double* __restrict__ in, double* 
 }
 
 void launch_recip_check(int64_t n, const double* in, double* out, int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_recip_check, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out, flag);
+  RMG_LAUNCH(k_recip_check, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out, flag);
   LAUNCH_CHECK();
 }
 
@@ -250,7 +252,7 @@ __global__ void k_diag(int64_t n, int ndof, int ncoef, int center, const double*
 
 void launch_diag(const Level& L, double* out, hipStream_t st) {
   const int center = L.npts == 27 ? 13 : (L.npts == 9 ? 4 : 2);
-  hipLaunchKernelGGL(k_diag, dim3(cdiv(L.ndofs(), kBlock)), dim3(kBlock), 0, st, L.n, L.ndof, L.ncoef(), center,
+  RMG_LAUNCH(k_diag, dim3(cdiv(L.ndofs(), kBlock)), dim3(kBlock), 0, st, L.n, L.ndof, L.ncoef(), center,
                      L.coef.as<double>(), out);
   LAUNCH_CHECK();
 }
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_start_vector(LevelView L, int level,
 }
 
 void launch_start_vector(const Level& L, int level, uint64_t seed, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_start_vector, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), level, seed, out);
+  RMG_LAUNCH(k_start_vector, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), level, seed, out);
   LAUNCH_CHECK();
 }
 
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_build_rw(LevelView F, LevelView C, c
 }
 
 void launch_build_rw(const Level& F, const Level& C, double* rw, hipStream_t st) {
-  hipLaunchKernelGGL(k_build_rw, dim3(C.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), F.pw.as<double>(),
+  RMG_LAUNCH(k_build_rw, dim3(C.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), F.pw.as<double>(),
                      rw);
   LAUNCH_CHECK();
 }
@@ -433,16 +435,16 @@ static void restrict_t(const Level& F, const Level& C, const V* r, V* w, hipStre
   if constexpr (NDOF == 1) {
     if (pw) {
       RMG_REQUIRE(F.dim == 3 && F.rw.p, RMG_ERR_ARG, "stored interpolation weights need a 3D level");
-      hipLaunchKernelGGL((k_restrict_rw<V>), g, b, 0, st, F.view(), C.view(), r, w, F.rw.as<double>());
+      RMG_LAUNCH((k_restrict_rw<V>), g, b, 0, st, F.view(), C.view(), r, w, F.rw.as<double>());
       LAUNCH_CHECK();
       iface_sum_inplace<V>(C, w, st);
       return;
     }
   }
   if (F.dim == 3)
-    hipLaunchKernelGGL((k_restrict<3, NDOF, V>), g, b, 0, st, F.view(), C.view(), r, w);
+    RMG_LAUNCH((k_restrict<3, NDOF, V>), g, b, 0, st, F.view(), C.view(), r, w);
   else
-    hipLaunchKernelGGL((k_restrict<2, NDOF, V>), g, b, 0, st, F.view(), C.view(), r, w);
+    RMG_LAUNCH((k_restrict<2, NDOF, V>), g, b, 0, st, F.view(), C.view(), r, w);
   LAUNCH_CHECK();
   iface_sum_inplace<V>(C, w, st);
 }
@@ -526,15 +528,15 @@ static void prolong_t(const Level& F, const Level& C, const V* ubar, V* u, hipSt
   if constexpr (NDOF == 1) {
     if (pw) {
       RMG_REQUIRE(F.dim == 3, RMG_ERR_ARG, "stored interpolation weights need a 3D level");
-      hipLaunchKernelGGL((k_prolong_add<3, 1, V, true>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
+      RMG_LAUNCH((k_prolong_add<3, 1, V, true>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
       LAUNCH_CHECK();
       return;
     }
   }
   if (F.dim == 3)
-    hipLaunchKernelGGL((k_prolong_add<3, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
+    RMG_LAUNCH((k_prolong_add<3, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
   else
-    hipLaunchKernelGGL((k_prolong_add<2, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
+    RMG_LAUNCH((k_prolong_add<2, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
   LAUNCH_CHECK();
 }
 
@@ -557,7 +559,7 @@ void launch_prolong_add(const Level& F, const Level& C, bool lowp, const void* u
 // live in LDS (one column per thread).  Dirichlet reading: a Dirichlet coarse row only collects
 // Dirichlet fine nodes; entries of a free row towards Dirichlet coarse nodes are zero.  STORED
 // weights come from the fine nodes' records (rate-3 lattice, extents 3^k + 1).
-template <int NPTSF, int DIM, int NDOF, int BS, bool STORED>
+template <int NPTSF, int DIM, int NDOF, int BS, bool STORED, bool DIRONLY = false>
 __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const double* __restrict__ coefF,
                                             double* __restrict__ coefC, const double* __restrict__ pw,
                                             const double* __restrict__ rw) {
@@ -576,6 +578,7 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
   int X, Y, Z;
   decompose(RC, li, X, Y, Z);
   const bool cdir = is_dirichlet(C, RC.ox + X, RC.oy + Y, RC.oz + Z);
+  if (DIRONLY && !cdir) return;  // the separable product wrote the free rows
   const int px = coarse_pos(X, RF.ex), py = coarse_pos(Y, RF.ey), pz = DIM == 3 ? coarse_pos(Z, RF.ez) : 0;
   int mxl, mxr, myl, myr, mzl = 0, mzr = 0;
   coarse_spans(X, RF.ex, RC.ex, mxl, mxr);
@@ -662,6 +665,132 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
   }
 }
 
+// ---------------------------------------------------- separable Galerkin product
+// With the geometric interpolation the prolongator of a 3D region is the tensor product of one
+// rate-3 interpolation per axis, P = Px (x) Py (x) Pz, so P^T A P = Qz^T Qy^T (Qx^T A Qx) Qy Qz with
+// Qa interpolating along axis a only.  Each factor is a one-axis Galerkin product of a 27-point
+// operator, which stays 27-point: along the coarsened axis an output node c sums the fine nodes f in
+// its two intervals (weight P(f, c)) and each of their couplings (da, d1, d2) to f + da, split over
+// the coarse nodes of f + da's interval (weights P(f + da, c + da')); the two other offsets pass
+// through.  Three passes replace the 5 x 5 x 5 window of the generic product: about 400 multiply-adds
+// per intermediate node against 27,000 per coarse node.  The passes use the full tensor weights;
+// entries of free coarse rows towards Dirichlet coarse nodes are zeroed at the end, and Dirichlet
+// coarse rows (which collect only Dirichlet fine nodes) come from the generic product.
+template <int AX, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_rap_axis(const RegionGeo* __restrict__ gin, const RegionGeo* __restrict__ gout,
+                                                     const BlockDesc* __restrict__ blocks, const double* __restrict__ sin_,
+                                                     double* __restrict__ sout, LevelView C) {
+  const BlockDesc bd = blocks[blockIdx.x];
+  const RegionGeo RI = gin[bd.region], RO = gout[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= RO.n) return;
+  int o[3];
+  decompose(RO, li, o[0], o[1], o[2]);
+  const int ein = AX == 0 ? RI.ex : (AX == 1 ? RI.ey : RI.ez);
+  const int eout = AX == 0 ? RO.ex : (AX == 1 ? RO.ey : RO.ez);
+  const int c = o[AX];
+  bool cdir = false;
+  if constexpr (LAST) {
+    const RegionGeo RC = C.regs[bd.region];
+    cdir = is_dirichlet(C, RC.ox + o[0], RC.oy + o[1], RC.oz + o[2]);
+    if (cdir) return;  // Dirichlet coarse rows: the generic product
+  }
+  const int pos = coarse_pos(c, ein);
+  int mL, mR;
+  coarse_spans(c, ein, eout, mL, mR);
+  double acc[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) acc[q] = 0.0;
+  constexpr int kStride = AX == 0 ? 1 : (AX == 1 ? 3 : 9);  // stencil-index step of the coarsened axis
+#pragma unroll
+  for (int t = -2; t <= 2; ++t) {
+    const int f = pos + t;
+    const double wf = tap(t, mL, mR);
+    if ((unsigned)f >= (unsigned)ein || wf == 0.0) continue;
+    int fi[3] = {o[0], o[1], o[2]};
+    fi[AX] = f;
+    const int64_t gi = RI.off + ((int64_t)fi[2] * RI.ey + fi[1]) * RI.ex + fi[0];
+#pragma unroll
+    for (int da = -1; da <= 1; ++da) {
+      if ((unsigned)(f + da) >= (unsigned)ein) continue;
+      int o0;
+      double w0, w1;
+      interval_weights(t + da, mL, mR, o0, w0, w1);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {  // the two other offsets
+        const int d1 = q % 3, d2 = q / 3;  // 0..2
+        int sbase;
+        if constexpr (AX == 0) sbase = d2 * 9 + d1 * 3;
+        else if constexpr (AX == 1) sbase = d2 * 9 + d1;
+        else sbase = d2 * 3 + d1;
+        const double a = sin_[coef_index(gi, sbase + (da + 1) * kStride, 27)];
+        const double wa = wf * a;
+        acc[sbase + (o0 + 1) * kStride] += wa * w0;
+        if (o0 + 2 <= 2) acc[sbase + (o0 + 2) * kStride] += wa * w1;
+      }
+    }
+  }
+  const int64_t go = RO.off + li;
+  if constexpr (LAST) {
+    const RegionGeo RC = C.regs[bd.region];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const int X = o[0] + q % 3 - 1, Y = o[1] + (q / 3) % 3 - 1, Z = o[2] + q / 9 - 1;
+      const bool inbox = (unsigned)X < (unsigned)RO.ex && (unsigned)Y < (unsigned)RO.ey && (unsigned)Z < (unsigned)RO.ez;
+      const bool zero = !inbox || is_dirichlet(C, RC.ox + X, RC.oy + Y, RC.oz + Z);
+      sout[coef_index(go, q, 27)] = zero ? 0.0 : acc[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 27; ++q) sout[coef_index(go, q, 27)] = acc[q];
+  }
+}
+
+// Separable product for a scalar 3D level with geometric interpolation: passes x, y, z through two
+// intermediate grids (coarse along x; coarse along x and y), then the Dirichlet coarse rows.
+static void launch_rap_separable(const Level& F, Level& C, hipStream_t st) {
+  std::vector<RegionGeo> g1(F.regs), g2(F.regs);
+  std::vector<BlockDesc> b1, b2;
+  int64_t n1 = 0, n2 = 0;
+  for (int k = 0; k < F.nreg; ++k) {
+    g1[k].ex = C.regs[k].ex;
+    g2[k].ex = C.regs[k].ex;
+    g2[k].ey = C.regs[k].ey;
+    for (RegionGeo* g : {&g1[k], &g2[k]}) g->n = g->ex * g->ey * g->ez;
+    g1[k].off = n1;
+    g2[k].off = n2;
+    for (int s0 = 0; s0 < g1[k].n; s0 += kBlock) b1.push_back(BlockDesc{k, s0});
+    for (int s0 = 0; s0 < g2[k].n; s0 += kBlock) b2.push_back(BlockDesc{k, s0});
+    n1 += g1[k].n;
+    n2 += g2[k].n;
+  }
+  DBuf dg1, dg2, db1, db2, s1, s2;
+  dg1.alloc(sizeof(RegionGeo) * g1.size());
+  dg2.alloc(sizeof(RegionGeo) * g2.size());
+  db1.alloc(sizeof(BlockDesc) * b1.size());
+  db2.alloc(sizeof(BlockDesc) * b2.size());
+  RMG_HIP(hipMemcpyAsync(dg1.p, g1.data(), dg1.bytes, hipMemcpyHostToDevice, st));
+  RMG_HIP(hipMemcpyAsync(dg2.p, g2.data(), dg2.bytes, hipMemcpyHostToDevice, st));
+  RMG_HIP(hipMemcpyAsync(db1.p, b1.data(), db1.bytes, hipMemcpyHostToDevice, st));
+  RMG_HIP(hipMemcpyAsync(db2.p, b2.data(), db2.bytes, hipMemcpyHostToDevice, st));
+  s1.alloc(sizeof(double) * coef_elems(n1, 27));
+  s2.alloc(sizeof(double) * coef_elems(n2, 27));
+  const LevelView cv = C.view();
+  RMG_LAUNCH((k_rap_axis<0, false>), dim3(b1.size()), dim3(kBlock), 0, st, F.d_regs.as<RegionGeo>(),
+             dg1.as<RegionGeo>(), db1.as<BlockDesc>(), F.coef.as<double>(), s1.as<double>(), cv);
+  RMG_LAUNCH((k_rap_axis<1, false>), dim3(b2.size()), dim3(kBlock), 0, st, dg1.as<RegionGeo>(),
+             dg2.as<RegionGeo>(), db2.as<BlockDesc>(), s1.as<double>(), s2.as<double>(), cv);
+  RMG_LAUNCH((k_rap_axis<2, true>), dim3(C.blocks.size()), dim3(kBlock), 0, st, dg2.as<RegionGeo>(),
+             C.d_regs.as<RegionGeo>(), C.d_blocks.as<BlockDesc>(), s2.as<double>(), C.coef.as<double>(), cv);
+  LAUNCH_CHECK();
+  // Dirichlet coarse rows
+  RMG_LAUNCH((k_rap<27, 3, 1, kBlock, false, true>), dim3(C.blocks.size()), dim3(kBlock), 0, st, F.view(), cv,
+             F.coef.as<double>(), C.coef.as<double>(), nullptr, nullptr);
+  LAUNCH_CHECK();
+  // the intermediates are freed when this returns: wait for the passes that read them
+  RMG_HIP(hipStreamSynchronize(st));
+}
+
 void launch_rap(const Level& F, Level& C, hipStream_t st) {
   const LevelView fv = F.view(), cv = C.view();
   const double* cf = F.coef.as<double>();
@@ -673,21 +802,25 @@ void launch_rap(const Level& F, Level& C, hipStream_t st) {
   if (F.ndof == 3) {
     RMG_REQUIRE(F.npts == 27, RMG_ERR_ARG, "3D levels need 27-point stencils");
     constexpr int BS = 32;
-    hipLaunchKernelGGL((k_rap<27, 3, 3, BS, false>), dim3(C.blocks.size() * (kBlock / BS)), dim3(BS), 0, st, fv, cv,
+    RMG_LAUNCH((k_rap<27, 3, 3, BS, false>), dim3(C.blocks.size() * (kBlock / BS)), dim3(BS), 0, st, fv, cv,
                        cf, cc, pw, rw);
+  } else if (F.dim == 3 && !pw && F.rap_separable) {
+    RMG_REQUIRE(F.npts == 27, RMG_ERR_ARG, "3D levels need 27-point stencils");
+    launch_rap_separable(F, C, st);
+    return;
   } else if (F.dim == 3) {
     RMG_REQUIRE(F.npts == 27, RMG_ERR_ARG, "3D levels need 27-point stencils");
     if (pw)
-      hipLaunchKernelGGL((k_rap<27, 3, 1, kBlock, true>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc,
+      RMG_LAUNCH((k_rap<27, 3, 1, kBlock, true>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc,
                          pw, rw);
     else
-      hipLaunchKernelGGL((k_rap<27, 3, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc,
+      RMG_LAUNCH((k_rap<27, 3, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc,
                          pw, rw);
   } else if (F.npts == 9) {
-    hipLaunchKernelGGL((k_rap<9, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw,
+    RMG_LAUNCH((k_rap<9, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw,
                        rw);
   } else {
-    hipLaunchKernelGGL((k_rap<5, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw,
+    RMG_LAUNCH((k_rap<5, 2, 1, kBlock, false>), dim3(C.blocks.size()), dim3(kBlock), 0, st, fv, cv, cf, cc, pw,
                        rw);
   }
   LAUNCH_CHECK();
@@ -708,7 +841,7 @@ __global__ __launch_bounds__(kBlock) void k_to_regional(LevelView L, const doubl
 }
 
 void launch_to_regional(const Level& L, const double* comp, double* reg, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_regional<double>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), comp, reg);
+  RMG_LAUNCH(k_to_regional<double>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), comp, reg);
   LAUNCH_CHECK();
 }
 
@@ -747,10 +880,10 @@ __global__ __launch_bounds__(kBlock) void k_to_composite_groups(const int64_t* _
 }
 
 void launch_to_composite(const Level& L, const double* reg, double* comp, int average, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_composite_nodes, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), reg, comp);
+  RMG_LAUNCH(k_to_composite_nodes, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), reg, comp);
   LAUNCH_CHECK();
   if (L.ngroups > 0) {
-    hipLaunchKernelGGL(k_to_composite_groups, dim3(cdiv(L.ngroups, kBlock)), dim3(kBlock), 0, st,
+    RMG_LAUNCH(k_to_composite_groups, dim3(cdiv(L.ngroups, kBlock)), dim3(kBlock), 0, st,
                        L.d_gptr.as<int64_t>(), L.d_gcopy.as<int>(), L.d_gcomp.as<int>(), L.ngroups, L.ndof, reg,
                        comp, average);
     LAUNCH_CHECK();
@@ -782,7 +915,7 @@ __global__ __launch_bounds__(256) void k_gemv(int n, const double* __restrict__ 
 
 void launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, 4)), dim3(256), 0, st, n, A, x, y);
+  RMG_LAUNCH(k_gemv, dim3(cdiv(n, 4)), dim3(256), 0, st, n, A, x, y);
   LAUNCH_CHECK();
 }
 
@@ -790,20 +923,20 @@ void launch_coarse_gather(const Level& L, bool lowp, const void* b, hipStream_t 
   const int n = L.nc;
   const int ncnode = (int)L.ncomp;
   if (lowp)
-    hipLaunchKernelGGL(k_gather<float>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, ncnode, L.ndof,
+    RMG_LAUNCH(k_gather<float>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, ncnode, L.ndof,
                        L.comp_owner.as<int>(), (const float*)b, L.cvec.as<double>());
   else
-    hipLaunchKernelGGL(k_gather<double>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, ncnode, L.ndof,
+    RMG_LAUNCH(k_gather<double>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, ncnode, L.ndof,
                        L.comp_owner.as<int>(), (const double*)b, L.cvec.as<double>());
   LAUNCH_CHECK();
 }
 
 void launch_coarse_scatter(const Level& L, bool lowp, void* u, hipStream_t st) {
   if (lowp)
-    hipLaunchKernelGGL(k_to_regional<float>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(),
+    RMG_LAUNCH(k_to_regional<float>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(),
                        L.cvec2.as<double>(), (float*)u);
   else
-    hipLaunchKernelGGL(k_to_regional<double>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(),
+    RMG_LAUNCH(k_to_regional<double>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(),
                        L.cvec2.as<double>(), (double*)u);
   LAUNCH_CHECK();
 }
@@ -811,7 +944,7 @@ void launch_coarse_scatter(const Level& L, bool lowp, void* u, hipStream_t st) {
 void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipStream_t st) {
   launch_coarse_gather(L, lowp, b, st);
   const int n = L.nc;
-  hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, 4)), dim3(256), 0, st, n, L.ainv.as<double>(), L.cvec.as<double>(),
+  RMG_LAUNCH(k_gemv, dim3(cdiv(n, 4)), dim3(256), 0, st, n, L.ainv.as<double>(), L.cvec.as<double>(),
                      L.cvec2.as<double>());
   LAUNCH_CHECK();
   launch_coarse_scatter(L, lowp, u, st);
@@ -963,13 +1096,13 @@ void launch_gauss_jordan(double* A, int n, hipStream_t st) {
   const int nt = (int)cdiv(n, 64);
   for (int k0 = 0; k0 < n; k0 += kGjB) {
     const int nb = std::min(kGjB, n - k0);
-    hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>());
-    hipLaunchKernelGGL(k_gj_tw, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>(),
+    RMG_LAUNCH(k_gj_panel, dim3(1), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>());
+    RMG_LAUNCH(k_gj_tw, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>(),
                        TT.as<double>(), W.as<double>());
-    hipLaunchKernelGGL(k_gj_rank, dim3(nt, nt), dim3(kBlock), 0, st, n, k0, nb, A, TT.as<double>());
-    hipLaunchKernelGGL(k_gj_rows, dim3(cdiv(n, kBlock), nb), dim3(kBlock), 0, st, n, k0, nb, A, W.as<double>(),
+    RMG_LAUNCH(k_gj_rank, dim3(nt, nt), dim3(kBlock), 0, st, n, k0, nb, A, TT.as<double>());
+    RMG_LAUNCH(k_gj_rows, dim3(cdiv(n, kBlock), nb), dim3(kBlock), 0, st, n, k0, nb, A, W.as<double>(),
                        X.as<double>());
-    hipLaunchKernelGGL(k_gj_cols, dim3(cdiv(n, kBlock / 64)), dim3(kBlock), 0, st, n, k0, nb, A, TT.as<double>());
+    RMG_LAUNCH(k_gj_cols, dim3(cdiv(n, kBlock / 64)), dim3(kBlock), 0, st, n, k0, nb, A, TT.as<double>());
   }
   LAUNCH_CHECK();
   RMG_HIP(hipStreamSynchronize(st));  // before the work buffers are released
@@ -983,7 +1116,7 @@ __global__ void k_check_inverse(int n, const double* __restrict__ A, int* flag) 
 }
 
 void launch_check_inverse(const double* A, int n, int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_check_inverse, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, A, flag);
+  RMG_LAUNCH(k_check_inverse, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, A, flag);
   LAUNCH_CHECK();
 }
 
@@ -1043,7 +1176,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_q1(LevelView L, Kmat K, con
 void launch_assemble_q1_scalar(const Level& L, const double* Kref, const double* elem_coef, hipStream_t st) {
   Kmat K;
   for (int i = 0; i < 64; ++i) K.k[i] = Kref[i];
-  hipLaunchKernelGGL(k_assemble_q1, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), K, elem_coef,
+  RMG_LAUNCH(k_assemble_q1, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), K, elem_coef,
                      L.coef.as<double>());
   LAUNCH_CHECK();
 }
@@ -1099,7 +1232,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_q1_elast(LevelView L, const
 }
 
 void launch_assemble_q1_elasticity(const Level& L, const double* Kdev, const double* youngs_dev, hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble_q1_elast, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), Kdev, youngs_dev,
+  RMG_LAUNCH(k_assemble_q1_elast, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), Kdev, youngs_dev,
                      L.coef.as<double>());
   LAUNCH_CHECK();
 }
@@ -1123,7 +1256,7 @@ __global__ void k_dirichlet_split(const int64_t* __restrict__ gptr, const int* _
 void launch_dirichlet_split(const Level& L, hipStream_t st) {
   if (L.ngroups == 0) return;
   const int center = L.npts == 27 ? 13 : (L.npts == 9 ? 4 : 2);
-  hipLaunchKernelGGL(k_dirichlet_split, dim3(cdiv(L.ngroups, kBlock)), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
+  RMG_LAUNCH(k_dirichlet_split, dim3(cdiv(L.ngroups, kBlock)), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
                      L.d_gcopy.as<int>(), L.d_gcomp.as<int>(), L.ngroups, L.view(), center, L.coef.as<double>());
   LAUNCH_CHECK();
 }
@@ -1156,9 +1289,9 @@ __global__ __launch_bounds__(kBlock) void k_mask_stencil(LevelView L, double* __
 
 void launch_mask_stencil(const Level& L, int* flag, hipStream_t st) {
   const dim3 g(L.blocks.size());
-  if (L.npts == 27) hipLaunchKernelGGL(k_mask_stencil<27>, g, dim3(kBlock), 0, st, L.view(), L.coef.as<double>(), flag);
-  else if (L.npts == 9) hipLaunchKernelGGL(k_mask_stencil<9>, g, dim3(kBlock), 0, st, L.view(), L.coef.as<double>(), flag);
-  else hipLaunchKernelGGL(k_mask_stencil<5>, g, dim3(kBlock), 0, st, L.view(), L.coef.as<double>(), flag);
+  if (L.npts == 27) RMG_LAUNCH(k_mask_stencil<27>, g, dim3(kBlock), 0, st, L.view(), L.coef.as<double>(), flag);
+  else if (L.npts == 9) RMG_LAUNCH(k_mask_stencil<9>, g, dim3(kBlock), 0, st, L.view(), L.coef.as<double>(), flag);
+  else RMG_LAUNCH(k_mask_stencil<5>, g, dim3(kBlock), 0, st, L.view(), L.coef.as<double>(), flag);
   LAUNCH_CHECK();
 }
 
@@ -1209,11 +1342,11 @@ __global__ __launch_bounds__(kBlock) void k_split_composite(LevelView L, const d
 void launch_split_composite(const Level& L, const double* comp, int* flag, hipStream_t st) {
   const dim3 g(L.blocks.size());
   if (L.npts == 27)
-    hipLaunchKernelGGL(k_split_composite<27>, g, dim3(kBlock), 0, st, L.view(), comp, L.ncomp, L.coef.as<double>(), flag);
+    RMG_LAUNCH(k_split_composite<27>, g, dim3(kBlock), 0, st, L.view(), comp, L.ncomp, L.coef.as<double>(), flag);
   else if (L.npts == 9)
-    hipLaunchKernelGGL(k_split_composite<9>, g, dim3(kBlock), 0, st, L.view(), comp, L.ncomp, L.coef.as<double>(), flag);
+    RMG_LAUNCH(k_split_composite<9>, g, dim3(kBlock), 0, st, L.view(), comp, L.ncomp, L.coef.as<double>(), flag);
   else
-    hipLaunchKernelGGL(k_split_composite<5>, g, dim3(kBlock), 0, st, L.view(), comp, L.ncomp, L.coef.as<double>(), flag);
+    RMG_LAUNCH(k_split_composite<5>, g, dim3(kBlock), 0, st, L.view(), comp, L.ncomp, L.coef.as<double>(), flag);
   LAUNCH_CHECK();
 }
 
@@ -1257,13 +1390,13 @@ void launch_csr_to_stencil(const Level& L, const int64_t* rowptr, const int* col
                            double* comp, int* flag, hipStream_t st) {
   const dim3 g(cdiv(L.ncomp, kBlock)), b(kBlock);
   if (L.npts == 27)
-    hipLaunchKernelGGL(k_csr_to_stencil<27>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
+    RMG_LAUNCH(k_csr_to_stencil<27>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
                        flag);
   else if (L.npts == 9)
-    hipLaunchKernelGGL(k_csr_to_stencil<9>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
+    RMG_LAUNCH(k_csr_to_stencil<9>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
                        flag);
   else
-    hipLaunchKernelGGL(k_csr_to_stencil<5>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
+    RMG_LAUNCH(k_csr_to_stencil<5>, g, b, 0, st, L.comp[0], L.comp[1], L.comp[2], rowptr, colind, vals, comp,
                        flag);
   LAUNCH_CHECK();
 }
@@ -1283,7 +1416,7 @@ __global__ void k_region_stencil_io(int64_t off, int nn, int ncoef, double* __re
 void launch_region_stencil_io(const Level& L, int region, double* soa, int to_level, hipStream_t st) {
   const RegionGeo& R = L.regs[region];
   const int64_t tot = (int64_t)R.n * L.ncoef();
-  hipLaunchKernelGGL(k_region_stencil_io, dim3(cdiv(tot, kBlock)), dim3(kBlock), 0, st, R.off, R.n, L.ncoef(),
+  RMG_LAUNCH(k_region_stencil_io, dim3(cdiv(tot, kBlock)), dim3(kBlock), 0, st, R.off, R.n, L.ncoef(),
                      L.coef.as<double>(), soa, to_level);
   LAUNCH_CHECK();
 }
@@ -1346,9 +1479,9 @@ void launch_make_lowp(Level& L, int coef_type, hipStream_t st) {
   }
   const dim3 g(cdiv(L.n, kBlock));
   if (L.ndof == 3)
-    hipLaunchKernelGGL(k_make_lowp<3>, g, dim3(kBlock), 0, st, L.n, L.coef.as<double>(), c32, cbf, centre);
+    RMG_LAUNCH(k_make_lowp<3>, g, dim3(kBlock), 0, st, L.n, L.coef.as<double>(), c32, cbf, centre);
   else
-    hipLaunchKernelGGL(k_make_lowp<1>, g, dim3(kBlock), 0, st, L.n, L.coef.as<double>(), c32, cbf, centre);
+    RMG_LAUNCH(k_make_lowp<1>, g, dim3(kBlock), 0, st, L.n, L.coef.as<double>(), c32, cbf, centre);
   LAUNCH_CHECK();
   L.dinv_lo.alloc(sizeof(float) * (size_t)L.ndofs());
   launch_f64_to_f32(L.ndofs(), L.dinv.as<double>(), L.dinv_lo.as<float>(), st);
@@ -1403,34 +1536,131 @@ __global__ __launch_bounds__(kBlock) void k_make_sym(LevelView L, const C* __res
 // Region table of the symmetric 2.5D kernel: the upper couplings of node (2, 2, 2) of every region
 // with at least 5 nodes a side (one block per region), then every node two or more nodes inside its
 // region (x, y, z in [2, extent - 3]) compares its own with them bit for bit and clears the
-// region's flag on a difference.
+// region's flag on a difference.  A deep node's lower coupling A(i, i+s) is the upper coupling of
+// its neighbour i+s, which lies in the layer around the deep box when the node is on the box's
+// surface (on the low faces, and on the high ones through the offsets that are lower in z or y
+// but not in x or y): the nodes of that layer (coordinates in [1, extent - 2]) compare their upper
+// couplings towards deep nodes with the table too, so that every coupling of a deep node, upper or
+// lower, is the table's bit for bit.
 __device__ __forceinline__ bool same_bits(double a, double b) { return __double_as_longlong(a) == __double_as_longlong(b); }
 __device__ __forceinline__ bool same_bits(float a, float b) { return __float_as_int(a) == __float_as_int(b); }
 
 template <class C>
-__global__ void k_sym_table_ref(LevelView L, const C* __restrict__ sym, C* __restrict__ table, int* __restrict__ ok) {
+__global__ void k_sym_table_ref(LevelView L, const C* __restrict__ sym, C* __restrict__ table, int* __restrict__ ok,
+                                int* __restrict__ face) {
   const int k = blockIdx.x, s = threadIdx.x;
   const RegionGeo R = L.regs[k];
   const bool deep = R.ex >= 5 && R.ey >= 5 && R.ez >= 5;
   if (s < kSymPts)
     table[k * kSymPts + s] = deep ? sym[coef_index(R.off + 2 + 2 * R.ex + 2 * (int64_t)R.ex * R.ey, s, kSymPts)] : (C)0;
   if (s == 0) ok[k] = deep ? 1 : 0;
+  if (s < 6) face[k * 6 + s] = deep ? 1 : 0;
 }
 
 template <class C>
 __global__ __launch_bounds__(kBlock) void k_sym_table_check(LevelView L, const C* __restrict__ sym,
-                                                            const C* __restrict__ table, int* __restrict__ ok) {
+                                                            const C* __restrict__ table, int* __restrict__ ok,
+                                                            int* __restrict__ face) {
   const BlockDesc bd = L.blocks[blockIdx.x];
   const RegionGeo R = L.regs[bd.region];
   const int li = bd.start + (int)threadIdx.x;
   if (li >= R.n) return;
   int x, y, z;
   decompose(R, li, x, y, z);
-  if (x < 2 || x >= R.ex - 2 || y < 2 || y >= R.ey - 2 || z < 2 || z >= R.ez - 2) return;
+  // Faces whose box may reach one node further out: on face (axis a, side) every node of the
+  // layer one node in (the other coordinates in [2, extent - 2)) carries the table in all its
+  // upper couplings, and every node on the face in the couplings pointing inwards (into that layer).
+  // Where faces meet, k_sym_table_box checks the box they make together.
+  {
+    const int c[3] = {x, y, z}, e[3] = {R.ex, R.ey, R.ez};
+    const int64_t gi0 = R.off + li;
+    for (int a = 0; a < 3; ++a)
+      for (int side = 0; side < 2; ++side) {
+        const int in1 = side ? e[a] - 2 : 1, out0 = side ? e[a] - 1 : 0;
+        bool others = true;  // the box's rows on this face lie inside the base box's range
+        for (int b = 0; b < 3; ++b)
+          if (b != a) others = others && c[b] >= 2 && c[b] < e[b] - 2;
+        bool same = true;
+        if (c[a] == in1 && others) {
+          for (int s = 0; s < kSymPts; ++s) same = same && same_bits(sym[coef_index(gi0, s, kSymPts)], table[bd.region * kSymPts + s]);
+        } else if (c[a] == out0) {
+          for (int s = 0; s < kSymPts; ++s) {
+            int d[3];
+            stencil_offset<27>(13 + s, d[0], d[1], d[2]);
+            if (d[a] != (side ? -1 : 1)) continue;
+            same = same && same_bits(sym[coef_index(gi0, s, kSymPts)], table[bd.region * kSymPts + s]);
+          }
+        }
+        if (!same) face[bd.region * 6 + 2 * a + side] = 0;
+      }
+  }
+  auto deep = [&](int a, int b, int c) {
+    return a >= 2 && a < R.ex - 2 && b >= 2 && b < R.ey - 2 && c >= 2 && c < R.ez - 2;
+  };
+  const bool layer1 = x >= 1 && x < R.ex - 1 && y >= 1 && y < R.ey - 1 && z >= 1 && z < R.ez - 1 && !deep(x, y, z);
+  if (!deep(x, y, z) && !layer1) return;
   const int64_t gi = R.off + li;
   bool same = true;
-  for (int s = 0; s < kSymPts; ++s) same = same && same_bits(sym[coef_index(gi, s, kSymPts)], table[bd.region * kSymPts + s]);
+  for (int s = 0; s < kSymPts; ++s) {
+    int dx, dy, dz;
+    stencil_offset<27>(13 + s, dx, dy, dz);
+    if (layer1 && !deep(x + dx, y + dy, z + dz)) continue;  // couplings that no deep node reads
+    same = same && same_bits(sym[coef_index(gi, s, kSymPts)], table[bd.region * kSymPts + s]);
+  }
   if (!same) ok[bd.region] = 0;
+}
+
+// The exact condition for a region's candidate deep box B: every node in B outside [2, e - 2)^3
+// carries the table in all its upper couplings, and every node outside B does in each upper
+// coupling towards a node of B.  A failure clears the region's flag (its box falls back to
+// [2, e - 2)^3, which k_sym_table_check verified).
+template <class C>
+__global__ __launch_bounds__(kBlock) void k_sym_table_box(LevelView L, const C* __restrict__ sym,
+                                                          const C* __restrict__ table, const DeepBox* __restrict__ boxes,
+                                                          int* __restrict__ good) {
+  const BlockDesc bd = L.blocks[blockIdx.x];
+  const RegionGeo R = L.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= R.n || !good[bd.region]) return;
+  const DeepBox B = boxes[bd.region];
+  int x, y, z;
+  decompose(R, li, x, y, z);
+  auto in = [&](int a, int b, int c) {
+    return a >= B.lo[0] && a < B.hi[0] && b >= B.lo[1] && b < B.hi[1] && c >= B.lo[2] && c < B.hi[2];
+  };
+  const bool base = x >= 2 && x < R.ex - 2 && y >= 2 && y < R.ey - 2 && z >= 2 && z < R.ez - 2;
+  const bool mine = in(x, y, z);
+  if (mine && base) return;  // checked against the table already
+  const int64_t gi = R.off + li;
+  bool same = true;
+  for (int s = 0; s < kSymPts; ++s) {
+    int dx, dy, dz;
+    stencil_offset<27>(13 + s, dx, dy, dz);
+    if (!mine && !in(x + dx, y + dy, z + dz)) continue;
+    same = same && same_bits(sym[coef_index(gi, s, kSymPts)], table[bd.region * kSymPts + s]);
+  }
+  if (!same) good[bd.region] = 0;
+}
+
+// Packed upper couplings of the served regions' x-face nodes (the shell nodes of the deep box's
+// rows: x outside [B.lo, B.hi) with y and z inside), in the order (z, y, x slot) from xoff[region]:
+// one thread per node.
+__global__ __launch_bounds__(kBlock) void k_pack_xface(LevelView L, const DeepBox* __restrict__ boxes,
+                                                       const int64_t* __restrict__ xoff,
+                                                       const double* __restrict__ sym, double* __restrict__ packed) {
+  const int k = blockIdx.y;
+  const RegionGeo R = L.regs[k];
+  const DeepBox B = boxes[k];
+  const int64_t n = xoff[k + 1] - xoff[k];
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const int nxr = B.lo[0] + R.ex - B.hi[0], rows = B.hi[1] - B.lo[1];
+  const int rz = (int)(j / ((int64_t)nxr * rows)), r = (int)(j - (int64_t)rz * nxr * rows);
+  const int row = r / nxr, px = r - row * nxr;
+  const int y = B.lo[1] + row, z = B.lo[2] + rz;
+  const int x = px < B.lo[0] ? px : B.hi[0] + px - B.lo[0];
+  const int64_t gi = R.off + ((int64_t)z * R.ey + y) * R.ex + x;
+  for (int s = 0; s < kSymPts; ++s) packed[coef_index(xoff[k] + j, s, kSymPts)] = sym[coef_index(gi, s, kSymPts)];
 }
 
 template <class C>
@@ -1440,19 +1670,74 @@ static void make_sym_table(Level& L, hipStream_t st) {
   const C* sym = static_cast<const C*>(L.coef_sym.p);
   tab.alloc(sizeof(C) * kSymPts * L.nreg);
   ok.alloc(sizeof(int) * L.nreg);
-  hipLaunchKernelGGL((k_sym_table_ref<C>), dim3(L.nreg), dim3(64), 0, st, L.view(), sym, tab.as<C>(), ok.as<int>());
-  hipLaunchKernelGGL((k_sym_table_check<C>), dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
-                     static_cast<const C*>(tab.p), ok.as<int>());
+  L.sym_table_face.alloc(sizeof(int) * 6 * L.nreg);
+  RMG_LAUNCH((k_sym_table_ref<C>), dim3(L.nreg), dim3(64), 0, st, L.view(), sym, tab.as<C>(), ok.as<int>(),
+             L.sym_table_face.as<int>());
+  RMG_LAUNCH((k_sym_table_check<C>), dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
+                     static_cast<const C*>(tab.p), ok.as<int>(), L.sym_table_face.as<int>());
   LAUNCH_CHECK();
   // no region served: drop the table, so the kernel without it runs
-  std::vector<int> flags(L.nreg);
+  std::vector<int> flags(L.nreg), faces(6 * L.nreg);
   RMG_HIP(hipMemcpyAsync(flags.data(), ok.p, sizeof(int) * L.nreg, hipMemcpyDeviceToHost, st));
+  RMG_HIP(hipMemcpyAsync(faces.data(), L.sym_table_face.p, sizeof(int) * 6 * L.nreg, hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));
+  L.sym_table_face.release();
+  // deep boxes: two nodes inside, one where the face allows it; where faces meet, the box they
+  // make together is checked as a whole, else the region keeps the two-node box
+  std::vector<DeepBox> boxes(L.nreg);
+  std::vector<int> widened(L.nreg, 0);
+  for (int k = 0; k < L.nreg; ++k) {
+    const RegionGeo& R = L.regs[k];
+    const int e[3] = {R.ex, R.ey, R.ez};
+    for (int a = 0; a < 3; ++a) {
+      const bool lo1 = flags[k] && faces[6 * k + 2 * a], hi1 = flags[k] && faces[6 * k + 2 * a + 1];
+      boxes[k].lo[a] = lo1 ? 1 : 2;
+      boxes[k].hi[a] = hi1 ? e[a] - 1 : e[a] - 2;
+      widened[k] = widened[k] || lo1 || hi1;
+    }
+  }
+  bool any_wide = false;
+  for (int w : widened) any_wide = any_wide || w;
+  if (any_wide) {
+    DBuf dbox, dgood;
+    dbox.alloc(sizeof(DeepBox) * L.nreg);
+    dgood.alloc(sizeof(int) * L.nreg);
+    RMG_HIP(hipMemcpyAsync(dbox.p, boxes.data(), sizeof(DeepBox) * L.nreg, hipMemcpyHostToDevice, st));
+    RMG_HIP(hipMemcpyAsync(dgood.p, widened.data(), sizeof(int) * L.nreg, hipMemcpyHostToDevice, st));
+    RMG_LAUNCH((k_sym_table_box<C>), dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
+               static_cast<const C*>(tab.p), dbox.as<DeepBox>(), dgood.as<int>());
+    LAUNCH_CHECK();
+    std::vector<int> good(L.nreg);
+    RMG_HIP(hipMemcpyAsync(good.data(), dgood.p, sizeof(int) * L.nreg, hipMemcpyDeviceToHost, st));
+    RMG_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < L.nreg; ++k)
+      if (widened[k] && !good[k]) {
+        const RegionGeo& R = L.regs[k];
+        const int e[3] = {R.ex, R.ey, R.ez};
+        for (int a = 0; a < 3; ++a) {
+          boxes[k].lo[a] = 2;
+          boxes[k].hi[a] = e[a] - 2;
+        }
+      }
+  }
   int served = 0;
   for (int f : flags) served += f != 0;
   if (served == 0) {
     tab.release();
     ok.release();
+    clear_split(L);
+  } else {
+    make_split(L, flags, boxes);
+    const int64_t nx = L.xface_off.back();
+    if (nx > 0) {
+      int64_t most = 0;
+      for (int k = 0; k < L.nreg; ++k) most = std::max(most, L.xface_off[k + 1] - L.xface_off[k]);
+      L.xface_coef.alloc(sizeof(double) * coef_elems(nx, kSymPts));
+      RMG_LAUNCH(k_pack_xface, dim3(cdiv(most, kBlock), L.nreg), dim3(kBlock), 0, st, L.view(),
+                 L.d_deep_box.as<DeepBox>(), L.d_xface_off.as<int64_t>(), static_cast<const double*>(L.coef_sym.p),
+                 L.xface_coef.as<double>());
+      LAUNCH_CHECK();
+    }
   }
 }
 
@@ -1462,15 +1747,15 @@ static void make_sym_t(Level& L, bool lowp, int* flag, hipStream_t st) {
   const dim3 g(L.blocks.size()), b(kBlock);
   if (!lowp) {
     L.coef_sym.alloc(sizeof(double) * ne);
-    hipLaunchKernelGGL((k_make_sym<NDOF, double>), g, b, 0, st, L.view(), L.coef.as<double>(), L.coef_sym.as<double>(),
+    RMG_LAUNCH((k_make_sym<NDOF, double>), g, b, 0, st, L.view(), L.coef.as<double>(), L.coef_sym.as<double>(),
                        1e-11, flag);
   } else if (L.ct_lo == kCoefF32) {
     L.coef_lo_sym.alloc(sizeof(float) * ne);
-    hipLaunchKernelGGL((k_make_sym<NDOF, float>), g, b, 0, st, L.view(), L.coef_lo.as<float>(),
+    RMG_LAUNCH((k_make_sym<NDOF, float>), g, b, 0, st, L.view(), L.coef_lo.as<float>(),
                        L.coef_lo_sym.as<float>(), 0.0, nullptr);
   } else {
     L.coef_lo_sym.alloc(sizeof(uint16_t) * ne);
-    hipLaunchKernelGGL((k_make_sym<NDOF, uint16_t>), g, b, 0, st, L.view(), L.coef_lo.as<uint16_t>(),
+    RMG_LAUNCH((k_make_sym<NDOF, uint16_t>), g, b, 0, st, L.view(), L.coef_lo.as<uint16_t>(),
                        L.coef_lo_sym.as<uint16_t>(), 0.0, nullptr);
   }
   LAUNCH_CHECK();
@@ -1482,6 +1767,7 @@ bool launch_make_sym(Level& L, bool lowp, hipStream_t st, bool table) {
   if (!lowp) {
     L.sym_table.release();
     L.sym_table_ok.release();
+    clear_split(L);
   }
   if (L.dim != 3 || L.npts != 27) return false;
   if (lowp) {
@@ -1536,9 +1822,9 @@ int64_t launch_cg_update(const Level& L, double* scalars, double* x, double* r, 
                          double* partials, hipStream_t st) {
   const int64_t nb = (int64_t)L.blocks.size();
   if (L.ndof == 3)
-    hipLaunchKernelGGL(k_cg_update<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials);
+    RMG_LAUNCH(k_cg_update<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials);
   else
-    hipLaunchKernelGGL(k_cg_update<1>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials);
+    RMG_LAUNCH(k_cg_update<1>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials);
   LAUNCH_CHECK();
   return nb + dot_groups(L, r, r, partials + nb, st);
 }
@@ -1552,7 +1838,7 @@ __global__ void k_cg_direction(int64_t n, const double* __restrict__ scalars, co
 }
 
 void launch_cg_direction(int64_t n, double* scalars, const double* z, double* p, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_direction, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, scalars, z, p);
+  RMG_LAUNCH(k_cg_direction, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, scalars, z, p);
   LAUNCH_CHECK();
 }
 
@@ -1569,7 +1855,7 @@ __global__ void k_cg_scalars(double* s, int mode) {
 }
 
 void launch_cg_scalars(double* scalars, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(1), 0, st, scalars, mode);
+  RMG_LAUNCH(k_cg_scalars, dim3(1), dim3(1), 0, st, scalars, mode);
   LAUNCH_CHECK();
 }
 

@@ -45,10 +45,10 @@ __global__ __launch_bounds__(kBlock) void k_csr_wave_apply(int64_t n, const int6
 void launch_sp_apply(const SpDev& M, const double* x, double* y, bool accumulate, hipStream_t st) {
   if (M.n == 0) return;
   if (M.wave)
-    hipLaunchKernelGGL(k_csr_wave_apply, dim3(cdiv(M.n, kWaveRows)), dim3(kBlock), 0, st, M.n, M.sptr.as<int64_t>(),
+    RMG_LAUNCH(k_csr_wave_apply, dim3(cdiv(M.n, kWaveRows)), dim3(kBlock), 0, st, M.n, M.sptr.as<int64_t>(),
                        M.col.as<int>(), M.val.as<double>(), x, y, accumulate ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_ell_apply, dim3(cdiv(M.n, kBlock)), dim3(kBlock), 0, st, M.n, M.sptr.as<int64_t>(),
+    RMG_LAUNCH(k_ell_apply, dim3(cdiv(M.n, kBlock)), dim3(kBlock), 0, st, M.n, M.sptr.as<int64_t>(),
                        M.col.as<int>(), M.val.as<double>(), x, y, accumulate ? 1 : 0);
   LAUNCH_CHECK();
 }
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_amg_cheb_first(int64_t n, double inv
 void launch_amg_cheb_first(int64_t n, double inv_theta, const double* dinv, const double* r, double* d, double* u,
                            bool zero, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_amg_cheb_first, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, inv_theta, dinv, r, d, u,
+  RMG_LAUNCH(k_amg_cheb_first, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, inv_theta, dinv, r, d, u,
                      zero ? 1 : 0);
   LAUNCH_CHECK();
 }
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_amg_cheb_step(int64_t n, double c1, 
 void launch_amg_cheb_step(int64_t n, double c1, double c2, const double* dinv, const double* b, const double* y,
                           double* d, double* u, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_amg_cheb_step, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, c1, c2, dinv, b, y, d, u);
+  RMG_LAUNCH(k_amg_cheb_step, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, c1, c2, dinv, b, y, d, u);
   LAUNCH_CHECK();
 }
 
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_amg_sub(int64_t n, const double* __r
 
 void launch_amg_sub(int64_t n, const double* b, const double* y, double* r, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_amg_sub, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, b, y, r);
+  RMG_LAUNCH(k_amg_sub, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, b, y, r);
   LAUNCH_CHECK();
 }
 

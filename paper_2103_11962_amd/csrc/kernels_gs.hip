@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_sweep(LevelView L, const int*
 
 template <int NPTS, int NDOF>
 static void gs_fill_launch(const Level& L, hipStream_t st) {
-  hipLaunchKernelGGL((k_gs_fill<NPTS, NDOF>), dim3(L.nreg), dim3(kGsThreads), 0, st, L.view(), L.gs_rplane.as<int>(),
+  RMG_LAUNCH((k_gs_fill<NPTS, NDOF>), dim3(L.nreg), dim3(kGsThreads), 0, st, L.view(), L.gs_rplane.as<int>(),
                      L.gs_pbase.as<int64_t>(), L.coef.as<double>(), L.dinv.as<double>(), L.gs_coef.as<double>(),
                      L.gs_dinv.as<double>());
   LAUNCH_CHECK();
@@ -202,10 +202,10 @@ static void gs_launch(const Level& L, const double* r, double* delta, double ome
   const double* di = L.gs_dinv.as<double>();
   double* ds = L.gs_d.as<double>();
   if (backward)
-    hipLaunchKernelGGL((k_gs_sweep<NPTS, NDOF, true>), dim3(L.nreg), dim3(kGsThreads), 0, st, V, rp, pb, cs, di, r,
+    RMG_LAUNCH((k_gs_sweep<NPTS, NDOF, true>), dim3(L.nreg), dim3(kGsThreads), 0, st, V, rp, pb, cs, di, r,
                        delta, ds, omega);
   else
-    hipLaunchKernelGGL((k_gs_sweep<NPTS, NDOF, false>), dim3(L.nreg), dim3(kGsThreads), 0, st, V, rp, pb, cs, di, r,
+    RMG_LAUNCH((k_gs_sweep<NPTS, NDOF, false>), dim3(L.nreg), dim3(kGsThreads), 0, st, V, rp, pb, cs, di, r,
                        delta, ds, omega);
   LAUNCH_CHECK();
 }
@@ -240,10 +240,10 @@ void launch_interface_avg(const Level& L, double* w, hipStream_t st) {
   if (L.ngroups == 0) return;
   const dim3 g(cdiv(L.ngroups, kBlock));
   if (L.ndof == 3)
-    hipLaunchKernelGGL((k_group_reduce<3, true>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
+    RMG_LAUNCH((k_group_reduce<3, true>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
                        L.d_gcopy.as<int>(), L.ngroups, w);
   else
-    hipLaunchKernelGGL((k_group_reduce<1, true>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
+    RMG_LAUNCH((k_group_reduce<1, true>), g, dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
                        L.d_gcopy.as<int>(), L.ngroups, w);
   LAUNCH_CHECK();
 }
@@ -252,9 +252,9 @@ void launch_group_reduce(const int64_t* gptr, const int* gcopy, int64_t ngroups,
   if (ngroups == 0) return;
   const dim3 g(cdiv(ngroups, kBlock));
   if (avg)
-    hipLaunchKernelGGL((k_group_reduce<1, true>), g, dim3(kBlock), 0, st, gptr, gcopy, ngroups, w);
+    RMG_LAUNCH((k_group_reduce<1, true>), g, dim3(kBlock), 0, st, gptr, gcopy, ngroups, w);
   else
-    hipLaunchKernelGGL((k_group_reduce<1, false>), g, dim3(kBlock), 0, st, gptr, gcopy, ngroups, w);
+    RMG_LAUNCH((k_group_reduce<1, false>), g, dim3(kBlock), 0, st, gptr, gcopy, ngroups, w);
   LAUNCH_CHECK();
 }
 

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_hyb_spmv(int64_t n, const int64_t* _
 
 void launch_hyb_spmv(const HLevelDev& L, const double* x, double* y, hipStream_t st) {
   if (L.n == 0) return;
-  hipLaunchKernelGGL(k_hyb_spmv, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, L.sptr.as<int64_t>(),
+  RMG_LAUNCH(k_hyb_spmv, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, L.sptr.as<int64_t>(),
                      L.col.as<int>(), L.val.as<double>(), x, y);
   LAUNCH_CHECK();
 }
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_hyb_finish(int64_t n, const double* 
 void launch_hyb_finish(int64_t n, const double* b, const double* y, const double* invm, double* out,
                        hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_hyb_finish, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, b, y, invm, out);
+  RMG_LAUNCH(k_hyb_finish, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, b, y, invm, out);
   LAUNCH_CHECK();
 }
 
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kHybGsThreads) void k_hyb_gs(const int* __restrict_
 void launch_hyb_gs(const HLevelDev& L, const double* r, double* d, double omega, bool backward, hipStream_t st) {
   if (L.n == 0) return;
   const HLevelDev::Sweep& S = backward ? L.bwd : L.fwd;
-  hipLaunchKernelGGL(k_hyb_gs, dim3(L.nreg), dim3(kHybGsThreads), 0, st, S.reg.as<int>(), S.lv.as<int>(),
+  RMG_LAUNCH(k_hyb_gs, dim3(L.nreg), dim3(kHybGsThreads), 0, st, S.reg.as<int>(), S.lv.as<int>(),
                      S.rows.as<int>(), S.tsptr.as<int64_t>(), S.tcnt.as<int>(), S.tcol.as<int>(),
                      S.tval.as<double>(), L.dinv.as<double>(), r, d, omega);
   LAUNCH_CHECK();
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_hyb_jacobi(int64_t n, double omega, 
 void launch_hyb_jacobi(int64_t n, double omega, const double* dinv, const double* r, double* u, bool zero,
                        hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_hyb_jacobi, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, omega, dinv, r, u, zero ? 1 : 0);
+  RMG_LAUNCH(k_hyb_jacobi, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, omega, dinv, r, u, zero ? 1 : 0);
   LAUNCH_CHECK();
 }
 
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_hyb_restrict(int64_t nc, const int64
 void launch_hyb_restrict(int64_t nc, const int64_t* cptr, const int* crows, const double* rs, double* bc,
                          hipStream_t st) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_hyb_restrict, dim3(cdiv(nc, kBlock)), dim3(kBlock), 0, st, nc, cptr, crows, rs, bc);
+  RMG_LAUNCH(k_hyb_restrict, dim3(cdiv(nc, kBlock)), dim3(kBlock), 0, st, nc, cptr, crows, rs, bc);
   LAUNCH_CHECK();
 }
 
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_hyb_prolong(int64_t n, const int* __
 
 void launch_hyb_prolong(int64_t n, const int* agg, const double* uc, double* u, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_hyb_prolong, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, agg, uc, u);
+  RMG_LAUNCH(k_hyb_prolong, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, agg, uc, u);
   LAUNCH_CHECK();
 }
 
@@ -153,11 +153,11 @@ __global__ __launch_bounds__(kBlock) void k_hyb_scatter(int64_t n, const int* __
 
 void launch_hyb_coarse(const HLevelDev& L, const double* b, double* z, hipStream_t st) {
   if (L.nc == 0) return;
-  hipLaunchKernelGGL(k_hyb_gather, dim3(cdiv(L.nc, kBlock)), dim3(kBlock), 0, st, L.nc, L.owner.as<int>(), b,
+  RMG_LAUNCH(k_hyb_gather, dim3(cdiv(L.nc, kBlock)), dim3(kBlock), 0, st, L.nc, L.owner.as<int>(), b,
                      L.cvec.as<double>());
   LAUNCH_CHECK();
   launch_dense_gemv(L.nc, L.ainv.as<double>(), L.cvec.as<double>(), L.cvec2.as<double>(), st);
-  hipLaunchKernelGGL(k_hyb_scatter, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, L.rowcomp.as<int>(),
+  RMG_LAUNCH(k_hyb_scatter, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, L.rowcomp.as<int>(),
                      L.cvec2.as<double>(), z);
   LAUNCH_CHECK();
 }

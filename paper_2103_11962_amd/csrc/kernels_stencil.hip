@@ -406,6 +406,236 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
   }
 }
 
+// ------------------------------------------ region-table split: deep tiles and the shell
+// A region whose nodes two or more nodes inside it all carry the region table's couplings (bit
+// for bit, checked at setup) is split into its deep box [2, e-2)^3, run by k_stencil_deep, and its
+// outer two layers (the shell), run by k_stencil_shell.  Every node's 27 products are summed in
+// the order of k_stencil3d's symmetric path (the upper couplings s = 13..26, then the lower ones
+// s = 0..12), so the results are those of streaming every coupling bit for bit.
+
+// Deep tiles: ty rows of tx deep nodes, nz planes, all inside the deep box, so every neighbour
+// lies inside the region and no node is shared.  Couplings come from the region's table (uniform
+// per tile: scalar loads); no coefficient is streamed.  The input vector's planes pass through two
+// LDS slots as in k_stencil3d; b and the old direction are read a plane ahead.
+template <int NT, StencilOp OP, bool DOT>
+__global__ __launch_bounds__(NT) void k_stencil_deep(LevelView L, const Tile3* __restrict__ tiles,
+                                                     const double* __restrict__ table, OpP<double> p,
+                                                     double* __restrict__ partials) {
+  constexpr int kPlane = tile_plane_cap(NT);
+  constexpr int kFetch = (kPlane + NT - 1) / NT;
+  constexpr bool kPreB = OP == StencilOp::Residual || OP == StencilOp::ResidualScaled || OP == StencilOp::Cheb ||
+                         OP == StencilOp::ChebFirst;
+  constexpr bool kPreD = OP == StencilOp::Cheb;
+  __shared__ double pl[2][kPlane];
+  const Tile3 T = tiles[blockIdx.x];
+  const RegionGeo R = L.regs[T.region];
+  const int t = threadIdx.x;
+  const int W = T.tx + 2, PL = (T.ty + 2) * W;
+  const int ty = t / T.tx, tx = t - ty * T.tx;
+  const bool active = ty < T.ty;
+  const int x = T.x0 + tx, y = T.y0 + ty;
+  const int sy = R.ex, sz = R.ex * R.ey;
+  const double* __restrict__ xr = p.x + R.off;
+  double tab[kSymPts];
+#pragma unroll
+  for (int k = 0; k < kSymPts; ++k) tab[k] = table[T.region * kSymPts + k];
+  double pre[kFetch];
+  auto fetch = [&](int zz) {
+#pragma unroll
+    for (int k = 0; k < kFetch; ++k) {
+      const int idx = t + k * NT;
+      double v = 0.0;
+      if (idx < PL) {
+        const int r = idx / W;
+        v = xr[(int64_t)zz * sz + (int64_t)(T.y0 - 1 + r) * sy + (T.x0 - 1 + idx - r * W)];
+      }
+      pre[k] = v;
+    }
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int k = 0; k < kFetch; ++k) {
+      const int idx = t + k * NT;
+      if (idx < PL) pl[slot][idx] = pre[k];
+    }
+  };
+  double rm[9], rc[9], rp[9];
+  auto readn = [&](int slot, double* r) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) r[j] = pl[slot][(ty + 1 + j / 3 - 1) * W + tx + 1 + j % 3 - 1];
+  };
+  const int z0 = T.z0, z1 = T.z0 + T.nz;
+  double nb = 0.0, nd = 0.0;
+  auto load_bd = [&](int z2) {
+    if (active && z2 < z1) {
+      const int64_t g = R.off + (int64_t)z2 * sz + (int64_t)y * sy + x;
+      if constexpr (kPreB) nb = p.b[g];
+      if constexpr (kPreD) nd = p.d[g];
+    }
+  };
+  load_bd(z0);
+  fetch(z0 - 1);
+  store(0);
+  fetch(z0);
+  store(1);
+  __syncthreads();
+  if (active) {
+    readn(0, rm);
+    readn(1, rc);
+  }
+  __syncthreads();
+  fetch(z0 + 1);
+  store(0);
+  __syncthreads();
+  double contrib = 0.0;
+  for (int zz = z0; zz < z1; ++zz) {
+    const int sp = (zz - z0) & 1;  // slot holding plane zz + 1
+    const double cb = nb, cd = nd;
+    load_bd(zz + 1);
+    if (active) readn(sp, rp);
+    if (zz + 2 <= z1) fetch(zz + 2);
+    if (active) {
+      double acc = 0.0;
+      // one rounding per product, as the contracted sums of the tiled kernels
+#pragma unroll
+      for (int s = 13; s < 27; ++s) acc = fma(tab[s - 13], s < 18 ? rc[s % 9] : rp[s % 9], acc);
+#pragma unroll
+      for (int s = 0; s < 13; ++s) acc = fma(tab[13 - s], s < 9 ? rm[s] : rc[s % 9], acc);
+      const int64_t gi = R.off + (int64_t)zz * sz + (int64_t)y * sy + x;
+      if constexpr (kPreB) contrib += finish_pre<OP, DOT, double, true>(p, gi, acc, 1, rc[4], tab[0], cb, cd);
+      else contrib += finish<OP, DOT, double, true>(p, gi, acc, 1, rc[4], tab[0]);
+    }
+    if (zz + 2 <= z1) store(sp ^ 1);  // plane zz + 2 replaces plane zz
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      rm[j] = rc[j];
+      rc[j] = rp[j];
+    }
+    __syncthreads();
+  }
+  if constexpr (DOT || OP == StencilOp::CgQ) {
+    double v = contrib;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __shared__ double sm[NT / 64];
+    if ((t & 63) == 0) sm[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int i = 0; i < NT / 64; ++i) s += sm[i];
+      partials[blockIdx.x] = s;
+    }
+  }
+}
+
+// Node of a table region's shell (the nodes outside its deep box B) from its index j in the region's
+// shell enumeration: the planes z < B.lo[2] and z >= B.hi[2] (x fastest), then for z in the box the
+// rows y < B.lo[1] and y >= B.hi[1], then for y and z in the box the nodes x < B.lo[0] and
+// x >= B.hi[0] (the x-face nodes, a few per row, rows in order).
+__device__ __forceinline__ void shell_node(const RegionGeo& R, const DeepBox& B, int j, int& x, int& y, int& z) {
+  const int nzl = B.lo[2], nyl = B.lo[1], nxl = B.lo[0];
+  const int rows_y = nyl + R.ey - B.hi[1], nxr = nxl + R.ex - B.hi[0];
+  const int dy = B.hi[1] - B.lo[1], dz = B.hi[2] - B.lo[2];
+  const int nz = (nzl + R.ez - B.hi[2]) * R.ex * R.ey, ny = rows_y * R.ex * dz;
+  if (j < nz) {
+    const int pz = j / (R.ex * R.ey), r = j - pz * R.ex * R.ey;
+    z = pz < nzl ? pz : B.hi[2] + pz - nzl;
+    y = r / R.ex;
+    x = r - y * R.ex;
+  } else if (j < nz + ny) {
+    j -= nz;
+    const int rz = j / (rows_y * R.ex), r = j - rz * rows_y * R.ex;
+    const int py = r / R.ex;
+    z = B.lo[2] + rz;
+    y = py < nyl ? py : B.hi[1] + py - nyl;
+    x = r - py * R.ex;
+  } else {
+    j -= nz + ny;
+    const int rz = j / (nxr * dy), r = j - rz * nxr * dy;
+    const int row = r / nxr, px = r - row * nxr;
+    z = B.lo[2] + rz;
+    y = B.lo[1] + row;
+    x = px < nxl ? px : B.hi[0] + px - nxl;
+    (void)dz;
+  }
+}
+
+// One thread per shell node of a table region (blocks of kBlock consecutive shell nodes of one
+// region; BlockDesc.start is the first shell index).  A node's own upper couplings are streamed;
+// a lower coupling A(i, i+s) is the neighbour's upper coupling at 26 - s, from the table when the
+// neighbour is deep, else from its record; neighbour values come through the cache.
+template <StencilOp OP, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_stencil_shell(LevelView L, const BlockDesc* __restrict__ blocks,
+                                                          const DeepBox* __restrict__ boxes,
+                                                          const double* __restrict__ coef,
+                                                          const double* __restrict__ table,
+                                                          const int64_t* __restrict__ xoff,
+                                                          const double* __restrict__ xcoef, OpP<double> p,
+                                                          double* __restrict__ partials) {
+  const BlockDesc bd = blocks[blockIdx.x];
+  const RegionGeo R = L.regs[bd.region];
+  const DeepBox B = boxes[bd.region];
+  const int j = bd.start + (int)threadIdx.x;
+  const int nshell = R.n - (B.hi[0] - B.lo[0]) * (B.hi[1] - B.lo[1]) * (B.hi[2] - B.lo[2]);
+  double contrib = 0.0;
+  if (j < nshell) {
+    int x, y, z;
+    shell_node(R, B, j, x, y, z);
+    const int sy = R.ex, sz = R.ex * R.ey;
+    const int li = z * sz + y * sy + x;
+    const int64_t gi = R.off + li;
+    const double* __restrict__ xr = p.x + R.off;
+    const double* __restrict__ tab = table + bd.region * kSymPts;
+    const int64_t x0 = xoff[bd.region];
+    auto inbox = [&](int dx, int dy, int dz) {
+      return (unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
+             (unsigned)(z + dz) < (unsigned)R.ez;
+    };
+    auto deep = [&](int xx, int yy, int zz) {
+      return xx >= B.lo[0] && xx < B.hi[0] && yy >= B.lo[1] && yy < B.hi[1] && zz >= B.lo[2] && zz < B.hi[2];
+    };
+    // packed index of an x-face node (a shell node of a deep row), or -1
+    const int nxr = B.lo[0] + R.ex - B.hi[0];
+    auto xface = [&](int xx, int yy, int zz) -> int64_t {
+      if (yy < B.lo[1] || yy >= B.hi[1] || zz < B.lo[2] || zz >= B.hi[2]) return -1;
+      const int px = xx < B.lo[0] ? xx : (xx >= B.hi[0] ? B.lo[0] + xx - B.hi[0] : -1);
+      if (px < 0) return -1;
+      return x0 + ((int64_t)(zz - B.lo[2]) * (B.hi[1] - B.lo[1]) + (yy - B.lo[1])) * nxr + px;
+    };
+    // upper coupling k of a non-deep node (regional index ln, coordinates xx, yy, zz)
+    auto upper = [&](int k, int ln, int xx, int yy, int zz) {
+      const int64_t q = xface(xx, yy, zz);
+      return q >= 0 ? xcoef[coef_index(q, k, kSymPts)] : coef[coef_index(R.off + ln, k, kSymPts)];
+    };
+    double acc = 0.0, ctr = 0.0;
+#pragma unroll
+    for (int s = 13; s < 27; ++s) {
+      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+      const double c = upper(s - 13, li, x, y, z);
+      const double v = inbox(dx, dy, dz) ? xr[li + dx + dy * sy + dz * sz] : 0.0;
+      if (s == 13) ctr = c;
+      acc = fma(c, v, acc);  // each product added with one rounding, as the tiled kernels do
+    }
+#pragma unroll
+    for (int s = 0; s < 13; ++s) {
+      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+      double c = 0.0, v = 0.0;
+      if (inbox(dx, dy, dz)) {
+        const int ln = li + dx + dy * sy + dz * sz;
+        c = deep(x + dx, y + dy, z + dz) ? tab[13 - s] : upper(13 - s, ln, x + dx, y + dy, z + dz);
+        v = xr[ln];
+      }
+      acc = fma(c, v, acc);
+    }
+    const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || z == 0 || z == R.ez - 1;
+    if (edge && is_shared(L, R, x, y, z)) p.out[gi] = acc;  // finished by k_iface
+    else contrib += finish<OP, DOT, double, true>(p, gi, acc, 1, xr[li], ctr);
+  }
+  if constexpr (DOT || OP == StencilOp::CgQ) {
+    const double s = block_sum(contrib);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
 // ----------------------------------------------------------- interface groups
 template <int NDOF, class V, StencilOp OP, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gptr, const int* __restrict__ gcopy,
@@ -449,6 +679,7 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   const bool tiled = NPTS == 27 && NDOF == 1 && L.use_tiles;
   const int ntiles = (int)L.tiles.size();
   const int grid3 = (L.tile_grid > 0 && L.tile_grid < ntiles) ? L.tile_grid : ntiles;
+  int64_t nparts = grid3;  // partial sums written by the tiled launches
   if (a.ev0) RMG_HIP(hipEventRecord(a.ev0, st));
   if constexpr (NPTS == 27 && NDOF == 1) {
     if (tiled) {
@@ -463,26 +694,45 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
           table_ok = static_cast<const int*>(L.sym_table_ok.p);
         }
       }
+      bool split = false;
+      if constexpr (std::is_same<V, double>::value && std::is_same<C, double>::value) {
+        if (table && sym && L.tile_threads == kTileThreadsF64) {
+          // region-table split: deep tiles, shell blocks, then the other regions' tiles, each with
+          // its own run of partial sums
+          const int64_t nd = (int64_t)L.deep_tiles.size(), ns = (int64_t)L.shell_blocks.size();
+          const int64_t no = (int64_t)L.other_tiles.size();
+          RMG_REQUIRE(L.table_served.size() == (size_t)L.nreg && (nd > 0 || ns > 0), RMG_ERR_ARG,
+                      "internal: region table without its split");
+          if (nd > 0)
+            RMG_LAUNCH((k_stencil_deep<kDeepThreads, OP, DOT>), dim3(nd), dim3(kDeepThreads), 0, st, v,
+                       L.d_deep_tiles.as<Tile3>(), table, p, a.partials);
+          if (ns > 0)
+            RMG_LAUNCH((k_stencil_shell<OP, DOT>), dim3(ns), dim3(kBlock), 0, st, v, L.d_shell_blocks.as<BlockDesc>(),
+                       L.d_deep_box.as<DeepBox>(), sym, table, L.d_xface_off.as<int64_t>(), L.xface_coef.as<double>(),
+                       p, a.partials ? a.partials + nd : nullptr);
+          if (no > 0)
+            RMG_LAUNCH((k_stencil3d<kTileThreadsF64, V, C, OP, DOT, true>), dim3(no), dim3(kTileThreadsF64), 0, st,
+                       v, L.d_other_tiles.as<Tile3>(), (int)no, sym, centre, nullptr, nullptr, p,
+                       a.partials ? a.partials + nd + ns : nullptr);
+          nparts = nd + ns + no;
+          split = true;
+        }
+      }
+      (void)table_ok;
       auto launch3d = [&](auto nt) {
         constexpr int NT = decltype(nt)::value;
         if (sym) {
           if constexpr (std::is_same<V, C>::value) {
-            if constexpr (NT == kTileThreadsF64 && std::is_same<V, double>::value) {
-              if (table) {
-                hipLaunchKernelGGL((k_stencil3d<NT, V, C, OP, DOT, true, true>), dim3(grid3), dim3(NT), 0, st, v,
-                                   L.d_tiles.as<Tile3>(), ntiles, sym, centre, table, table_ok, p, a.partials);
-                return;
-              }
-            }
-            hipLaunchKernelGGL((k_stencil3d<NT, V, C, OP, DOT, true>), dim3(grid3), dim3(NT), 0, st, v,
+            RMG_LAUNCH((k_stencil3d<NT, V, C, OP, DOT, true>), dim3(grid3), dim3(NT), 0, st, v,
                                L.d_tiles.as<Tile3>(), ntiles, sym, centre, nullptr, nullptr, p, a.partials);
           }
         } else {
-          hipLaunchKernelGGL((k_stencil3d<NT, V, C, OP, DOT, false>), dim3(grid3), dim3(NT), 0, st, v,
+          RMG_LAUNCH((k_stencil3d<NT, V, C, OP, DOT, false>), dim3(grid3), dim3(NT), 0, st, v,
                              L.d_tiles.as<Tile3>(), ntiles, coef, centre, nullptr, nullptr, p, a.partials);
         }
       };
-      if constexpr (sizeof(V) == 8) {
+      if (split) {
+      } else if constexpr (sizeof(V) == 8) {
         if (L.tile_threads == kTileThreadsF64) launch3d(std::integral_constant<int, kTileThreadsF64>());
         else launch3d(std::integral_constant<int, kTileThreadsF32>());
       } else {
@@ -496,12 +746,12 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
     auto node = [&](const LevelView& vk, int nblocks, double* part) {
       if constexpr (NPTS == 27) {
         if (symc) {
-          hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT, true>), dim3(nblocks), dim3(kBlock), 0, st, vk,
+          RMG_LAUNCH((k_stencil<NPTS, NDOF, V, C, OP, DOT, true>), dim3(nblocks), dim3(kBlock), 0, st, vk,
                              symc, centre, p, part);
           return;
         }
       }
-      hipLaunchKernelGGL((k_stencil<NPTS, NDOF, V, C, OP, DOT, false>), dim3(nblocks), dim3(kBlock), 0, st, vk, coef,
+      RMG_LAUNCH((k_stencil<NPTS, NDOF, V, C, OP, DOT, false>), dim3(nblocks), dim3(kBlock), 0, st, vk, coef,
                          centre, p, part);
     };
     if (L.per_region) {
@@ -520,11 +770,11 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   }
   LAUNCH_CHECK();
   if (a.ev1) RMG_HIP(hipEventRecord(a.ev1, st));
-  const int64_t nb = tiled ? (int64_t)grid3 : (int64_t)L.blocks.size();
+  const int64_t nb = tiled ? nparts : (int64_t)L.blocks.size();
   int64_t ngb = 0;
   if (L.ngroups > 0) {
     ngb = cdiv(L.ngroups, kBlock);
-    hipLaunchKernelGGL((k_iface<NDOF, V, OP, DOT>), dim3(ngb), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
+    RMG_LAUNCH((k_iface<NDOF, V, OP, DOT>), dim3(ngb), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
                        L.d_gcopy.as<int>(), L.ngroups, p, a.partials ? a.partials + nb : nullptr);
     LAUNCH_CHECK();
   }

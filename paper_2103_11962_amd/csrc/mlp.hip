@@ -376,7 +376,7 @@ __global__ void k_adam(int n, float* __restrict__ th, const float* __restrict__ 
 // --------------------------------------------------------------- launchers
 void mlp_forward(int64_t n, const float* X, const float* theta, float* Z, float* A1, float* A2, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_mlp_forward, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, X, theta, Z, A1, A2);
+  RMG_LAUNCH(k_mlp_forward, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, X, theta, Z, A1, A2);
   LAUNCH_CHECK();
 }
 
@@ -387,16 +387,16 @@ int64_t mlp_loss(int64_t n, const float* Z, const float* E, const float* X, int 
   upload_tables();
   const int64_t nb = mlp_loss_partials(n);
   if (kind == 1)
-    hipLaunchKernelGGL(k_mlp_loss<true>, dim3(nb), dim3(kBlock), 0, st, n, Z, E, X, dZ, partials);
+    RMG_LAUNCH(k_mlp_loss<true>, dim3(nb), dim3(kBlock), 0, st, n, Z, E, X, dZ, partials);
   else
-    hipLaunchKernelGGL(k_mlp_loss<false>, dim3(nb), dim3(kBlock), 0, st, n, Z, E, X, dZ, partials);
+    RMG_LAUNCH(k_mlp_loss<false>, dim3(nb), dim3(kBlock), 0, st, n, Z, E, X, dZ, partials);
   LAUNCH_CHECK();
   return nb;
 }
 
 void mlp_backact(int64_t n, const float* dZ, const float* A1, const float* A2, const float* theta, float* D1,
                  float* D2, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_backact, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, dZ, A1, A2, theta, D1, D2);
+  RMG_LAUNCH(k_mlp_backact, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, dZ, A1, A2, theta, D1, D2);
   LAUNCH_CHECK();
 }
 
@@ -410,25 +410,25 @@ void mlp_weight_grads(int64_t n, const float* X, const float* A1, const float* A
   const int ofs_b1 = kMlpH * kMlpIn, ofs_W2 = ofs_b1 + kMlpH, ofs_b2 = ofs_W2 + kMlpH * kMlpH,
             ofs_W3 = ofs_b2 + kMlpH, ofs_b3 = ofs_W3 + kMlpOut * kMlpH;
   auto reduce = [&](int R, int C, int wofs, int bofs) {
-    hipLaunchKernelGGL(k_mlp_wgrad_reduce, dim3(cdiv(R * (C + 1), 64)), dim3(kBlock), 0, st, R, C, nblk, part, grad,
+    RMG_LAUNCH(k_mlp_wgrad_reduce, dim3(cdiv(R * (C + 1), 64)), dim3(kBlock), 0, st, R, C, nblk, part, grad,
                        wofs, bofs);
     LAUNCH_CHECK();
   };
-  hipLaunchKernelGGL((k_mlp_wgrad<kMlpOut, kMlpH, 13, 4>), dim3(nblk), dim3(256), 0, st, n, dZ, A2, 1, per_block,
+  RMG_LAUNCH((k_mlp_wgrad<kMlpOut, kMlpH, 13, 4>), dim3(nblk), dim3(256), 0, st, n, dZ, A2, 1, per_block,
                      part);
   LAUNCH_CHECK();
   reduce(kMlpOut, kMlpH, ofs_W3, ofs_b3);
-  hipLaunchKernelGGL((k_mlp_wgrad<kMlpH, kMlpH, 4, 4>), dim3(nblk), dim3(256), 0, st, n, D2, A1, 1, per_block, part);
+  RMG_LAUNCH((k_mlp_wgrad<kMlpH, kMlpH, 4, 4>), dim3(nblk), dim3(256), 0, st, n, D2, A1, 1, per_block, part);
   LAUNCH_CHECK();
   reduce(kMlpH, kMlpH, ofs_W2, ofs_b2);
-  hipLaunchKernelGGL((k_mlp_wgrad<kMlpH, kMlpIn, 4, 2>), dim3(nblk), dim3(256), 0, st, n, D1, X, 0, per_block, part);
+  RMG_LAUNCH((k_mlp_wgrad<kMlpH, kMlpIn, 4, 2>), dim3(nblk), dim3(256), 0, st, n, D1, X, 0, per_block, part);
   LAUNCH_CHECK();
   reduce(kMlpH, kMlpIn, 0, ofs_b1);
 }
 
 void mlp_adam(float* theta, const float* grad, float* m, float* v, int t, double lr, hipStream_t st) {
   const float c1 = (float)(1.0 - std::pow(0.9, t)), c2 = (float)(1.0 - std::pow(0.999, t));
-  hipLaunchKernelGGL(k_adam, dim3(cdiv(kMlpParams, kBlock)), dim3(kBlock), 0, st, kMlpParams, theta, grad, m, v,
+  RMG_LAUNCH(k_adam, dim3(cdiv(kMlpParams, kBlock)), dim3(kBlock), 0, st, kMlpParams, theta, grad, m, v,
                      (float)lr, c1, c2);
   LAUNCH_CHECK();
 }
@@ -487,13 +487,13 @@ __global__ __launch_bounds__(kBlock) void k_cell_targets(LevelView L, const int6
 
 void cell_features(const Level& L, const int64_t* cell_off, int64_t ncell, const float* logc, float* X,
                    hipStream_t st) {
-  hipLaunchKernelGGL(k_cell_features, dim3(cdiv(ncell, kBlock)), dim3(kBlock), 0, st, L.view(), cell_off, ncell, logc,
+  RMG_LAUNCH(k_cell_features, dim3(cdiv(ncell, kBlock)), dim3(kBlock), 0, st, L.view(), cell_off, ncell, logc,
                      X);
   LAUNCH_CHECK();
 }
 
 void cell_targets(const Level& L, const int64_t* cell_off, int64_t ncell, const double* e, float* E, hipStream_t st) {
-  hipLaunchKernelGGL(k_cell_targets, dim3(cdiv(ncell, kBlock)), dim3(kBlock), 0, st, L.view(), cell_off, ncell, e, E);
+  RMG_LAUNCH(k_cell_targets, dim3(cdiv(ncell, kBlock)), dim3(kBlock), 0, st, L.view(), cell_off, ncell, e, E);
   LAUNCH_CHECK();
 }
 
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_learned_weights(LevelView F, LevelVi
 
 void learned_weights(const Level& F, const Level& C, const float* Z, const int* cellrow, double* pw, hipStream_t st) {
   upload_tables();
-  hipLaunchKernelGGL(k_learned_weights, dim3(F.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), Z, cellrow,
+  RMG_LAUNCH(k_learned_weights, dim3(F.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), Z, cellrow,
                      pw);
   LAUNCH_CHECK();
 }
@@ -645,10 +645,10 @@ __global__ __launch_bounds__(kBlock) void k_check_weight_copies(LevelView F, Lev
 }
 
 void check_weights(const Level& F, const Level& C, const double* pw, int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_check_weights, dim3(F.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), pw, flag);
+  RMG_LAUNCH(k_check_weights, dim3(F.blocks.size()), dim3(kBlock), 0, st, F.view(), C.view(), pw, flag);
   LAUNCH_CHECK();
   if (F.ngroups > 0) {
-    hipLaunchKernelGGL(k_check_weight_copies, dim3(cdiv(F.ngroups, kBlock)), dim3(kBlock), 0, st, F.view(), C.view(),
+    RMG_LAUNCH(k_check_weight_copies, dim3(cdiv(F.ngroups, kBlock)), dim3(kBlock), 0, st, F.view(), C.view(),
                        F.d_gptr.as<int64_t>(), F.d_gcopy.as<int>(), F.d_gcomp.as<int>(), F.ngroups, pw, flag);
     LAUNCH_CHECK();
   }
@@ -662,7 +662,7 @@ __global__ void k_log(int64_t n, const double* __restrict__ in, float* __restric
 
 void launch_log(int64_t n, const double* in, float* out, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_log, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out);
+  RMG_LAUNCH(k_log, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, in, out);
   LAUNCH_CHECK();
 }
 

@@ -67,6 +67,16 @@ static bool shared_node(const Level& L, const RegionGeo& R, int x, int y, int z)
          (y == R.ey - 1 && gy != L.comp[1] - 1) || (z == 0 && gz != 0) || (z == R.ez - 1 && gz != L.comp[2] - 1);
 }
 
+template <class T>
+static void upload(DBuf& d, const std::vector<T>& v) {
+  if (v.empty()) {
+    d.release();
+    return;
+  }
+  d.alloc(sizeof(T) * v.size());
+  RMG_HIP(hipMemcpy(d.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+}
+
 // 2.5D tiles of a 3D level: L.tile_threads-node tiles of whole (or that many nodes of) x-rows, `depth` planes deep,
 // ordered largest first so a persistent launch hands out the costly tiles early.
 void make_tiles(Level& L, int depth) {
@@ -97,6 +107,82 @@ void make_tiles(Level& L, int depth) {
     L.d_tiles.alloc(sizeof(Tile3) * L.tiles.size());
     RMG_HIP(hipMemcpy(L.d_tiles.p, L.tiles.data(), sizeof(Tile3) * L.tiles.size(), hipMemcpyHostToDevice));
   }
+  if (!L.table_served.empty()) {  // a split exists: the regions it does not serve run these tiles
+    L.other_tiles.clear();
+    for (const Tile3& T : L.tiles)
+      if (!L.table_served[T.region]) L.other_tiles.push_back(T);
+    upload(L.d_other_tiles, L.other_tiles);
+  }
+}
+
+void clear_split(Level& L) {
+  L.table_served.clear();
+  L.deep_tiles.clear();
+  L.shell_blocks.clear();
+  L.other_tiles.clear();
+  L.d_deep_tiles.release();
+  L.d_shell_blocks.release();
+  L.d_other_tiles.release();
+  L.xface_off.clear();
+  L.d_xface_off.release();
+  L.xface_coef.release();
+  L.deep_box.clear();
+  L.d_deep_box.release();
+}
+
+// Served regions (at least 5 nodes a side): the deep box in tiles of whole deep rows (kDeepThreads
+// nodes at most, rows shared out evenly) and kDeepPlanes-or-fewer planes (planes shared out evenly),
+// largest first; shell nodes in blocks of kBlock.
+void make_split(Level& L, const std::vector<int>& served, const std::vector<DeepBox>& boxes) {
+  std::vector<int> keep = served;
+  std::vector<DeepBox> box = boxes;
+  clear_split(L);
+  L.table_served = keep;
+  L.deep_box = box;
+  L.xface_off.assign(L.nreg + 1, 0);
+  for (int k = 0; k < L.nreg; ++k) {
+    if (!keep[k]) continue;
+    const RegionGeo& R = L.regs[k];
+    const DeepBox& B = box[k];
+    const int e[3] = {R.ex, R.ey, R.ez};
+    for (int a = 0; a < 3; ++a)
+      RMG_REQUIRE(B.lo[a] >= 1 && B.lo[a] <= 2 && B.hi[a] <= e[a] - 1 && B.hi[a] >= e[a] - 2 && B.hi[a] > B.lo[a],
+                  RMG_ERR_ARG, "internal: deep box outside one-to-two node faces");
+    const int dx = B.hi[0] - B.lo[0], dy = B.hi[1] - B.lo[1], dz = B.hi[2] - B.lo[2];
+    RMG_REQUIRE(dx <= kDeepThreads, RMG_ERR_ARG, "internal: deep row wider than a deep tile");
+    const int tymax = std::min(dy, kDeepThreads / dx);
+    const int nty = (dy + tymax - 1) / tymax;
+    const int ntz = (dz + kDeepPlanes - 1) / kDeepPlanes;
+    for (int iz = 0, z0 = B.lo[2]; iz < ntz; ++iz) {
+      const int nz = dz / ntz + (iz < dz % ntz ? 1 : 0);
+      for (int j = 0, y0 = B.lo[1]; j < nty; ++j) {
+        const int ty = dy / nty + (j < dy % nty ? 1 : 0);
+        L.deep_tiles.push_back(Tile3{k, B.lo[0], y0, z0, dx, ty, nz, 0});
+        y0 += ty;
+      }
+      z0 += nz;
+    }
+    const int nshell = R.n - dx * dy * dz;
+    for (int start = 0; start < nshell; start += kBlock) L.shell_blocks.push_back(BlockDesc{k, start});
+    L.xface_off[k + 1] = (int64_t)(R.ex - dx) * dy * dz;  // shell nodes of the deep rows
+  }
+  for (int k = 0; k < L.nreg; ++k) L.xface_off[k + 1] += L.xface_off[k];
+  upload(L.d_xface_off, L.xface_off);
+  upload(L.d_deep_box, L.deep_box);
+  std::stable_sort(L.deep_tiles.begin(), L.deep_tiles.end(), [](const Tile3& a, const Tile3& b) {
+    return (int64_t)a.tx * a.ty * a.nz > (int64_t)b.tx * b.ty * b.nz;
+  });
+  for (const Tile3& T : L.deep_tiles)
+    RMG_REQUIRE(T.tx * T.ty <= kDeepThreads && (T.tx + 2) * (T.ty + 2) <= tile_plane_cap(kDeepThreads) &&
+                    T.x0 >= box[T.region].lo[0] && T.y0 >= box[T.region].lo[1] && T.z0 >= box[T.region].lo[2] &&
+                    T.x0 + T.tx <= box[T.region].hi[0] && T.y0 + T.ty <= box[T.region].hi[1] &&
+                    T.z0 + T.nz <= box[T.region].hi[2],
+                RMG_ERR_ARG, "internal: deep tile outside the deep box");
+  for (const Tile3& T : L.tiles)
+    if (!keep[T.region]) L.other_tiles.push_back(T);
+  upload(L.d_deep_tiles, L.deep_tiles);
+  upload(L.d_shell_blocks, L.shell_blocks);
+  upload(L.d_other_tiles, L.other_tiles);
 }
 
 // Offsets, block table and interface groups of a level whose regs/comp are set.

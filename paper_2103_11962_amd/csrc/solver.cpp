@@ -40,7 +40,10 @@ KernelTimer::~KernelTimer() {
 }
 
 static int64_t partial_capacity(const Level& L) {
-  return (int64_t)std::max(L.blocks.size(), L.tiles.size()) + (L.ngroups + kBlock - 1) / kBlock + 16;
+  // node blocks, 2.5D tiles or the region-table split (deep tiles, shell blocks, other regions'
+  // tiles), then the interface groups
+  const int64_t split = (int64_t)(L.deep_tiles.size() + L.shell_blocks.size() + L.tiles.size());
+  return std::max({(int64_t)L.blocks.size(), (int64_t)L.tiles.size(), split}) + (L.ngroups + kBlock - 1) / kBlock + 16;
 }
 
 static double* scal(rmg_handle* h) { return h->scalars.as<double>(); }
@@ -226,7 +229,9 @@ static void configure_level(rmg_handle* h, Level& L, bool with_b, bool sym) {
   const size_t tiles21 = L.tiles.size();
   // FP64 tiles run one block per CU: on a level large enough for tiles, 41-plane tiles read two
   // halo planes per 41 instead of per 21, kept while they still give every CU four or more.
-  if (L.dim == 3 && fp64 && tiles21 >= kAutoTileMin) {
+  if (o.tile_planes == 41 && L.dim == 3) {
+    make_tiles(L, 41);
+  } else if (o.tile_planes == 0 && L.dim == 3 && fp64 && tiles21 >= kAutoTileMin) {
     make_tiles(L, 41);
     if (L.tiles.size() < kDeepTileMin) make_tiles(L, 21);
   }
@@ -247,6 +252,7 @@ static void configure_level(rmg_handle* h, Level& L, bool with_b, bool sym) {
     L.coef_sym.release();
     L.sym_table.release();
     L.sym_table_ok.release();
+    clear_split(L);
   }
 }
 
@@ -320,6 +326,7 @@ static int build_levels(rmg_handle* h, bool stored) {
         L.rw.release();
       }
     }
+    L.rap_separable = o.galerkin_generic == 0;
     launch_rap(L, *C, st);
     // the V-cycle's copy of this level's operator, made after the Galerkin product used it
     if (lowp) {
@@ -497,35 +504,40 @@ void smooth_iterate(rmg_handle* h, int level, const double* b, double* u, double
 // numbers, training errors 32 + sample).
 constexpr int kRhoStream = 63;
 
-double convergence_factor(rmg_handle* h, int cycles) {
+double convergence_factor(rmg_handle* h, int cycles, double* work) {
   Level& L = *h->levels[0];
   hipStream_t st = h->stream;
   const int64_t n = L.ndofs();
-  DBuf zero, x, r, z;
-  zero.alloc(sizeof(double) * n);
-  x.alloc(sizeof(double) * n);
-  r.alloc(sizeof(double) * n);
-  z.alloc(sizeof(double) * n);
-  launch_zero(n, zero.as<double>(), st);
-  launch_start_vector(L, kRhoStream, h->opt.seed, x.as<double>(), st);
+  DBuf own;
+  if (!work) {
+    own.alloc(sizeof(double) * 4 * (size_t)n);
+    work = own.as<double>();
+  }
+  // work: the zero right-hand side, the iterate, its residual and the correction, n each
+  double* zero = work;
+  double* x = work + n;
+  double* r = work + 2 * n;
+  double* z = work + 3 * n;
+  launch_zero(n, zero, st);
+  launch_start_vector(L, kRhoStream, h->opt.seed, x, st);
   auto residual = [&] {
     StencilArgs a;
     a.op = StencilOp::Residual;
-    a.x = x.p;
-    a.out = r.p;
-    a.b = zero.p;
+    a.x = x;
+    a.out = r;
+    a.b = zero;
     launch_stencil_op(L, a, st);
   };
   residual();
-  dot(h, L, r.as<double>(), r.as<double>(), kTmp);
+  dot(h, L, r, r, kTmp);
   read_scalars(h);
   const double r0 = std::sqrt(h->host_scalars[kTmp]);
   for (int c = 0; c < cycles; ++c) {
-    apply_preconditioner(h, r.as<double>(), z.as<double>());
-    launch_add(n, z.as<double>(), x.as<double>(), st);
+    apply_preconditioner(h, r, z);
+    launch_add(n, z, x, st);
     residual();
   }
-  dot(h, L, r.as<double>(), r.as<double>(), kTmp);
+  dot(h, L, r, r, kTmp);
   read_scalars(h);
   const double rk = std::sqrt(h->host_scalars[kTmp]);
   if (!(r0 > 0.0)) return 0.0;
@@ -837,6 +849,19 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
   int it = 0;
   double rel = 1.0;
   bool converged = false;
+  // out = b - A x and its relative norm (true_rel)
+  double true_rel = -1.0;
+  auto true_residual = [&](double* out) {
+    StencilArgs a;
+    a.op = StencilOp::Residual;
+    a.x = x;
+    a.out = out;
+    a.b = b;
+    launch_stencil_op(L, a, st);
+    dot(h, L, out, out, kTmp);
+    read_scalars(h);
+    true_rel = std::sqrt(h->host_scalars[kTmp]) / bnorm;
+  };
   push_hist(1.0);
   if (bnorm == 0.0) {
     launch_zero(n, x, st);
@@ -875,8 +900,13 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
       rel = std::sqrt(rr) / bnorm;
       push_hist(rel);
       if (rel <= rtol) {
-        converged = true;
-        break;
+        // the tolerance is on the system's relative residual: the recursively updated r is
+        // accepted only if b - A x agrees, else CG goes on from the true residual
+        true_residual(r);
+        if (true_rel <= rtol) {
+          converged = true;
+          break;
+        }
       }
       if (it >= maxit) break;
       if (graphs) RMG_HIP(hipGraphLaunch(h->graph_b, st));
@@ -884,17 +914,8 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
     }
   }
   RMG_HIP(hipEventRecord(e1, st));
-  // true residual
-  {
-    StencilArgs a;
-    a.op = StencilOp::Residual;
-    a.x = x;
-    a.out = q;
-    a.b = b;
-    launch_stencil_op(L, a, st);
-  }
-  dot(h, L, q, q, kTmp);
-  read_scalars(h);
+  RMG_HIP(hipEventSynchronize(e1));
+  if (!converged && bnorm > 0.0) true_residual(q);  // reported true residual of the last iterate
   if (h->profiling)
     for (auto& t : h->timers) t.harvest();
   level_times_report(h, info);
@@ -910,7 +931,7 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
     info->iterations = it;
     info->converged = converged ? 1 : 0;
     info->relres = rel;
-    info->true_relres = bnorm > 0.0 ? std::sqrt(h->host_scalars[kTmp]) / bnorm : 0.0;
+    info->true_relres = bnorm > 0.0 ? true_rel : 0.0;
     info->solve_ms = ms;
     info->history_len = hist_len;
     info->setup_ms = h->setup_ms;

@@ -40,7 +40,7 @@ SYMBOLS = (
     "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr", "rmg_mg_solve",
     "rmg_mlp_set_loss", "rmg_set_region_kinds", "rmg_hybrid_level_info", "rmg_hybrid_aggregates",
     "rmg_hybrid_composite_ids", "rmg_hybrid_matrix", "rmg_amg_levels", "rmg_amg_level_info", "rmg_amg_matrix",
-    "rmg_level_table_regions",
+    "rmg_level_table_regions", "rmg_level_tiles", "rmg_kernel_launches"
 )
 SMOOTHER_CHEBYSHEV, SMOOTHER_JACOBI, SMOOTHER_GS, SMOOTHER_GS_FB, SMOOTHER_SYMGS = 0, 1, 2, 3, 4
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
@@ -73,6 +73,8 @@ class Options(ctypes.Structure):
         ("coarse_amg", ctypes.c_int),
         ("amg_coarse_size", ctypes.c_int),
         ("region_table", ctypes.c_int),
+        ("tile_planes", ctypes.c_int),
+        ("galerkin_generic", ctypes.c_int),
     ]
 
 
@@ -186,6 +188,8 @@ def load():
         "rmg_level_kernel": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "rmg_set_composite_csr": (I, [H, I, ctypes.c_int64, P, P, P, I]),
         "rmg_level_table_regions": (I, [H, I, ctypes.POINTER(I)]),
+        "rmg_level_tiles": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "rmg_kernel_launches": (I, [ctypes.POINTER(ctypes.c_int64)]),
         "rmg_mg_solve": (I, [H, P, P, I, D, I, ctypes.POINTER(SolveInfo)]),
         "rmg_mlp_set_loss": (I, [H, I]),
         "rmg_set_region_kinds": (I, [H, P]),
@@ -223,6 +227,13 @@ def _ptr(t):
     if not t.is_contiguous() or t.dtype != torch.float64:
         raise ValueError("device vectors must be contiguous float64 tensors")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def kernel_launches() -> int:
+    """Kernel launches the library has issued in this process so far."""
+    n = ctypes.c_int64()
+    _check(load().rmg_kernel_launches(ctypes.byref(n)))
+    return n.value
 
 
 def default_options(**kw) -> Options:
@@ -440,6 +451,11 @@ class Handle:
         k, c, cl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(load().rmg_level_kernel(self._h, level, ctypes.byref(k), ctypes.byref(c), ctypes.byref(cl)))
         return {"kernel": k.value, "coefs": c.value, "coefs_lo": cl.value}
+
+    def level_tiles(self, level):
+        n, t, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().rmg_level_tiles(self._h, level, ctypes.byref(n), ctypes.byref(t), ctypes.byref(p)))
+        return {"ntiles": n.value, "threads": t.value, "planes": p.value}
 
     def level_table_regions(self, level):
         n = ctypes.c_int()

@@ -125,6 +125,7 @@ def workload(name: str, seed: int = 0) -> Workload:
 
     ``c1``  2D five-point Poisson, 2x2 regions of 82^2 nodes, 3 levels, Chebyshev degree 2.
     ``c2``  3D Q1 Laplacian, 4x4x4 regions of 82^3, 4 levels, degree 3.
+    ``c2_octant``  2x2x2 of c2's regions (82^3 each, composite 163^3) with c2's mesh width and levels.
     ``c3``  3D Q1 elasticity, 3x3x3 regions of 55^3, E per region lognormal, nu = 0.3.
     ``c4``  3D Q1 Laplacian on 8x8x4 regions with slab extents from {28,55,82,109}.
     ``c5``  3D Q1 diffusion with jump coefficients, 4x4x4 regions of 82^3.
@@ -144,6 +145,9 @@ def workload(name: str, seed: int = 0) -> Workload:
         return Workload(name, 2, 1, o, e, full(2), 3, 2, "fd5", seed=seed)
     if name == "c2":
         o, e = _uniform_layout(3, 4, 82)
+        return Workload(name, 3, 1, o, e, full(3), 4, 3, "laplace", h=1.0 / 324, seed=seed)
+    if name == "c2_octant":  # 2x2x2 of c2's 64 regions (composite 163^3), c2's mesh width and levels
+        o, e = _uniform_layout(3, 2, 82)
         return Workload(name, 3, 1, o, e, full(3), 4, 3, "laplace", h=1.0 / 324, seed=seed)
     if name == "c2_small":
         o, e = _uniform_layout(3, 2, 10)
@@ -193,7 +197,7 @@ def workload(name: str, seed: int = 0) -> Workload:
     raise KeyError(name)
 
 
-WORKLOADS = ("c1", "c1_small", "c2", "c2_small", "c2_mid", "c3", "c3_small",
+WORKLOADS = ("c1", "c1_small", "c2", "c2_octant", "c2_small", "c2_mid", "c3", "c3_small",
              "c4", "c4_small", "c5", "c5_small", "table1_rect", "uneven2d_small", "uneven3d_small",
              "uneven3e_small", "uneven_c4_small", "uneven_tiny3d", "uneven_tiny2d")
 

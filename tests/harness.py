@@ -75,3 +75,39 @@ def stencil_soa(coef, dim, ndof=1):
 def vshape(lay):
     """numpy shape of a composite vector of the layout."""
     return lay.shape + ((lay.ndof,) if lay.ndof > 1 else ())
+
+
+def assert_close(got, ref, tol, floor=0.1, what=""):
+    """Element-wise parity: |got_i - ref_i| <= tol * (|ref_i| + floor * max_j |ref_j|) for every i.
+
+    ``tol`` is the relative tolerance of the comparison.  The absolute part admits the rounding of
+    entries that are small only through cancellation: every entry of a stencil product, a transfer,
+    a smoother or a cycle is a sum of terms as large as the largest entries, so both sides round it
+    at that scale, not at its own.  With the default floor 0.1 and the FP64 tolerances used here
+    (1e-12, 1e-13) that is 1e-13 (1e-14) of the largest entry, about 450 (45) units in the last
+    place of it: the rounding of the few hundred operations such a chain performs (the largest
+    deviation seen on MI355X is 4e-14 of the largest entry).  A single entry off by more than that —
+    an interface corner, a tile edge — fails, however long the vector; a norm-wise test would let
+    one entry deviate by sqrt(n) times as much.
+    """
+    g = np.asarray(got, dtype=np.float64).ravel()
+    r = np.asarray(ref, dtype=np.float64).ravel()
+    assert g.shape == r.shape, (what, g.shape, r.shape)
+    assert np.all(np.isfinite(g)), (what, "non-finite entries")
+    scale = float(np.max(np.abs(r))) if r.size else 0.0
+    bound = tol * (np.abs(r) + floor * scale)
+    err = np.abs(g - r)
+    bad = err > bound
+    if np.any(bad):
+        i = int(np.argmax(err - bound))
+        raise AssertionError(
+            f"{what}: {int(bad.sum())} of {g.size} entries outside tol {tol:g} (floor {floor:g}); "
+            f"worst index {i}: got {g[i]!r}, ref {r[i]!r}, |err| {err[i]:.3e}, bound {bound[i]:.3e}, "
+            f"max|ref| {scale:.3e}, max|err|/max|ref| {float(err.max()) / max(scale, 1e-300):.3e}")
+
+
+def max_rel_err(got, ref):
+    """max_i |got_i - ref_i| / max_i |ref_i| (reported beside element-wise checks)."""
+    g = np.asarray(got, dtype=np.float64).ravel()
+    r = np.asarray(ref, dtype=np.float64).ravel()
+    return float(np.max(np.abs(g - r)) / max(float(np.max(np.abs(r))), 1e-300)) if r.size else 0.0

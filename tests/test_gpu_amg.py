@@ -18,11 +18,6 @@ CASES = [("c2_mid", 2, 200), ("c1", 2, 100), ("uneven3d_small", 2, 30), ("uneven
 IDS = [c[0] for c in CASES]
 
 
-def rel(a, b):
-    a, b = np.ravel(a), np.ravel(b)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
 @pytest.fixture(scope="module")
 def problems(hip_device):
     cache = {}
@@ -50,11 +45,11 @@ def test_amg_levels(problems, case):
     assert h.amg_levels() == len(ref) >= 2
     for l, L in enumerate(ref):
         A = h.amg_matrix(l, 0).toarray()
-        assert rel(A, L.A.toarray()) < 1e-12, (l, rel(A, L.A.toarray()))
+        harness.assert_close(A, L.A.toarray(), 1e-12, what=repr(l))
         if L.P is not None:
             P = h.amg_matrix(l, 1).toarray()
             assert P.shape == L.P.shape
-            assert rel(P, L.P.toarray()) < 1e-13, (l, rel(P, L.P.toarray()))
+            harness.assert_close(P, L.P.toarray(), 1e-13, what=repr(l))
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
@@ -68,7 +63,7 @@ def test_vcycle_with_amg_coarse_solve(problems, case):
     z = torch.empty(lay.n_composite, dtype=torch.float64, device="cuda:0")
     h.apply_vcycle(harness.to_dev(b), z)
     ref = lay.to_composite_owner(regional.vcycle(levels, lay.to_regional(b), opt)).reshape(-1)
-    assert rel(z.cpu().numpy(), ref) < 1e-12
+    harness.assert_close(z.cpu().numpy(), ref, 1e-12)
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
@@ -84,7 +79,7 @@ def test_pcg_with_amg_coarse_solve(problems, case):
     out = h.solve(harness.to_dev(b), x, rtol=1e-8)
     assert out["iterations"] == ref.iterations and ref.converged
     np.testing.assert_allclose(out["history"], ref.history, rtol=1e-8)
-    assert rel(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1)) < 1e-10
+    harness.assert_close(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1), 1e-10)
 
 
 def test_fp32_vcycle_and_graph_replay(hip_device):
@@ -103,12 +98,12 @@ def test_fp32_vcycle_and_graph_replay(hip_device):
             x2 = torch.zeros_like(b)
             out2 = h.solve(b, x2, rtol=1e-8)  # replay of the recorded graphs
             assert torch.equal(x, x2) and out2["iterations"] == out["iterations"]
-        assert out["converged"] and out["true_relres"] <= 1.5e-8
+        assert out["converged"] and out["true_relres"] <= 1e-8
         outs.append((out, x))
         h.close()
     (o32, x32), (og, xg), (oe, xe) = outs
     assert torch.equal(xg, xe) and og["iterations"] == oe["iterations"]
-    assert rel(x32.cpu().numpy(), xe.cpu().numpy()) < 1e-6
+    harness.assert_close(x32.cpu().numpy(), xe.cpu().numpy(), 1e-6, floor=1.0)  # FP32 V-cycle: absolute rounding
 
 
 def test_amg_option_errors(hip_device):
@@ -152,5 +147,5 @@ def test_full_size_three_region_levels(hip_device):
     out = h.solve(b, x, rtol=1e-8)
     print(f"[gpu-amg] {out['iterations']} PCG iterations, {out['solve_ms']:.1f} ms, true relres "
           f"{out['true_relres']:.2e}", flush=True)
-    assert out["converged"] and out["true_relres"] <= 1.5e-8 and out["iterations"] <= 12
+    assert out["converged"] and out["true_relres"] <= 1e-8 and out["iterations"] <= 12
     h.close()

@@ -98,7 +98,7 @@ def test_fullsize_matvec_and_solve(hip_device, tmp_path, name, opts):
     bd = harness.to_dev(b)
     xs = torch.zeros_like(bd)
     out = h.solve(bd, xs, rtol=1e-8, maxit=200)
-    assert out["converged"] and out["true_relres"] <= 1.5e-8, out
+    assert out["converged"] and out["true_relres"] <= 1e-8, out
     res_lib = at(bd - composite_matvec(h, w, xs), w, nodes)
     xsol = xs.cpu().numpy().reshape(shp)
     res_or = np.array([b[gz, gy, gx] for gx, gy, gz in nodes]) - assembly.q1_rows(
@@ -124,7 +124,7 @@ def test_fullsize_learned_interpolation(hip_device):
     b = harness.to_dev(synth.rhs(w))
     x = torch.zeros_like(b)
     out = h.solve(b, x, rtol=1e-8, maxit=200)
-    assert out["converged"] and out["true_relres"] <= 1.5e-8
+    assert out["converged"] and out["true_relres"] <= 1e-8
     h.close()
 
 
@@ -143,7 +143,7 @@ def test_fullsize_gauss_seidel_pcg(hip_device):
     bd = harness.to_dev(b)
     xs = torch.zeros_like(bd)
     out = h.solve(bd, xs, rtol=1e-8, maxit=100)
-    assert out["converged"] and out["true_relres"] <= 1.5e-8, out
+    assert out["converged"] and out["true_relres"] <= 1e-8, out
     nx, ny, nz = w.composite_shape_xyz
     nodes = sample_nodes(w)
     dn = synth.dirichlet_nodes((nx, ny, nz), w.dirichlet_mask)
@@ -155,3 +155,26 @@ def test_fullsize_gauss_seidel_pcg(hip_device):
     print(f"[fullsize] symmetric GS PCG: {out['iterations']} iterations, {out['solve_ms']:.1f} ms", flush=True)
     h.close()
 
+
+
+def test_fullsize_table_equals_streaming(hip_device):
+    """At the benchmark's own size and launch shape (4x4x4 regions of 82^3: 1,280 tiles of 768
+    threads marching 41 planes), one V-cycle with the region table equals the V-cycle that streams
+    every coupling bit for bit; the same shape on 2x2x2 of these regions is compared with the
+    oracle element by element in test_gpu_production_tiles."""
+    import torch
+
+    w = synth.workload("c2")
+    print("[fullsize] c2 region table on / off", flush=True)
+    b = harness.to_dev(synth.rhs(w))
+    zs = {}
+    for t in (1, 0):
+        h = harness.gpu_problem(w, region_table=t)
+        shape = h.level_tiles(0)
+        assert shape == {"ntiles": 1280, "threads": 768, "planes": 41}, shape
+        assert h.level_table_regions(0) == (64 if t else 0)
+        z = torch.empty_like(b)
+        h.apply_vcycle(b, z)
+        zs[t] = z
+        h.close()
+    assert torch.equal(zs[1], zs[0])

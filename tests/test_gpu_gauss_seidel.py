@@ -21,10 +21,6 @@ CASES = ["c1_small", "c2_small", "c3_small", "c4_small", "c5_small", "uneven2d_s
 NAMES = {2: "gs", 3: "sgs", 4: "symgs"}
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
-
-
 @pytest.mark.parametrize("name", CASES)
 def test_gs_smoother_regional_output(hip_device, name):
     import torch
@@ -40,7 +36,7 @@ def test_gs_smoother_regional_output(hip_device, name):
     u = torch.empty(lay.n_regional, dtype=torch.float64, device="cuda:0")
     h.smooth(0, harness.to_dev(lay.flatten(br)), u)
     got = u.cpu().numpy()
-    assert rel(got, lay.flatten(ref)) < 1e-12
+    harness.assert_close(got, lay.flatten(ref), 1e-12)
     # copies of an interface dof agree after the averaging
     avg = lay.flatten(lay.to_regional(lay.to_composite_avg(lay.unflatten(got))))
     assert np.abs(got - avg).max() <= 1e-15 * np.abs(got).max()
@@ -62,7 +58,7 @@ def test_gs_vcycle(hip_device, name, smoother):
     z = torch.empty(lay.n_composite, dtype=torch.float64, device="cuda:0")
     h.apply_vcycle(harness.to_dev(b), z)
     ref = lay.to_composite_owner(regional.vcycle(levels, lay.to_regional(b), opt)).reshape(-1)
-    assert rel(z.cpu().numpy(), ref) < 1e-12
+    harness.assert_close(z.cpu().numpy(), ref, 1e-12)
     h.close()
 
 
@@ -80,7 +76,7 @@ def test_symmetric_gs_pcg(hip_device):
     out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100)
     assert out["iterations"] == ref.iterations and ref.converged
     np.testing.assert_allclose(out["history"], ref.history, rtol=1e-8)
-    assert rel(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1)) < 1e-10
+    harness.assert_close(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1), 1e-10)
     h.close()
 
 
@@ -113,7 +109,7 @@ def test_table1_structure_gauss_seidel(hip_device):
     # (a few 1e-17 relative to the initial residual), hence the absolute floor
     np.testing.assert_allclose(hg, hr, rtol=1e-8, atol=1e-15)
     assert hr[-1] <= 1e-12 < hr[-2]
-    assert rel(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1)) < 1e-10
+    harness.assert_close(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1), 1e-10)
     ratio = hr[1:] / hc[1:]
     assert np.all(ratio > 0.5) and np.all(ratio < 2.0), ratio
     print(f"[table1 gs] {n} cycles; regional/composite residual ratio {ratio.min():.3f} .. {ratio.max():.3f}",
@@ -142,7 +138,7 @@ def test_table1_rectangular_gauss_seidel(hip_device):
     hr = np.asarray(hr)
     np.testing.assert_allclose(np.asarray(out["history"][: n + 1]), hr, rtol=1e-8, atol=1e-15)
     assert hr[-1] <= 1e-12 < hr[-2]
-    assert rel(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1)) < 1e-10
+    harness.assert_close(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1), 1e-10)
     print(f"[table1-rect gs] {n} cycles", flush=True)
     h.close()
 

@@ -27,10 +27,6 @@ LAYOUTS = {
 SMOOTHERS = {1: "jacobi", 2: "gs", 4: "symgs"}
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
-
-
 def workload(ext):
     o, e = synth.tensor_layout([[ext] * 3] * 3)
     return synth.Workload(f"fd7_{ext}", 3, 1, o, e, 63, 3, 2, "fd7", seed=0)
@@ -103,7 +99,7 @@ def test_hybrid_cycle_parity(hip_device, name, smoother, gamma):
     h = gpu_handle(w, kinds, smoother, omega, gamma)
     z = torch.empty(b.size, dtype=torch.float64, device="cuda:0")
     h.apply_vcycle(harness.to_dev(b), z)
-    assert rel(z.cpu().numpy(), ref) < 1e-12
+    harness.assert_close(z.cpu().numpy(), ref, 1e-12)
     h.close()
 
 
@@ -132,7 +128,7 @@ def test_table5_setting_parity(hip_device, name, method):
     out = h.solve(harness.to_dev(b), x, rtol=1e-6, maxit=100, method=method)
     assert out["converged"] and out["iterations"] == len(hr) - 1
     np.testing.assert_allclose(out["history"], hr, rtol=1e-8)
-    assert rel(x.cpu().numpy(), lv[0].to_composite_owner(xr)) < 1e-9
+    harness.assert_close(x.cpu().numpy(), lv[0].to_composite_owner(xr), 1e-9)
     h.close()
 
 
@@ -253,7 +249,7 @@ def test_hybrid_other_layouts(hip_device, case):
         np.testing.assert_array_equal(h.hybrid_aggregates(l), agg)
     z = torch.empty(b.size, dtype=torch.float64, device="cuda:0")
     h.apply_vcycle(harness.to_dev(b), z)
-    assert rel(z.cpu().numpy(), ref) < 1e-12
+    harness.assert_close(z.cpu().numpy(), ref, 1e-12)
     h.close()
 
 

@@ -14,10 +14,6 @@ from tests import harness
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
-
-
 def test_table1_structure_jacobi_histories(hip_device):
     import torch
 
@@ -42,7 +38,7 @@ def test_table1_structure_jacobi_histories(hip_device):
     big = hc > 1e-9
     np.testing.assert_allclose(hg[big], hc[big], rtol=1e-6)
     assert hc[-1] <= 1e-12 and (n == 1 or hc[-2] > 1e-12)  # same stopping cycle
-    assert rel(x.cpu().numpy(), xc) < 1e-10
+    harness.assert_close(x.cpu().numpy(), xc, 1e-10)
     print(f"[table1] {n} cycles to 1e-12, asymptotic factor {(hc[-1] / hc[-11]) ** 0.1:.3f}", flush=True)
     h.close()
 
@@ -63,7 +59,7 @@ def test_chebyshev_mg_as_solver(hip_device, name):
     xr, hr = regional.stationary(levels, lay.to_regional(b), lay.zeros_regional(), opt, n)
     np.testing.assert_allclose(out["history"][: n + 1], hr, rtol=1e-8)
     assert out["converged"] and hr[-1] <= 1e-8 < hr[-2]
-    assert rel(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1)) < 1e-10
+    harness.assert_close(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1), 1e-10)
     h.close()
 
 
@@ -81,7 +77,7 @@ def test_jacobi_smoothed_pcg(hip_device):
     out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=200)
     assert out["iterations"] == ref.iterations
     np.testing.assert_allclose(out["history"], ref.history, rtol=1e-8)
-    assert rel(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1)) < 1e-10
+    harness.assert_close(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1), 1e-10)
     h.close()
 
 
@@ -127,7 +123,7 @@ def test_table1_rectangular_histories(hip_device, smoother):
     big = hr > 1e-9
     np.testing.assert_allclose(hg[big], hr[big], rtol=1e-6)
     assert hr[-1] <= 1e-12 and hr[-2] > 1e-12  # same stopping cycle
-    assert rel(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1)) < 1e-10
+    harness.assert_close(x.cpu().numpy(), lay.to_composite_owner(xr).reshape(-1), 1e-10)
     h.close()
     one = Layout(2, [[0, 0]], [list(w.composite_shape_xyz)], w.dirichlet_mask)
     sl = composite.setup(one, assembly.composite_fd5(one), opt)

@@ -13,10 +13,6 @@ pytestmark = pytest.mark.gpu
 CASES = [("c1_small", 5), ("c2_small", 27), ("c5_small", 27), ("c4_small", 27)]
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
-
-
 def composite_matrix(w, lay):
     from oracle import assembly
 
@@ -48,7 +44,7 @@ def test_csr_split_and_solve(hip_device, name, npts):
         got = h.level_stencil(0, k, npts, ref.shape[1])
         if npts == 5:  # the oracle stores five-point rows in the 9-point order
             ref = ref[[1, 3, 4, 5, 7]]
-        assert rel(got, ref) < 1e-14, k
+        harness.assert_close(got, ref, 1e-14, what=repr(k))
     opt = regional.Options(nlevels=w.nlevels, degree=w.cheb_degree)
     levels = regional.setup(lay, coefs, opt)
     b = synth.rhs(w)
@@ -56,7 +52,7 @@ def test_csr_split_and_solve(hip_device, name, npts):
     x = torch.zeros(lay.n_composite, dtype=torch.float64, device="cuda:0")
     out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100)
     assert out["iterations"] == ref.iterations
-    assert rel(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1)) < 1e-10
+    harness.assert_close(x.cpu().numpy(), lay.to_composite_owner(ref.x).reshape(-1), 1e-10)
     h.close()
 
 
@@ -84,7 +80,7 @@ def test_duplicate_entries_add_up(hip_device):
     h.set_composite_csr(27, Dcsr)
     coefs = assembly.split_composite(lay, A)
     got = h.level_stencil(0, 0, 27, coefs[0][0].size)
-    assert rel(got, coefs[0].reshape(27, -1)) < 1e-14
+    harness.assert_close(got, coefs[0].reshape(27, -1), 1e-14)
     h.close()
 
 

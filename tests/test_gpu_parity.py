@@ -26,12 +26,6 @@ SMALL = [("c1_small", 0), ("c2_small", 1), ("c2_small", 2), ("c4_small", 1), ("c
 IDS = [f"{n}-k{k}" for n, k in SMALL]
 
 
-def rel(a, b):
-    a = np.asarray(a, dtype=np.float64).ravel()
-    b = np.asarray(b, dtype=np.float64).ravel()
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
 @pytest.fixture(scope="module")
 def problems(hip_device):
     cache = {}
@@ -70,7 +64,7 @@ def test_level_operators(problems, name):
             got = h.level_stencil(l, k, info["npts"] * L.lay.ndof ** 2, ref.shape[1])
             if info["npts"] == 5:
                 got = five_to_nine(got)
-            assert rel(got, ref) < 1e-12, (l, k, rel(got, ref))
+            harness.assert_close(got, ref, 1e-12, what=repr((l, k)))
 
 
 @pytest.mark.parametrize("name", SMALL, ids=IDS)
@@ -86,7 +80,7 @@ def test_coarse_composite_matrix(problems, name):
     w, h, (lay, levels, opt) = problems(name)
     Ab = levels[-1].Abar
     got = h.coarse_matrix(Ab.shape[0])
-    assert rel(got, Ab) < 1e-12
+    harness.assert_close(got, Ab, 1e-12)
 
 
 @pytest.mark.parametrize("name", SMALL, ids=IDS)
@@ -104,7 +98,7 @@ def test_regional_matvec_and_interface_sum(problems, name):
     z = torch.empty_like(reg)
     h.regional_matvec(0, reg, z)
     ref = lay.flatten(L0.matvec(lay.to_regional(x)))
-    assert rel(z.cpu().numpy(), ref) < 1e-13
+    harness.assert_close(z.cpu().numpy(), ref, 1e-13)
     # interface sum of an inconsistent regional vector
     v = rng.uniform(-1, 1, size=lay.n_regional)
     w_ = torch.empty_like(reg)
@@ -113,7 +107,7 @@ def test_regional_matvec_and_interface_sum(problems, name):
     # composite conversions: owner copy and average
     comp = torch.empty(lay.n_composite, dtype=torch.float64, device="cuda:0")
     h.to_composite(0, harness.to_dev(v), comp, average=True)
-    assert rel(comp.cpu().numpy(), lay.to_composite_avg(lay.unflatten(v)).reshape(-1)) < 1e-15
+    harness.assert_close(comp.cpu().numpy(), lay.to_composite_avg(lay.unflatten(v)).reshape(-1), 1e-15)
 
 
 @pytest.mark.parametrize("name", SMALL, ids=IDS)
@@ -132,7 +126,7 @@ def test_transfers(problems, name):
         wg = torch.empty(C.lay.n_regional, dtype=torch.float64, device="cuda:0")
         h.restrict(l, harness.to_dev(F.lay.flatten(rr)), wg)
         wref = C.lay.flatten(transfer.regional_restrict(F.lay, C.lay, F.P, rr))
-        assert rel(wg.cpu().numpy(), wref) < 1e-13, l
+        harness.assert_close(wg.cpu().numpy(), wref, 1e-13, what=repr(l))
         ub = rng.uniform(-1, 1, size=harness.vshape(C.lay))
         ub[C.lay.dirichlet] = 0.0
         u0 = rng.uniform(-1, 1, size=harness.vshape(F.lay))
@@ -140,7 +134,7 @@ def test_transfers(problems, name):
         h.prolongate_add(l, harness.to_dev(C.lay.flatten(C.lay.to_regional(ub))), ug)
         uref = F.lay.flatten([a + b for a, b in zip(F.lay.to_regional(u0), transfer.regional_prolongate(
             F.lay, C.lay, F.P, C.lay.to_regional(ub)))])
-        assert rel(ug.cpu().numpy(), uref) < 1e-13, l
+        harness.assert_close(ug.cpu().numpy(), uref, 1e-13, what=repr(l))
 
 
 @pytest.mark.parametrize("name", SMALL, ids=IDS)
@@ -156,7 +150,7 @@ def test_smoother(problems, name):
     u = torch.empty(lay.n_regional, dtype=torch.float64, device="cuda:0")
     h.smooth(0, harness.to_dev(lay.flatten(br)), u)
     ref = regional.chebyshev(L0, lay.zeros_regional(), br, br, opt)
-    assert rel(u.cpu().numpy(), lay.flatten(ref)) < 1e-12
+    harness.assert_close(u.cpu().numpy(), lay.flatten(ref), 1e-12)
 
 
 @pytest.mark.parametrize("name", SMALL, ids=IDS)
@@ -170,7 +164,7 @@ def test_vcycle(problems, name):
     z = torch.empty(lay.n_composite, dtype=torch.float64, device="cuda:0")
     h.apply_vcycle(harness.to_dev(b), z)
     ref = lay.to_composite_owner(regional.vcycle(levels, lay.to_regional(b), opt)).reshape(-1)
-    assert rel(z.cpu().numpy(), ref) < 1e-12
+    harness.assert_close(z.cpu().numpy(), ref, 1e-12)
 
 
 @pytest.mark.parametrize("name", SMALL, ids=IDS)
@@ -187,9 +181,9 @@ def test_pcg(problems, name):
     xref = lay.to_composite_owner(ref.x).reshape(-1)
     assert out["converged"] and ref.converged
     assert out["iterations"] == ref.iterations
-    np.testing.assert_allclose(out["history"], ref.history, rtol=1e-8, atol=0)
-    assert rel(x.cpu().numpy(), xref) < 1e-10
-    assert out["true_relres"] <= 1.5e-8
+    np.testing.assert_allclose(out["history"], ref.history, rtol=1e-10, atol=0)
+    harness.assert_close(x.cpu().numpy(), xref, 1e-10)
+    assert out["true_relres"] <= 1e-8
 
 
 def test_errors_are_reported(hip_device):
@@ -246,9 +240,11 @@ def test_mixed_precision_solve(hip_device, name, precision, kernel):
     ref = regional.pcg(levels, lay.to_regional(b), opt, rtol=1e-12, maxit=200)
     xref = lay.to_composite_owner(ref.x).reshape(-1)
     h.close()
-    assert out["converged"] and out["true_relres"] <= 1.5e-8, out
+    assert out["converged"] and out["true_relres"] <= 1e-8, out
     assert out["iterations"] <= ref.iterations + 6
-    assert rel(x.cpu().numpy(), xref) < 1e-6
+    # a 1e-8 residual bounds the error by kappa * 1e-8 in norm; element-wise against the largest
+    # entry (floor 1: low-precision preconditioning spreads the error evenly, not proportionally)
+    harness.assert_close(x.cpu().numpy(), xref, 1e-6, floor=1.0)
 
 
 def test_mixed_vcycle_close_to_fp64(hip_device):
@@ -265,9 +261,11 @@ def test_mixed_vcycle_close_to_fp64(hip_device):
         h = harness.gpu_problem(w, precision=precision)
         z = torch.empty(lay.n_composite, dtype=torch.float64, device="cuda:0")
         h.apply_vcycle(harness.to_dev(b), z)
-        err = rel(z.cpu().numpy(), ref)
+        got = z.cpu().numpy()
         h.close()
-        assert err < tol, (precision, err)
+        # FP32 / BF16 rounding is absolute at the scale of the cycle's vectors, so the bound is
+        # taken against the largest entry (floor 1) as well as each entry
+        harness.assert_close(got, ref, tol, floor=1.0, what=f"precision {precision}")
 
 
 @pytest.mark.parametrize("kernel", [2, 3])
@@ -289,14 +287,14 @@ def test_half_stencil_matches_full(hip_device, kernel):
         out = h.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100)
         assert out["iterations"] == ref.iterations
         xs[sym] = x.cpu().numpy()
-        assert rel(xs[sym], lay.to_composite_owner(ref.x).reshape(-1)) < 1e-10
+        harness.assert_close(xs[sym], lay.to_composite_owner(ref.x).reshape(-1), 1e-10)
         h.close()
         hl = harness.gpu_problem(w, stencil_kernel=kernel, symmetric=sym, precision=1)
         x.zero_()
         out = hl.solve(harness.to_dev(b), x, rtol=1e-8, maxit=100)
-        assert out["converged"] and out["true_relres"] <= 1.5e-8
+        assert out["converged"] and out["true_relres"] <= 1e-8
         hl.close()
-    assert rel(xs[1], xs[0]) < 1e-12
+    harness.assert_close(xs[1], xs[0], 1e-12)
 
 
 def test_asymmetric_stencils_use_the_full_kernel(hip_device):
@@ -328,7 +326,7 @@ def test_asymmetric_stencils_use_the_full_kernel(hip_device):
     z = torch.empty_like(reg)
     h.regional_matvec(0, reg, z)
     ref = lay.interface_sum([assembly.apply_stencil(pert[k], lay.to_regional(x)[k], 3, 1) for k in range(lay.nreg)])
-    assert rel(z.cpu().numpy(), lay.flatten(ref)) < 1e-13
+    harness.assert_close(z.cpu().numpy(), lay.flatten(ref), 1e-13)
     h.close()
 
 
@@ -346,8 +344,31 @@ def test_block_half_stencil_matches_full(hip_device, precision):
         assert h.level_kernel(0)["coefs" if precision == 0 else "coefs_lo"] == (126 if sym else 243)
         x = torch.zeros_like(b)
         out = h.solve(b, x, rtol=1e-8, maxit=100)
-        assert out["converged"] and out["true_relres"] <= 1.5e-8
+        assert out["converged"] and out["true_relres"] <= 1e-8
         xs[sym], its[sym] = x.cpu().numpy(), out["iterations"]
         h.close()
     assert its[0] == its[1]
-    assert rel(xs[1], xs[0]) < (1e-12 if precision == 0 else 1e-8)
+    harness.assert_close(xs[1], xs[0], (1e-12 if precision == 0 else 1e-8), floor=(1e-3 if precision == 0 else 1.0))
+
+
+@pytest.mark.parametrize("name", ["c2_mid", "c4_small", "uneven3d_small", "uneven_tiny3d", "c5_small", "c2_small"])
+def test_galerkin_separable_matches_generic(hip_device, name):
+    """The separable Galerkin product (three one-axis products of the tensor-product rate-3
+    interpolation, the default on scalar 3D levels) and the generic product over each coarse node's
+    5 x 5 x 5 fine window give every coarse level's stencils, including the Dirichlet rows, to
+    rounding; both match the oracle's sparse products entry by entry."""
+    w = synth.workload(name)
+    lay, levels, opt = harness.oracle_problem(w)
+    got = {}
+    for gen in (0, 1):
+        h = harness.gpu_problem(w, galerkin_generic=gen)
+        got[gen] = []
+        for l, L in enumerate(levels[1:], start=1):
+            for k in range(L.lay.nreg):
+                ref = harness.stencil_soa(L.coefs[k], L.lay.dim, L.lay.ndof)
+                g = h.level_stencil(l, k, 27, ref.shape[1])
+                harness.assert_close(g, ref, 1e-12, what=f"generic={gen} level {l} region {k}")
+                got[gen].append(g)
+        h.close()
+    for a, b in zip(got[0], got[1]):
+        harness.assert_close(a, b, 1e-13, what="separable vs generic")

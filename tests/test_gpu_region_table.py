@@ -1,8 +1,9 @@
-"""Region table of the symmetric 2.5D kernel: where every node two or more nodes inside a region
-has the same stored upper couplings, the kernel takes them from a 14-value table of the region
-instead of streaming them.  Each case solves twice, with the table (default) and with every
-coupling streamed (region_table = 0): V-cycle output, PCG iterate and residual history must agree
-bit for bit.  The regions served by the table follow the coefficients: every region with at least
+"""Region table of the symmetric FP64 levels: where every node two or more nodes inside a region
+(one on faces whose next layer allows it) has the same stored upper couplings, those nodes run as
+deep-box tiles that take their couplings from a 14-value table of the region instead of streaming
+them, and the region's outer layers run as node blocks.  Each case solves twice, with the table
+(default) and with every coupling streamed (region_table = 0): the V-cycle output must agree bit
+for bit, the PCG iterate and residual history to the rounding of the CG inner product.  The regions served by the table follow the coefficients: every region with at least
 5 nodes a side of a constant-coefficient Laplacian, none under per-element random coefficients or
 on regions too thin to have such nodes; the FP32 V-cycle (narrower tiles) builds no table.
 """
@@ -56,10 +57,12 @@ def test_table_equals_streamed_couplings(hip_device, case):
     thick = int(sum(min(int(v) for v in e) >= 5 for e in np.asarray(w.extents)))
     want = thick if expect == "thick" else expect
     assert n0 == 0 and n1 == want
-    assert torch.equal(z1, z0)
+    assert torch.equal(z1, z0)  # every stencil operation of the cycle, bit for bit
+    # CG: the product's fused inner-product partial sums follow the launch decomposition (deep
+    # tiles and shell blocks with the table, whole tiles without), so only their rounding differs
     assert o1["iterations"] == o0["iterations"] and o1["converged"]
-    np.testing.assert_array_equal(o1["history"], o0["history"])
-    assert torch.equal(x1, x0)
+    np.testing.assert_allclose(o1["history"], o0["history"], rtol=1e-12, atol=0)
+    harness.assert_close(x1.cpu().numpy(), x0.cpu().numpy(), 1e-13, what="PCG x, table vs streaming")
 
 
 def test_table_option_error(hip_device):
