@@ -468,6 +468,18 @@ rmg_status rmg_get_prolongator_weights(rmg_handle* h, double* host_out);
  * rho = (||r_cycles|| / ||r_0||)^(1/cycles) in the composite 2-norm.  Synchronises. */
 rmg_status rmg_convergence_factor(rmg_handle* h, int cycles, double* rho);
 
+/* rmg_convergence_factor for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same computation and
+ * result, with its four work vectors (the zero right-hand side, iterate, residual and correction)
+ * in a fixed 32 MiB array per GPU instead of memory allocated per call, so it calls neither
+ * hipMalloc nor the handle's allocator.  The hierarchy's own buffers, made by
+ * rmg_setup_hierarchy, are used as by rmg_convergence_factor.  RMG_ERR_ARG when the finest level
+ * has more than 1,048,576 regional dofs (4 x 8 bytes each must fit in the array).  Every call on
+ * a GPU shares that GPU's array and leaves its contents behind (each call rewrites all it
+ * reads), so calls that overlap on one GPU (several threads, or handles on different streams)
+ * race.  Synchronises. */
+rmg_status rmg_convergence_factor_noalloc(rmg_handle* h, int cycles, double* rho);
+
 /* ---- MLP training on the device ----
  * Training data are pairs (X, E) per coarse cell: X the 27 features above and
  * E the values of a smooth error on the cell's 4 x 4 x 4 fine nodes (x

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_lib", "libregmg.so")
 
-SOURCES = ["kernels.hip", "kernels_stencil.hip", "kernels_gs.hip", "kernels_hybrid.hip", "kernels_amg.hip", "mlp.hip",
+SOURCES = ["kernels.hip", "kernels_stencil.hip", "kernels_gs.hip", "kernels_hybrid.hip", "kernels_amg.hip", "mlp.hip", "noalloc.hip",
            "planner.cpp", "solver.cpp", "learned.cpp", "hybrid.cpp", "amg.cpp", "api.cpp"]
 
 FLAGS = [

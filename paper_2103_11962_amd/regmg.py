@@ -40,7 +40,7 @@ SYMBOLS = (
     "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr", "rmg_mg_solve",
     "rmg_mlp_set_loss", "rmg_set_region_kinds", "rmg_hybrid_level_info", "rmg_hybrid_aggregates",
     "rmg_hybrid_composite_ids", "rmg_hybrid_matrix", "rmg_amg_levels", "rmg_amg_level_info", "rmg_amg_matrix",
-    "rmg_level_table_regions", "rmg_level_tiles", "rmg_kernel_launches"
+    "rmg_level_table_regions", "rmg_level_tiles", "rmg_kernel_launches", "rmg_convergence_factor_noalloc",
 )
 SMOOTHER_CHEBYSHEV, SMOOTHER_JACOBI, SMOOTHER_GS, SMOOTHER_GS_FB, SMOOTHER_SYMGS = 0, 1, 2, 3, 4
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
@@ -171,6 +171,7 @@ def load():
                                      ctypes.POINTER(D)]),
         "rmg_get_prolongator_weights": (I, [H, P]),
         "rmg_convergence_factor": (I, [H, I, ctypes.POINTER(D)]),
+        "rmg_convergence_factor_noalloc": (I, [H, I, ctypes.POINTER(D)]),
         "rmg_mlp_create": (I, [ctypes.POINTER(H), I, P]),
         "rmg_mlp_destroy": (I, [H]),
         "rmg_mlp_set_params": (I, [H, P]),
@@ -523,6 +524,11 @@ class Handle:
     def convergence_factor(self, cycles=10):
         rho = ctypes.c_double()
         _check(load().rmg_convergence_factor(self._h, cycles, ctypes.byref(rho)))
+        return rho.value
+
+    def convergence_factor_noalloc(self, cycles=10):
+        rho = ctypes.c_double()
+        _check(load().rmg_convergence_factor_noalloc(self._h, cycles, ctypes.byref(rho)))
         return rho.value
 
 
