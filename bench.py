@@ -659,10 +659,8 @@ def main():
     def stored_bytes_per_row(table):
         bpr = float(cheb_bytes_per_row(lk["coefs"], not tiled))
         if table:
-            # couplings of nodes two or more nodes inside a region come from the region table
-            ext = np.asarray(w.extents, dtype=np.int64)
-            deep = float(np.prod(np.maximum(ext - 4, 0), axis=1).sum()) / rows
-            bpr -= 8 * lk["coefs"] * deep
+            # every region served: every coupling comes from the regions' class tables
+            bpr -= 8 * lk["coefs"]
         return bpr
 
     stored_bpr = stored_bytes_per_row(table_regions == w.nreg)
@@ -721,14 +719,14 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_stencil3d<Cheb, half stencil, region table> (finest-level fused Chebyshev step, 2.5D "
-                       "tiles, upper half of the symmetric stencil, interior couplings from the region table)"
-                       if table_regions else
+            "kernel": ("k_stencil_table<Cheb> (finest-level fused Chebyshev step, whole-row 2.5D tiles, every "
+                       "coupling from the regions' class tables)"
+                       if table_regions == w.nreg else
                        "k_stencil3d<Cheb, half stencil> (finest-level fused Chebyshev step, 2.5D tiles, upper "
                        "half of the symmetric stencil streamed)" if lk["coefs"] == 14 else
                        "k_stencil3d<Cheb> (finest-level fused Chebyshev step, 2.5D tiles)"),
-            # the bytes this kernel must move per row: u, b, d read, d, u written, the upper couplings
-            # of the rows the region table does not serve, D^-1 of shared rows
+            # the bytes this kernel must move per row: u, b, d read, d, u written, D^-1 of shared rows,
+            # and the upper couplings of rows whose region the class tables do not serve
             "bytes_per_row": round(stored_bpr, 2),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

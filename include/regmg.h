@@ -137,15 +137,16 @@ typedef struct {
                          with at most amg_coarse_size rows */
   int amg_coarse_size; /* rows of the directly solved AMG level, in [1, 20000] (default 2000) */
   int region_table;   /* 1 (default): on FP64 levels run by the symmetric 2.5D kernel on 768-thread
-                         tiles (the FP64 V-cycle; the FP32 V-cycle's narrower tiles gained nothing
-                         from it and always stream), setup compares the
-                         stored upper couplings of every node two or more nodes inside its region
-                         (all 27 neighbours then lie inside the region) with those of the node
-                         (2, 2, 2); where all are equal bit for bit (a constant-coefficient
-                         region, as the structured regions of the Q1 Laplacian, the per-region
-                         diffusion and elasticity problems give), the kernel takes them from a
-                         14-value table of the region instead of streaming them from memory.
-                         Results are bit for bit those of 0, which always streams them */
+                         tiles (the FP64 V-cycle; the FP32 V-cycle's narrower tiles always
+                         stream), setup sorts every region's nodes into 125 classes (per axis: the
+                         two low layers, the inside, the two high layers) and compares each node's
+                         27 couplings (its stored upper ones and its neighbours' mirrored ones)
+                         with those of its class's first node; where all are equal bit for bit (a
+                         region whose operator is the same everywhere inside, as the structured
+                         regions of the Q1 Laplacian, the per-region diffusion and elasticity
+                         problems give), the region runs whole-row tiles that take every coupling
+                         from the region's 125 x 27 class table instead of streaming them from
+                         memory.  Results are bit for bit those of 0, which always streams them */
   int tile_planes;    /* planes per 2.5D tile: 0 (default) chooses (41 on FP64 levels that keep at
                          least 1024 such tiles, else 21); 21 or 41 forces that depth on every
                          tiled level, so that a problem small enough for the oracle runs the launch
@@ -335,7 +336,7 @@ rmg_status rmg_kernel_launches(int64_t* count);
 /* 2.5D tile shape of `level`: the number of tiles, threads per tile block and planes per tile
  * (all 0 where the level runs node-parallel kernels).  Any output may be NULL. */
 rmg_status rmg_level_tiles(rmg_handle* h, int level, int* ntiles, int* threads, int* planes);
-/* Regions of `level` whose interior couplings the symmetric 2.5D kernel takes from the region table
+/* Regions of `level` whose couplings the 2.5D kernels take from the region's class table
  * (rmg_options.region_table); 0 where no table was built.  Output may be NULL. */
 rmg_status rmg_level_table_regions(rmg_handle* h, int level, int* nregions);
 /* Copy region `region`'s stencil on `level` to host memory in the layout of

@@ -249,10 +249,10 @@ static void begin_operator_change(rmg_handle* h, Level& L) {
   h->have_hierarchy = false;
   h->have_operator = false;
   h->drop_graphs();
-  L.coef_sym.release();  // the half stencils and region table of the old operator
+  L.coef_sym.release();  // the half stencils and class tables of the old operator
   L.coef_lo_sym.release();
-  L.sym_table.release();
-  L.sym_table_ok.release();
+  L.class_table.release();
+  L.class_table_ok.release();
   clear_split(L);
 }
 
@@ -730,7 +730,7 @@ rmg_status rmg_level_table_regions(rmg_handle* h, int level, int* nregions) {
   API_BEGIN
   use_device(h);
   Level& L = level_of(h, level);
-  const DBuf& ok = L.sym_table_ok;
+  const DBuf& ok = L.class_table_ok;
   int count = 0;
   if (ok.p) {
     std::vector<int> flags(L.nreg);

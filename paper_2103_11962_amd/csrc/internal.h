@@ -92,18 +92,19 @@ constexpr size_t kDeepTileMin = 1024;  // 41-plane FP64 tiles needed before they
 // whose V-cycle runs in FP32 uses the narrow tiles for every operation.
 constexpr int kTileThreadsF64 = 768;
 constexpr int kTileThreadsF32 = 512;
-// Threads per deep-box tile of the region-table split (k_stencil_deep: no coupling stream, about 90
-// VGPRs, so several 4-wave blocks share a CU) and planes per tile (two per 78-plane deep box).
-constexpr int kDeepThreads = 256;
-constexpr int kDeepPlanes = 40;
+// Threads per whole-region tile of a table region (k_stencil_table): the inner x-nodes of a few rows
+// padded to whole wavefronts plus their rows' four x-face nodes; planes and rows per tile at most.
+constexpr int kTableThreads = 384;
+constexpr int kTablePlanes = 41;
+constexpr int kTableRows = 4;
 // Largest (tx + 2)(ty + 2) over tiles of at most nt nodes (tx * ty <= nt): the single row, ty = 1.
 constexpr int tile_plane_cap(int nt) { return 3 * (nt + 2); }
-
-// Nodes of a region-table region whose couplings, upper and lower, are the table's: [lo, hi) per
-// axis, two nodes inside the region, or one on a face whose layer-one nodes carry the table too.
-struct DeepBox {
-  int lo[3], hi[3];
-};
+// Region tables: a node's class along an axis of extent e >= 5 is its coordinate on the two low
+// layers (0, 1), 2 inside, and 3, 4 on the two high layers; a node's class is (cz * 5 + cy) * 5 + cx,
+// and a served region keeps, per class, the 27 couplings in stencil order that every node of the
+// class has.
+constexpr int kClasses = 125;
+constexpr int kClassPts = 27;
 
 // A 2.5D tile of a 3D region: ty x-rows of tx nodes starting at (x0, y0), planes z0 .. z0+nz-1.
 struct Tile3 {
@@ -184,27 +185,18 @@ struct Level {
   // operator (FP64, wave-tiled, ncoef() values per node: npts blocks of ndof x ndof)
   DBuf coef;
   DBuf coef_sym;     // symmetric scalar 27-point levels: the upper half (kSymPts per node), else empty
-  // per region: the upper couplings shared by every node two or more nodes inside the region
-  // (kSymPts values from coef_sym) and a flag that they all agree; built for FP64 levels run by
-  // 768-thread 2.5D tiles, else empty
-  DBuf sym_table, sym_table_ok;
-  // With the table: each served region runs as deep-box tiles (every node two or more nodes
-  // inside, couplings from the table) and its outer two layers as node blocks; the tiles of the
-  // other regions run the streaming 2.5D kernel.  Built with the table (make_split), refreshed
-  // when the tiles change.
-  std::vector<int> table_served;     // per region: 1 when the table serves it
-  std::vector<DeepBox> deep_box;     // per region: the box of nodes whose couplings are the table's
-  DBuf d_deep_box, sym_table_face;   // device copy; per region and face (x-, x+, y-, y+, z-, z+) a flag
-                                     // that the box may reach one node from that face
-  std::vector<Tile3> deep_tiles;     // kDeepThreads-thread tiles of the served regions' deep boxes
-  std::vector<BlockDesc> shell_blocks;  // kBlock shell nodes of one served region (start = shell index)
+  // Region tables (FP64 levels run by 768-thread 2.5D tiles, else empty): per region the
+  // kClasses x kClassPts couplings of its node classes, and a flag that every node of the region
+  // has its class's couplings bit for bit (the couplings the streaming kernel reads: its own upper
+  // ones and its neighbours' mirrored ones, 0 towards neighbours outside the region).
+  DBuf class_table, class_table_ok;
+  // With the tables: the served regions run whole-row tiles that take every coupling from the
+  // tables (k_stencil_table), the other regions the level's streaming 2.5D tiles.  Built with the
+  // tables (make_split), refreshed when the tiles change.
+  std::vector<int> table_served;     // per region: 1 when the tables serve it
+  std::vector<Tile3> table_tiles;    // whole-row tiles of the served regions (k_stencil_table)
   std::vector<Tile3> other_tiles;    // the level's 2.5D tiles of the regions not served
-  DBuf d_deep_tiles, d_shell_blocks, d_other_tiles;
-  // The shell's x-face nodes (x < 2 or x >= ex - 2, y and z two or more inside) sit four to a row,
-  // so their couplings would be read a few lanes per cache line: their upper couplings are also
-  // kept packed in shell order (wave-tiled, kSymPts per node), from d_xface_off[region] on.
-  std::vector<int64_t> xface_off;    // per region: first packed x-face node (served regions)
-  DBuf d_xface_off, xface_coef;
+  DBuf d_table_tiles, d_other_tiles;
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
   DBuf pw;        // stored interpolation weights to the next level, double [n][8] (null: geometric)
   DBuf rw;        // with pw: the same weights per coarse node (125 taps, wave-tiled) for the restriction
@@ -319,9 +311,9 @@ void coarse_geometry(int dim, const std::vector<RegionGeo>& fine, std::vector<Re
 Level* make_coarse_level(const Level& fine);
 void build_tables(Level& L);
 void make_tiles(Level& L, int depth);
-// Region-table split of a level whose table flags are `served` (per region): deep tiles, shell
-// blocks and the remaining regions' tiles (also rebuilt by make_tiles while a split exists).
-void make_split(Level& L, const std::vector<int>& served, const std::vector<DeepBox>& boxes);
+// Region-table split of a level whose table flags are `served` (per region): whole-row tiles of the
+// served regions and the remaining regions' tiles (also rebuilt by make_tiles while a split exists).
+void make_split(Level& L, const std::vector<int>& served);
 void clear_split(Level& L);
 void build_coarse_solver(rmg_handle* h, Level& L);
 

@@ -1533,211 +1533,81 @@ __global__ __launch_bounds__(kBlock) void k_make_sym(LevelView L, const C* __res
   if (bad) atomicOr(flag, 1);
 }
 
-// Region table of the symmetric 2.5D kernel: the upper couplings of node (2, 2, 2) of every region
-// with at least 5 nodes a side (one block per region), then every node two or more nodes inside its
-// region (x, y, z in [2, extent - 3]) compares its own with them bit for bit and clears the
-// region's flag on a difference.  A deep node's lower coupling A(i, i+s) is the upper coupling of
-// its neighbour i+s, which lies in the layer around the deep box when the node is on the box's
-// surface (on the low faces, and on the high ones through the offsets that are lower in z or y
-// but not in x or y): the nodes of that layer (coordinates in [1, extent - 2]) compare their upper
-// couplings towards deep nodes with the table too, so that every coupling of a deep node, upper or
-// lower, is the table's bit for bit.
+// Region tables of the symmetric 2.5D kernel.  Along an axis of extent e >= 5 a node's class is its
+// coordinate on the two low layers (0, 1), 2 inside and 3, 4 on the two high layers; a node's class
+// is (cz * 5 + cy) * 5 + cx.  A region's table holds, per class, the 27 couplings of the class's
+// first node (x, y, z each 0, 1, 2, e - 2 or e - 1) as the streaming kernel reads them: its own
+// upper couplings and its neighbours' upper couplings towards it, 0 towards neighbours outside the
+// region.  The region is served when every node has its class's 27 couplings bit for bit; on a
+// region whose operator is the same everywhere inside (one material, interface faces alike) that
+// holds, and the tiles that serve it read no couplings from memory.
 __device__ __forceinline__ bool same_bits(double a, double b) { return __double_as_longlong(a) == __double_as_longlong(b); }
-__device__ __forceinline__ bool same_bits(float a, float b) { return __float_as_int(a) == __float_as_int(b); }
 
-template <class C>
-__global__ void k_sym_table_ref(LevelView L, const C* __restrict__ sym, C* __restrict__ table, int* __restrict__ ok,
-                                int* __restrict__ face) {
-  const int k = blockIdx.x, s = threadIdx.x;
-  const RegionGeo R = L.regs[k];
-  const bool deep = R.ex >= 5 && R.ey >= 5 && R.ez >= 5;
-  if (s < kSymPts)
-    table[k * kSymPts + s] = deep ? sym[coef_index(R.off + 2 + 2 * R.ex + 2 * (int64_t)R.ex * R.ey, s, kSymPts)] : (C)0;
-  if (s == 0) ok[k] = deep ? 1 : 0;
-  if (s < 6) face[k * 6 + s] = deep ? 1 : 0;
+__device__ __forceinline__ int axis_class(int v, int e) { return v < 2 ? v : (v >= e - 2 ? v - e + 5 : 2); }
+__device__ __forceinline__ int class_node(int c, int e) { return c <= 2 ? c : e - 5 + c; }
+
+// Coupling s of node (x, y, z) of region R, A(i, i + offset(s)), as the symmetric kernels read it.
+__device__ __forceinline__ double read_coupling(const RegionGeo& R, const double* __restrict__ sym, int x, int y,
+                                                int z, int s) {
+  const int64_t gi = R.off + ((int64_t)z * R.ey + y) * R.ex + x;
+  if (s >= 13) return sym[coef_index(gi, s - 13, kSymPts)];
+  int dx, dy, dz;
+  stencil_offset<27>(s, dx, dy, dz);
+  if ((unsigned)(x + dx) >= (unsigned)R.ex || (unsigned)(y + dy) >= (unsigned)R.ey || (unsigned)(z + dz) >= (unsigned)R.ez)
+    return 0.0;
+  return sym[coef_index(gi + dx + (int64_t)dy * R.ex + (int64_t)dz * R.ex * R.ey, 13 - s, kSymPts)];
 }
 
-template <class C>
-__global__ __launch_bounds__(kBlock) void k_sym_table_check(LevelView L, const C* __restrict__ sym,
-                                                            const C* __restrict__ table, int* __restrict__ ok,
-                                                            int* __restrict__ face) {
+// One block per region, one thread per class.
+__global__ __launch_bounds__(128) void k_class_table_ref(LevelView L, const double* __restrict__ sym,
+                                                         double* __restrict__ table, int* __restrict__ ok) {
+  const int k = blockIdx.x, c = threadIdx.x;
+  const RegionGeo R = L.regs[k];
+  const bool big = R.ex >= 5 && R.ey >= 5 && R.ez >= 5;
+  if (c == 0) ok[k] = big ? 1 : 0;
+  if (c >= kClasses) return;
+  const int x = class_node(c % 5, R.ex), y = class_node(c / 5 % 5, R.ey), z = class_node(c / 25, R.ez);
+  double* out = table + ((int64_t)k * kClasses + c) * kClassPts;
+  for (int s = 0; s < kClassPts; ++s) out[s] = big ? read_coupling(R, sym, x, y, z, s) : 0.0;
+}
+
+// One thread per node: a coupling that differs from its class's clears the region's flag.
+__global__ __launch_bounds__(kBlock) void k_class_table_check(LevelView L, const double* __restrict__ sym,
+                                                              const double* __restrict__ table, int* __restrict__ ok) {
   const BlockDesc bd = L.blocks[blockIdx.x];
   const RegionGeo R = L.regs[bd.region];
   const int li = bd.start + (int)threadIdx.x;
-  if (li >= R.n) return;
+  if (li >= R.n || !ok[bd.region]) return;
   int x, y, z;
   decompose(R, li, x, y, z);
-  // Faces whose box may reach one node further out: on face (axis a, side) every node of the
-  // layer one node in (the other coordinates in [2, extent - 2)) carries the table in all its
-  // upper couplings, and every node on the face in the couplings pointing inwards (into that layer).
-  // Where faces meet, k_sym_table_box checks the box they make together.
-  {
-    const int c[3] = {x, y, z}, e[3] = {R.ex, R.ey, R.ez};
-    const int64_t gi0 = R.off + li;
-    for (int a = 0; a < 3; ++a)
-      for (int side = 0; side < 2; ++side) {
-        const int in1 = side ? e[a] - 2 : 1, out0 = side ? e[a] - 1 : 0;
-        bool others = true;  // the box's rows on this face lie inside the base box's range
-        for (int b = 0; b < 3; ++b)
-          if (b != a) others = others && c[b] >= 2 && c[b] < e[b] - 2;
-        bool same = true;
-        if (c[a] == in1 && others) {
-          for (int s = 0; s < kSymPts; ++s) same = same && same_bits(sym[coef_index(gi0, s, kSymPts)], table[bd.region * kSymPts + s]);
-        } else if (c[a] == out0) {
-          for (int s = 0; s < kSymPts; ++s) {
-            int d[3];
-            stencil_offset<27>(13 + s, d[0], d[1], d[2]);
-            if (d[a] != (side ? -1 : 1)) continue;
-            same = same && same_bits(sym[coef_index(gi0, s, kSymPts)], table[bd.region * kSymPts + s]);
-          }
-        }
-        if (!same) face[bd.region * 6 + 2 * a + side] = 0;
-      }
-  }
-  auto deep = [&](int a, int b, int c) {
-    return a >= 2 && a < R.ex - 2 && b >= 2 && b < R.ey - 2 && c >= 2 && c < R.ez - 2;
-  };
-  const bool layer1 = x >= 1 && x < R.ex - 1 && y >= 1 && y < R.ey - 1 && z >= 1 && z < R.ez - 1 && !deep(x, y, z);
-  if (!deep(x, y, z) && !layer1) return;
-  const int64_t gi = R.off + li;
+  const int c = (axis_class(z, R.ez) * 5 + axis_class(y, R.ey)) * 5 + axis_class(x, R.ex);
+  const double* ref = table + ((int64_t)bd.region * kClasses + c) * kClassPts;
   bool same = true;
-  for (int s = 0; s < kSymPts; ++s) {
-    int dx, dy, dz;
-    stencil_offset<27>(13 + s, dx, dy, dz);
-    if (layer1 && !deep(x + dx, y + dy, z + dz)) continue;  // couplings that no deep node reads
-    same = same && same_bits(sym[coef_index(gi, s, kSymPts)], table[bd.region * kSymPts + s]);
-  }
+  for (int s = 0; s < kClassPts; ++s) same = same && same_bits(read_coupling(R, sym, x, y, z, s), ref[s]);
   if (!same) ok[bd.region] = 0;
 }
 
-// The exact condition for a region's candidate deep box B: every node in B outside [2, e - 2)^3
-// carries the table in all its upper couplings, and every node outside B does in each upper
-// coupling towards a node of B.  A failure clears the region's flag (its box falls back to
-// [2, e - 2)^3, which k_sym_table_check verified).
-template <class C>
-__global__ __launch_bounds__(kBlock) void k_sym_table_box(LevelView L, const C* __restrict__ sym,
-                                                          const C* __restrict__ table, const DeepBox* __restrict__ boxes,
-                                                          int* __restrict__ good) {
-  const BlockDesc bd = L.blocks[blockIdx.x];
-  const RegionGeo R = L.regs[bd.region];
-  const int li = bd.start + (int)threadIdx.x;
-  if (li >= R.n || !good[bd.region]) return;
-  const DeepBox B = boxes[bd.region];
-  int x, y, z;
-  decompose(R, li, x, y, z);
-  auto in = [&](int a, int b, int c) {
-    return a >= B.lo[0] && a < B.hi[0] && b >= B.lo[1] && b < B.hi[1] && c >= B.lo[2] && c < B.hi[2];
-  };
-  const bool base = x >= 2 && x < R.ex - 2 && y >= 2 && y < R.ey - 2 && z >= 2 && z < R.ez - 2;
-  const bool mine = in(x, y, z);
-  if (mine && base) return;  // checked against the table already
-  const int64_t gi = R.off + li;
-  bool same = true;
-  for (int s = 0; s < kSymPts; ++s) {
-    int dx, dy, dz;
-    stencil_offset<27>(13 + s, dx, dy, dz);
-    if (!mine && !in(x + dx, y + dy, z + dz)) continue;
-    same = same && same_bits(sym[coef_index(gi, s, kSymPts)], table[bd.region * kSymPts + s]);
-  }
-  if (!same) good[bd.region] = 0;
-}
-
-// Packed upper couplings of the served regions' x-face nodes (the shell nodes of the deep box's
-// rows: x outside [B.lo, B.hi) with y and z inside), in the order (z, y, x slot) from xoff[region]:
-// one thread per node.
-__global__ __launch_bounds__(kBlock) void k_pack_xface(LevelView L, const DeepBox* __restrict__ boxes,
-                                                       const int64_t* __restrict__ xoff,
-                                                       const double* __restrict__ sym, double* __restrict__ packed) {
-  const int k = blockIdx.y;
-  const RegionGeo R = L.regs[k];
-  const DeepBox B = boxes[k];
-  const int64_t n = xoff[k + 1] - xoff[k];
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
-  const int nxr = B.lo[0] + R.ex - B.hi[0], rows = B.hi[1] - B.lo[1];
-  const int rz = (int)(j / ((int64_t)nxr * rows)), r = (int)(j - (int64_t)rz * nxr * rows);
-  const int row = r / nxr, px = r - row * nxr;
-  const int y = B.lo[1] + row, z = B.lo[2] + rz;
-  const int x = px < B.lo[0] ? px : B.hi[0] + px - B.lo[0];
-  const int64_t gi = R.off + ((int64_t)z * R.ey + y) * R.ex + x;
-  for (int s = 0; s < kSymPts; ++s) packed[coef_index(xoff[k] + j, s, kSymPts)] = sym[coef_index(gi, s, kSymPts)];
-}
-
-template <class C>
-static void make_sym_table(Level& L, hipStream_t st) {
-  DBuf& tab = L.sym_table;
-  DBuf& ok = L.sym_table_ok;
-  const C* sym = static_cast<const C*>(L.coef_sym.p);
-  tab.alloc(sizeof(C) * kSymPts * L.nreg);
+static void make_class_table(Level& L, hipStream_t st) {
+  DBuf& tab = L.class_table;
+  DBuf& ok = L.class_table_ok;
+  const double* sym = static_cast<const double*>(L.coef_sym.p);
+  tab.alloc(sizeof(double) * kClasses * kClassPts * L.nreg);
   ok.alloc(sizeof(int) * L.nreg);
-  L.sym_table_face.alloc(sizeof(int) * 6 * L.nreg);
-  RMG_LAUNCH((k_sym_table_ref<C>), dim3(L.nreg), dim3(64), 0, st, L.view(), sym, tab.as<C>(), ok.as<int>(),
-             L.sym_table_face.as<int>());
-  RMG_LAUNCH((k_sym_table_check<C>), dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
-                     static_cast<const C*>(tab.p), ok.as<int>(), L.sym_table_face.as<int>());
+  RMG_LAUNCH(k_class_table_ref, dim3(L.nreg), dim3(128), 0, st, L.view(), sym, tab.as<double>(), ok.as<int>());
+  RMG_LAUNCH(k_class_table_check, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
+             static_cast<const double*>(tab.p), ok.as<int>());
   LAUNCH_CHECK();
-  // no region served: drop the table, so the kernel without it runs
-  std::vector<int> flags(L.nreg), faces(6 * L.nreg);
+  std::vector<int> flags(L.nreg);
   RMG_HIP(hipMemcpyAsync(flags.data(), ok.p, sizeof(int) * L.nreg, hipMemcpyDeviceToHost, st));
-  RMG_HIP(hipMemcpyAsync(faces.data(), L.sym_table_face.p, sizeof(int) * 6 * L.nreg, hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));
-  L.sym_table_face.release();
-  // deep boxes: two nodes inside, one where the face allows it; where faces meet, the box they
-  // make together is checked as a whole, else the region keeps the two-node box
-  std::vector<DeepBox> boxes(L.nreg);
-  std::vector<int> widened(L.nreg, 0);
-  for (int k = 0; k < L.nreg; ++k) {
-    const RegionGeo& R = L.regs[k];
-    const int e[3] = {R.ex, R.ey, R.ez};
-    for (int a = 0; a < 3; ++a) {
-      const bool lo1 = flags[k] && faces[6 * k + 2 * a], hi1 = flags[k] && faces[6 * k + 2 * a + 1];
-      boxes[k].lo[a] = lo1 ? 1 : 2;
-      boxes[k].hi[a] = hi1 ? e[a] - 1 : e[a] - 2;
-      widened[k] = widened[k] || lo1 || hi1;
-    }
-  }
-  bool any_wide = false;
-  for (int w : widened) any_wide = any_wide || w;
-  if (any_wide) {
-    DBuf dbox, dgood;
-    dbox.alloc(sizeof(DeepBox) * L.nreg);
-    dgood.alloc(sizeof(int) * L.nreg);
-    RMG_HIP(hipMemcpyAsync(dbox.p, boxes.data(), sizeof(DeepBox) * L.nreg, hipMemcpyHostToDevice, st));
-    RMG_HIP(hipMemcpyAsync(dgood.p, widened.data(), sizeof(int) * L.nreg, hipMemcpyHostToDevice, st));
-    RMG_LAUNCH((k_sym_table_box<C>), dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
-               static_cast<const C*>(tab.p), dbox.as<DeepBox>(), dgood.as<int>());
-    LAUNCH_CHECK();
-    std::vector<int> good(L.nreg);
-    RMG_HIP(hipMemcpyAsync(good.data(), dgood.p, sizeof(int) * L.nreg, hipMemcpyDeviceToHost, st));
-    RMG_HIP(hipStreamSynchronize(st));
-    for (int k = 0; k < L.nreg; ++k)
-      if (widened[k] && !good[k]) {
-        const RegionGeo& R = L.regs[k];
-        const int e[3] = {R.ex, R.ey, R.ez};
-        for (int a = 0; a < 3; ++a) {
-          boxes[k].lo[a] = 2;
-          boxes[k].hi[a] = e[a] - 2;
-        }
-      }
-  }
   int served = 0;
   for (int f : flags) served += f != 0;
-  if (served == 0) {
+  if (served == 0) {  // no region served: drop the tables, so the streaming kernel runs
     tab.release();
     ok.release();
     clear_split(L);
   } else {
-    make_split(L, flags, boxes);
-    const int64_t nx = L.xface_off.back();
-    if (nx > 0) {
-      int64_t most = 0;
-      for (int k = 0; k < L.nreg; ++k) most = std::max(most, L.xface_off[k + 1] - L.xface_off[k]);
-      L.xface_coef.alloc(sizeof(double) * coef_elems(nx, kSymPts));
-      RMG_LAUNCH(k_pack_xface, dim3(cdiv(most, kBlock), L.nreg), dim3(kBlock), 0, st, L.view(),
-                 L.d_deep_box.as<DeepBox>(), L.d_xface_off.as<int64_t>(), static_cast<const double*>(L.coef_sym.p),
-                 L.xface_coef.as<double>());
-      LAUNCH_CHECK();
-    }
+    make_split(L, flags);
   }
 }
 
@@ -1765,8 +1635,8 @@ bool launch_make_sym(Level& L, bool lowp, hipStream_t st, bool table) {
   DBuf& out = lowp ? L.coef_lo_sym : L.coef_sym;
   out.release();
   if (!lowp) {
-    L.sym_table.release();
-    L.sym_table_ok.release();
+    L.class_table.release();
+    L.class_table_ok.release();
     clear_split(L);
   }
   if (L.dim != 3 || L.npts != 27) return false;
@@ -1786,7 +1656,7 @@ bool launch_make_sym(Level& L, bool lowp, hipStream_t st, bool table) {
   RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));
   if (hflag) out.release();
-  else if (table && L.ndof == 1) make_sym_table<double>(L, st);
+  else if (table && L.ndof == 1) make_class_table(L, st);
   return hflag == 0;
 }
 

@@ -193,15 +193,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
 // streams its node's 14 couplings once and leaves the ones its neighbours need in LDS: the
 // couplings towards z+1 for the next plane, the in-plane ones for this plane.  Only neighbours
 // outside the tile (its edge rows, and plane z-1 of the tile's first plane) are read from memory,
-// so HBM carries about 14 instead of 27 coefficients per node.  TAB: with the region table (the
-// region's flag set), a node two or more nodes inside its region takes its 14 couplings
-// from the table, which equals every such node's stored ones bit for bit, and the memory read is
-// skipped; neighbours read from memory are served the same way.
+// so HBM carries about 14 instead of 27 coefficients per node.
 // NT threads per block (the level's tile_threads); tiles hold at most NT nodes.
-template <int NT, class V, class C, StencilOp OP, bool DOT, bool SYM, bool TAB = false>
+template <int NT, class V, class C, StencilOp OP, bool DOT, bool SYM>
 __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __restrict__ tiles, int ntiles,
                                                   const C* __restrict__ coef, const float* __restrict__ centre,
-                                                  const C* __restrict__ table, const int* __restrict__ table_ok,
                                                   OpP<V> p, double* __restrict__ partials) {
   constexpr int kT3 = NT;
   constexpr int kT3Plane = tile_plane_cap(NT);
@@ -304,29 +300,13 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
         auto in_tile = [&](int dx, int dy) {
           return (unsigned)(tx + dx) < (unsigned)T.tx && (unsigned)(ty + dy) < (unsigned)T.ty;
         };
-        bool rtab = false;
-        const C* __restrict__ tab = nullptr;
-        if constexpr (TAB) {
-          rtab = table_ok[T.region] != 0;
-          tab = table + T.region * kSymPts;
-        }
-        auto deep = [&](int xx, int yy, int z2) {
-          if constexpr (!TAB) return false;
-          return rtab && xx >= 2 && xx < R.ex - 2 && yy >= 2 && yy < R.ey - 2 && z2 >= 2 && z2 < R.ez - 2;
-        };
-        auto mirror = [&](int s, int dx, int dy, int dz) {  // A(i + offset(s), i) from the table or memory
-          if (deep(x + dx, y + dy, zz + dz)) return (V)CoefLoad<C>::get(tab + 13 - s);
+        auto mirror = [&](int s, int dx, int dy, int dz) {  // A(i + offset(s), i) from memory
           return (V)CoefLoad<C>::get(coef + coef_index(gi + dx + dy * sy + dz * sz, 13 - s, kSymPts));
         };
         if (active) {
-          if (deep(x, y, zz)) {
+          const C* __restrict__ cf = coef + coef_index(gi, 0, kSymPts);
 #pragma unroll
-            for (int k = 0; k < kSymPts; ++k) up[k] = (V)CoefLoad<C>::get(tab + k);
-          } else {
-            const C* __restrict__ cf = coef + coef_index(gi, 0, kSymPts);
-#pragma unroll
-            for (int k = 0; k < kSymPts; ++k) up[k] = (V)CoefLoad<C>::get(cf + k * kTile);
-          }
+          for (int k = 0; k < kSymPts; ++k) up[k] = (V)CoefLoad<C>::get(cf + k * kTile);
 #pragma unroll
           for (int s = 0; s < 9; ++s) {  // z-1: the neighbour's coupling towards z+1
             const int dx = s % 3 - 1, dy = s / 3 - 1;
@@ -406,112 +386,187 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
   }
 }
 
-// ------------------------------------------ region-table split: deep tiles and the shell
-// A region whose nodes two or more nodes inside it all carry the region table's couplings (bit
-// for bit, checked at setup) is split into its deep box [2, e-2)^3, run by k_stencil_deep, and its
-// outer two layers (the shell), run by k_stencil_shell.  Every node's 27 products are summed in
-// the order of k_stencil3d's symmetric path (the upper couplings s = 13..26, then the lower ones
-// s = 0..12), so the results are those of streaming every coupling bit for bit.
+// ------------------------------------------------------- region-table tiles
+__device__ __forceinline__ int axis_class_of(int v, int e) { return v < 2 ? v : (v >= e - 2 ? v - e + 5 : 2); }
 
-// Deep tiles: ty rows of tx deep nodes, nz planes, all inside the deep box, so every neighbour
-// lies inside the region and no node is shared.  Couplings come from the region's table (uniform
-// per tile: scalar loads); no coefficient is streamed.  The input vector's planes pass through two
-// LDS slots as in k_stencil3d; b and the old direction are read a plane ahead.
-template <int NT, StencilOp OP, bool DOT>
-__global__ __launch_bounds__(NT) void k_stencil_deep(LevelView L, const Tile3* __restrict__ tiles,
-                                                     const double* __restrict__ table, OpP<double> p,
-                                                     double* __restrict__ partials) {
-  constexpr int kPlane = tile_plane_cap(NT);
-  constexpr int kFetch = (kPlane + NT - 1) / NT;
+// Whole-region tiles of a region served by its class tables: ty full x-rows, nz planes.  The lanes
+// of the rows' inner nodes (x in [2, ex - 2)) come first, padded to whole wavefronts, then the rows'
+// four x-face nodes.  A node's couplings are its class's (scalar loads from the region's table): a
+// wavefront takes the classes of its nodes one after the other, so one whose nodes share a class
+// (every inner wavefront away from the y-faces) runs one pass.  No coupling is read per node.  The
+// input vector's planes, whole rows with their halo, pass through two LDS slots; each plane is
+// fetched four planes ahead into registers and b and d two planes ahead, so that two planes' loads
+// are in flight while one is computed.  Consecutive blocks are dealt to the eight XCDs in turn, so
+// the blocks are mapped to tiles such that every XCD runs a contiguous run of tiles and neighbouring
+// tiles share their halo rows through its L2.  Every node sums its 27 products in k_stencil3d's
+// order with one rounding each, so the results are those of streaming every coupling bit for bit.
+template <StencilOp OP, bool DOT>
+__global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, const Tile3* __restrict__ tiles,
+                                                                 const double* __restrict__ table, OpP<double> p,
+                                                                 double* __restrict__ partials) {
+  constexpr int NT = kTableThreads;
+  constexpr int kPlane = 2 * NT;  // a tile's rows with their halo: two loads per lane (make_split)
+  constexpr int kFetch = 2;
   constexpr bool kPreB = OP == StencilOp::Residual || OP == StencilOp::ResidualScaled || OP == StencilOp::Cheb ||
                          OP == StencilOp::ChebFirst;
   constexpr bool kPreD = OP == StencilOp::Cheb;
+  constexpr int kXcds = 8;
+  constexpr int kXRows = 4 * kTableRows;  // x-face lanes: four a row
   __shared__ double pl[2][kPlane];
-  const Tile3 T = tiles[blockIdx.x];
+  __shared__ double xt[5][kClassPts][kXRows];  // the x-face lanes' couplings by z class
+  const int nb = (int)gridDim.x, xcd = (int)blockIdx.x % kXcds, q = nb / kXcds, rem = nb % kXcds;
+  const int ti = xcd * q + min(xcd, rem) + (int)blockIdx.x / kXcds;
+  const Tile3 T = tiles[ti];
   const RegionGeo R = L.regs[T.region];
+  const double* __restrict__ tab = table + (int64_t)T.region * kClasses * kClassPts;
   const int t = threadIdx.x;
-  const int W = T.tx + 2, PL = (T.ty + 2) * W;
-  const int ty = t / T.tx, tx = t - ty * T.tx;
-  const bool active = ty < T.ty;
-  const int x = T.x0 + tx, y = T.y0 + ty;
+  // lane -> (row, x): inner-x lanes, padded to a wavefront boundary, then x-face lanes
+  const int dxw = R.ex - 4, ndl = T.ty * dxw, pad = (ndl + 63) & ~63;
+  int row = 0, x = 0;
+  bool active = false;
+  if (t < ndl) {
+    row = t / dxw;
+    x = 2 + t - row * dxw;
+    active = true;
+  } else if (t >= pad && t < pad + 4 * T.ty) {
+    const int u = t - pad;
+    row = u >> 2;
+    x = (u & 3) < 2 ? (u & 3) : R.ex - 4 + (u & 3);
+    active = true;
+  }
+  const int y = T.y0 + row;
+  const int cxy = axis_class_of(y, R.ey) * 5 + axis_class_of(x, R.ex);
+  const int W = R.ex + 2, PL = (T.ty + 2) * W;
   const int sy = R.ex, sz = R.ex * R.ey;
   const double* __restrict__ xr = p.x + R.off;
-  double tab[kSymPts];
-#pragma unroll
-  for (int k = 0; k < kSymPts; ++k) tab[k] = table[T.region * kSymPts + k];
-  double pre[kFetch];
-  auto fetch = [&](int zz) {
+  // Loads are issued unconditionally (out-of-range positions read a valid element and are zeroed
+  // when stored), so that the compiler counts the loads in flight exactly and waits only for the
+  // plane it needs.
+  auto fetch = [&](int zz, double(&pre)[kFetch]) {
+    const int zc = min(max(zz, 0), R.ez - 1);
 #pragma unroll
     for (int k = 0; k < kFetch; ++k) {
-      const int idx = t + k * NT;
-      double v = 0.0;
-      if (idx < PL) {
-        const int r = idx / W;
-        v = xr[(int64_t)zz * sz + (int64_t)(T.y0 - 1 + r) * sy + (T.x0 - 1 + idx - r * W)];
-      }
-      pre[k] = v;
+      const int idx = min(t + k * NT, PL - 1);
+      const int r = idx / W;
+      const int xx = min(max(idx - r * W - 1, 0), R.ex - 1), yy = min(max(T.y0 - 1 + r, 0), R.ey - 1);
+      pre[k] = xr[(int64_t)zc * sz + (int64_t)yy * sy + xx];
     }
   };
-  auto store = [&](int slot) {
+  auto store = [&](int slot, int zz, const double(&pre)[kFetch]) {
 #pragma unroll
     for (int k = 0; k < kFetch; ++k) {
       const int idx = t + k * NT;
-      if (idx < PL) pl[slot][idx] = pre[k];
+      if (idx < PL) {
+        const int r = idx / W;
+        const int xx = idx - r * W - 1, yy = T.y0 - 1 + r;
+        const bool in = (unsigned)zz < (unsigned)R.ez && (unsigned)yy < (unsigned)R.ey && (unsigned)xx < (unsigned)R.ex;
+        pl[slot][idx] = in ? pre[k] : 0.0;
+      }
     }
   };
   double rm[9], rc[9], rp[9];
   auto readn = [&](int slot, double* r) {
 #pragma unroll
-    for (int j = 0; j < 9; ++j) r[j] = pl[slot][(ty + 1 + j / 3 - 1) * W + tx + 1 + j % 3 - 1];
+    for (int j = 0; j < 9; ++j) r[j] = pl[slot][(row + j / 3) * W + x + j % 3];
   };
   const int z0 = T.z0, z1 = T.z0 + T.nz;
-  double nb = 0.0, nd = 0.0;
-  auto load_bd = [&](int z2) {
-    if (active && z2 < z1) {
-      const int64_t g = R.off + (int64_t)z2 * sz + (int64_t)y * sy + x;
-      if constexpr (kPreB) nb = p.b[g];
-      if constexpr (kPreD) nd = p.d[g];
-    }
+  auto load_bd = [&](int z2, double& b2, double& d2) {  // inactive lanes and planes past the tile: a valid node
+    const int64_t g = R.off + (int64_t)min(z2, z1 - 1) * sz + (int64_t)y * sy + x;
+    if constexpr (kPreB) b2 = p.b[g];
+    if constexpr (kPreD) d2 = p.d[g];
   };
-  load_bd(z0);
-  fetch(z0 - 1);
-  store(0);
-  fetch(z0);
-  store(1);
+  for (int e = t; e < 5 * kClassPts * kXRows; e += NT) {  // couplings of the x-face lanes' classes
+    const int u = e % kXRows, s2 = e / kXRows % kClassPts, cz = e / (kXRows * kClassPts);
+    const int yu = min(T.y0 + (u >> 2), R.ey - 1), xu = (u & 3) < 2 ? (u & 3) : R.ex - 4 + (u & 3);
+    xt[cz][s2][u] = tab[((cz * 5 + axis_class_of(yu, R.ey)) * 5 + axis_class_of(xu, R.ex)) * kClassPts + s2];
+  }
+  double preA[kFetch], preB[kFetch];
+  double nbA = 0.0, ndA = 0.0, nbB = 0.0, ndB = 0.0;
+  load_bd(z0, nbA, ndA);
+  load_bd(z0 + 1, nbB, ndB);
+  fetch(z0 - 1, preA);
+  fetch(z0, preB);
+  store(0, z0 - 1, preA);
+  store(1, z0, preB);
   __syncthreads();
   if (active) {
     readn(0, rm);
     readn(1, rc);
   }
   __syncthreads();
-  fetch(z0 + 1);
-  store(0);
+  fetch(z0 + 1, preA);
+  store(0, z0 + 1, preA);
+  fetch(z0 + 2, preA);
+  fetch(z0 + 3, preB);
   __syncthreads();
   double contrib = 0.0;
-  for (int zz = z0; zz < z1; ++zz) {
+  // one plane: its products from LDS (plane zz + 1) and registers (zz - 1, zz); plane zz + 2 goes
+  // to LDS from the registers that fetched it two planes ago, which then fetch plane zz + 4
+  // (past the tile's last plane it only keeps the loads in step: see the loop below)
+  auto plane = [&](int zz, double(&pre)[kFetch], double& b2, double& d2) {
     const int sp = (zz - z0) & 1;  // slot holding plane zz + 1
-    const double cb = nb, cd = nd;
-    load_bd(zz + 1);
-    if (active) readn(sp, rp);
-    if (zz + 2 <= z1) fetch(zz + 2);
-    if (active) {
-      double acc = 0.0;
-      // one rounding per product, as the contracted sums of the tiled kernels
+    const bool work = active && zz < z1;
+    if (work) readn(sp, rp);
+    if (zz + 2 <= z1) store(sp ^ 1, zz + 2, pre);  // plane zz + 2 replaces plane zz
+    fetch(zz + 4, pre);
+    const double cb = b2, cd = d2;
+    load_bd(zz + 2, b2, d2);
+    if (work) {
+      const int cls = axis_class_of(zz, R.ez) * 25 + cxy;
+      double acc = 0.0, ctr = 0.0;
+      if (t >= pad) {
+        // the x-face wavefront (four classes a row): each lane reads its class's couplings from
+        // the block's copy in LDS, nine at a time (the empty asm keeps the chunks' reads apart)
+        const double* __restrict__ xc = &xt[axis_class_of(zz, R.ez)][0][t - pad];
+        auto chunk = [&](int s0) {
+          double cf[9];
 #pragma unroll
-      for (int s = 13; s < 27; ++s) acc = fma(tab[s - 13], s < 18 ? rc[s % 9] : rp[s % 9], acc);
+          for (int k = 0; k < 9; ++k) cf[k] = xc[((s0 + k) % 27) * kXRows];
 #pragma unroll
-      for (int s = 0; s < 13; ++s) acc = fma(tab[13 - s], s < 9 ? rm[s] : rc[s % 9], acc);
+          for (int k = 0; k < 9; ++k) {
+            const int s = (s0 + k) % 27;
+            acc = fma(cf[k], s >= 18 ? rp[s % 9] : (s >= 9 ? rc[s % 9] : rm[s]), acc);
+          }
+          __asm__ volatile("" ::: "memory");
+        };
+        chunk(13);
+        chunk(22);
+        chunk(4);
+        ctr = xc[13 * kXRows];
+      } else {
+        for (;;) {  // the classes of this wavefront's nodes, one after the other
+          const int c = __builtin_amdgcn_readfirstlane(cls);
+          int cu = c;  // the same class, in a scalar register the compiler cannot trade for cls below,
+          __asm__ volatile("" : "+s"(cu));  // so that the table is read with scalar loads
+          if (cls == c) {
+            const double* __restrict__ tc = tab + cu * kClassPts;
+#pragma unroll
+            for (int s = 13; s < 27; ++s) acc = fma(tc[s], s < 18 ? rc[s % 9] : rp[s % 9], acc);
+#pragma unroll
+            for (int s = 0; s < 13; ++s) acc = fma(tc[s], s < 9 ? rm[s] : rc[s % 9], acc);
+            ctr = tc[13];
+            break;
+          }
+        }
+      }
       const int64_t gi = R.off + (int64_t)zz * sz + (int64_t)y * sy + x;
-      if constexpr (kPreB) contrib += finish_pre<OP, DOT, double, true>(p, gi, acc, 1, rc[4], tab[0], cb, cd);
-      else contrib += finish<OP, DOT, double, true>(p, gi, acc, 1, rc[4], tab[0]);
+      const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
+      if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
+      else if constexpr (kPreB) contrib += finish_pre<OP, DOT, double, true>(p, gi, acc, 1, rc[4], ctr, cb, cd);
+      else contrib += finish<OP, DOT, double, true>(p, gi, acc, 1, rc[4], ctr);
     }
-    if (zz + 2 <= z1) store(sp ^ 1);  // plane zz + 2 replaces plane zz
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
       rm[j] = rc[j];
       rc[j] = rp[j];
     }
     __syncthreads();
+  };
+  // Both halves run on every pass, also past the last plane, so that every pass issues the same
+  // loads and the compiler's count of loads in flight stays exact around the loop.
+  for (int zz = z0; zz < z1; zz += 2) {
+    plane(zz, preA, nbA, ndA);
+    plane(zz + 1, preB, nbB, ndB);
   }
   if constexpr (DOT || OP == StencilOp::CgQ) {
     double v = contrib;
@@ -524,115 +579,6 @@ __global__ __launch_bounds__(NT) void k_stencil_deep(LevelView L, const Tile3* _
       for (int i = 0; i < NT / 64; ++i) s += sm[i];
       partials[blockIdx.x] = s;
     }
-  }
-}
-
-// Node of a table region's shell (the nodes outside its deep box B) from its index j in the region's
-// shell enumeration: the planes z < B.lo[2] and z >= B.hi[2] (x fastest), then for z in the box the
-// rows y < B.lo[1] and y >= B.hi[1], then for y and z in the box the nodes x < B.lo[0] and
-// x >= B.hi[0] (the x-face nodes, a few per row, rows in order).
-__device__ __forceinline__ void shell_node(const RegionGeo& R, const DeepBox& B, int j, int& x, int& y, int& z) {
-  const int nzl = B.lo[2], nyl = B.lo[1], nxl = B.lo[0];
-  const int rows_y = nyl + R.ey - B.hi[1], nxr = nxl + R.ex - B.hi[0];
-  const int dy = B.hi[1] - B.lo[1], dz = B.hi[2] - B.lo[2];
-  const int nz = (nzl + R.ez - B.hi[2]) * R.ex * R.ey, ny = rows_y * R.ex * dz;
-  if (j < nz) {
-    const int pz = j / (R.ex * R.ey), r = j - pz * R.ex * R.ey;
-    z = pz < nzl ? pz : B.hi[2] + pz - nzl;
-    y = r / R.ex;
-    x = r - y * R.ex;
-  } else if (j < nz + ny) {
-    j -= nz;
-    const int rz = j / (rows_y * R.ex), r = j - rz * rows_y * R.ex;
-    const int py = r / R.ex;
-    z = B.lo[2] + rz;
-    y = py < nyl ? py : B.hi[1] + py - nyl;
-    x = r - py * R.ex;
-  } else {
-    j -= nz + ny;
-    const int rz = j / (nxr * dy), r = j - rz * nxr * dy;
-    const int row = r / nxr, px = r - row * nxr;
-    z = B.lo[2] + rz;
-    y = B.lo[1] + row;
-    x = px < nxl ? px : B.hi[0] + px - nxl;
-    (void)dz;
-  }
-}
-
-// One thread per shell node of a table region (blocks of kBlock consecutive shell nodes of one
-// region; BlockDesc.start is the first shell index).  A node's own upper couplings are streamed;
-// a lower coupling A(i, i+s) is the neighbour's upper coupling at 26 - s, from the table when the
-// neighbour is deep, else from its record; neighbour values come through the cache.
-template <StencilOp OP, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_stencil_shell(LevelView L, const BlockDesc* __restrict__ blocks,
-                                                          const DeepBox* __restrict__ boxes,
-                                                          const double* __restrict__ coef,
-                                                          const double* __restrict__ table,
-                                                          const int64_t* __restrict__ xoff,
-                                                          const double* __restrict__ xcoef, OpP<double> p,
-                                                          double* __restrict__ partials) {
-  const BlockDesc bd = blocks[blockIdx.x];
-  const RegionGeo R = L.regs[bd.region];
-  const DeepBox B = boxes[bd.region];
-  const int j = bd.start + (int)threadIdx.x;
-  const int nshell = R.n - (B.hi[0] - B.lo[0]) * (B.hi[1] - B.lo[1]) * (B.hi[2] - B.lo[2]);
-  double contrib = 0.0;
-  if (j < nshell) {
-    int x, y, z;
-    shell_node(R, B, j, x, y, z);
-    const int sy = R.ex, sz = R.ex * R.ey;
-    const int li = z * sz + y * sy + x;
-    const int64_t gi = R.off + li;
-    const double* __restrict__ xr = p.x + R.off;
-    const double* __restrict__ tab = table + bd.region * kSymPts;
-    const int64_t x0 = xoff[bd.region];
-    auto inbox = [&](int dx, int dy, int dz) {
-      return (unsigned)(x + dx) < (unsigned)R.ex && (unsigned)(y + dy) < (unsigned)R.ey &&
-             (unsigned)(z + dz) < (unsigned)R.ez;
-    };
-    auto deep = [&](int xx, int yy, int zz) {
-      return xx >= B.lo[0] && xx < B.hi[0] && yy >= B.lo[1] && yy < B.hi[1] && zz >= B.lo[2] && zz < B.hi[2];
-    };
-    // packed index of an x-face node (a shell node of a deep row), or -1
-    const int nxr = B.lo[0] + R.ex - B.hi[0];
-    auto xface = [&](int xx, int yy, int zz) -> int64_t {
-      if (yy < B.lo[1] || yy >= B.hi[1] || zz < B.lo[2] || zz >= B.hi[2]) return -1;
-      const int px = xx < B.lo[0] ? xx : (xx >= B.hi[0] ? B.lo[0] + xx - B.hi[0] : -1);
-      if (px < 0) return -1;
-      return x0 + ((int64_t)(zz - B.lo[2]) * (B.hi[1] - B.lo[1]) + (yy - B.lo[1])) * nxr + px;
-    };
-    // upper coupling k of a non-deep node (regional index ln, coordinates xx, yy, zz)
-    auto upper = [&](int k, int ln, int xx, int yy, int zz) {
-      const int64_t q = xface(xx, yy, zz);
-      return q >= 0 ? xcoef[coef_index(q, k, kSymPts)] : coef[coef_index(R.off + ln, k, kSymPts)];
-    };
-    double acc = 0.0, ctr = 0.0;
-#pragma unroll
-    for (int s = 13; s < 27; ++s) {
-      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
-      const double c = upper(s - 13, li, x, y, z);
-      const double v = inbox(dx, dy, dz) ? xr[li + dx + dy * sy + dz * sz] : 0.0;
-      if (s == 13) ctr = c;
-      acc = fma(c, v, acc);  // each product added with one rounding, as the tiled kernels do
-    }
-#pragma unroll
-    for (int s = 0; s < 13; ++s) {
-      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
-      double c = 0.0, v = 0.0;
-      if (inbox(dx, dy, dz)) {
-        const int ln = li + dx + dy * sy + dz * sz;
-        c = deep(x + dx, y + dy, z + dz) ? tab[13 - s] : upper(13 - s, ln, x + dx, y + dy, z + dz);
-        v = xr[ln];
-      }
-      acc = fma(c, v, acc);
-    }
-    const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || z == 0 || z == R.ez - 1;
-    if (edge && is_shared(L, R, x, y, z)) p.out[gi] = acc;  // finished by k_iface
-    else contrib += finish<OP, DOT, double, true>(p, gi, acc, 1, xr[li], ctr);
-  }
-  if constexpr (DOT || OP == StencilOp::CgQ) {
-    const double s = block_sum(contrib);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
   }
 }
 
@@ -685,50 +631,40 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
     if (tiled) {
       const C* sym = nullptr;
       const C* table = nullptr;
-      const int* table_ok = nullptr;
       if constexpr (std::is_same<V, C>::value) {
         sym = static_cast<const C*>(a.lowp ? L.coef_lo_sym.p : L.coef_sym.p);
-        // the region table serves the FP64 operator on 768-thread tiles
-        if (!a.lowp && L.tile_threads == kTileThreadsF64 && L.sym_table.p && L.sym_table_ok.p) {
-          table = static_cast<const C*>(L.sym_table.p);
-          table_ok = static_cast<const int*>(L.sym_table_ok.p);
-        }
+        // the class tables serve the FP64 operator on 768-thread tiles
+        if (!a.lowp && L.tile_threads == kTileThreadsF64 && L.class_table.p && L.class_table_ok.p)
+          table = static_cast<const C*>(L.class_table.p);
       }
       bool split = false;
       if constexpr (std::is_same<V, double>::value && std::is_same<C, double>::value) {
         if (table && sym && L.tile_threads == kTileThreadsF64) {
-          // region-table split: deep tiles, shell blocks, then the other regions' tiles, each with
-          // its own run of partial sums
-          const int64_t nd = (int64_t)L.deep_tiles.size(), ns = (int64_t)L.shell_blocks.size();
-          const int64_t no = (int64_t)L.other_tiles.size();
-          RMG_REQUIRE(L.table_served.size() == (size_t)L.nreg && (nd > 0 || ns > 0), RMG_ERR_ARG,
-                      "internal: region table without its split");
-          if (nd > 0)
-            RMG_LAUNCH((k_stencil_deep<kDeepThreads, OP, DOT>), dim3(nd), dim3(kDeepThreads), 0, st, v,
-                       L.d_deep_tiles.as<Tile3>(), table, p, a.partials);
-          if (ns > 0)
-            RMG_LAUNCH((k_stencil_shell<OP, DOT>), dim3(ns), dim3(kBlock), 0, st, v, L.d_shell_blocks.as<BlockDesc>(),
-                       L.d_deep_box.as<DeepBox>(), sym, table, L.d_xface_off.as<int64_t>(), L.xface_coef.as<double>(),
-                       p, a.partials ? a.partials + nd : nullptr);
+          // region-table split: the served regions' whole-region tiles, then the other regions'
+          // tiles, each with its own run of partial sums
+          const int64_t nd = (int64_t)L.table_tiles.size(), no = (int64_t)L.other_tiles.size();
+          RMG_REQUIRE(L.table_served.size() == (size_t)L.nreg && nd > 0, RMG_ERR_ARG,
+                      "internal: class tables without their split");
+          RMG_LAUNCH((k_stencil_table<OP, DOT>), dim3(nd), dim3(kTableThreads), 0, st, v, L.d_table_tiles.as<Tile3>(),
+                     table, p, a.partials);
           if (no > 0)
             RMG_LAUNCH((k_stencil3d<kTileThreadsF64, V, C, OP, DOT, true>), dim3(no), dim3(kTileThreadsF64), 0, st,
-                       v, L.d_other_tiles.as<Tile3>(), (int)no, sym, centre, nullptr, nullptr, p,
-                       a.partials ? a.partials + nd + ns : nullptr);
-          nparts = nd + ns + no;
+                       v, L.d_other_tiles.as<Tile3>(), (int)no, sym, centre, p,
+                       a.partials ? a.partials + nd : nullptr);
+          nparts = nd + no;
           split = true;
         }
       }
-      (void)table_ok;
       auto launch3d = [&](auto nt) {
         constexpr int NT = decltype(nt)::value;
         if (sym) {
           if constexpr (std::is_same<V, C>::value) {
             RMG_LAUNCH((k_stencil3d<NT, V, C, OP, DOT, true>), dim3(grid3), dim3(NT), 0, st, v,
-                               L.d_tiles.as<Tile3>(), ntiles, sym, centre, nullptr, nullptr, p, a.partials);
+                               L.d_tiles.as<Tile3>(), ntiles, sym, centre, p, a.partials);
           }
         } else {
           RMG_LAUNCH((k_stencil3d<NT, V, C, OP, DOT, false>), dim3(grid3), dim3(NT), 0, st, v,
-                             L.d_tiles.as<Tile3>(), ntiles, coef, centre, nullptr, nullptr, p, a.partials);
+                             L.d_tiles.as<Tile3>(), ntiles, coef, centre, p, a.partials);
         }
       };
       if (split) {

@@ -117,71 +117,54 @@ void make_tiles(Level& L, int depth) {
 
 void clear_split(Level& L) {
   L.table_served.clear();
-  L.deep_tiles.clear();
-  L.shell_blocks.clear();
+  L.table_tiles.clear();
   L.other_tiles.clear();
-  L.d_deep_tiles.release();
-  L.d_shell_blocks.release();
+  L.d_table_tiles.release();
   L.d_other_tiles.release();
-  L.xface_off.clear();
-  L.d_xface_off.release();
-  L.xface_coef.release();
-  L.deep_box.clear();
-  L.d_deep_box.release();
 }
 
-// Served regions (at least 5 nodes a side): the deep box in tiles of whole deep rows (kDeepThreads
-// nodes at most, rows shared out evenly) and kDeepPlanes-or-fewer planes (planes shared out evenly),
-// largest first; shell nodes in blocks of kBlock.
-void make_split(Level& L, const std::vector<int>& served, const std::vector<DeepBox>& boxes) {
+// Lanes of a table tile of ty rows of extent ex: the rows' inner x-nodes (x in [2, ex - 2)) padded
+// to whole wavefronts, then four x-face nodes per row.
+static int table_lanes(int ex, int ty) { return ((ty * (ex - 4) + 63) & ~63) + 4 * ty; }
+
+// Served regions (at least 5 nodes a side): whole-row tiles of ty rows, ty the most (at most
+// kTableRows) whose lanes fit kTableThreads and whose plane with its halo takes two loads per lane,
+// rows shared out evenly, and
+// at most kTablePlanes planes (planes shared out evenly), largest first.
+void make_split(Level& L, const std::vector<int>& served) {
   std::vector<int> keep = served;
-  std::vector<DeepBox> box = boxes;
   clear_split(L);
   L.table_served = keep;
-  L.deep_box = box;
-  L.xface_off.assign(L.nreg + 1, 0);
   for (int k = 0; k < L.nreg; ++k) {
     if (!keep[k]) continue;
     const RegionGeo& R = L.regs[k];
-    const DeepBox& B = box[k];
-    const int e[3] = {R.ex, R.ey, R.ez};
-    for (int a = 0; a < 3; ++a)
-      RMG_REQUIRE(B.lo[a] >= 1 && B.lo[a] <= 2 && B.hi[a] <= e[a] - 1 && B.hi[a] >= e[a] - 2 && B.hi[a] > B.lo[a],
-                  RMG_ERR_ARG, "internal: deep box outside one-to-two node faces");
-    const int dx = B.hi[0] - B.lo[0], dy = B.hi[1] - B.lo[1], dz = B.hi[2] - B.lo[2];
-    RMG_REQUIRE(dx <= kDeepThreads, RMG_ERR_ARG, "internal: deep row wider than a deep tile");
-    const int tymax = std::min(dy, kDeepThreads / dx);
-    const int nty = (dy + tymax - 1) / tymax;
-    const int ntz = (dz + kDeepPlanes - 1) / kDeepPlanes;
-    for (int iz = 0, z0 = B.lo[2]; iz < ntz; ++iz) {
-      const int nz = dz / ntz + (iz < dz % ntz ? 1 : 0);
-      for (int j = 0, y0 = B.lo[1]; j < nty; ++j) {
-        const int ty = dy / nty + (j < dy % nty ? 1 : 0);
-        L.deep_tiles.push_back(Tile3{k, B.lo[0], y0, z0, dx, ty, nz, 0});
+    RMG_REQUIRE(R.ex >= 5 && R.ey >= 5 && R.ez >= 5, RMG_ERR_ARG, "internal: table region under 5 nodes a side");
+    int tymax = 0;
+    while (tymax < std::min(R.ey, kTableRows) && table_lanes(R.ex, tymax + 1) <= kTableThreads &&
+           (R.ex + 2) * (tymax + 3) <= 2 * kTableThreads)
+      ++tymax;
+    RMG_REQUIRE(tymax >= 1, RMG_ERR_ARG, "internal: region row wider than a table tile");
+    const int nty = (R.ey + tymax - 1) / tymax;
+    const int ntz = (R.ez + kTablePlanes - 1) / kTablePlanes;
+    for (int iz = 0, z0 = 0; iz < ntz; ++iz) {
+      const int nz = R.ez / ntz + (iz < R.ez % ntz ? 1 : 0);
+      for (int j = 0, y0 = 0; j < nty; ++j) {
+        const int ty = R.ey / nty + (j < R.ey % nty ? 1 : 0);
+        L.table_tiles.push_back(Tile3{k, 0, y0, z0, R.ex, ty, nz, 0});
         y0 += ty;
       }
       z0 += nz;
     }
-    const int nshell = R.n - dx * dy * dz;
-    for (int start = 0; start < nshell; start += kBlock) L.shell_blocks.push_back(BlockDesc{k, start});
-    L.xface_off[k + 1] = (int64_t)(R.ex - dx) * dy * dz;  // shell nodes of the deep rows
   }
-  for (int k = 0; k < L.nreg; ++k) L.xface_off[k + 1] += L.xface_off[k];
-  upload(L.d_xface_off, L.xface_off);
-  upload(L.d_deep_box, L.deep_box);
-  std::stable_sort(L.deep_tiles.begin(), L.deep_tiles.end(), [](const Tile3& a, const Tile3& b) {
-    return (int64_t)a.tx * a.ty * a.nz > (int64_t)b.tx * b.ty * b.nz;
-  });
-  for (const Tile3& T : L.deep_tiles)
-    RMG_REQUIRE(T.tx * T.ty <= kDeepThreads && (T.tx + 2) * (T.ty + 2) <= tile_plane_cap(kDeepThreads) &&
-                    T.x0 >= box[T.region].lo[0] && T.y0 >= box[T.region].lo[1] && T.z0 >= box[T.region].lo[2] &&
-                    T.x0 + T.tx <= box[T.region].hi[0] && T.y0 + T.ty <= box[T.region].hi[1] &&
-                    T.z0 + T.nz <= box[T.region].hi[2],
-                RMG_ERR_ARG, "internal: deep tile outside the deep box");
+  for (const Tile3& T : L.table_tiles) {
+    const RegionGeo& R = L.regs[T.region];
+    RMG_REQUIRE(table_lanes(T.tx, T.ty) <= kTableThreads && T.ty <= kTableRows && (T.tx + 2) * (T.ty + 2) <= 2 * kTableThreads &&
+                    T.x0 == 0 && T.tx == R.ex && T.y0 + T.ty <= R.ey && T.z0 + T.nz <= R.ez && T.nz >= 1,
+                RMG_ERR_ARG, "internal: table tile does not fit its block");
+  }
   for (const Tile3& T : L.tiles)
     if (!keep[T.region]) L.other_tiles.push_back(T);
-  upload(L.d_deep_tiles, L.deep_tiles);
-  upload(L.d_shell_blocks, L.shell_blocks);
+  upload(L.d_table_tiles, L.table_tiles);
   upload(L.d_other_tiles, L.other_tiles);
 }
 

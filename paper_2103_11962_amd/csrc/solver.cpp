@@ -40,9 +40,9 @@ KernelTimer::~KernelTimer() {
 }
 
 static int64_t partial_capacity(const Level& L) {
-  // node blocks, 2.5D tiles or the region-table split (deep tiles, shell blocks, other regions'
+  // node blocks, 2.5D tiles or the region-table split (whole-region table tiles, other regions'
   // tiles), then the interface groups
-  const int64_t split = (int64_t)(L.deep_tiles.size() + L.shell_blocks.size() + L.tiles.size());
+  const int64_t split = (int64_t)(L.table_tiles.size() + L.tiles.size());
   return std::max({(int64_t)L.blocks.size(), (int64_t)L.tiles.size(), split}) + (L.ngroups + kBlock - 1) / kBlock + 16;
 }
 
@@ -250,8 +250,8 @@ static void configure_level(rmg_handle* h, Level& L, bool with_b, bool sym) {
     launch_make_sym(L, false, h->stream, o.region_table != 0 && L.use_tiles && L.tile_threads == kTileThreadsF64);
   } else {
     L.coef_sym.release();
-    L.sym_table.release();
-    L.sym_table_ok.release();
+    L.class_table.release();
+    L.class_table_ok.release();
     clear_split(L);
   }
 }
