@@ -336,15 +336,11 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
         const int64_t gi = R.off + li;
         V acc = (V)0, ctr = (V)0;  // ctr: centre coefficient (the diagonal of a one-region node)
         if constexpr (SYM) {
+          // stencil order, one rounding each (as k_stencil_table sums them)
 #pragma unroll
-          for (int s = 13; s < 27; ++s) {
-            const int j = s % 9, dz = s / 9 - 1;
-            acc += up[s - 13] * (dz == 0 ? rc[j] : rp[j]);
-          }
-#pragma unroll
-          for (int s = 0; s < 13; ++s) {
+          for (int s = 0; s < 27; ++s) {
             const int j = s % 9;
-            acc += lo[s] * (s < 9 ? rm[j] : rc[j]);
+            acc = fma(s < 13 ? lo[s] : up[s - 13], s < 9 ? rm[j] : (s < 18 ? rc[j] : rp[j]), acc);
           }
           ctr = up[0];
         } else {
@@ -396,10 +392,12 @@ __device__ __forceinline__ int axis_class_of(int v, int e) { return v < 2 ? v : 
 // (every inner wavefront away from the y-faces) runs one pass.  No coupling is read per node.  The
 // input vector's planes, whole rows with their halo, pass through two LDS slots; each plane is
 // fetched four planes ahead into registers and b and d two planes ahead, so that two planes' loads
-// are in flight while one is computed.  Consecutive blocks are dealt to the eight XCDs in turn, so
+// are in flight while one is computed, and each plane read adds its products to the running sums
+// of the three nodes it neighbours in z.  Consecutive blocks are dealt to the eight XCDs in turn, so
 // the blocks are mapped to tiles such that every XCD runs a contiguous run of tiles and neighbouring
-// tiles share their halo rows through its L2.  Every node sums its 27 products in k_stencil3d's
-// order with one rounding each, so the results are those of streaming every coupling bit for bit.
+// tiles share their halo rows through its L2.  Every node sums its 27 products in stencil order with
+// one rounding each, as k_stencil3d does, so the results are those of streaming every coupling bit
+// for bit.
 template <StencilOp OP, bool DOT>
 __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, const Tile3* __restrict__ tiles,
                                                                  const double* __restrict__ table, OpP<double> p,
@@ -464,10 +462,10 @@ __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, co
       }
     }
   };
-  double rm[9], rc[9], rp[9];
-  auto readn = [&](int slot, double* r) {
+  double v9[9];  // this lane's 3 x 3 neighbourhood on the plane read last
+  auto readn = [&](int slot) {
 #pragma unroll
-    for (int j = 0; j < 9; ++j) r[j] = pl[slot][(row + j / 3) * W + x + j % 3];
+    for (int j = 0; j < 9; ++j) v9[j] = pl[slot][(row + j / 3) * W + x + j % 3];
   };
   const int z0 = T.z0, z1 = T.z0 + T.nz;
   auto load_bd = [&](int z2, double& b2, double& d2) {  // inactive lanes and planes past the tile: a valid node
@@ -480,6 +478,64 @@ __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, co
     const int yu = min(T.y0 + (u >> 2), R.ey - 1), xu = (u & 3) < 2 ? (u & 3) : R.ex - 4 + (u & 3);
     xt[cz][s2][u] = tab[((cz * 5 + axis_class_of(yu, R.ey)) * 5 + axis_class_of(xu, R.ex)) * kClassPts + s2];
   }
+  // Running sums: once plane q has been added, a0 is node q - 1's sum, a1 node q's and a2 node
+  // q + 1's.  A plane adds its nine values to the three nodes it neighbours in z (as their plane
+  // z + 1, z and z - 1), so each node adds its 27 products in stencil order with one rounding each,
+  // and only the plane read last is held in registers.
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, ctr = 0.0, xprev = 0.0;
+  auto czc = [&](int z) { return min(max(axis_class_of(z, R.ez), 0), 4); };
+  auto add_plane = [&](int q) {
+    a2 = 0.0;
+    if (t >= pad) {
+      // the x-face wavefront (four classes a row): each lane reads its class's couplings from
+      // the block's copy in LDS, nine at a time (the empty asm keeps the chunks' reads apart)
+      const int u = t - pad;
+      auto chunk = [&](const double* __restrict__ xc, double& acc) {
+        double cf[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) cf[j] = xc[j * kXRows];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) acc = fma(cf[j], v9[j], acc);
+        __asm__ volatile("" ::: "memory");
+      };
+      chunk(&xt[czc(q - 1)][18][u], a0);
+      chunk(&xt[czc(q)][9][u], a1);
+      chunk(&xt[czc(q + 1)][0][u], a2);
+      ctr = xt[czc(q - 1)][13][u];
+    } else {
+      // the classes of this wavefront's nodes, one after the other (the mask of lanes left and the
+      // leading lane are wavefront-uniform, so every pass reads its class afresh)
+      uint64_t left = __builtin_amdgcn_ballot_w64(true);
+      while (left) {
+        const int c = __builtin_amdgcn_readlane(cxy, (int)__builtin_ctzll(left));
+        // the three classes' table offsets, in scalar registers the compiler cannot trade for
+        // per-lane values below, so that the table is read with scalar loads
+        int o0 = __builtin_amdgcn_readfirstlane((czc(q - 1) * 25 + c) * kClassPts);
+        int o1 = __builtin_amdgcn_readfirstlane((czc(q) * 25 + c) * kClassPts);
+        int o2 = __builtin_amdgcn_readfirstlane((czc(q + 1) * 25 + c) * kClassPts);
+        __asm__ volatile("" : "+s"(o0), "+s"(o1), "+s"(o2));
+        const bool mine = cxy == c;
+        if (mine) {
+          const double* __restrict__ t0 = tab + o0;
+          const double* __restrict__ t1 = tab + o1;
+          const double* __restrict__ t2 = tab + o2;
+#pragma unroll
+          for (int j = 0; j < 9; ++j) a0 = fma(t0[18 + j], v9[j], a0);
+#pragma unroll
+          for (int j = 0; j < 9; ++j) a1 = fma(t1[9 + j], v9[j], a1);
+#pragma unroll
+          for (int j = 0; j < 9; ++j) a2 = fma(t2[j], v9[j], a2);
+          ctr = t0[13];
+        }
+        left &= ~__builtin_amdgcn_ballot_w64(mine);
+      }
+    }
+  };
+  auto shift = [&]() {
+    a0 = a1;
+    a1 = a2;
+    xprev = v9[4];
+  };
   double preA[kFetch], preB[kFetch];
   double nbA = 0.0, ndA = 0.0, nbB = 0.0, ndB = 0.0;
   load_bd(z0, nbA, ndA);
@@ -489,9 +545,13 @@ __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, co
   store(0, z0 - 1, preA);
   store(1, z0, preB);
   __syncthreads();
-  if (active) {
-    readn(0, rm);
-    readn(1, rc);
+  if (active) {  // planes z0 - 1 and z0: the first two thirds of node z0, the first of z0 + 1
+    readn(0);
+    add_plane(z0 - 1);
+    shift();
+    readn(1);
+    add_plane(z0);
+    shift();
   }
   __syncthreads();
   fetch(z0 + 1, preA);
@@ -500,65 +560,25 @@ __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, co
   fetch(z0 + 3, preB);
   __syncthreads();
   double contrib = 0.0;
-  // one plane: its products from LDS (plane zz + 1) and registers (zz - 1, zz); plane zz + 2 goes
-  // to LDS from the registers that fetched it two planes ago, which then fetch plane zz + 4
-  // (past the tile's last plane it only keeps the loads in step: see the loop below)
+  // one plane: plane zz + 1 from LDS completes node zz; plane zz + 2 goes to LDS from the
+  // registers that fetched it two planes ago, which then fetch plane zz + 4 (past the tile's last
+  // plane it only keeps the loads in step: see the loop below)
   auto plane = [&](int zz, double(&pre)[kFetch], double& b2, double& d2) {
     const int sp = (zz - z0) & 1;  // slot holding plane zz + 1
     const bool work = active && zz < z1;
-    if (work) readn(sp, rp);
+    if (work) readn(sp);
     if (zz + 2 <= z1) store(sp ^ 1, zz + 2, pre);  // plane zz + 2 replaces plane zz
     fetch(zz + 4, pre);
     const double cb = b2, cd = d2;
     load_bd(zz + 2, b2, d2);
     if (work) {
-      const int cls = axis_class_of(zz, R.ez) * 25 + cxy;
-      double acc = 0.0, ctr = 0.0;
-      if (t >= pad) {
-        // the x-face wavefront (four classes a row): each lane reads its class's couplings from
-        // the block's copy in LDS, nine at a time (the empty asm keeps the chunks' reads apart)
-        const double* __restrict__ xc = &xt[axis_class_of(zz, R.ez)][0][t - pad];
-        auto chunk = [&](int s0) {
-          double cf[9];
-#pragma unroll
-          for (int k = 0; k < 9; ++k) cf[k] = xc[((s0 + k) % 27) * kXRows];
-#pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            const int s = (s0 + k) % 27;
-            acc = fma(cf[k], s >= 18 ? rp[s % 9] : (s >= 9 ? rc[s % 9] : rm[s]), acc);
-          }
-          __asm__ volatile("" ::: "memory");
-        };
-        chunk(13);
-        chunk(22);
-        chunk(4);
-        ctr = xc[13 * kXRows];
-      } else {
-        for (;;) {  // the classes of this wavefront's nodes, one after the other
-          const int c = __builtin_amdgcn_readfirstlane(cls);
-          int cu = c;  // the same class, in a scalar register the compiler cannot trade for cls below,
-          __asm__ volatile("" : "+s"(cu));  // so that the table is read with scalar loads
-          if (cls == c) {
-            const double* __restrict__ tc = tab + cu * kClassPts;
-#pragma unroll
-            for (int s = 13; s < 27; ++s) acc = fma(tc[s], s < 18 ? rc[s % 9] : rp[s % 9], acc);
-#pragma unroll
-            for (int s = 0; s < 13; ++s) acc = fma(tc[s], s < 9 ? rm[s] : rc[s % 9], acc);
-            ctr = tc[13];
-            break;
-          }
-        }
-      }
+      add_plane(zz + 1);
       const int64_t gi = R.off + (int64_t)zz * sz + (int64_t)y * sy + x;
       const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
-      if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
-      else if constexpr (kPreB) contrib += finish_pre<OP, DOT, double, true>(p, gi, acc, 1, rc[4], ctr, cb, cd);
-      else contrib += finish<OP, DOT, double, true>(p, gi, acc, 1, rc[4], ctr);
-    }
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      rm[j] = rc[j];
-      rc[j] = rp[j];
+      if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = a0;  // finished by k_iface
+      else if constexpr (kPreB) contrib += finish_pre<OP, DOT, double, true>(p, gi, a0, 1, xprev, ctr, cb, cd);
+      else contrib += finish<OP, DOT, double, true>(p, gi, a0, 1, xprev, ctr);
+      shift();
     }
     __syncthreads();
   };
