@@ -48,7 +48,7 @@ ALGO_COEFS = 27
 # plain-copy calibration, read from the committed counter summary; used only while the sources
 # that define the kernel, its tiles, launch shapes and region table hash as they did when the
 # counters were taken.
-COUNTERS = os.path.join(ROOT, "profiles", "k_stencil3d_cheb_c2_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "k_stencil_table_cheb_c2_counters.md")
 KERNEL_SOURCES = ("kernels_stencil.hip", "kernels.hip", "planner.cpp", "solver.cpp", "api.cpp")
 
 
