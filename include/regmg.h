@@ -63,7 +63,14 @@ typedef enum {
 typedef enum {
   RMG_PREC_FP64 = 0,        /* whole V-cycle in FP64 */
   RMG_PREC_FP32 = 1,        /* V-cycle in FP32 inside FP64 CG */
-  RMG_PREC_FP32_BF16 = 2    /* FP32 V-cycle, finest-level stencil off-diagonals in BF16 */
+  RMG_PREC_FP32_BF16 = 2,   /* FP32 V-cycle, finest-level stencil off-diagonals in BF16 */
+  RMG_PREC_FP32_BF16_AUTO = 3 /* FP32 V-cycle; each smoothed level's stencil off-diagonals in BF16
+                                where the measured convergence factor allows it: setup measures the
+                                factor of bf16_cycles stationary V-cycles (rmg_convergence_factor)
+                                with every level in FP32, then, finest level first, switches one
+                                level at a time to BF16 and keeps it there when the factor stays
+                                within (1 + bf16_tolerance) of the FP32 one (rmg_level_precision
+                                reports the choice and both factors) */
 } rmg_precision;
 
 typedef struct rmg_handle rmg_handle;
@@ -156,6 +163,10 @@ typedef struct {
                          the tensor product of one rate-3 interpolation per axis); 1: the generic
                          product of every coarse node over its 5 x 5 x 5 fine window (also used for
                          2D, elasticity and stored weights) */
+  double bf16_tolerance; /* RMG_PREC_FP32_BF16_AUTO: relative rise of the measured convergence
+                         factor over the all-FP32 one that a BF16 level may cause (default 0.05) */
+  int bf16_cycles;    /* RMG_PREC_FP32_BF16_AUTO: stationary V-cycles per measured factor, in
+                         [1, 1000] (default 10) */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -329,6 +340,13 @@ rmg_status rmg_level_info(rmg_handle* h, int level, int64_t* n_regional, int64_t
  * symmetric 27-point stencil); coefs_lo = the same for the low-precision
  * V-cycle copy (0 when there is none).  Any output may be NULL. */
 rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, int* coefs_lo);
+/* Storage of level `level`'s stencil in the low-precision V-cycle (Section 3.4 smoother, the
+ * mixed-precision variant): coef_type 0 FP64 (no low-precision copy: precision RMG_PREC_FP64, or the
+ * coarsest level), 1 FP32, 2 BF16 off-diagonals with FP32 centre blocks.  With
+ * RMG_PREC_FP32_BF16_AUTO, rho_fp32 is the convergence factor measured with every level in FP32
+ * and rho_bf16 the factor measured with this level switched to BF16 (and the finer levels as
+ * decided); -1 where the level was not tried.  Any output may be NULL. */
+rmg_status rmg_level_precision(rmg_handle* h, int level, int* coef_type, double* rho_fp32, double* rho_bf16);
 /* Kernel launches this library has issued in the process so far (every handle and trainer, every
  * thread; a replayed HIP graph counts once per captured launch when it was recorded, not when
  * replayed).  The difference around a call is that call's launch count. */

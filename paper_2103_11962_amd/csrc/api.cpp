@@ -160,6 +160,8 @@ void rmg_options_default(rmg_options* o) {
   o->region_table = 1;
   o->tile_planes = 0;
   o->galerkin_generic = 0;
+  o->bf16_tolerance = 0.05;
+  o->bf16_cycles = 10;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -485,8 +487,12 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->cheb_degree >= 1 && opt->cheb_degree <= 16, RMG_ERR_ARG, "cheb_degree must be in [1, 16]");
   RMG_REQUIRE(opt->eig_ratio > 1.0 && opt->boost > 0.0, RMG_ERR_ARG, "need eig_ratio > 1 and boost > 0");
   RMG_REQUIRE(opt->power_iters >= 1, RMG_ERR_ARG, "power_iters must be >= 1");
-  RMG_REQUIRE(opt->precision >= RMG_PREC_FP64 && opt->precision <= RMG_PREC_FP32_BF16, RMG_ERR_ARG,
+  RMG_REQUIRE(opt->precision >= RMG_PREC_FP64 && opt->precision <= RMG_PREC_FP32_BF16_AUTO, RMG_ERR_ARG,
               "unknown precision");
+  RMG_REQUIRE(opt->precision != RMG_PREC_FP32_BF16_AUTO ||
+                  (std::isfinite(opt->bf16_tolerance) && opt->bf16_tolerance >= 0.0 && opt->bf16_cycles >= 1 &&
+                   opt->bf16_cycles <= 1000),
+              RMG_ERR_ARG, "bf16_tolerance must be finite and >= 0, bf16_cycles in [1, 1000]");
   RMG_REQUIRE(opt->precision == RMG_PREC_FP64 || h->dim == 3, RMG_ERR_ARG,
               "the low-precision V-cycle needs 27-point (3D) levels");
   RMG_REQUIRE(opt->stencil_kernel >= 0 && opt->stencil_kernel <= 3, RMG_ERR_ARG, "stencil_kernel must be 0..3");
@@ -705,6 +711,16 @@ rmg_status rmg_level_kernel(rmg_handle* h, int level, int* kernel, int* coefs, i
   // the 2.5D kernel has no half-stencil path for BF16 storage
   const bool sym_lo = L.coef_lo_sym.p && !(tiled && L.ct_lo == kCoefBF16);
   if (coefs_lo) *coefs_lo = L.ct_lo == kCoefF64 ? 0 : (sym_lo ? kSymPts * nb : L.ncoef());
+  API_END
+}
+
+rmg_status rmg_level_precision(rmg_handle* h, int level, int* coef_type, double* rho_fp32, double* rho_bf16) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  if (coef_type) *coef_type = L.ct_lo == kCoefF64 ? 0 : (L.ct_lo == kCoefF32 ? 1 : 2);
+  if (rho_fp32) *rho_fp32 = L.rho_fp32;
+  if (rho_bf16) *rho_bf16 = L.rho_bf16;
   API_END
 }
 

@@ -213,6 +213,9 @@ struct Level {
   DBuf b, u, u2, d, r;
   // low-precision V-cycle copy (FP32 vectors; FP32 or BF16 coefficients)
   int ct_lo = kCoefF64;  // kCoefF64: no copy
+  // per-level BF16 decision (RMG_PREC_FP32_BF16_AUTO): factor with every level FP32, with this
+  // level BF16; -1 where not tried
+  double rho_fp32 = -1.0, rho_bf16 = -1.0;
   DBuf coef_lo;          // float or uint16 (bf16), wave-tiled like coef
   DBuf center_lo;        // bf16 storage only: FP32 centre blocks [n][ndof*ndof]
   DBuf coef_lo_sym;      // FP32 storage of a symmetric level: the upper half, else empty

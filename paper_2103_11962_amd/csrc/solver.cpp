@@ -340,6 +340,9 @@ static int build_levels(rmg_handle* h, bool stored) {
   return pflags;
 }
 
+static void judge_learned(rmg_handle* h);
+static void choose_bf16_levels(rmg_handle* h);
+
 void setup_hierarchy(rmg_handle* h) {
   const rmg_options& o = h->opt;
   Level* L0 = h->levels[0];
@@ -380,8 +383,14 @@ void setup_hierarchy(rmg_handle* h) {
               "stored or learned interpolation needs a scalar 3D problem");
   h->p_flags = build_levels(h, stored);
   if (stored && h->p_flags == 0) h->p_used = h->pmode;
-  if (h->p_used != RMG_P_LEARNED || o.judge_cycles <= 0) return;
-  // the judge: keep the learned hierarchy only if it converges faster than the geometric one
+  if (h->p_used == RMG_P_LEARNED && o.judge_cycles > 0) judge_learned(h);
+  if (o.precision == RMG_PREC_FP32_BF16_AUTO) choose_bf16_levels(h);
+}
+
+// The judge: keep the learned hierarchy only if it converges faster than the geometric one.
+static void judge_learned(rmg_handle* h) {
+  const rmg_options& o = h->opt;
+  Level* L0 = h->levels[0];
   const double rl = convergence_factor(h, o.judge_cycles);
   std::vector<Level*> learned(h->levels.begin() + 1, h->levels.end());
   h->levels.resize(1);
@@ -408,6 +417,34 @@ void setup_hierarchy(rmg_handle* h) {
     h->p_used = RMG_P_GEOMETRIC;
     h->p_flags = RMG_PW_JUDGED_WORSE;
   }
+}
+
+// Low-precision copy of a level's stencil for the V-cycle, as build_levels makes it.
+static void set_level_lowp(rmg_handle* h, Level& L, int coef_type) {
+  launch_make_lowp(L, coef_type, h->stream);
+  if (h->opt.symmetric) launch_make_sym(L, true, h->stream, false);
+}
+
+// Per-level BF16 (RMG_PREC_FP32_BF16_AUTO): the convergence factor of bf16_cycles stationary
+// V-cycles with every level in FP32 is the reference; finest level first, each smoothed 27-point
+// level is switched to BF16 off-diagonals and kept there when the factor, measured with the finer
+// levels as already decided, stays within (1 + bf16_tolerance) of the reference.
+static void choose_bf16_levels(rmg_handle* h) {
+  const rmg_options& o = h->opt;
+  const int nl = (int)h->levels.size();
+  for (Level* L : h->levels) L->rho_fp32 = L->rho_bf16 = -1.0;
+  const double ref = convergence_factor(h, o.bf16_cycles);
+  RMG_REQUIRE(std::isfinite(ref), RMG_ERR_NUMERIC, "convergence factor of the FP32 V-cycle is not finite");
+  for (int l = 0; l < nl - 1; ++l) {
+    Level& L = *h->levels[l];
+    if (L.npts != 27 || L.ct_lo != kCoefF32) continue;
+    set_level_lowp(h, L, kCoefBF16);
+    const double rho = convergence_factor(h, o.bf16_cycles);
+    L.rho_fp32 = ref;
+    L.rho_bf16 = rho;
+    if (!(std::isfinite(rho) && rho <= ref * (1.0 + o.bf16_tolerance))) set_level_lowp(h, L, kCoefF32);
+  }
+  RMG_HIP(hipStreamSynchronize(h->stream));
 }
 
 // Buffers of one level for the FP64 or the FP32 V-cycle.

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "lib
 LAYOUT_COMPOSITE = 0
 LAYOUT_REGIONAL = 1
 PDE_LAPLACE, PDE_DIFFUSION, PDE_ELASTICITY = 0, 1, 2
-PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_FP32_BF16, PREC_FP32_BF16_AUTO = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_NODE, KERNEL_TILED = 0, 1, 2
 
 STATUS = {
@@ -41,6 +41,7 @@ SYMBOLS = (
     "rmg_mlp_set_loss", "rmg_set_region_kinds", "rmg_hybrid_level_info", "rmg_hybrid_aggregates",
     "rmg_hybrid_composite_ids", "rmg_hybrid_matrix", "rmg_amg_levels", "rmg_amg_level_info", "rmg_amg_matrix",
     "rmg_level_table_regions", "rmg_level_tiles", "rmg_kernel_launches", "rmg_convergence_factor_noalloc",
+    "rmg_level_precision",
 )
 SMOOTHER_CHEBYSHEV, SMOOTHER_JACOBI, SMOOTHER_GS, SMOOTHER_GS_FB, SMOOTHER_SYMGS = 0, 1, 2, 3, 4
 TIMED_CHEB, TIMED_CG_MATVEC = 0, 1
@@ -75,6 +76,8 @@ class Options(ctypes.Structure):
         ("region_table", ctypes.c_int),
         ("tile_planes", ctypes.c_int),
         ("galerkin_generic", ctypes.c_int),
+        ("bf16_tolerance", ctypes.c_double),
+        ("bf16_cycles", ctypes.c_int),
     ]
 
 
@@ -187,6 +190,8 @@ def load():
         "rmg_mlp_train": (I, [H, I, D, P]),
         "rmg_mlp_init_params": (I, [H, ctypes.c_uint64, D, P]),
         "rmg_level_kernel": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "rmg_level_precision": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
         "rmg_set_composite_csr": (I, [H, I, ctypes.c_int64, P, P, P, I]),
         "rmg_level_table_regions": (I, [H, I, ctypes.POINTER(I)]),
         "rmg_level_tiles": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
@@ -452,6 +457,11 @@ class Handle:
         k, c, cl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(load().rmg_level_kernel(self._h, level, ctypes.byref(k), ctypes.byref(c), ctypes.byref(cl)))
         return {"kernel": k.value, "coefs": c.value, "coefs_lo": cl.value}
+
+    def level_precision(self, level):
+        t, r32, rbf = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(load().rmg_level_precision(self._h, level, ctypes.byref(t), ctypes.byref(r32), ctypes.byref(rbf)))
+        return {"coef_type": t.value, "rho_fp32": r32.value, "rho_bf16": rbf.value}
 
     def level_tiles(self, level):
         n, t, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
