@@ -9,6 +9,11 @@ Readings of points the paper leaves open:
   extra delta factor in the printed initialisation is dropped; it is
   inconsistent with rho = 1/(theta delta)); degree K means K corrections and
   K-1 residual updates inside the smoother.
+* D~ of a system (Section 3.2 smoother setup speaks of the diagonal): the point
+  diagonal by default; with ``block_diag`` the ndof x ndof nodal blocks of
+  [[A]]'s centre stencil summed over the copies (Psi^T Psi column by column) and
+  inverted per node, used wherever D~^-1 enters (power method, Chebyshev,
+  Jacobi).
 * Eigenvalue interval [lambda/eta, kappa*lambda] with lambda the largest
   eigenvalue of D~^-1 A, estimated by power iterations from the counter-based
   start vector of ``rng``; eta = 20, kappa = 1.1, 10 iterations by default.
@@ -61,7 +66,14 @@ class Level:
     P: list = None  # region prolongators to the next level
     Abar: np.ndarray = None  # coarsest composite operator (dense)
     amg: list = None  # coarsest level with the AMG coarse solver: its levels (amg.setup)
+    dblk: list = None  # block_diag: per region the inverse nodal blocks of D~, shape (..., ndof, ndof)
     extra: dict = field(default_factory=dict)
+
+    def apply_dinv(self, r):
+        """D~^-1 r: the point diagonal's reciprocal, or the inverse nodal blocks (block_diag)."""
+        if self.dblk is None:
+            return mul(self.dinv, r)
+        return [np.einsum("...ab,...b->...a", Dk, rk) for Dk, rk in zip(self.dblk, r)]
 
     def matvec(self, x):
         """Psi^T Psi [[A]] [[x]]: region-local stencil products, then interface sum (RegMatVec)."""
@@ -84,6 +96,7 @@ class Options:
     smoother: str = "chebyshev"  # or "jacobi", "gs", "sgs", "symgs"
     gamma: int = 1  # coarse-level cycles per visit: 1 V-cycle, 2 W-cycle
     jacobi_omega: float = 0.6
+    block_diag: bool = False  # systems (ndof > 1): D~ of nodal blocks instead of the point diagonal
     coarse_amg: bool = False  # coarse solve: one AMG V-cycle on Abar instead of a direct solve
     amg_coarse_size: int = 2000  # the AMG's directly solved level has at most this many rows
 
@@ -92,6 +105,14 @@ def composite_diagonal(lay: Layout, coefs):
     """D~ = Psi^T Psi diag([[A]]) (Section 3.2 smoother setup)."""
     d = [assembly.diagonal(coefs[k], lay.dim, lay.ndof) for k in range(lay.nreg)]
     return lay.interface_sum(d)
+
+
+def composite_block_diagonal(lay: Layout, coefs):
+    """Nodal-block D~ of a system (ndof > 1): every node's ndof x ndof centre block of [[A]] summed
+    over the node's copies (Psi^T Psi applied column by column); shape (..., ndof, ndof) per region."""
+    cen = [coefs[k][assembly.center(lay.dim)] for k in range(lay.nreg)]  # (..., a, b)
+    cols = [lay.interface_sum([c[..., :, j] for c in cen]) for j in range(lay.ndof)]
+    return [np.stack([cols[j][k] for j in range(lay.ndof)], axis=-1) for k in range(lay.nreg)]
 
 
 def start_vector(lay: Layout, level: int, seed: int):
@@ -112,7 +133,7 @@ def power_method(L: Level, x0, iters: int):
     x = lin(1.0 / lay.norm(x0), x0)
     lam = 0.0
     for _ in range(iters):
-        y = mul(L.dinv, L.matvec(x))
+        y = L.apply_dinv(L.matvec(x))
         lam = lay.dot(x, y)
         x = lin(1.0 / lay.norm(y), y)
     return lam
@@ -140,6 +161,10 @@ def setup(lay0: Layout, coefs0, opt: Options, P0=None):
                 L.Abar = coarse_composite(lay, coefs)
             break
         L.dinv = [1.0 / d for d in composite_diagonal(lay, coefs)]
+        if opt.block_diag:
+            if lay.ndof == 1 or opt.smoother not in ("chebyshev", "jacobi"):
+                raise ValueError("nodal-block D~ needs a system (ndof > 1) and the Chebyshev or Jacobi smoother")
+            L.dblk = [np.linalg.inv(B) for B in composite_block_diagonal(lay, coefs)]
         if opt.smoother == "chebyshev":
             L.lam = power_method(L, start_vector(lay, l, opt.seed), opt.power_iters)
         coarse = lay.coarsen()
@@ -163,13 +188,13 @@ def chebyshev(L: Level, u, b, r, opt: Options):
     theta = 0.5 * (alpha + beta)
     delta = 2.0 / (beta - alpha)
     rho = 1.0 / (theta * delta)
-    d = lin(1.0 / theta, mul(L.dinv, r))
+    d = lin(1.0 / theta, L.apply_dinv(r))
     u = lin(1.0, u, 1.0, d)
     for _ in range(opt.degree - 1):
         r = L.residual(b, u)
         rho_old = rho
         rho = 1.0 / (2.0 * theta * delta - rho_old)
-        d = lin(rho * rho_old, d, 2.0 * rho * delta, mul(L.dinv, r))
+        d = lin(rho * rho_old, d, 2.0 * rho * delta, L.apply_dinv(r))
         u = lin(1.0, u, 1.0, d)
     return u
 
@@ -179,7 +204,7 @@ def jacobi(L: Level, u, b, r, opt: Options):
     for i in range(opt.degree):
         if i:
             r = L.residual(b, u)
-        u = lin(1.0, u, opt.jacobi_omega, mul(L.dinv, r))
+        u = lin(1.0, u, opt.jacobi_omega, L.apply_dinv(r))
     return u
 
 
