@@ -167,6 +167,12 @@ typedef struct {
                          factor over the all-FP32 one that a BF16 level may cause (default 0.05) */
   int bf16_cycles;    /* RMG_PREC_FP32_BF16_AUTO: stationary V-cycles per measured factor, in
                          [1, 1000] (default 10) */
+  int block_diag;     /* D~ of a 3-dof system (Section 3.2 smoother setup): 0 (default) the point
+                         diagonal; 1 the 3 x 3 nodal blocks of [[A]]'s centre stencil summed over
+                         each node's copies, inverted per node and applied wherever D~^-1 enters
+                         (power method, Chebyshev and Jacobi smoothers, FP64 and low-precision
+                         V-cycles).  Needs ndof 3 and smoother 0 or 1 (RMG_ERR_ARG otherwise);
+                         RMG_ERR_NUMERIC if a summed block is not positive definite */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */

@@ -162,6 +162,7 @@ void rmg_options_default(rmg_options* o) {
   o->galerkin_generic = 0;
   o->bf16_tolerance = 0.05;
   o->bf16_cycles = 10;
+  o->block_diag = 0;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -503,6 +504,9 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
               "tile_planes must be 0, 21 or 41");
   RMG_REQUIRE(opt->galerkin_generic == 0 || opt->galerkin_generic == 1, RMG_ERR_ARG,
               "galerkin_generic must be 0 or 1");
+  RMG_REQUIRE(opt->block_diag == 0 || opt->block_diag == 1, RMG_ERR_ARG, "block_diag must be 0 or 1");
+  RMG_REQUIRE(!opt->block_diag || (h->ndof == 3 && opt->smoother <= 1 && !opt->hybrid), RMG_ERR_ARG,
+              "block_diag needs a 3-dof problem and the Chebyshev or Jacobi smoother");
   RMG_REQUIRE(opt->smoother >= 0 && opt->smoother <= 4, RMG_ERR_ARG,
               "smoother must be 0 (Chebyshev), 1 (Jacobi), 2 (Gauss-Seidel), 3 (forward/backward "
               "Gauss-Seidel) or 4 (symmetric Gauss-Seidel)");

@@ -198,6 +198,8 @@ struct Level {
   std::vector<Tile3> other_tiles;    // the level's 2.5D tiles of the regions not served
   DBuf d_table_tiles, d_other_tiles;
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
+  DBuf dinv9;     // block_diag (3-dof levels): inverse nodal 3 x 3 blocks of D~, double [n][9] row-major
+  DBuf dinv9_lo;  // its FP32 copy for the low-precision V-cycle
   DBuf pw;        // stored interpolation weights to the next level, double [n][8] (null: geometric)
   DBuf rw;        // with pw: the same weights per coarse node (125 taps, wave-tiled) for the restriction
   // region-local Gauss-Seidel (smoothers 2-4): the level's stencils and D~^-1 copied into the

@@ -35,6 +35,7 @@ struct StencilArgs {
   double c1 = 0.0, c2 = 0.0;
   double* partials = nullptr;  // CgQ / dot-fused variants: one double per block
   const void* dotw = nullptr;  // Cheb: when set, partial sums of (dotw, u_out) are produced
+  const void* dinv9 = nullptr; // Cheb, ChebFirst on 3-dof levels: nodal-block D~^-1 (9 per node), else null
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // when set, recorded around the stencil kernel only
 };
 
@@ -61,7 +62,7 @@ void launch_reduce(const double* partials, int64_t n, double* scalars, int slot,
 
 // Pointwise: d = c * dinv * b; u = d (first Chebyshev step from a zero guess).
 void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* d, void* u,
-                      hipStream_t st);
+                      hipStream_t st, const void* dinv9 = nullptr);
 
 // Restriction level -> level+1 (input already divided by multiplicity), including coarse interface sum.
 void launch_restrict(const Level& F, const Level& C, bool lowp, const void* r_scaled, void* w, hipStream_t st);
@@ -82,6 +83,9 @@ void launch_start_vector(const Level& L, int level, uint64_t seed, double* out, 
 void launch_scale(int64_t n, const double* scalars, int slot, int mode, const double* x, double* y,
                   hipStream_t st);  // mode 0: y = x / sqrt(s); mode 1: y = x * s
 void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStream_t st);  // y = a*b
+void launch_mul_block3(int64_t nodes, const double* D9, const double* x, double* y, hipStream_t st);
+// Nodal-block D~^-1 of a 3-dof level into L.dinv9 (RMG_ERR_NUMERIC if a block is not positive definite).
+void launch_block_diag(Level& L, hipStream_t st);
 void launch_add(int64_t n, const double* x, double* y, hipStream_t st);  // y += x
 void launch_log(int64_t n, const double* in, float* out, hipStream_t st);  // out = log(in), FP32
 void launch_f64_to_f32(int64_t n, const double* in, float* out, hipStream_t st);

@@ -149,9 +149,36 @@ __global__ void k_cheb_zero(int64_t n, const V* __restrict__ b, const V* __restr
   u[i] = v;
 }
 
+// The same with the nodal-block D~^-1 of a 3-dof level (one row-major 3 x 3 block per node).
+template <class V>
+__global__ void k_cheb_zero_block3(int64_t nodes, const V* __restrict__ b, const V* __restrict__ dinv9, V c,
+                                   V* __restrict__ d, V* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nodes) return;
+  const V* __restrict__ D = dinv9 + i * 9;
+  const V b0 = b[3 * i], b1 = b[3 * i + 1], b2 = b[3 * i + 2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const V v = c * (D[3 * a] * b0 + D[3 * a + 1] * b1 + D[3 * a + 2] * b2);
+    d[3 * i + a] = v;
+    u[3 * i + a] = v;
+  }
+}
+
 void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* d, void* u,
-                      hipStream_t st) {
+                      hipStream_t st, const void* dinv9) {
   const int64_t n = L.ndofs();
+  if (dinv9) {
+    RMG_REQUIRE(L.ndof == 3, RMG_ERR_ARG, "internal: nodal blocks on a scalar level");
+    if (lowp)
+      RMG_LAUNCH(k_cheb_zero_block3<float>, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, (const float*)b,
+                 (const float*)dinv9, (float)c, (float*)d, (float*)u);
+    else
+      RMG_LAUNCH(k_cheb_zero_block3<double>, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, (const double*)b,
+                 (const double*)dinv9, c, (double*)d, (double*)u);
+    LAUNCH_CHECK();
+    return;
+  }
   if (lowp)
     RMG_LAUNCH(k_cheb_zero<float>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, (const float*)b,
                        (const float*)dinv, (float)c, (float*)d, (float*)u);
@@ -184,6 +211,92 @@ __global__ void k_mul(int64_t n, const double* __restrict__ a, const double* __r
 void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStream_t st) {
   RMG_LAUNCH(k_mul, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, a, b, y);
   LAUNCH_CHECK();
+}
+
+// y = blockdiag(D) x with one row-major 3 x 3 block per node.
+__global__ void k_mul_block3(int64_t nodes, const double* __restrict__ D9, const double* __restrict__ x,
+                             double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nodes) return;
+  const double* __restrict__ D = D9 + i * 9;
+  const double x0 = x[3 * i], x1 = x[3 * i + 1], x2 = x[3 * i + 2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) y[3 * i + a] = D[3 * a] * x0 + D[3 * a + 1] * x1 + D[3 * a + 2] * x2;
+}
+
+void launch_mul_block3(int64_t nodes, const double* D9, const double* x, double* y, hipStream_t st) {
+  RMG_LAUNCH(k_mul_block3, dim3(cdiv(nodes, kBlock)), dim3(kBlock), 0, st, nodes, D9, x, y);
+  LAUNCH_CHECK();
+}
+
+// Nodal-block D~ of a 3-dof level (Section 3.2 smoother setup, block reading): column j of every
+// node's centre block of [[A]], as a regional 3-vector per node, so that the interface sum adds
+// the copies' blocks column by column.
+__global__ __launch_bounds__(kBlock) void k_centre_column(LevelView L, const double* __restrict__ coef, int j,
+                                                          double* __restrict__ col) {
+  const BlockDesc bd = L.blocks[blockIdx.x];
+  const RegionGeo R = L.regs[bd.region];
+  const int li = bd.start + (int)threadIdx.x;
+  if (li >= R.n) return;
+  const int64_t gi = R.off + li;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) col[gi * 3 + a] = coef[coef_index(gi, (13 * 3 + a) * 3 + j, 27 * 9)];
+}
+
+// Inverse of each node's summed block (adjugate over the determinant); a block whose determinant
+// is not positive and finite sets the flag.
+__global__ void k_block_inv3(int64_t nodes, const double* __restrict__ c0, const double* __restrict__ c1,
+                             const double* __restrict__ c2, double* __restrict__ D9, int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nodes) return;
+  const double* col[3] = {c0, c1, c2};
+  double B[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) B[a][j] = col[j][3 * i + a];
+  const double k00 = B[1][1] * B[2][2] - B[1][2] * B[2][1], k01 = B[0][2] * B[2][1] - B[0][1] * B[2][2],
+               k02 = B[0][1] * B[1][2] - B[0][2] * B[1][1];
+  const double k10 = B[1][2] * B[2][0] - B[1][0] * B[2][2], k11 = B[0][0] * B[2][2] - B[0][2] * B[2][0],
+               k12 = B[0][2] * B[1][0] - B[0][0] * B[1][2];
+  const double k20 = B[1][0] * B[2][1] - B[1][1] * B[2][0], k21 = B[0][1] * B[2][0] - B[0][0] * B[2][1],
+               k22 = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+  const double det = B[0][0] * k00 + B[0][1] * k10 + B[0][2] * k20;
+  if (!(det > 0.0) || !isfinite(det)) atomicOr(flag, 1);
+  const double r = 1.0 / det;
+  double* __restrict__ D = D9 + i * 9;
+  D[0] = k00 * r;
+  D[1] = k01 * r;
+  D[2] = k02 * r;
+  D[3] = k10 * r;
+  D[4] = k11 * r;
+  D[5] = k12 * r;
+  D[6] = k20 * r;
+  D[7] = k21 * r;
+  D[8] = k22 * r;
+}
+
+void launch_block_diag(Level& L, hipStream_t st) {
+  RMG_REQUIRE(L.ndof == 3 && L.npts == 27, RMG_ERR_ARG, "nodal-block D~ needs a 3-dof 27-point level");
+  const size_t nv = (size_t)L.ndofs();
+  DBuf cols, flag;
+  cols.alloc(sizeof(double) * 3 * nv);
+  flag.alloc(sizeof(int));
+  RMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  double* c = cols.as<double>();
+  for (int j = 0; j < 3; ++j) {
+    RMG_LAUNCH(k_centre_column, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), L.coef.as<double>(), j,
+               c + j * nv);
+    launch_interface_sum(L, c + j * nv, c + j * nv, st);
+  }
+  L.dinv9.alloc(sizeof(double) * 9 * (size_t)L.n);
+  RMG_LAUNCH(k_block_inv3, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, c, c + nv, c + 2 * nv,
+             L.dinv9.as<double>(), flag.as<int>());
+  LAUNCH_CHECK();
+  int hflag = 0;
+  RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  RMG_HIP(hipStreamSynchronize(st));
+  RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "a nodal block of the composite diagonal is not positive definite");
 }
 
 __global__ void k_add(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
@@ -1485,6 +1598,11 @@ void launch_make_lowp(Level& L, int coef_type, hipStream_t st) {
   LAUNCH_CHECK();
   L.dinv_lo.alloc(sizeof(float) * (size_t)L.ndofs());
   launch_f64_to_f32(L.ndofs(), L.dinv.as<double>(), L.dinv_lo.as<float>(), st);
+  L.dinv9_lo.release();
+  if (L.dinv9.p) {
+    L.dinv9_lo.alloc(sizeof(float) * 9 * (size_t)L.n);
+    launch_f64_to_f32(9 * L.n, L.dinv9.as<double>(), L.dinv9_lo.as<float>(), st);
+  }
 }
 
 // ------------------------------------------------------ symmetric half stencil

@@ -21,7 +21,29 @@ struct OpP {
   V* d;
   V c1, c2;
   const V* dotw;
+  const V* dinv9;  // NDOF 3 with nodal blocks: D~^-1 as one row-major 3 x 3 block per node, else null
 };
+
+// The Chebyshev / Jacobi update of the three dofs of node `node` with the nodal-block D~^-1:
+// r = b - z, dd = c2 (D~^-1 r) (+ c1 d), out = x + dd; bi, dold the node's b and old direction.
+template <StencilOp OP, bool DOT, class V>
+__device__ __forceinline__ double finish_block3_value(const OpP<V>& p, int64_t node, const V (&z)[3], const V (&xs)[3],
+                                                      V (&out)[3], V (&dd)[3]) {
+  const V* __restrict__ D = p.dinv9 + node * 9;
+  V r[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) r[a] = p.b[node * 3 + a] - z[a];
+  double c = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const V y = D[3 * a] * r[0] + D[3 * a + 1] * r[1] + D[3 * a + 2] * r[2];
+    dd[a] = p.c2 * y;
+    if constexpr (OP == StencilOp::Cheb) dd[a] = p.c1 * p.d[node * 3 + a] + dd[a];
+    out[a] = xs[a] + dd[a];
+    if constexpr (DOT) c += (double)p.dotw[node * 3 + a] * (double)out[a];
+  }
+  return c;
+}
 
 // Final update of dof i once z = (Psi^T Psi A x)_i is known; m = multiplicity of its node,
 // xself = x_i: the value `out` the operation writes to p.out[i] and, for the Chebyshev steps, the
@@ -168,8 +190,25 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
 #pragma unroll
       for (int a = 0; a < NDOF; ++a) p.out[gi * NDOF + a] = acc[a];  // summed over copies by k_iface
     } else {
+      bool block = false;
+      if constexpr (NDOF == 3 && (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst)) {
+        if (p.dinv9) {
+          V xs[3], out[3], dd[3];
 #pragma unroll
-      for (int a = 0; a < NDOF; ++a) contrib += finish<OP, DOT, V>(p, gi * NDOF + a, acc[a], 1, xr[li * NDOF + a]);
+          for (int a = 0; a < 3; ++a) xs[a] = xr[li * 3 + a];
+          contrib += finish_block3_value<OP, DOT, V>(p, gi, acc, xs, out, dd);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            p.d[gi * 3 + a] = dd[a];
+            p.out[gi * 3 + a] = out[a];
+          }
+          block = true;
+        }
+      }
+      if (!block) {
+#pragma unroll
+        for (int a = 0; a < NDOF; ++a) contrib += finish<OP, DOT, V>(p, gi * NDOF + a, acc[a], 1, xr[li * NDOF + a]);
+      }
     }
   }
   if constexpr (DOT || OP == StencilOp::CgQ) {
@@ -611,8 +650,33 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
   if (g < ng) {
     const int64_t a0 = gptr[g], e = gptr[g + 1];
     const int m = (int)(e - a0);
+    bool block = false;
+    if constexpr (NDOF == 3 && (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst)) {
+      if (p.dinv9) {  // nodal blocks: the node's three sums first, then the block update
+        const int64_t n0 = gcopy[a0];
+        V z[3], xs[3], out[3], dd[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          V s = (V)0;
+          for (int64_t c = a0; c < e; ++c) s += p.out[(int64_t)gcopy[c] * 3 + a];
+          z[a] = s;
+          xs[a] = p.x[n0 * 3 + a];
+        }
+        contrib += finish_block3_value<OP, DOT, V>(p, n0, z, xs, out, dd);
+        for (int64_t c = a0; c < e; ++c) {
+          const int64_t i = (int64_t)gcopy[c] * 3;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            p.d[i + a] = dd[a];
+            p.out[i + a] = out[a];
+          }
+        }
+        block = true;
+      }
+    }
 #pragma unroll
     for (int a = 0; a < NDOF; ++a) {
+      if (block) break;
       V s = (V)0;
       for (int64_t c = a0; c < e; ++c) s += p.out[(int64_t)gcopy[c] * NDOF + a];
       // the copies of a composite dof hold equal b, x, d and D~^-1 (consistent regional vectors),
@@ -638,7 +702,8 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
 template <int NPTS, int NDOF, class V, class C, StencilOp OP, bool DOT>
 static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   OpP<V> p{static_cast<const V*>(a.x), static_cast<V*>(a.out), static_cast<const V*>(a.b),
-           static_cast<const V*>(a.dinv), static_cast<V*>(a.d), (V)a.c1, (V)a.c2, static_cast<const V*>(a.dotw)};
+           static_cast<const V*>(a.dinv), static_cast<V*>(a.d), (V)a.c1, (V)a.c2, static_cast<const V*>(a.dotw),
+           static_cast<const V*>(a.dinv9)};
   const C* coef = a.lowp ? L.coef_lo.as<C>() : L.coef.as<C>();
   const float* centre = L.center_lo.as<float>();
   const LevelView v = L.view();

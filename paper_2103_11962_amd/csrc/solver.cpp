@@ -75,7 +75,8 @@ static double power_method(rmg_handle* h, Level& L, int level) {
     a.x = x;
     a.out = t;
     launch_stencil_op(L, a, st);
-    launch_mul(L.ndofs(), L.dinv.as<double>(), t, y, st);
+    if (L.dinv9.p) launch_mul_block3(L.n, L.dinv9.as<double>(), t, y, st);
+    else launch_mul(L.ndofs(), L.dinv.as<double>(), t, y, st);
     dot(h, L, x, y, kTmp2);
     dot(h, L, y, y, kTmp);
     launch_scale(L.ndofs(), scal(h), kTmp, 0, y, x, st);
@@ -302,6 +303,10 @@ static int build_levels(rmg_handle* h, bool stored) {
     RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
     RMG_HIP(hipStreamSynchronize(st));
     RMG_REQUIRE(hflag == 0, RMG_ERR_NUMERIC, "composite diagonal not positive on level " + std::to_string(l));
+    // block_diag: the nodal 3 x 3 blocks of D~, inverted per node, wherever D~^-1 enters
+    if (o.block_diag) launch_block_diag(L, st);
+    else L.dinv9.release();
+    L.dinv9_lo.release();
     L.lambda = power_method(h, L, l);
     RMG_REQUIRE(std::isfinite(L.lambda) && L.lambda > 0.0, RMG_ERR_NUMERIC,
                 "power method failed on level " + std::to_string(l));
@@ -451,11 +456,12 @@ static void choose_bf16_levels(rmg_handle* h) {
 struct Bufs {
   void *b, *u, *u2, *d, *r;
   const void* dinv;
+  const void* dinv9;  // nodal-block D~^-1 (block_diag), else null
 };
 
 static Bufs bufs(Level& L, bool lowp) {
-  if (lowp) return {L.b32.p, L.u32.p, L.u232.p, L.d32.p, L.r32.p, L.dinv_lo.p};
-  return {L.b.p, L.u.p, L.u2.p, L.d.p, L.r.p, L.dinv.p};
+  if (lowp) return {L.b32.p, L.u32.p, L.u232.p, L.d32.p, L.r32.p, L.dinv_lo.p, L.dinv9_lo.p};
+  return {L.b.p, L.u.p, L.u2.p, L.d.p, L.r.p, L.dinv.p, L.dinv9.p};
 }
 
 static void cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, const void* b, const void* uin,
@@ -468,6 +474,7 @@ static void cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, con
   a.out = uout;
   a.b = b;
   a.dinv = B.dinv;
+  a.dinv9 = B.dinv9;
   a.d = B.d;
   a.c1 = L.cheb_c1[k];
   a.c2 = L.cheb_c2[k];
@@ -516,7 +523,7 @@ void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out)
   }
   const int K = h->opt.cheb_degree;
   void* buf[2] = {L.u.p, u_out};
-  launch_cheb_zero(L, false, b, L.dinv.p, L.cheb_c2[0], L.d.p, buf[0], st);
+  launch_cheb_zero(L, false, b, L.dinv.p, L.cheb_c2[0], L.d.p, buf[0], st, L.dinv9.p);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
     cheb_step(h, L, false, k, false, b, buf[cur], buf[1 - cur]);
@@ -724,7 +731,7 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
   const Bufs B = bufs(L, lowp);
   // ping-pong buffers arranged so that the last post-smoothing step writes z
   void* buf[2] = {B.u, z};
-  launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], B.d, buf[0], st);
+  launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], B.d, buf[0], st, B.dinv9);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
     cheb_step(h, L, lowp, k, false, b, buf[cur], buf[1 - cur]);

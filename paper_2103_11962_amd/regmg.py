@@ -78,6 +78,7 @@ class Options(ctypes.Structure):
         ("galerkin_generic", ctypes.c_int),
         ("bf16_tolerance", ctypes.c_double),
         ("bf16_cycles", ctypes.c_int),
+        ("block_diag", ctypes.c_int),
     ]
 
 
