@@ -12,6 +12,13 @@ Hierarchy (smoothed aggregation, after the SA-AMG the section cites):
   not aggregated.  Coarse rows are numbered by the smallest row of their aggregate;
 * tentative prolongator T: a 1 in the column of its aggregate for every aggregated row (the
   constant near-null space of a scalar problem);
+* systems (the section's "operator and its nullspace"): the rows are grouped into nodes (``nodes``:
+  dof offsets), aggregation runs on the node graph in which nodes I and J are coupled when their
+  block has ||A_IJ||_F > 1e-12 sqrt(||A_II||_F ||A_JJ||_F), a node is free when all its rows are, and
+  the tentative prolongator is built from the near-null space B (rows x k): per aggregate, the rows
+  of B of its dofs (ascending) are factored B_a = Q_a R_a (thin QR, diag(R_a) >= 0); Q_a fills the
+  aggregate's k columns of T and R_a gives the coarse near-null space, whose nodes are the
+  aggregates (k dofs each).  An aggregate with fewer than k dofs is an error;
 * smoothed prolongator P = (I - omega D^-1 A) T, omega = 4 / (3 rho), rho = max_i sum_j |a_ij| / a_ii
   (Gershgorin's bound on lambda_max(D^-1 A), so no random start vector is needed);
 * coarse operator P^T A P; coarsening stops at the first level with at most ``coarse_size`` rows,
@@ -67,6 +74,63 @@ def aggregates(A: sp.csr_matrix, free: np.ndarray) -> np.ndarray:
     return out
 
 
+def node_graph(A: sp.csr_matrix, nodes: np.ndarray) -> sp.csr_matrix:
+    """Nodes coupled by a block of Frobenius norm > STRENGTH sqrt(||A_II||_F ||A_JJ||_F)."""
+    nn = nodes.size - 1
+    node = np.repeat(np.arange(nn), np.diff(nodes))
+    C = sp.coo_matrix(A)
+    S = sp.csr_matrix((C.data ** 2, (node[C.row], node[C.col])), shape=(nn, nn))  # duplicates summed
+    S.sum_duplicates()
+    F = sp.coo_matrix(S)
+    F.data = np.sqrt(F.data)
+    d = np.zeros(nn)
+    on = F.row == F.col
+    d[F.row[on]] = F.data[on]
+    keep = on | (F.data > STRENGTH * np.sqrt(d[F.row] * d[F.col]))
+    return sp.csr_matrix((F.data[keep], (F.row[keep], F.col[keep])), shape=(nn, nn))
+
+
+def tentative_system(agg: np.ndarray, nodes: np.ndarray, B: np.ndarray):
+    """T and the coarse near-null space from per-aggregate thin QR of B (aggregates over nodes)."""
+    k = B.shape[1]
+    na = int(agg.max()) + 1 if (agg >= 0).any() else 0
+    rows, cols, vals = [], [], []
+    Bc = np.zeros((na * k, k))
+    members = [[] for _ in range(na)]
+    for I in range(agg.size):
+        if agg[I] >= 0:
+            members[agg[I]].extend(range(nodes[I], nodes[I + 1]))
+    for a in range(na):
+        dofs = np.asarray(sorted(members[a]), dtype=np.int64)
+        if dofs.size < k:
+            raise ValueError(f"aggregate {a} has {dofs.size} dofs, fewer than the near-null space's {k}")
+        Q, R = np.linalg.qr(B[dofs])
+        sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+        Q, R = Q * sgn, R * sgn[:, None]
+        rows.append(np.repeat(dofs, k))
+        cols.append(np.tile(np.arange(a * k, (a + 1) * k), dofs.size))
+        vals.append(Q.ravel())
+        Bc[a * k:(a + 1) * k] = R
+    n = int(nodes[-1])
+    if na == 0:
+        return sp.csr_matrix((n, 0)), Bc
+    T = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, na * k))
+    return T, Bc
+
+
+def rigid_body_modes(coords: np.ndarray) -> np.ndarray:
+    """Near-null space of 3D elasticity at nodes (n, 3): three translations, then the rotations
+    (-y, x, 0), (0, -z, y), (z, 0, -x); rows node-major, dof fastest."""
+    n = coords.shape[0]
+    x, y, z = coords[:, 0], coords[:, 1], coords[:, 2]
+    B = np.zeros((n, 3, 6))
+    B[:, 0, 0] = B[:, 1, 1] = B[:, 2, 2] = 1.0
+    B[:, 0, 3], B[:, 1, 3] = -y, x
+    B[:, 1, 4], B[:, 2, 4] = -z, y
+    B[:, 0, 5], B[:, 2, 5] = z, -x
+    return B.reshape(3 * n, 6)
+
+
 def tentative(agg: np.ndarray) -> sp.csr_matrix:
     rows = np.flatnonzero(agg >= 0)
     nc = int(agg.max()) + 1 if rows.size else 0
@@ -81,8 +145,9 @@ def gershgorin(A: sp.csr_matrix) -> float:
 
 
 def setup(A: sp.csr_matrix, free: np.ndarray, coarse_size: int = 2000, degree: int = 2, eta: float = 20.0,
-          max_levels: int = 20):
-    """AMG levels of A; the last one is solved directly."""
+          max_levels: int = 20, nodes: np.ndarray = None, B: np.ndarray = None):
+    """AMG levels of A; the last one is solved directly.  ``nodes`` (dof offsets of the nodes) and
+    ``B`` (near-null space, rows x k) select the system form; ``free`` flags rows."""
     levels = []
     A = sp.csr_matrix(A)
     free = np.asarray(free, dtype=bool)
@@ -91,8 +156,13 @@ def setup(A: sp.csr_matrix, free: np.ndarray, coarse_size: int = 2000, degree: i
         levels.append(L)
         if A.shape[0] <= coarse_size:
             break
-        agg = aggregates(A, free)
-        T = tentative(agg)
+        if nodes is None:
+            agg = aggregates(A, free)
+            T = tentative(agg)
+        else:
+            nfree = np.array([free[nodes[I]:nodes[I + 1]].all() for I in range(nodes.size - 1)])
+            agg = aggregates(node_graph(A, nodes), nfree)
+            T, Bc = tentative_system(agg, nodes, B)
         if T.shape[1] == 0 or T.shape[1] >= A.shape[0]:
             break
         L.agg = agg
@@ -102,6 +172,9 @@ def setup(A: sp.csr_matrix, free: np.ndarray, coarse_size: int = 2000, degree: i
         L.P = sp.csr_matrix(T - L.omega * (Dinv @ (A @ T)))
         A = sp.csr_matrix(L.P.T @ A @ L.P)
         free = np.ones(A.shape[0], dtype=bool)
+        if nodes is not None:
+            k = B.shape[1]
+            nodes, B = np.arange(0, A.shape[0] + 1, k), Bc
     else:
         levels.append(AmgLevel(A, free, degree=degree, eta=eta))
     last = levels[-1]

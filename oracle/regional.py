@@ -139,6 +139,22 @@ def power_method(L: Level, x0, iters: int):
     return lam
 
 
+def finest_coordinates(levels):
+    """Coordinates (n, 3) of the last level's composite nodes (x fastest) on the finest lattice,
+    relative to the finest lattice's centre: each coarse lattice line is a line of the level above
+    (Layout.fine_positions), followed up to level 0."""
+    lay = levels[-1].lay
+    axes = []
+    for d in range(lay.dim):
+        p = np.arange(int(lay.shape_xyz[d]))
+        for L in reversed(levels[1:]):
+            p = np.asarray(L.lay.fine_positions[d])[p]
+        n0 = int(levels[0].lay.shape_xyz[d])
+        axes.append(p - 0.5 * (n0 - 1))
+    grids = np.meshgrid(*axes[::-1], indexing="ij")  # (z, y, x) order, x fastest
+    return np.stack([g.reshape(-1) for g in grids[::-1]], axis=1)
+
+
 def coarse_composite(lay: Layout, coefs):
     """Abar = Psi-bar [[Abar]] Psi-bar^T as a dense matrix."""
     return assembly.assemble_from_regions(lay, coefs).toarray()
@@ -153,10 +169,19 @@ def setup(lay0: Layout, coefs0, opt: Options, P0=None):
         levels.append(L)
         if l == opt.nlevels - 1:
             if opt.coarse_amg:  # Section 3.5: an AMG V-cycle on Abar replaces the direct solver
-                if lay.ndof != 1:
-                    raise ValueError("the AMG coarse solver handles scalar problems")
-                L.amg = amg.setup(assembly.assemble_from_regions(lay, coefs), ~lay.dirichlet.reshape(-1),
-                                  opt.amg_coarse_size, opt.degree, opt.eig_ratio)
+                Ab = assembly.assemble_from_regions(lay, coefs)
+                free = ~lay.dirichlet.reshape(-1)
+                if lay.ndof == 1:
+                    L.amg = amg.setup(Ab, free, opt.amg_coarse_size, opt.degree, opt.eig_ratio)
+                elif lay.ndof == 3 and lay.dim == 3:
+                    # the near-null space from the region hierarchy: rigid-body modes at the
+                    # coarsest nodes' positions on the finest lattice (coarse points are fine nodes)
+                    B = amg.rigid_body_modes(finest_coordinates(levels))
+                    nn = free.size
+                    L.amg = amg.setup(Ab, np.repeat(free, 3), opt.amg_coarse_size, opt.degree, opt.eig_ratio,
+                                      nodes=np.arange(0, 3 * nn + 1, 3), B=B)
+                else:
+                    raise ValueError("the AMG coarse solver handles scalar problems and 3D elasticity")
             else:
                 L.Abar = coarse_composite(lay, coefs)
             break
