@@ -135,9 +135,14 @@ typedef struct {
                          (hybrid hierarchy only) */
   int coarse_amg;     /* coarse solver of the region hierarchy (Section 3.5): 0 (default) the
                          dense inverse of Abar (at most 20,000 composite dofs); 1: one V-cycle of
-                         smoothed-aggregation AMG on Abar (scalar problems, geometric region
-                         hierarchy): staged plain aggregation of the free rows (roots, joins,
-                         leftovers), P = (I - omega D^-1 A) T with omega = 4 / (3 rho) and rho the
+                         smoothed-aggregation AMG on Abar (geometric region hierarchy; scalar
+                         problems and 3D elasticity): staged plain aggregation of the free rows
+                         (roots, joins, leftovers) -- for elasticity of the free nodes, on the graph
+                         of blocks with Frobenius norm > 1e-12 sqrt(||A_II|| ||A_JJ||) --, the
+                         tentative prolongator (a 1 per aggregated row; for elasticity a thin QR
+                         per aggregate of the six rigid-body modes at the coarsest nodes' positions
+                         on the finest lattice, the coarse nodes being the aggregates with six dofs
+                         each), P = (I - omega D^-1 A) T with omega = 4 / (3 rho) and rho the
                          Gershgorin bound max_i sum_j |a_ij| / a_ii, coarse operators P^T A P, the
                          degree-cheb_degree Chebyshev smoother on [rho / eig_ratio, rho] before and
                          after each coarse correction, and a dense inverse on the first AMG level

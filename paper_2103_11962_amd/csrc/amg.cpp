@@ -5,6 +5,11 @@
 //    (one composite matrix has no interfaces), on the graph of couplings |a_ij| >
 //    1e-12 sqrt(a_ii a_jj) between free rows (rounding residue of a Galerkin product is no
 //    coupling); Dirichlet rows are not aggregated;
+//  * systems (3D elasticity): the near-null space from the region hierarchy, the six rigid-body
+//    modes at the coarsest nodes' positions on the finest lattice; aggregation on the node graph
+//    (blocks of Frobenius norm > 1e-12 sqrt(||A_II|| ||A_JJ||)), the tentative prolongator from a
+//    thin QR of each aggregate's rows of the near-null space (diag R >= 0), coarse nodes = the
+//    aggregates with six dofs each and near-null space R;
 //  * tentative prolongator T (a 1 per aggregated row), smoothed P = (I - omega D^-1 A) T with
 //    omega = 4 / (3 rho) and rho = max_i sum_j |a_ij| / a_ii (Gershgorin's bound on
 //    lambda_max(D^-1 A));
@@ -26,6 +31,9 @@ namespace {
 
 constexpr double kStrength = 1e-12;  // relative size below which an entry is no graph coupling
 constexpr int kMaxAmgLevels = 20;
+constexpr int kRigidModes = 6;       // near-null space of 3D elasticity
+
+void spgemm(const Csr& X, const Csr& Y, Csr& Z);
 
 void stencil_offset_host(int npts, int s, int& dx, int& dy, int& dz) {
   if (npts == 27) {
@@ -44,12 +52,13 @@ void stencil_offset_host(int npts, int s, int& dx, int& dy, int& dz) {
 // owner copy of every composite node (the lowest region containing it).
 void composite_matrix(rmg_handle* h, const Level& L, Csr& A, std::vector<uint8_t>& free, std::vector<int32_t>& owner) {
   hipStream_t st = h->stream;
-  const int64_t n = L.ncomp;
-  std::vector<double> coef(coef_elems(L.n, L.npts));
+  const int nd = L.ndof, nc = L.ncoef();
+  const int64_t n = L.ncomp * nd;
+  std::vector<double> coef(coef_elems(L.n, nc));
   RMG_HIP(hipMemcpyAsync(coef.data(), L.coef.p, sizeof(double) * coef.size(), hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));
   std::vector<std::vector<std::pair<int32_t, double>>> rows((size_t)n);
-  owner.assign((size_t)n, -1);
+  owner.assign((size_t)L.ncomp, -1);
   const int cx = L.comp[0], cy = L.comp[1];
   for (int k = 0; k < L.nreg; ++k) {
     const RegionGeo& R = L.regs[k];
@@ -63,10 +72,12 @@ void composite_matrix(rmg_handle* h, const Level& L, Csr& A, std::vector<uint8_t
             int dx, dy, dz;
             stencil_offset_host(L.npts, s, dx, dy, dz);
             if (x + dx < 0 || x + dx >= R.ex || y + dy < 0 || y + dy >= R.ey || z + dz < 0 || z + dz >= R.ez) continue;
-            const double v = coef[coef_index(R.off + li, s, L.npts)];
-            if (v == 0.0) continue;
             const int64_t j = ((int64_t)(R.oz + z + dz) * cy + (R.oy + y + dy)) * cx + (R.ox + x + dx);
-            rows[i].push_back({(int32_t)j, v});
+            for (int a = 0; a < nd; ++a)
+              for (int b = 0; b < nd; ++b) {  // block (a, b) of offset s
+                const double v = coef[coef_index(R.off + li, (s * nd + a) * nd + b, nc)];
+                if (v != 0.0) rows[i * nd + a].push_back({(int32_t)(j * nd + b), v});
+              }
           }
         }
   }
@@ -91,11 +102,198 @@ void composite_matrix(rmg_handle* h, const Level& L, Csr& A, std::vector<uint8_t
   }
   free.assign((size_t)n, 1);
   const unsigned m = L.mask;
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t i = 0; i < L.ncomp; ++i) {
     const int gx = (int)(i % cx), gy = (int)((i / cx) % cy), gz = (int)(i / ((int64_t)cx * cy));
     const bool dir = ((m & 1u) && gx == 0) || ((m & 2u) && gx == cx - 1) || ((m & 4u) && gy == 0) ||
                      ((m & 8u) && gy == cy - 1) || ((m & 16u) && gz == 0) || ((m & 32u) && gz == L.comp[2] - 1);
-    free[i] = dir ? 0 : 1;
+    for (int a = 0; a < nd; ++a) free[i * nd + a] = dir ? 0 : 1;  // a Dirichlet node fixes all its dofs
+  }
+}
+
+// Positions of the coarsest level's composite nodes (x fastest) on the finest lattice, relative
+// to its centre: every coarse lattice line is the line of the level above at the region's coarse
+// point min(3 X, extent - 1), followed up to level 0.
+std::vector<double> finest_coordinates(rmg_handle* h) {
+  const int nl = (int)h->levels.size();
+  const Level& Lc = *h->levels[nl - 1];
+  std::vector<std::vector<double>> axis(3);
+  for (int d = 0; d < 3; ++d) {
+    std::vector<int64_t> p((size_t)Lc.comp[d]);
+    for (int64_t i = 0; i < Lc.comp[d]; ++i) p[(size_t)i] = i;
+    for (int l = nl - 1; l >= 1; --l) {
+      const Level& C = *h->levels[l];
+      const Level& F = *h->levels[l - 1];
+      std::vector<int64_t> line((size_t)C.comp[d], -1);
+      for (int k = 0; k < C.nreg; ++k) {
+        const int co[3] = {C.regs[k].ox, C.regs[k].oy, C.regs[k].oz}, ce[3] = {C.regs[k].ex, C.regs[k].ey, C.regs[k].ez};
+        const int fo[3] = {F.regs[k].ox, F.regs[k].oy, F.regs[k].oz}, fe[3] = {F.regs[k].ex, F.regs[k].ey, F.regs[k].ez};
+        for (int X = 0; X < ce[d]; ++X) line[(size_t)(co[d] + X)] = fo[d] + std::min(3 * X, fe[d] - 1);
+      }
+      for (auto& v : p) {
+        RMG_REQUIRE(line[(size_t)v] >= 0, RMG_ERR_SHAPE, "internal: coarse lattice line without a fine line");
+        v = line[(size_t)v];
+      }
+    }
+    const double c = 0.5 * (h->levels[0]->comp[d] - 1);
+    axis[d].resize(p.size());
+    for (size_t i = 0; i < p.size(); ++i) axis[d][i] = (double)p[i] - c;
+  }
+  std::vector<double> X((size_t)Lc.ncomp * 3);
+  for (int64_t i = 0; i < Lc.ncomp; ++i) {
+    const int64_t gx = i % Lc.comp[0], gy = (i / Lc.comp[0]) % Lc.comp[1], gz = i / ((int64_t)Lc.comp[0] * Lc.comp[1]);
+    X[(size_t)i * 3] = axis[0][(size_t)gx];
+    X[(size_t)i * 3 + 1] = axis[1][(size_t)gy];
+    X[(size_t)i * 3 + 2] = axis[2][(size_t)gz];
+  }
+  return X;
+}
+
+// Rigid-body modes (rows node-major, dof fastest; k = 6 columns, row-major): translations, then
+// the rotations (-y, x, 0), (0, -z, y), (z, 0, -x).
+std::vector<double> rigid_body_modes(const std::vector<double>& X) {
+  const size_t n = X.size() / 3;
+  std::vector<double> B(n * 3 * 6, 0.0);
+  for (size_t i = 0; i < n; ++i) {
+    const double x = X[i * 3], y = X[i * 3 + 1], z = X[i * 3 + 2];
+    double* r0 = &B[(i * 3) * 6];
+    double* r1 = &B[(i * 3 + 1) * 6];
+    double* r2 = &B[(i * 3 + 2) * 6];
+    r0[0] = r1[1] = r2[2] = 1.0;
+    r0[3] = -y;
+    r1[3] = x;
+    r1[4] = -z;
+    r2[4] = y;
+    r0[5] = z;
+    r2[5] = -x;
+  }
+  return B;
+}
+
+// Node graph of a system: nodes I, J (dof ranges nodes[I] .. nodes[I+1]) coupled when their block
+// has Frobenius norm > kStrength sqrt(||A_II|| ||A_JJ||); free when all their rows are.
+void node_graph(const Csr& A, const std::vector<int64_t>& nodes, const std::vector<uint8_t>& free,
+                std::vector<int64_t>& ptr, std::vector<int32_t>& col, std::vector<double>& val,
+                std::vector<uint8_t>& nfree) {
+  const int64_t nn = (int64_t)nodes.size() - 1;
+  std::vector<int32_t> node((size_t)A.rows);
+  for (int64_t I = 0; I < nn; ++I)
+    for (int64_t r = nodes[I]; r < nodes[I + 1]; ++r) node[(size_t)r] = (int32_t)I;
+  std::vector<std::vector<std::pair<int32_t, double>>> sq((size_t)nn);  // squared block norms
+  for (int64_t I = 0; I < nn; ++I) {
+    auto& row = sq[(size_t)I];
+    for (int64_t r = nodes[I]; r < nodes[I + 1]; ++r)
+      for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e) row.push_back({node[(size_t)A.col[e]], A.val[e] * A.val[e]});
+    std::stable_sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    size_t w = 0;
+    for (size_t e = 0; e < row.size();) {
+      const int32_t J = row[e].first;
+      double acc = 0.0;
+      for (; e < row.size() && row[e].first == J; ++e) acc += row[e].second;
+      row[w++] = {J, acc};
+    }
+    row.resize(w);
+  }
+  std::vector<double> dn((size_t)nn, 0.0);
+  for (int64_t I = 0; I < nn; ++I)
+    for (const auto& e : sq[(size_t)I])
+      if (e.first == I) dn[(size_t)I] = std::sqrt(e.second);
+  ptr.assign(1, 0);
+  col.clear();
+  val.clear();
+  for (int64_t I = 0; I < nn; ++I) {
+    for (const auto& e : sq[(size_t)I]) {
+      const double f = std::sqrt(e.second);
+      if (e.first == I || f > kStrength * std::sqrt(dn[(size_t)I] * dn[(size_t)e.first])) {
+        col.push_back(e.first);
+        val.push_back(f);
+      }
+    }
+    ptr.push_back((int64_t)col.size());
+  }
+  nfree.assign((size_t)nn, 1);
+  for (int64_t I = 0; I < nn; ++I)
+    for (int64_t r = nodes[I]; r < nodes[I + 1]; ++r)
+      if (!free[(size_t)r]) nfree[(size_t)I] = 0;
+}
+
+// Tentative prolongator of a system: per aggregate (its dofs ascending), B_a = Q R by modified
+// Gram-Schmidt with a second pass (diag R > 0); Q fills the aggregate's k columns, R its k rows of
+// the coarse near-null space Bc.  RMG_ERR_NUMERIC when an aggregate has fewer dofs than k or its
+// rows of B are rank deficient.
+void tentative_system(const std::vector<int32_t>& agg, int64_t na, const std::vector<int64_t>& nodes,
+                      const std::vector<double>& B, int k, int64_t nrows, Csr& T, std::vector<double>& Bc) {
+  std::vector<std::vector<int64_t>> members((size_t)na);
+  for (size_t I = 0; I < agg.size(); ++I)
+    if (agg[I] >= 0)
+      for (int64_t r = nodes[I]; r < nodes[I + 1]; ++r) members[(size_t)agg[I]].push_back(r);
+  std::vector<std::vector<std::pair<int32_t, double>>> rows((size_t)nrows);
+  Bc.assign((size_t)na * k * k, 0.0);
+  for (int64_t a = 0; a < na; ++a) {
+    auto& dofs = members[(size_t)a];
+    std::sort(dofs.begin(), dofs.end());
+    const size_t m = dofs.size();
+    RMG_REQUIRE(m >= (size_t)k, RMG_ERR_NUMERIC, "AMG: an aggregate has fewer dofs than the near-null space");
+    std::vector<double> Q(m * k), R((size_t)k * k, 0.0);
+    for (size_t i = 0; i < m; ++i)
+      for (int j = 0; j < k; ++j) Q[i * k + j] = B[(size_t)dofs[i] * k + j];
+    for (int j = 0; j < k; ++j) {
+      for (int pass = 0; pass < 2; ++pass)
+        for (int q = 0; q < j; ++q) {
+          double s = 0.0;
+          for (size_t i = 0; i < m; ++i) s += Q[i * k + q] * Q[i * k + j];
+          for (size_t i = 0; i < m; ++i) Q[i * k + j] -= s * Q[i * k + q];
+          R[(size_t)q * k + j] += s;
+        }
+      double nrm = 0.0;
+      for (size_t i = 0; i < m; ++i) nrm += Q[i * k + j] * Q[i * k + j];
+      nrm = std::sqrt(nrm);
+      RMG_REQUIRE(nrm > 0.0 && std::isfinite(nrm), RMG_ERR_NUMERIC, "AMG: near-null space rank deficient on an aggregate");
+      R[(size_t)j * k + j] = nrm;
+      for (size_t i = 0; i < m; ++i) Q[i * k + j] /= nrm;
+    }
+    for (size_t i = 0; i < m; ++i)
+      for (int j = 0; j < k; ++j) rows[(size_t)dofs[i]].push_back({(int32_t)(a * k + j), Q[i * k + j]});
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Bc[((size_t)a * k + i) * k + j] = R[(size_t)i * k + j];
+  }
+  T.rows = nrows;
+  T.cols = na * k;
+  T.ptr.assign(1, 0);
+  T.col.clear();
+  T.val.clear();
+  for (int64_t r = 0; r < nrows; ++r) {
+    for (const auto& e : rows[(size_t)r]) {
+      T.col.push_back(e.first);
+      T.val.push_back(e.second);
+    }
+    T.ptr.push_back((int64_t)T.col.size());
+  }
+}
+
+// P = T - omega D^-1 A T for a general T (exact zeros dropped, columns ascending).
+void smooth_tentative(const Csr& A, const std::vector<double>& diag, const Csr& T, double omega, Csr& P) {
+  Csr AT;
+  spgemm(A, T, AT);
+  P.rows = T.rows;
+  P.cols = T.cols;
+  P.ptr.assign(1, 0);
+  P.col.clear();
+  P.val.clear();
+  for (int64_t i = 0; i < T.rows; ++i) {
+    const double dinv = 1.0 / diag[(size_t)i];
+    int64_t e = T.ptr[i], q = AT.ptr[i];
+    while (e < T.ptr[i + 1] || q < AT.ptr[i + 1]) {
+      const int32_t ce = e < T.ptr[i + 1] ? T.col[e] : INT32_MAX, cq = q < AT.ptr[i + 1] ? AT.col[q] : INT32_MAX;
+      const int32_t c = std::min(ce, cq);
+      const double t = ce == c ? T.val[e++] : 0.0;
+      const double s = cq == c ? AT.val[q++] : 0.0;
+      const double v = t - omega * (dinv * s);
+      if (v != 0.0) {
+        P.col.push_back(c);
+        P.val.push_back(v);
+      }
+    }
+    P.ptr.push_back((int64_t)P.col.size());
   }
 }
 
@@ -311,7 +509,8 @@ void amg_destroy(rmg_handle* h) {
 
 void amg_setup(rmg_handle* h, Level& L) {
   amg_destroy(h);
-  RMG_REQUIRE(L.ndof == 1, RMG_ERR_ARG, "the AMG coarse solver handles scalar problems");
+  RMG_REQUIRE(L.ndof == 1 || (L.ndof == 3 && L.dim == 3), RMG_ERR_ARG,
+              "the AMG coarse solver handles scalar problems and 3D elasticity");
   hipStream_t st = h->stream;
   const rmg_options& o = h->opt;
   auto* amg = new Amg();
@@ -322,6 +521,15 @@ void amg_setup(rmg_handle* h, Level& L) {
   composite_matrix(h, L, A, free, owner);
   RMG_REQUIRE(A.rows < ((int64_t)1 << 31), RMG_ERR_SHAPE, "coarsest composite problem too large");
   L.nc = (int)A.rows;
+  // systems: dof offsets of the nodes and the near-null space (rows x kRigidModes, row-major)
+  const bool sys = L.ndof == 3;
+  std::vector<int64_t> nodes;
+  std::vector<double> B;
+  if (sys) {
+    nodes.resize((size_t)L.ncomp + 1);
+    for (int64_t I = 0; I <= L.ncomp; ++I) nodes[(size_t)I] = 3 * I;
+    B = rigid_body_modes(finest_coordinates(h));
+  }
   upload(L.comp_owner, owner, st);
   L.cvec.alloc(sizeof(double) * (size_t)L.nc);
   L.cvec2.alloc(sizeof(double) * (size_t)L.nc);
@@ -335,7 +543,21 @@ void amg_setup(rmg_handle* h, Level& L) {
     const std::vector<double> diag = diagonal(V.A);
     for (int64_t i = 0; i < V.A.rows; ++i)
       RMG_REQUIRE(diag[i] > 0.0, RMG_ERR_NUMERIC, "AMG: diagonal not positive");
-    const int64_t nc = aggregates(V.A, diag, free, V.agg);
+    int64_t nc = 0;
+    Csr T;
+    std::vector<double> Bc;
+    if (!sys) {
+      nc = aggregates(V.A, diag, free, V.agg);
+    } else {
+      std::vector<int64_t> gp;
+      std::vector<int32_t> gc;
+      std::vector<double> gv;
+      std::vector<uint8_t> nfree;
+      node_graph(V.A, nodes, free, gp, gc, gv, nfree);
+      const int64_t na = aggregate_plain(gp, gc, gv, nfree, V.agg);
+      nc = na * kRigidModes;
+      if (na > 0 && nc < V.A.rows) tentative_system(V.agg, na, nodes, B, kRigidModes, V.A.rows, T, Bc);
+    }
     if (nc == 0 || nc >= V.A.rows) {
       V.agg.clear();
       break;
@@ -348,12 +570,18 @@ void amg_setup(rmg_handle* h, Level& L) {
     }
     V.rho = rho;
     V.omega = 4.0 / (3.0 * rho);
-    smoothed_prolongator(V.A, diag, V.agg, nc, V.omega, V.P);
+    if (!sys) smoothed_prolongator(V.A, diag, V.agg, nc, V.omega, V.P);
+    else smooth_tentative(V.A, diag, T, V.omega, V.P);
     Csr AP, Pt;
     spgemm(V.A, V.P, AP);
     transpose(V.P, Pt);
     spgemm(Pt, AP, A);
     free.assign((size_t)nc, 1);
+    if (sys) {  // the aggregates become the coarse nodes, with kRigidModes dofs each
+      nodes.resize((size_t)nc / kRigidModes + 1);
+      for (size_t I = 0; I < nodes.size(); ++I) nodes[I] = (int64_t)I * kRigidModes;
+      B.swap(Bc);
+    }
   }
   // device arrays
   const int nl = (int)amg->lv.size();

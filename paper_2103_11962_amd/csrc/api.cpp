@@ -528,7 +528,8 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
               "amg_coarse_size must be in [1, 20000]");
   RMG_REQUIRE(!opt->coarse_amg || !opt->hybrid, RMG_ERR_ARG,
               "the AMG coarse solver belongs to the geometric region hierarchy (not the hybrid one)");
-  RMG_REQUIRE(!opt->coarse_amg || h->ndof == 1, RMG_ERR_ARG, "the AMG coarse solver handles scalar problems");
+  RMG_REQUIRE(!opt->coarse_amg || h->ndof == 1 || (h->ndof == 3 && h->dim == 3), RMG_ERR_ARG,
+              "the AMG coarse solver handles scalar problems and 3D elasticity");
   h->opt = *opt;
   h->autotune_cache = opt->autotune_cache ? std::string(opt->autotune_cache) : std::string();
   h->opt.autotune_cache = nullptr;  // the caller's string is borrowed for this call only

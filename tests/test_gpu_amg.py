@@ -1,5 +1,6 @@
 """AMG coarse solver below the region hierarchy (Section 3.5, second coarse-level option) on the
-GPU against the oracle: every AMG level's matrix and smoothed prolongator, one region V-cycle, PCG
+GPU against the oracle: every AMG level's matrix and smoothed prolongator (scalar problems, and 3D
+elasticity with the rigid-body near-null space on node aggregates), one region V-cycle, PCG
 histories, the FP32 V-cycle, graph replay, option errors, and the full-size 3D Laplacian with
 three region levels, whose coarsest composite operator (37^3 = 50,653 dofs) is too large for the
 dense inverse.
@@ -14,8 +15,8 @@ pytestmark = pytest.mark.gpu
 
 # (workload, region levels, rows of the directly solved AMG level)
 CASES = [("c2_mid", 2, 200), ("c1", 2, 100), ("uneven3d_small", 2, 30), ("uneven_c4_small", 3, 40),
-         ("c2_small", 2, 20)]
-IDS = [c[0] for c in CASES]
+         ("c2_small", 2, 20), ("c3_small", 2, 200), ("c3_small", 2, 60)]
+IDS = [f"{c[0]}-{c[2]}" for c in CASES]
 
 
 @pytest.fixture(scope="module")
@@ -121,12 +122,6 @@ def test_amg_option_errors(hip_device):
     assert e.value.status == "RMG_ERR_NOT_SETUP"
     h.setup_hierarchy(nlevels=2, cheb_degree=2)  # back to the direct solver
     assert h.amg_levels() == 0
-    h.close()
-    e3 = synth.workload("c3_small")
-    h = harness.gpu_problem(e3, setup=False)
-    with pytest.raises(regmg.RmgError) as e:
-        h.setup_hierarchy(nlevels=2, cheb_degree=2, coarse_amg=1)
-    assert e.value.status == "RMG_ERR_ARG"
     h.close()
 
 
