@@ -69,6 +69,11 @@ __device__ __forceinline__ void decompose(const RegionGeo& R, int li, int& x, in
 
 // 1/m for a coarse interval of m = 1, 2 or 3 cells.  num * (1/m) equals num / m exactly for
 // 0 <= num <= m (2 * (1/3) rounds like 2/3, 3 * (1/3) rounds to 1), with no division.
+// Node class of a region's class tables along an axis of extent e >= 5: the coordinate on the two
+// low layers (0, 1), 2 inside, 3 and 4 on the two high layers; and the first node of class c.
+__device__ __forceinline__ int axis_class(int v, int e) { return v < 2 ? v : (v >= e - 2 ? v - e + 5 : 2); }
+__device__ __forceinline__ int class_node(int c, int e) { return c <= 2 ? c : e - 5 + c; }
+
 __device__ __forceinline__ double inv_span(int m) { return m == 3 ? 1.0 / 3.0 : (m == 2 ? 0.5 : 1.0); }
 
 // Rate-3 coarsening of one region axis of e fine nodes into E coarse nodes: coarse node C sits at

@@ -672,10 +672,12 @@ void launch_prolong_add(const Level& F, const Level& C, bool lowp, const void* u
 // live in LDS (one column per thread).  Dirichlet reading: a Dirichlet coarse row only collects
 // Dirichlet fine nodes; entries of a free row towards Dirichlet coarse nodes are zero.  STORED
 // weights come from the fine nodes' records (rate-3 lattice, extents 3^k + 1).
+// DIRONLY: only the Dirichlet coarse rows, thread t taking row list[t] (region, index) of nlist.
 template <int NPTSF, int DIM, int NDOF, int BS, bool STORED, bool DIRONLY = false>
 __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const double* __restrict__ coefF,
                                             double* __restrict__ coefC, const double* __restrict__ pw,
-                                            const double* __restrict__ rw) {
+                                            const double* __restrict__ rw, const BlockDesc* __restrict__ list = nullptr,
+                                            int64_t nlist = 0) {
   constexpr int NC = DIM == 3 ? 27 : 9;
   constexpr int NB = NDOF * NDOF;
   constexpr int SUB = kBlock / BS;
@@ -683,10 +685,19 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
   const int tid = threadIdx.x;
 #pragma unroll
   for (int o = 0; o < NC * NB; ++o) acc[o][tid] = 0.0;
-  const BlockDesc bd = C.blocks[blockIdx.x / SUB];
+  BlockDesc bd;
+  int li;
+  if constexpr (DIRONLY) {
+    const int64_t t = (int64_t)blockIdx.x * BS + tid;
+    if (t >= nlist) return;  // no block-wide synchronisation below: private LDS columns
+    bd = list[t];
+    li = bd.start;
+  } else {
+    bd = C.blocks[blockIdx.x / SUB];
+    li = bd.start + (int)(blockIdx.x % SUB) * BS + tid;
+  }
   const RegionGeo RC = C.regs[bd.region];
   const RegionGeo RF = F.regs[bd.region];
-  const int li = bd.start + (int)(blockIdx.x % SUB) * BS + tid;
   if (li >= RC.n) return;  // no block-wide synchronisation below: private LDS columns
   int X, Y, Z;
   decompose(RC, li, X, Y, Z);
@@ -792,9 +803,22 @@ __global__ __launch_bounds__(BS) void k_rap(LevelView F, LevelView C, const doub
 template <int AX, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_rap_axis(const RegionGeo* __restrict__ gin, const RegionGeo* __restrict__ gout,
                                                      const BlockDesc* __restrict__ blocks, const double* __restrict__ sin_,
-                                                     double* __restrict__ sout, LevelView C) {
+                                                     double* __restrict__ sout, LevelView C,
+                                                     const double* __restrict__ sym, const double* __restrict__ table,
+                                                     const int* __restrict__ served) {
   const BlockDesc bd = blocks[blockIdx.x];
   const RegionGeo RI = gin[bd.region], RO = gout[bd.region];
+  // The x pass of a symmetric level takes the couplings its stencil operations apply: the stored
+  // upper half and the neighbours' mirrored upper couplings (sym), or, in a region served by its
+  // class tables, the same values from the table; otherwise the stored stencils.
+  // (the region's table is copied to LDS once per block: every fine node reads 27 of its entries)
+  __shared__ double stab[AX == 0 ? kClasses * kClassPts : 1];
+  const bool use_tab = AX == 0 && table && served && served[bd.region];
+  if (use_tab) {
+    const double* __restrict__ tg = table + (int64_t)bd.region * kClasses * kClassPts;
+    for (int e = threadIdx.x; e < kClasses * kClassPts; e += kBlock) stab[e] = tg[e];
+    __syncthreads();
+  }
   const int li = bd.start + (int)threadIdx.x;
   if (li >= RO.n) return;
   int o[3];
@@ -815,33 +839,55 @@ __global__ __launch_bounds__(kBlock) void k_rap_axis(const RegionGeo* __restrict
 #pragma unroll
   for (int q = 0; q < 27; ++q) acc[q] = 0.0;
   constexpr int kStride = AX == 0 ? 1 : (AX == 1 ? 3 : 9);  // stencil-index step of the coarsened axis
+  // The products, with the couplings read by `get(fi, gi, tcb, s)`; each source is its own copy of
+  // the loops, so that the loads of one fine node are issued together.
+  auto accumulate = [&](auto get) {
 #pragma unroll
-  for (int t = -2; t <= 2; ++t) {
-    const int f = pos + t;
-    const double wf = tap(t, mL, mR);
-    if ((unsigned)f >= (unsigned)ein || wf == 0.0) continue;
-    int fi[3] = {o[0], o[1], o[2]};
-    fi[AX] = f;
-    const int64_t gi = RI.off + ((int64_t)fi[2] * RI.ey + fi[1]) * RI.ex + fi[0];
+    for (int t = -2; t <= 2; ++t) {
+      const int f = pos + t;
+      const double wf = tap(t, mL, mR);
+      if ((unsigned)f >= (unsigned)ein || wf == 0.0) continue;
+      int fi[3] = {o[0], o[1], o[2]};
+      fi[AX] = f;
+      const int64_t gi = RI.off + ((int64_t)fi[2] * RI.ey + fi[1]) * RI.ex + fi[0];
+      const int tcb =
+          use_tab ? ((axis_class(fi[2], RI.ez) * 5 + axis_class(fi[1], RI.ey)) * 5 + axis_class(fi[0], RI.ex)) * kClassPts
+                  : 0;
 #pragma unroll
-    for (int da = -1; da <= 1; ++da) {
-      if ((unsigned)(f + da) >= (unsigned)ein) continue;
-      int o0;
-      double w0, w1;
-      interval_weights(t + da, mL, mR, o0, w0, w1);
+      for (int da = -1; da <= 1; ++da) {
+        if ((unsigned)(f + da) >= (unsigned)ein) continue;
+        int o0;
+        double w0, w1;
+        interval_weights(t + da, mL, mR, o0, w0, w1);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {  // the two other offsets
-        const int d1 = q % 3, d2 = q / 3;  // 0..2
-        int sbase;
-        if constexpr (AX == 0) sbase = d2 * 9 + d1 * 3;
-        else if constexpr (AX == 1) sbase = d2 * 9 + d1;
-        else sbase = d2 * 3 + d1;
-        const double a = sin_[coef_index(gi, sbase + (da + 1) * kStride, 27)];
-        const double wa = wf * a;
-        acc[sbase + (o0 + 1) * kStride] += wa * w0;
-        if (o0 + 2 <= 2) acc[sbase + (o0 + 2) * kStride] += wa * w1;
+        for (int q = 0; q < 9; ++q) {  // the two other offsets
+          const int d1 = q % 3, d2 = q / 3;  // 0..2
+          int sbase;
+          if constexpr (AX == 0) sbase = d2 * 9 + d1 * 3;
+          else if constexpr (AX == 1) sbase = d2 * 9 + d1;
+          else sbase = d2 * 3 + d1;
+          const double wa = wf * get(fi, gi, tcb, sbase + (da + 1) * kStride);
+          acc[sbase + (o0 + 1) * kStride] += wa * w0;
+          if (o0 + 2 <= 2) acc[sbase + (o0 + 2) * kStride] += wa * w1;
+        }
       }
     }
+  };
+  if (use_tab) {
+    accumulate([&](const int*, int64_t, int tcb, int sidx) { return stab[tcb + sidx]; });
+  } else if (AX == 0 && sym) {
+    accumulate([&](const int* fi, int64_t gi, int, int sidx) {
+      if (sidx >= 13) return sym[coef_index(gi, sidx - 13, kSymPts)];
+      // the neighbour's upper coupling towards this node, 0 outside the region
+      int dx, dy, dz;
+      stencil_offset<27>(sidx, dx, dy, dz);
+      const bool in = (unsigned)(fi[0] + dx) < (unsigned)RI.ex && (unsigned)(fi[1] + dy) < (unsigned)RI.ey &&
+                      (unsigned)(fi[2] + dz) < (unsigned)RI.ez;
+      return in ? sym[coef_index(gi + dx + (int64_t)dy * RI.ex + (int64_t)dz * RI.ex * RI.ey, 13 - sidx, kSymPts)]
+                : 0.0;
+    });
+  } else {
+    accumulate([&](const int*, int64_t gi, int, int sidx) { return sin_[coef_index(gi, sidx, 27)]; });
   }
   const int64_t go = RO.off + li;
   if constexpr (LAST) {
@@ -889,17 +935,42 @@ static void launch_rap_separable(const Level& F, Level& C, hipStream_t st) {
   s1.alloc(sizeof(double) * coef_elems(n1, 27));
   s2.alloc(sizeof(double) * coef_elems(n2, 27));
   const LevelView cv = C.view();
+  const bool tables = F.class_table.p && F.class_table_ok.p;
   RMG_LAUNCH((k_rap_axis<0, false>), dim3(b1.size()), dim3(kBlock), 0, st, F.d_regs.as<RegionGeo>(),
-             dg1.as<RegionGeo>(), db1.as<BlockDesc>(), F.coef.as<double>(), s1.as<double>(), cv);
+             dg1.as<RegionGeo>(), db1.as<BlockDesc>(), F.coef.as<double>(), s1.as<double>(), cv,
+             F.coef_sym.as<double>(), tables ? F.class_table.as<double>() : nullptr,
+             tables ? F.class_table_ok.as<int>() : nullptr);
   RMG_LAUNCH((k_rap_axis<1, false>), dim3(b2.size()), dim3(kBlock), 0, st, dg1.as<RegionGeo>(),
-             dg2.as<RegionGeo>(), db2.as<BlockDesc>(), s1.as<double>(), s2.as<double>(), cv);
+             dg2.as<RegionGeo>(), db2.as<BlockDesc>(), s1.as<double>(), s2.as<double>(), cv, nullptr, nullptr,
+             nullptr);
   RMG_LAUNCH((k_rap_axis<2, true>), dim3(C.blocks.size()), dim3(kBlock), 0, st, dg2.as<RegionGeo>(),
-             C.d_regs.as<RegionGeo>(), C.d_blocks.as<BlockDesc>(), s2.as<double>(), C.coef.as<double>(), cv);
+             C.d_regs.as<RegionGeo>(), C.d_blocks.as<BlockDesc>(), s2.as<double>(), C.coef.as<double>(), cv, nullptr,
+             nullptr, nullptr);
   LAUNCH_CHECK();
-  // Dirichlet coarse rows
-  RMG_LAUNCH((k_rap<27, 3, 1, kBlock, false, true>), dim3(C.blocks.size()), dim3(kBlock), 0, st, F.view(), cv,
-             F.coef.as<double>(), C.coef.as<double>(), nullptr, nullptr);
-  LAUNCH_CHECK();
+  // Dirichlet coarse rows, one thread each from the list of them (rows or planes on a Dirichlet
+  // face entirely, else the two end nodes of the row)
+  std::vector<BlockDesc> drows;
+  const unsigned m = C.mask;
+  auto dir = [&](int g, int n, unsigned lo, unsigned hi) { return ((m & lo) && g == 0) || ((m & hi) && g == n - 1); };
+  for (int k = 0; k < C.nreg; ++k) {
+    const RegionGeo& R = C.regs[k];
+    for (int z = 0; z < R.ez; ++z)
+      for (int y = 0; y < R.ey; ++y) {
+        const bool whole = dir(R.oz + z, C.comp[2], 16u, 32u) || dir(R.oy + y, C.comp[1], 4u, 8u);
+        for (int x = 0; x < R.ex; x = (whole || x + 1 == R.ex || R.ex < 2) ? x + 1 : R.ex - 1)
+          if (whole || dir(R.ox + x, C.comp[0], 1u, 2u)) drows.push_back(BlockDesc{k, (z * R.ey + y) * R.ex + x});
+      }
+  }
+  if (!drows.empty()) {
+    DBuf dl;
+    dl.alloc(sizeof(BlockDesc) * drows.size());
+    RMG_HIP(hipMemcpyAsync(dl.p, drows.data(), dl.bytes, hipMemcpyHostToDevice, st));
+    RMG_LAUNCH((k_rap<27, 3, 1, kBlock, false, true>), dim3(cdiv((int64_t)drows.size(), kBlock)), dim3(kBlock), 0, st,
+               F.view(), cv, F.coef.as<double>(), C.coef.as<double>(), nullptr, nullptr, dl.as<BlockDesc>(),
+               (int64_t)drows.size());
+    LAUNCH_CHECK();
+    RMG_HIP(hipStreamSynchronize(st));  // before the list is released
+  }
   // the intermediates are freed when this returns: wait for the passes that read them
   RMG_HIP(hipStreamSynchronize(st));
 }
@@ -1071,41 +1142,51 @@ void launch_coarse_solve(const Level& L, bool lowp, const void* b, void* u, hipS
 // (stored nb x n), the rank-nb update of A_RR as a tiled GEMM, and the panel rows and columns.
 constexpr int kGjB = 64;  // panel width
 
-__global__ __launch_bounds__(kBlock) void k_gj_panel(int n, int k0, int nb, const double* __restrict__ A,
-                                                     double* __restrict__ X) {
-  __shared__ double s[kGjB][kGjB + 1];
-  __shared__ double rowk[kGjB], colk[kGjB];
-  for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
-    const int i = e / nb, j = e - i * nb;
-    s[i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
-  }
+// The panel inverse: one 1024-thread block, lane j = column, 16 row groups of 4 rows each; per
+// pivot k every thread reads the pivot row and column and its own entries from one LDS copy of
+// the panel and writes the updated entries to the other (one barrier per pivot), the reciprocal
+// of the pivot taken once.
+constexpr int kGjPanelThreads = 1024;
+
+__global__ __launch_bounds__(kGjPanelThreads) void k_gj_panel(int n, int k0, int nb, const double* __restrict__ A,
+                                                              double* __restrict__ X) {
+  constexpr int kRows = kGjPanelThreads / kGjB;  // row groups
+  constexpr int kPer = kGjB / kRows;             // rows per thread
+  __shared__ double s[2][kGjB][kGjB + 1];
+  const int j = threadIdx.x % kGjB, i0 = threadIdx.x / kGjB;
+  for (int i = i0; i < nb; i += kRows)
+    if (j < nb) s[0][i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
   __syncthreads();
+  int cur = 0;
   for (int k = 0; k < nb; ++k) {
-    if ((int)threadIdx.x < nb) {
-      rowk[threadIdx.x] = s[k][threadIdx.x];
-      colk[threadIdx.x] = s[threadIdx.x][k];
+    const double rp = 1.0 / s[cur][k][k];
+    if (j < nb) {
+      const double rowk = s[cur][k][j];
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        const int i = i0 + kRows * r;
+        if (i >= nb) continue;
+        const double colk = s[cur][i][k];
+        double v;
+        if (i == k && j == k) v = rp;
+        else if (i == k) v = rowk * rp;
+        else if (j == k) v = -colk * rp;
+        else v = s[cur][i][j] - colk * (rowk * rp);
+        s[cur ^ 1][i][j] = v;
+      }
     }
-    __syncthreads();
-    const double p = rowk[k];
-    for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
-      const int i = e / nb, j = e - i * nb;
-      double v;
-      if (i == k && j == k) v = 1.0 / p;
-      else if (i == k) v = rowk[j] / p;
-      else if (j == k) v = -colk[i] / p;
-      else v = s[i][j] - colk[i] * (rowk[j] / p);
-      s[i][j] = v;
-    }
+    cur ^= 1;
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
-    const int i = e / nb, j = e - i * nb;
-    X[i * kGjB + j] = s[i][j];
-  }
+  for (int i = i0; i < nb; i += kRows)
+    if (j < nb) X[i * kGjB + j] = s[cur][i][j];
 }
 
 // TT[q][i] = sum_p A[i][k0+p] X[p][q] (T transposed) and W[p][j] = sum_q X[p][q] A[k0+q][j], one
-// thread per index i (= j), X in LDS.  Rows and columns inside the panel are computed but unused.
+// thread per index i (= j) and per chunk of kGjChunk outputs q (p) (blockIdx.y), X in LDS.  Rows
+// and columns inside the panel are computed but unused.
+constexpr int kGjChunk = 8;
+
 __global__ __launch_bounds__(kBlock) void k_gj_tw(int n, int k0, int nb, const double* __restrict__ A,
                                                   const double* __restrict__ X, double* __restrict__ TT,
                                                   double* __restrict__ W) {
@@ -1121,7 +1202,8 @@ __global__ __launch_bounds__(kBlock) void k_gj_tw(int n, int k0, int nb, const d
   double a[kGjB];
 #pragma unroll
   for (int p = 0; p < kGjB; ++p) a[p] = p < nb ? A[(int64_t)i * n + k0 + p] : 0.0;  // row i, panel columns
-  for (int q = 0; q < nb; ++q) {
+  const int c0 = blockIdx.y * kGjChunk, c1 = min(nb, c0 + kGjChunk);
+  for (int q = c0; q < c1; ++q) {
     double t = 0.0;
 #pragma unroll
     for (int p = 0; p < kGjB; ++p) t += a[p] * sx[p][q];
@@ -1129,7 +1211,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_tw(int n, int k0, int nb, const d
   }
 #pragma unroll
   for (int q = 0; q < kGjB; ++q) a[q] = q < nb ? A[(int64_t)(k0 + q) * n + i] : 0.0;  // column i, panel rows
-  for (int p = 0; p < nb; ++p) {
+  for (int p = c0; p < c1; ++p) {
     double w = 0.0;
 #pragma unroll
     for (int q = 0; q < kGjB; ++q) w += sx[p][q] * a[q];
@@ -1209,8 +1291,8 @@ void launch_gauss_jordan(double* A, int n, hipStream_t st) {
   const int nt = (int)cdiv(n, 64);
   for (int k0 = 0; k0 < n; k0 += kGjB) {
     const int nb = std::min(kGjB, n - k0);
-    RMG_LAUNCH(k_gj_panel, dim3(1), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>());
-    RMG_LAUNCH(k_gj_tw, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>(),
+    RMG_LAUNCH(k_gj_panel, dim3(1), dim3(kGjPanelThreads), 0, st, n, k0, nb, A, X.as<double>());
+    RMG_LAUNCH(k_gj_tw, dim3(cdiv(n, kBlock), cdiv(nb, kGjChunk)), dim3(kBlock), 0, st, n, k0, nb, A, X.as<double>(),
                        TT.as<double>(), W.as<double>());
     RMG_LAUNCH(k_gj_rank, dim3(nt, nt), dim3(kBlock), 0, st, n, k0, nb, A, TT.as<double>());
     RMG_LAUNCH(k_gj_rows, dim3(cdiv(n, kBlock), nb), dim3(kBlock), 0, st, n, k0, nb, A, W.as<double>(),
@@ -1661,8 +1743,6 @@ __global__ __launch_bounds__(kBlock) void k_make_sym(LevelView L, const C* __res
 // holds, and the tiles that serve it read no couplings from memory.
 __device__ __forceinline__ bool same_bits(double a, double b) { return __double_as_longlong(a) == __double_as_longlong(b); }
 
-__device__ __forceinline__ int axis_class(int v, int e) { return v < 2 ? v : (v >= e - 2 ? v - e + 5 : 2); }
-__device__ __forceinline__ int class_node(int c, int e) { return c <= 2 ? c : e - 5 + c; }
 
 // Coupling s of node (x, y, z) of region R, A(i, i + offset(s)), as the symmetric kernels read it.
 __device__ __forceinline__ double read_coupling(const RegionGeo& R, const double* __restrict__ sym, int x, int y,

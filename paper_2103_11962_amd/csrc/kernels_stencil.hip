@@ -422,7 +422,6 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
 }
 
 // ------------------------------------------------------- region-table tiles
-__device__ __forceinline__ int axis_class_of(int v, int e) { return v < 2 ? v : (v >= e - 2 ? v - e + 5 : 2); }
 
 // Whole-region tiles of a region served by its class tables: ty full x-rows, nz planes.  The lanes
 // of the rows' inner nodes (x in [2, ex - 2)) come first, padded to whole wavefronts, then the rows'
@@ -472,7 +471,7 @@ __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, co
     active = true;
   }
   const int y = T.y0 + row;
-  const int cxy = axis_class_of(y, R.ey) * 5 + axis_class_of(x, R.ex);
+  const int cxy = axis_class(y, R.ey) * 5 + axis_class(x, R.ex);
   const int W = R.ex + 2, PL = (T.ty + 2) * W;
   const int sy = R.ex, sz = R.ex * R.ey;
   const double* __restrict__ xr = p.x + R.off;
@@ -515,14 +514,14 @@ __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, co
   for (int e = t; e < 5 * kClassPts * kXRows; e += NT) {  // couplings of the x-face lanes' classes
     const int u = e % kXRows, s2 = e / kXRows % kClassPts, cz = e / (kXRows * kClassPts);
     const int yu = min(T.y0 + (u >> 2), R.ey - 1), xu = (u & 3) < 2 ? (u & 3) : R.ex - 4 + (u & 3);
-    xt[cz][s2][u] = tab[((cz * 5 + axis_class_of(yu, R.ey)) * 5 + axis_class_of(xu, R.ex)) * kClassPts + s2];
+    xt[cz][s2][u] = tab[((cz * 5 + axis_class(yu, R.ey)) * 5 + axis_class(xu, R.ex)) * kClassPts + s2];
   }
   // Running sums: once plane q has been added, a0 is node q - 1's sum, a1 node q's and a2 node
   // q + 1's.  A plane adds its nine values to the three nodes it neighbours in z (as their plane
   // z + 1, z and z - 1), so each node adds its 27 products in stencil order with one rounding each,
   // and only the plane read last is held in registers.
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, ctr = 0.0, xprev = 0.0;
-  auto czc = [&](int z) { return min(max(axis_class_of(z, R.ez), 0), 4); };
+  auto czc = [&](int z) { return min(max(axis_class(z, R.ez), 0), 4); };
   auto add_plane = [&](int q) {
     a2 = 0.0;
     if (t >= pad) {
