@@ -111,7 +111,7 @@ def cpu_baseline(gpu_iterations: int, n_rows: int):
     }
 
 
-PREC_NAME = {0: "fp64", 1: "fp32", 2: "fp32_bf16"}
+PREC_NAME = {0: "fp64", 1: "fp32", 2: "fp32_bf16", 3: "fp32_bf16_auto"}
 
 
 def _handle(w, dev):
@@ -192,7 +192,8 @@ def _cheb_gbs(h, kind, precision, rows, stored=True):
 
 
 def variant_mixed(dev):
-    """Elasticity 3x3x3 regions of 55^3: FP64 V-cycle vs FP32 vs FP32 with BF16 coefficients."""
+    """Elasticity 3x3x3 regions of 55^3: FP64 V-cycle vs FP32 vs FP32 with BF16 coefficients on level 0
+    vs BF16 on the levels the measured convergence factor allows, and FP64 with the nodal-block D~."""
     import numpy as np
 
     import synth
@@ -200,25 +201,32 @@ def variant_mixed(dev):
     w = synth.workload("c3")
     b = _to_dev(synth.rhs(w), dev)
     out, x64 = {}, None
-    for prec in (0, 1, 2):
+    for name, prec, extra in (("fp64", 0, {}), ("fp32", 1, {}), ("fp32_bf16", 2, {}), ("fp32_bf16_auto", 3, {}),
+                              ("fp64_block_diag", 0, dict(block_diag=1))):
         h = _handle(w, dev)
-        setup_ms = _setup(h, w, precision=prec)
+        setup_ms = _setup(h, w, precision=prec, **extra)
         rows = h.level_info(0)["n_regional"] // 3
+        # the storage level 0 ended up with (the automatic choice decides per level)
+        pl = [h.level_precision(l) for l in range(w.nlevels)]
+        peff = prec if prec != 3 else (2 if pl[0]["coef_type"] == 2 else 1)
         h.profile(True)
         ms, res, x = _timed_solves(h, b)
         entry = {"setup_ms": setup_ms, "solve_ms": ms, "iterations": res["iterations"],
                  "true_relres": res["true_relres"],
-                 "cheb_gbs": _cheb_gbs(h, "block3", prec, rows, stored=False),
-                 "cheb_bytes_per_node": _cheb_bytes(h, "block3", prec, stored=False),
-                 "cheb_gbs_at_stored_bytes": _cheb_gbs(h, "block3", prec, rows),
-                 "cheb_stored_bytes_per_node": _cheb_bytes(h, "block3", prec)}
-        if prec == 0:
+                 "cheb_gbs": _cheb_gbs(h, "block3", peff, rows, stored=False),
+                 "cheb_bytes_per_node": _cheb_bytes(h, "block3", peff, stored=False),
+                 "cheb_gbs_at_stored_bytes": _cheb_gbs(h, "block3", peff, rows),
+                 "cheb_stored_bytes_per_node": _cheb_bytes(h, "block3", peff)}
+        if prec == 3:
+            entry["levels"] = [{"coef_type": p["coef_type"], "rho_fp32": p["rho_fp32"], "rho_bf16": p["rho_bf16"]}
+                               for p in pl]
+        if name == "fp64":
             x64 = x.clone()
         else:
             entry["x_rel_diff_vs_fp64"] = float((x - x64).norm() / x64.norm())
-        out[PREC_NAME[prec]] = entry
+        out[name] = entry
         h.close()
-        print(f"[bench] mixed {PREC_NAME[prec]}: {ms:.1f} ms, {res['iterations']} its", file=sys.stderr, flush=True)
+        print(f"[bench] mixed {name}: {ms:.1f} ms, {res['iterations']} its", file=sys.stderr, flush=True)
     out["speedup_fp32_bf16_vs_fp64"] = out["fp64"]["solve_ms"] / out["fp32_bf16"]["solve_ms"]
     out["workload"] = ("3D Q1 elasticity, 3x3x3 regions of 55^3 nodes (3 dofs/node), E lognormal per region, "
                        "nu 0.3, 4-level V-cycle, Chebyshev degree 3, PCG to 1e-8 (flexible in FP32/BF16)")
