@@ -60,8 +60,9 @@ int64_t launch_dot(const Level& L, const double* a, const double* b, double* par
 // Deterministic sum of `n` partials into scalars[slot].
 void launch_reduce(const double* partials, int64_t n, double* scalars, int slot, hipStream_t st);
 
-// Pointwise: d = c * dinv * b; u = d (first Chebyshev step from a zero guess).
-void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* d, void* u,
+// Pointwise: u = c * dinv * b (first Chebyshev step from a zero guess) and prev = 0, the iterate
+// before it, which the next step reads as u_(k-2) from its output buffer.
+void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* prev, void* u,
                       hipStream_t st, const void* dinv9 = nullptr);
 
 // Restriction level -> level+1 (input already divided by multiplicity), including coarse interface sum.

@@ -25,10 +25,10 @@ struct OpP {
 };
 
 // The Chebyshev / Jacobi update of the three dofs of node `node` with the nodal-block D~^-1:
-// r = b - z, dd = c2 (D~^-1 r) (+ c1 d), out = x + dd; bi, dold the node's b and old direction.
+// r = b - z, dd = c2 (D~^-1 r) (+ c1 dold), out = x + dd; dold the node's previous correction.
 template <StencilOp OP, bool DOT, class V>
 __device__ __forceinline__ double finish_block3_value(const OpP<V>& p, int64_t node, const V (&z)[3], const V (&xs)[3],
-                                                      V (&out)[3], V (&dd)[3]) {
+                                                      const V (&dold)[3], V (&out)[3], V (&dd)[3]) {
   const V* __restrict__ D = p.dinv9 + node * 9;
   V r[3];
 #pragma unroll
@@ -38,7 +38,7 @@ __device__ __forceinline__ double finish_block3_value(const OpP<V>& p, int64_t n
   for (int a = 0; a < 3; ++a) {
     const V y = D[3 * a] * r[0] + D[3 * a + 1] * r[1] + D[3 * a + 2] * r[2];
     dd[a] = p.c2 * y;
-    if constexpr (OP == StencilOp::Cheb) dd[a] = p.c1 * p.d[node * 3 + a] + dd[a];
+    if constexpr (OP == StencilOp::Cheb) dd[a] = fma(p.c1, dold[a], dd[a]);
     out[a] = xs[a] + dd[a];
     if constexpr (DOT) c += (double)p.dotw[node * 3 + a] * (double)out[a];
   }
@@ -47,13 +47,18 @@ __device__ __forceinline__ double finish_block3_value(const OpP<V>& p, int64_t n
 
 // Final update of dof i once z = (Psi^T Psi A x)_i is known; m = multiplicity of its node,
 // xself = x_i: the value `out` the operation writes to p.out[i] and, for the Chebyshev steps, the
-// new direction `dd` for p.d[i].  Returns the dof's contribution to the fused reduction, if any.
+// new correction `dd`.  Returns the dof's contribution to the fused reduction, if any.
 // OWN: the dof belongs to one region, whose centre coefficient `centre` is then the composite
 // diagonal: the Chebyshev steps take 1 / centre (the same correctly rounded quotient as the stored
 // D~^-1) instead of reading it.
+// The Chebyshev steps keep no direction vector: the previous correction d_(k-1) = u_(k-1) - u_(k-2)
+// is the difference of the step's input and the iterate before it, which the output buffer holds
+// until the step overwrites it (the cycle's two buffers alternate, and the zero-guess step clears
+// the second), so a step reads u_(k-2) in place of d and writes only u_k.  `dold` is that
+// difference (shared dofs: the stencil kernel leaves it in p.d for the interface kernel).
 template <StencilOp OP, bool DOT, class V, bool OWN = false>
-__device__ __forceinline__ double finish_value(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre, V& out,
-                                               V& dd) {
+__device__ __forceinline__ double finish_value(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre, V dold,
+                                               V& out, V& dd) {
   if constexpr (OP == StencilOp::Matvec) {
     out = z;
     return 0.0;
@@ -68,7 +73,7 @@ __device__ __forceinline__ double finish_value(const OpP<V>& p, int64_t i, V z, 
     const V r = p.b[i] - z;
     const V di = OWN ? (V)1 / centre : p.dinv[i];
     dd = p.c2 * (di * r);
-    if constexpr (OP == StencilOp::Cheb) dd = p.c1 * p.d[i] + dd;
+    if constexpr (OP == StencilOp::Cheb) dd = fma(p.c1, dold, dd);  // one rounding in every kernel
     out = xself + dd;
     if constexpr (DOT) return (double)p.dotw[i] * (double)out;
     return 0.0;
@@ -78,20 +83,35 @@ __device__ __forceinline__ double finish_value(const OpP<V>& p, int64_t i, V z, 
   }
 }
 
+// The previous correction of a dof the stencil kernel finishes: x_i - u_(k-2), the latter read from
+// the output buffer before it is overwritten (0 for the Jacobi steps, which have c1 = 0).
+template <class V>
+__device__ __forceinline__ V prev_correction(const OpP<V>& p, V xself, V uprev) {
+  return p.c1 != (V)0 ? xself - uprev : (V)0;
+}
+
 // The same, written to dof i.
 template <StencilOp OP, bool DOT, class V, bool OWN = false>
 __device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre = (V)0) {
-  V out, dd = (V)0;
-  const double c = finish_value<OP, DOT, V, OWN>(p, i, z, m, xself, centre, out, dd);
-  if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) p.d[i] = dd;
+  V out, dd = (V)0, dold = (V)0;
+  if constexpr (OP == StencilOp::Cheb) dold = prev_correction(p, xself, p.out[i]);
+  const double c = finish_value<OP, DOT, V, OWN>(p, i, z, m, xself, centre, dold, out, dd);
   p.out[i] = out;
   return c;
 }
 
-// The same with b_i and the old direction d_i already in registers (read a plane ahead); the
-// arithmetic is finish_value's.
+// A shared dof's partial product goes to p.out for the interface kernel; a Chebyshev step first
+// leaves its previous correction in p.d, since the partial replaces u_(k-2).
+template <StencilOp OP, class V>
+__device__ __forceinline__ void write_partial(const OpP<V>& p, int64_t i, V z, V xself, V uprev) {
+  if constexpr (OP == StencilOp::Cheb) p.d[i] = prev_correction(p, xself, uprev);
+  p.out[i] = z;
+}
+
+// The same with b_i and u_(k-2) (the output buffer's old value) already in registers (read a
+// plane ahead); the arithmetic is finish_value's.
 template <StencilOp OP, bool DOT, class V, bool OWN = false>
-__device__ __forceinline__ double finish_pre(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre, V bi, V dold) {
+__device__ __forceinline__ double finish_pre(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre, V bi, V uprev) {
   if constexpr (OP == StencilOp::Residual) {
     p.out[i] = bi - z;
     return 0.0;
@@ -103,9 +123,8 @@ __device__ __forceinline__ double finish_pre(const OpP<V>& p, int64_t i, V z, in
     const V r = bi - z;
     const V di = OWN ? (V)1 / centre : p.dinv[i];
     V dd = p.c2 * (di * r);
-    if constexpr (OP == StencilOp::Cheb) dd = p.c1 * dold + dd;
+    if constexpr (OP == StencilOp::Cheb) dd = fma(p.c1, prev_correction(p, xself, uprev), dd);
     const V out = xself + dd;
-    p.d[i] = dd;
     p.out[i] = out;
     if constexpr (DOT) return (double)p.dotw[i] * (double)out;
     return 0.0;
@@ -188,20 +207,21 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
     }
     if (!inner && is_shared(L, R, x, y, z)) {
 #pragma unroll
-      for (int a = 0; a < NDOF; ++a) p.out[gi * NDOF + a] = acc[a];  // summed over copies by k_iface
+      for (int a = 0; a < NDOF; ++a)  // summed over copies by k_iface
+        write_partial<OP, V>(p, gi * NDOF + a, acc[a], xr[li * NDOF + a], p.out[gi * NDOF + a]);
     } else {
       bool block = false;
       if constexpr (NDOF == 3 && (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst)) {
         if (p.dinv9) {
-          V xs[3], out[3], dd[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) xs[a] = xr[li * 3 + a];
-          contrib += finish_block3_value<OP, DOT, V>(p, gi, acc, xs, out, dd);
+          V xs[3], dold[3], out[3], dd[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            p.d[gi * 3 + a] = dd[a];
-            p.out[gi * 3 + a] = out[a];
+            xs[a] = xr[li * 3 + a];
+            dold[a] = OP == StencilOp::Cheb ? prev_correction(p, xs[a], p.out[gi * 3 + a]) : (V)0;
           }
+          contrib += finish_block3_value<OP, DOT, V>(p, gi, acc, xs, dold, out, dd);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) p.out[gi * 3 + a] = out[a];
           block = true;
         }
       }
@@ -301,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
       if (active && z2 < z1) {
         const int64_t g = R.off + (int64_t)z2 * sz + (int64_t)y * sy + x;
         if constexpr (kPreB) nb = p.b[g];
-        if constexpr (kPreD) nd = p.d[g];
+        if constexpr (kPreD) nd = p.out[g];  // u_(k-2), see finish_value
       }
     };
     if constexpr (kPreB) load_bd(z0);
@@ -394,8 +414,10 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
           }
         }
         const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
-        if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = acc;  // finished by k_iface
-        else if constexpr (kPreB) contrib += finish_pre<OP, DOT, V, kOwnDiag>(p, gi, acc, 1, rc[4], ctr, cb, cd);
+        if (edge && is_shared(L, R, x, y, zz)) {  // finished by k_iface
+          if constexpr (kPreD) write_partial<OP, V>(p, gi, acc, rc[4], cd);
+          else write_partial<OP, V>(p, gi, acc, rc[4], OP == StencilOp::Cheb ? p.out[gi] : (V)0);
+        } else if constexpr (kPreB) contrib += finish_pre<OP, DOT, V, kOwnDiag>(p, gi, acc, 1, rc[4], ctr, cb, cd);
         else contrib += finish<OP, DOT, V, kOwnDiag>(p, gi, acc, 1, rc[4], ctr);
       }
       store(sp ^ 1);  // plane zz+2 replaces plane zz
@@ -509,7 +531,7 @@ __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, co
   auto load_bd = [&](int z2, double& b2, double& d2) {  // inactive lanes and planes past the tile: a valid node
     const int64_t g = R.off + (int64_t)min(z2, z1 - 1) * sz + (int64_t)y * sy + x;
     if constexpr (kPreB) b2 = p.b[g];
-    if constexpr (kPreD) d2 = p.d[g];
+    if constexpr (kPreD) d2 = p.out[g];  // u_(k-2), see finish_value
   };
   for (int e = t; e < 5 * kClassPts * kXRows; e += NT) {  // couplings of the x-face lanes' classes
     const int u = e % kXRows, s2 = e / kXRows % kClassPts, cz = e / (kXRows * kClassPts);
@@ -613,7 +635,7 @@ __global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, co
       add_plane(zz + 1);
       const int64_t gi = R.off + (int64_t)zz * sz + (int64_t)y * sy + x;
       const bool edge = x == 0 || x == R.ex - 1 || y == 0 || y == R.ey - 1 || zz == 0 || zz == R.ez - 1;
-      if (edge && is_shared(L, R, x, y, zz)) p.out[gi] = a0;  // finished by k_iface
+      if (edge && is_shared(L, R, x, y, zz)) write_partial<OP, double>(p, gi, a0, xprev, cd);  // finished by k_iface
       else if constexpr (kPreB) contrib += finish_pre<OP, DOT, double, true>(p, gi, a0, 1, xprev, ctr, cb, cd);
       else contrib += finish<OP, DOT, double, true>(p, gi, a0, 1, xprev, ctr);
       shift();
@@ -653,22 +675,20 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
     if constexpr (NDOF == 3 && (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst)) {
       if (p.dinv9) {  // nodal blocks: the node's three sums first, then the block update
         const int64_t n0 = gcopy[a0];
-        V z[3], xs[3], out[3], dd[3];
+        V z[3], xs[3], dold[3], out[3], dd[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           V s = (V)0;
           for (int64_t c = a0; c < e; ++c) s += p.out[(int64_t)gcopy[c] * 3 + a];
           z[a] = s;
           xs[a] = p.x[n0 * 3 + a];
+          dold[a] = OP == StencilOp::Cheb ? p.d[n0 * 3 + a] : (V)0;  // left there by the stencil kernel
         }
-        contrib += finish_block3_value<OP, DOT, V>(p, n0, z, xs, out, dd);
+        contrib += finish_block3_value<OP, DOT, V>(p, n0, z, xs, dold, out, dd);
         for (int64_t c = a0; c < e; ++c) {
           const int64_t i = (int64_t)gcopy[c] * 3;
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            p.d[i + a] = dd[a];
-            p.out[i + a] = out[a];
-          }
+          for (int a = 0; a < 3; ++a) p.out[i + a] = out[a];
         }
         block = true;
       }
@@ -678,17 +698,14 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
       if (block) break;
       V s = (V)0;
       for (int64_t c = a0; c < e; ++c) s += p.out[(int64_t)gcopy[c] * NDOF + a];
-      // the copies of a composite dof hold equal b, x, d and D~^-1 (consistent regional vectors),
-      // so the update is computed from the first copy (the lowest region, which owns the dof) and
-      // written to every copy
+      // the copies of a composite dof hold equal b, x, D~^-1 and previous correction (consistent
+      // regional vectors), so the update is computed from the first copy (the lowest region, which
+      // owns the dof) and written to every copy
       const int64_t i0 = (int64_t)gcopy[a0] * NDOF + a;
       V out, dd = (V)0;
-      contrib += finish_value<OP, DOT, V>(p, i0, s, m, p.x[i0], (V)0, out, dd);
-      for (int64_t c = a0; c < e; ++c) {
-        const int64_t i = (int64_t)gcopy[c] * NDOF + a;
-        if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) p.d[i] = dd;
-        p.out[i] = out;
-      }
+      const V dold = OP == StencilOp::Cheb ? p.d[i0] : (V)0;  // left there by the stencil kernel
+      contrib += finish_value<OP, DOT, V>(p, i0, s, m, p.x[i0], (V)0, dold, out, dd);
+      for (int64_t c = a0; c < e; ++c) p.out[(int64_t)gcopy[c] * NDOF + a] = out;
     }
   }
   if constexpr (DOT || OP == StencilOp::CgQ) {

@@ -523,7 +523,7 @@ void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out)
   }
   const int K = h->opt.cheb_degree;
   void* buf[2] = {L.u.p, u_out};
-  launch_cheb_zero(L, false, b, L.dinv.p, L.cheb_c2[0], L.d.p, buf[0], st, L.dinv9.p);
+  launch_cheb_zero(L, false, b, L.dinv.p, L.cheb_c2[0], buf[1], buf[0], st, L.dinv9.p);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
     cheb_step(h, L, false, k, false, b, buf[cur], buf[1 - cur]);
@@ -731,7 +731,7 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
   const Bufs B = bufs(L, lowp);
   // ping-pong buffers arranged so that the last post-smoothing step writes z
   void* buf[2] = {B.u, z};
-  launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], B.d, buf[0], st, B.dinv9);
+  launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], buf[1], buf[0], st, B.dinv9);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
     cheb_step(h, L, lowp, k, false, b, buf[cur], buf[1 - cur]);
