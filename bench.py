@@ -28,15 +28,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PCG time-to-1e-8 residual + stencil GB/s, FP64 vs mixed/learned forms"
 HBM_PEAK_GBS = 8000.0
-# Bytes per regional row of the finest-level FP64 kernels for `coefs` stencil coefficients per row:
-# the Chebyshev step reads the coefficients, u, b, D^-1, d and writes d, u; the CG product reads
-# the coefficients and p and writes q.  The algorithmic figures are the method's 27-point
-# operator: 264 B/row for the fused Chebyshev step, 232 B/row for the product.  On a symmetric
-# level the kernels store and stream only the upper half (14 coefficients), and the tiled FP64
-# Chebyshev kernel takes D^-1 of a one-region row from its centre coefficient instead of reading
-# it (only shared rows, about 5%, read it when their interface sum is finished): 152 and 128 B/row.
+# Bytes per regional row of the finest-level FP64 kernels for `coefs` stencil coefficients per row.
+# The method's Chebyshev step (Algorithm 2 with its direction vector d) reads the coefficients, u,
+# b, D^-1, d and writes d, u: 264 B/row for the 27-point operator; the CG product reads the
+# coefficients and p and writes q: 232 B/row.  The kernels here keep no direction vector: a step
+# takes d_(k-1) = u_(k-1) - u_(k-2) from the buffer it overwrites with u_k, so it reads u_(k-1),
+# b, u_(k-2) (and D^-1) and writes u_k.  On a symmetric level they stream only the upper half (14
+# coefficients), and the tiled FP64 Chebyshev kernels take D^-1 of a one-region row from its
+# centre coefficient instead of reading it (only shared rows, about 5%, read it when their
+# interface sum is finished): 144 B/row for the streamed step, 128 B/row for the product.
+METHOD_CHEB_BYTES_PER_ROW = 8 * 27 + 6 * 8
+
+
 def cheb_bytes_per_row(coefs, reads_dinv=True):
-    return 8 * coefs + (6 if reads_dinv else 5) * 8
+    return 8 * coefs + (5 if reads_dinv else 4) * 8
 
 
 def cg_matvec_bytes_per_row(coefs):
@@ -165,21 +170,25 @@ def _setup(h, w, **opts):
 
 def _cheb_bytes(h, kind, precision, stored=True):
     """Bytes per node of the level-0 Chebyshev step: the stencil blocks (stored: the ones the level
-    streams, full or upper half, see rmg_level_kernel; else the method's full 27 blocks), u, b,
-    D~^-1, d read and d, u written; with BF16 storage the centre block comes from an FP32 array.
-    Stored: the scalar tiled kernel in FP64 or FP32 computes D~^-1 of one-region rows instead of
-    reading it."""
+    streams, full or upper half, see rmg_level_kernel; else the method's full 27 blocks) and the
+    vectors u_(k-1), b, u_(k-2), D~^-1 read and u_k written (the method's step also reads and
+    writes its direction vector d: one vector more each way); with BF16 storage the centre block
+    comes from an FP32 array.  Stored: the scalar tiled kernel in FP64 or FP32 computes D~^-1 of
+    one-region rows instead of reading it."""
     lk = h.level_kernel(0)
     nd = 1 if kind == "scalar" else 3
     nb = nd * nd
     coefs = lk["coefs"] if stored else 27 * nb
     coefs_lo = lk["coefs_lo"] if stored else 27 * nb
-    vecs = 5 if stored and kind == "scalar" and lk["kernel"] in (1, 2) and precision in (0, 1) else 6
+    if stored:
+        vecs = 4 if kind == "scalar" and lk["kernel"] in (1, 2) and precision in (0, 1) else 5
+    else:
+        vecs = 6
     if precision == 0:
         return coefs * 8 + vecs * nd * 8
     if precision == 1:
         return coefs_lo * 4 + vecs * nd * 4
-    return (coefs_lo - nb) * 2 + nb * 4 + 6 * nd * 4
+    return (coefs_lo - nb) * 2 + nb * 4 + vecs * nd * 4
 
 
 def _cheb_gbs(h, kind, precision, rows, stored=True):
@@ -673,7 +682,7 @@ def main():
 
     stored_bpr = stored_bytes_per_row(table_regions == w.nreg)
     achieved = stored_bpr * rows / (avg_cheb * 1e-3) / 1e9
-    method_bpr = cheb_bytes_per_row(ALGO_COEFS)
+    method_bpr = METHOD_CHEB_BYTES_PER_ROW
     achieved_cg = cg_matvec_bytes_per_row(ALGO_COEFS) * rows / (avg_cg * 1e-3) / 1e9
     traffic, traffic_sha = counted_traffic()
     if args.workload != "c2" or traffic_sha != kernel_source_sha():

@@ -19,8 +19,9 @@ enum class StencilOp {
   Matvec,          // y = Psi^T Psi A x
   Residual,        // r = b - Psi^T Psi A x
   ResidualScaled,  // r = (b - Psi^T Psi A x) / mult (input of the regional restriction)
-  Cheb,            // r = b - Psi^T Psi A u; d = c1 d + c2 D~^-1 r; u_out = u + d
-  ChebFirst,       // same with the old direction ignored (c1 treated as 0)
+  Cheb,            // r = b - Psi^T Psi A u; u_out = u + c1 (u - u_out) + c2 D~^-1 r, where u_out holds
+                   // the iterate before u on entry (the previous correction is their difference)
+  ChebFirst,       // same with the previous correction ignored (c1 treated as 0)
   CgQ,             // q = Psi^T Psi A p and partial sums of (p, q)
 };
 
@@ -31,7 +32,7 @@ struct StencilArgs {
   void* out = nullptr;         // y / r / u_out / q
   const void* b = nullptr;     // right-hand side (Residual*, Cheb*)
   const void* dinv = nullptr;
-  void* d = nullptr;
+  void* d = nullptr;           // Cheb*: shared rows' correction, stored for the interface kernel
   double c1 = 0.0, c2 = 0.0;
   double* partials = nullptr;  // CgQ / dot-fused variants: one double per block
   const void* dotw = nullptr;  // Cheb: when set, partial sums of (dotw, u_out) are produced

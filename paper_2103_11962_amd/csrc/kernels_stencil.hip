@@ -451,15 +451,17 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
 // wavefront takes the classes of its nodes one after the other, so one whose nodes share a class
 // (every inner wavefront away from the y-faces) runs one pass.  No coupling is read per node.  The
 // input vector's planes, whole rows with their halo, pass through two LDS slots; each plane is
-// fetched four planes ahead into registers and b and d two planes ahead, so that two planes' loads
-// are in flight while one is computed, and each plane read adds its products to the running sums
-// of the three nodes it neighbours in z.  Consecutive blocks are dealt to the eight XCDs in turn, so
+// fetched four planes ahead into registers and b and u_(k-2) two planes ahead, so that two planes'
+// loads are in flight while one is computed, and each plane read adds its products to the running
+// sums of the three nodes it neighbours in z.  The kernel is held to 80 VGPRs (six waves per SIMD):
+// four 6-wave blocks per CU instead of three, at the cost of one spilled register in the Chebyshev
+// step.  Consecutive blocks are dealt to the eight XCDs in turn, so
 // the blocks are mapped to tiles such that every XCD runs a contiguous run of tiles and neighbouring
 // tiles share their halo rows through its L2.  Every node sums its 27 products in stencil order with
 // one rounding each, as k_stencil3d does, so the results are those of streaming every coupling bit
 // for bit.
 template <StencilOp OP, bool DOT>
-__global__ __launch_bounds__(kTableThreads) void k_stencil_table(LevelView L, const Tile3* __restrict__ tiles,
+__global__ __launch_bounds__(kTableThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_stencil_table(LevelView L, const Tile3* __restrict__ tiles,
                                                                  const double* __restrict__ table, OpP<double> p,
                                                                  double* __restrict__ partials) {
   constexpr int NT = kTableThreads;
