@@ -178,6 +178,11 @@ typedef struct {
                          (power method, Chebyshev and Jacobi smoothers, FP64 and low-precision
                          V-cycles).  Needs ndof 3 and smoother 0 or 1 (RMG_ERR_ARG otherwise);
                          RMG_ERR_NUMERIC if a summed block is not positive definite */
+  int transfer_rows;  /* geometric restriction and prolongation (Section 3.3): 1 (default) by rows and
+                         planes (a block owns whole rows of a region and walks its planes, staging
+                         the values it reads in LDS) wherever every region's rows fit a block
+                         (coarse and fine rows of at most 256 nodes); 0 one thread per node.  Both
+                         give the same results bit for bit */
 } rmg_options;
 
 /* Filled by rmg_options_default with the values above. */
@@ -365,6 +370,10 @@ rmg_status rmg_kernel_launches(int64_t* count);
 /* 2.5D tile shape of `level`: the number of tiles, threads per tile block and planes per tile
  * (all 0 where the level runs node-parallel kernels).  Any output may be NULL. */
 rmg_status rmg_level_tiles(rmg_handle* h, int level, int* ntiles, int* threads, int* planes);
+/* Tiles of the transfers between `level` and the next coarser one (rmg_options.transfer_rows): the
+ * restriction's and the prolongation's blocks, 0 where they run one thread per node (and on the
+ * coarsest level).  Any output may be NULL. */
+rmg_status rmg_level_transfer_tiles(rmg_handle* h, int level, int* restriction_tiles, int* prolongation_tiles);
 /* Regions of `level` whose couplings the 2.5D kernels take from the region's class table
  * (rmg_options.region_table); 0 where no table was built.  Output may be NULL. */
 rmg_status rmg_level_table_regions(rmg_handle* h, int level, int* nregions);

@@ -163,6 +163,7 @@ void rmg_options_default(rmg_options* o) {
   o->bf16_tolerance = 0.05;
   o->bf16_cycles = 10;
   o->block_diag = 0;
+  o->transfer_rows = 1;
 }
 
 const char* rmg_last_error(void) { return g_last_error.c_str(); }
@@ -505,6 +506,7 @@ rmg_status rmg_setup_hierarchy(rmg_handle* h, const rmg_options* opt) {
   RMG_REQUIRE(opt->galerkin_generic == 0 || opt->galerkin_generic == 1, RMG_ERR_ARG,
               "galerkin_generic must be 0 or 1");
   RMG_REQUIRE(opt->block_diag == 0 || opt->block_diag == 1, RMG_ERR_ARG, "block_diag must be 0 or 1");
+  RMG_REQUIRE(opt->transfer_rows == 0 || opt->transfer_rows == 1, RMG_ERR_ARG, "transfer_rows must be 0 or 1");
   RMG_REQUIRE(!opt->block_diag || (h->ndof == 3 && opt->smoother <= 1 && !opt->hybrid), RMG_ERR_ARG,
               "block_diag needs a 3-dof problem and the Chebyshev or Jacobi smoother");
   RMG_REQUIRE(opt->smoother >= 0 && opt->smoother <= 4, RMG_ERR_ARG,
@@ -744,6 +746,15 @@ rmg_status rmg_level_tiles(rmg_handle* h, int level, int* ntiles, int* threads, 
   if (ntiles) *ntiles = tiled ? (int)L.tiles.size() : 0;
   if (threads) *threads = tiled ? L.tile_threads : 0;
   if (planes) *planes = tiled ? L.tile_depth : 0;
+  API_END
+}
+
+rmg_status rmg_level_transfer_tiles(rmg_handle* h, int level, int* restriction_tiles, int* prolongation_tiles) {
+  API_BEGIN
+  use_device(h);
+  Level& L = level_of(h, level);
+  if (restriction_tiles) *restriction_tiles = (int)L.rtiles.size();
+  if (prolongation_tiles) *prolongation_tiles = (int)L.ptiles.size();
   API_END
 }
 

@@ -82,6 +82,8 @@ struct BlockDesc {
 };
 
 constexpr int kBlock = 256;  // threads per block for node-parallel kernels
+constexpr int kProlongStageXY = 384;  // coarse nodes per plane a prolongation tile stages at most
+constexpr int kXferStagePerThread = 12;  // fine values per thread a restriction tile stages per plane at most
 
 constexpr size_t kAutoTileMin = 2048;  // 2.5D tiles needed on a level before they are used by default
 constexpr size_t kDeepTileMin = 1024;  // 41-plane FP64 tiles needed before they replace 21-plane ones
@@ -197,6 +199,13 @@ struct Level {
   std::vector<Tile3> table_tiles;    // whole-row tiles of the served regions (k_stencil_table)
   std::vector<Tile3> other_tiles;    // the level's 2.5D tiles of the regions not served
   DBuf d_table_tiles, d_other_tiles;
+  // Transfers to the next level by rows and planes (make_transfer_tiles; empty: one thread per
+  // node).  Restriction tiles hold coarse rows y0 .. y0+ty-1 and planes z0 .. z0+nz-1 of a region
+  // (tx = the coarse row length), prolongation tiles fine rows and planes; rtile_vals is the most
+  // fine values (nodes times ndof) a restriction tile stages per plane.
+  std::vector<Tile3> rtiles, ptiles;  // a prolongation tile's rows reach at most kProlongStageXY coarse nodes a plane
+  DBuf d_rtiles, d_ptiles;
+  int64_t rtile_vals = 0;
   DBuf dinv;      // double [n * ndof]: 1 / point diagonal of the composite operator
   DBuf dinv9;     // block_diag (3-dof levels): inverse nodal 3 x 3 blocks of D~, double [n][9] row-major
   DBuf dinv9_lo;  // its FP32 copy for the low-precision V-cycle
@@ -319,6 +328,9 @@ void make_tiles(Level& L, int depth);
 // Region-table split of a level whose table flags are `served` (per region): whole-row tiles of the
 // served regions and the remaining regions' tiles (also rebuilt by make_tiles while a split exists).
 void make_split(Level& L, const std::vector<int>& served);
+// Row-and-plane tiles of the transfers between F and the next level C (F.rtiles, F.ptiles), or
+// none when `rows` is false or a region's rows are too long for them.
+void make_transfer_tiles(Level& F, const Level& C, bool rows);
 void clear_split(Level& L);
 void build_coarse_solver(rmg_handle* h, Level& L);
 

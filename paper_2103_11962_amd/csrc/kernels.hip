@@ -61,20 +61,33 @@ void launch_interface_sum(const Level& L, const double* v, double* w, hipStream_
 }
 
 // ------------------------------------------------------------ reductions
+// Node blocks per block of the owner-masked dot products (kDescsPerBlock) and of the CG update
+// (kUpdateDescs): each block sums that many consecutive node blocks, so the deterministic final
+// reduction (one block) reads few partials.  The update, which also stores two vectors, runs
+// fastest with two.
+constexpr int kDescsPerBlock = 8;
+constexpr int kUpdateDescs = 2;
+
+static int64_t reduction_blocks(const Level& L, int per) { return cdiv((int64_t)L.blocks.size(), per); }
+
 template <int NDOF>
 __global__ __launch_bounds__(kBlock) void k_dot_nodes(LevelView L, const double* __restrict__ a,
                                                       const double* __restrict__ b, double* __restrict__ partials) {
-  const BlockDesc bd = L.blocks[blockIdx.x];
-  const RegionGeo R = L.regs[bd.region];
-  const int li = bd.start + (int)threadIdx.x;
   double c = 0.0;
-  if (li < R.n) {
-    int x, y, z;
-    decompose(R, li, x, y, z);
-    if (!is_shared(L, R, x, y, z)) {
-      const int64_t gi = (R.off + li) * NDOF;
+  for (int j = 0; j < kDescsPerBlock; ++j) {
+    const int64_t d = (int64_t)blockIdx.x * kDescsPerBlock + j;
+    if (d >= L.nblocks) break;
+    const BlockDesc bd = L.blocks[d];
+    const RegionGeo R = L.regs[bd.region];
+    const int li = bd.start + (int)threadIdx.x;
+    if (li < R.n) {
+      int x, y, z;
+      decompose(R, li, x, y, z);
+      if (!is_shared(L, R, x, y, z)) {
+        const int64_t gi = (R.off + li) * NDOF;
 #pragma unroll
-      for (int k = 0; k < NDOF; ++k) c += a[gi + k] * b[gi + k];
+        for (int k = 0; k < NDOF; ++k) c += a[gi + k] * b[gi + k];
+      }
     }
   }
   const double s = block_sum(c);
@@ -110,7 +123,7 @@ static int64_t dot_groups(const Level& L, const double* a, const double* b, doub
 }
 
 int64_t launch_dot(const Level& L, const double* a, const double* b, double* partials, hipStream_t st) {
-  const int64_t nb = (int64_t)L.blocks.size();
+  const int64_t nb = reduction_blocks(L, kDescsPerBlock);
   if (L.ndof == 3) RMG_LAUNCH(k_dot_nodes<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), a, b, partials);
   else RMG_LAUNCH(k_dot_nodes<1>, dim3(nb), dim3(kBlock), 0, st, L.view(), a, b, partials);
   LAUNCH_CHECK();
@@ -121,8 +134,17 @@ constexpr int kReduceThreads = 1024;
 
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double* __restrict__ partials, int64_t n,
                                                            double* scalars, int slot) {
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kReduceThreads) s += partials[i];
+  // four strided sums per thread, so that four loads are in flight
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * kReduceThreads < n; i += 4 * kReduceThreads) {
+    s0 += partials[i];
+    s1 += partials[i + kReduceThreads];
+    s2 += partials[i + 2 * kReduceThreads];
+    s3 += partials[i + 3 * kReduceThreads];
+  }
+  for (; i < n; i += kReduceThreads) s0 += partials[i];
+  const double s = (s0 + s1) + (s2 + s3);
   __shared__ double sm[kReduceThreads];
   sm[threadIdx.x] = s;
   __syncthreads();
@@ -477,6 +499,127 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView F, LevelView C, c
   for (int a = 0; a < NDOF; ++a) w[gi * NDOF + a] = acc[a];
 }
 
+// The same restriction by rows and planes (tiles of make_transfer_tiles): a block owns whole
+// coarse rows (one thread per coarse node) and a few coarse planes of one region, walks the fine
+// planes that reach them and stages each plane's fine rows in LDS with coalesced loads, so every
+// fine value is read from memory once per block instead of once per coarse node that weights it.
+// A fine plane adds to the two coarse planes whose intervals hold it; each coarse node's sum takes
+// its terms in the order of k_restrict (planes, rows, then x ascending, zero weights skipped, the
+// same weight products), so the two kernels give the same results bit for bit.
+__device__ __forceinline__ bool dir_axis(unsigned mask, int bit, int g, int n) {
+  return (((mask >> bit) & 1u) && g == 0) || (((mask >> (bit + 1)) & 1u) && g == n - 1);
+}
+
+template <int DIM, int NDOF, class V>
+__global__ __launch_bounds__(kBlock) void k_restrict_planes(LevelView F, LevelView C, const Tile3* __restrict__ tiles,
+                                                            int64_t stage_vals, const V* __restrict__ r,
+                                                            V* __restrict__ w) {
+  extern __shared__ double xfer_stage[];
+  V* const stage0 = reinterpret_cast<V*>(xfer_stage);
+  V* const stage1 = stage0 + stage_vals;
+  const Tile3 T = tiles[blockIdx.x];
+  const RegionGeo RF = F.regs[T.region];
+  const RegionGeo RC = C.regs[T.region];
+  const int t = threadIdx.x;
+  const int fy0 = max(coarse_pos(T.y0, RF.ey) - 2, 0);
+  const int fy1 = min(coarse_pos(T.y0 + T.ty - 1, RF.ey) + 2, RF.ey - 1);
+  const int fz0 = DIM == 3 ? max(coarse_pos(T.z0, RF.ez) - 2, 0) : 0;
+  const int fz1 = DIM == 3 ? min(coarse_pos(T.z0 + T.nz - 1, RF.ez) + 2, RF.ez - 1) : 0;
+  const int nval = (fy1 - fy0 + 1) * RF.ex * NDOF;
+  const bool act = t < RC.ex * T.ty;
+  const int X = act ? t % RC.ex : 0, Y = T.y0 + (act ? t / RC.ex : 0);
+  const int px = coarse_pos(X, RF.ex), py = coarse_pos(Y, RF.ey);
+  int mxl, mxr, myl, myr;
+  coarse_spans(X, RF.ex, RC.ex, mxl, mxr);
+  coarse_spans(Y, RF.ey, RC.ey, myl, myr);
+  double wxs[5], wys[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    wxs[k] = tap(k - 2, mxl, mxr);
+    wys[k] = tap(k - 2, myl, myr);
+  }
+  const bool dxy = dir_axis(C.mask, 0, RC.ox + X, C.cx) || dir_axis(C.mask, 2, RC.oy + Y, C.cy);
+  V acc0[NDOF], acc1[NDOF];  // coarse planes zc and zc + 1
+#pragma unroll
+  for (int a = 0; a < NDOF; ++a) acc0[a] = acc1[a] = (V)0;
+  int zc = fz0 / 3;
+  auto flush = [&](int Z, const V* acc) {
+    if (!act || Z < T.z0 || Z >= T.z0 + T.nz) return;
+    const bool dir = dxy || dir_axis(C.mask, 4, RC.oz + Z, C.cz);
+    const int64_t gi = (RC.off + ((int64_t)Z * RC.ey + Y) * RC.ex + X) * NDOF;
+#pragma unroll
+    for (int a = 0; a < NDOF; ++a) w[gi + a] = dir ? (V)0 : acc[a];
+  };
+  // a plane's staged rows pass through registers (fetched while the plane before is summed) into
+  // one of two LDS buffers
+  V pre[kXferStagePerThread];
+  auto fetch = [&](int fz) {
+    const V* __restrict__ src = r + (RF.off + ((int64_t)fz * RF.ey + fy0) * RF.ex) * NDOF;
+#pragma unroll
+    for (int j = 0; j < kXferStagePerThread; ++j) {
+      const int i = t + j * kBlock;
+      pre[j] = i < nval ? src[i] : (V)0;
+    }
+  };
+  auto put = [&](V* __restrict__ dst) {
+#pragma unroll
+    for (int j = 0; j < kXferStagePerThread; ++j) {
+      const int i = t + j * kBlock;
+      if (i < nval) dst[i] = pre[j];
+    }
+  };
+  fetch(fz0);
+  put(stage0);
+  for (int fz = fz0, buf = 0; fz <= fz1; ++fz, buf ^= 1) {
+    if (fz < fz1) fetch(fz + 1);
+    __syncthreads();  // this plane's rows are staged; the other buffer's readers are done
+    const V* __restrict__ rows = buf ? stage1 : stage0;
+    if (DIM == 3 && fz / 3 != zc) {  // coarse plane zc has all its terms
+      flush(zc, acc0);
+#pragma unroll
+      for (int a = 0; a < NDOF; ++a) {
+        acc0[a] = acc1[a];
+        acc1[a] = (V)0;
+      }
+      zc = fz / 3;
+    }
+    double wz0 = 1.0, wz1 = 0.0;
+    if (DIM == 3) {
+      int ml, mr;
+      coarse_spans(zc, RF.ez, RC.ez, ml, mr);
+      wz0 = tap(fz - coarse_pos(zc, RF.ez), ml, mr);
+      if (zc + 1 < RC.ez) {
+        coarse_spans(zc + 1, RF.ez, RC.ez, ml, mr);
+        wz1 = tap(fz - coarse_pos(zc + 1, RF.ez), ml, mr);
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int ky = 0; ky < 5; ++ky) {
+        const double wy = wys[ky];
+        if (wy == 0.0) continue;
+        const double wzy0 = wz0 * wy, wzy1 = wz1 * wy;
+        const V* __restrict__ row = rows + (py + ky - 2 - fy0) * RF.ex * NDOF;
+#pragma unroll
+        for (int kx = 0; kx < 5; ++kx) {
+          const double wx = wxs[kx];
+          if (wx == 0.0) continue;
+          const V w0 = (V)(wzy0 * wx), w1 = (V)(wzy1 * wx);
+#pragma unroll
+          for (int a = 0; a < NDOF; ++a) {
+            const V v = row[(px + kx - 2) * NDOF + a];
+            if (wz0 != 0.0) acc0[a] += w0 * v;
+            if (wz1 != 0.0) acc1[a] += w1 * v;
+          }
+        }
+      }
+    }
+    if (fz < fz1) put(buf ? stage0 : stage1);
+  }
+  flush(zc, acc0);
+  if (DIM == 3 && zc + 1 < RC.ez) flush(zc + 1, acc1);
+}
+
 // Stored interpolation, coarse-major copy of the restriction weights: for every coarse node C the
 // 125 weights P(3C + t, C), t in [-2, 2]^3 (slot (tz+2)*25 + (ty+2)*5 + tx+2), wave-tiled like the
 // stencil coefficients so that the restriction streams them instead of gathering single slots of
@@ -544,6 +687,21 @@ __global__ __launch_bounds__(kBlock) void k_restrict_rw(LevelView F, LevelView C
 template <int NDOF, class V>
 static void restrict_t(const Level& F, const Level& C, const V* r, V* w, hipStream_t st) {
   const double* pw = F.pw.as<double>();
+  if (!pw && !F.rtiles.empty()) {
+    const dim3 g(F.rtiles.size()), b(kBlock);
+    RMG_REQUIRE(F.rtile_vals <= (int64_t)kXferStagePerThread * kBlock, RMG_ERR_ARG,
+                "internal: restriction tile stages more than its block holds");
+    const size_t lds = 2 * sizeof(V) * (size_t)F.rtile_vals;
+    if (F.dim == 3)
+      RMG_LAUNCH((k_restrict_planes<3, NDOF, V>), g, b, lds, st, F.view(), C.view(), F.d_rtiles.as<Tile3>(),
+                 F.rtile_vals, r, w);
+    else
+      RMG_LAUNCH((k_restrict_planes<2, NDOF, V>), g, b, lds, st, F.view(), C.view(), F.d_rtiles.as<Tile3>(),
+                 F.rtile_vals, r, w);
+    LAUNCH_CHECK();
+    iface_sum_inplace<V>(C, w, st);
+    return;
+  }
   const dim3 g(C.blocks.size()), b(kBlock);
   if constexpr (NDOF == 1) {
     if (pw) {
@@ -634,6 +792,92 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView F, LevelView C
   for (int a = 0; a < NDOF; ++a) u[fi + a] += acc[a];
 }
 
+// The same prolongation by rows and planes (tiles of make_transfer_tiles): a thread keeps one fine
+// node's x and y interpolation (coarse candidates, weights, Dirichlet faces) and walks the tile's
+// planes; per plane the block stages the coarse values its rows interpolate from (two coarse
+// planes of the few coarse rows bracketing the tile's rows) in LDS with coalesced loads, so each
+// is read from memory once per block rather than by every fine node next to it.  Terms, weights and
+// their order are k_prolong_add's: the results are the same bit for bit.
+
+template <int DIM, int NDOF, class V>
+__global__ __launch_bounds__(kBlock) void k_prolong_rows(LevelView F, LevelView C, const Tile3* __restrict__ tiles,
+                                                         const V* __restrict__ ubar, V* __restrict__ u) {
+  __shared__ V stage[2][2 * kProlongStageXY * NDOF];  // two buffers of two coarse planes
+  const Tile3 T = tiles[blockIdx.x];
+  const RegionGeo RF = F.regs[T.region];
+  const RegionGeo RC = C.regs[T.region];
+  const int t = threadIdx.x;
+  const bool act = t < RF.ex * T.ty;
+  const int x = act ? t % RF.ex : 0, y = T.y0 + (act ? t / RF.ex : 0);
+  // coarse rows [cy0, cy1] bracket the tile's fine rows (at most three)
+  int cy0, cy1;
+  {
+    double w0, w1;
+    bracket(T.y0, RF.ey, RC.ey, cy0, w0, w1);
+    bracket(T.y0 + T.ty - 1, RF.ey, RC.ey, cy1, w0, w1);
+    cy1 = min(cy1 + 1, RC.ey - 1);
+  }
+  const int nrow = cy1 - cy0 + 1, nxy = nrow * RC.ex;
+  const int nstage = (DIM == 3 ? 2 : 1) * nxy * NDOF;
+  int lx, ly;
+  double ax[2], ay[2];
+  bracket(x, RF.ex, RC.ex, lx, ax[0], ax[1]);
+  bracket(y, RF.ey, RC.ey, ly, ay[0], ay[1]);
+  const bool fdxy = dir_axis(F.mask, 0, RF.ox + x, F.cx) || dir_axis(F.mask, 2, RF.oy + y, F.cy);
+  int sxy[2][2];  // staged position (row - cy0, X) of each candidate
+  bool dxy[2][2];
+#pragma unroll
+  for (int iy = 0; iy < 2; ++iy) {
+    const int Y = min(ly + iy, RC.ey - 1);
+#pragma unroll
+    for (int ix = 0; ix < 2; ++ix) {
+      const int X = min(lx + ix, RC.ex - 1);
+      sxy[iy][ix] = (Y - cy0) * RC.ex + X;
+      dxy[iy][ix] = dir_axis(C.mask, 0, RC.ox + X, C.cx) || dir_axis(C.mask, 2, RC.oy + Y, C.cy);
+    }
+  }
+  const V* __restrict__ ub = ubar + RC.off * NDOF;
+  for (int z = T.z0, buf = 0; z < T.z0 + T.nz; ++z, buf ^= 1) {
+    int lz = 0;
+    double az[2] = {1.0, 0.0};
+    if (DIM == 3) bracket(z, RF.ez, RC.ez, lz, az[0], az[1]);
+    // stage coarse planes lz and lz + 1 (clamped into the box) of rows cy0 .. cy1: [iz][row][X][dof]
+    V* __restrict__ S = stage[buf];
+    for (int i = t; i < nstage; i += kBlock) {
+      const int iz = i / (nxy * NDOF), rem = i - iz * nxy * NDOF;
+      const int Z = min(lz + iz, RC.ez - 1);
+      S[i] = ub[((int64_t)Z * RC.ey + cy0) * RC.ex * NDOF + rem];
+    }
+    __syncthreads();  // staged; the other buffer's readers finished before the previous barrier
+    if (act) {
+      const bool fdir = fdxy || dir_axis(F.mask, 4, RF.oz + z, F.cz);
+      V acc[NDOF];
+#pragma unroll
+      for (int a = 0; a < NDOF; ++a) acc[a] = (V)0;
+#pragma unroll
+      for (int iz = 0; iz < (DIM == 3 ? 2 : 1); ++iz) {
+        const int Z = min(lz + iz, RC.ez - 1);
+        const bool dz = dir_axis(C.mask, 4, RC.oz + Z, C.cz);
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy) {
+          const double wzy = az[iz] * ay[iy];
+#pragma unroll
+          for (int ix = 0; ix < 2; ++ix) {
+            const bool off = !fdir && (dz || dxy[iy][ix]);
+            const V wt = off ? (V)0 : (V)(wzy * ax[ix]);
+            const int si = (iz * nxy + sxy[iy][ix]) * NDOF;
+#pragma unroll
+            for (int a = 0; a < NDOF; ++a) acc[a] += wt * S[si + a];
+          }
+        }
+      }
+      const int64_t fi = (RF.off + ((int64_t)z * RF.ey + y) * RF.ex + x) * NDOF;
+#pragma unroll
+      for (int a = 0; a < NDOF; ++a) u[fi + a] += acc[a];
+    }
+  }
+}
+
 template <int NDOF, class V>
 static void prolong_t(const Level& F, const Level& C, const V* ubar, V* u, hipStream_t st) {
   const double* pw = F.pw.as<double>();
@@ -645,6 +889,15 @@ static void prolong_t(const Level& F, const Level& C, const V* ubar, V* u, hipSt
       LAUNCH_CHECK();
       return;
     }
+  }
+  if (!F.ptiles.empty()) {
+    const dim3 gt(F.ptiles.size());
+    if (F.dim == 3)
+      RMG_LAUNCH((k_prolong_rows<3, NDOF, V>), gt, b, 0, st, F.view(), C.view(), F.d_ptiles.as<Tile3>(), ubar, u);
+    else
+      RMG_LAUNCH((k_prolong_rows<2, NDOF, V>), gt, b, 0, st, F.view(), C.view(), F.d_ptiles.as<Tile3>(), ubar, u);
+    LAUNCH_CHECK();
+    return;
   }
   if (F.dim == 3)
     RMG_LAUNCH((k_prolong_add<3, NDOF, V, false>), g, b, 0, st, F.view(), C.view(), ubar, u, pw);
@@ -1864,22 +2117,26 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(LevelView L, const double*
                                                       double* __restrict__ x, double* __restrict__ r,
                                                       const double* __restrict__ p, const double* __restrict__ q,
                                                       double* __restrict__ partials) {
-  const BlockDesc bd = L.blocks[blockIdx.x];
-  const RegionGeo R = L.regs[bd.region];
-  const int li = bd.start + (int)threadIdx.x;
+  const double alpha = scalars[kAlpha];
   double c = 0.0;
-  if (li < R.n) {
-    const double alpha = scalars[kAlpha];
-    int xx, yy, zz;
-    decompose(R, li, xx, yy, zz);
-    const bool own = !is_shared(L, R, xx, yy, zz);
+  for (int j = 0; j < kUpdateDescs; ++j) {
+    const int64_t d = (int64_t)blockIdx.x * kUpdateDescs + j;
+    if (d >= L.nblocks) break;
+    const BlockDesc bd = L.blocks[d];
+    const RegionGeo R = L.regs[bd.region];
+    const int li = bd.start + (int)threadIdx.x;
+    if (li < R.n) {
+      int xx, yy, zz;
+      decompose(R, li, xx, yy, zz);
+      const bool own = !is_shared(L, R, xx, yy, zz);
 #pragma unroll
-    for (int a = 0; a < NDOF; ++a) {
-      const int64_t gi = (R.off + li) * NDOF + a;
-      x[gi] = x[gi] + alpha * p[gi];
-      const double rn = r[gi] + (-alpha) * q[gi];
-      r[gi] = rn;
-      if (own) c += rn * rn;
+      for (int a = 0; a < NDOF; ++a) {
+        const int64_t gi = (R.off + li) * NDOF + a;
+        x[gi] = x[gi] + alpha * p[gi];
+        const double rn = r[gi] + (-alpha) * q[gi];
+        r[gi] = rn;
+        if (own) c += rn * rn;
+      }
     }
   }
   const double s = block_sum(c);
@@ -1888,7 +2145,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(LevelView L, const double*
 
 int64_t launch_cg_update(const Level& L, double* scalars, double* x, double* r, const double* p, const double* q,
                          double* partials, hipStream_t st) {
-  const int64_t nb = (int64_t)L.blocks.size();
+  const int64_t nb = reduction_blocks(L, kUpdateDescs);
   if (L.ndof == 3)
     RMG_LAUNCH(k_cg_update<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials);
   else

@@ -168,6 +168,136 @@ void make_split(Level& L, const std::vector<int>& served) {
   upload(L.d_other_tiles, L.other_tiles);
 }
 
+// Transfer tiles.  Restriction: a block of kBlock threads owns whole coarse rows (one thread per
+// coarse node, at most kBlock / EX rows) and up to kXferCoarsePlanes coarse planes, and stages per
+// fine plane the fine rows that reach them (three per coarse row plus two on either side), at most
+// kXferStagePerThread values per thread.  Prolongation: a block owns up to kBlock / ex whole fine rows
+// (whose coarse rows fit its stage) and kXferFinePlanes fine planes.  Rows and planes are shared
+// out evenly; on small levels tiles take fewer planes, then fewer rows, until the level has
+// kXferMinTiles of them (or single rows and planes).
+constexpr int kXferCoarsePlanes = 4;
+constexpr int kXferFinePlanes = 8;
+constexpr int64_t kXferStageBytes = 8 * kXferStagePerThread * kBlock;  // FP64 values staged per plane at most
+constexpr size_t kXferMinTiles = 1024;
+
+void make_transfer_tiles(Level& F, const Level& C, bool rows_and_planes) {
+  F.rtiles.clear();
+  F.ptiles.clear();
+  F.rtile_vals = 0;
+  auto cpos = [](int c, int e) { return std::min(3 * c, e - 1); };
+  // start of the coarse interval of fine node g (the next coarse node for an interval's end node)
+  auto lo_of = [](int g, int e, int E) {
+    if (E < 2) return 0;
+    int lo = std::min(g / 3, E - 2);
+    const int p0 = 3 * lo, m = std::min(p0 + 3, e - 1) - p0;
+    return g - p0 == m ? lo + 1 : lo;
+  };
+  bool ok = rows_and_planes && F.nreg == C.nreg && (F.dim == 2 || F.dim == 3);
+  for (int k = 0; ok && k < F.nreg; ++k)
+    if (C.regs[k].ex > kBlock || F.regs[k].ex > kBlock || C.regs[k].ex > kProlongStageXY) ok = false;
+  // even shares of n items in parts of at most cap
+  auto shares = [](int n, int cap) {
+    const int parts = (n + cap - 1) / cap;
+    std::vector<int> v(parts);
+    for (int j = 0; j < parts; ++j) v[j] = n / parts + (j < n % parts ? 1 : 0);
+    return v;
+  };
+  // restriction tiles with at most ny coarse rows (capped per region) and nz coarse planes
+  auto build_r = [&](int nycap, int nzcap) {
+    F.rtiles.clear();
+    F.rtile_vals = 0;
+    for (int k = 0; k < F.nreg; ++k) {
+      const RegionGeo& RF = F.regs[k];
+      const RegionGeo& RC = C.regs[k];
+      auto rows = [&](int y0, int n) {
+        return std::min(cpos(y0 + n - 1, RF.ey) + 2, RF.ey - 1) - std::max(cpos(y0, RF.ey) - 2, 0) + 1;
+      };
+      auto stage_bytes = [&](int n) { return (int64_t)std::min(3 * (n - 1) + 5, RF.ey) * RF.ex * F.ndof * 8; };
+      int ny = std::min({RC.ey, kBlock / RC.ex, nycap});
+      while (ny > 1 && stage_bytes(ny) > kXferStageBytes) --ny;
+      if (stage_bytes(ny) > kXferStageBytes) return false;
+      int z0 = 0;
+      for (int nz : shares(RC.ez, F.dim == 3 ? nzcap : 1)) {
+        int y0 = 0;
+        for (int ty : shares(RC.ey, ny)) {
+          F.rtiles.push_back(Tile3{k, 0, y0, z0, RC.ex, ty, nz, 0});
+          F.rtile_vals = std::max(F.rtile_vals, (int64_t)rows(y0, ty) * RF.ex * F.ndof);
+          y0 += ty;
+        }
+        z0 += nz;
+      }
+    }
+    return true;
+  };
+  // prolongation tiles with at most fy fine rows (capped per region) and nz fine planes
+  auto build_p = [&](int fycap, int nzcap) {
+    F.ptiles.clear();
+    for (int k = 0; k < F.nreg; ++k) {
+      const RegionGeo& RF = F.regs[k];
+      const RegionGeo& RC = C.regs[k];
+      auto crows = [&](int y0, int n) {
+        return std::min(lo_of(y0 + n - 1, RF.ey, RC.ey) + 1, RC.ey - 1) - lo_of(y0, RF.ey, RC.ey) + 1;
+      };
+      auto fits = [&](int n) {
+        int y0 = 0;
+        for (int ty : shares(RF.ey, n)) {
+          if (crows(y0, ty) * RC.ex > kProlongStageXY) return false;
+          y0 += ty;
+        }
+        return true;
+      };
+      int fy = std::min({RF.ey, std::max(1, kBlock / RF.ex), fycap});
+      while (fy > 1 && !fits(fy)) --fy;
+      if (!fits(fy)) return false;
+      int z0 = 0;
+      for (int nz : shares(RF.ez, F.dim == 3 ? nzcap : 1)) {
+        int y0 = 0;
+        for (int ty : shares(RF.ey, fy)) {
+          F.ptiles.push_back(Tile3{k, 0, y0, z0, RF.ex, ty, nz, 0});
+          y0 += ty;
+        }
+        z0 += nz;
+      }
+    }
+    return true;
+  };
+  if (ok) {
+    int ny = kBlock, nz = kXferCoarsePlanes;
+    ok = build_r(ny, nz);
+    while (ok && F.rtiles.size() < kXferMinTiles && (nz > 1 || ny > 1)) {
+      if (nz > 1) nz /= 2;
+      else ny = std::max(1, std::min(ny, kBlock) / 2);
+      ok = build_r(ny, nz);
+    }
+  }
+  if (ok) {
+    int fy = kBlock, nz = kXferFinePlanes;
+    ok = build_p(fy, nz);
+    while (ok && F.ptiles.size() < kXferMinTiles && (nz > 1 || fy > 1)) {
+      if (nz > 1) nz /= 2;
+      else fy = std::max(1, std::min(fy, kBlock) / 2);
+      ok = build_p(fy, nz);
+    }
+  }
+  for (const Tile3& T : F.rtiles) {
+    const RegionGeo& RC = C.regs[T.region];
+    RMG_REQUIRE(T.tx * T.ty <= kBlock && T.y0 + T.ty <= RC.ey && T.z0 + T.nz <= RC.ez && T.ty >= 1 && T.nz >= 1,
+                RMG_ERR_ARG, "internal: restriction tile does not fit its block");
+  }
+  for (const Tile3& T : F.ptiles) {
+    const RegionGeo& RF = F.regs[T.region];
+    RMG_REQUIRE(T.tx * T.ty <= kBlock && T.y0 + T.ty <= RF.ey && T.z0 + T.nz <= RF.ez && T.ty >= 1 && T.nz >= 1,
+                RMG_ERR_ARG, "internal: prolongation tile does not fit its block");
+  }
+  if (!ok) {
+    F.rtiles.clear();
+    F.ptiles.clear();
+    F.rtile_vals = 0;
+  }
+  upload(F.d_rtiles, F.rtiles);
+  upload(F.d_ptiles, F.ptiles);
+}
+
 // Offsets, block table and interface groups of a level whose regs/comp are set.
 void build_tables(Level& L) {
   int64_t off = 0;

@@ -322,6 +322,7 @@ static int build_levels(rmg_handle* h, bool stored) {
     // next level: geometry, interpolation weights, then the per-region Galerkin product (FP64)
     Level* C = make_coarse_level(L);
     h->levels.push_back(C);
+    make_transfer_tiles(L, *C, o.transfer_rows != 0);
     C->coef.alloc(sizeof(double) * coef_elems(C->n, C->ncoef()));
     if (l == 0) {
       if (stored) {

@@ -40,7 +40,7 @@ SYMBOLS = (
     "rmg_mlp_train", "rmg_mlp_init_params", "rmg_level_kernel", "rmg_set_composite_csr", "rmg_mg_solve",
     "rmg_mlp_set_loss", "rmg_set_region_kinds", "rmg_hybrid_level_info", "rmg_hybrid_aggregates",
     "rmg_hybrid_composite_ids", "rmg_hybrid_matrix", "rmg_amg_levels", "rmg_amg_level_info", "rmg_amg_matrix",
-    "rmg_level_table_regions", "rmg_level_tiles", "rmg_kernel_launches", "rmg_convergence_factor_noalloc",
+    "rmg_level_table_regions", "rmg_level_tiles", "rmg_level_transfer_tiles", "rmg_kernel_launches", "rmg_convergence_factor_noalloc",
     "rmg_level_precision",
 )
 SMOOTHER_CHEBYSHEV, SMOOTHER_JACOBI, SMOOTHER_GS, SMOOTHER_GS_FB, SMOOTHER_SYMGS = 0, 1, 2, 3, 4
@@ -79,6 +79,7 @@ class Options(ctypes.Structure):
         ("bf16_tolerance", ctypes.c_double),
         ("bf16_cycles", ctypes.c_int),
         ("block_diag", ctypes.c_int),
+        ("transfer_rows", ctypes.c_int),
     ]
 
 
@@ -196,6 +197,7 @@ def load():
         "rmg_set_composite_csr": (I, [H, I, ctypes.c_int64, P, P, P, I]),
         "rmg_level_table_regions": (I, [H, I, ctypes.POINTER(I)]),
         "rmg_level_tiles": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "rmg_level_transfer_tiles": (I, [H, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "rmg_kernel_launches": (I, [ctypes.POINTER(ctypes.c_int64)]),
         "rmg_mg_solve": (I, [H, P, P, I, D, I, ctypes.POINTER(SolveInfo)]),
         "rmg_mlp_set_loss": (I, [H, I]),
@@ -468,6 +470,11 @@ class Handle:
         n, t, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(load().rmg_level_tiles(self._h, level, ctypes.byref(n), ctypes.byref(t), ctypes.byref(p)))
         return {"ntiles": n.value, "threads": t.value, "planes": p.value}
+
+    def level_transfer_tiles(self, level):
+        r, p = ctypes.c_int(), ctypes.c_int()
+        _check(load().rmg_level_transfer_tiles(self._h, level, ctypes.byref(r), ctypes.byref(p)))
+        return {"restriction": r.value, "prolongation": p.value}
 
     def level_table_regions(self, level):
         n = ctypes.c_int()
