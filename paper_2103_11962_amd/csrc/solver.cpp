@@ -465,8 +465,10 @@ static Bufs bufs(Level& L, bool lowp) {
   return {L.b.p, L.u.p, L.u2.p, L.d.p, L.r.p, L.dinv.p, L.dinv9.p};
 }
 
-static void cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, const void* b, const void* uin,
-                      void* uout) {
+// One Chebyshev step uin -> uout; with dotw (FP64), also the partial sums of (dotw, uout) over the
+// owned copies into h->partials, whose count it returns.
+static int64_t cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, const void* b, const void* uin,
+                         void* uout, const double* dotw = nullptr) {
   const Bufs B = bufs(L, lowp);
   StencilArgs a;
   a.op = first ? StencilOp::ChebFirst : StencilOp::Cheb;
@@ -479,8 +481,12 @@ static void cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, con
   a.d = B.d;
   a.c1 = L.cheb_c1[k];
   a.c2 = L.cheb_c2[k];
-  if (h->profiling && &L == h->levels[0] && !first) h->timers[kTimedCheb].acquire(&a.ev0, &a.ev1);
-  launch_stencil_op(L, a, h->stream);
+  if (dotw) {
+    a.dotw = dotw;
+    a.partials = h->partials.as<double>();
+  }
+  if (h->profiling && &L == h->levels[0] && !first && !dotw) h->timers[kTimedCheb].acquire(&a.ev0, &a.ev1);
+  return launch_stencil_op(L, a, h->stream);
 }
 
 // Region-local Gauss-Seidel (Section 3.4, Algorithm 1), cheb_degree sweeps on u in place (FP64).
@@ -692,7 +698,7 @@ void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit,
   }
 }
 
-void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
+void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, const double* dotw, int slot) {
   const int nl = (int)h->levels.size();
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
@@ -754,27 +760,32 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z) {
   span = level_span_begin(h, level);
   launch_prolong_add(L, C, lowp, BC.u2, buf[cur], st);
   for (int k = 0; k < K; ++k) {
-    cheb_step(h, L, lowp, k, k == 0, b, buf[cur], buf[1 - cur]);
+    // the last step also sums (dotw, z) when asked (the CG inner product (r, z))
+    const double* w = (k == K - 1 && dotw && !lowp) ? dotw : nullptr;
+    const int64_t np = cheb_step(h, L, lowp, k, k == 0, b, buf[cur], buf[1 - cur], w);
+    if (w) launch_reduce(h->partials.as<double>(), np, scal(h), slot, st);
     cur = 1 - cur;
   }
   level_span_end(h, span);
   RMG_REQUIRE(buf[cur] == z, RMG_ERR_ARG, "internal: V-cycle buffer parity");
 }
 
-// z = M^-1 r with the configured precision (FP64 regional vectors in and out).
-static void precondition(rmg_handle* h, const double* r, double* z) {
+// z = M^-1 r with the configured precision (FP64 regional vectors in and out); with slot >= 0 also
+// (r, z) into that scalar slot, summed by the V-cycle's last Chebyshev step where it has one.
+static void precondition(rmg_handle* h, const double* r, double* z, int slot = -1) {
   Level& L = *h->levels[0];
   if (h->hy) {
     hybrid_cycle(h, r, z);
-    return;
+  } else if (h->opt.precision == RMG_PREC_FP64) {
+    const bool fused = slot >= 0 && h->opt.smoother <= 1 && h->levels.size() > 1;
+    vcycle(h, 0, false, r, z, fused ? r : nullptr, slot);
+    if (fused) return;
+  } else {
+    launch_f64_to_f32(L.ndofs(), r, L.b32.as<float>(), h->stream);
+    vcycle(h, 0, true, L.b32.p, h->cg_z32.p);
+    launch_f32_to_f64(L.ndofs(), h->cg_z32.as<float>(), z, h->stream);
   }
-  if (h->opt.precision == RMG_PREC_FP64) {
-    vcycle(h, 0, false, r, z);
-    return;
-  }
-  launch_f64_to_f32(L.ndofs(), r, L.b32.as<float>(), h->stream);
-  vcycle(h, 0, true, L.b32.p, h->cg_z32.p);
-  launch_f32_to_f64(L.ndofs(), h->cg_z32.as<float>(), z, h->stream);
+  if (slot >= 0) dot(h, L, r, z, slot);
 }
 
 void apply_preconditioner(rmg_handle* h, const double* r, double* z) { precondition(h, r, z); }
@@ -869,8 +880,7 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
   };
   // second half: z = M^-1 r, beta, p update
   auto body_b = [&]() {
-    precondition(h, r, z);
-    dot(h, L, r, z, kRZnew);
+    precondition(h, r, z, kRZnew);
     if (flexible) {
       dot(h, L, z, q, kZQ);
       launch_cg_scalars(scal(h), 2, st);
@@ -913,9 +923,8 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
     rel = 0.0;
     converged = true;
   } else {
-    precondition(h, r, z);
+    precondition(h, r, z, kRZ);
     launch_copy(n, z, p, st);
-    dot(h, L, r, z, kRZ);
     if (graphs && (!h->graph_a || h->graph_b_ptr != b || h->graph_x_ptr != x)) {
       h->drop_graphs();
       const bool prof = h->profiling;
