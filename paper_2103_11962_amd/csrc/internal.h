@@ -88,12 +88,13 @@ constexpr int kXferStagePerThread = 12;  // fine values per thread a restriction
 constexpr size_t kAutoTileMin = 2048;  // 2.5D tiles needed on a level before they are used by default
 constexpr size_t kDeepTileMin = 1024;  // 41-plane FP64 tiles needed before they replace 21-plane ones
 
-// Threads per 2.5D tile block.  The FP64 kernel needs about 142 VGPRs (3 waves per SIMD), so a
+// Threads per 2.5D tile block.  The FP64 kernel needs about 150 VGPRs (3 waves per SIMD), so a
 // 768-thread block (12 waves) is the widest that fits and one block runs per CU; the FP32 kernel
-// needs about 91 (5 waves per SIMD), where two 512-thread blocks (16 waves) run per CU.  A level
-// whose V-cycle runs in FP32 uses the narrow tiles for every operation.
+// needs about 93 (5 waves per SIMD), where five 256-thread blocks (20 waves) run per CU (two
+// 512-thread blocks, 16 waves, took 6% longer per step on a 113M-row level).  A level whose
+// V-cycle runs in FP32 uses the narrow tiles for every operation.
 constexpr int kTileThreadsF64 = 768;
-constexpr int kTileThreadsF32 = 512;
+constexpr int kTileThreadsF32 = 256;
 // Threads per whole-region tile of a table region (k_stencil_table): the inner x-nodes of a few rows
 // padded to whole wavefronts plus their rows' four x-face nodes; planes and rows per tile at most.
 constexpr int kTableThreads = 384;

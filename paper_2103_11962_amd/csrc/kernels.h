@@ -21,7 +21,8 @@ enum class StencilOp {
   ResidualScaled,  // r = (b - Psi^T Psi A x) / mult (input of the regional restriction)
   Cheb,            // r = b - Psi^T Psi A u; u_out = u + c1 (u - u_out) + c2 D~^-1 r, where u_out holds
                    // the iterate before u on entry (the previous correction is their difference)
-  ChebFirst,       // same with the previous correction ignored (c1 treated as 0)
+  ChebFirst,       // u_out = u + c1 u + c2 D~^-1 r: the iterate before u was zero (the step after a
+                   // zero-guess start), or c1 = 0 for a step with no previous correction
   CgQ,             // q = Psi^T Psi A p and partial sums of (p, q)
 };
 
@@ -61,10 +62,10 @@ int64_t launch_dot(const Level& L, const double* a, const double* b, double* par
 // Deterministic sum of `n` partials into scalars[slot].
 void launch_reduce(const double* partials, int64_t n, double* scalars, int slot, hipStream_t st);
 
-// Pointwise: u = c * dinv * b (first Chebyshev step from a zero guess) and prev = 0, the iterate
-// before it, which the next step reads as u_(k-2) from its output buffer.
-void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* prev, void* u,
-                      hipStream_t st, const void* dinv9 = nullptr);
+// Pointwise: u = c * dinv * b, the first Chebyshev step from a zero guess (the step after it runs
+// as ChebFirst with its c1: its previous correction is u itself).
+void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* u, hipStream_t st,
+                      const void* dinv9 = nullptr);
 
 // Restriction level -> level+1 (input already divided by multiplicity), including coarse interface sum.
 void launch_restrict(const Level& F, const Level& C, bool lowp, const void* r_scaled, void* w, hipStream_t st);

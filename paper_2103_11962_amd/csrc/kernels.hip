@@ -162,51 +162,46 @@ void launch_reduce(const double* partials, int64_t n, double* scalars, int slot,
 
 // ------------------------------------------------------------ pointwise
 template <class V>
-__global__ void k_cheb_zero(int64_t n, const V* __restrict__ b, const V* __restrict__ dinv, V c,
-                            V* __restrict__ prev, V* __restrict__ u) {
+__global__ void k_cheb_zero(int64_t n, const V* __restrict__ b, const V* __restrict__ dinv, V c, V* __restrict__ u) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const V v = c * (dinv[i] * b[i]);
-  prev[i] = (V)0;  // the iterate before u_0 (zero guess): the next step's u_(k-2)
-  u[i] = v;
+  u[i] = c * (dinv[i] * b[i]);
 }
 
 // The same with the nodal-block D~^-1 of a 3-dof level (one row-major 3 x 3 block per node).
 template <class V>
 __global__ void k_cheb_zero_block3(int64_t nodes, const V* __restrict__ b, const V* __restrict__ dinv9, V c,
-                                   V* __restrict__ prev, V* __restrict__ u) {
+                                   V* __restrict__ u) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nodes) return;
   const V* __restrict__ D = dinv9 + i * 9;
   const V b0 = b[3 * i], b1 = b[3 * i + 1], b2 = b[3 * i + 2];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const V v = c * (D[3 * a] * b0 + D[3 * a + 1] * b1 + D[3 * a + 2] * b2);
-    prev[3 * i + a] = (V)0;
-    u[3 * i + a] = v;
+    u[3 * i + a] = c * (D[3 * a] * b0 + D[3 * a + 1] * b1 + D[3 * a + 2] * b2);
   }
 }
 
-void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* prev, void* u,
-                      hipStream_t st, const void* dinv9) {
+void launch_cheb_zero(const Level& L, bool lowp, const void* b, const void* dinv, double c, void* u, hipStream_t st,
+                      const void* dinv9) {
   const int64_t n = L.ndofs();
   if (dinv9) {
     RMG_REQUIRE(L.ndof == 3, RMG_ERR_ARG, "internal: nodal blocks on a scalar level");
     if (lowp)
       RMG_LAUNCH(k_cheb_zero_block3<float>, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, (const float*)b,
-                 (const float*)dinv9, (float)c, (float*)prev, (float*)u);
+                 (const float*)dinv9, (float)c, (float*)u);
     else
       RMG_LAUNCH(k_cheb_zero_block3<double>, dim3(cdiv(L.n, kBlock)), dim3(kBlock), 0, st, L.n, (const double*)b,
-                 (const double*)dinv9, c, (double*)prev, (double*)u);
+                 (const double*)dinv9, c, (double*)u);
     LAUNCH_CHECK();
     return;
   }
   if (lowp)
     RMG_LAUNCH(k_cheb_zero<float>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, (const float*)b,
-                       (const float*)dinv, (float)c, (float*)prev, (float*)u);
+                       (const float*)dinv, (float)c, (float*)u);
   else
     RMG_LAUNCH(k_cheb_zero<double>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, n, (const double*)b,
-                       (const double*)dinv, c, (double*)prev, (double*)u);
+                       (const double*)dinv, c, (double*)u);
   LAUNCH_CHECK();
 }
 

@@ -38,7 +38,7 @@ __device__ __forceinline__ double finish_block3_value(const OpP<V>& p, int64_t n
   for (int a = 0; a < 3; ++a) {
     const V y = D[3 * a] * r[0] + D[3 * a + 1] * r[1] + D[3 * a + 2] * r[2];
     dd[a] = p.c2 * y;
-    if constexpr (OP == StencilOp::Cheb) dd[a] = fma(p.c1, dold[a], dd[a]);
+    if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) dd[a] = fma(p.c1, dold[a], dd[a]);
     out[a] = xs[a] + dd[a];
     if constexpr (DOT) c += (double)p.dotw[node * 3 + a] * (double)out[a];
   }
@@ -53,9 +53,11 @@ __device__ __forceinline__ double finish_block3_value(const OpP<V>& p, int64_t n
 // D~^-1) instead of reading it.
 // The Chebyshev steps keep no direction vector: the previous correction d_(k-1) = u_(k-1) - u_(k-2)
 // is the difference of the step's input and the iterate before it, which the output buffer holds
-// until the step overwrites it (the cycle's two buffers alternate, and the zero-guess step clears
-// the second), so a step reads u_(k-2) in place of d and writes only u_k.  `dold` is that
-// difference (shared dofs: the stencil kernel leaves it in p.d for the interface kernel).
+// until the step overwrites it (the cycle's two buffers alternate), so a step reads u_(k-2) in
+// place of d and writes only u_k.  The step after a zero-guess start (ChebFirst) has u_(k-2) = 0
+// and reads nothing for it: its previous correction is u_(k-1) itself.  `dold` is the previous
+// correction (shared dofs of a Cheb step: the stencil kernel leaves it in p.d for the interface
+// kernel).
 template <StencilOp OP, bool DOT, class V, bool OWN = false>
 __device__ __forceinline__ double finish_value(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre, V dold,
                                                V& out, V& dd) {
@@ -73,7 +75,7 @@ __device__ __forceinline__ double finish_value(const OpP<V>& p, int64_t i, V z, 
     const V r = p.b[i] - z;
     const V di = OWN ? (V)1 / centre : p.dinv[i];
     dd = p.c2 * (di * r);
-    if constexpr (OP == StencilOp::Cheb) dd = fma(p.c1, dold, dd);  // one rounding in every kernel
+    dd = fma(p.c1, dold, dd);  // one rounding in every kernel
     out = xself + dd;
     if constexpr (DOT) return (double)p.dotw[i] * (double)out;
     return 0.0;
@@ -95,6 +97,7 @@ template <StencilOp OP, bool DOT, class V, bool OWN = false>
 __device__ __forceinline__ double finish(const OpP<V>& p, int64_t i, V z, int m, V xself, V centre = (V)0) {
   V out, dd = (V)0, dold = (V)0;
   if constexpr (OP == StencilOp::Cheb) dold = prev_correction(p, xself, p.out[i]);
+  if constexpr (OP == StencilOp::ChebFirst) dold = xself;
   const double c = finish_value<OP, DOT, V, OWN>(p, i, z, m, xself, centre, dold, out, dd);
   p.out[i] = out;
   return c;
@@ -124,6 +127,7 @@ __device__ __forceinline__ double finish_pre(const OpP<V>& p, int64_t i, V z, in
     const V di = OWN ? (V)1 / centre : p.dinv[i];
     V dd = p.c2 * (di * r);
     if constexpr (OP == StencilOp::Cheb) dd = fma(p.c1, prev_correction(p, xself, uprev), dd);
+    if constexpr (OP == StencilOp::ChebFirst) dd = fma(p.c1, xself, dd);
     const V out = xself + dd;
     p.out[i] = out;
     if constexpr (DOT) return (double)p.dotw[i] * (double)out;
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             xs[a] = xr[li * 3 + a];
-            dold[a] = OP == StencilOp::Cheb ? prev_correction(p, xs[a], p.out[gi * 3 + a]) : (V)0;
+            dold[a] = OP == StencilOp::Cheb ? prev_correction(p, xs[a], p.out[gi * 3 + a]) : xs[a];
           }
           contrib += finish_block3_value<OP, DOT, V>(p, gi, acc, xs, dold, out, dd);
 #pragma unroll
@@ -684,7 +688,8 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
           for (int64_t c = a0; c < e; ++c) s += p.out[(int64_t)gcopy[c] * 3 + a];
           z[a] = s;
           xs[a] = p.x[n0 * 3 + a];
-          dold[a] = OP == StencilOp::Cheb ? p.d[n0 * 3 + a] : (V)0;  // left there by the stencil kernel
+          // Cheb: left in p.d by the stencil kernel; ChebFirst: u_(k-1) itself
+          dold[a] = OP == StencilOp::Cheb ? p.d[n0 * 3 + a] : xs[a];
         }
         contrib += finish_block3_value<OP, DOT, V>(p, n0, z, xs, dold, out, dd);
         for (int64_t c = a0; c < e; ++c) {
@@ -705,8 +710,9 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
       // owns the dof) and written to every copy
       const int64_t i0 = (int64_t)gcopy[a0] * NDOF + a;
       V out, dd = (V)0;
-      const V dold = OP == StencilOp::Cheb ? p.d[i0] : (V)0;  // left there by the stencil kernel
-      contrib += finish_value<OP, DOT, V>(p, i0, s, m, p.x[i0], (V)0, dold, out, dd);
+      const V xs0 = p.x[i0];
+      const V dold = OP == StencilOp::Cheb ? p.d[i0] : xs0;  // Cheb: left in p.d by the stencil kernel
+      contrib += finish_value<OP, DOT, V>(p, i0, s, m, xs0, (V)0, dold, out, dd);
       for (int64_t c = a0; c < e; ++c) p.out[(int64_t)gcopy[c] * NDOF + a] = out;
     }
   }

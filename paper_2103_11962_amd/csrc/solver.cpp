@@ -465,13 +465,17 @@ static Bufs bufs(Level& L, bool lowp) {
   return {L.b.p, L.u.p, L.u2.p, L.d.p, L.r.p, L.dinv.p, L.dinv9.p};
 }
 
+// Kinds of Chebyshev step: the iterate before uin is in uout (Next), is zero (AfterZero: the step
+// after the zero-guess start), or there is no previous correction (Start: smoothing an iterate).
+enum class ChebKind { Next, AfterZero, Start };
+
 // One Chebyshev step uin -> uout; with dotw (FP64), also the partial sums of (dotw, uout) over the
 // owned copies into h->partials, whose count it returns.
-static int64_t cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, const void* b, const void* uin,
+static int64_t cheb_step(rmg_handle* h, Level& L, bool lowp, int k, ChebKind kind, const void* b, const void* uin,
                          void* uout, const double* dotw = nullptr) {
   const Bufs B = bufs(L, lowp);
   StencilArgs a;
-  a.op = first ? StencilOp::ChebFirst : StencilOp::Cheb;
+  a.op = kind == ChebKind::Next ? StencilOp::Cheb : StencilOp::ChebFirst;
   a.lowp = lowp;
   a.x = uin;
   a.out = uout;
@@ -479,13 +483,14 @@ static int64_t cheb_step(rmg_handle* h, Level& L, bool lowp, int k, bool first, 
   a.dinv = B.dinv;
   a.dinv9 = B.dinv9;
   a.d = B.d;
-  a.c1 = L.cheb_c1[k];
+  a.c1 = kind == ChebKind::Start ? 0.0 : L.cheb_c1[k];
   a.c2 = L.cheb_c2[k];
   if (dotw) {
     a.dotw = dotw;
     a.partials = h->partials.as<double>();
   }
-  if (h->profiling && &L == h->levels[0] && !first && !dotw) h->timers[kTimedCheb].acquire(&a.ev0, &a.ev1);
+  if (h->profiling && &L == h->levels[0] && kind == ChebKind::Next && !dotw)
+    h->timers[kTimedCheb].acquire(&a.ev0, &a.ev1);
   return launch_stencil_op(L, a, h->stream);
 }
 
@@ -530,10 +535,10 @@ void smooth_zero_guess(rmg_handle* h, int level, const double* b, double* u_out)
   }
   const int K = h->opt.cheb_degree;
   void* buf[2] = {L.u.p, u_out};
-  launch_cheb_zero(L, false, b, L.dinv.p, L.cheb_c2[0], buf[1], buf[0], st, L.dinv9.p);
+  launch_cheb_zero(L, false, b, L.dinv.p, L.cheb_c2[0], buf[0], st, L.dinv9.p);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
-    cheb_step(h, L, false, k, false, b, buf[cur], buf[1 - cur]);
+    cheb_step(h, L, false, k, k == 1 ? ChebKind::AfterZero : ChebKind::Next, b, buf[cur], buf[1 - cur]);
     cur = 1 - cur;
   }
   if (buf[cur] != u_out) launch_copy(L.ndofs(), (const double*)buf[cur], u_out, st);
@@ -545,7 +550,7 @@ void smooth_iterate(rmg_handle* h, int level, const double* b, double* u, double
   void* buf[2] = {u, tmp};
   int cur = 0;
   for (int k = 0; k < h->opt.cheb_degree; ++k) {
-    cheb_step(h, L, false, k, k == 0, b, buf[cur], buf[1 - cur]);
+    cheb_step(h, L, false, k, k == 0 ? ChebKind::Start : ChebKind::Next, b, buf[cur], buf[1 - cur]);
     cur = 1 - cur;
   }
   if (cur) launch_copy(L.ndofs(), tmp, u, h->stream);
@@ -738,10 +743,10 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, const d
   const Bufs B = bufs(L, lowp);
   // ping-pong buffers arranged so that the last post-smoothing step writes z
   void* buf[2] = {B.u, z};
-  launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], buf[1], buf[0], st, B.dinv9);
+  launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], buf[0], st, B.dinv9);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
-    cheb_step(h, L, lowp, k, false, b, buf[cur], buf[1 - cur]);
+    cheb_step(h, L, lowp, k, k == 1 ? ChebKind::AfterZero : ChebKind::Next, b, buf[cur], buf[1 - cur]);
     cur = 1 - cur;
   }
   // residual divided by multiplicity, restriction and coarse interface sum (Section 3.3)
@@ -762,7 +767,8 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, const d
   for (int k = 0; k < K; ++k) {
     // the last step also sums (dotw, z) when asked (the CG inner product (r, z))
     const double* w = (k == K - 1 && dotw && !lowp) ? dotw : nullptr;
-    const int64_t np = cheb_step(h, L, lowp, k, k == 0, b, buf[cur], buf[1 - cur], w);
+    const int64_t np =
+        cheb_step(h, L, lowp, k, k == 0 ? ChebKind::Start : ChebKind::Next, b, buf[cur], buf[1 - cur], w);
     if (w) launch_reduce(h->partials.as<double>(), np, scal(h), slot, st);
     cur = 1 - cur;
   }
