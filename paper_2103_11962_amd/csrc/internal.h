@@ -346,10 +346,9 @@ void amg_destroy(rmg_handle* h);
 void setup_hierarchy(rmg_handle* h);
 // z = V_level(b) with zero initial guess; z must not be one of the level's work vectors.
 // lowp: FP32 vectors and the levels' low-precision operators (b, z are float*), else FP64.
-// dotw (FP64, Chebyshev or Jacobi smoother, not the coarsest level): (dotw, z) over the owned
-// copies, summed by the last smoothing step, goes to scalar slot `slot`.
-void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, const double* dotw = nullptr,
-            int slot = -1);
+// dot_slot >= 0 (FP64, Chebyshev or Jacobi smoother, not the coarsest level): (b, z) over the
+// owned copies, summed by the last smoothing step, goes to that scalar slot.
+void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, int dot_slot = -1);
 // z = M^-1 r (one V-cycle in the configured precision); FP64 regional vectors.
 void apply_preconditioner(rmg_handle* h, const double* r, double* z);
 void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,

@@ -36,7 +36,7 @@ struct StencilArgs {
   void* d = nullptr;           // Cheb*: shared rows' correction, stored for the interface kernel
   double c1 = 0.0, c2 = 0.0;
   double* partials = nullptr;  // CgQ / dot-fused variants: one double per block
-  const void* dotw = nullptr;  // Cheb: when set, partial sums of (dotw, u_out) are produced
+  bool dot_rhs = false;        // Cheb*, FP64: also partial sums of (b, u_out) over the owned copies
   const void* dinv9 = nullptr; // Cheb, ChebFirst on 3-dof levels: nodal-block D~^-1 (9 per node), else null
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // when set, recorded around the stencil kernel only
 };

@@ -20,7 +20,6 @@ struct OpP {
   const V* dinv;
   V* d;
   V c1, c2;
-  const V* dotw;
   const V* dinv9;  // NDOF 3 with nodal blocks: D~^-1 as one row-major 3 x 3 block per node, else null
 };
 
@@ -40,7 +39,7 @@ __device__ __forceinline__ double finish_block3_value(const OpP<V>& p, int64_t n
     dd[a] = p.c2 * y;
     if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) dd[a] = fma(p.c1, dold[a], dd[a]);
     out[a] = xs[a] + dd[a];
-    if constexpr (DOT) c += (double)p.dotw[node * 3 + a] * (double)out[a];
+    if constexpr (DOT) c += (double)p.b[node * 3 + a] * (double)out[a];
   }
   return c;
 }
@@ -72,12 +71,13 @@ __device__ __forceinline__ double finish_value(const OpP<V>& p, int64_t i, V z, 
     out = (m == 1) ? r : r / (V)m;
     return 0.0;
   } else if constexpr (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst) {
-    const V r = p.b[i] - z;
+    const V bi = p.b[i];
+    const V r = bi - z;
     const V di = OWN ? (V)1 / centre : p.dinv[i];
     dd = p.c2 * (di * r);
     dd = fma(p.c1, dold, dd);  // one rounding in every kernel
     out = xself + dd;
-    if constexpr (DOT) return (double)p.dotw[i] * (double)out;
+    if constexpr (DOT) return (double)bi * (double)out;
     return 0.0;
   } else {  // CgQ
     out = z;
@@ -130,7 +130,7 @@ __device__ __forceinline__ double finish_pre(const OpP<V>& p, int64_t i, V z, in
     if constexpr (OP == StencilOp::ChebFirst) dd = fma(p.c1, xself, dd);
     const V out = xself + dd;
     p.out[i] = out;
-    if constexpr (DOT) return (double)p.dotw[i] * (double)out;
+    if constexpr (DOT) return (double)bi * (double)out;
     return 0.0;
   } else {
     return finish<OP, DOT, V, OWN>(p, i, z, m, xself, centre);
@@ -459,13 +459,13 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
 // loads are in flight while one is computed, and each plane read adds its products to the running
 // sums of the three nodes it neighbours in z.  The kernel is held to 80 VGPRs (six waves per SIMD):
 // four 6-wave blocks per CU instead of three, at the cost of one spilled register in the Chebyshev
-// step.  Consecutive blocks are dealt to the eight XCDs in turn, so
+// step; the variant that also sums (b, u_out) keeps five waves, where it needs no spill.  Consecutive blocks are dealt to the eight XCDs in turn, so
 // the blocks are mapped to tiles such that every XCD runs a contiguous run of tiles and neighbouring
 // tiles share their halo rows through its L2.  Every node sums its 27 products in stencil order with
 // one rounding each, as k_stencil3d does, so the results are those of streaming every coupling bit
 // for bit.
 template <StencilOp OP, bool DOT>
-__global__ __launch_bounds__(kTableThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_stencil_table(LevelView L, const Tile3* __restrict__ tiles,
+__global__ __launch_bounds__(kTableThreads) __attribute__((amdgpu_waves_per_eu(DOT ? 5 : 6))) void k_stencil_table(LevelView L, const Tile3* __restrict__ tiles,
                                                                  const double* __restrict__ table, OpP<double> p,
                                                                  double* __restrict__ partials) {
   constexpr int NT = kTableThreads;
@@ -726,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gp
 template <int NPTS, int NDOF, class V, class C, StencilOp OP, bool DOT>
 static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   OpP<V> p{static_cast<const V*>(a.x), static_cast<V*>(a.out), static_cast<const V*>(a.b),
-           static_cast<const V*>(a.dinv), static_cast<V*>(a.d), (V)a.c1, (V)a.c2, static_cast<const V*>(a.dotw),
+           static_cast<const V*>(a.dinv), static_cast<V*>(a.d), (V)a.c1, (V)a.c2,
            static_cast<const V*>(a.dinv9)};
   const C* coef = a.lowp ? L.coef_lo.as<C>() : L.coef.as<C>();
   const float* centre = L.center_lo.as<float>();
@@ -829,7 +829,7 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
 // FP64: every operation.
 template <int NPTS, int NDOF>
 static int64_t ops_f64(const Level& L, const StencilArgs& a, hipStream_t st) {
-  const bool dot = a.dotw != nullptr;
+  const bool dot = a.dot_rhs;
   switch (a.op) {
     case StencilOp::Matvec: return run<NPTS, NDOF, double, double, StencilOp::Matvec, false>(L, a, st);
     case StencilOp::Residual: return run<NPTS, NDOF, double, double, StencilOp::Residual, false>(L, a, st);
@@ -849,7 +849,7 @@ static int64_t ops_f64(const Level& L, const StencilArgs& a, hipStream_t st) {
 // FP32 vectors: the V-cycle operations only.
 template <int NDOF, class C>
 static int64_t ops_f32(const Level& L, const StencilArgs& a, hipStream_t st) {
-  RMG_REQUIRE(a.dotw == nullptr, RMG_ERR_ARG, "internal: fused dot products need FP64 vectors");
+  RMG_REQUIRE(!a.dot_rhs, RMG_ERR_ARG, "internal: fused dot products need FP64 vectors");
   switch (a.op) {
     case StencilOp::Matvec: return run<27, NDOF, float, C, StencilOp::Matvec, false>(L, a, st);
     case StencilOp::ResidualScaled: return run<27, NDOF, float, C, StencilOp::ResidualScaled, false>(L, a, st);

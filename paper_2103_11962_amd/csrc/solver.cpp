@@ -469,10 +469,10 @@ static Bufs bufs(Level& L, bool lowp) {
 // after the zero-guess start), or there is no previous correction (Start: smoothing an iterate).
 enum class ChebKind { Next, AfterZero, Start };
 
-// One Chebyshev step uin -> uout; with dotw (FP64), also the partial sums of (dotw, uout) over the
+// One Chebyshev step uin -> uout; with dot (FP64), also the partial sums of (b, uout) over the
 // owned copies into h->partials, whose count it returns.
 static int64_t cheb_step(rmg_handle* h, Level& L, bool lowp, int k, ChebKind kind, const void* b, const void* uin,
-                         void* uout, const double* dotw = nullptr) {
+                         void* uout, bool dot = false) {
   const Bufs B = bufs(L, lowp);
   StencilArgs a;
   a.op = kind == ChebKind::Next ? StencilOp::Cheb : StencilOp::ChebFirst;
@@ -485,11 +485,11 @@ static int64_t cheb_step(rmg_handle* h, Level& L, bool lowp, int k, ChebKind kin
   a.d = B.d;
   a.c1 = kind == ChebKind::Start ? 0.0 : L.cheb_c1[k];
   a.c2 = L.cheb_c2[k];
-  if (dotw) {
-    a.dotw = dotw;
+  if (dot) {
+    a.dot_rhs = true;
     a.partials = h->partials.as<double>();
   }
-  if (h->profiling && &L == h->levels[0] && kind == ChebKind::Next && !dotw)
+  if (h->profiling && &L == h->levels[0] && kind == ChebKind::Next && !dot)
     h->timers[kTimedCheb].acquire(&a.ev0, &a.ev1);
   return launch_stencil_op(L, a, h->stream);
 }
@@ -703,7 +703,7 @@ void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit,
   }
 }
 
-void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, const double* dotw, int slot) {
+void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, int dot_slot) {
   const int nl = (int)h->levels.size();
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
@@ -765,11 +765,11 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, const d
   span = level_span_begin(h, level);
   launch_prolong_add(L, C, lowp, BC.u2, buf[cur], st);
   for (int k = 0; k < K; ++k) {
-    // the last step also sums (dotw, z) when asked (the CG inner product (r, z))
-    const double* w = (k == K - 1 && dotw && !lowp) ? dotw : nullptr;
+    // the last step also sums (b, z) when asked (the CG inner product (r, z))
+    const bool dot = k == K - 1 && dot_slot >= 0 && !lowp;
     const int64_t np =
-        cheb_step(h, L, lowp, k, k == 0 ? ChebKind::Start : ChebKind::Next, b, buf[cur], buf[1 - cur], w);
-    if (w) launch_reduce(h->partials.as<double>(), np, scal(h), slot, st);
+        cheb_step(h, L, lowp, k, k == 0 ? ChebKind::Start : ChebKind::Next, b, buf[cur], buf[1 - cur], dot);
+    if (dot) launch_reduce(h->partials.as<double>(), np, scal(h), dot_slot, st);
     cur = 1 - cur;
   }
   level_span_end(h, span);
@@ -784,7 +784,7 @@ static void precondition(rmg_handle* h, const double* r, double* z, int slot = -
     hybrid_cycle(h, r, z);
   } else if (h->opt.precision == RMG_PREC_FP64) {
     const bool fused = slot >= 0 && h->opt.smoother <= 1 && h->levels.size() > 1;
-    vcycle(h, 0, false, r, z, fused ? r : nullptr, slot);
+    vcycle(h, 0, false, r, z, fused ? slot : -1);
     if (fused) return;
   } else {
     launch_f64_to_f32(L.ndofs(), r, L.b32.as<float>(), h->stream);
