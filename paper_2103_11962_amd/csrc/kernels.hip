@@ -134,17 +134,15 @@ constexpr int kReduceThreads = 1024;
 
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double* __restrict__ partials, int64_t n,
                                                            double* scalars, int slot) {
-  // four strided sums per thread, so that four loads are in flight
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  // eight strided sums per thread, so that eight loads are in flight
+  double sj[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int64_t i = threadIdx.x;
-  for (; i + 3 * kReduceThreads < n; i += 4 * kReduceThreads) {
-    s0 += partials[i];
-    s1 += partials[i + kReduceThreads];
-    s2 += partials[i + 2 * kReduceThreads];
-    s3 += partials[i + 3 * kReduceThreads];
+  for (; i + 7 * kReduceThreads < n; i += 8 * kReduceThreads) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sj[j] += partials[i + j * kReduceThreads];
   }
-  for (; i < n; i += kReduceThreads) s0 += partials[i];
-  const double s = (s0 + s1) + (s2 + s3);
+  for (; i < n; i += kReduceThreads) sj[0] += partials[i];
+  const double s = ((sj[0] + sj[1]) + (sj[2] + sj[3])) + ((sj[4] + sj[5]) + (sj[6] + sj[7]));
   __shared__ double sm[kReduceThreads];
   sm[threadIdx.x] = s;
   __syncthreads();
