@@ -127,6 +127,15 @@ __device__ __forceinline__ double tap(int t, int mL, int mR) {
   return t == 0 ? 1.0 : (d < m ? (double)(m - d) * inv_span(m) : 0.0);
 }
 
+// Work item of block b in a grid of n blocks.  The hardware deals consecutive blocks to the eight
+// XCDs in turn, each with its own L2; this mapping gives every XCD a contiguous run of items, so
+// neighbouring items (tiles, node blocks) that share data run on the same XCD and meet in its L2.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int kXcds = 8;
+  const int x = b % kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + min(x, r) + b / kXcds;
+}
+
 // Sum over a block of kBlock threads; the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

@@ -510,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_planes(LevelView F, LevelVi
   extern __shared__ double xfer_stage[];
   V* const stage0 = reinterpret_cast<V*>(xfer_stage);
   V* const stage1 = stage0 + stage_vals;
-  const Tile3 T = tiles[blockIdx.x];
+  const Tile3 T = tiles[xcd_item((int)blockIdx.x, (int)gridDim.x)];
   const RegionGeo RF = F.regs[T.region];
   const RegionGeo RC = C.regs[T.region];
   const int t = threadIdx.x;
@@ -796,7 +796,7 @@ template <int DIM, int NDOF, class V>
 __global__ __launch_bounds__(kBlock) void k_prolong_rows(LevelView F, LevelView C, const Tile3* __restrict__ tiles,
                                                          const V* __restrict__ ubar, V* __restrict__ u) {
   __shared__ V stage[2][2 * kProlongStageXY * NDOF];  // two buffers of two coarse planes
-  const Tile3 T = tiles[blockIdx.x];
+  const Tile3 T = tiles[xcd_item((int)blockIdx.x, (int)gridDim.x)];
   const RegionGeo RF = F.regs[T.region];
   const RegionGeo RC = C.regs[T.region];
   const int t = threadIdx.x;

@@ -158,7 +158,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
                                                     double* __restrict__ partials) {
   constexpr int NB = NDOF * NDOF;
   constexpr int NCOEF = SYM ? kSymPts * NB : NPTS * NB;
-  const BlockDesc bd = L.blocks[blockIdx.x];
+  // every XCD runs a contiguous run of node blocks, so a block finds the records of the plane below
+  // (its lower couplings on symmetric levels) in its own XCD's L2; its partial sum goes to the
+  // node block's slot, as without the mapping
+  const int blk = xcd_item((int)blockIdx.x, (int)gridDim.x);
+  const BlockDesc bd = L.blocks[blk];
   const RegionGeo R = L.regs[bd.region];
   const int li = bd.start + (int)threadIdx.x;
   double contrib = 0.0;
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
   }
   if constexpr (DOT || OP == StencilOp::CgQ) {
     const double s = block_sum(contrib);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    if (threadIdx.x == 0) partials[blk] = s;
   }
 }
 
@@ -276,8 +280,11 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
   __shared__ C srow[SYM ? 4 : 1][SYM ? kT3 : 1];
   const int t = threadIdx.x;
   double contrib = 0.0;
-  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
-    const Tile3 T = tiles[ti];
+  // one tile per block: every XCD runs a contiguous run of tiles (xcd_item), so neighbouring
+  // tiles' halo rows meet in its L2; persistent grids stride over the tiles
+  const bool one = (int)gridDim.x == ntiles;
+  for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
+    const Tile3 T = tiles[one ? xcd_item(it, ntiles) : it];
     const RegionGeo R = L.regs[T.region];
     const int W = T.tx + 2, PL = (T.ty + 2) * W;
     const V* __restrict__ xr = p.x + R.off;
@@ -442,7 +449,8 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
     if (t == 0) {
       double s = 0.0;
       for (int i = 0; i < kT3 / 64; ++i) s += sm[i];
-      partials[blockIdx.x] = s;
+      // one tile per block: the tile's slot, as without the mapping
+      partials[one ? xcd_item((int)blockIdx.x, ntiles) : (int)blockIdx.x] = s;
     }
   }
 }
@@ -459,8 +467,8 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
 // loads are in flight while one is computed, and each plane read adds its products to the running
 // sums of the three nodes it neighbours in z.  The kernel is held to 80 VGPRs (six waves per SIMD):
 // four 6-wave blocks per CU instead of three, at the cost of one spilled register in the Chebyshev
-// step; the variant that also sums (b, u_out) keeps five waves, where it needs no spill.  Consecutive blocks are dealt to the eight XCDs in turn, so
-// the blocks are mapped to tiles such that every XCD runs a contiguous run of tiles and neighbouring
+// step; the variant that also sums (b, u_out) keeps five waves, where it needs no spill.  Blocks
+// are mapped to tiles so that every XCD runs a contiguous run of tiles (xcd_item) and neighbouring
 // tiles share their halo rows through its L2.  Every node sums its 27 products in stencil order with
 // one rounding each, as k_stencil3d does, so the results are those of streaming every coupling bit
 // for bit.
@@ -474,13 +482,10 @@ __global__ __launch_bounds__(kTableThreads) __attribute__((amdgpu_waves_per_eu(D
   constexpr bool kPreB = OP == StencilOp::Residual || OP == StencilOp::ResidualScaled || OP == StencilOp::Cheb ||
                          OP == StencilOp::ChebFirst;
   constexpr bool kPreD = OP == StencilOp::Cheb;
-  constexpr int kXcds = 8;
   constexpr int kXRows = 4 * kTableRows;  // x-face lanes: four a row
   __shared__ double pl[2][kPlane];
   __shared__ double xt[5][kClassPts][kXRows];  // the x-face lanes' couplings by z class
-  const int nb = (int)gridDim.x, xcd = (int)blockIdx.x % kXcds, q = nb / kXcds, rem = nb % kXcds;
-  const int ti = xcd * q + min(xcd, rem) + (int)blockIdx.x / kXcds;
-  const Tile3 T = tiles[ti];
+  const Tile3 T = tiles[xcd_item((int)blockIdx.x, (int)gridDim.x)];
   const RegionGeo R = L.regs[T.region];
   const double* __restrict__ tab = table + (int64_t)T.region * kClasses * kClassPts;
   const int t = threadIdx.x;
