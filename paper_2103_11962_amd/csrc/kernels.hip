@@ -2050,8 +2050,10 @@ static void make_class_table(Level& L, hipStream_t st) {
     tab.release();
     ok.release();
     clear_split(L);
-  } else {
+  } else if (L.use_tiles && L.tile_threads == kTileThreadsF64) {
     make_split(L, flags);
+  } else {
+    clear_split(L);  // node blocks: each block of a served region reads the tables
   }
 }
 

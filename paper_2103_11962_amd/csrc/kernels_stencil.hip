@@ -152,12 +152,19 @@ __device__ __forceinline__ auto coefv(const C* __restrict__ cf, const float* __r
 // kSymPts blocks per node; the block of a lower offset s is the transpose of the neighbour's
 // upper block at offset 26 - s, read from the neighbour's record (consecutive lanes read
 // consecutive records, and the record was streamed moments before by a nearby block).
+// table (FP64 scalar 27-point symmetric levels, else null): the regions' class tables, used for
+// the regions whose flag in table_ok is set: a node's 27 couplings are its class's (the values the
+// half stencil applies, bit for bit), read from the small table instead of from its own and its
+// neighbours' records.
 template <int NPTS, int NDOF, class V, class C, StencilOp OP, bool DOT, bool SYM>
 __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __restrict__ coef,
                                                     const float* __restrict__ centre, OpP<V> p,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials, const double* __restrict__ table,
+                                                    const int* __restrict__ table_ok) {
   constexpr int NB = NDOF * NDOF;
   constexpr int NCOEF = SYM ? kSymPts * NB : NPTS * NB;
+  constexpr bool kTab = NPTS == 27 && NDOF == 1 && SYM && std::is_same<V, double>::value &&
+                        std::is_same<C, double>::value;
   // every XCD runs a contiguous run of node blocks, so a block finds the records of the plane below
   // (its lower couplings on symmetric levels) in its own XCD's L2; its partial sum goes to the
   // node block's slot, as without the mapping
@@ -174,6 +181,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
     const C* __restrict__ cf = coef + coef_index(gi, 0, NCOEF);
     const int sy = R.ex, sz = R.ex * R.ey;
     const bool inner = x > 0 && x < R.ex - 1 && y > 0 && y < R.ey - 1 && (NPTS != 27 || (z > 0 && z < R.ez - 1));
+    const bool tabbed = kTab && table && table_ok[bd.region];  // uniform over the block (one region)
+    const double* __restrict__ tc =
+        tabbed ? table + ((int64_t)bd.region * kClasses +
+                          (axis_class(z, R.ez) * 5 + axis_class(y, R.ey)) * 5 + axis_class(x, R.ex)) * kClassPts
+               : nullptr;
     V acc[NDOF];
 #pragma unroll
     for (int a = 0; a < NDOF; ++a) acc[a] = (V)0;
@@ -186,7 +198,9 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
       if (ok) {
         const int nb = li + dx + dy * sy + dz * sz;
         if constexpr (SYM) {
-          if (s >= 13) {
+          if (kTab && tabbed) {
+            acc[0] += (V)tc[s] * xr[nb];
+          } else if (s >= 13) {
 #pragma unroll
             for (int a = 0; a < NDOF; ++a)
 #pragma unroll
@@ -753,12 +767,11 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
       }
       bool split = false;
       if constexpr (std::is_same<V, double>::value && std::is_same<C, double>::value) {
-        if (table && sym && L.tile_threads == kTileThreadsF64) {
+        if (table && sym && L.tile_threads == kTileThreadsF64 && !L.table_tiles.empty()) {
           // region-table split: the served regions' whole-region tiles, then the other regions'
           // tiles, each with its own run of partial sums
           const int64_t nd = (int64_t)L.table_tiles.size(), no = (int64_t)L.other_tiles.size();
-          RMG_REQUIRE(L.table_served.size() == (size_t)L.nreg && nd > 0, RMG_ERR_ARG,
-                      "internal: class tables without their split");
+          RMG_REQUIRE(L.table_served.size() == (size_t)L.nreg, RMG_ERR_ARG, "internal: class tables without their split");
           RMG_LAUNCH((k_stencil_table<OP, DOT>), dim3(nd), dim3(kTableThreads), 0, st, v, L.d_table_tiles.as<Tile3>(),
                      table, p, a.partials);
           if (no > 0)
@@ -793,16 +806,20 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   }
   if (!tiled) {
     const C* symc = static_cast<const C*>(a.lowp ? L.coef_lo_sym.p : L.coef_sym.p);
+    // the class tables of an FP64 level run by node blocks
+    const bool ntab = !a.lowp && NPTS == 27 && NDOF == 1 && L.class_table.p && L.class_table_ok.p;
+    const double* ntable = ntab ? L.class_table.as<double>() : nullptr;
+    const int* ntable_ok = ntab ? L.class_table_ok.as<int>() : nullptr;
     auto node = [&](const LevelView& vk, int nblocks, double* part) {
       if constexpr (NPTS == 27) {
         if (symc) {
           RMG_LAUNCH((k_stencil<NPTS, NDOF, V, C, OP, DOT, true>), dim3(nblocks), dim3(kBlock), 0, st, vk,
-                             symc, centre, p, part);
+                             symc, centre, p, part, ntable, ntable_ok);
           return;
         }
       }
       RMG_LAUNCH((k_stencil<NPTS, NDOF, V, C, OP, DOT, false>), dim3(nblocks), dim3(kBlock), 0, st, vk, coef,
-                         centre, p, part);
+                         centre, p, part, nullptr, nullptr);
     };
     if (L.per_region) {
       // unbatched: one launch per region over its slice of the block table (partials keep their slots)
