@@ -97,9 +97,12 @@ constexpr int kTileThreadsF64 = 768;
 constexpr int kTileThreadsF32 = 256;
 // Threads per whole-region tile of a table region (k_stencil_table): the inner x-nodes of a few rows
 // padded to whole wavefronts plus their rows' four x-face nodes; planes and rows per tile at most.
-constexpr int kTableThreads = 384;
+// Five rows of 82 nodes fill 468 of 512 lanes; at six waves per SIMD three 8-wave blocks run per CU
+// (on C2: 284 us per Chebyshev step, against 307 us for four rows in 384 threads, 288 us for eight
+// rows in 768, 312 us for seven in 640).
+constexpr int kTableThreads = 512;
 constexpr int kTablePlanes = 41;
-constexpr int kTableRows = 4;
+constexpr int kTableRows = 5;
 // Largest (tx + 2)(ty + 2) over tiles of at most nt nodes (tx * ty <= nt): the single row, ty = 1.
 constexpr int tile_plane_cap(int nt) { return 3 * (nt + 2); }
 // Region tables: a node's class along an axis of extent e >= 5 is its coordinate on the two low

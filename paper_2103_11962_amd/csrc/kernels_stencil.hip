@@ -479,9 +479,9 @@ __global__ __launch_bounds__(NT) void k_stencil3d(LevelView L, const Tile3* __re
 // input vector's planes, whole rows with their halo, pass through two LDS slots; each plane is
 // fetched four planes ahead into registers and b and u_(k-2) two planes ahead, so that two planes'
 // loads are in flight while one is computed, and each plane read adds its products to the running
-// sums of the three nodes it neighbours in z.  The kernel is held to 80 VGPRs (six waves per SIMD):
-// four 6-wave blocks per CU instead of three, at the cost of one spilled register in the Chebyshev
-// step; the variant that also sums (b, u_out) keeps five waves, where it needs no spill.  Blocks
+// sums of the three nodes it neighbours in z.  The kernel is held to 80 VGPRs (six waves per SIMD,
+// three 8-wave blocks per CU), at the cost of one spilled register in the Chebyshev step; the
+// variant that also sums (b, u_out) keeps five waves, where it needs no spill.  Blocks
 // are mapped to tiles so that every XCD runs a contiguous run of tiles (xcd_item) and neighbouring
 // tiles share their halo rows through its L2.  Every node sums its 27 products in stencil order with
 // one rounding each, as k_stencil3d does, so the results are those of streaming every coupling bit
