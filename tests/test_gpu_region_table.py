@@ -40,8 +40,9 @@ def run(w, b, **kw):
     x = torch.zeros_like(b)
     out = h.solve(b, x, rtol=1e-8)
     served = h.level_table_regions(0)
+    served1 = h.level_table_regions(1) if w.nlevels > 2 else 0  # node-block level below
     h.close()
-    return z, x, out, served
+    return z, x, out, served, served1
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
@@ -52,11 +53,18 @@ def test_table_equals_streamed_couplings(hip_device, case):
     w = synth.workload(name)
     b = harness.to_dev(synth.rhs(w))
     print(f"[gpu-table] {name} {kw}", flush=True)
-    z1, x1, o1, n1 = run(w, b, **kw)
-    z0, x0, o0, n0 = run(w, b, region_table=0, **kw)
+    z1, x1, o1, n1, m1 = run(w, b, **kw)
+    z0, x0, o0, n0, m0 = run(w, b, region_table=0, **kw)
     thick = int(sum(min(int(v) for v in e) >= 5 for e in np.asarray(w.extents)))
     want = thick if expect == "thick" else expect
     assert n0 == 0 and n1 == want
+    # the Galerkin level below a constant-coefficient layout of 28^3 regions (10^3 there) is served
+    # too; none without tables or in the FP32 V-cycle
+    assert m0 == 0
+    if kw.get("precision", 0) != 0:
+        assert m1 == 0
+    elif name == "c2_mid":
+        assert m1 == len(w.extents)
     assert torch.equal(z1, z0)  # every stencil operation of the cycle, bit for bit
     # CG: the product's fused inner-product partial sums follow the launch decomposition (deep
     # tiles and shell blocks with the table, whole tiles without), so only their rounding differs
