@@ -148,17 +148,19 @@ typedef struct {
                          after each coarse correction, and a dense inverse on the first AMG level
                          with at most amg_coarse_size rows */
   int amg_coarse_size; /* rows of the directly solved AMG level, in [1, 20000] (default 2000) */
-  int region_table;   /* 1 (default): on FP64 levels run by the symmetric 2.5D kernel on 768-thread
-                         tiles (the FP64 V-cycle; the FP32 V-cycle's narrower tiles always
-                         stream), setup sorts every region's nodes into 125 classes (per axis: the
-                         two low layers, the inside, the two high layers) and compares each node's
-                         27 couplings (its stored upper ones and its neighbours' mirrored ones)
-                         with those of its class's first node; where all are equal bit for bit (a
-                         region whose operator is the same everywhere inside, as the structured
-                         regions of the Q1 Laplacian, the per-region diffusion and elasticity
-                         problems give), the region runs whole-row tiles that take every coupling
-                         from the region's 125 x 27 class table instead of streaming them from
-                         memory.  Results are bit for bit those of 0, which always streams them */
+  int region_table;   /* 1 (default): on symmetric 27-point FP64 levels of the FP64 V-cycle (scalar
+                         levels on 768-thread 2.5D tiles or node blocks, 3-dof levels on node
+                         blocks; the FP32 V-cycle always streams), setup sorts every region's nodes
+                         into 125 classes (per axis: the two low layers, the inside, the two high
+                         layers) and compares each node's 27 couplings (its stored upper ones and
+                         its neighbours' mirrored ones; 3 x 3 blocks on 3-dof levels) with those of
+                         its class's first node; where all are equal bit for bit (a region whose
+                         operator is the same everywhere inside, as the structured regions of the
+                         Q1 Laplacian, the per-region diffusion and elasticity problems give), the
+                         region's couplings come from its 125 x 27 class table (whole-row tiles on
+                         tiled levels, each node's class row on node blocks) instead of being
+                         streamed from memory.  Results are bit for bit those of 0, which always
+                         streams them */
   int tile_planes;    /* planes per 2.5D tile: 0 (default) chooses (41 on FP64 levels that keep at
                          least 1024 such tiles, else 21); 21 or 41 forces that depth on every
                          tiled level, so that a problem small enough for the oracle runs the launch

@@ -1991,33 +1991,42 @@ __device__ __forceinline__ bool same_bits(double a, double b) { return __double_
 
 
 // Coupling s of node (x, y, z) of region R, A(i, i + offset(s)), as the symmetric kernels read it.
+template <int NDOF>
 __device__ __forceinline__ double read_coupling(const RegionGeo& R, const double* __restrict__ sym, int x, int y,
-                                                int z, int s) {
+                                                int z, int s, int a, int b) {
+  constexpr int NB = NDOF * NDOF, NC = kSymPts * NB;
   const int64_t gi = R.off + ((int64_t)z * R.ey + y) * R.ex + x;
-  if (s >= 13) return sym[coef_index(gi, s - 13, kSymPts)];
+  if (s >= 13) return sym[coef_index(gi, (s - 13) * NB + a * NDOF + b, NC)];
   int dx, dy, dz;
   stencil_offset<27>(s, dx, dy, dz);
   if ((unsigned)(x + dx) >= (unsigned)R.ex || (unsigned)(y + dy) >= (unsigned)R.ey || (unsigned)(z + dz) >= (unsigned)R.ez)
     return 0.0;
-  return sym[coef_index(gi + dx + (int64_t)dy * R.ex + (int64_t)dz * R.ex * R.ey, 13 - s, kSymPts)];
+  // a lower block is the transpose of the neighbour's upper block
+  return sym[coef_index(gi + dx + (int64_t)dy * R.ex + (int64_t)dz * R.ex * R.ey, (13 - s) * NB + b * NDOF + a, NC)];
 }
 
-// One block per region, one thread per class.
+// One block per region, one thread per class; a class's row holds its 27 (blocks of) couplings in
+// stencil order, each block row-major.
+template <int NDOF>
 __global__ __launch_bounds__(128) void k_class_table_ref(LevelView L, const double* __restrict__ sym,
                                                          double* __restrict__ table, int* __restrict__ ok) {
+  constexpr int NB = NDOF * NDOF;
   const int k = blockIdx.x, c = threadIdx.x;
   const RegionGeo R = L.regs[k];
   const bool big = R.ex >= 5 && R.ey >= 5 && R.ez >= 5;
   if (c == 0) ok[k] = big ? 1 : 0;
   if (c >= kClasses) return;
   const int x = class_node(c % 5, R.ex), y = class_node(c / 5 % 5, R.ey), z = class_node(c / 25, R.ez);
-  double* out = table + ((int64_t)k * kClasses + c) * kClassPts;
-  for (int s = 0; s < kClassPts; ++s) out[s] = big ? read_coupling(R, sym, x, y, z, s) : 0.0;
+  double* out = table + ((int64_t)k * kClasses + c) * kClassPts * NB;
+  for (int s = 0; s < kClassPts; ++s)
+    for (int e = 0; e < NB; ++e) out[s * NB + e] = big ? read_coupling<NDOF>(R, sym, x, y, z, s, e / NDOF, e % NDOF) : 0.0;
 }
 
 // One thread per node: a coupling that differs from its class's clears the region's flag.
+template <int NDOF>
 __global__ __launch_bounds__(kBlock) void k_class_table_check(LevelView L, const double* __restrict__ sym,
                                                               const double* __restrict__ table, int* __restrict__ ok) {
+  constexpr int NB = NDOF * NDOF;
   const BlockDesc bd = L.blocks[blockIdx.x];
   const RegionGeo R = L.regs[bd.region];
   const int li = bd.start + (int)threadIdx.x;
@@ -2025,9 +2034,11 @@ __global__ __launch_bounds__(kBlock) void k_class_table_check(LevelView L, const
   int x, y, z;
   decompose(R, li, x, y, z);
   const int c = (axis_class(z, R.ez) * 5 + axis_class(y, R.ey)) * 5 + axis_class(x, R.ex);
-  const double* ref = table + ((int64_t)bd.region * kClasses + c) * kClassPts;
+  const double* ref = table + ((int64_t)bd.region * kClasses + c) * kClassPts * NB;
   bool same = true;
-  for (int s = 0; s < kClassPts; ++s) same = same && same_bits(read_coupling(R, sym, x, y, z, s), ref[s]);
+  for (int s = 0; s < kClassPts; ++s)
+    for (int e = 0; e < NB; ++e)
+      same = same && same_bits(read_coupling<NDOF>(R, sym, x, y, z, s, e / NDOF, e % NDOF), ref[s * NB + e]);
   if (!same) ok[bd.region] = 0;
 }
 
@@ -2035,11 +2046,18 @@ static void make_class_table(Level& L, hipStream_t st) {
   DBuf& tab = L.class_table;
   DBuf& ok = L.class_table_ok;
   const double* sym = static_cast<const double*>(L.coef_sym.p);
-  tab.alloc(sizeof(double) * kClasses * kClassPts * L.nreg);
+  const int nb = L.ndof * L.ndof;
+  tab.alloc(sizeof(double) * kClasses * kClassPts * nb * L.nreg);
   ok.alloc(sizeof(int) * L.nreg);
-  RMG_LAUNCH(k_class_table_ref, dim3(L.nreg), dim3(128), 0, st, L.view(), sym, tab.as<double>(), ok.as<int>());
-  RMG_LAUNCH(k_class_table_check, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
-             static_cast<const double*>(tab.p), ok.as<int>());
+  if (L.ndof == 3) {
+    RMG_LAUNCH(k_class_table_ref<3>, dim3(L.nreg), dim3(128), 0, st, L.view(), sym, tab.as<double>(), ok.as<int>());
+    RMG_LAUNCH(k_class_table_check<3>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
+               static_cast<const double*>(tab.p), ok.as<int>());
+  } else {
+    RMG_LAUNCH(k_class_table_ref<1>, dim3(L.nreg), dim3(128), 0, st, L.view(), sym, tab.as<double>(), ok.as<int>());
+    RMG_LAUNCH(k_class_table_check<1>, dim3(L.blocks.size()), dim3(kBlock), 0, st, L.view(), sym,
+               static_cast<const double*>(tab.p), ok.as<int>());
+  }
   LAUNCH_CHECK();
   std::vector<int> flags(L.nreg);
   RMG_HIP(hipMemcpyAsync(flags.data(), ok.p, sizeof(int) * L.nreg, hipMemcpyDeviceToHost, st));
@@ -2102,7 +2120,7 @@ bool launch_make_sym(Level& L, bool lowp, hipStream_t st, bool table) {
   RMG_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
   RMG_HIP(hipStreamSynchronize(st));
   if (hflag) out.release();
-  else if (table && L.ndof == 1) make_class_table(L, st);
+  else if (table) make_class_table(L, st);
   return hflag == 0;
 }
 

@@ -152,10 +152,10 @@ __device__ __forceinline__ auto coefv(const C* __restrict__ cf, const float* __r
 // kSymPts blocks per node; the block of a lower offset s is the transpose of the neighbour's
 // upper block at offset 26 - s, read from the neighbour's record (consecutive lanes read
 // consecutive records, and the record was streamed moments before by a nearby block).
-// table (FP64 scalar 27-point symmetric levels, else null): the regions' class tables, used for
-// the regions whose flag in table_ok is set: a node's 27 couplings are its class's (the values the
-// half stencil applies, bit for bit), read from the small table instead of from its own and its
-// neighbours' records.
+// table (FP64 27-point symmetric levels, else null): the regions' class tables, used for the
+// regions whose flag in table_ok is set: a node's 27 couplings (3 x 3 blocks on 3-dof levels) are
+// its class's (the values the half stencil applies, bit for bit), read from the small table
+// instead of from its own and its neighbours' records.
 template <int NPTS, int NDOF, class V, class C, StencilOp OP, bool DOT, bool SYM>
 __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __restrict__ coef,
                                                     const float* __restrict__ centre, OpP<V> p,
@@ -163,8 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
                                                     const int* __restrict__ table_ok) {
   constexpr int NB = NDOF * NDOF;
   constexpr int NCOEF = SYM ? kSymPts * NB : NPTS * NB;
-  constexpr bool kTab = NPTS == 27 && NDOF == 1 && SYM && std::is_same<V, double>::value &&
-                        std::is_same<C, double>::value;
+  constexpr bool kTab = NPTS == 27 && SYM && std::is_same<V, double>::value && std::is_same<C, double>::value;
   // every XCD runs a contiguous run of node blocks, so a block finds the records of the plane below
   // (its lower couplings on symmetric levels) in its own XCD's L2; its partial sum goes to the
   // node block's slot, as without the mapping
@@ -184,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
     const bool tabbed = kTab && table && table_ok[bd.region];  // uniform over the block (one region)
     const double* __restrict__ tc =
         tabbed ? table + ((int64_t)bd.region * kClasses +
-                          (axis_class(z, R.ez) * 5 + axis_class(y, R.ey)) * 5 + axis_class(x, R.ex)) * kClassPts
+                          (axis_class(z, R.ez) * 5 + axis_class(y, R.ey)) * 5 + axis_class(x, R.ex)) * kClassPts * NB
                : nullptr;
     V acc[NDOF];
 #pragma unroll
@@ -199,7 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView L, const C* __rest
         const int nb = li + dx + dy * sy + dz * sz;
         if constexpr (SYM) {
           if (kTab && tabbed) {
-            acc[0] += (V)tc[s] * xr[nb];
+#pragma unroll
+            for (int a = 0; a < NDOF; ++a)
+#pragma unroll
+              for (int b = 0; b < NDOF; ++b) acc[a] += (V)tc[(s * NDOF + a) * NDOF + b] * xr[nb * NDOF + b];
           } else if (s >= 13) {
 #pragma unroll
             for (int a = 0; a < NDOF; ++a)
@@ -807,7 +809,7 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   if (!tiled) {
     const C* symc = static_cast<const C*>(a.lowp ? L.coef_lo_sym.p : L.coef_sym.p);
     // the class tables of an FP64 level run by node blocks
-    const bool ntab = !a.lowp && NPTS == 27 && NDOF == 1 && L.class_table.p && L.class_table_ok.p;
+    const bool ntab = !a.lowp && NPTS == 27 && L.class_table.p && L.class_table_ok.p;
     const double* ntable = ntab ? L.class_table.as<double>() : nullptr;
     const int* ntable_ok = ntab ? L.class_table_ok.as<int>() : nullptr;
     auto node = [&](const LevelView& vk, int nblocks, double* part) {

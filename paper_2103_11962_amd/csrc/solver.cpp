@@ -249,7 +249,7 @@ static void configure_level(rmg_handle* h, Level& L, bool with_b, bool sym) {
   L.coef_lo_sym.release();
   if (sym) {
     // class tables for the FP64 2.5D tiles and, on FP64 levels run by node blocks, for those blocks
-    const bool tables = o.region_table != 0 && fp64 && L.ndof == 1 && L.npts == 27 &&
+    const bool tables = o.region_table != 0 && fp64 && L.npts == 27 &&
                         ((L.use_tiles && L.tile_threads == kTileThreadsF64) || (!L.use_tiles && !L.per_region));
     launch_make_sym(L, false, h->stream, tables);
   } else {

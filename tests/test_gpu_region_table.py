@@ -1,11 +1,12 @@
-"""Region table of the symmetric FP64 levels: where every node two or more nodes inside a region
-(one on faces whose next layer allows it) has the same stored upper couplings, those nodes run as
-deep-box tiles that take their couplings from a 14-value table of the region instead of streaming
-them, and the region's outer layers run as node blocks.  Each case solves twice, with the table
-(default) and with every coupling streamed (region_table = 0): the V-cycle output must agree bit
-for bit, the PCG iterate and residual history to the rounding of the CG inner product.  The regions served by the table follow the coefficients: every region with at least
-5 nodes a side of a constant-coefficient Laplacian, none under per-element random coefficients or
-on regions too thin to have such nodes; the FP32 V-cycle (narrower tiles) builds no table.
+"""Region class tables of the symmetric FP64 levels: where every node of a region has, bit for bit,
+the 27 couplings (3 x 3 blocks for elasticity) of its class (per axis the two low layers, the
+inside, the two high layers), the region takes its couplings from its 125-class table: whole-row
+class-table tiles on tiled levels, each node's class row on node-block levels.  Each case solves
+twice, with the tables (default) and with every coupling streamed (region_table = 0): the V-cycle
+output must agree bit for bit, the PCG iterate and residual history to the rounding of the CG
+inner product.  The regions served follow the coefficients: every region with at least 5 nodes a
+side of a constant-coefficient Laplacian or per-region elasticity, none under per-element random
+coefficients or on regions too thin; the FP32 V-cycle builds no table.
 """
 import numpy as np
 import pytest
@@ -26,6 +27,7 @@ CASES = [
     ("uneven_c4_small", dict(stencil_kernel=2), "thick"),
     ("c4_small", dict(stencil_kernel=2), "thick"),
     ("c5_small", dict(stencil_kernel=2), 0),
+    ("c3_small", dict(), "thick"),  # elasticity: node blocks read 3 x 3 blocks from the class tables
     ("uneven_tiny3d", dict(stencil_kernel=2), 0),
 ]
 IDS = [f"{n}-" + "-".join(f"{k}{v}" for k, v in kw.items()) for n, kw, _ in CASES]
