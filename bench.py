@@ -168,17 +168,20 @@ def _setup(h, w, **opts):
     return (time.perf_counter() - t0) * 1e3
 
 
-def _cheb_bytes(h, kind, precision, stored=True):
+def _cheb_bytes(h, kind, precision, stored=True, nreg=None):
     """Bytes per node of the level-0 Chebyshev step: the stencil blocks (stored: the ones the level
-    streams, full or upper half, see rmg_level_kernel; else the method's full 27 blocks) and the
-    vectors u_(k-1), b, u_(k-2), D~^-1 read and u_k written (the method's step also reads and
-    writes its direction vector d: one vector more each way); with BF16 storage the centre block
-    comes from an FP32 array.  Stored: the scalar tiled kernel in FP64 or FP32 computes D~^-1 of
-    one-region rows instead of reading it."""
+    streams, full or upper half, see rmg_level_kernel, none for regions served by their class
+    tables when nreg is given; else the method's full 27 blocks) and the vectors u_(k-1), b,
+    u_(k-2), D~^-1 read and u_k written (the method's step also reads and writes its direction
+    vector d: one vector more each way); with BF16 storage the centre block comes from an FP32
+    array.  Stored: the scalar tiled kernel in FP64 or FP32 computes D~^-1 of one-region rows
+    instead of reading it."""
     lk = h.level_kernel(0)
     nd = 1 if kind == "scalar" else 3
     nb = nd * nd
     coefs = lk["coefs"] if stored else 27 * nb
+    if stored and precision == 0 and nreg:
+        coefs *= 1.0 - h.level_table_regions(0) / nreg
     coefs_lo = lk["coefs_lo"] if stored else 27 * nb
     if stored:
         vecs = 4 if kind == "scalar" and lk["kernel"] in (1, 2) and precision in (0, 1) else 5
@@ -191,13 +194,13 @@ def _cheb_bytes(h, kind, precision, stored=True):
     return (coefs_lo - nb) * 2 + nb * 4 + vecs * nd * 4
 
 
-def _cheb_gbs(h, kind, precision, rows, stored=True):
+def _cheb_gbs(h, kind, precision, rows, stored=True, nreg=None):
     from paper_2103_11962_amd import regmg
 
     n, ms = h.profile_query(regmg.TIMED_CHEB)
     if n == 0:
         return None
-    return _cheb_bytes(h, kind, precision, stored) * rows / (ms / n * 1e-3) / 1e9
+    return _cheb_bytes(h, kind, precision, stored, nreg) * rows / (ms / n * 1e-3) / 1e9
 
 
 def variant_mixed(dev):
@@ -224,8 +227,9 @@ def variant_mixed(dev):
                  "true_relres": res["true_relres"],
                  "cheb_gbs": _cheb_gbs(h, "block3", peff, rows, stored=False),
                  "cheb_bytes_per_node": _cheb_bytes(h, "block3", peff, stored=False),
-                 "cheb_gbs_at_stored_bytes": _cheb_gbs(h, "block3", peff, rows),
-                 "cheb_stored_bytes_per_node": _cheb_bytes(h, "block3", peff)}
+                 "cheb_gbs_at_stored_bytes": _cheb_gbs(h, "block3", peff, rows, nreg=len(w.extents)),
+                 "cheb_stored_bytes_per_node": _cheb_bytes(h, "block3", peff, nreg=len(w.extents)),
+                 "table_regions": h.level_table_regions(0)}
         if prec == 3:
             entry["levels"] = [{"coef_type": p["coef_type"], "rho_fp32": p["rho_fp32"], "rho_bf16": p["rho_bf16"]}
                                for p in pl]
