@@ -205,7 +205,9 @@ def _cheb_gbs(h, kind, precision, rows, stored=True, nreg=None):
 
 def variant_mixed(dev):
     """Elasticity 3x3x3 regions of 55^3: FP64 V-cycle vs FP32 vs FP32 with BF16 coefficients on level 0
-    vs BF16 on the levels the measured convergence factor allows, and FP64 with the nodal-block D~."""
+    vs BF16 on the levels the measured convergence factor allows, FP64 with the nodal-block D~, and
+    FP64 streaming every block (region_table = 0: the FP64 V-cycle otherwise reads the per-region
+    elasticity blocks from the class tables, which the low-precision V-cycles do not have)."""
     import numpy as np
 
     import synth
@@ -214,7 +216,7 @@ def variant_mixed(dev):
     b = _to_dev(synth.rhs(w), dev)
     out, x64 = {}, None
     for name, prec, extra in (("fp64", 0, {}), ("fp32", 1, {}), ("fp32_bf16", 2, {}), ("fp32_bf16_auto", 3, {}),
-                              ("fp64_block_diag", 0, dict(block_diag=1))):
+                              ("fp64_block_diag", 0, dict(block_diag=1)), ("fp64_streamed", 0, dict(region_table=0))):
         h = _handle(w, dev)
         setup_ms = _setup(h, w, precision=prec, **extra)
         rows = h.level_info(0)["n_regional"] // 3
