@@ -351,7 +351,9 @@ void setup_hierarchy(rmg_handle* h);
 // lowp: FP32 vectors and the levels' low-precision operators (b, z are float*), else FP64.
 // dot_slot >= 0 (FP64, Chebyshev or Jacobi smoother, not the coarsest level): (b, z) over the
 // owned copies, summed by the last smoothing step, goes to that scalar slot.
-void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, int dot_slot = -1);
+// start_ready: the level's zero-guess start u_0 = c D~^-1 b is already in its u (written by the CG
+// update), so the cycle does not compute it.
+void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, int dot_slot = -1, bool start_ready = false);
 // z = M^-1 r (one V-cycle in the configured precision); FP64 regional vectors.
 void apply_preconditioner(rmg_handle* h, const double* r, double* z);
 void pcg(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,

@@ -137,9 +137,11 @@ void launch_csr_to_stencil(const Level& L, const int64_t* rowptr, const int* col
 void launch_region_stencil_io(const Level& L, int region, double* soa, int to_level, hipStream_t st);
 
 // CG helpers (FP64).
-// x += alpha p; r -= alpha q; partial sums of owner-masked (r, r).
+// x += alpha p; r -= alpha q; partial sums of owner-masked (r, r); with u0 (scalar levels) also
+// u0 = c0 * dinv * r, the V-cycle's zero-guess start from the new r (as launch_cheb_zero).
 int64_t launch_cg_update(const Level& L, double* scalars, double* x, double* r, const double* p,
-                         const double* q, double* partials, hipStream_t st);
+                         const double* q, double* partials, hipStream_t st, const double* dinv = nullptr,
+                         double c0 = 0.0, double* u0 = nullptr);
 // p = z + beta p.
 void launch_cg_direction(int64_t n, double* scalars, const double* z, double* p, hipStream_t st);
 // mode 0: alpha = rz / pq; mode 1: beta = rz_new / rz, rz = rz_new;

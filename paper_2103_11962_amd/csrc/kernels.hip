@@ -2125,11 +2125,14 @@ bool launch_make_sym(Level& L, bool lowp, hipStream_t st, bool table) {
 }
 
 // ------------------------------------------------------------------ CG
+// With u0 (scalar levels): also the V-cycle's zero-guess start from the new residual, u0 = c0 D~^-1 r,
+// as k_cheb_zero computes it.
 template <int NDOF>
 __global__ __launch_bounds__(kBlock) void k_cg_update(LevelView L, const double* __restrict__ scalars,
                                                       double* __restrict__ x, double* __restrict__ r,
                                                       const double* __restrict__ p, const double* __restrict__ q,
-                                                      double* __restrict__ partials) {
+                                                      double* __restrict__ partials, const double* __restrict__ dinv,
+                                                      double c0, double* __restrict__ u0) {
   const double alpha = scalars[kAlpha];
   double c = 0.0;
   for (int j = 0; j < kUpdateDescs; ++j) {
@@ -2148,6 +2151,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(LevelView L, const double*
         x[gi] = x[gi] + alpha * p[gi];
         const double rn = r[gi] + (-alpha) * q[gi];
         r[gi] = rn;
+        if (NDOF == 1 && u0) u0[gi] = c0 * (dinv[gi] * rn);
         if (own) c += rn * rn;
       }
     }
@@ -2157,12 +2161,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(LevelView L, const double*
 }
 
 int64_t launch_cg_update(const Level& L, double* scalars, double* x, double* r, const double* p, const double* q,
-                         double* partials, hipStream_t st) {
+                         double* partials, hipStream_t st, const double* dinv, double c0, double* u0) {
   const int64_t nb = reduction_blocks(L, kUpdateDescs);
+  RMG_REQUIRE(!u0 || (L.ndof == 1 && dinv), RMG_ERR_ARG, "internal: fused zero-guess start needs a scalar level");
   if (L.ndof == 3)
-    RMG_LAUNCH(k_cg_update<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials);
+    RMG_LAUNCH(k_cg_update<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials, nullptr,
+               0.0, nullptr);
   else
-    RMG_LAUNCH(k_cg_update<1>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials);
+    RMG_LAUNCH(k_cg_update<1>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials, dinv, c0,
+               u0);
   LAUNCH_CHECK();
   return nb + dot_groups(L, r, r, partials + nb, st);
 }

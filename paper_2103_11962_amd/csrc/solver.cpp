@@ -706,7 +706,7 @@ void mg_solve(rmg_handle* h, const double* b, double* x, double rtol, int maxit,
   }
 }
 
-void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, int dot_slot) {
+void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, int dot_slot, bool start_ready) {
   const int nl = (int)h->levels.size();
   Level& L = *h->levels[level];
   hipStream_t st = h->stream;
@@ -746,7 +746,8 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, int dot
   const Bufs B = bufs(L, lowp);
   // ping-pong buffers arranged so that the last post-smoothing step writes z
   void* buf[2] = {B.u, z};
-  launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], buf[0], st, B.dinv9);
+  // the zero-guess start (already in B.u when the CG update wrote it from the new residual)
+  if (!start_ready) launch_cheb_zero(L, lowp, b, B.dinv, L.cheb_c2[0], buf[0], st, B.dinv9);
   int cur = 0;
   for (int k = 1; k < K; ++k) {
     cheb_step(h, L, lowp, k, k == 1 ? ChebKind::AfterZero : ChebKind::Next, b, buf[cur], buf[1 - cur]);
@@ -781,13 +782,14 @@ void vcycle(rmg_handle* h, int level, bool lowp, const void* b, void* z, int dot
 
 // z = M^-1 r with the configured precision (FP64 regional vectors in and out); with slot >= 0 also
 // (r, z) into that scalar slot, summed by the V-cycle's last Chebyshev step where it has one.
-static void precondition(rmg_handle* h, const double* r, double* z, int slot = -1) {
+// start_ready: the finest level's zero-guess start is already in its u (fused_start_ok).
+static void precondition(rmg_handle* h, const double* r, double* z, int slot = -1, bool start_ready = false) {
   Level& L = *h->levels[0];
   if (h->hy) {
     hybrid_cycle(h, r, z);
   } else if (h->opt.precision == RMG_PREC_FP64) {
     const bool fused = slot >= 0 && h->opt.smoother <= 1 && h->levels.size() > 1;
-    vcycle(h, 0, false, r, z, fused ? slot : -1);
+    vcycle(h, 0, false, r, z, fused ? slot : -1, start_ready);
     if (fused) return;
   } else {
     launch_f64_to_f32(L.ndofs(), r, L.b32.as<float>(), h->stream);
@@ -849,6 +851,14 @@ struct GraphStream {
   }
 };
 
+// Whether the CG update can also write the FP64 V-cycle's zero-guess start on the finest level
+// (scalar Chebyshev or Jacobi smoothing with the point D~ below a coarser level).
+static bool fused_start_ok(rmg_handle* h) {
+  const Level& L = *h->levels[0];
+  return !h->hy && h->opt.precision == RMG_PREC_FP64 && h->opt.smoother <= 1 && h->levels.size() > 1 &&
+         L.ndof == 1 && !L.dinv9.p && L.u.p && L.dinv.p;
+}
+
 static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int maxit, rmg_solve_info* info,
                      rmg_status* status) {
   Level& L = *h->levels[0];
@@ -857,6 +867,8 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
   // the hybrid cycle's region-local sweeps average the interface copies: not exactly symmetric
   const bool flexible = h->opt.precision != RMG_PREC_FP64 || h->hy != nullptr;
   const bool graphs = h->opt.use_graph != 0;
+  // the CG update also writes the V-cycle's zero-guess start from the new residual
+  const bool fused_start = fused_start_ok(h);
   double* r = h->cg_r.as<double>();
   double* p = h->cg_p.as<double>();
   double* q = h->cg_q.as<double>();
@@ -884,12 +896,14 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
     const int64_t np = launch_stencil_op(L, a, st);
     launch_reduce(part, np, scal(h), kPQ, st);
     launch_cg_scalars(scal(h), 0, st);
-    const int64_t nu = launch_cg_update(L, scal(h), x, r, p, q, part, st);
+    const int64_t nu = fused_start ? launch_cg_update(L, scal(h), x, r, p, q, part, st, L.dinv.as<double>(),
+                                                      L.cheb_c2[0], L.u.as<double>())
+                                   : launch_cg_update(L, scal(h), x, r, p, q, part, st);
     launch_reduce(part, nu, scal(h), kRR, st);
   };
   // second half: z = M^-1 r, beta, p update
   auto body_b = [&]() {
-    precondition(h, r, z, kRZnew);
+    precondition(h, r, z, kRZnew, fused_start);
     if (flexible) {
       dot(h, L, z, q, kZQ);
       launch_cg_scalars(scal(h), 2, st);
@@ -969,6 +983,11 @@ static void pcg_impl(rmg_handle* h, const double* b, double* x, double rtol, int
         if (true_rel <= rtol) {
           converged = true;
           break;
+        }
+        // CG goes on from the true residual: the zero-guess start the update wrote is stale
+        if (fused_start && it < maxit) {
+          Level& L0 = *h->levels[0];
+          launch_cheb_zero(L0, false, r, L0.dinv.p, L0.cheb_c2[0], L0.u.p, st);
         }
       }
       if (it >= maxit) break;
