@@ -185,6 +185,7 @@ struct Level {
   bool per_region = false;   // stencil operations launch the node-parallel kernel once per region
   // interface groups: copies of each shared composite node, ascending region order
   int64_t ngroups = 0;
+  int64_t ngroups2 = 0;  // the first ngroups2 groups have two copies (groups are ordered by size)
   DBuf d_gptr;    // int64 [ngroups+1]
   DBuf d_gcopy;   // int32 regional node indices
   DBuf d_gcomp;   // int32 composite node index of each group

@@ -690,13 +690,15 @@ __global__ __launch_bounds__(kTableThreads) __attribute__((amdgpu_waves_per_eu(D
 }
 
 // ----------------------------------------------------------- interface groups
+// ng2: the first ng2 groups have two copies each (their copies start at 2 g, no gptr read).
 template <int NDOF, class V, StencilOp OP, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_iface(const int64_t* __restrict__ gptr, const int* __restrict__ gcopy,
-                                                  int64_t ng, OpP<V> p, double* __restrict__ partials) {
+                                                  int64_t ng, int64_t ng2, OpP<V> p, double* __restrict__ partials) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double contrib = 0.0;
   if (g < ng) {
-    const int64_t a0 = gptr[g], e = gptr[g + 1];
+    const bool two = g < ng2;
+    const int64_t a0 = two ? 2 * g : gptr[g], e = two ? a0 + 2 : gptr[g + 1];
     const int m = (int)(e - a0);
     bool block = false;
     if constexpr (NDOF == 3 && (OP == StencilOp::Cheb || OP == StencilOp::ChebFirst)) {
@@ -844,7 +846,7 @@ static int64_t run(const Level& L, const StencilArgs& a, hipStream_t st) {
   if (L.ngroups > 0) {
     ngb = cdiv(L.ngroups, kBlock);
     RMG_LAUNCH((k_iface<NDOF, V, OP, DOT>), dim3(ngb), dim3(kBlock), 0, st, L.d_gptr.as<int64_t>(),
-                       L.d_gcopy.as<int>(), L.ngroups, p, a.partials ? a.partials + nb : nullptr);
+                       L.d_gcopy.as<int>(), L.ngroups, L.ngroups2, p, a.partials ? a.partials + nb : nullptr);
     LAUNCH_CHECK();
   }
   return (DOT || OP == StencilOp::CgQ) ? nb + ngb : 0;

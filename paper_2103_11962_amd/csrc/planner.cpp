@@ -367,6 +367,8 @@ void build_tables(Level& L) {
     gcomp2.push_back(gcomp[g]);
   }
   L.ngroups = ng;
+  L.ngroups2 = 0;
+  while (L.ngroups2 < ng && gptr2[L.ngroups2 + 1] - gptr2[L.ngroups2] == 2) ++L.ngroups2;
   // 2.5D tiles for the 3D stencil kernel, 21 planes deep by default; used when the level has
   // enough tiles to fill the GPU unless the options or the autotuner say otherwise.
   make_tiles(L, 21);
