@@ -2132,7 +2132,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(LevelView L, const double*
                                                       double* __restrict__ x, double* __restrict__ r,
                                                       const double* __restrict__ p, const double* __restrict__ q,
                                                       double* __restrict__ partials, const double* __restrict__ dinv,
-                                                      double c0, double* __restrict__ u0) {
+                                                      double c0, double* __restrict__ u0,
+                                                      const double* __restrict__ table, const int* __restrict__ table_ok) {
   const double alpha = scalars[kAlpha];
   double c = 0.0;
   for (int j = 0; j < kUpdateDescs; ++j) {
@@ -2151,7 +2152,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(LevelView L, const double*
         x[gi] = x[gi] + alpha * p[gi];
         const double rn = r[gi] + (-alpha) * q[gi];
         r[gi] = rn;
-        if (NDOF == 1 && u0) u0[gi] = c0 * (dinv[gi] * rn);
+        if (NDOF == 1 && u0) {
+          // a one-region row of a region served by its class table: D~^-1 is 1 / its class's centre
+          // coupling (the quotient the stored D~^-1 holds), so the row's D~^-1 is not read
+          double di;
+          if (table && own && table_ok[bd.region]) {
+            const int cls = (axis_class(zz, R.ez) * 5 + axis_class(yy, R.ey)) * 5 + axis_class(xx, R.ex);
+            di = 1.0 / table[((int64_t)bd.region * kClasses + cls) * kClassPts + 13];
+          } else {
+            di = dinv[gi];
+          }
+          u0[gi] = c0 * (di * rn);
+        }
         if (own) c += rn * rn;
       }
     }
@@ -2166,10 +2178,13 @@ int64_t launch_cg_update(const Level& L, double* scalars, double* x, double* r, 
   RMG_REQUIRE(!u0 || (L.ndof == 1 && dinv), RMG_ERR_ARG, "internal: fused zero-guess start needs a scalar level");
   if (L.ndof == 3)
     RMG_LAUNCH(k_cg_update<3>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials, nullptr,
-               0.0, nullptr);
-  else
+               0.0, nullptr, nullptr, nullptr);
+  else {
+    // the class tables give D~^-1 of the served regions' one-region rows (when dinv is the level's own)
+    const bool tab = u0 && dinv == L.dinv.as<double>() && L.npts == 27 && L.class_table.p && L.class_table_ok.p;
     RMG_LAUNCH(k_cg_update<1>, dim3(nb), dim3(kBlock), 0, st, L.view(), scalars, x, r, p, q, partials, dinv, c0,
-               u0);
+               u0, tab ? L.class_table.as<double>() : nullptr, tab ? L.class_table_ok.as<int>() : nullptr);
+  }
   LAUNCH_CHECK();
   return nb + dot_groups(L, r, r, partials + nb, st);
 }
